@@ -1,0 +1,67 @@
+"""Sampled rows of G^r by sparse LU (oracle; test infrastructure only).
+
+For any device size: factor A(E) = z I - H - Sigma with a general sparse LU
+(SuperLU, partial pivoting) and solve A^T x = e_s, so that x_k = (A^-1)_{s,k}
+is row s of G^r.  From that row (Eq. 1 and Eq. 2 for diagonal Sigma^<):
+
+  G^r_ss = x_s,   A_c,ss = sum_{k in c} Gamma_c,k |x_k|^2,
+  G^<_ss = i (f_L A_L,ss + f_R A_R,ss).
+
+The transmission T = sum_{i in L} Gamma_L,i A_R,ii needs the rows of every
+left-contact site; it is computed only when asked for.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spl
+
+from .negf import contact_sigmas, gamma_of, fermi
+
+
+def _factor(dev, z):
+    h = dev.scipy_h()
+    a = (-h).tolil()
+    a.setdiag(a.diagonal() + z)
+    for sites, sig in contact_sigmas(dev, z):
+        for s, v in zip(sites, sig):
+            a[s, s] -= v
+    return spl.splu(sp.csc_matrix(a))
+
+
+def _rows(lu, n, sites):
+    b = np.zeros((n, len(sites)), dtype=np.complex128)
+    b[np.asarray(sites), np.arange(len(sites))] = 1.0
+    return lu.solve(b, trans="T")         # column j = row sites[j] of A^-1
+
+
+def solve_sites(dev, energies, eta, kT, mu_L, mu_R, sites, want_trans=False, chunk=128):
+    energies = np.asarray(energies, dtype=np.float64)
+    sites = np.asarray(sites, dtype=np.int64)
+    ne = len(energies)
+    out = {k: np.zeros((ne, len(sites)), np.complex128) for k in ("gr", "gl")}
+    for k in ("a_l", "a_r"):
+        out[k] = np.zeros((ne, len(sites)))
+    out["trans"] = np.full(ne, np.nan)
+    fl = fermi(energies, mu_L, kT)
+    fr = fermi(energies, mu_R, kT)
+    for e, en in enumerate(energies):
+        z = en + 1j * eta
+        lu = _factor(dev, z)
+        (ls, sl), (rs, sr) = contact_sigmas(dev, z)
+        gam_l, gam_r = gamma_of(sl), gamma_of(sr)
+        for c0 in range(0, len(sites), chunk):
+            blk = sites[c0:c0 + chunk]
+            x = _rows(lu, dev.n, blk)
+            out["gr"][e, c0:c0 + len(blk)] = x[blk, np.arange(len(blk))]
+            out["a_l"][e, c0:c0 + len(blk)] = gam_l @ (np.abs(x[ls]) ** 2)
+            out["a_r"][e, c0:c0 + len(blk)] = gam_r @ (np.abs(x[rs]) ** 2)
+        out["gl"][e] = 1j * (fl[e] * out["a_l"][e] + fr[e] * out["a_r"][e])
+        if want_trans:
+            t = 0.0
+            for c0 in range(0, len(ls), chunk):
+                blk = ls[c0:c0 + chunk]
+                x = _rows(lu, dev.n, blk)
+                t += gam_l[c0:c0 + len(blk)] @ (gam_r @ (np.abs(x[rs]) ** 2))
+            out["trans"][e] = t
+    return out

@@ -1,0 +1,201 @@
+"""Synthetic tight-binding devices with the shapes of the paper's workloads.
+
+Conventions (shared by every consumer):
+
+* Cuboid site index  s = x + Nx*(y + Ny*z);  coordinates (x, y, z).
+* 7-point nearest-neighbour Hamiltonian with hopping ``t`` and hard walls on
+  every face (cuboid device of the paper's operation-count section).
+* Contacts: the x = 0 face (left, index 0) and the x = Nx-1 face (right,
+  index 1).  Every contact site couples with hopping ``coupling`` to its own
+  semi-infinite 1D chain (on-site ``lead_onsite``, hopping ``lead_hopping``);
+  the self-energy itself is computed by the solver / oracle, not here.
+* Honeycomb trilayer: brick-wall lattice, site index s = x + Wx*(y + Wy*l),
+  coordinates (x, y, l); the vertical axis (l) is never split.
+
+Only inputs live here.  No Green's-function arithmetic.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Contact:
+    sites: np.ndarray          # int64 site indices
+    lead_onsite: float
+    lead_hopping: float
+    coupling: float
+
+
+@dataclass
+class Device:
+    name: str
+    n: int
+    indptr: np.ndarray         # int64 [n+1]
+    indices: np.ndarray        # int32 [nnz]
+    values: np.ndarray         # complex128 [nnz]
+    coords: np.ndarray         # int32 [n, 3]
+    contacts: list             # [left, right] Contact
+    split_axes: tuple = (0, 1, 2)
+    meta: dict = field(default_factory=dict)
+
+    def dense_h(self) -> np.ndarray:
+        """Dense complex H (small devices only)."""
+        h = np.zeros((self.n, self.n), dtype=np.complex128)
+        for r in range(self.n):
+            for p in range(self.indptr[r], self.indptr[r + 1]):
+                h[r, self.indices[p]] += self.values[p]
+        return h
+
+    def scipy_h(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.values, self.indices.astype(np.int64), self.indptr),
+                             shape=(self.n, self.n))
+
+    @property
+    def grid(self):
+        return tuple(int(v) for v in self.meta.get("grid", ()))
+
+
+def _csr_from_lists(n, rows, cols, vals):
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    vals = np.asarray(vals, dtype=np.complex128)
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(indptr, rows + 1, 1)
+    indptr = np.cumsum(indptr)
+    return indptr, cols.astype(np.int32), vals
+
+
+def cuboid(nx: int, ny: int, nz: int, t: float = -1.0, onsite=None,
+           name: str | None = None) -> Device:
+    """7-point cuboid with per-site 1D leads on the x = 0 and x = Nx-1 faces."""
+    n = nx * ny * nz
+    onsite = np.zeros(n) if onsite is None else np.asarray(onsite, dtype=np.float64)
+    assert onsite.shape == (n,)
+    idx = np.arange(n, dtype=np.int64)
+    x = idx % nx
+    y = (idx // nx) % ny
+    z = idx // (nx * ny)
+    rows, cols, vals = [idx], [idx], [onsite.astype(np.complex128)]
+    for axis, stride, coord, size in ((0, 1, x, nx), (1, nx, y, ny), (2, nx * ny, z, nz)):
+        for sgn in (-1, 1):
+            ok = (coord + sgn >= 0) & (coord + sgn < size)
+            rows.append(idx[ok])
+            cols.append(idx[ok] + sgn * stride)
+            vals.append(np.full(int(ok.sum()), t, dtype=np.complex128))
+    indptr, indices, values = _csr_from_lists(n, np.concatenate(rows), np.concatenate(cols),
+                                              np.concatenate(vals))
+    coords = np.stack([x, y, z], axis=1).astype(np.int32)
+    left = idx[x == 0]
+    right = idx[x == nx - 1]
+    contacts = [Contact(left, 0.0, t, t), Contact(right, 0.0, t, t)]
+    return Device(name or f"cuboid{nx}x{ny}x{nz}", n, indptr, indices, values, coords,
+                  contacts, (0, 1, 2), {"grid": (nx, ny, nz), "t": t})
+
+
+def chain(m: int, t: float = -1.0, onsite=None) -> Device:
+    """An m-site 1D chain; each end site couples to a semi-infinite lead."""
+    return cuboid(m, 1, 1, t=t, onsite=onsite, name=f"chain{m}")
+
+
+def trilayer(wx: int = 116, wy: int = 115, t_inplane: float = -2.7,
+             t_inter: float = 0.4, bn_onsite: float = 1.4, both_edges_all_layers=False) -> Device:
+    """Graphene / BN / graphene brick-wall trilayer (vertical stacking).
+
+    In-plane bonds: (x,y)-(x+1,y) always; (x,y)-(x,y+1) when (x+y) is even.
+    Layer 1 (BN) on-site +bn_onsite on (x+y) even, -bn_onsite on odd; layers 0
+    and 2 on-site 0.  Interlayer hopping between the same (x, y) of adjacent
+    layers.  Leads: left on the x = 0 edge of layer 0, right on the x = Wx-1
+    edge of layer 2 (vertical tunnelling through the BN layer).
+    """
+    nl = 3
+    n = wx * wy * nl
+    idx = np.arange(n, dtype=np.int64)
+    x = idx % wx
+    y = (idx // wx) % wy
+    lay = idx // (wx * wy)
+    onsite = np.zeros(n)
+    bn = lay == 1
+    onsite[bn & ((x + y) % 2 == 0)] = bn_onsite
+    onsite[bn & ((x + y) % 2 == 1)] = -bn_onsite
+    rows, cols, vals = [idx], [idx], [onsite.astype(np.complex128)]
+    # x bonds
+    for sgn in (-1, 1):
+        ok = (x + sgn >= 0) & (x + sgn < wx)
+        rows.append(idx[ok]); cols.append(idx[ok] + sgn); vals.append(np.full(int(ok.sum()), t_inplane + 0j))
+    # y bonds: up when (x+y) even, down when (x+y) odd
+    up = ((x + y) % 2 == 0) & (y + 1 < wy)
+    rows.append(idx[up]); cols.append(idx[up] + wx); vals.append(np.full(int(up.sum()), t_inplane + 0j))
+    dn = ((x + y) % 2 == 1) & (y - 1 >= 0)
+    rows.append(idx[dn]); cols.append(idx[dn] - wx); vals.append(np.full(int(dn.sum()), t_inplane + 0j))
+    # interlayer
+    for sgn in (-1, 1):
+        ok = (lay + sgn >= 0) & (lay + sgn < nl)
+        rows.append(idx[ok]); cols.append(idx[ok] + sgn * wx * wy)
+        vals.append(np.full(int(ok.sum()), t_inter + 0j))
+    indptr, indices, values = _csr_from_lists(n, np.concatenate(rows), np.concatenate(cols),
+                                              np.concatenate(vals))
+    coords = np.stack([x, y, lay], axis=1).astype(np.int32)
+    if both_edges_all_layers:
+        left, right = idx[x == 0], idx[x == wx - 1]
+    else:
+        left, right = idx[(x == 0) & (lay == 0)], idx[(x == wx - 1) & (lay == 2)]
+    contacts = [Contact(left, 0.0, t_inplane, t_inplane), Contact(right, 0.0, t_inplane, t_inplane)]
+    return Device(f"trilayer{wx}x{wy}", n, indptr, indices, values, coords, contacts, (0, 1),
+                  {"grid": (wx, wy, nl), "t": t_inplane})
+
+
+def energy_grid(lo: float, hi: float, count: int) -> np.ndarray:
+    """Uniform grid with both end points included."""
+    return np.linspace(lo, hi, count)
+
+
+# --- the paper-shaped workloads ------------------------------------------------------------
+
+def _uniform_onsite(n, seed, half_width=0.5):
+    return np.random.default_rng(seed).uniform(-half_width, half_width, n)
+
+
+def config0_device(seed: int = 0) -> Device:
+    """8^3 cube, t = -1, on-site U[-0.5, 0.5] (site order), leads on the x faces."""
+    n = 8 ** 3
+    return cuboid(8, 8, 8, onsite=_uniform_onsite(n, seed), name="cube8")
+
+
+def config1_device(seed: int = 0, n_side: int = 32) -> Device:
+    """32^3 cube (32,768 sites), same Hamiltonian model as the 8^3 case."""
+    n = n_side ** 3
+    return cuboid(n_side, n_side, n_side, onsite=_uniform_onsite(n, seed), name=f"cube{n_side}")
+
+
+def config2_devices(seed: int = 0, count: int = 64, lo: int = 16, hi: int = 48, sigma: float = 0.3):
+    """Uneven cuboids: sides integers in [lo, hi], on-site N(0, sigma^2) per device."""
+    sizes = np.random.default_rng(seed).integers(lo, hi + 1, size=(count, 3))
+    out = []
+    for d, (nx, ny, nz) in enumerate(sizes):
+        n = int(nx * ny * nz)
+        onsite = np.random.default_rng((seed, d)).normal(0.0, sigma, n)
+        out.append(cuboid(int(nx), int(ny), int(nz), onsite=onsite, name=f"cuboid{d}"))
+    return out
+
+
+def config3_device() -> Device:
+    return trilayer(116, 115)
+
+
+def learned_grid_device(n_side: int, sigma: float, seed: int) -> Device:
+    """Cube with Gaussian on-site disorder N(0, sigma^2) for the learned-grid study."""
+    n = n_side ** 3
+    onsite = np.random.default_rng(seed).normal(0.0, sigma, n) if sigma > 0 else np.zeros(n)
+    return cuboid(n_side, n_side, n_side, onsite=onsite, name=f"cube{n_side}s{sigma:g}")
+
+
+CONFIG0 = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, energies=(-5.0, 5.0, 16), leaf_side=4)
+CONFIG1 = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, energies=(-6.0, 6.0, 256), leaf_side=8)
+CONFIG2 = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, energies=(-6.0, 6.0, 128), leaf_side=8)
+CONFIG3 = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, energies=(-3.0, 3.0, 512), leaf_side=8)
