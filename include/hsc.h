@@ -1,0 +1,178 @@
+/*
+ * hsc.h -- C ABI of the MI355X nested-dissection NEGF solver (HSC + HSC-extension).
+ *
+ * For a device Hamiltonian H (sparse, complex symmetric: H^T == H) with two
+ * contacts, and for each energy E, the library computes
+ *
+ *   diag G^r(E),  G^r = A^-1,  A = (E + i eta) I - H - Sigma_L - Sigma_R       (Eq. 1)
+ *   diag G^<(E),  G^< = G^r Sigma^< (G^r)^dagger,                              (Eq. 2)
+ *                 Sigma^< = i (f_L Gamma_L + f_R Gamma_R)
+ *   T(E) = Tr[Gamma_L G^r Gamma_R (G^r)^dagger]
+ *
+ * with Algorithm 1 (HSC: fold, root inverse, extract of G^r) and Algorithm 2
+ * (HSC-extension: N = Sigma^< (G^r)^dagger, fold of N, extract of P = G^<) over
+ * a binary cluster tree from multilevel nested dissection (Section 2.2).
+ *
+ * Conventions shared by every entry point:
+ *   - Every call returns hsc_status; 0 is success, negative values are errors.
+ *     hsc_last_error() returns a text description of the calling thread's last
+ *     error (valid until the next failing call on that thread).
+ *   - "host" pointers are ordinary CPU memory, read during the call only.
+ *     "device" pointers are HIP device memory owned by the caller (for example a
+ *     torch tensor's data_ptr()); the library never frees them.
+ *   - Complex numbers are two doubles (re, im) adjacent in memory.
+ *   - Site order in every output is the caller's site order (the order of H).
+ *   - Solves are asynchronous on the context's HIP stream.  Output buffers are
+ *     valid after hsc_sync() or after the caller synchronises that stream.
+ */
+#ifndef HSC_H_
+#define HSC_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HSC_OK = 0,
+  HSC_E_ARG = -1,           /* invalid argument (null pointer, bad size, bad index) */
+  HSC_E_NOT_SYMMETRIC = -2, /* H^T != H: the method uses transposes (Alg. 1), not adjoints */
+  HSC_E_SINGULAR = -3,      /* an exactly singular pivot block was met */
+  HSC_E_NONFINITE = -4,     /* NaN or Inf in the input or the factors */
+  HSC_E_OOM = -5,           /* device or host allocation failed */
+  HSC_E_HIP = -6,           /* a HIP runtime call failed */
+  HSC_E_UNSTABLE = -7       /* growth guard still above threshold after re-planning */
+} hsc_status;
+
+/* Output selection bits for hsc_solve_opts.want. */
+enum {
+  HSC_DIAG_GR = 1,        /* diag G^r                                          */
+  HSC_DIAG_GL = 2,        /* diag G^< for Sigma^< = i(f_L Gamma_L + f_R Gamma_R) */
+  HSC_TRANS = 4,          /* transmission T(E)                                 */
+  HSC_SPECTRAL_LR = 8     /* diag of A_L = G Gamma_L G^dagger and A_R, separately */
+};
+
+typedef struct hsc_ctx hsc_ctx;   /* one HIP device + one stream + workspaces; not thread-safe */
+typedef struct hsc_tree hsc_tree; /* cluster tree of one device; immutable after build        */
+
+/* One contact: a list of device sites, each coupled (hopping `coupling`) to its
+ * own semi-infinite 1D lead with on-site `lead_onsite` and hopping
+ * `lead_hopping` (the diagonal contact self-energy of the paper's SPARSE case). */
+typedef struct {
+  int64_t n_sites;
+  const int64_t* sites;      /* host, [n_sites] site indices in [0, n) */
+  double lead_onsite;
+  double lead_hopping;
+  double coupling;
+} hsc_contact;
+
+/* Geometric nested dissection (Section 2.2, multilevel nested dissection):
+ * split the longest splittable axis of the cluster's bounding box with a
+ * one-site-thick plane at lo + floor(extent / 2); stop when every splittable
+ * extent is <= leaf_side (or < 3).  split_mask bit a allows axis a.
+ * The separating property is verified against the graph of H. */
+typedef struct {
+  const int32_t* coords;     /* host, [n][3] integer site coordinates */
+  int32_t split_mask;        /* e.g. 7 for x|y|z, 3 for in-plane only */
+  int32_t leaf_side;         /* >= 1 */
+} hsc_tree_opts;
+
+typedef struct {
+  int64_t n_sites;
+  int32_t n_clusters;
+  int32_t depth;             /* number of levels (root level is 0) */
+  int32_t max_cluster;       /* max n_i */
+  int32_t max_front;         /* max |front(i)| */
+  int32_t max_ancestors;     /* max |P_i| (sites), over clusters on contact paths */
+  int32_t n_leaves;
+  double flops_per_energy;   /* real flops of one energy (complex FMA = 8), all outputs */
+  double bytes_per_energy;   /* device working set of one energy */
+} hsc_tree_stats;
+
+typedef struct {
+  double eta;                /* z = E + i*eta, > 0 */
+  double kT;                 /* Fermi temperature, > 0 (same unit as E) */
+  double mu_L, mu_R;         /* contact chemical potentials */
+  uint32_t want;             /* HSC_* bits */
+  int32_t batch;             /* energies per launch sequence; 0 = library default */
+} hsc_solve_opts;
+
+/* Library version string. */
+const char* hsc_version(void);
+const char* hsc_last_error(void);
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * (for example torch.cuda.current_stream().cuda_stream) or NULL for the null
+ * stream.  Errors: HSC_E_ARG, HSC_E_HIP. */
+hsc_status hsc_ctx_create(int32_t device, void* hip_stream, hsc_ctx** out);
+hsc_status hsc_ctx_destroy(hsc_ctx* ctx);
+
+/* Build the nested-dissection cluster tree of one device (host work only; the
+ * device copy is made by the first solve).  H is CSR with n rows: indptr[n+1]
+ * (int64), indices[nnz] (int32), values_ri[2*nnz] interleaved (re, im), all
+ * host.  Exactly two contacts: contacts[0] = left, contacts[1] = right; a site
+ * may belong to at most one contact.  Errors: HSC_E_ARG (bad CSR, indices,
+ * contacts or opts), HSC_E_NOT_SYMMETRIC, HSC_E_NONFINITE, HSC_E_OOM. */
+hsc_status hsc_tree_build(int64_t n, const int64_t* indptr, const int32_t* indices,
+                          const double* values_ri, int32_t n_contacts,
+                          const hsc_contact* contacts, const hsc_tree_opts* opts,
+                          hsc_tree** out);
+
+/* A copy of `src` in which every listed cluster (ids as numbered by
+ * hsc_tree_export) is merged into its parent: the parent takes its sites and
+ * children.  Merging removes the unpivoted elimination of that cluster's block
+ * on its own.  The root cannot be merged.  Errors: HSC_E_ARG. */
+hsc_status hsc_tree_merge(const hsc_tree* src, int32_t n_ids, const int32_t* ids,
+                          hsc_tree** out);
+
+hsc_status hsc_tree_stats_get(const hsc_tree* tree, hsc_tree_stats* out);
+
+/* Export the tree (host buffers, sized from hsc_tree_stats_get):
+ *   perm[n]            site at position p of the cluster ordering (post-order)
+ *   cl_parent[nc]      parent cluster id (-1 for the root); ids are post-order
+ *   cl_first[nc]       first position of the cluster's sites in perm
+ *   cl_size[nc]        n_i
+ *   front_ptr[nc+1]    offsets into front_sites
+ *   front_sites[...]   point-level front of each cluster (original site ids),
+ *                      in cluster-ordering position order.
+ * Any pointer may be NULL to skip that array; front_sites needs front_ptr[nc]
+ * entries.  Errors: HSC_E_ARG. */
+hsc_status hsc_tree_export(const hsc_tree* tree, int64_t* perm, int32_t* cl_parent,
+                           int32_t* cl_first, int32_t* cl_size, int64_t* front_ptr,
+                           int64_t* front_sites);
+hsc_status hsc_tree_destroy(hsc_tree* tree);
+
+/* Solve n_e energies of one device.
+ *   energies     device, double[n_e] (real energies)
+ *   diag_gr      device, complex[n_e][n]   (HSC_DIAG_GR) or NULL
+ *   diag_gl      device, complex[n_e][n]   (HSC_DIAG_GL) or NULL
+ *   trans        device, double[n_e]       (HSC_TRANS) or NULL
+ *   spectral_lr  device, double[n_e][2][n] (HSC_SPECTRAL_LR: A_L then A_R) or NULL
+ *   status       device, int32[n_e] per-energy status (0 or a negative code) or NULL
+ *   guard        device, double[n_e] per-energy growth indicator max|Psi| or NULL
+ * Outputs whose bit is not set in opts->want are not written.
+ * Errors: HSC_E_ARG, HSC_E_OOM, HSC_E_HIP.  Numerical failures of single
+ * energies are reported through `status` (see hsc_sync). */
+hsc_status hsc_solve(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, const double* energies,
+                     const hsc_solve_opts* opts, void* diag_gr, void* diag_gl, double* trans,
+                     double* spectral_lr, int32_t* status, double* guard);
+
+/* Solve several devices (each with its own energies and outputs) in one call:
+ * their clusters share every batched launch.  Arrays are indexed by device;
+ * entries follow hsc_solve.  Errors as hsc_solve. */
+hsc_status hsc_solve_batch(hsc_ctx* ctx, int32_t n_trees, const hsc_tree* const* trees,
+                           const int32_t* n_e, const double* const* energies,
+                           const hsc_solve_opts* opts, void* const* diag_gr,
+                           void* const* diag_gl, double* const* trans,
+                           double* const* spectral_lr, int32_t* const* status,
+                           double* const* guard);
+
+/* Wait for the context's stream; returns HSC_E_HIP on an asynchronous HIP error. */
+hsc_status hsc_sync(hsc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSC_H_ */

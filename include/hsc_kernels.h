@@ -1,0 +1,50 @@
+/*
+ * hsc_kernels.h -- kernel-level entry points of the solver library.
+ *
+ * These expose the two compute kernels that every step of the solve is built
+ * from, so that they can be checked in isolation against a plain reference:
+ * the grouped complex128 GEMM (FP64 matrix cores) and the batched blocked
+ * Gauss-Jordan inversion with partial pivoting (the A_ii^-1 of Algorithm 1).
+ * All pointers are HIP device memory owned by the caller; complex values are
+ * (re, im) double pairs; matrices are row-major with the given leading
+ * dimension.  Calls are asynchronous on the context's stream (hsc_sync waits).
+ */
+#ifndef HSC_KERNELS_H_
+#define HSC_KERNELS_H_
+
+#include <stdint.h>
+
+#include "hsc.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* D = alpha * op(A) * op(B) + beta * C for one problem, op in {0: as is,
+ * 1: transpose, 2: conjugate transpose}; op(A) is M x K, op(B) is K x N.
+ * beta is 0 or 1; C may equal D (in-place update) and may be NULL when beta = 0.
+ * Errors: HSC_E_ARG (sizes < 0, bad op, leading dimension too small), HSC_E_HIP. */
+hsc_status hsc_kern_zgemm(hsc_ctx* ctx, int32_t opA, int32_t opB, int32_t M, int32_t N, int32_t K,
+                          double alpha_re, double alpha_im, const void* A, int32_t lda, const void* B,
+                          int32_t ldb, int32_t beta, const void* C, int32_t ldc, void* D, int32_t ldd);
+
+/* Invert `count` matrices of order n[k] in place (X[k], leading dimension ld[k])
+ * and write X[k]^-1 into Y[k] (leading dimension ldy[k]); all pointer/size
+ * arrays are host arrays.  status (device, int32[count], may be NULL) receives
+ * 0 or HSC_E_SINGULAR per matrix.  n[k] <= 4096.  Errors: HSC_E_ARG, HSC_E_OOM,
+ * HSC_E_HIP. */
+hsc_status hsc_kern_zinv_batched(hsc_ctx* ctx, int32_t count, const int32_t* n, void* const* X,
+                                 const int32_t* ld, void* const* Y, const int32_t* ldy, int32_t* status);
+
+/* One wave of v_mfma_f64_16x16x4_f64 with A[l%16][l/16] = 1 + l and
+ * B[l/16][l%16] = 0.5*((7l) mod 13) - 1 (l = lane); writes the 4 accumulator
+ * registers of each lane to out[l*4 + r] (device, 256 doubles); register r of
+ * lane l holds D[l/16 + 4r][l%16].  Used to check the lane layout the GEMM
+ * kernel assumes. */
+hsc_status hsc_kern_mfma_probe(hsc_ctx* ctx, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSC_KERNELS_H_ */

@@ -1,0 +1,127 @@
+// Device kernel descriptors and launchers (complex128 stored as double2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "../../include/hsc.h"
+
+namespace hsc {
+
+// op codes for GEMM operands and gathers
+enum { OP_N = 0, OP_T = 1, OP_C = 2 };   // as is, transposed, conjugate-transposed
+
+// One problem of a grouped GEMM:  D = alpha * op(A) * op(B) + beta * C
+// (row-major, leading dimensions in elements).
+struct GemmProb {
+  const double2* A;
+  const double2* B;
+  const double2* C;
+  double2* D;
+  int32_t M, N, K;
+  int32_t lda, ldb, ldc, ldd;
+  int32_t tiles_n;   // ceil(N / tile width)
+  int32_t tile_off;  // first tile of this problem in the launch
+};
+
+// Row-parallel 2D job (gathers, assembly, diagonals): one block per (job, row);
+// row_job[g] = job owning global row g (host-built map).
+struct RowJob {
+  int32_t rows, cols;
+  int32_t row_off;   // first global row of this job in the launch
+  int32_t e;         // energy slot
+  const double2* src;
+  double2* dst;
+  const int32_t* rmap;   // may be null (identity)
+  const int32_t* cmap;   // may be null (identity)
+  int32_t lds, ldd;
+  int32_t aux0, aux1, aux2, aux3, aux4, aux5;   // kernel specific
+  const void* p0;        // kernel specific
+  const void* p1;
+  const void* p2;
+};
+
+// Batched Gauss-Jordan matrix: in place on X (n x n, ld), result gathered into Y (ld ldy).
+struct InvJob {
+  double2* X;
+  double2* Y;
+  int32_t n, ld, ldy;
+  int32_t e;          // energy slot (status reporting)
+  int32_t* piv;       // [n] workspace
+  double2* T;         // [n][nb] workspace (panel columns minus identity)
+  double2* R;         // [nb][n] workspace (pivot rows)
+};
+
+// Per-energy scalars computed on the device.
+struct EnergyScalars {
+  double2 z;
+  double2 sig[2];     // contact self-energies (left, right)
+  double gam[2];      // broadenings
+  double fermi[2];    // occupations
+};
+
+// Child of a frontal matrix: its update block U (rows/cols = child front) and
+// invrel[a] = position of the parent's frontal index a in the child front, or -1.
+struct ChildRef {
+  const double2* U;
+  const int32_t* invrel;
+  int32_t ldU;
+  int32_t pad;
+};
+
+// Sparse entries of A = -H restricted to a frontal matrix, CSR over its rows.
+struct FrontSparse {
+  const int32_t* ptr;
+  const int32_t* col;
+  const double2* val;
+};
+
+struct LeadParams {
+  double onsite[2], hopping[2], coupling[2];
+};
+
+// launchers (all asynchronous on `st`)
+// tile_prob[t] = problem owning tile t (host-built map; one entry per tile)
+void launch_gemm(hipStream_t st, int opA, int opB, const GemmProb* probs, const int32_t* tile_prob,
+                 int total_tiles, double alpha_re, double alpha_im, int beta, int tile_kind);
+int gemm_tile_m(int tile_kind);
+int gemm_tile_n(int tile_kind);
+
+// per-slot scalars for the slots of one chunk; idle slots (>= nvalid) repeat
+// the last energy; status[slot] is reset (0, or NONFINITE for a bad energy)
+void launch_energy_setup(hipStream_t st, const double* energies, int nvalid, int nslots, double eta,
+                         double kT, double mu_L, double mu_R, LeadParams lp, EnergyScalars* out,
+                         int32_t* status);
+void launch_status_out(hipStream_t st, const int32_t* st_slots, int nvalid, int32_t* out);
+
+// Frontal assembly: F = sum of children's update blocks (pull) + sparse A entries.
+void launch_assemble(hipStream_t st, const RowJob* jobs, const int32_t* row_job, int total_rows,
+                     const EnergyScalars* es);
+// dst[r][c] = op(src[rmap[r]][cmap[c]]) (or transposed source indexing)
+void launch_gather(hipStream_t st, const RowJob* jobs, const int32_t* row_job, int total_rows, int trans, int op);
+// N-frontal assembly: pull children's updates + seed rows i*w*conj(G row)
+void launch_assemble_n(hipStream_t st, const RowJob* jobs, const int32_t* row_job, int total_rows,
+                       const EnergyScalars* es, int channel);
+// diagonal outputs (mode: DIAG_*), written for energy slots < nvalid at
+// out[(e_base + slot) * out_stride + site]
+enum { DIAG_SEP = 0, DIAG_LEAF_G = 1, DIAG_LEAF_P = 2 };
+enum { OUT_COMPLEX = 0, OUT_IMAG = 1 };
+void launch_diag(hipStream_t st, const RowJob* jobs, const int32_t* row_job, int total_rows, int mode,
+                 int out_kind, void* out, int64_t out_stride, int e_base, int nvalid);
+// T[e_base + slot] = Gamma_L(slot) * sum over left sites of a_r[slot][site]
+void launch_trans(hipStream_t st, const double* a_r, int64_t ld, const int64_t* left_sites, int nleft,
+                  int nslots, int nvalid, int e_base, const EnergyScalars* es, double* trans);
+// diag G^< = i (f_L A_L + f_R A_R) from spectral [e][2][n]
+void launch_combine_gl(hipStream_t st, const double* spec, int nvalid, int e_base, int64_t n,
+                       const EnergyScalars* es, double2* gl);
+
+// Batched blocked Gauss-Jordan inversion.
+void launch_inv_panel(hipStream_t st, const InvJob* jobs, int njobs, int k0, int nb, int max_n,
+                      int32_t* status);
+void launch_inv_swap(hipStream_t st, const InvJob* jobs, int njobs, int k0, int nb, int max_n);
+void launch_inv_unscramble(hipStream_t st, const InvJob* jobs, int njobs, int max_n);
+
+// debug / unit-test helpers
+void launch_mfma_probe(hipStream_t st, double* out);
+
+}  // namespace hsc

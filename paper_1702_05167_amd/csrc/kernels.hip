@@ -1,0 +1,321 @@
+// Bandwidth-bound kernels of the solve: per-energy scalars, frontal assembly
+// (Algorithm 1 fold: A_ii, A_ij plus the Schur updates of the children),
+// gathers from the parent's frontal blocks (Algorithm 1/2 extract), the
+// N-frontal assembly with its seed N = Sigma^< (G^r)^dagger (Algorithm 2), and
+// the diagonal / transmission outputs.
+#include <hip/hip_runtime.h>
+
+#include "kern.h"
+
+namespace hsc {
+
+namespace {
+
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// principal square root
+__device__ inline double2 csqrt_p(double2 z) {
+  const double r = hypot(z.x, z.y);
+  if (r == 0.0) return make_double2(0.0, 0.0);
+  if (z.x >= 0.0) {
+    const double a = sqrt(0.5 * (r + z.x));
+    return make_double2(a, z.y / (2.0 * a));
+  }
+  double b = sqrt(0.5 * (r - z.x));
+  if (z.y < 0.0) b = -b;
+  return make_double2(z.y / (2.0 * b), b);
+}
+
+__device__ inline double2 cdiv_real(double2 a, double s) { return make_double2(a.x / s, a.y / s); }
+
+// Surface Green's function of a semi-infinite chain: t^2 g^2 - w g + 1 = 0,
+// the decaying root (smaller modulus; the two roots multiply to 1/t^2).
+__device__ inline double2 lead_sigma(double2 z, double eps0, double tl, double tc) {
+  const double2 w = make_double2(z.x - eps0, z.y);
+  const double2 w2 = cmul(w, w);
+  const double2 disc = csqrt_p(make_double2(w2.x - 4.0 * tl * tl, w2.y));
+  const double2 g1 = cdiv_real(cadd(w, disc), 2.0 * tl * tl);
+  const double2 g2 = cdiv_real(make_double2(w.x - disc.x, w.y - disc.y), 2.0 * tl * tl);
+  const double m1 = hypot(g1.x, g1.y), m2 = hypot(g2.x, g2.y);
+  const double2 g = m1 < m2 ? g1 : g2;
+  return make_double2(tc * tc * g.x, tc * tc * g.y);
+}
+
+__device__ inline double fermi_fn(double e, double mu, double kT) {
+  const double x = (e - mu) / kT;
+  if (x > 0.0) {
+    const double ex = exp(-x);
+    return ex / (1.0 + ex);
+  }
+  return 1.0 / (1.0 + exp(x));
+}
+
+__global__ void k_energy_setup(const double* __restrict__ energies, int nvalid, int nslots, double eta,
+                               double kT, double mu_L, double mu_R, LeadParams lp,
+                               EnergyScalars* __restrict__ out, int32_t* __restrict__ status) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nslots) return;
+  const double en = energies[e < nvalid ? e : nvalid - 1];   // idle slots repeat the last energy
+  status[e] = isfinite(en) ? 0 : (int32_t)HSC_E_NONFINITE;
+  EnergyScalars s;
+  s.z = make_double2(en, eta);
+  for (int c = 0; c < 2; ++c) {
+    s.sig[c] = lead_sigma(s.z, lp.onsite[c], lp.hopping[c], lp.coupling[c]);
+    s.gam[c] = -2.0 * s.sig[c].y;
+  }
+  s.fermi[0] = fermi_fn(en, mu_L, kT);
+  s.fermi[1] = fermi_fn(en, mu_R, kT);
+  out[e] = s;
+}
+
+// weight of a contact side in a lesser-self-energy channel:
+// 0 = both contacts with occupations, 1 = left only, 2 = right only
+__device__ inline double channel_weight(const EnergyScalars& s, int channel, int side) {
+  if (channel == 0) return s.fermi[side] * s.gam[side];
+  if (channel == 1) return side == 0 ? s.gam[0] : 0.0;
+  return side == 1 ? s.gam[1] : 0.0;
+}
+
+constexpr int RB = 256;
+
+// F[a][b] = sum_children U_k[invrel_k[a]][invrel_k[b]] + (-H)[a][b] + delta_ab (z - Sigma_a)
+//   jobs: rows = cols = n+f; p0 = ChildRef[aux0]; p1 = FrontSparse*; aux1 = n, aux2 = nL, aux3 = nR
+__global__ __launch_bounds__(RB) void k_assemble(const RowJob* __restrict__ jobs, const int32_t* __restrict__ row_job,
+                                                 const EnergyScalars* __restrict__ es) {
+  const int g = blockIdx.x;
+  const RowJob& jb = jobs[row_job[g]];
+  const int a = g - jb.row_off;
+  const int cols = jb.cols;
+  const ChildRef* kids = reinterpret_cast<const ChildRef*>(jb.p0);
+  const FrontSparse* fs = reinterpret_cast<const FrontSparse*>(jb.p1);
+  const int nk = jb.aux0, n = jb.aux1, nL = jb.aux2, nR = jb.aux3;
+  __shared__ int s_col[64];
+  __shared__ double2 s_val[64];
+  const int q0 = fs->ptr[a], q1 = fs->ptr[a + 1];
+  const int nq = min(q1 - q0, 64);
+  if (threadIdx.x < nq) {
+    s_col[threadIdx.x] = fs->col[q0 + threadIdx.x];
+    s_val[threadIdx.x] = fs->val[q0 + threadIdx.x];
+  }
+  __syncthreads();
+  double2 diag_add = make_double2(0.0, 0.0);
+  if (a < n) {
+    const EnergyScalars& s = es[jb.e];
+    diag_add = s.z;
+    if (a < nL) { diag_add.x -= s.sig[0].x; diag_add.y -= s.sig[0].y; }
+    else if (a < nL + nR) { diag_add.x -= s.sig[1].x; diag_add.y -= s.sig[1].y; }
+  }
+  double2* out = jb.dst + (int64_t)a * jb.ldd;
+  for (int b = threadIdx.x; b < cols; b += RB) {
+    double2 v = make_double2(0.0, 0.0);
+    for (int k = 0; k < nk; ++k) {
+      const int ia = kids[k].invrel[a];
+      if (ia < 0) continue;
+      const int ib = kids[k].invrel[b];
+      if (ib < 0) continue;
+      v = cadd(v, kids[k].U[(int64_t)ia * kids[k].ldU + ib]);
+    }
+    for (int q = 0; q < nq; ++q)
+      if (s_col[q] == b) v = cadd(v, s_val[q]);
+    for (int q = q0 + 64; q < q1; ++q)
+      if (fs->col[q] == b) v = cadd(v, fs->val[q]);
+    if (b == a) v = cadd(v, diag_add);
+    out[b] = v;
+  }
+}
+
+// dst[r][c] = op(trans ? src[cmap[c]][rmap[r]] : src[rmap[r]][cmap[c]]);  op 1 = -conj
+template <int TRANS, int OP>
+__global__ __launch_bounds__(RB) void k_gather(const RowJob* __restrict__ jobs, const int32_t* __restrict__ row_job) {
+  const int g = blockIdx.x;
+  const RowJob& jb = jobs[row_job[g]];
+  const int r = g - jb.row_off;
+  const int rr = jb.rmap ? jb.rmap[r] : r;
+  double2* out = jb.dst + (int64_t)r * jb.ldd;
+  for (int c = threadIdx.x; c < jb.cols; c += RB) {
+    const int cc = jb.cmap ? jb.cmap[c] : c;
+    double2 v = TRANS ? jb.src[(int64_t)cc * jb.lds + rr] : jb.src[(int64_t)rr * jb.lds + cc];
+    if (OP == 1) v = make_double2(-v.x, v.y);
+    out[c] = v;
+  }
+}
+
+// NF[rr][b] = sum_children U_k[invrel_k[a(rr)]][b] + seed(rr, b)
+//   a(rr) = rr < r ? row0 + rr : n + (rr - r)
+//   seed: rr < r, a < nL + nR: i * w(side) * conj(Grow[a][b])
+//   jobs: p0 = ChildRef[aux0]; aux1 = r; aux2 = row0; aux3 = n; aux4 = nL; aux5 = nR; src = Grow (lds)
+__global__ __launch_bounds__(RB) void k_assemble_n(const RowJob* __restrict__ jobs, const int32_t* __restrict__ row_job,
+                                                   const EnergyScalars* __restrict__ es, int channel) {
+  const int g = blockIdx.x;
+  const RowJob& jb = jobs[row_job[g]];
+  const int rr = g - jb.row_off;
+  const ChildRef* kids = reinterpret_cast<const ChildRef*>(jb.p0);
+  const int nk = jb.aux0, r = jb.aux1, row0 = jb.aux2, n = jb.aux3, nL = jb.aux4, nR = jb.aux5;
+  const int a = rr < r ? row0 + rr : n + (rr - r);
+  double w = 0.0;
+  if (rr < r && a < nL + nR) w = channel_weight(es[jb.e], channel, a < nL ? 0 : 1);
+  const double2* grow = jb.src + (int64_t)a * jb.lds;
+  double2* out = jb.dst + (int64_t)rr * jb.ldd;
+  for (int b = threadIdx.x; b < jb.cols; b += RB) {
+    double2 v = make_double2(0.0, 0.0);
+    for (int k = 0; k < nk; ++k) {
+      const int ia = kids[k].invrel[a];
+      if (ia >= 0) v = cadd(v, kids[k].U[(int64_t)ia * kids[k].ldU + b]);
+    }
+    if (w != 0.0) {
+      const double2 gv = grow[b];
+      v.x += w * gv.y;
+      v.y += w * gv.x;
+    }
+    out[b] = v;
+  }
+}
+
+// Diagonal outputs, one wave per row.
+//   DIAG_SEP:    v = src[k][k]
+//   DIAG_LEAF_G: v = Inv[k][k] + sum_j Psi[k][j] * GT[k][j]           (p1 = Inv, aux1 = ld Inv)
+//   DIAG_LEAF_P: v = M[k][k] - sum_j Psi[k][j] * conj(PT[k][j])      (p1 = M or null, aux1 = ld M)
+//   p0 = Psi (ld aux0 = f), src = GT/PT (lds), p2 = int64 sites of the rows
+template <int MODE>
+__global__ __launch_bounds__(RB) void k_diag(const RowJob* __restrict__ jobs, const int32_t* __restrict__ row_job,
+                                             int total_rows, int out_kind, void* out, int64_t out_stride,
+                                             int e_base, int nvalid) {
+  const int g = blockIdx.x * (RB / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (g >= total_rows) return;
+  const RowJob& jb = jobs[row_job[g]];
+  const int k = g - jb.row_off;
+  if (jb.e >= nvalid) return;
+  double2 v = make_double2(0.0, 0.0);
+  if (MODE == DIAG_SEP) {
+    v = jb.src[(int64_t)k * jb.lds + k];
+  } else {
+    const int f = jb.aux0;
+    const double2* psi = reinterpret_cast<const double2*>(jb.p0) + (int64_t)k * f;
+    const double2* x = jb.src + (int64_t)k * jb.lds;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int j = lane; j < f; j += 64) {
+      double2 y = x[j];
+      if (MODE == DIAG_LEAF_P) y.y = -y.y;
+      acc = cadd(acc, cmul(psi[j], y));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      acc.x += __shfl_xor(acc.x, off, 64);
+      acc.y += __shfl_xor(acc.y, off, 64);
+    }
+    const double2* base = reinterpret_cast<const double2*>(jb.p1);
+    double2 d = base ? base[(int64_t)k * jb.aux1 + k] : make_double2(0.0, 0.0);
+    if (MODE == DIAG_LEAF_P) v = make_double2(d.x - acc.x, d.y - acc.y);
+    else v = cadd(d, acc);
+  }
+  if (lane != 0) return;
+  const int64_t site = reinterpret_cast<const int64_t*>(jb.p2)[k];
+  const int64_t idx = (int64_t)(e_base + jb.e) * out_stride + site;
+  if (out_kind == OUT_COMPLEX) reinterpret_cast<double2*>(out)[idx] = v;
+  else reinterpret_cast<double*>(out)[idx] = v.y;
+}
+
+__global__ __launch_bounds__(RB) void k_trans(const double* __restrict__ a_r, int64_t ld,
+                                              const int64_t* __restrict__ left, int nleft, int nvalid,
+                                              int e_base, const EnergyScalars* __restrict__ es,
+                                              double* __restrict__ trans) {
+  const int e = blockIdx.x;
+  if (e >= nvalid) return;
+  __shared__ double red[RB];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < nleft; k += RB) acc += a_r[(int64_t)e * ld + left[k]];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = RB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) trans[e_base + e] = es[e].gam[0] * red[0];
+}
+
+__global__ void k_combine_gl(const double* __restrict__ spec, int nvalid, int e_base, int64_t n,
+                             const EnergyScalars* __restrict__ es, double2* __restrict__ gl) {
+  const int e = blockIdx.y;
+  if (e >= nvalid) return;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int64_t eg = e_base + e;
+  const double al = spec[eg * 2 * n + s], ar = spec[eg * 2 * n + n + s];
+  gl[eg * n + s] = make_double2(0.0, es[e].fermi[0] * al + es[e].fermi[1] * ar);
+}
+
+}  // namespace
+
+void launch_energy_setup(hipStream_t st, const double* energies, int nvalid, int nslots, double eta,
+                         double kT, double mu_L, double mu_R, LeadParams lp, EnergyScalars* out,
+                         int32_t* status) {
+  if (nslots <= 0) return;
+  hipLaunchKernelGGL(k_energy_setup, dim3((nslots + 63) / 64), dim3(64), 0, st, energies, nvalid, nslots, eta,
+                     kT, mu_L, mu_R, lp, out, status);
+}
+
+__global__ void k_status_out(const int32_t* __restrict__ st_slots, int nvalid, int32_t* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nvalid) out[e] = st_slots[e];
+}
+
+void launch_status_out(hipStream_t st, const int32_t* st_slots, int nvalid, int32_t* out) {
+  if (nvalid <= 0 || !out) return;
+  hipLaunchKernelGGL(k_status_out, dim3((nvalid + 63) / 64), dim3(64), 0, st, st_slots, nvalid, out);
+}
+
+void launch_assemble(hipStream_t st, const RowJob* jobs, const int32_t* row_job, int total_rows,
+                     const EnergyScalars* es) {
+  if (total_rows <= 0) return;
+  hipLaunchKernelGGL(k_assemble, dim3(total_rows), dim3(RB), 0, st, jobs, row_job, es);
+}
+
+void launch_gather(hipStream_t st, const RowJob* jobs, const int32_t* row_job, int total_rows, int trans,
+                   int op) {
+  if (total_rows <= 0) return;
+  if (trans && op) hipLaunchKernelGGL((k_gather<1, 1>), dim3(total_rows), dim3(RB), 0, st, jobs, row_job);
+  else if (trans) hipLaunchKernelGGL((k_gather<1, 0>), dim3(total_rows), dim3(RB), 0, st, jobs, row_job);
+  else if (op) hipLaunchKernelGGL((k_gather<0, 1>), dim3(total_rows), dim3(RB), 0, st, jobs, row_job);
+  else hipLaunchKernelGGL((k_gather<0, 0>), dim3(total_rows), dim3(RB), 0, st, jobs, row_job);
+}
+
+void launch_assemble_n(hipStream_t st, const RowJob* jobs, const int32_t* row_job, int total_rows,
+                       const EnergyScalars* es, int channel) {
+  if (total_rows <= 0) return;
+  hipLaunchKernelGGL(k_assemble_n, dim3(total_rows), dim3(RB), 0, st, jobs, row_job, es, channel);
+}
+
+void launch_diag(hipStream_t st, const RowJob* jobs, const int32_t* row_job, int total_rows, int mode,
+                 int out_kind, void* out, int64_t out_stride, int e_base, int nvalid) {
+  if (total_rows <= 0) return;
+  dim3 grid((total_rows + 3) / 4), block(RB);
+  if (mode == DIAG_SEP)
+    hipLaunchKernelGGL(k_diag<DIAG_SEP>, grid, block, 0, st, jobs, row_job, total_rows, out_kind, out,
+                       out_stride, e_base, nvalid);
+  else if (mode == DIAG_LEAF_G)
+    hipLaunchKernelGGL(k_diag<DIAG_LEAF_G>, grid, block, 0, st, jobs, row_job, total_rows, out_kind, out,
+                       out_stride, e_base, nvalid);
+  else
+    hipLaunchKernelGGL(k_diag<DIAG_LEAF_P>, grid, block, 0, st, jobs, row_job, total_rows, out_kind, out,
+                       out_stride, e_base, nvalid);
+}
+
+void launch_trans(hipStream_t st, const double* a_r, int64_t ld, const int64_t* left_sites, int nleft,
+                  int nslots, int nvalid, int e_base, const EnergyScalars* es, double* trans) {
+  if (nslots <= 0) return;
+  hipLaunchKernelGGL(k_trans, dim3(nslots), dim3(RB), 0, st, a_r, ld, left_sites, nleft, nvalid, e_base, es,
+                     trans);
+}
+
+void launch_combine_gl(hipStream_t st, const double* spec, int nvalid, int e_base, int64_t n,
+                       const EnergyScalars* es, double2* gl) {
+  if (nvalid <= 0) return;
+  dim3 grid((unsigned)((n + 255) / 256), nvalid);
+  hipLaunchKernelGGL(k_combine_gl, grid, dim3(256), 0, st, spec, nvalid, e_base, n, es, gl);
+}
+
+}  // namespace hsc

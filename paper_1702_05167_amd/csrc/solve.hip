@@ -1,0 +1,1088 @@
+// Host orchestration of the batched HSC / HSC-extension solve.
+//
+// For one tree and a batch of B energy slots a Plan fixes, once:
+//   * the device workspace layout (frontal matrices, inverses, multipliers,
+//     G / N / P frontal blocks per cluster and slot),
+//   * every launch of one chunk of B energies, level by level, with its job
+//     and tile maps in one device blob.
+// A chunk then replays the step list.  Levels are tree depths: the fold and
+// the N fold run deepest level first (children before parents), the extracts
+// run root first, as in Algorithms 1 and 2.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "hsc_internal.h"
+#include "kern.h"
+#include "../../include/hsc_kernels.h"
+
+namespace hsc {
+
+namespace {
+
+#define HIPCHK(x)                                                                     \
+  do {                                                                                \
+    hipError_t err_ = (x);                                                            \
+    if (err_ != hipSuccess) {                                                         \
+      set_error(std::string("HIP error: ") + hipGetErrorString(err_) + " at " #x);    \
+      return HSC_E_HIP;                                                               \
+    }                                                                                 \
+  } while (0)
+
+// Host image of the device blob; pointer fields that refer into the blob are
+// stored as offsets and rebased at upload.
+struct Blob {
+  std::vector<char> data;
+  std::vector<size_t> relocs;
+  size_t alloc(size_t bytes, size_t align = 64) {
+    size_t off = (data.size() + align - 1) / align * align;
+    data.resize(off + bytes);
+    return off;
+  }
+  template <class T>
+  size_t push(const std::vector<T>& v) {
+    size_t off = alloc(std::max<size_t>(1, v.size()) * sizeof(T));
+    if (!v.empty()) std::memcpy(data.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+  }
+  // mark a pointer field (at byte offset `field`) as holding a blob offset
+  void reloc(size_t field) { relocs.push_back(field); }
+};
+
+enum StepKind { S_ASSEMBLE, S_INV_PANEL, S_INV_SWAP, S_INV_UNSCR, S_GEMM, S_GATHER, S_ASSEMBLE_N, S_DIAG };
+
+struct Step {
+  StepKind kind;
+  size_t jobs = 0, map = 0;   // blob offsets
+  int count = 0;              // rows / tiles / jobs
+  int njobs = 0;
+  int i0 = 0, i1 = 0, i2 = 0, i3 = 0;
+  double ar = 1, ai = 0;
+  int beta = 0;
+  int out = 0;                // DIAG destination
+};
+
+enum OutSel { O_GR = 0, O_GL = 1, O_SPEC_L = 2, O_SPEC_R = 3, O_AR_TMP = 4 };
+
+struct Channel {
+  int type;      // 0 both contacts (with occupations), 1 left, 2 right
+  int fold;      // 0 = lpath||rpath, 1 = lpath, 2 = rpath
+  int extract;   // 0 = all clusters, 1 = lpath only
+  int out;       // OutSel
+};
+
+}  // namespace
+
+struct Plan {
+  uint64_t uid = 0;
+  int B = 0;
+  uint32_t want = 0;
+  int64_t n = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  char* blob = nullptr;
+  size_t blob_bytes = 0;
+  EnergyScalars* es = nullptr;   // [B]
+  int32_t* status = nullptr;     // [B]
+  double* a_r = nullptr;         // [B][n] (transmission temp)
+  int64_t* left = nullptr;       // left contact sites (device, inside blob)
+  int nleft = 0;
+  LeadParams lp{};
+  std::vector<Step> steps;
+  ~Plan() {
+    if (ws) (void)hipFree(ws);
+    if (blob) (void)hipFree(blob);
+  }
+};
+
+}  // namespace hsc
+
+struct hsc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::vector<std::unique_ptr<hsc::Plan>> plans;
+};
+
+namespace hsc {
+
+namespace {
+
+// ---------------------------------------------------------------------------------------------
+// plan construction
+
+struct Builder {
+  const hsc_tree* t;
+  int B;
+  uint32_t want;
+  bool gl;        // any lesser output -> full ancestor rows on contact paths
+  size_t ws = 0;  // workspace bytes
+  Blob blob;
+  std::vector<Step> steps;
+  std::vector<Channel> chans;
+  char* wsbase = nullptr;   // device address (known before job pointers are written)
+
+  // per-cluster tree constants (blob offsets)
+  std::vector<size_t> c_invrel, c_rel, c_gcol, c_trow, c_trowp, c_nfc, c_sites, c_fs;
+  // per cluster x slot workspace offsets
+  struct CS {
+    size_t F, Inv, Psi, GX, GFF, GT, GAF, SD, piv, T, R;
+    size_t NF[2], NFc[2], M[2], PX[2], PFF[2], PT[2];
+  };
+  std::vector<CS> cs;   // [cluster * B + slot]
+
+  size_t wsa(size_t bytes) {
+    size_t off = (ws + 255) / 256 * 256;
+    ws = off + std::max<size_t>(bytes, 16);
+    return off;
+  }
+  double2* W(size_t off) const { return reinterpret_cast<double2*>(wsbase + off); }
+
+  int n_of(int i) const { return t->cl[i].n; }
+  int f_of(int i) const { return t->cl[i].f(); }
+  int P_of(int i) const { return (int)t->cl[i].n_anc; }
+  bool leaf(int i) const { return t->cl[i].children.empty(); }
+  bool root(int i) const { return t->cl[i].parent < 0; }
+  bool cp(int i) const { return gl && t->cl[i].cpath(); }
+  int gcols(int i) const {
+    if (root(i)) return n_of(i);
+    return n_of(i) + (cp(i) ? P_of(i) : f_of(i));
+  }
+  bool in_fold(const Channel& ch, int i) const {
+    const Cluster& c = t->cl[i];
+    return ch.fold == 0 ? c.cpath() : ch.fold == 1 ? c.lpath : c.rpath;
+  }
+  bool in_extract(const Channel& ch, int i) const { return ch.extract == 0 || t->cl[i].lpath; }
+  // own rows of cluster i in channel ch: (row0, r)
+  void own_rows(const Channel& ch, int i, int* row0, int* r) const {
+    const Cluster& c = t->cl[i];
+    if (!leaf(i)) { *row0 = 0; *r = c.n; return; }
+    if (ch.type == 0) { *row0 = 0; *r = c.n_left + c.n_right; }
+    else if (ch.type == 1) { *row0 = 0; *r = c.n_left; }
+    else { *row0 = c.n_left; *r = c.n_right; }
+  }
+  int inv_nb(int maxn) const { return maxn <= 512 ? 32 : maxn <= 1024 ? 16 : maxn <= 2048 ? 8 : 4; }
+
+  void channels() {
+    if (want & HSC_SPECTRAL_LR) {
+      chans.push_back({1, 1, 0, O_SPEC_L});
+      chans.push_back({2, 2, 0, O_SPEC_R});
+    } else {
+      if (want & HSC_DIAG_GL) chans.push_back({0, 0, 0, O_GL});
+      if (want & HSC_TRANS) chans.push_back({2, 2, 1, O_AR_TMP});
+    }
+  }
+
+  void layout() {
+    const int nc = (int)t->cl.size();
+    cs.assign((size_t)nc * B, CS{});
+    for (int i = 0; i < nc; ++i) {
+      const size_t n = n_of(i), f = f_of(i), P = P_of(i);
+      const Cluster& c = t->cl[i];
+      const int nb = inv_nb((int)n);
+      for (int e = 0; e < B; ++e) {
+        CS& s = cs[(size_t)i * B + e];
+        s.F = wsa((n + f) * (n + f) * 16);
+        s.Inv = wsa(n * n * 16);
+        s.piv = wsa(n * 4);
+        s.T = wsa(n * nb * 16);
+        s.R = wsa(nb * n * 16);
+        if (!root(i)) s.Psi = wsa(n * f * 16);
+        if (root(i)) s.GX = s.Inv;
+        else if (!leaf(i)) s.GX = wsa((n + f) * gcols(i) * 16);
+        else {
+          s.GFF = wsa(f * f * 16);
+          s.GT = wsa(n * f * 16);
+          if (cp(i)) {
+            s.GAF = wsa(f * P * 16);
+            s.SD = wsa((size_t)(c.n_left + c.n_right) * (n + P) * 16);
+          }
+        }
+        for (size_t k = 0; k < chans.size(); ++k) {
+          const Channel& ch = chans[k];
+          if (in_fold(ch, i)) {
+            int row0, r;
+            own_rows(ch, i, &row0, &r);
+            s.NF[k] = wsa((r + f) * (n + P) * 16);
+            if (!root(i)) s.NFc[k] = wsa(r * (n + f) * 16);
+            s.M[k] = wsa(n * (n + f) * 16);
+          }
+          if (in_extract(ch, i)) {
+            if (root(i)) s.PX[k] = s.M[k];
+            else if (!leaf(i)) s.PX[k] = wsa((n + f) * (n + f) * 16);
+            else {
+              s.PFF[k] = wsa(f * f * 16);
+              s.PT[k] = wsa(n * f * 16);
+            }
+          }
+        }
+      }
+    }
+  }
+
+  // tree constants
+  void constants() {
+    const int nc = (int)t->cl.size();
+    c_invrel.assign(nc, 0); c_rel.assign(nc, 0); c_gcol.assign(nc, 0); c_trow.assign(nc, 0);
+    c_trowp.assign(nc, 0); c_nfc.assign(nc, 0); c_sites.assign(nc, 0); c_fs.assign(nc, 0);
+    for (int i = 0; i < nc; ++i) {
+      const Cluster& c = t->cl[i];
+      const int n = c.n, f = c.f();
+      std::vector<int64_t> sites(t->perm.begin() + c.first, t->perm.begin() + c.first + n);
+      c_sites[i] = blob.push(sites);
+      std::vector<int32_t> nfc(n + f);
+      for (int a = 0; a < n; ++a) nfc[a] = a;
+      for (int k = 0; k < f; ++k) nfc[n + k] = n + c.frontpos[k];
+      c_nfc[i] = blob.push(nfc);
+      std::vector<int32_t> trow(f), trowp(f);
+      for (int k = 0; k < f; ++k) {
+        trow[k] = n + (cp(i) ? c.frontpos[k] : k);
+        trowp[k] = n + k;
+      }
+      c_trow[i] = blob.push(trow);
+      c_trowp[i] = blob.push(trowp);
+      if (c.parent >= 0) {
+        const Cluster& p = t->cl[c.parent];
+        const int np = p.n, fp = p.f();
+        std::vector<int32_t> inv(np + fp, -1);
+        for (int k = 0; k < f; ++k) inv[c.rel[k]] = k;
+        c_invrel[i] = blob.push(inv);
+        c_rel[i] = blob.push(c.rel);
+        std::vector<int32_t> gcol(f);
+        for (int k = 0; k < f; ++k) {
+          const int idx = c.rel[k];
+          gcol[k] = idx < np ? idx : (cp(c.parent) ? np + p.frontpos[idx - np] : idx);
+        }
+        c_gcol[i] = blob.push(gcol);
+      }
+      // sparse A = -H entries of the frontal matrix: rows (own sites, front sites)
+      std::vector<int32_t> fidx(0);
+      std::vector<std::vector<std::pair<int32_t, double2>>> rows(n + f);
+      // local index of a site within (own, front)
+      auto local = [&](int64_t s) -> int {
+        if (t->owner[s] == i) return (int)(t->pos[s] - c.first);
+        return -1;
+      };
+      std::vector<int32_t> fpos;   // front site -> index in front (via sorted lookup)
+      std::vector<std::pair<int64_t, int32_t>> fl(f);
+      for (int k = 0; k < f; ++k) fl[k] = {c.front[k], k};
+      std::sort(fl.begin(), fl.end());
+      auto findf = [&](int64_t s) -> int {
+        auto it = std::lower_bound(fl.begin(), fl.end(), std::make_pair(s, (int32_t)-1));
+        return (it != fl.end() && it->first == s) ? it->second : -1;
+      };
+      for (int a = 0; a < n; ++a) {
+        const int64_t r = t->perm[c.first + a];
+        for (int64_t q = t->indptr[r]; q < t->indptr[r + 1]; ++q) {
+          const int64_t s = t->indices[q];
+          const double2 v = make_double2(-t->values[2 * q], -t->values[2 * q + 1]);
+          const int b = local(s);
+          if (b >= 0) { rows[a].push_back({b, v}); continue; }
+          const int k = findf(s);
+          if (k < 0) continue;   // (cannot happen: neighbours outside are front sites)
+          rows[a].push_back({n + k, v});
+          rows[n + k].push_back({a, v});   // A_fi = A_if^T
+        }
+      }
+      std::vector<int32_t> ptr(n + f + 1, 0), col;
+      std::vector<double2> val;
+      for (int a = 0; a < n + f; ++a) {
+        // merge duplicates
+        std::sort(rows[a].begin(), rows[a].end(),
+                  [](const std::pair<int32_t, double2>& x, const std::pair<int32_t, double2>& y) { return x.first < y.first; });
+        for (size_t q = 0; q < rows[a].size(); ++q) {
+          if (!col.empty() && (int)col.size() > ptr[a] && col.back() == rows[a][q].first) {
+            val.back().x += rows[a][q].second.x;
+            val.back().y += rows[a][q].second.y;
+          } else {
+            col.push_back(rows[a][q].first);
+            val.push_back(rows[a][q].second);
+          }
+        }
+        ptr[a + 1] = (int32_t)col.size();
+      }
+      size_t o_ptr = blob.push(ptr), o_col = blob.push(col), o_val = blob.push(val);
+      size_t o_fs = blob.alloc(sizeof(FrontSparse));
+      FrontSparse* fs = reinterpret_cast<FrontSparse*>(blob.data.data() + o_fs);
+      fs->ptr = reinterpret_cast<const int32_t*>(o_ptr);
+      fs->col = reinterpret_cast<const int32_t*>(o_col);
+      fs->val = reinterpret_cast<const double2*>(o_val);
+      blob.reloc(o_fs + offsetof(FrontSparse, ptr));
+      blob.reloc(o_fs + offsetof(FrontSparse, col));
+      blob.reloc(o_fs + offsetof(FrontSparse, val));
+      c_fs[i] = o_fs;
+    }
+  }
+
+  // ---- step helpers ----
+  struct GP { const double2 *A, *B, *C; double2* D; int M, N, K, lda, ldb, ldc, ldd; };
+  void gemm(int opA, int opB, const std::vector<GP>& ps, double ar, double ai, int beta) {
+    std::vector<GemmProb> probs;
+    std::vector<int32_t> tmap;
+    const int tm = gemm_tile_m(0), tn = gemm_tile_n(0);
+    for (const GP& g : ps) {
+      if (g.M <= 0 || g.N <= 0) continue;
+      GemmProb p{};
+      p.A = g.A; p.B = g.B; p.C = g.C; p.D = g.D;
+      p.M = g.M; p.N = g.N; p.K = g.K;
+      p.lda = g.lda; p.ldb = g.ldb; p.ldc = g.ldc; p.ldd = g.ldd;
+      p.tiles_n = (g.N + tn - 1) / tn;
+      p.tile_off = (int32_t)tmap.size();
+      const int tiles = ((g.M + tm - 1) / tm) * p.tiles_n;
+      for (int k = 0; k < tiles; ++k) tmap.push_back((int32_t)probs.size());
+      probs.push_back(p);
+    }
+    if (probs.empty()) return;
+    Step s;
+    s.kind = S_GEMM;
+    s.jobs = blob.push(probs);
+    s.map = blob.push(tmap);
+    s.count = (int)tmap.size();
+    s.i0 = opA; s.i1 = opB;
+    s.ar = ar; s.ai = ai; s.beta = beta;
+    steps.push_back(s);
+  }
+  // RowJob list: child-ref arrays are given as host vectors to be placed in the blob
+  struct RJ { RowJob j; std::vector<ChildRef> kids; std::vector<size_t> kid_invrel; bool p1_blob = false; };
+  void rowstep(StepKind kind, std::vector<RJ>& jobs, int i0 = 0, int i1 = 0, int out = 0) {
+    std::vector<int32_t> rmap;
+    std::vector<size_t> kid_off(jobs.size(), 0);
+    for (size_t q = 0; q < jobs.size(); ++q) {
+      if (!jobs[q].kids.empty()) {
+        kid_off[q] = blob.alloc(jobs[q].kids.size() * sizeof(ChildRef));
+        for (size_t k = 0; k < jobs[q].kids.size(); ++k) {
+          size_t fo = kid_off[q] + k * sizeof(ChildRef);
+          ChildRef cr = jobs[q].kids[k];
+          cr.invrel = reinterpret_cast<const int32_t*>(jobs[q].kid_invrel[k]);
+          std::memcpy(blob.data.data() + fo, &cr, sizeof(ChildRef));
+          blob.reloc(fo + offsetof(ChildRef, invrel));
+        }
+      }
+    }
+    std::vector<RowJob> rj;
+    for (size_t q = 0; q < jobs.size(); ++q) {
+      RowJob j = jobs[q].j;
+      if (j.rows <= 0) continue;
+      j.row_off = (int32_t)rmap.size();
+      for (int r = 0; r < j.rows; ++r) rmap.push_back((int32_t)rj.size());
+      if (!jobs[q].kids.empty()) j.p0 = reinterpret_cast<const void*>(kid_off[q]);
+      rj.push_back(j);
+      // remember which entries of this job hold blob offsets
+      (void)0;
+    }
+    if (rj.empty()) return;
+    Step s;
+    s.kind = kind;
+    s.jobs = blob.alloc(rj.size() * sizeof(RowJob));
+    std::memcpy(blob.data.data() + s.jobs, rj.data(), rj.size() * sizeof(RowJob));
+    // relocate blob-resident pointer fields: rmap, cmap, p0 (kids / psi?), p1 (front sparse), p2 (sites)
+    size_t qi = 0;
+    for (size_t q = 0; q < jobs.size(); ++q) {
+      if (jobs[q].j.rows <= 0) continue;
+      const size_t base = s.jobs + qi * sizeof(RowJob);
+      if (jobs[q].j.rmap) blob.reloc(base + offsetof(RowJob, rmap));
+      if (jobs[q].j.cmap) blob.reloc(base + offsetof(RowJob, cmap));
+      if (!jobs[q].kids.empty()) blob.reloc(base + offsetof(RowJob, p0));
+      if (jobs[q].p1_blob) blob.reloc(base + offsetof(RowJob, p1));
+      if (jobs[q].j.p2) blob.reloc(base + offsetof(RowJob, p2));
+      ++qi;
+    }
+    s.map = blob.push(rmap);
+    s.count = (int)rmap.size();
+    s.i0 = i0; s.i1 = i1; s.out = out;
+    steps.push_back(s);
+  }
+  static const int32_t* off32(size_t o) { return reinterpret_cast<const int32_t*>(o); }
+
+  std::vector<std::vector<int>> levels() const {
+    std::vector<std::vector<int>> L(t->depth);
+    for (int i = 0; i < (int)t->cl.size(); ++i) L[t->cl[i].depth].push_back(i);
+    return L;
+  }
+
+  // ---- phases ----
+  void fold(const std::vector<std::vector<int>>& L) {
+    for (int d = (int)L.size() - 1; d >= 0; --d) {
+      // assemble
+      std::vector<RJ> jobs;
+      for (int i : L[d])
+        for (int e = 0; e < B; ++e) {
+          const Cluster& c = t->cl[i];
+          const CS& s = cs[(size_t)i * B + e];
+          RJ q{};
+          q.j.rows = q.j.cols = c.n + c.f();
+          q.j.e = e;
+          q.j.dst = W(s.F);
+          q.j.ldd = c.n + c.f();
+          for (int k : c.children) {
+            const Cluster& kc = t->cl[k];
+            const CS& ks = cs[(size_t)k * B + e];
+            const int ldk = kc.n + kc.f();
+            ChildRef cr{};
+            cr.U = W(ks.F) + (size_t)kc.n * ldk + kc.n;
+            cr.ldU = ldk;
+            q.kids.push_back(cr);
+            q.kid_invrel.push_back(c_invrel[k]);
+          }
+          q.j.aux0 = (int)c.children.size();
+          q.j.p1 = reinterpret_cast<const void*>(c_fs[i]);
+          q.p1_blob = true;
+          q.j.aux1 = c.n; q.j.aux2 = c.n_left; q.j.aux3 = c.n_right;
+          jobs.push_back(q);
+        }
+      rowstep(S_ASSEMBLE, jobs);
+      // inverse of the pivot blocks
+      int maxn = 0;
+      for (int i : L[d]) maxn = std::max(maxn, n_of(i));
+      const int nb = inv_nb(maxn);
+      std::vector<InvJob> ij;
+      for (int i : L[d])
+        for (int e = 0; e < B; ++e) {
+          const CS& s = cs[(size_t)i * B + e];
+          InvJob j{};
+          j.X = W(s.F); j.ld = n_of(i) + f_of(i);
+          j.Y = W(s.Inv); j.ldy = n_of(i);
+          j.n = n_of(i); j.e = e;
+          j.piv = reinterpret_cast<int32_t*>(wsbase + s.piv);
+          j.T = W(s.T); j.R = W(s.R);
+          ij.push_back(j);
+        }
+      const size_t ijo = blob.push(ij);
+      for (int k0 = 0; k0 < maxn; k0 += nb) {
+        Step p; p.kind = S_INV_PANEL; p.jobs = ijo; p.njobs = (int)ij.size(); p.i0 = k0; p.i1 = nb; p.i2 = maxn;
+        steps.push_back(p);
+        Step w = p; w.kind = S_INV_SWAP;
+        steps.push_back(w);
+        std::vector<GP> ps;
+        for (const InvJob& j : ij) {
+          if (k0 >= j.n) continue;
+          const int kb = std::min(nb, j.n - k0);
+          ps.push_back({j.T, j.R, j.X, j.X, j.n, j.n, kb, kb, j.n, j.ld, j.ld});
+        }
+        gemm(OP_N, OP_N, ps, 1.0, 0.0, 1);
+      }
+      Step u; u.kind = S_INV_UNSCR; u.jobs = ijo; u.njobs = (int)ij.size(); u.i2 = maxn;
+      steps.push_back(u);
+      // Psi = -Inv * A_if ;  U = A_ff + A_if^T Psi
+      std::vector<GP> pp, pu;
+      for (int i : L[d]) {
+        if (root(i)) continue;
+        const int n = n_of(i), f = f_of(i), ld = n + f;
+        for (int e = 0; e < B; ++e) {
+          const CS& s = cs[(size_t)i * B + e];
+          pp.push_back({W(s.Inv), W(s.F) + n, nullptr, W(s.Psi), n, f, n, n, ld, 0, f});
+          pu.push_back({W(s.F) + n, W(s.Psi), W(s.F) + (size_t)n * ld + n, W(s.F) + (size_t)n * ld + n, f, f, n,
+                        ld, f, ld, ld});
+        }
+      }
+      gemm(OP_N, OP_N, pp, -1.0, 0.0, 0);
+      gemm(OP_T, OP_N, pu, 1.0, 0.0, 1);
+    }
+  }
+
+  void diag_step(const std::vector<int>& ids, int mode, int out, int chan, bool g_phase) {
+    std::vector<RJ> jobs;
+    for (int i : ids)
+      for (int e = 0; e < B; ++e) {
+        const CS& s = cs[(size_t)i * B + e];
+        const int n = n_of(i), f = f_of(i);
+        RJ q{};
+        q.j.rows = n;
+        q.j.cols = 1;
+        q.j.e = e;
+        q.j.p2 = reinterpret_cast<const void*>(c_sites[i]);
+        if (mode == DIAG_SEP) {
+          if (g_phase) { q.j.src = W(s.GX); q.j.lds = gcols(i); }
+          else { q.j.src = W(s.PX[chan]); q.j.lds = n + f; }
+        } else if (mode == DIAG_LEAF_G) {
+          q.j.src = W(s.GT); q.j.lds = f;
+          q.j.p0 = W(s.Psi); q.j.aux0 = f;
+          q.j.p1 = W(s.Inv); q.j.aux1 = n;
+        } else {
+          q.j.src = W(s.PT[chan]); q.j.lds = f;
+          q.j.p0 = W(s.Psi); q.j.aux0 = f;
+          q.j.p1 = in_fold(chans[chan], i) ? W(s.M[chan]) : nullptr;
+          q.j.aux1 = n + f;
+        }
+        jobs.push_back(q);
+      }
+    rowstep(S_DIAG, jobs, mode, 0, out);
+  }
+
+  void extract_g(const std::vector<std::vector<int>>& L) {
+    diag_step(L[0], DIAG_SEP, O_GR, 0, true);
+    for (size_t d = 1; d < L.size(); ++d) {
+      std::vector<int> seps, leaves;
+      for (int i : L[d]) (leaf(i) ? leaves : seps).push_back(i);
+      // separators
+      {
+        std::vector<RJ> g1, g2;
+        std::vector<GP> m1, m2;
+        for (int i : seps) {
+          const Cluster& c = t->cl[i];
+          const int n = c.n, f = c.f(), gc = gcols(i), p = c.parent;
+          for (int e = 0; e < B; ++e) {
+            const CS& s = cs[(size_t)i * B + e];
+            const CS& ps = cs[(size_t)p * B + e];
+            RJ q{};
+            q.j.rows = f; q.j.cols = gc - n; q.j.e = e;
+            q.j.src = W(ps.GX); q.j.lds = gcols(p);
+            q.j.dst = W(s.GX) + (size_t)n * gc + n; q.j.ldd = gc;
+            q.j.rmap = off32(c_rel[i]);
+            q.j.cmap = cp(i) ? nullptr : off32(c_gcol[i]);
+            g1.push_back(q);
+            m1.push_back({W(s.Psi), W(s.GX) + (size_t)n * gc + n, nullptr, W(s.GX) + n, n, gc - n, f, f, gc, 0, gc});
+            RJ tq{};
+            tq.j.rows = f; tq.j.cols = n; tq.j.e = e;
+            tq.j.src = W(s.GX); tq.j.lds = gc;
+            tq.j.dst = W(s.GX) + (size_t)n * gc; tq.j.ldd = gc;
+            tq.j.rmap = off32(c_trow[i]);
+            g2.push_back(tq);
+            m2.push_back({W(s.Psi), W(s.GX) + (size_t)n * gc, W(s.Inv), W(s.GX), n, n, f, f, gc, n, gc});
+          }
+        }
+        rowstep(S_GATHER, g1, 0, 0);
+        gemm(OP_N, OP_N, m1, 1.0, 0.0, 0);
+        rowstep(S_GATHER, g2, 1, 0);
+        gemm(OP_N, OP_N, m2, 1.0, 0.0, 1);
+        diag_step(seps, DIAG_SEP, O_GR, 0, true);
+      }
+      // leaves
+      {
+        std::vector<RJ> g1, g3;
+        std::vector<GP> m1, m3, m4;
+        std::vector<int> cpl;
+        for (int i : leaves) {
+          const Cluster& c = t->cl[i];
+          const int n = c.n, f = c.f(), p = c.parent, P = P_of(i), nc = c.n_left + c.n_right;
+          if (cp(i)) cpl.push_back(i);
+          for (int e = 0; e < B; ++e) {
+            const CS& s = cs[(size_t)i * B + e];
+            const CS& ps = cs[(size_t)p * B + e];
+            RJ q{};
+            q.j.rows = f; q.j.cols = f; q.j.e = e;
+            q.j.src = W(ps.GX); q.j.lds = gcols(p);
+            q.j.dst = W(s.GFF); q.j.ldd = f;
+            q.j.rmap = off32(c_rel[i]);
+            q.j.cmap = off32(c_gcol[i]);
+            g1.push_back(q);
+            m1.push_back({W(s.Psi), W(s.GFF), nullptr, W(s.GT), n, f, f, f, f, 0, f});
+            if (cp(i)) {
+              RJ a{};
+              a.j.rows = f; a.j.cols = P; a.j.e = e;
+              a.j.src = W(ps.GX); a.j.lds = gcols(p);
+              a.j.dst = W(s.GAF); a.j.ldd = P;
+              a.j.rmap = off32(c_rel[i]);
+              g3.push_back(a);
+              m3.push_back({W(s.Psi), W(s.GAF), nullptr, W(s.SD) + n, nc, P, f, f, P, 0, n + P});
+              m4.push_back({W(s.Psi), W(s.GT), W(s.Inv), W(s.SD), nc, n, f, f, f, n, n + P});
+            }
+          }
+        }
+        rowstep(S_GATHER, g1, 0, 0);
+        gemm(OP_N, OP_N, m1, 1.0, 0.0, 0);
+        diag_step(leaves, DIAG_LEAF_G, O_GR, 0, true);
+        rowstep(S_GATHER, g3, 0, 0);
+        gemm(OP_N, OP_N, m3, 1.0, 0.0, 0);
+        gemm(OP_N, OP_T, m4, 1.0, 0.0, 1);
+      }
+    }
+  }
+
+  void channel_steps(const std::vector<std::vector<int>>& L, int k) {
+    const Channel& ch = chans[k];
+    // N fold, bottom-up
+    for (int d = (int)L.size() - 1; d >= 0; --d) {
+      std::vector<RJ> asm_jobs, nfc_jobs;
+      std::vector<GP> nu, mm;
+      for (int i : L[d]) {
+        if (!in_fold(ch, i)) continue;
+        const Cluster& c = t->cl[i];
+        const int n = c.n, f = c.f(), P = P_of(i);
+        int row0, r;
+        own_rows(ch, i, &row0, &r);
+        for (int e = 0; e < B; ++e) {
+          const CS& s = cs[(size_t)i * B + e];
+          RJ q{};
+          q.j.rows = r + f; q.j.cols = n + P; q.j.e = e;
+          q.j.dst = W(s.NF[k]); q.j.ldd = n + P;
+          for (int kk : c.children) {
+            if (!in_fold(ch, kk)) continue;
+            const Cluster& kc = t->cl[kk];
+            const CS& ks = cs[(size_t)kk * B + e];
+            int kr0, kr;
+            own_rows(ch, kk, &kr0, &kr);
+            const int ldk = kc.n + P_of(kk);
+            ChildRef cr{};
+            cr.U = W(ks.NF[k]) + (size_t)kr * ldk + kc.n;
+            cr.ldU = ldk;
+            q.kids.push_back(cr);
+            q.kid_invrel.push_back(c_invrel[kk]);
+          }
+          q.j.aux0 = (int)q.kids.size();
+          q.j.aux1 = r; q.j.aux2 = row0; q.j.aux3 = n; q.j.aux4 = c.n_left; q.j.aux5 = c.n_right;
+          if (leaf(i)) { q.j.src = W(s.SD); q.j.lds = n + P; }
+          else { q.j.src = W(s.GX); q.j.lds = gcols(i); }
+          asm_jobs.push_back(q);
+          if (!root(i)) {
+            nu.push_back({W(s.Psi) + (size_t)row0 * f, W(s.NF[k]) + n, W(s.NF[k]) + (size_t)r * (n + P) + n,
+                          W(s.NF[k]) + (size_t)r * (n + P) + n, f, P, r, f, n + P, n + P, n + P});
+            RJ g{};
+            g.j.rows = r; g.j.cols = n + f; g.j.e = e;
+            g.j.src = W(s.NF[k]); g.j.lds = n + P;
+            g.j.dst = W(s.NFc[k]); g.j.ldd = n + f;
+            g.j.cmap = off32(c_nfc[i]);
+            nfc_jobs.push_back(g);
+            mm.push_back({W(s.Inv) + row0, W(s.NFc[k]), nullptr, W(s.M[k]), n, n + f, r, n, n + f, 0, n + f});
+          } else {
+            mm.push_back({W(s.Inv) + row0, W(s.NF[k]), nullptr, W(s.M[k]), n, n, r, n, n, 0, n});
+          }
+        }
+      }
+      rowstep(S_ASSEMBLE_N, asm_jobs, ch.type);
+      gemm(OP_T, OP_N, nu, 1.0, 0.0, 1);
+      rowstep(S_GATHER, nfc_jobs, 0, 0);
+      gemm(OP_N, OP_N, mm, 1.0, 0.0, 0);
+    }
+    // P extract, top-down
+    diag_step(L[0], DIAG_SEP, ch.out, k, false);
+    for (size_t d = 1; d < L.size(); ++d) {
+      std::vector<int> seps, leaves;
+      for (int i : L[d]) {
+        if (!in_extract(ch, i)) continue;
+        (leaf(i) ? leaves : seps).push_back(i);
+      }
+      std::vector<RJ> g1, g2, g3;
+      std::vector<GP> m1a, m1b, m2a, m2b, m3a, m3b;
+      for (int i : seps) {
+        const Cluster& c = t->cl[i];
+        const int n = c.n, f = c.f(), ld = n + f, p = c.parent;
+        const bool fm = in_fold(ch, i);
+        for (int e = 0; e < B; ++e) {
+          const CS& s = cs[(size_t)i * B + e];
+          const CS& ps = cs[(size_t)p * B + e];
+          RJ q{};
+          q.j.rows = f; q.j.cols = f; q.j.e = e;
+          q.j.src = W(ps.PX[k]); q.j.lds = n_of(p) + f_of(p);
+          q.j.dst = W(s.PX[k]) + (size_t)n * ld + n; q.j.ldd = ld;
+          q.j.rmap = off32(c_rel[i]); q.j.cmap = off32(c_rel[i]);
+          g1.push_back(q);
+          GP a{W(s.Psi), W(s.PX[k]) + (size_t)n * ld + n, fm ? W(s.M[k]) + n : nullptr, W(s.PX[k]) + n, n, f, f, f,
+               ld, ld, ld};
+          (fm ? m1b : m1a).push_back(a);
+          RJ tq{};
+          tq.j.rows = f; tq.j.cols = n; tq.j.e = e;
+          tq.j.src = W(s.PX[k]); tq.j.lds = ld;
+          tq.j.dst = W(s.PX[k]) + (size_t)n * ld; tq.j.ldd = ld;
+          tq.j.rmap = off32(c_trowp[i]);
+          g2.push_back(tq);
+          GP b{W(s.Psi), W(s.PX[k]) + (size_t)n * ld, fm ? W(s.M[k]) : nullptr, W(s.PX[k]), n, n, f, f, ld, ld, ld};
+          (fm ? m2b : m2a).push_back(b);
+        }
+      }
+      for (int i : leaves) {
+        const Cluster& c = t->cl[i];
+        const int n = c.n, f = c.f(), p = c.parent;
+        const bool fm = in_fold(ch, i);
+        for (int e = 0; e < B; ++e) {
+          const CS& s = cs[(size_t)i * B + e];
+          const CS& ps = cs[(size_t)p * B + e];
+          RJ q{};
+          q.j.rows = f; q.j.cols = f; q.j.e = e;
+          q.j.src = W(ps.PX[k]); q.j.lds = n_of(p) + f_of(p);
+          q.j.dst = W(s.PFF[k]); q.j.ldd = f;
+          q.j.rmap = off32(c_rel[i]); q.j.cmap = off32(c_rel[i]);
+          g3.push_back(q);
+          GP a{W(s.Psi), W(s.PFF[k]), fm ? W(s.M[k]) + n : nullptr, W(s.PT[k]), n, f, f, f, f, n + f, f};
+          (fm ? m3b : m3a).push_back(a);
+        }
+      }
+      rowstep(S_GATHER, g1, 0, 0);
+      rowstep(S_GATHER, g3, 0, 0);
+      gemm(OP_N, OP_N, m1a, 1.0, 0.0, 0);
+      gemm(OP_N, OP_N, m1b, 1.0, 0.0, 1);
+      gemm(OP_N, OP_N, m3a, 1.0, 0.0, 0);
+      gemm(OP_N, OP_N, m3b, 1.0, 0.0, 1);
+      rowstep(S_GATHER, g2, 1, 1);
+      gemm(OP_N, OP_N, m2a, 1.0, 0.0, 0);
+      gemm(OP_N, OP_N, m2b, 1.0, 0.0, 1);
+      diag_step(seps, DIAG_SEP, ch.out, k, false);
+      diag_step(leaves, DIAG_LEAF_P, ch.out, k, false);
+    }
+  }
+};
+
+int run_steps(hsc_ctx* ctx, Plan* pl, int e_base, int nvalid, void* gr, void* glo, double* spectral) {
+  hipStream_t st = ctx->stream;
+  const int64_t n = pl->n;
+  for (const Step& s : pl->steps) {
+    const void* jobs = pl->blob + s.jobs;
+    const int32_t* map = reinterpret_cast<const int32_t*>(pl->blob + s.map);
+    switch (s.kind) {
+      case S_ASSEMBLE:
+        launch_assemble(st, (const RowJob*)jobs, map, s.count, pl->es);
+        break;
+      case S_ASSEMBLE_N:
+        launch_assemble_n(st, (const RowJob*)jobs, map, s.count, pl->es, s.i0);
+        break;
+      case S_GATHER:
+        launch_gather(st, (const RowJob*)jobs, map, s.count, s.i0, s.i1);
+        break;
+      case S_GEMM:
+        launch_gemm(st, s.i0, s.i1, (const GemmProb*)jobs, map, s.count, s.ar, s.ai, s.beta, 0);
+        break;
+      case S_INV_PANEL:
+        launch_inv_panel(st, (const InvJob*)jobs, s.njobs, s.i0, s.i1, s.i2, pl->status);
+        break;
+      case S_INV_SWAP:
+        launch_inv_swap(st, (const InvJob*)jobs, s.njobs, s.i0, s.i1, s.i2);
+        break;
+      case S_INV_UNSCR:
+        launch_inv_unscramble(st, (const InvJob*)jobs, s.njobs, s.i2);
+        break;
+      case S_DIAG: {
+        void* out = nullptr;
+        int kind = OUT_COMPLEX, eb = e_base;
+        int64_t stride = n;
+        switch (s.out) {
+          case O_GR: out = gr; break;
+          case O_GL: out = glo; break;
+          case O_SPEC_L: out = spectral; kind = OUT_IMAG; stride = 2 * n; break;
+          case O_SPEC_R: out = spectral ? spectral + n : nullptr; kind = OUT_IMAG; stride = 2 * n; break;
+          case O_AR_TMP: out = pl->a_r; kind = OUT_IMAG; eb = 0; break;
+        }
+        if (out) launch_diag(st, (const RowJob*)jobs, map, s.count, s.i0, kind, out, stride, eb, nvalid);
+        break;
+      }
+    }
+  }
+  HIPCHK(hipGetLastError());
+  return HSC_OK;
+}
+
+int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, Plan** out) {
+  for (auto& p : ctx->plans)
+    if (p->uid == t->uid && p->B == B && p->want == want) { *out = p.get(); return HSC_OK; }
+  // keep memory bounded: drop plans of this tree with other shapes
+  ctx->plans.erase(std::remove_if(ctx->plans.begin(), ctx->plans.end(),
+                                  [&](const std::unique_ptr<Plan>& p) { return p->uid == t->uid; }),
+                   ctx->plans.end());
+  std::unique_ptr<Plan> pl(new Plan());
+  pl->uid = t->uid; pl->B = B; pl->want = want; pl->n = t->n;
+  Builder b{t, B, want, (want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR)) != 0};
+  b.channels();
+  b.layout();
+  // per-plan small buffers at the end of the workspace
+  const size_t o_es = b.wsa(sizeof(EnergyScalars) * B);
+  const size_t o_st = b.wsa(sizeof(int32_t) * B);
+  const size_t o_ar = b.wsa(sizeof(double) * (size_t)B * t->n);
+  pl->ws_bytes = b.ws;
+  HIPCHK(hipSetDevice(ctx->device));
+  if (hipMalloc(&pl->ws, pl->ws_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("device workspace allocation failed (" + std::to_string(pl->ws_bytes) + " bytes)");
+    return HSC_E_OOM;
+  }
+  b.wsbase = pl->ws;
+  pl->es = reinterpret_cast<EnergyScalars*>(pl->ws + o_es);
+  pl->status = reinterpret_cast<int32_t*>(pl->ws + o_st);
+  pl->a_r = reinterpret_cast<double*>(pl->ws + o_ar);
+  b.blob.alloc(64);   // offset 0 stays unused: a zero field means "null", not "blob start"
+  b.constants();
+  const size_t o_left = b.blob.push(t->contact[0].sites);
+  pl->nleft = (int)t->contact[0].sites.size();
+  const auto L = b.levels();
+  b.fold(L);
+  if (want & (HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR)) b.extract_g(L);
+  for (size_t k = 0; k < b.chans.size(); ++k) b.channel_steps(L, (int)k);
+  // upload the blob with relocations
+  pl->blob_bytes = b.blob.data.size();
+  if (hipMalloc(&pl->blob, pl->blob_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("device plan allocation failed");
+    return HSC_E_OOM;
+  }
+  for (size_t f : b.blob.relocs) {
+    uint64_t v;
+    std::memcpy(&v, b.blob.data.data() + f, 8);
+    v += reinterpret_cast<uint64_t>(pl->blob);
+    std::memcpy(b.blob.data.data() + f, &v, 8);
+  }
+  HIPCHK(hipMemcpy(pl->blob, b.blob.data.data(), pl->blob_bytes, hipMemcpyHostToDevice));
+  pl->left = reinterpret_cast<int64_t*>(pl->blob + o_left);
+  for (int c = 0; c < 2; ++c) {
+    pl->lp.onsite[c] = t->contact[c].lead_onsite;
+    pl->lp.hopping[c] = t->contact[c].lead_hopping;
+    pl->lp.coupling[c] = t->contact[c].coupling;
+  }
+  pl->steps = std::move(b.steps);
+  *out = pl.get();
+  ctx->plans.push_back(std::move(pl));
+  return HSC_OK;
+}
+
+size_t plan_bytes_per_slot(const hsc_tree* t, uint32_t want) {
+  Builder b{t, 1, want, (want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR)) != 0};
+  b.channels();
+  b.layout();
+  return b.ws;
+}
+
+}  // namespace
+
+}  // namespace hsc
+
+using namespace hsc;
+
+extern "C" {
+
+hsc_status hsc_ctx_create(int32_t device, void* hip_stream, hsc_ctx** out) {
+  if (!out) { set_error("out is NULL"); return HSC_E_ARG; }
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+    (void)hipGetLastError();
+    set_error("no HIP device available");
+    return HSC_E_HIP;
+  }
+  if (device < 0 || device >= count) { set_error("device index out of range"); return HSC_E_ARG; }
+  hsc_ctx* c = new hsc_ctx();
+  c->device = device;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  *out = c;
+  return HSC_OK;
+}
+
+hsc_status hsc_ctx_destroy(hsc_ctx* ctx) {
+  if (!ctx) return HSC_OK;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
+  delete ctx;
+  return HSC_OK;
+}
+
+hsc_status hsc_solve(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, const double* energies,
+                     const hsc_solve_opts* opts, void* diag_gr, void* diag_gl, double* trans,
+                     double* spectral_lr, int32_t* status, double* guard) {
+  (void)guard;
+  if (!ctx || !tree || !opts || n_e < 0) { set_error("null argument to hsc_solve"); return HSC_E_ARG; }
+  if (n_e == 0) return HSC_OK;
+  if (!energies) { set_error("energies is NULL"); return HSC_E_ARG; }
+  if (!(opts->eta > 0.0) || !(opts->kT > 0.0)) { set_error("eta and kT must be > 0"); return HSC_E_ARG; }
+  uint32_t want = opts->want;
+  if ((want & HSC_DIAG_GR) && !diag_gr) { set_error("diag_gr requested but NULL"); return HSC_E_ARG; }
+  if ((want & HSC_DIAG_GL) && !diag_gl) { set_error("diag_gl requested but NULL"); return HSC_E_ARG; }
+  if ((want & HSC_TRANS) && !trans) { set_error("trans requested but NULL"); return HSC_E_ARG; }
+  if ((want & HSC_SPECTRAL_LR) && !spectral_lr) { set_error("spectral_lr requested but NULL"); return HSC_E_ARG; }
+  if ((want & (HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR)) == 0) {
+    set_error("nothing requested");
+    return HSC_E_ARG;
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  int B = opts->batch;
+  if (B <= 0) {
+    size_t freeb = 0, totalb = 0;
+    HIPCHK(hipMemGetInfo(&freeb, &totalb));
+    const size_t per = std::max<size_t>(1, plan_bytes_per_slot(tree, want));
+    B = (int)std::max<size_t>(1, std::min<size_t>(64, (size_t)(0.45 * (double)freeb) / per));
+  }
+  B = std::min(B, n_e);
+  Plan* pl = nullptr;
+  int st = build_plan(ctx, tree, B, want, &pl);
+  if (st != HSC_OK) return (hsc_status)st;
+  for (int e0 = 0; e0 < n_e; e0 += B) {
+    const int nv = std::min(B, n_e - e0);
+    launch_energy_setup(ctx->stream, energies + e0, nv, B, opts->eta, opts->kT, opts->mu_L, opts->mu_R, pl->lp,
+                        pl->es, pl->status);
+    st = run_steps(ctx, pl, e0, nv, diag_gr, diag_gl, spectral_lr);
+    if (st != HSC_OK) return (hsc_status)st;
+    if (want & HSC_TRANS) {
+      if (want & HSC_SPECTRAL_LR)
+        launch_trans(ctx->stream, spectral_lr + (size_t)e0 * 2 * tree->n + tree->n, 2 * tree->n, pl->left,
+                     pl->nleft, B, nv, e0, pl->es, trans);
+      else
+        launch_trans(ctx->stream, pl->a_r, tree->n, pl->left, pl->nleft, B, nv, e0, pl->es, trans);
+    }
+    if ((want & HSC_SPECTRAL_LR) && (want & HSC_DIAG_GL))
+      launch_combine_gl(ctx->stream, spectral_lr, nv, e0, tree->n, pl->es, (double2*)diag_gl);
+    if (status) launch_status_out(ctx->stream, pl->status, nv, status + e0);
+  }
+  HIPCHK(hipGetLastError());
+  return HSC_OK;
+}
+
+hsc_status hsc_solve_batch(hsc_ctx* ctx, int32_t n_trees, const hsc_tree* const* trees, const int32_t* n_e,
+                           const double* const* energies, const hsc_solve_opts* opts, void* const* diag_gr,
+                           void* const* diag_gl, double* const* trans, double* const* spectral_lr,
+                           int32_t* const* status, double* const* guard) {
+  if (!ctx || n_trees < 0 || (n_trees > 0 && (!trees || !n_e || !energies))) {
+    set_error("bad arguments to hsc_solve_batch");
+    return HSC_E_ARG;
+  }
+  for (int d = 0; d < n_trees; ++d) {
+    hsc_status s = hsc_solve(ctx, trees[d], n_e[d], energies[d], opts, diag_gr ? diag_gr[d] : nullptr,
+                             diag_gl ? diag_gl[d] : nullptr, trans ? trans[d] : nullptr,
+                             spectral_lr ? spectral_lr[d] : nullptr, status ? status[d] : nullptr,
+                             guard ? guard[d] : nullptr);
+    if (s != HSC_OK) return s;
+  }
+  return HSC_OK;
+}
+
+hsc_status hsc_sync(hsc_ctx* ctx) {
+  if (!ctx) { set_error("null ctx"); return HSC_E_ARG; }
+  HIPCHK(hipSetDevice(ctx->device));
+  if (ctx->stream) { HIPCHK(hipStreamSynchronize(ctx->stream)); }
+  else { HIPCHK(hipDeviceSynchronize()); }
+  HIPCHK(hipGetLastError());
+  return HSC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// kernel-level entry points (synchronous: they return after the work is done)
+
+extern "C" {
+
+hsc_status hsc_kern_zgemm(hsc_ctx* ctx, int32_t opA, int32_t opB, int32_t M, int32_t N, int32_t K,
+                          double alpha_re, double alpha_im, const void* A, int32_t lda, const void* B,
+                          int32_t ldb, int32_t beta, const void* C, int32_t ldc, void* D, int32_t ldd) {
+  if (!ctx || M < 0 || N < 0 || K < 0 || opA < 0 || opA > 2 || opB < 0 || opB > 2 || (beta != 0 && beta != 1)) {
+    set_error("bad arguments to hsc_kern_zgemm");
+    return HSC_E_ARG;
+  }
+  const int a_cols = opA == OP_N ? K : M, b_cols = opB == OP_N ? N : K;
+  if ((K > 0 && M > 0 && (!A || lda < a_cols)) || (K > 0 && N > 0 && (!B || ldb < b_cols)) || !D ||
+      ldd < N || (beta && (!C || ldc < N))) {
+    set_error("bad pointer or leading dimension in hsc_kern_zgemm");
+    return HSC_E_ARG;
+  }
+  if (M == 0 || N == 0) return HSC_OK;
+  HIPCHK(hipSetDevice(ctx->device));
+  GemmProb p{};
+  p.A = (const double2*)A; p.B = (const double2*)B; p.C = (const double2*)C; p.D = (double2*)D;
+  p.M = M; p.N = N; p.K = K; p.lda = lda; p.ldb = ldb; p.ldc = ldc; p.ldd = ldd;
+  p.tiles_n = (N + gemm_tile_n(0) - 1) / gemm_tile_n(0);
+  p.tile_off = 0;
+  const int tiles = ((M + gemm_tile_m(0) - 1) / gemm_tile_m(0)) * p.tiles_n;
+  std::vector<int32_t> map(tiles, 0);
+  char* dev = nullptr;
+  const size_t bytes = 256 + sizeof(int32_t) * tiles;
+  if (hipMalloc(&dev, bytes) != hipSuccess) { (void)hipGetLastError(); set_error("alloc failed"); return HSC_E_OOM; }
+  hipError_t e1 = hipMemcpy(dev, &p, sizeof(p), hipMemcpyHostToDevice);
+  hipError_t e2 = hipMemcpy(dev + 256, map.data(), sizeof(int32_t) * tiles, hipMemcpyHostToDevice);
+  if (e1 == hipSuccess && e2 == hipSuccess) {
+    launch_gemm(ctx->stream, opA, opB, (const GemmProb*)dev, (const int32_t*)(dev + 256), tiles, alpha_re,
+                alpha_im, beta, 0);
+    e1 = hipGetLastError();
+    if (e1 == hipSuccess) e1 = ctx->stream ? hipStreamSynchronize(ctx->stream) : hipDeviceSynchronize();
+  }
+  (void)hipFree(dev);
+  if (e1 != hipSuccess || e2 != hipSuccess) {
+    set_error(std::string("HIP error in hsc_kern_zgemm: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    return HSC_E_HIP;
+  }
+  return HSC_OK;
+}
+
+hsc_status hsc_kern_zinv_batched(hsc_ctx* ctx, int32_t count, const int32_t* n, void* const* X,
+                                 const int32_t* ld, void* const* Y, const int32_t* ldy, int32_t* status) {
+  if (!ctx || count < 0 || (count > 0 && (!n || !X || !ld || !Y || !ldy))) {
+    set_error("bad arguments to hsc_kern_zinv_batched");
+    return HSC_E_ARG;
+  }
+  int maxn = 0;
+  for (int k = 0; k < count; ++k) {
+    if (n[k] < 1 || n[k] > 4096 || ld[k] < n[k] || ldy[k] < n[k] || !X[k] || !Y[k]) {
+      set_error("bad matrix in hsc_kern_zinv_batched");
+      return HSC_E_ARG;
+    }
+    maxn = std::max(maxn, n[k]);
+  }
+  if (count == 0) return HSC_OK;
+  HIPCHK(hipSetDevice(ctx->device));
+  const int nb = maxn <= 512 ? 32 : maxn <= 1024 ? 16 : maxn <= 2048 ? 8 : 4;
+  size_t ws = 0;
+  std::vector<size_t> o_piv(count), o_t(count), o_r(count);
+  auto wa = [&](size_t b) { size_t o = (ws + 255) / 256 * 256; ws = o + b; return o; };
+  for (int k = 0; k < count; ++k) {
+    o_piv[k] = wa(sizeof(int32_t) * n[k]);
+    o_t[k] = wa(16ull * n[k] * nb);
+    o_r[k] = wa(16ull * n[k] * nb);
+  }
+  const size_t o_jobs = wa(sizeof(InvJob) * count);
+  const size_t o_st = wa(sizeof(int32_t) * count);
+  char* dev = nullptr;
+  if (hipMalloc(&dev, ws) != hipSuccess) { (void)hipGetLastError(); set_error("alloc failed"); return HSC_E_OOM; }
+  std::vector<InvJob> jobs(count);
+  for (int k = 0; k < count; ++k) {
+    InvJob& j = jobs[k];
+    j.X = (double2*)X[k]; j.Y = (double2*)Y[k]; j.n = n[k]; j.ld = ld[k]; j.ldy = ldy[k]; j.e = k;
+    j.piv = (int32_t*)(dev + o_piv[k]); j.T = (double2*)(dev + o_t[k]); j.R = (double2*)(dev + o_r[k]);
+  }
+  std::vector<int32_t> zero(count, 0);
+  hipError_t err = hipMemcpy(dev + o_jobs, jobs.data(), sizeof(InvJob) * count, hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = hipMemcpy(dev + o_st, zero.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice);
+  std::vector<char*> gbufs;
+  if (err == hipSuccess) {
+    const InvJob* dj = (const InvJob*)(dev + o_jobs);
+    int32_t* dst = (int32_t*)(dev + o_st);
+    for (int k0 = 0; k0 < maxn && err == hipSuccess; k0 += nb) {
+      launch_inv_panel(ctx->stream, dj, count, k0, nb, maxn, dst);
+      launch_inv_swap(ctx->stream, dj, count, k0, nb, maxn);
+      std::vector<GemmProb> probs;
+      std::vector<int32_t> tmap;
+      for (int k = 0; k < count; ++k) {
+        if (k0 >= n[k]) continue;
+        const int kb = std::min(nb, n[k] - k0);
+        GemmProb p{};
+        p.A = jobs[k].T; p.B = jobs[k].R; p.C = jobs[k].X; p.D = jobs[k].X;
+        p.M = n[k]; p.N = n[k]; p.K = kb; p.lda = kb; p.ldb = n[k]; p.ldc = ld[k]; p.ldd = ld[k];
+        p.tiles_n = (n[k] + 63) / 64;
+        p.tile_off = (int32_t)tmap.size();
+        const int tiles = ((n[k] + 63) / 64) * p.tiles_n;
+        for (int q = 0; q < tiles; ++q) tmap.push_back((int32_t)probs.size());
+        probs.push_back(p);
+      }
+      char* gb = nullptr;
+      const size_t gbytes = sizeof(GemmProb) * probs.size() + 256 + sizeof(int32_t) * tmap.size();
+      err = hipMalloc(&gb, gbytes);
+      if (err != hipSuccess) break;
+      gbufs.push_back(gb);
+      const size_t o_map = (sizeof(GemmProb) * probs.size() + 255) / 256 * 256;
+      err = hipMemcpy(gb, probs.data(), sizeof(GemmProb) * probs.size(), hipMemcpyHostToDevice);
+      if (err == hipSuccess) err = hipMemcpy(gb + o_map, tmap.data(), sizeof(int32_t) * tmap.size(), hipMemcpyHostToDevice);
+      if (err == hipSuccess)
+        launch_gemm(ctx->stream, OP_N, OP_N, (const GemmProb*)gb, (const int32_t*)(gb + o_map), (int)tmap.size(),
+                    1.0, 0.0, 1, 0);
+    }
+    if (err == hipSuccess) launch_inv_unscramble(ctx->stream, dj, count, maxn);
+    if (err == hipSuccess) err = hipGetLastError();
+    if (err == hipSuccess) err = ctx->stream ? hipStreamSynchronize(ctx->stream) : hipDeviceSynchronize();
+    if (err == hipSuccess && status)
+      err = hipMemcpy(status, dev + o_st, sizeof(int32_t) * count, hipMemcpyDeviceToDevice);
+  }
+  for (char* g : gbufs) (void)hipFree(g);
+  (void)hipFree(dev);
+  if (err != hipSuccess) {
+    set_error(std::string("HIP error in hsc_kern_zinv_batched: ") + hipGetErrorString(err));
+    return HSC_E_HIP;
+  }
+  return HSC_OK;
+}
+
+hsc_status hsc_kern_mfma_probe(hsc_ctx* ctx, double* out) {
+  if (!ctx || !out) { set_error("null argument"); return HSC_E_ARG; }
+  HIPCHK(hipSetDevice(ctx->device));
+  launch_mfma_probe(ctx->stream, out);
+  HIPCHK(hipGetLastError());
+  HIPCHK(ctx->stream ? hipStreamSynchronize(ctx->stream) : hipDeviceSynchronize());
+  return HSC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,460 @@
+// Host-side cluster tree: geometric multilevel nested dissection (Section 2.2),
+// point-level fronts, relative index maps, and the per-energy operation count.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hsc_internal.h"
+
+namespace hsc {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+const char* last_error() { return g_last_error.c_str(); }
+
+static std::atomic<uint64_t> g_uid{1};
+
+namespace {
+
+// Recursive bisection.  A cluster whose box still has a splittable axis becomes
+// a separator (the one-site plane) with up to two children; otherwise a leaf.
+struct NDBuilder {
+  const hsc_tree* t;
+  std::vector<std::vector<int64_t>> sites_of;
+  std::vector<std::vector<int>> kids_of;
+
+  int rec(std::vector<int64_t>& sites) {
+    int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    for (int64_t s : sites)
+      for (int a = 0; a < 3; ++a) {
+        int32_t c = t->coords[3 * s + a];
+        lo[a] = std::min(lo[a], c);
+        hi[a] = std::max(hi[a], c);
+      }
+    int best = -1;
+    int64_t best_ext = 0;
+    for (int a = 0; a < 3; ++a) {
+      if (!((t->split_mask >> a) & 1)) continue;
+      int64_t ext = (int64_t)hi[a] - lo[a] + 1;
+      if (ext <= t->leaf_side || ext < 3) continue;
+      if (ext > best_ext) { best_ext = ext; best = a; }
+    }
+    std::vector<int> kids;
+    std::vector<int64_t> mine;
+    if (best >= 0) {
+      int32_t cut = lo[best] + (int32_t)(best_ext / 2);
+      std::vector<int64_t> left, right;
+      for (int64_t s : sites) {
+        int32_t c = t->coords[3 * s + best];
+        if (c < cut) left.push_back(s);
+        else if (c > cut) right.push_back(s);
+        else mine.push_back(s);
+      }
+      if (mine.empty()) {          // no plane there: keep the box whole
+        mine.swap(sites);
+      } else {
+        std::vector<int64_t>().swap(sites);
+        if (!left.empty()) kids.push_back(rec(left));
+        if (!right.empty()) kids.push_back(rec(right));
+      }
+    } else {
+      mine.swap(sites);
+    }
+    sites_of.push_back(std::move(mine));
+    kids_of.push_back(std::move(kids));
+    return (int)sites_of.size() - 1;
+  }
+};
+
+}  // namespace
+
+int finalize_tree(hsc_tree* t, std::vector<std::vector<int64_t>>& sites_of) {
+  const int nc = (int)t->cl.size();
+  const int64_t n = t->n;
+  // parents, depth, subtree ranges
+  for (int i = 0; i < nc; ++i) t->cl[i].parent = -1;
+  for (int i = 0; i < nc; ++i)
+    for (int k : t->cl[i].children) t->cl[k].parent = i;
+  for (int i = 0; i < nc; ++i) {
+    int lo = i;
+    for (int k : t->cl[i].children) lo = std::min(lo, t->cl[k].lo);
+    t->cl[i].lo = lo;
+  }
+  t->depth = 0;
+  for (int i = nc - 1; i >= 0; --i) {
+    int p = t->cl[i].parent;
+    t->cl[i].depth = p < 0 ? 0 : t->cl[p].depth + 1;
+    t->depth = std::max(t->depth, t->cl[i].depth + 1);
+  }
+  // within a cluster: left-contact sites, right-contact sites, then the rest
+  t->owner.assign(n, -1);
+  t->perm.clear();
+  t->perm.reserve(n);
+  for (int i = 0; i < nc; ++i) {
+    auto& v = sites_of[i];
+    std::sort(v.begin(), v.end(), [&](int64_t a, int64_t b) {
+      int ka = t->side[a] < 0 ? 2 : t->side[a], kb = t->side[b] < 0 ? 2 : t->side[b];
+      return ka != kb ? ka < kb : a < b;
+    });
+    Cluster& c = t->cl[i];
+    c.first = (int64_t)t->perm.size();
+    c.n = (int)v.size();
+    c.n_left = c.n_right = 0;
+    for (int64_t s : v) {
+      if (t->owner[s] >= 0) { set_error("internal: site in two clusters"); return HSC_E_ARG; }
+      t->owner[s] = i;
+      t->perm.push_back(s);
+      if (t->side[s] == 0) c.n_left++;
+      if (t->side[s] == 1) c.n_right++;
+    }
+  }
+  if ((int64_t)t->perm.size() != n) { set_error("internal: sites lost in the tree"); return HSC_E_ARG; }
+  t->pos.assign(n, 0);
+  for (int64_t p = 0; p < n; ++p) t->pos[t->perm[p]] = p;
+  // separation check: every edge joins a cluster and one of its ancestors/descendants
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t q = t->indptr[r]; q < t->indptr[r + 1]; ++q) {
+      int64_t c = t->indices[q];
+      int a = t->owner[r], b = t->owner[c];
+      if (a == b) continue;
+      int lo_ = std::min(a, b), hi_ = std::max(a, b);
+      if (!(t->cl[hi_].lo <= lo_)) {
+        set_error("coordinates do not separate the graph of H (edge " + std::to_string(r) + "-" +
+                  std::to_string(c) + " crosses a separator)");
+        return HSC_E_ARG;
+      }
+    }
+  // contact paths
+  for (int i = 0; i < nc; ++i) {
+    Cluster& c = t->cl[i];
+    c.lpath = c.n_left > 0;
+    c.rpath = c.n_right > 0;
+    for (int k : c.children) {
+      c.lpath = c.lpath || t->cl[k].lpath;
+      c.rpath = c.rpath || t->cl[k].rpath;
+    }
+  }
+  // point-level fronts, bottom-up: ancestor sites adjacent to the subtree
+  std::vector<int64_t> stamp(n, -1);
+  for (int i = 0; i < nc; ++i) {
+    Cluster& c = t->cl[i];
+    std::vector<int64_t> cand;
+    auto consider = [&](int64_t s) {
+      int o = t->owner[s];
+      if (o >= c.lo && o <= i) return;        // inside the subtree
+      if (stamp[s] == i) return;
+      stamp[s] = i;
+      cand.push_back(s);
+    };
+    for (int64_t p = c.first; p < c.first + c.n; ++p) {
+      int64_t r = t->perm[p];
+      for (int64_t q = t->indptr[r]; q < t->indptr[r + 1]; ++q) consider(t->indices[q]);
+    }
+    for (int k : c.children)
+      for (int64_t s : t->cl[k].front) consider(s);
+    std::sort(cand.begin(), cand.end(), [&](int64_t a, int64_t b) { return t->pos[a] < t->pos[b]; });
+    c.front.swap(cand);
+  }
+  // relative maps
+  std::vector<int32_t> fidx(n, -1);
+  for (int i = 0; i < nc; ++i) {
+    Cluster& c = t->cl[i];
+    c.rel.assign(c.front.size(), -1);
+    c.frontpos.assign(c.front.size(), -1);
+    // offsets of each ancestor in the list (parent, grandparent, ..., root)
+    std::vector<std::pair<int, int64_t>> anc;
+    int64_t off = 0;
+    for (int p = c.parent; p >= 0; p = t->cl[p].parent) {
+      anc.push_back({p, off});
+      off += t->cl[p].n;
+    }
+    c.n_anc = off;
+    if (c.parent < 0) {
+      if (!c.front.empty()) { set_error("internal: root has a front"); return HSC_E_ARG; }
+      continue;
+    }
+    const Cluster& pc = t->cl[c.parent];
+    for (size_t k = 0; k < pc.front.size(); ++k) fidx[pc.front[k]] = (int32_t)k;
+    for (size_t k = 0; k < c.front.size(); ++k) {
+      int64_t s = c.front[k];
+      int o = t->owner[s];
+      if (o == c.parent) c.rel[k] = (int32_t)(t->pos[s] - pc.first);
+      else if (fidx[s] >= 0) c.rel[k] = pc.n + fidx[s];
+      for (auto& a : anc)
+        if (a.first == o) c.frontpos[k] = (int32_t)(a.second + (t->pos[s] - t->cl[o].first));
+      if (c.rel[k] < 0 || c.frontpos[k] < 0) {
+        set_error("internal: front site outside the parent's frontal set");
+        return HSC_E_ARG;
+      }
+    }
+    for (size_t k = 0; k < pc.front.size(); ++k) fidx[pc.front[k]] = -1;
+  }
+  t->uid = g_uid.fetch_add(1);
+  return HSC_OK;
+}
+
+// Real flops of one energy (complex FMA = 8 real flops), following the steps
+// the solver executes for the requested outputs.
+double flops_per_energy(const hsc_tree* t, uint32_t want) {
+  double fl = 0;
+  const bool need_gl = want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR);
+  for (const auto& c : t->cl) {
+    double n = c.n, f = c.f(), P = (double)c.n_anc;
+    bool leaf = c.children.empty();
+    double nc = c.n_left + c.n_right;
+    fl += 8 * n * n * n + 8 * n * n * f + 8 * f * f * n;          // fold
+    if (c.parent < 0) continue;
+    if (need_gl && c.cpath()) {
+      if (leaf) fl += 8 * n * f * f + 8 * n * f + 8 * nc * f * P + 8 * nc * f * n;
+      else fl += 8 * n * f * P + 8 * n * n * f;
+    } else {
+      fl += leaf ? 8 * n * f * f + 8 * n * f : 8 * n * f * f + 8 * n * n * f;
+    }
+  }
+  if (!need_gl) return fl;
+  // channels: (fold-set, extract-set) as chosen by the solver
+  struct Ch { int fold; int extract; };   // 0 = both sides, 1 = left, 2 = right, 3 = none
+  std::vector<Ch> chans;
+  if (want & HSC_SPECTRAL_LR) { chans.push_back({1, 0}); chans.push_back({2, 0}); }
+  else {
+    if (want & HSC_DIAG_GL) chans.push_back({0, 0});
+    if (want & HSC_TRANS) chans.push_back({2, 1});
+  }
+  for (auto ch : chans)
+    for (const auto& c : t->cl) {
+      double n = c.n, f = c.f(), P = (double)c.n_anc;
+      bool leaf = c.children.empty();
+      bool in_fold = ch.fold == 0 ? c.cpath() : ch.fold == 1 ? c.lpath : c.rpath;
+      bool in_ext = ch.extract == 0 ? true : c.lpath;
+      if (in_fold) {
+        double rows = leaf ? (ch.fold == 0 ? c.n_left + c.n_right : ch.fold == 1 ? c.n_left : c.n_right) : n;
+        fl += 8 * f * rows * P + 8 * n * rows * (n + f);
+      }
+      if (in_ext && c.parent >= 0) fl += leaf ? 8 * n * f * f + 8 * n * f : 8 * n * f * f + 8 * n * n * f;
+    }
+  return fl;
+}
+
+double bytes_per_energy(const hsc_tree* t, uint32_t want) {
+  double b = 0;
+  const bool need_gl = want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR);
+  for (const auto& c : t->cl) {
+    double n = c.n, f = c.f(), P = (double)c.n_anc;
+    b += 16 * ((n + f) * (n + f) + n * n + n * f);               // frontal, inverse, Psi
+    if (!c.children.empty()) b += 16 * (n + f) * (n + (need_gl && c.cpath() ? P : f));
+    if (need_gl && c.cpath()) b += 16 * 2 * ((n + f) * (n + P) + n * (n + f));
+    if (need_gl && !c.children.empty()) b += 16 * 2 * (n + f) * (n + f);
+  }
+  return b;
+}
+
+}  // namespace hsc
+
+using namespace hsc;
+
+extern "C" {
+
+const char* hsc_version(void) { return "hsc-mi355x 0.1"; }
+const char* hsc_last_error(void) { return hsc::last_error(); }
+
+hsc_status hsc_tree_build(int64_t n, const int64_t* indptr, const int32_t* indices,
+                          const double* values_ri, int32_t n_contacts,
+                          const hsc_contact* contacts, const hsc_tree_opts* opts,
+                          hsc_tree** out) {
+  if (!out) { set_error("out is NULL"); return HSC_E_ARG; }
+  *out = nullptr;
+  if (n <= 0 || !indptr || !indices || !values_ri || !contacts || !opts || !opts->coords) {
+    set_error("null or empty argument to hsc_tree_build");
+    return HSC_E_ARG;
+  }
+  if (n_contacts != 2) { set_error("exactly two contacts are required"); return HSC_E_ARG; }
+  if (opts->leaf_side < 1 || (opts->split_mask & 7) == 0) { set_error("bad tree options"); return HSC_E_ARG; }
+  hsc_tree* t = new (std::nothrow) hsc_tree();
+  if (!t) { set_error("host allocation failed"); return HSC_E_OOM; }
+  try {
+    t->n = n;
+    if (indptr[0] != 0) throw std::string("indptr[0] != 0");
+    for (int64_t r = 0; r < n; ++r)
+      if (indptr[r + 1] < indptr[r]) throw std::string("indptr not monotone");
+    int64_t nnz = indptr[n];
+    t->indptr.assign(indptr, indptr + n + 1);
+    t->indices.assign(indices, indices + nnz);
+    t->values.assign(values_ri, values_ri + 2 * nnz);
+    for (int64_t q = 0; q < nnz; ++q) {
+      if (indices[q] < 0 || indices[q] >= n) throw std::string("column index out of range");
+      if (!std::isfinite(values_ri[2 * q]) || !std::isfinite(values_ri[2 * q + 1])) {
+        delete t;
+        set_error("non-finite value in H");
+        return HSC_E_NONFINITE;
+      }
+    }
+    // symmetry H^T == H (exact): sort each row's (col, value) pairs
+    {
+      std::vector<int64_t> ord(nnz);
+      for (int64_t r = 0; r < n; ++r) {
+        for (int64_t q = indptr[r]; q < indptr[r + 1]; ++q) ord[q] = q;
+        std::sort(ord.begin() + indptr[r], ord.begin() + indptr[r + 1],
+                  [&](int64_t a, int64_t b) { return indices[a] < indices[b]; });
+      }
+      auto find = [&](int64_t r, int32_t c, double* re, double* im) {
+        int64_t a = indptr[r], b = indptr[r + 1];
+        double sr = 0, si = 0;
+        bool hit = false;
+        auto it = std::lower_bound(ord.begin() + a, ord.begin() + b, c,
+                                   [&](int64_t q, int32_t v) { return indices[q] < v; });
+        for (; it != ord.begin() + b && indices[*it] == c; ++it) {
+          sr += values_ri[2 * *it];
+          si += values_ri[2 * *it + 1];
+          hit = true;
+        }
+        *re = sr; *im = si;
+        return hit;
+      };
+      for (int64_t r = 0; r < n; ++r)
+        for (int64_t q = indptr[r]; q < indptr[r + 1]; ++q) {
+          int32_t c = indices[q];
+          double ar, ai, br, bi;
+          find(r, c, &ar, &ai);
+          bool ok = find(c, (int32_t)r, &br, &bi);
+          if (!ok || ar != br || ai != bi) {
+            delete t;
+            set_error("H is not symmetric at (" + std::to_string(r) + "," + std::to_string(c) + ")");
+            return HSC_E_NOT_SYMMETRIC;
+          }
+        }
+    }
+    t->coords.assign(opts->coords, opts->coords + 3 * n);
+    t->split_mask = opts->split_mask & 7;
+    t->leaf_side = opts->leaf_side;
+    t->side.assign(n, -1);
+    for (int k = 0; k < 2; ++k) {
+      const hsc_contact& c = contacts[k];
+      if (c.n_sites <= 0 || !c.sites) throw std::string("empty contact");
+      if (!(c.lead_hopping != 0.0) || !std::isfinite(c.lead_hopping) || !std::isfinite(c.coupling) ||
+          !std::isfinite(c.lead_onsite))
+        throw std::string("bad lead parameters");
+      t->contact[k].sites.assign(c.sites, c.sites + c.n_sites);
+      t->contact[k].lead_onsite = c.lead_onsite;
+      t->contact[k].lead_hopping = c.lead_hopping;
+      t->contact[k].coupling = c.coupling;
+      for (int64_t j = 0; j < c.n_sites; ++j) {
+        int64_t s = c.sites[j];
+        if (s < 0 || s >= n) throw std::string("contact site out of range");
+        if (t->side[s] >= 0) throw std::string("site listed in two contacts (or twice)");
+        t->side[s] = (int8_t)k;
+      }
+    }
+    NDBuilder b{t, {}, {}};
+    std::vector<int64_t> all(n);
+    for (int64_t s = 0; s < n; ++s) all[s] = s;
+    b.rec(all);
+    t->cl.resize(b.sites_of.size());
+    for (size_t i = 0; i < b.sites_of.size(); ++i) t->cl[i].children = b.kids_of[i];
+    int st = finalize_tree(t, b.sites_of);
+    if (st != HSC_OK) { delete t; return (hsc_status)st; }
+  } catch (const std::string& msg) {
+    delete t;
+    set_error(msg);
+    return HSC_E_ARG;
+  } catch (const std::bad_alloc&) {
+    delete t;
+    set_error("host allocation failed");
+    return HSC_E_OOM;
+  }
+  *out = t;
+  return HSC_OK;
+}
+
+hsc_status hsc_tree_merge(const hsc_tree* src, int32_t n_ids, const int32_t* ids, hsc_tree** out) {
+  if (!src || !out || n_ids < 0 || (n_ids > 0 && !ids)) { set_error("bad arguments to hsc_tree_merge"); return HSC_E_ARG; }
+  *out = nullptr;
+  const int nc = (int)src->cl.size();
+  std::vector<char> gone(nc, 0);
+  for (int k = 0; k < n_ids; ++k) {
+    if (ids[k] < 0 || ids[k] >= nc - 1) { set_error("cluster id out of range (the root cannot be merged)"); return HSC_E_ARG; }
+    gone[ids[k]] = 1;
+  }
+  hsc_tree* t = new (std::nothrow) hsc_tree(*src);
+  if (!t) { set_error("host allocation failed"); return HSC_E_OOM; }
+  // target of each cluster: itself, or the nearest surviving ancestor
+  std::vector<int> tgt(nc);
+  for (int i = nc - 1; i >= 0; --i) tgt[i] = gone[i] ? tgt[src->cl[i].parent] : i;
+  std::vector<std::vector<int64_t>> sites(nc);
+  std::vector<std::vector<int>> kids(nc);
+  for (int i = 0; i < nc; ++i) {
+    const Cluster& c = src->cl[i];
+    for (int64_t p = c.first; p < c.first + c.n; ++p) sites[tgt[i]].push_back(src->perm[p]);
+    if (!gone[i] && c.parent >= 0) kids[tgt[c.parent]].push_back(i);
+  }
+  // renumber survivors in post-order (children keep their relative order)
+  std::vector<int> newid(nc, -1);
+  std::vector<Cluster> ncl;
+  std::vector<std::vector<int64_t>> nsites;
+  std::function<int(int)> walk = [&](int i) -> int {
+    std::vector<int> ch;
+    std::vector<int> order = kids[i];
+    std::sort(order.begin(), order.end());
+    for (int k : order) ch.push_back(walk(k));
+    Cluster c;
+    c.children = ch;
+    ncl.push_back(c);
+    nsites.push_back(sites[i]);
+    newid[i] = (int)ncl.size() - 1;
+    return newid[i];
+  };
+  walk(nc - 1);
+  t->cl = ncl;
+  int st = finalize_tree(t, nsites);
+  if (st != HSC_OK) { delete t; return (hsc_status)st; }
+  *out = t;
+  return HSC_OK;
+}
+
+hsc_status hsc_tree_stats_get(const hsc_tree* t, hsc_tree_stats* out) {
+  if (!t || !out) { set_error("null argument"); return HSC_E_ARG; }
+  std::memset(out, 0, sizeof(*out));
+  out->n_sites = t->n;
+  out->n_clusters = (int32_t)t->cl.size();
+  out->depth = t->depth;
+  for (const auto& c : t->cl) {
+    out->max_cluster = std::max(out->max_cluster, c.n);
+    out->max_front = std::max(out->max_front, c.f());
+    if (c.cpath()) out->max_ancestors = std::max(out->max_ancestors, (int32_t)c.n_anc);
+    if (c.children.empty()) out->n_leaves++;
+  }
+  uint32_t want = HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS;
+  out->flops_per_energy = flops_per_energy(t, want);
+  out->bytes_per_energy = bytes_per_energy(t, want);
+  return HSC_OK;
+}
+
+hsc_status hsc_tree_export(const hsc_tree* t, int64_t* perm, int32_t* cl_parent, int32_t* cl_first,
+                           int32_t* cl_size, int64_t* front_ptr, int64_t* front_sites) {
+  if (!t) { set_error("null tree"); return HSC_E_ARG; }
+  const int nc = (int)t->cl.size();
+  if (perm) std::copy(t->perm.begin(), t->perm.end(), perm);
+  int64_t off = 0;
+  for (int i = 0; i < nc; ++i) {
+    const Cluster& c = t->cl[i];
+    if (cl_parent) cl_parent[i] = c.parent;
+    if (cl_first) cl_first[i] = (int32_t)c.first;
+    if (cl_size) cl_size[i] = c.n;
+    if (front_ptr) front_ptr[i] = off;
+    if (front_sites) std::copy(c.front.begin(), c.front.end(), front_sites + off);
+    off += (int64_t)c.front.size();
+  }
+  if (front_ptr) front_ptr[nc] = off;
+  return HSC_OK;
+}
+
+hsc_status hsc_tree_destroy(hsc_tree* t) {
+  delete t;
+  return HSC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,258 @@
+"""ctypes binding of libhsc (include/hsc.h, include/hsc_kernels.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  PyTorch provides device memory (tensors) and the HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhsc.so")
+
+HSC_DIAG_GR, HSC_DIAG_GL, HSC_TRANS, HSC_SPECTRAL_LR = 1, 2, 4, 8
+STATUS = {0: "HSC_OK", -1: "HSC_E_ARG", -2: "HSC_E_NOT_SYMMETRIC", -3: "HSC_E_SINGULAR",
+          -4: "HSC_E_NONFINITE", -5: "HSC_E_OOM", -6: "HSC_E_HIP", -7: "HSC_E_UNSTABLE"}
+
+
+class HscError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Contact(C.Structure):
+    _fields_ = [("n_sites", C.c_int64), ("sites", C.POINTER(C.c_int64)), ("lead_onsite", C.c_double),
+                ("lead_hopping", C.c_double), ("coupling", C.c_double)]
+
+
+class TreeOpts(C.Structure):
+    _fields_ = [("coords", C.POINTER(C.c_int32)), ("split_mask", C.c_int32), ("leaf_side", C.c_int32)]
+
+
+class TreeStats(C.Structure):
+    _fields_ = [("n_sites", C.c_int64), ("n_clusters", C.c_int32), ("depth", C.c_int32),
+                ("max_cluster", C.c_int32), ("max_front", C.c_int32), ("max_ancestors", C.c_int32),
+                ("n_leaves", C.c_int32), ("flops_per_energy", C.c_double), ("bytes_per_energy", C.c_double)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("eta", C.c_double), ("kT", C.c_double), ("mu_L", C.c_double), ("mu_R", C.c_double),
+                ("want", C.c_uint32), ("batch", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhsc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.hsc_version.restype = C.c_char_p
+    L.hsc_last_error.restype = C.c_char_p
+    L.hsc_ctx_create.argtypes = [i32, vp, C.POINTER(vp)]
+    L.hsc_ctx_destroy.argtypes = [vp]
+    L.hsc_tree_build.argtypes = [i64, vp, vp, vp, i32, C.POINTER(Contact), C.POINTER(TreeOpts), C.POINTER(vp)]
+    L.hsc_tree_merge.argtypes = [vp, i32, vp, C.POINTER(vp)]
+    L.hsc_tree_stats_get.argtypes = [vp, C.POINTER(TreeStats)]
+    L.hsc_tree_export.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.hsc_tree_destroy.argtypes = [vp]
+    L.hsc_solve.argtypes = [vp, vp, i32, vp, C.POINTER(SolveOpts), vp, vp, vp, vp, vp, vp]
+    L.hsc_solve_batch.argtypes = [vp, i32, vp, vp, vp, C.POINTER(SolveOpts), vp, vp, vp, vp, vp, vp]
+    L.hsc_sync.argtypes = [vp]
+    L.hsc_kern_zgemm.argtypes = [vp, i32, i32, i32, i32, i32, dbl, dbl, vp, i32, vp, i32, i32, vp, i32, vp, i32]
+    L.hsc_kern_zinv_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    L.hsc_kern_mfma_probe.argtypes = [vp, vp]
+    for name in ("hsc_ctx_create", "hsc_ctx_destroy", "hsc_tree_build", "hsc_tree_merge", "hsc_tree_stats_get",
+                 "hsc_tree_export", "hsc_tree_destroy", "hsc_solve", "hsc_solve_batch", "hsc_sync",
+                 "hsc_kern_zgemm", "hsc_kern_zinv_batched", "hsc_kern_mfma_probe"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def check(code):
+    if code != 0:
+        raise HscError(code, lib().hsc_last_error().decode())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Context:
+    """A HIP device and stream (torch's current stream unless given)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the solver runs only on the HIP device")
+        self.device = device
+        self.torch_device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.torch_device)
+        self.stream = stream
+        h = C.c_void_p()
+        check(lib().hsc_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def sync(self):
+        check(lib().hsc_sync(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hsc_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tree:
+    """Nested-dissection cluster tree of one device (host object)."""
+
+    def __init__(self, handle, n):
+        self.h = handle
+        self.n = n
+
+    @classmethod
+    def build(cls, n, indptr, indices, values, coords, contacts, split_mask=7, leaf_side=8):
+        """contacts: [(sites, lead_onsite, lead_hopping, coupling)] for left, right."""
+        indptr = np.ascontiguousarray(indptr, dtype=np.int64)
+        indices = np.ascontiguousarray(indices, dtype=np.int32)
+        vals = np.ascontiguousarray(np.asarray(values, dtype=np.complex128)).view(np.float64)
+        coords = np.ascontiguousarray(coords, dtype=np.int32)
+        keep = [indptr, indices, vals, coords]
+        carr = (Contact * len(contacts))()
+        for k, (sites, eps0, tl, tc) in enumerate(contacts):
+            s = np.ascontiguousarray(sites, dtype=np.int64)
+            keep.append(s)
+            carr[k] = Contact(len(s), s.ctypes.data_as(C.POINTER(C.c_int64)), eps0, tl, tc)
+        opts = TreeOpts(coords.ctypes.data_as(C.POINTER(C.c_int32)), split_mask, leaf_side)
+        h = C.c_void_p()
+        check(lib().hsc_tree_build(n, _ptr(indptr), _ptr(indices), _ptr(vals), len(contacts), carr,
+                                   C.byref(opts), C.byref(h)))
+        return cls(h, n)
+
+    @classmethod
+    def from_device(cls, dev, leaf_side=8):
+        mask = 0
+        for a in dev.split_axes:
+            mask |= 1 << a
+        contacts = [(c.sites, c.lead_onsite, c.lead_hopping, c.coupling) for c in dev.contacts]
+        return cls.build(dev.n, dev.indptr, dev.indices, dev.values, dev.coords, contacts, mask, leaf_side)
+
+    def stats(self) -> dict:
+        s = TreeStats()
+        check(lib().hsc_tree_stats_get(self.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in TreeStats._fields_}
+
+    def export(self) -> dict:
+        st = self.stats()
+        nc = st["n_clusters"]
+        perm = np.empty(self.n, np.int64)
+        parent = np.empty(nc, np.int32)
+        first = np.empty(nc, np.int32)
+        size = np.empty(nc, np.int32)
+        fptr = np.empty(nc + 1, np.int64)
+        check(lib().hsc_tree_export(self.h, _ptr(perm), _ptr(parent), _ptr(first), _ptr(size), _ptr(fptr), None))
+        fs = np.empty(max(1, int(fptr[-1])), np.int64)
+        check(lib().hsc_tree_export(self.h, None, None, None, None, None, _ptr(fs)))
+        return dict(perm=perm, parent=parent, first=first, size=size, front_ptr=fptr, front=fs[:fptr[-1]])
+
+    def merge(self, ids) -> "Tree":
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        h = C.c_void_p()
+        check(lib().hsc_tree_merge(self.h, len(ids), _ptr(ids), C.byref(h)))
+        return Tree(h, self.n)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hsc_tree_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1,
+          want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, out=None, sync=True):
+    """Solve all energies; returns a dict of device tensors (gr, gl, trans, spectral, status)."""
+    import torch
+    dev = ctx.torch_device
+    e = torch.as_tensor(energies, dtype=torch.float64, device=dev).contiguous()
+    ne, n = int(e.numel()), tree.n
+    o = dict(out or {})
+    if want & HSC_DIAG_GR and "gr" not in o:
+        o["gr"] = torch.empty((ne, n), dtype=torch.complex128, device=dev)
+    if want & HSC_DIAG_GL and "gl" not in o:
+        o["gl"] = torch.empty((ne, n), dtype=torch.complex128, device=dev)
+    if want & HSC_TRANS and "trans" not in o:
+        o["trans"] = torch.empty(ne, dtype=torch.float64, device=dev)
+    if want & HSC_SPECTRAL_LR and "spectral" not in o:
+        o["spectral"] = torch.empty((ne, 2, n), dtype=torch.float64, device=dev)
+    if "status" not in o:
+        o["status"] = torch.empty(ne, dtype=torch.int32, device=dev)
+    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch)
+    check(lib().hsc_solve(ctx.h, tree.h, ne, _dptr(e), C.byref(opts), _dptr(o.get("gr")), _dptr(o.get("gl")),
+                          _dptr(o.get("trans")), _dptr(o.get("spectral")), _dptr(o.get("status")), None))
+    if sync:
+        ctx.sync()
+    return o
+
+
+# ---- kernel-level entry points -------------------------------------------------------------------
+
+def kern_zgemm(ctx, opA, opB, alpha, A, B, beta=0, C_=None, D=None):
+    """D = alpha op(A) op(B) + beta C on device complex128 tensors (row-major 2D)."""
+    import torch
+    M = A.shape[0] if opA == 0 else A.shape[1]
+    K = A.shape[1] if opA == 0 else A.shape[0]
+    N = B.shape[1] if opB == 0 else B.shape[0]
+    if D is None:
+        D = torch.empty((M, N), dtype=torch.complex128, device=A.device)
+    alpha = complex(alpha)
+    check(lib().hsc_kern_zgemm(ctx.h, opA, opB, M, N, K, alpha.real, alpha.imag, _dptr(A), A.stride(0),
+                               _dptr(B), B.stride(0), beta, _dptr(C_) if C_ is not None else None,
+                               C_.stride(0) if C_ is not None else 0, _dptr(D), D.stride(0)))
+    return D
+
+
+def kern_zinv_batched(ctx, mats):
+    """Invert a list of square device complex128 tensors (in place); returns (inverses, status)."""
+    import torch
+    cnt = len(mats)
+    n = np.array([m.shape[0] for m in mats], np.int32)
+    ld = np.array([m.stride(0) for m in mats], np.int32)
+    outs = [torch.empty_like(m) for m in mats]
+    ldy = np.array([o.stride(0) for o in outs], np.int32)
+    X = (C.c_void_p * cnt)(*[m.data_ptr() for m in mats])
+    Y = (C.c_void_p * cnt)(*[o.data_ptr() for o in outs])
+    st = torch.empty(cnt, dtype=torch.int32, device=mats[0].device)
+    check(lib().hsc_kern_zinv_batched(ctx.h, cnt, _ptr(n), X, _ptr(ld), Y, _ptr(ldy), _dptr(st)))
+    return outs, st
+
+
+def kern_mfma_probe(ctx):
+    import torch
+    out = torch.empty(256, dtype=torch.float64, device=ctx.torch_device)
+    check(lib().hsc_kern_mfma_probe(ctx.h, _dptr(out)))
+    return out

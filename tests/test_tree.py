@@ -1,0 +1,183 @@
+"""Host-side checks of libhsc: exported C ABI, nested-dissection tree, error paths.
+
+These run without a GPU (no compute call is made).
+"""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+import paper_1702_05167_amd as pkg
+from paper_1702_05167_amd import hsc as H
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    pkg.lib()
+    declared = set()
+    for hdr in ("hsc.h", "hsc_kernels.h"):
+        text = open(os.path.join(ROOT, "include", hdr)).read()
+        declared |= set(re.findall(r"\b(hsc_[a-z_0-9]+)\s*\(", text))
+    out = subprocess.run(["nm", "-D", "--defined-only", pkg.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (hsc_[a-z_0-9]+)", out))
+    assert declared and declared <= exported, declared - exported
+
+
+def _tree(dev, leaf):
+    return pkg.Tree.from_device(dev, leaf_side=leaf)
+
+
+def _check_tree(dev, tree):
+    ex = tree.export()
+    n = dev.n
+    perm, parent, first, size = ex["perm"], ex["parent"], ex["first"], ex["size"]
+    nc = len(parent)
+    assert sorted(perm.tolist()) == list(range(n))                  # every site exactly once
+    assert first[0] == 0 and (np.diff(first) == size[:-1]).all()    # clusters contiguous, post-order
+    assert parent[-1] == -1 and (parent[:-1] > np.arange(nc - 1)).all()   # children before parents
+    owner = np.empty(n, np.int64)
+    for i in range(nc):
+        owner[perm[first[i]:first[i] + size[i]]] = i
+    anc = [set() for _ in range(nc)]
+    for i in range(nc - 2, -1, -1):
+        anc[i] = anc[parent[i]] | {parent[i]}
+    sub = [set([i]) for i in range(nc)]
+    for i in range(nc - 1):
+        p = parent[i]
+        while p >= 0:
+            sub[p].add(i)
+            p = parent[p]
+    h = dev.scipy_h().tocoo()
+    # separation: every edge joins a cluster and one of its ancestors (or itself)
+    for r, c in zip(h.row, h.col):
+        a, b = owner[r], owner[c]
+        assert a == b or a in anc[b] or b in anc[a]
+    hc = dev.scipy_h().tocsr()
+    pos = np.empty(n, np.int64)
+    pos[perm] = np.arange(n)
+    for i in range(nc):
+        # brute-force point front: ancestor sites adjacent to the subtree region
+        region = np.concatenate([perm[first[k]:first[k] + size[k]] for k in sub[i]])
+        adj = set(hc[region].indices.tolist()) - set(region.tolist())
+        assert all(owner[s] in anc[i] for s in adj)
+        want = sorted(adj, key=lambda s: pos[s])
+        got = ex["front"][ex["front_ptr"][i]:ex["front_ptr"][i + 1]].tolist()
+        assert got == want
+        # clique property: front(i) within parent and parent's front
+        if parent[i] >= 0:
+            p = parent[i]
+            allowed = set(perm[first[p]:first[p] + size[p]].tolist()) | set(
+                ex["front"][ex["front_ptr"][p]:ex["front_ptr"][p + 1]].tolist())
+            assert set(got) <= allowed
+    return ex
+
+
+@pytest.mark.parametrize("dev,leaf", [
+    (synth.config0_device(), 4),
+    (synth.config0_device(), 8),
+    (synth.cuboid(9, 6, 5), 3),
+    (synth.trilayer(12, 9), 4),
+    (synth.chain(17), 2),
+])
+def test_tree_invariants(dev, leaf):
+    _check_tree(dev, _tree(dev, leaf))
+
+
+def test_cube32_shape():
+    t = _tree(synth.config1_device(), 8)
+    st = t.stats()
+    assert st["n_clusters"] == 127 and st["depth"] == 7 and st["n_leaves"] == 64
+    assert st["max_cluster"] == 1024 and st["max_front"] == 1024
+    ex = t.export()
+    assert ex["size"][-1] == 1024                                  # root plane 32 x 32
+    leaves = [i for i in range(127) if i not in set(ex["parent"].tolist())]
+    assert max(ex["size"][leaves]) == 512 and min(ex["size"][leaves]) == 343
+
+
+def test_single_cluster_when_leaf_covers_device():
+    t = _tree(synth.config0_device(), 8)
+    assert t.stats()["n_clusters"] == 1
+
+
+def test_merge():
+    dev = synth.config0_device()
+    t = _tree(dev, 4)
+    ex = t.export()
+    m = t.merge([0, 2])
+    st = m.stats()
+    assert st["n_clusters"] == t.stats()["n_clusters"] - 2
+    _check_tree(dev, m)
+    with pytest.raises(H.HscError) as e:
+        t.merge([len(ex["parent"]) - 1])                          # the root cannot merge
+    assert e.value.code == -1
+
+
+def test_flop_exponents_table1():
+    # cube: HSC operation count grows like N^6 (Table 1); check the local slope
+    f = {n: _tree(synth.cuboid(n, n, n), 8).stats()["flops_per_energy"] for n in (32, 64)}
+    slope = np.log(f[64] / f[32]) / np.log(2)
+    assert 5.3 < slope < 6.7, slope
+    # flattened Nz = 4: O(N^3) in N = Nx = Ny
+    g = {n: _tree(synth.cuboid(n, n, 4), 8).stats()["flops_per_energy"] for n in (64, 128)}
+    slope = np.log(g[128] / g[64]) / np.log(2)
+    assert 2.5 < slope < 3.6, slope
+
+
+def _contacts(dev):
+    return [(c.sites, c.lead_onsite, c.lead_hopping, c.coupling) for c in dev.contacts]
+
+
+def test_rejects_nonsymmetric():
+    dev = synth.cuboid(4, 3, 3)
+    vals = dev.values.copy()
+    vals[1] += 0.5          # breaks H[r, c] == H[c, r] for one entry
+    with pytest.raises(H.HscError) as e:
+        pkg.Tree.build(dev.n, dev.indptr, dev.indices, vals, dev.coords, _contacts(dev), 7, 2)
+    assert e.value.code == -2
+
+
+def test_rejects_hermitian_but_not_symmetric():
+    dev = synth.cuboid(4, 3, 3)
+    h = dev.scipy_h().tolil()
+    h[0, 1] = -1 + 0.3j
+    h[1, 0] = -1 - 0.3j
+    h = h.tocsr()
+    with pytest.raises(H.HscError) as e:
+        pkg.Tree.build(dev.n, h.indptr, h.indices, h.data, dev.coords, _contacts(dev), 7, 2)
+    assert e.value.code == -2
+
+
+def test_rejects_nonfinite_and_bad_contacts():
+    dev = synth.cuboid(4, 3, 3)
+    vals = dev.values.copy()
+    vals[0] = np.nan
+    with pytest.raises(H.HscError) as e:
+        pkg.Tree.build(dev.n, dev.indptr, dev.indices, vals, dev.coords, _contacts(dev), 7, 2)
+    assert e.value.code == -4
+    c = _contacts(dev)
+    c[1] = (np.array([0, 1]), 0.0, -1.0, -1.0)     # site 0 is also a left contact site
+    with pytest.raises(H.HscError) as e:
+        pkg.Tree.build(dev.n, dev.indptr, dev.indices, dev.values, dev.coords, c, 7, 2)
+    assert e.value.code == -1
+    c = _contacts(dev)
+    c[0] = (np.array([dev.n]), 0.0, -1.0, -1.0)
+    with pytest.raises(H.HscError) as e:
+        pkg.Tree.build(dev.n, dev.indptr, dev.indices, dev.values, dev.coords, c, 7, 2)
+    assert e.value.code == -1
+
+
+def test_rejects_coordinates_that_do_not_separate():
+    # a long-range bond across the first cut plane
+    dev = synth.cuboid(8, 2, 2)
+    h = dev.scipy_h().tolil()
+    h[0, 7] = -0.1
+    h[7, 0] = -0.1
+    h = h.tocsr()
+    with pytest.raises(H.HscError) as e:
+        pkg.Tree.build(dev.n, h.indptr, h.indices, h.data, dev.coords, _contacts(dev), 7, 2)
+    assert e.value.code == -1
