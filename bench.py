@@ -1,0 +1,127 @@
+#!/usr/bin/env python
+"""Throughput of the HSC / HSC-extension solve on one MI355X.
+
+Workload: the 32^3 cube (32,768 sites, 7-point, t = -1, on-site U[-0.5, 0.5]
+seed 0, per-site 1D leads on the x faces), 256 energies uniform in [-6, 6],
+eta = 1e-8, kT = 0.025, mu_L/R = +-0.1, nested-dissection leaves <= 8 per side.
+One step = diag G^r, diag G^< and T for all 256 energies (inputs resident on
+the device).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_MFMA_PEAK_TFLOPS = 78.6
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n-side", type=int, default=32)
+    ap.add_argument("--energies", type=int, default=256)
+    ap.add_argument("--batch", type=int, default=0, help="energies per launch sequence (0 = auto)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the one-energy-per-launch-sequence run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); energies shard across GPUs "
+              "with no communication but the output gather, so the one-GPU figure is the per-GPU rate.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_1702_05167_amd as pkg
+
+    N, NE = args.n_side, args.energies
+    dev = synth.config1_device(n_side=N)
+    tree = pkg.Tree.from_device(dev, leaf_side=8)
+    st = tree.stats()
+    ctx = pkg.Context(0)
+    E = torch.linspace(-6.0, 6.0, NE, dtype=torch.float64, device="cuda:0")
+    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1)
+    want = pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS
+    out = pkg.solve(ctx, tree, E, want=want, batch=args.batch, **kw)     # buffers + plan
+    for _ in range(args.warmup):
+        pkg.solve(ctx, tree, E, want=want, batch=args.batch, out=out, sync=False, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pkg.solve(ctx, tree, E, want=want, batch=args.batch, out=out, sync=False, **kw)
+    ctx.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = NE * args.steps / dt
+    status_ok = int(out["status"].abs().sum().item()) == 0
+
+    # per-kernel timing of one step (events around every launch on the solver's stream)
+    ctx.profile(True)
+    pkg.solve(ctx, tree, E, want=want, batch=args.batch, out=out, sync=True, **kw)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    g = prof["gemm"]
+    achieved = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
+    total_ms = sum(v["ms"] for v in prof.values())
+
+    plain = None
+    if not args.no_plain:
+        sub = E[: min(NE, 32)]
+        pkg.solve(ctx, tree, sub[:2], want=want, batch=1, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pkg.solve(ctx, tree, sub, want=want, batch=1, **kw)
+        torch.cuda.synchronize()
+        plain = len(sub) / (time.perf_counter() - t1)
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        t2 = time.perf_counter()
+        oracle.rgf.solve(dev, [0.3], 1e-8, 0.025, 0.1, -0.1)
+        cdt = time.perf_counter() - t2
+        cpu = {"value": 1.0 / cdt, "unit": "energies/s", "cores": threads, "kind": "oracle",
+               "sample": f"slab RGF (oracle/rgf.py), one energy (E=0.3) of the same {N}^3 cube, {cdt:.1f} s"}
+
+    line = {
+        "metric": "energies/s (diag G^r,G^<), 32^3 cube, batched vs plain; % FP64 MFMA peak",
+        "value": value,
+        "unit": "energies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": f"cube{N}^3 x {NE} energies in [-6,6] (diag G^r, diag G^<, T)",
+                   "sites": int(dev.n), "energies": NE, "leaf_side": 8, "clusters": st["n_clusters"],
+                   "batch": args.batch or "auto", "plain_energies_per_s": plain,
+                   "flops_per_energy": st["flops_per_energy"],
+                   "whole_solve_tflops": st["flops_per_energy"] * value / 1e12,
+                   "status_ok": status_ok,
+                   "kernel_ms_per_step": {k: round(v["ms"], 3) for k, v in prof.items()},
+                   "kernel_ms_total": round(total_ms, 3)},
+        "roofline": {"bound": "mfma", "kernel": "k_zgemm (grouped complex128 GEMM)", "achieved": achieved,
+                     "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
+                     "traffic": None, "launches": int(g["launches"])},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -96,6 +96,15 @@ typedef struct {
   double mu_L, mu_R;         /* contact chemical potentials */
   uint32_t want;             /* HSC_* bits */
   int32_t batch;             /* energies per launch sequence; 0 = library default */
+  /* Growth guard.  Algorithm 1 inverts each cluster block A_ii with no
+   * pivoting across clusters; a nearly singular block amplifies rounding
+   * errors.  When guard_tau > 0, every energy whose non-root blocks have
+   * ||(A_ii)^-1||_inf > guard_tau is solved again on a tree in which those
+   * clusters are merged into their parents (a delayed pivot), for up to
+   * guard_rounds rounds; energies still above the threshold get status
+   * HSC_E_UNSTABLE.  With guard_tau > 0 the call waits for the device. */
+  double guard_tau;          /* 0 disables the guard */
+  int32_t guard_rounds;      /* maximum re-planning rounds (e.g. 6) */
 } hsc_solve_opts;
 
 /* Library version string. */
@@ -150,7 +159,10 @@ hsc_status hsc_tree_destroy(hsc_tree* tree);
  *   trans        device, double[n_e]       (HSC_TRANS) or NULL
  *   spectral_lr  device, double[n_e][2][n] (HSC_SPECTRAL_LR: A_L then A_R) or NULL
  *   status       device, int32[n_e] per-energy status (0 or a negative code) or NULL
- *   guard        device, double[n_e] per-energy growth indicator max|Psi| or NULL
+ *   guard        device, double[n_e][n_clusters][2] or NULL: for every pivot block
+ *                A_ii of Algorithm 1, ||(A_ii)^-1||_inf and ||Psi_i||_inf (max row
+ *                sums of moduli: conditioning and growth of the unpivoted cluster
+ *                elimination; clusters in hsc_tree_export order)
  * Outputs whose bit is not set in opts->want are not written.
  * Errors: HSC_E_ARG, HSC_E_OOM, HSC_E_HIP.  Numerical failures of single
  * energies are reported through `status` (see hsc_sync). */
@@ -170,6 +182,17 @@ hsc_status hsc_solve_batch(hsc_ctx* ctx, int32_t n_trees, const hsc_tree* const*
 
 /* Wait for the context's stream; returns HSC_E_HIP on an asynchronous HIP error. */
 hsc_status hsc_sync(hsc_ctx* ctx);
+
+/* Launch timing.  While enabled, every kernel launch of a solve is bracketed by
+ * HIP events on the context's stream; hsc_sync() folds the elapsed times into
+ * per-kind totals.  Enabling (or disabling) resets the totals.  Kinds:
+ * 0 assemble, 1 inverse panel, 2 inverse swap, 3 inverse unscramble, 4 GEMM,
+ * 5 gather, 6 N assembly, 7 diagonal output, 8 growth indicators.
+ * hsc_ctx_profile_read writes out[3*k + {0,1,2}] = launches, milliseconds,
+ * algorithmic real flops (GEMM: 8 M N K per problem) for k < n_kinds.
+ * Errors: HSC_E_ARG. */
+hsc_status hsc_ctx_profile(hsc_ctx* ctx, int32_t enable);
+hsc_status hsc_ctx_profile_read(hsc_ctx* ctx, double* out, int32_t n_kinds);
 
 #ifdef __cplusplus
 }

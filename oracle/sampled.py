@@ -9,6 +9,11 @@ is row s of G^r.  From that row (Eq. 1 and Eq. 2 for diagonal Sigma^<):
 
 The transmission T = sum_{i in L} Gamma_L,i A_R,ii needs the rows of every
 left-contact site; it is computed only when asked for.
+
+Rows and columns are first permuted by a geometric nested-dissection order
+(bisect the longest box axis, separator last) only to keep the sparse
+factors small; a symmetric permutation does not change A^-1, and SuperLU's
+partial row pivoting keeps the factorisation stable in any column order.
 """
 from __future__ import annotations
 
@@ -19,20 +24,56 @@ import scipy.sparse.linalg as spl
 from .negf import contact_sigmas, gamma_of, fermi
 
 
+def _bisection_order(coords, leaf=4):
+    """Sites ordered as: first half, second half, separator plane (recursively)."""
+    out = []
+
+    def rec(idx):
+        c = coords[idx]
+        lo, hi = c.min(0), c.max(0)
+        ext = hi - lo + 1
+        a = int(np.argmax(ext))
+        if ext[a] <= leaf or ext[a] < 3:
+            out.append(idx)
+            return
+        cut = lo[a] + ext[a] // 2
+        rec(idx[c[:, a] < cut])
+        rec(idx[c[:, a] > cut])
+        out.append(idx[c[:, a] == cut])
+
+    rec(np.arange(len(coords)))
+    return np.concatenate(out)
+
+
+class _Factor:
+    """LU of P A P^T; solves are returned in the original site order."""
+
+    def __init__(self, dev, z):
+        h = dev.scipy_h()
+        a = (-h).tolil()
+        a.setdiag(a.diagonal() + z)
+        for sites, sig in contact_sigmas(dev, z):
+            for s, v in zip(sites, sig):
+                a[s, s] -= v
+        a = sp.csc_matrix(a)
+        self.p = _bisection_order(np.asarray(dev.coords))
+        self.lu = spl.splu(a[self.p][:, self.p].tocsc(), permc_spec="NATURAL")
+
+    def solve_t(self, b):
+        """x = A^-T b."""
+        x = np.empty_like(b)
+        x[self.p] = self.lu.solve(b[self.p], trans="T")
+        return x
+
+
 def _factor(dev, z):
-    h = dev.scipy_h()
-    a = (-h).tolil()
-    a.setdiag(a.diagonal() + z)
-    for sites, sig in contact_sigmas(dev, z):
-        for s, v in zip(sites, sig):
-            a[s, s] -= v
-    return spl.splu(sp.csc_matrix(a))
+    return _Factor(dev, z)
 
 
 def _rows(lu, n, sites):
     b = np.zeros((n, len(sites)), dtype=np.complex128)
     b[np.asarray(sites), np.arange(len(sites))] = 1.0
-    return lu.solve(b, trans="T")         # column j = row sites[j] of A^-1
+    return lu.solve_t(b)                  # column j = row sites[j] of A^-1
 
 
 def solve_sites(dev, energies, eta, kT, mu_L, mu_R, sites, want_trans=False, chunk=128):

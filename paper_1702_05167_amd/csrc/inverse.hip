@@ -36,7 +36,7 @@ __device__ inline double2 crcp(double2 a) {
 }
 
 template <int RPT, int NB>
-__global__ __launch_bounds__(PT) void k_inv_panel(const InvJob* __restrict__ jobs, int k0, int nbw,
+__global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_inv_panel(const InvJob* __restrict__ jobs, int k0, int nbw,
                                                   int32_t* __restrict__ status) {
   const InvJob jb = jobs[blockIdx.x];
   const int n = jb.n;
@@ -45,10 +45,11 @@ __global__ __launch_bounds__(PT) void k_inv_panel(const InvJob* __restrict__ job
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   __shared__ double red_v[PT / 64];
   __shared__ int red_i[PT / 64];
-  __shared__ double2 rowp[NB], rowc[NB];
+  __shared__ double2 rowp[NB], rowc[NB], srow[NB];
   __shared__ int bad;
   if (t == 0) bad = 0;
 
+  // the panel: row t + q*PT of the n x nb block, in registers
   double2 P[RPT][NB];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
@@ -64,79 +65,86 @@ __global__ __launch_bounds__(PT) void k_inv_panel(const InvJob* __restrict__ job
 
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    if (j >= nb) break;
-    const int c = k0 + j;
-    // pivot search over rows >= c (largest |re|+|im|, smallest row on ties)
-    double bv = -1.0;
-    int bi = n;
+    if (j < nb) {   // uniform over the block
+      const int c = k0 + j;
+      // pivot: largest |re|+|im| among rows >= c, smallest row on ties
+      double bv = -1.0;
+      int bi = n;
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = t + q * PT;
-      if (r >= c && r < n) {
-        const double v = cabs1(P[q][j]);
-        if (v > bv) { bv = v; bi = r; }
-      }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(bv, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-    }
-    if (lane == 0) { red_v[w] = bv; red_i[w] = bi; }
-    __syncthreads();
-    double pv = red_v[0];
-    int prow = red_i[0];
-#pragma unroll
-    for (int k = 1; k < PT / 64; ++k) {
-      const double ov = red_v[k];
-      const int oi = red_i[k];
-      if (ov > pv || (ov == pv && oi < prow)) { pv = ov; prow = oi; }
-    }
-    // exchange rows c and prow through LDS
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = t + q * PT;
-      if (r == prow) {
-#pragma unroll
-        for (int jj = 0; jj < NB; ++jj) rowp[jj] = P[q][jj];
-      }
-      if (r == c && prow != c) {
-#pragma unroll
-        for (int jj = 0; jj < NB; ++jj) rowc[jj] = P[q][jj];
-      }
-    }
-    if (t == 0) jb.piv[c] = prow;
-    __syncthreads();
-    const double2 pivv = rowp[j];
-    if (!(pv > 0.0) || !isfinite(pivv.x) || !isfinite(pivv.y)) {
-      if (t == 0) bad = 1;
-    }
-    const double2 inv = crcp(pivv);
-    double2 s[NB];
-#pragma unroll
-    for (int jj = 0; jj < NB; ++jj) s[jj] = cmul(rowp[jj], inv);
-    s[j] = inv;
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = t + q * PT;
-      if (r == prow && prow != c) {
-#pragma unroll
-        for (int jj = 0; jj < NB; ++jj) P[q][jj] = rowc[jj];
-      }
-      if (r == c) {
-#pragma unroll
-        for (int jj = 0; jj < NB; ++jj) P[q][jj] = s[jj];
-      } else {
-        const double2 m = P[q][j];
-#pragma unroll
-        for (int jj = 0; jj < NB; ++jj) {
-          const double2 u = cmul(m, s[jj]);
-          P[q][jj].x -= u.x;
-          P[q][jj].y -= u.y;
+      for (int q = 0; q < RPT; ++q) {
+        const int r = t + q * PT;
+        if (r >= c && r < n) {
+          const double v = cabs1(P[q][j]);
+          if (v > bv) { bv = v; bi = r; }
         }
-        const double2 u = cmul(m, inv);
-        P[q][j] = make_double2(-u.x, -u.y);
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+      }
+      if (lane == 0) { red_v[w] = bv; red_i[w] = bi; }
+      __syncthreads();
+      double pv = red_v[0];
+      int prow = red_i[0];
+#pragma unroll
+      for (int k = 1; k < PT / 64; ++k) {
+        const double ov = red_v[k];
+        const int oi = red_i[k];
+        if (ov > pv || (ov == pv && oi < prow)) { pv = ov; prow = oi; }
+      }
+      if (prow >= n) {   // no candidate row (cannot happen for n <= RPT*PT): keep row c, flag
+        prow = c;
+        pv = 0.0;
+      }
+      // rows c and prow go through LDS
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int r = t + q * PT;
+        if (r == prow) {
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj) rowp[jj] = P[q][jj];
+        }
+        if (r == c && prow != c) {
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj) rowc[jj] = P[q][jj];
+        }
+      }
+      if (t == 0) jb.piv[c] = prow;
+      __syncthreads();
+      // scaled pivot row
+      if (t < NB) {
+        const double2 pivv = rowp[j];
+        const double2 inv = crcp(pivv);
+        srow[t] = (t == j) ? inv : cmul(rowp[t], inv);
+        if (t == 0 && (!(pv > 0.0) || !isfinite(pivv.x) || !isfinite(pivv.y))) bad = 1;
+      }
+      __syncthreads();
+      const double2 inv = srow[j];
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int r = t + q * PT;
+        if (r == c) {
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj) P[q][jj] = srow[jj];
+        } else {
+          if (r == prow) {
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) P[q][jj] = rowc[jj];
+          }
+          const double2 m = P[q][j];
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj) {
+            if (jj != j) {
+              const double2 u = cmul(m, srow[jj]);
+              P[q][jj].x -= u.x;
+              P[q][jj].y -= u.y;
+            }
+          }
+          const double2 u = cmul(m, inv);
+          P[q][j] = make_double2(-u.x, -u.y);
+        }
       }
     }
   }
@@ -216,10 +224,10 @@ __global__ __launch_bounds__(256) void k_inv_unscramble(const InvJob* __restrict
 
 void launch_inv_panel(hipStream_t st, const InvJob* jobs, int njobs, int k0, int nb, int max_n,
                       int32_t* status) {
-  if (njobs <= 0) return;
+  if (njobs <= 0 || max_n > 8 * PT) return;   // callers validate n <= 4096
   dim3 g(njobs), b(PT);
-  if (max_n <= 512 && nb <= 32)
-    hipLaunchKernelGGL((k_inv_panel<1, 32>), g, b, 0, st, jobs, k0, nb, status);
+  if (max_n <= 512 && nb <= 16)
+    hipLaunchKernelGGL((k_inv_panel<1, 16>), g, b, 0, st, jobs, k0, nb, status);
   else if (max_n <= 1024 && nb <= 16)
     hipLaunchKernelGGL((k_inv_panel<2, 16>), g, b, 0, st, jobs, k0, nb, status);
   else if (max_n <= 2048 && nb <= 8)

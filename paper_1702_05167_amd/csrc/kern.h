@@ -121,6 +121,10 @@ void launch_inv_panel(hipStream_t st, const InvJob* jobs, int njobs, int k0, int
 void launch_inv_swap(hipStream_t st, const InvJob* jobs, int njobs, int k0, int nb, int max_n);
 void launch_inv_unscramble(hipStream_t st, const InvJob* jobs, int njobs, int max_n);
 
+// guard[(e_base + slot) * nclusters + cluster][0..1] = ||Inv||_inf, ||Psi||_inf (one block per job)
+void launch_guard(hipStream_t st, const RowJob* jobs, int njobs, int nclusters, int e_base, int nvalid,
+                  double* out);
+
 // debug / unit-test helpers
 void launch_mfma_probe(hipStream_t st, double* out);
 

@@ -248,7 +248,52 @@ __global__ void k_combine_gl(const double* __restrict__ spec, int nvalid, int e_
   gl[eg * n + s] = make_double2(0.0, es[e].fermi[0] * al + es[e].fermi[1] * ar);
 }
 
+// per (cluster, slot): infinity norms (max row sum of moduli) of Inv = A_ii^-1
+// and of Psi.  For the complex-symmetric Inv, ||Inv||_2 <= ||Inv||_inf.
+//   jobs: src = Inv (n x n, ld lds), p0 = Psi (n x f), aux0 = n, aux1 = f, aux2 = cluster index
+__global__ __launch_bounds__(RB) void k_guard(const RowJob* __restrict__ jobs, int nclusters, int e_base, int nvalid,
+                                              double* __restrict__ out) {
+  const RowJob& jb = jobs[blockIdx.x];
+  if (jb.e >= nvalid) return;
+  const int n = jb.aux0, f = jb.aux1;
+  const double2* psi = reinterpret_cast<const double2*>(jb.p0);
+  __shared__ double red[2][RB];
+  double mi = 0.0, mp = 0.0;
+  for (int r = threadIdx.x; r < n; r += RB) {
+    double si = 0.0, sp = 0.0;
+    const double2* row = jb.src + (int64_t)r * jb.lds;
+    for (int j = 0; j < n; ++j) si += hypot(row[j].x, row[j].y);
+    if (psi) {
+      const double2* prow = psi + (int64_t)r * f;
+      for (int j = 0; j < f; ++j) sp += hypot(prow[j].x, prow[j].y);
+    }
+    mi = fmax(mi, si);
+    mp = fmax(mp, sp);
+  }
+  red[0][threadIdx.x] = mi;
+  red[1][threadIdx.x] = mp;
+  __syncthreads();
+  for (int s = RB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + s]);
+      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int64_t o = ((int64_t)(e_base + jb.e) * nclusters + jb.aux2) * 2;
+    out[o] = red[0][0];
+    out[o + 1] = red[1][0];
+  }
+}
+
 }  // namespace
+
+void launch_guard(hipStream_t st, const RowJob* jobs, int njobs, int nclusters, int e_base, int nvalid,
+                  double* out) {
+  if (njobs <= 0 || !out) return;
+  hipLaunchKernelGGL(k_guard, dim3(njobs), dim3(RB), 0, st, jobs, nclusters, e_base, nvalid, out);
+}
 
 void launch_energy_setup(hipStream_t st, const double* energies, int nvalid, int nslots, double eta,
                          double kT, double mu_L, double mu_R, LeadParams lp, EnergyScalars* out,

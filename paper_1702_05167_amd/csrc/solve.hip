@@ -53,7 +53,7 @@ struct Blob {
   void reloc(size_t field) { relocs.push_back(field); }
 };
 
-enum StepKind { S_ASSEMBLE, S_INV_PANEL, S_INV_SWAP, S_INV_UNSCR, S_GEMM, S_GATHER, S_ASSEMBLE_N, S_DIAG };
+enum StepKind { S_ASSEMBLE, S_INV_PANEL, S_INV_SWAP, S_INV_UNSCR, S_GEMM, S_GATHER, S_ASSEMBLE_N, S_DIAG, S_GUARD };
 
 struct Step {
   StepKind kind;
@@ -64,9 +64,13 @@ struct Step {
   double ar = 1, ai = 0;
   int beta = 0;
   int out = 0;                // DIAG destination
+  double flops = 0;           // algorithmic real flops of this launch (GEMM: 8 M N K)
 };
 
 enum OutSel { O_GR = 0, O_GL = 1, O_SPEC_L = 2, O_SPEC_R = 3, O_AR_TMP = 4 };
+
+// largest dense cluster block the batched inversion handles (512 threads x 8 rows)
+constexpr int kMaxCluster = 4096;
 
 struct Channel {
   int type;      // 0 both contacts (with occupations), 1 left, 2 right
@@ -105,6 +109,12 @@ struct hsc_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::vector<std::unique_ptr<hsc::Plan>> plans;
+  // optional per-launch timing: events around every launch, grouped by step kind
+  bool profile = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+  std::vector<std::pair<int, double>> ev_meta;   // (kind, flops) per recorded launch
+  size_t ev_used = 0;
+  double prof[16][3] = {};                        // kind -> launches, ms, flops
 };
 
 namespace hsc {
@@ -159,12 +169,12 @@ struct Builder {
   // own rows of cluster i in channel ch: (row0, r)
   void own_rows(const Channel& ch, int i, int* row0, int* r) const {
     const Cluster& c = t->cl[i];
-    if (!leaf(i)) { *row0 = 0; *r = c.n; return; }
+    if (!leaf(i) || root(i)) { *row0 = 0; *r = c.n; return; }
     if (ch.type == 0) { *row0 = 0; *r = c.n_left + c.n_right; }
     else if (ch.type == 1) { *row0 = 0; *r = c.n_left; }
     else { *row0 = c.n_left; *r = c.n_right; }
   }
-  int inv_nb(int maxn) const { return maxn <= 512 ? 32 : maxn <= 1024 ? 16 : maxn <= 2048 ? 8 : 4; }
+  int inv_nb(int maxn) const { return maxn <= 1024 ? 16 : maxn <= 2048 ? 8 : 4; }
 
   void channels() {
     if (want & HSC_SPECTRAL_LR) {
@@ -338,6 +348,7 @@ struct Builder {
     if (probs.empty()) return;
     Step s;
     s.kind = S_GEMM;
+    for (const GemmProb& p : probs) s.flops += 8.0 * p.M * p.N * p.K;
     s.jobs = blob.push(probs);
     s.map = blob.push(tmap);
     s.count = (int)tmap.size();
@@ -481,6 +492,23 @@ struct Builder {
       gemm(OP_N, OP_N, pp, -1.0, 0.0, 0);
       gemm(OP_T, OP_N, pu, 1.0, 0.0, 1);
     }
+    // conditioning / growth indicators of every pivot block
+    std::vector<RowJob> gj;
+    for (int i = 0; i < (int)t->cl.size(); ++i)
+      for (int e = 0; e < B; ++e) {
+        const CS& s = cs[(size_t)i * B + e];
+        RowJob j{};
+        j.e = e;
+        j.src = W(s.Inv); j.lds = n_of(i);
+        j.p0 = root(i) ? nullptr : W(s.Psi);
+        j.aux0 = n_of(i); j.aux1 = f_of(i); j.aux2 = i;
+        gj.push_back(j);
+      }
+    Step g;
+    g.kind = S_GUARD;
+    g.jobs = blob.push(gj);
+    g.njobs = (int)gj.size();
+    steps.push_back(g);
   }
 
   void diag_step(const std::vector<int>& ids, int mode, int out, int chan, bool g_phase) {
@@ -624,7 +652,7 @@ struct Builder {
           }
           q.j.aux0 = (int)q.kids.size();
           q.j.aux1 = r; q.j.aux2 = row0; q.j.aux3 = n; q.j.aux4 = c.n_left; q.j.aux5 = c.n_right;
-          if (leaf(i)) { q.j.src = W(s.SD); q.j.lds = n + P; }
+          if (leaf(i) && !root(i)) { q.j.src = W(s.SD); q.j.lds = n + P; }
           else { q.j.src = W(s.GX); q.j.lds = gcols(i); }
           asm_jobs.push_back(q);
           if (!root(i)) {
@@ -715,10 +743,25 @@ struct Builder {
   }
 };
 
-int run_steps(hsc_ctx* ctx, Plan* pl, int e_base, int nvalid, void* gr, void* glo, double* spectral) {
+int run_steps(hsc_ctx* ctx, Plan* pl, int e_base, int nvalid, void* gr, void* glo, double* spectral,
+              double* guard, int nclusters) {
   hipStream_t st = ctx->stream;
   const int64_t n = pl->n;
   for (const Step& s : pl->steps) {
+    hipEvent_t ev1 = nullptr;
+    if (ctx->profile) {
+      if (ctx->ev_used == ctx->ev_pool.size()) {
+        hipEvent_t a, b;
+        HIPCHK(hipEventCreate(&a));
+        HIPCHK(hipEventCreate(&b));
+        ctx->ev_pool.push_back({a, b});
+        ctx->ev_meta.push_back({0, 0.0});
+      }
+      HIPCHK(hipEventRecord(ctx->ev_pool[ctx->ev_used].first, st));
+      ev1 = ctx->ev_pool[ctx->ev_used].second;
+      ctx->ev_meta[ctx->ev_used] = {(int)s.kind, s.flops};
+      ctx->ev_used++;
+    }
     const void* jobs = pl->blob + s.jobs;
     const int32_t* map = reinterpret_cast<const int32_t*>(pl->blob + s.map);
     switch (s.kind) {
@@ -743,6 +786,9 @@ int run_steps(hsc_ctx* ctx, Plan* pl, int e_base, int nvalid, void* gr, void* gl
       case S_INV_UNSCR:
         launch_inv_unscramble(st, (const InvJob*)jobs, s.njobs, s.i2);
         break;
+      case S_GUARD:
+        launch_guard(st, (const RowJob*)jobs, s.njobs, nclusters, e_base, nvalid, guard);
+        break;
       case S_DIAG: {
         void* out = nullptr;
         int kind = OUT_COMPLEX, eb = e_base;
@@ -758,18 +804,37 @@ int run_steps(hsc_ctx* ctx, Plan* pl, int e_base, int nvalid, void* gr, void* gl
         break;
       }
     }
+    if (ev1) HIPCHK(hipEventRecord(ev1, st));
   }
   HIPCHK(hipGetLastError());
   return HSC_OK;
 }
 
 int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, Plan** out) {
-  for (auto& p : ctx->plans)
-    if (p->uid == t->uid && p->B == B && p->want == want) { *out = p.get(); return HSC_OK; }
-  // keep memory bounded: drop plans of this tree with other shapes
+  for (size_t k = 0; k < ctx->plans.size(); ++k)
+    if (ctx->plans[k]->uid == t->uid && ctx->plans[k]->B == B && ctx->plans[k]->want == want) {
+      // most recently used goes last
+      std::unique_ptr<Plan> p = std::move(ctx->plans[k]);
+      ctx->plans.erase(ctx->plans.begin() + k);
+      ctx->plans.push_back(std::move(p));
+      *out = ctx->plans.back().get();
+      return HSC_OK;
+    }
+  // keep memory bounded: drop plans of this tree with other shapes, then the
+  // least recently used ones beyond a few
   ctx->plans.erase(std::remove_if(ctx->plans.begin(), ctx->plans.end(),
                                   [&](const std::unique_ptr<Plan>& p) { return p->uid == t->uid; }),
                    ctx->plans.end());
+  HIPCHK(hipSetDevice(ctx->device));
+  if (ctx->stream) { HIPCHK(hipStreamSynchronize(ctx->stream)); }
+  else { HIPCHK(hipDeviceSynchronize()); }
+  while (ctx->plans.size() > 3) ctx->plans.erase(ctx->plans.begin());
+  for (const Cluster& c : t->cl)
+    if (c.n > kMaxCluster) {
+      set_error("cluster of " + std::to_string(c.n) + " sites exceeds the dense-block limit of " +
+                std::to_string(kMaxCluster) + " (use a smaller leaf side)");
+      return HSC_E_ARG;
+    }
   std::unique_ptr<Plan> pl(new Plan());
   pl->uid = t->uid; pl->B = B; pl->want = want; pl->n = t->n;
   Builder b{t, B, want, (want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR)) != 0};
@@ -861,14 +926,17 @@ hsc_status hsc_ctx_destroy(hsc_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   else (void)hipDeviceSynchronize();
+  for (auto& e : ctx->ev_pool) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
   delete ctx;
   return HSC_OK;
 }
 
-hsc_status hsc_solve(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, const double* energies,
-                     const hsc_solve_opts* opts, void* diag_gr, void* diag_gl, double* trans,
-                     double* spectral_lr, int32_t* status, double* guard) {
-  (void)guard;
+static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, const double* energies,
+                             const hsc_solve_opts* opts, void* diag_gr, void* diag_gl, double* trans,
+                             double* spectral_lr, int32_t* status, double* guard) {
   if (!ctx || !tree || !opts || n_e < 0) { set_error("null argument to hsc_solve"); return HSC_E_ARG; }
   if (n_e == 0) return HSC_OK;
   if (!energies) { set_error("energies is NULL"); return HSC_E_ARG; }
@@ -898,7 +966,7 @@ hsc_status hsc_solve(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, const doub
     const int nv = std::min(B, n_e - e0);
     launch_energy_setup(ctx->stream, energies + e0, nv, B, opts->eta, opts->kT, opts->mu_L, opts->mu_R, pl->lp,
                         pl->es, pl->status);
-    st = run_steps(ctx, pl, e0, nv, diag_gr, diag_gl, spectral_lr);
+    st = run_steps(ctx, pl, e0, nv, diag_gr, diag_gl, spectral_lr, guard, (int)tree->cl.size());
     if (st != HSC_OK) return (hsc_status)st;
     if (want & HSC_TRANS) {
       if (want & HSC_SPECTRAL_LR)
@@ -913,6 +981,159 @@ hsc_status hsc_solve(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, const doub
   }
   HIPCHK(hipGetLastError());
   return HSC_OK;
+}
+
+// Growth guard: re-solve flagged energies on merged trees (delayed pivots).
+// Energies are grouped by (current tree, set of flagged clusters); each group
+// merges its flagged clusters into their parents (never beyond the dense-block
+// limit) and is solved again, until no block is flagged or the rounds run out.
+namespace {
+struct GuardItem {
+  int e;                                   // index into the caller's arrays
+  std::shared_ptr<hsc_tree> tree;          // null: the caller's tree
+  std::vector<int> bad;                    // flagged clusters of that tree
+};
+std::vector<int> flagged(const double* g, int nc, double tau) {
+  std::vector<int> b;
+  for (int i = 0; i < nc - 1; ++i)
+    if (!(g[2 * i] <= tau)) b.push_back(i);
+  return b;
+}
+}  // namespace
+
+static hsc_status guard_loop(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, const double* energies,
+                             const hsc_solve_opts* opts, void* diag_gr, void* diag_gl, double* trans,
+                             double* spectral_lr, int32_t* status, double* guard_dev) {
+  const int64_t n = tree->n;
+  const uint32_t want = opts->want;
+  std::vector<double> e_host(n_e);
+  HIPCHK(hipMemcpy(e_host.data(), energies, sizeof(double) * n_e, hipMemcpyDeviceToHost));
+  const int nc0 = (int)tree->cl.size();
+  std::vector<double> g((size_t)n_e * nc0 * 2);
+  HIPCHK(hipMemcpy(g.data(), guard_dev, sizeof(double) * g.size(), hipMemcpyDeviceToHost));
+  std::vector<GuardItem> items;
+  for (int e = 0; e < n_e; ++e) {
+    std::vector<int> b = flagged(&g[(size_t)e * nc0 * 2], nc0, opts->guard_tau);
+    if (!b.empty()) items.push_back({e, nullptr, b});
+  }
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  for (int round = 0; round < opts->guard_rounds && !items.empty(); ++round) {
+    // group by (tree, flagged set)
+    std::sort(items.begin(), items.end(), [](const GuardItem& a, const GuardItem& b) {
+      if (a.tree.get() != b.tree.get()) return a.tree.get() < b.tree.get();
+      return a.bad < b.bad;
+    });
+    std::vector<GuardItem> next;
+    for (size_t g0 = 0; g0 < items.size();) {
+      size_t g1 = g0;
+      while (g1 < items.size() && items[g1].tree.get() == items[g0].tree.get() && items[g1].bad == items[g0].bad) ++g1;
+      const hsc_tree* t = items[g0].tree ? items[g0].tree.get() : tree;
+      // merge the flagged clusters, parents first, within the block-size limit
+      std::vector<char> mark(t->cl.size(), 0);
+      for (int i : items[g0].bad) mark[i] = 1;
+      std::vector<int64_t> size(t->cl.size());
+      for (size_t i = 0; i < t->cl.size(); ++i) size[i] = t->cl[i].n;
+      std::vector<int32_t> ids;
+      for (int i = (int)mark.size() - 2; i >= 0; --i) {
+        if (!mark[i]) continue;
+        int p = t->cl[i].parent;
+        while (p >= 0 && mark[p]) p = t->cl[p].parent;   // nearest surviving ancestor
+        if (p < 0 || size[p] + size[i] > kMaxCluster) { mark[i] = 0; continue; }
+        size[p] += size[i];
+        size[i] = 0;
+        ids.push_back((int32_t)i);
+      }
+      if (ids.empty()) {   // nothing can be merged: these energies stay flagged
+        for (size_t q = g0; q < g1; ++q) next.push_back(items[q]);
+        g0 = g1;
+        continue;
+      }
+      hsc_tree* m = nullptr;
+      hsc_status rc = hsc_tree_merge(t, (int32_t)ids.size(), ids.data(), &m);
+      if (rc != HSC_OK) return rc;
+      std::shared_ptr<hsc_tree> mt(m, hsc_tree_destroy);
+      const int nc = (int)m->cl.size();
+      const int k = (int)(g1 - g0);
+      std::vector<double> eh(k);
+      for (int q = 0; q < k; ++q) eh[q] = e_host[items[g0 + q].e];
+      const size_t o_e = 0, o_gr = al(8 * (size_t)k), o_gl = al(o_gr + 16 * (size_t)k * n),
+                   o_sp = al(o_gl + 16 * (size_t)k * n), o_tr = al(o_sp + 16 * (size_t)k * n),
+                   o_st = al(o_tr + 8 * (size_t)k), o_gd = al(o_st + 4 * (size_t)k),
+                   bytes = al(o_gd + 16 * (size_t)k * nc);
+      char* tmp = nullptr;
+      if (hipMalloc(&tmp, bytes) != hipSuccess) { (void)hipGetLastError(); set_error("guard temporaries"); return HSC_E_OOM; }
+      std::unique_ptr<char, hipError_t (*)(void*)> hold(tmp, hipFree);
+      HIPCHK(hipMemcpy(tmp + o_e, eh.data(), 8 * k, hipMemcpyHostToDevice));
+      rc = solve_core(ctx, m, k, (double*)(tmp + o_e), opts, tmp + o_gr, tmp + o_gl, (double*)(tmp + o_tr),
+                      (double*)(tmp + o_sp), (int32_t*)(tmp + o_st), (double*)(tmp + o_gd));
+      if (rc != HSC_OK) return rc;
+      hipStream_t st = ctx->stream;
+      for (int q = 0; q < k; ++q) {
+        const int e = items[g0 + q].e;
+        if ((want & HSC_DIAG_GR) && diag_gr)
+          HIPCHK(hipMemcpyAsync((char*)diag_gr + 16 * (size_t)e * n, tmp + o_gr + 16 * (size_t)q * n, 16 * n,
+                                hipMemcpyDeviceToDevice, st));
+        if ((want & HSC_DIAG_GL) && diag_gl)
+          HIPCHK(hipMemcpyAsync((char*)diag_gl + 16 * (size_t)e * n, tmp + o_gl + 16 * (size_t)q * n, 16 * n,
+                                hipMemcpyDeviceToDevice, st));
+        if ((want & HSC_SPECTRAL_LR) && spectral_lr)
+          HIPCHK(hipMemcpyAsync(spectral_lr + 2 * (size_t)e * n, tmp + o_sp + 16 * (size_t)q * n, 16 * n,
+                                hipMemcpyDeviceToDevice, st));
+        if ((want & HSC_TRANS) && trans)
+          HIPCHK(hipMemcpyAsync(trans + e, tmp + o_tr + 8 * (size_t)q, 8, hipMemcpyDeviceToDevice, st));
+        if (status)
+          HIPCHK(hipMemcpyAsync(status + e, tmp + o_st + 4 * (size_t)q, 4, hipMemcpyDeviceToDevice, st));
+      }
+      std::vector<double> gk((size_t)k * nc * 2);
+      HIPCHK(hipMemcpyAsync(gk.data(), tmp + o_gd, sizeof(double) * gk.size(), hipMemcpyDeviceToHost, st));
+      HIPCHK(st ? hipStreamSynchronize(st) : hipDeviceSynchronize());
+      for (int q = 0; q < k; ++q) {
+        std::vector<int> b = flagged(&gk[(size_t)q * nc * 2], nc, opts->guard_tau);
+        if (!b.empty()) next.push_back({items[g0 + q].e, mt, b});
+      }
+      const uint64_t uid = m->uid;   // merged plans are temporary
+      ctx->plans.erase(std::remove_if(ctx->plans.begin(), ctx->plans.end(),
+                                      [&](const std::unique_ptr<Plan>& p) { return p->uid == uid; }),
+                       ctx->plans.end());
+      g0 = g1;
+    }
+    items.swap(next);
+  }
+  if (!items.empty() && status) {
+    const int32_t code = HSC_E_UNSTABLE;
+    for (const GuardItem& it : items) HIPCHK(hipMemcpy(status + it.e, &code, 4, hipMemcpyHostToDevice));
+  }
+  return HSC_OK;
+}
+
+hsc_status hsc_solve(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, const double* energies,
+                     const hsc_solve_opts* opts, void* diag_gr, void* diag_gl, double* trans,
+                     double* spectral_lr, int32_t* status, double* guard) {
+  if (!opts || !(opts->guard_tau > 0.0))
+    return solve_core(ctx, tree, n_e, energies, opts, diag_gr, diag_gl, trans, spectral_lr, status, guard);
+  if (!ctx || !tree || n_e < 0 || opts->guard_rounds < 0) { set_error("bad arguments to hsc_solve"); return HSC_E_ARG; }
+  if (n_e == 0) return HSC_OK;
+  HIPCHK(hipSetDevice(ctx->device));
+  double* gd = guard;
+  char* own = nullptr;
+  if (!gd) {
+    if (hipMalloc(&own, sizeof(double) * 2 * (size_t)n_e * tree->cl.size()) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("guard buffer allocation failed");
+      return HSC_E_OOM;
+    }
+    gd = (double*)own;
+  }
+  hsc_status rc = solve_core(ctx, tree, n_e, energies, opts, diag_gr, diag_gl, trans, spectral_lr, status, gd);
+  if (rc == HSC_OK) {
+    if (ctx->stream) { HIPCHK(hipStreamSynchronize(ctx->stream)); } else { HIPCHK(hipDeviceSynchronize()); }
+    rc = guard_loop(ctx, tree, n_e, energies, opts, diag_gr, diag_gl, trans, spectral_lr, status, gd);
+  }
+  if (own) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(own);
+  }
+  return rc;
 }
 
 hsc_status hsc_solve_batch(hsc_ctx* ctx, int32_t n_trees, const hsc_tree* const* trees, const int32_t* n_e,
@@ -939,6 +1160,31 @@ hsc_status hsc_sync(hsc_ctx* ctx) {
   if (ctx->stream) { HIPCHK(hipStreamSynchronize(ctx->stream)); }
   else { HIPCHK(hipDeviceSynchronize()); }
   HIPCHK(hipGetLastError());
+  // fold recorded launch timings into the per-kind totals
+  for (size_t k = 0; k < ctx->ev_used; ++k) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->ev_pool[k].first, ctx->ev_pool[k].second));
+    const int kind = ctx->ev_meta[k].first;
+    ctx->prof[kind][0] += 1;
+    ctx->prof[kind][1] += ms;
+    ctx->prof[kind][2] += ctx->ev_meta[k].second;
+  }
+  ctx->ev_used = 0;
+  return HSC_OK;
+}
+
+hsc_status hsc_ctx_profile(hsc_ctx* ctx, int32_t enable) {
+  if (!ctx) { set_error("null ctx"); return HSC_E_ARG; }
+  ctx->profile = enable != 0;
+  ctx->ev_used = 0;
+  std::memset(ctx->prof, 0, sizeof(ctx->prof));
+  return HSC_OK;
+}
+
+hsc_status hsc_ctx_profile_read(hsc_ctx* ctx, double* out, int32_t n_kinds) {
+  if (!ctx || !out || n_kinds < 0) { set_error("bad arguments"); return HSC_E_ARG; }
+  for (int k = 0; k < n_kinds && k < 16; ++k)
+    for (int q = 0; q < 3; ++q) out[3 * k + q] = ctx->prof[k][q];
   return HSC_OK;
 }
 
@@ -1006,7 +1252,7 @@ hsc_status hsc_kern_zinv_batched(hsc_ctx* ctx, int32_t count, const int32_t* n, 
   }
   if (count == 0) return HSC_OK;
   HIPCHK(hipSetDevice(ctx->device));
-  const int nb = maxn <= 512 ? 32 : maxn <= 1024 ? 16 : maxn <= 2048 ? 8 : 4;
+  const int nb = maxn <= 1024 ? 16 : maxn <= 2048 ? 8 : 4;
   size_t ws = 0;
   std::vector<size_t> o_piv(count), o_t(count), o_r(count);
   auto wa = [&](size_t b) { size_t o = (ws + 255) / 256 * 256; ws = o + b; return o; };

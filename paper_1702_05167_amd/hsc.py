@@ -41,7 +41,8 @@ class TreeStats(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("eta", C.c_double), ("kT", C.c_double), ("mu_L", C.c_double), ("mu_R", C.c_double),
-                ("want", C.c_uint32), ("batch", C.c_int32)]
+                ("want", C.c_uint32), ("batch", C.c_int32), ("guard_tau", C.c_double),
+                ("guard_rounds", C.c_int32)]
 
 
 _lib = None
@@ -68,11 +69,14 @@ def lib():
     L.hsc_solve.argtypes = [vp, vp, i32, vp, C.POINTER(SolveOpts), vp, vp, vp, vp, vp, vp]
     L.hsc_solve_batch.argtypes = [vp, i32, vp, vp, vp, C.POINTER(SolveOpts), vp, vp, vp, vp, vp, vp]
     L.hsc_sync.argtypes = [vp]
+    L.hsc_ctx_profile.argtypes = [vp, i32]
+    L.hsc_ctx_profile_read.argtypes = [vp, vp, i32]
     L.hsc_kern_zgemm.argtypes = [vp, i32, i32, i32, i32, i32, dbl, dbl, vp, i32, vp, i32, i32, vp, i32, vp, i32]
     L.hsc_kern_zinv_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
     L.hsc_kern_mfma_probe.argtypes = [vp, vp]
     for name in ("hsc_ctx_create", "hsc_ctx_destroy", "hsc_tree_build", "hsc_tree_merge", "hsc_tree_stats_get",
                  "hsc_tree_export", "hsc_tree_destroy", "hsc_solve", "hsc_solve_batch", "hsc_sync",
+                 "hsc_ctx_profile", "hsc_ctx_profile_read",
                  "hsc_kern_zgemm", "hsc_kern_zinv_batched", "hsc_kern_mfma_probe"):
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -110,6 +114,19 @@ class Context:
 
     def sync(self):
         check(lib().hsc_sync(self.h))
+
+    PROFILE_KINDS = ("assemble", "inv_panel", "inv_swap", "inv_unscramble", "gemm", "gather",
+                     "assemble_n", "diag", "guard")
+
+    def profile(self, enable: bool):
+        check(lib().hsc_ctx_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        k = len(self.PROFILE_KINDS)
+        buf = np.zeros(3 * k)
+        check(lib().hsc_ctx_profile_read(self.h, _ptr(buf), k))
+        return {name: dict(launches=buf[3 * i], ms=buf[3 * i + 1], flops=buf[3 * i + 2])
+                for i, name in enumerate(self.PROFILE_KINDS)}
 
     def close(self):
         if getattr(self, "h", None):
@@ -194,7 +211,8 @@ class Tree:
 
 
 def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1,
-          want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, out=None, sync=True):
+          want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, out=None, sync=True, guard=False,
+          guard_tau=0.0, guard_rounds=6):
     """Solve all energies; returns a dict of device tensors (gr, gl, trans, spectral, status)."""
     import torch
     dev = ctx.torch_device
@@ -211,9 +229,12 @@ def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R
         o["spectral"] = torch.empty((ne, 2, n), dtype=torch.float64, device=dev)
     if "status" not in o:
         o["status"] = torch.empty(ne, dtype=torch.int32, device=dev)
-    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch)
+    if guard and "guard" not in o:
+        o["guard"] = torch.zeros((ne, tree.stats()["n_clusters"], 2), dtype=torch.float64, device=dev)
+    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, guard_tau, guard_rounds)
     check(lib().hsc_solve(ctx.h, tree.h, ne, _dptr(e), C.byref(opts), _dptr(o.get("gr")), _dptr(o.get("gl")),
-                          _dptr(o.get("trans")), _dptr(o.get("spectral")), _dptr(o.get("status")), None))
+                          _dptr(o.get("trans")), _dptr(o.get("spectral")), _dptr(o.get("status")),
+                          _dptr(o.get("guard"))))
     if sync:
         ctx.sync()
     return o
