@@ -31,6 +31,9 @@ def main():
     ap.add_argument("--batch", type=int, default=0, help="energies per launch sequence (0 = auto)")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-energy-per-launch-sequence run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--precision", type=int, default=1,
+                    help="fold arithmetic: 1 = double-double (default), 0 = complex128 as in Algorithm 1")
+    ap.add_argument("--no-alt", action="store_true", help="skip timing the other fold precision")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); energies shard across GPUs "
@@ -49,7 +52,7 @@ def main():
     st = tree.stats()
     ctx = pkg.Context(0)
     E = torch.linspace(-6.0, 6.0, NE, dtype=torch.float64, device="cuda:0")
-    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1)
+    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=args.precision)
     want = pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS
     out = pkg.solve(ctx, tree, E, want=want, batch=args.batch, **kw)     # buffers + plan
     for _ in range(args.warmup):
@@ -72,6 +75,18 @@ def main():
     g = prof["gemm"]
     achieved = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
     total_ms = sum(v["ms"] for v in prof.values())
+    gd = prof["dd_gemm"]
+    dd_rate = gd["flops"] / (gd["ms"] * 1e-3) / 1e12 if gd["ms"] > 0 else None
+
+    alt = None
+    if not args.no_alt:
+        kw_alt = dict(kw, precision=1 - args.precision)
+        pkg.solve(ctx, tree, E[:8], want=want, batch=args.batch, **kw_alt)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        pkg.solve(ctx, tree, E, want=want, batch=args.batch, **kw_alt)
+        torch.cuda.synchronize()
+        alt = NE / (time.perf_counter() - t3)
 
     plain = None
     if not args.no_plain:
@@ -110,6 +125,9 @@ def main():
         "config": {"workload": f"cube{N}^3 x {NE} energies in [-6,6] (diag G^r, diag G^<, T)",
                    "sites": int(dev.n), "energies": NE, "leaf_side": 8, "clusters": st["n_clusters"],
                    "batch": args.batch or "auto", "plain_energies_per_s": plain,
+                   "fold": "double-double" if args.precision == 1 else "complex128",
+                   "other_fold_energies_per_s": alt,
+                   "dd_gemm_equiv_tflops": dd_rate,
                    "flops_per_energy": st["flops_per_energy"],
                    "whole_solve_tflops": st["flops_per_energy"] * value / 1e12,
                    "status_ok": status_ok,

@@ -105,6 +105,13 @@ typedef struct {
    * HSC_E_UNSTABLE.  With guard_tau > 0 the call waits for the device. */
   double guard_tau;          /* 0 disables the guard */
   int32_t guard_rounds;      /* maximum re-planning rounds (e.g. 6) */
+  /* Arithmetic of the fold (block inverses, multipliers Psi, Schur updates):
+   * 0 = complex128 (Algorithm 1 as written, on the FP64 matrix cores);
+   * 1 = double-double (about 106-bit significands, FP64 vector units); the
+   * extracts stay complex128.  The unpivoted cluster elimination amplifies the
+   * fold's rounding errors by up to ~1/sigma_min(A_ii)^2 at energies where a
+   * cluster block is nearly singular; 1 removes that loss. */
+  int32_t precision;
 } hsc_solve_opts;
 
 /* Library version string. */

@@ -1,0 +1,98 @@
+// Double-double arithmetic (value = hi + lo, |lo| <= ulp(hi)/2) for the fold.
+//
+// The unpivoted cluster elimination of Algorithm 1 forms Schur complements
+// whose entries mix large (1/sigma_min of a nearly singular block) and O(1)
+// parts; carrying the fold in double-double keeps the O(1) parts exact to
+// FP64 level.  Built from the classic error-free transformations:
+//   two_sum (Knuth): s + e == a + b exactly,
+//   two_prod via fused multiply-add: p + e == a * b exactly.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace hsc {
+
+struct dd {
+  double hi, lo;
+};
+
+struct zdd {   // complex double-double, 32 bytes
+  dd re, im;
+};
+
+__device__ __forceinline__ dd two_sum(double a, double b) {
+  const double s = a + b;
+  const double bb = s - a;
+  const double e = (a - (s - bb)) + (b - bb);
+  return dd{s, e};
+}
+
+__device__ __forceinline__ dd quick_two_sum(double a, double b) {   // |a| >= |b|
+  const double s = a + b;
+  return dd{s, b - (s - a)};
+}
+
+__device__ __forceinline__ dd two_prod(double a, double b) {
+  const double p = a * b;
+  return dd{p, fma(a, b, -p)};
+}
+
+// sum with error bounded by ~2^-104 (|x| + |y|) (the "sloppy" double-double add):
+// absolute accuracy relative to the operands, which is what the fold needs.
+__device__ __forceinline__ dd dd_add(dd x, dd y) {
+  dd s = two_sum(x.hi, y.hi);
+  s.lo += x.lo + y.lo;
+  return quick_two_sum(s.hi, s.lo);
+}
+
+__device__ __forceinline__ dd dd_neg(dd x) { return dd{-x.hi, -x.lo}; }
+__device__ __forceinline__ dd dd_sub(dd x, dd y) { return dd_add(x, dd_neg(y)); }
+
+__device__ __forceinline__ dd dd_mul(dd x, dd y) {
+  dd p = two_prod(x.hi, y.hi);
+  p.lo = fma(x.hi, y.lo, p.lo);
+  p.lo = fma(x.lo, y.hi, p.lo);
+  return quick_two_sum(p.hi, p.lo);
+}
+
+__device__ __forceinline__ dd dd_from(double a) { return dd{a, 0.0}; }
+
+// x / y: two Newton corrections of the FP64 quotient
+__device__ __forceinline__ dd dd_div(dd x, dd y) {
+  const double q1 = x.hi / y.hi;
+  dd r = dd_sub(x, dd_mul(dd_from(q1), y));
+  const double q2 = r.hi / y.hi;
+  r = dd_sub(r, dd_mul(dd_from(q2), y));
+  const double q3 = r.hi / y.hi;
+  dd q = quick_two_sum(q1, q2);
+  return dd_add(q, dd_from(q3));
+}
+
+__device__ __forceinline__ zdd zdd_from(double2 v) { return zdd{dd{v.x, 0.0}, dd{v.y, 0.0}}; }
+__device__ __forceinline__ double2 zdd_round(zdd v) { return make_double2(v.re.hi + v.re.lo, v.im.hi + v.im.lo); }
+__device__ __forceinline__ zdd zdd_zero() { return zdd{dd{0.0, 0.0}, dd{0.0, 0.0}}; }
+__device__ __forceinline__ zdd zdd_add(zdd a, zdd b) { return zdd{dd_add(a.re, b.re), dd_add(a.im, b.im)}; }
+__device__ __forceinline__ zdd zdd_sub(zdd a, zdd b) { return zdd{dd_sub(a.re, b.re), dd_sub(a.im, b.im)}; }
+__device__ __forceinline__ zdd zdd_neg(zdd a) { return zdd{dd_neg(a.re), dd_neg(a.im)}; }
+
+__device__ __forceinline__ zdd zdd_mul(zdd a, zdd b) {
+  return zdd{dd_sub(dd_mul(a.re, b.re), dd_mul(a.im, b.im)), dd_add(dd_mul(a.re, b.im), dd_mul(a.im, b.re))};
+}
+
+// acc + a * b
+__device__ __forceinline__ zdd zdd_fma(zdd acc, zdd a, zdd b) { return zdd_add(acc, zdd_mul(a, b)); }
+
+// 1 / a = conj(a) / |a|^2, with the larger component scaled out
+__device__ __forceinline__ zdd zdd_rcp(zdd a) {
+  const double s = fmax(fabs(a.re.hi), fabs(a.im.hi));
+  if (s == 0.0) return zdd_zero();
+  const dd inv_s = dd_from(1.0 / s);   // exact only up to rounding; it cancels below
+  const dd ar = dd_mul(a.re, inv_s), ai = dd_mul(a.im, inv_s);
+  const dd den = dd_add(dd_mul(ar, ar), dd_mul(ai, ai));   // |a/s|^2
+  const dd qr = dd_div(ar, den), qi = dd_div(dd_neg(ai), den);
+  return zdd{dd_mul(qr, inv_s), dd_mul(qi, inv_s)};
+}
+
+__device__ __forceinline__ double zdd_cabs1(zdd a) { return fabs(a.re.hi) + fabs(a.im.hi); }
+
+}  // namespace hsc

@@ -1,0 +1,350 @@
+// The fold of Algorithm 1 in double-double: frontal assembly, blocked
+// Gauss-Jordan inversion of the pivot blocks, and the multiplier / Schur-update
+// products.  Same structure as the FP64 kernels (inverse.hip, gemm.hip,
+// kernels.hip); every value is a complex double-double (dd.h) and the products
+// run on the FP64 vector units (on this chip their peak equals the FP64 matrix
+// cores', and double-double needs the error-free fused multiply-add).
+#include <hip/hip_runtime.h>
+
+#include "dd.h"
+#include "kern.h"
+
+namespace hsc {
+
+namespace {
+
+constexpr int RB = 256;
+
+// ---------------------------------------------------------------------------------------------
+// assembly: F[a][b] = sum_children U_k[invrel_k[a]][invrel_k[b]] + (-H)[a][b] + delta_ab (z - Sigma_a)
+__global__ __launch_bounds__(RB) void k_dd_assemble(const RowJob* __restrict__ jobs,
+                                                    const int32_t* __restrict__ row_job,
+                                                    const EnergyScalars* __restrict__ es) {
+  const int g = blockIdx.x;
+  const RowJob& jb = jobs[row_job[g]];
+  const int a = g - jb.row_off;
+  const int cols = jb.cols;
+  const ChildRef* kids = reinterpret_cast<const ChildRef*>(jb.p0);
+  const FrontSparse* fs = reinterpret_cast<const FrontSparse*>(jb.p1);
+  const int nk = jb.aux0, n = jb.aux1, nL = jb.aux2, nR = jb.aux3;
+  __shared__ int s_col[64];
+  __shared__ double2 s_val[64];
+  const int q0 = fs->ptr[a], q1 = fs->ptr[a + 1];
+  const int nq = min(q1 - q0, 64);
+  if (threadIdx.x < nq) {
+    s_col[threadIdx.x] = fs->col[q0 + threadIdx.x];
+    s_val[threadIdx.x] = fs->val[q0 + threadIdx.x];
+  }
+  __syncthreads();
+  zdd diag_add = zdd_zero();
+  if (a < n) {   // z - Sigma_a, as the exact sum of the two FP64 inputs
+    const EnergyScalars& s = es[jb.e];
+    if (a < nL + nR) {
+      const double2 sg = a < nL ? s.sig[0] : s.sig[1];
+      diag_add = zdd{two_sum(s.z.x, -sg.x), two_sum(s.z.y, -sg.y)};
+    } else {
+      diag_add = zdd_from(s.z);
+    }
+  }
+  zdd* out = reinterpret_cast<zdd*>(jb.dst) + (int64_t)a * jb.ldd;
+  for (int b = threadIdx.x; b < cols; b += RB) {
+    zdd v = zdd_zero();
+    for (int k = 0; k < nk; ++k) {
+      const int ia = kids[k].invrel[a];
+      if (ia < 0) continue;
+      const int ib = kids[k].invrel[b];
+      if (ib < 0) continue;
+      v = zdd_add(v, reinterpret_cast<const zdd*>(kids[k].U)[(int64_t)ia * kids[k].ldU + ib]);
+    }
+    for (int q = 0; q < nq; ++q)
+      if (s_col[q] == b) v = zdd_add(v, zdd_from(s_val[q]));
+    for (int q = q0 + 64; q < q1; ++q)
+      if (fs->col[q] == b) v = zdd_add(v, zdd_from(fs->val[q]));
+    if (b == a) v = zdd_add(v, diag_add);
+    out[b] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Gauss-Jordan panel in double-double (same algorithm as k_inv_panel)
+constexpr int PT = 512;
+
+template <int RPT, int NB>
+__global__ __launch_bounds__(PT) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_dd_inv_panel(
+    const InvJobDD* __restrict__ jobs, int k0, int nbw, int32_t* __restrict__ status) {
+  const InvJobDD jb = jobs[blockIdx.x];
+  const int n = jb.n;
+  if (k0 >= n) return;
+  const int nb = min(nbw, n - k0);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  __shared__ double red_v[PT / 64];
+  __shared__ int red_i[PT / 64];
+  __shared__ zdd rowp[NB], rowc[NB], srow[NB];
+  __shared__ int bad;
+  if (t == 0) bad = 0;
+
+  zdd P[RPT][NB];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = t + q * PT;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) P[q][j] = (r < n && j < nb) ? jb.X[(int64_t)r * jb.ld + k0 + j] : zdd_zero();
+  }
+  __syncthreads();
+
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    if (j < nb) {
+      const int c = k0 + j;
+      double bv = -1.0;
+      int bi = n;
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int r = t + q * PT;
+        if (r >= c && r < n) {
+          const double v = zdd_cabs1(P[q][j]);
+          if (v > bv) { bv = v; bi = r; }
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+      }
+      if (lane == 0) { red_v[w] = bv; red_i[w] = bi; }
+      __syncthreads();
+      double pv = red_v[0];
+      int prow = red_i[0];
+#pragma unroll
+      for (int k = 1; k < PT / 64; ++k) {
+        const double ov = red_v[k];
+        const int oi = red_i[k];
+        if (ov > pv || (ov == pv && oi < prow)) { pv = ov; prow = oi; }
+      }
+      if (prow >= n) { prow = c; pv = 0.0; }
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int r = t + q * PT;
+        if (r == prow) {
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj) rowp[jj] = P[q][jj];
+        }
+        if (r == c && prow != c) {
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj) rowc[jj] = P[q][jj];
+        }
+      }
+      if (t == 0) jb.piv[c] = prow;
+      __syncthreads();
+      if (t < NB) {
+        const zdd pivv = rowp[j];
+        const zdd inv = zdd_rcp(pivv);
+        srow[t] = (t == j) ? inv : zdd_mul(rowp[t], inv);
+        if (t == 0 && (!(pv > 0.0) || !isfinite(pivv.re.hi) || !isfinite(pivv.im.hi))) bad = 1;
+      }
+      __syncthreads();
+      const zdd inv = srow[j];
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int r = t + q * PT;
+        if (r == c) {
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj) P[q][jj] = srow[jj];
+        } else {
+          if (r == prow) {
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) P[q][jj] = rowc[jj];
+          }
+          const zdd m = P[q][j];
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj)
+            if (jj != j) P[q][jj] = zdd_sub(P[q][jj], zdd_mul(m, srow[jj]));
+          P[q][j] = zdd_neg(zdd_mul(m, inv));
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = t + q * PT;
+    if (r < n) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (j < nb) {
+          jb.X[(int64_t)r * jb.ld + k0 + j] = P[q][j];
+          zdd v = P[q][j];
+          if (r == k0 + j) v.re = dd_add(v.re, dd_from(-1.0));
+          jb.T[(int64_t)r * nb + j] = v;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (t == 0 && bad && status) atomicMin(&status[jb.e], (int32_t)HSC_E_SINGULAR);
+}
+
+__global__ __launch_bounds__(256) void k_dd_inv_swap(const InvJobDD* __restrict__ jobs, int k0, int nbw,
+                                                     int chunks) {
+  const InvJobDD jb = jobs[blockIdx.x / chunks];
+  const int n = jb.n;
+  if (k0 >= n) return;
+  const int nb = min(nbw, n - k0);
+  const int col = (blockIdx.x % chunks) * 256 + threadIdx.x;
+  if (col >= n) return;
+  const bool in_panel = col >= k0 && col < k0 + nb;
+  if (!in_panel) {
+    for (int j = 0; j < nb; ++j) {
+      const int c = k0 + j, p = jb.piv[c];
+      if (p != c) {
+        zdd* a = jb.X + (int64_t)c * jb.ld + col;
+        zdd* b = jb.X + (int64_t)p * jb.ld + col;
+        const zdd x = *a;
+        *a = *b;
+        *b = x;
+      }
+    }
+  }
+  for (int j = 0; j < nb; ++j)
+    jb.R[(int64_t)j * n + col] = in_panel ? zdd_zero() : jb.X[(int64_t)(k0 + j) * jb.ld + col];
+}
+
+__global__ __launch_bounds__(256) void k_dd_inv_unscramble(const InvJobDD* __restrict__ jobs, int rows_per_block,
+                                                           int chunks) {
+  extern __shared__ int idx[];
+  const InvJobDD jb = jobs[blockIdx.x / chunks];
+  const int n = jb.n;
+  const int r0 = (blockIdx.x % chunks) * rows_per_block;
+  if (r0 >= n) return;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) idx[j] = j;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int c = n - 1; c >= 0; --c) {
+      const int p = jb.piv[c];
+      const int a = idx[c];
+      idx[c] = idx[p];
+      idx[p] = a;
+    }
+  }
+  __syncthreads();
+  const int r1 = min(n, r0 + rows_per_block);
+  for (int r = r0; r < r1; ++r)
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      const zdd v = jb.X[(int64_t)r * jb.ld + idx[j]];
+      jb.Y[(int64_t)r * jb.ldy + j] = v;
+      jb.Y64[(int64_t)r * jb.ldy64 + j] = zdd_round(v);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// grouped complex double-double GEMM: 32 x 32 output tile, 256 threads, 2 x 2 outputs per thread.
+//   OPA 0: A'(m,k) = A[m*lda + k];  OPA 1: A'(m,k) = A[k*lda + m];  B is never transposed.
+constexpr int DT = 32, DK = 8;
+
+template <int OPA>
+__global__ __launch_bounds__(256) void k_dd_gemm(const GemmProbDD* __restrict__ probs,
+                                                 const int32_t* __restrict__ tile_prob, int total_tiles, int negate,
+                                                 int beta) {
+  __shared__ zdd As[DK][DT + 1];
+  __shared__ zdd Bs[DK][DT + 1];
+  const int per = (total_tiles + 7) >> 3;
+  const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (tile >= total_tiles) return;
+  const GemmProbDD& pr = probs[tile_prob[tile]];
+  const int local = tile - pr.tile_off;
+  const int m0 = (local / pr.tiles_n) * DT, n0 = (local % pr.tiles_n) * DT;
+  const int M = pr.M, N = pr.N, K = pr.K;
+  const int t = threadIdx.x;
+  const int tm = (t / 16) * 2, tn = (t % 16) * 2;   // this thread's 2 x 2 block
+  zdd acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = zdd_zero();
+  for (int k0 = 0; k0 < K; k0 += DK) {
+    // stage A' (DT x DK) and B (DK x DT): 256 elements each, one per thread
+    {
+      const int mm = OPA == 0 ? t / DK : t % DT;
+      const int kk = OPA == 0 ? t % DK : t / DT;
+      const int gm = m0 + mm, gk = k0 + kk;
+      zdd v = zdd_zero();
+      if (gm < M && gk < K) v = OPA == 0 ? pr.A[(int64_t)gm * pr.lda + gk] : pr.A[(int64_t)gk * pr.lda + gm];
+      As[kk][mm] = v;
+      const int bk = t / DT, bn = t % DT;
+      const int gbk = k0 + bk, gbn = n0 + bn;
+      zdd u = zdd_zero();
+      if (gbk < K && gbn < N) u = pr.B[(int64_t)gbk * pr.ldb + gbn];
+      Bs[bk][bn] = u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < DK; ++kk) {
+      const zdd a0 = As[kk][tm], a1 = As[kk][tm + 1];
+      const zdd b0 = Bs[kk][tn], b1 = Bs[kk][tn + 1];
+      acc[0][0] = zdd_fma(acc[0][0], a0, b0);
+      acc[0][1] = zdd_fma(acc[0][1], a0, b1);
+      acc[1][0] = zdd_fma(acc[1][0], a1, b0);
+      acc[1][1] = zdd_fma(acc[1][1], a1, b1);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int row = m0 + tm + i, col = n0 + tn + j;
+      if (row < M && col < N) {
+        zdd o = negate ? zdd_neg(acc[i][j]) : acc[i][j];
+        if (beta) o = zdd_add(o, pr.C[(int64_t)row * pr.ldc + col]);
+        pr.D[(int64_t)row * pr.ldd + col] = o;
+        if (pr.D64) pr.D64[(int64_t)row * pr.ldd64 + col] = zdd_round(o);
+      }
+    }
+}
+
+}  // namespace
+
+int dd_gemm_tile() { return DT; }
+int dd_inv_nb(int max_n) { return max_n <= 512 ? 8 : max_n <= 1024 ? 8 : max_n <= 2048 ? 4 : 2; }
+
+void launch_dd_gemm(hipStream_t st, int opA, const GemmProbDD* probs, const int32_t* tile_prob, int total_tiles,
+                    int negate, int beta) {
+  if (total_tiles <= 0) return;
+  const int per = (total_tiles + 7) / 8;
+  if (opA == 0)
+    hipLaunchKernelGGL((k_dd_gemm<0>), dim3(per * 8), dim3(256), 0, st, probs, tile_prob, total_tiles, negate, beta);
+  else
+    hipLaunchKernelGGL((k_dd_gemm<1>), dim3(per * 8), dim3(256), 0, st, probs, tile_prob, total_tiles, negate, beta);
+}
+
+void launch_dd_assemble(hipStream_t st, const RowJob* jobs, const int32_t* row_job, int total_rows,
+                        const EnergyScalars* es) {
+  if (total_rows <= 0) return;
+  hipLaunchKernelGGL(k_dd_assemble, dim3(total_rows), dim3(RB), 0, st, jobs, row_job, es);
+}
+
+void launch_dd_inv_panel(hipStream_t st, const InvJobDD* jobs, int njobs, int k0, int nb, int max_n,
+                         int32_t* status) {
+  if (njobs <= 0 || max_n > 8 * PT) return;
+  dim3 g(njobs), b(PT);
+  if (max_n <= 512) hipLaunchKernelGGL((k_dd_inv_panel<1, 8>), g, b, 0, st, jobs, k0, nb, status);
+  else if (max_n <= 1024) hipLaunchKernelGGL((k_dd_inv_panel<2, 8>), g, b, 0, st, jobs, k0, nb, status);
+  else if (max_n <= 2048) hipLaunchKernelGGL((k_dd_inv_panel<4, 4>), g, b, 0, st, jobs, k0, nb, status);
+  else hipLaunchKernelGGL((k_dd_inv_panel<8, 2>), g, b, 0, st, jobs, k0, nb, status);
+}
+
+void launch_dd_inv_swap(hipStream_t st, const InvJobDD* jobs, int njobs, int k0, int nb, int max_n) {
+  if (njobs <= 0) return;
+  const int chunks = (max_n + 255) / 256;
+  hipLaunchKernelGGL(k_dd_inv_swap, dim3(njobs * chunks), dim3(256), 0, st, jobs, k0, nb, chunks);
+}
+
+void launch_dd_inv_unscramble(hipStream_t st, const InvJobDD* jobs, int njobs, int max_n) {
+  if (njobs <= 0) return;
+  const int rpb = 16;
+  const int chunks = (max_n + rpb - 1) / rpb;
+  hipLaunchKernelGGL(k_dd_inv_unscramble, dim3(njobs * chunks), dim3(256), max_n * sizeof(int), st, jobs, rpb,
+                     chunks);
+}
+
+}  // namespace hsc

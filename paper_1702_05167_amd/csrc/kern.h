@@ -125,6 +125,44 @@ void launch_inv_unscramble(hipStream_t st, const InvJob* jobs, int njobs, int ma
 void launch_guard(hipStream_t st, const RowJob* jobs, int njobs, int nclusters, int e_base, int nvalid,
                   double* out);
 
+// ---- double-double fold (see dd.h) ----
+struct zdd;
+// Batched Gauss-Jordan in double-double: in place on X (zdd, ld); the inverse
+// goes to Y (zdd, ldy) and, rounded, to Y64 (complex128, ldy64).
+struct InvJobDD {
+  zdd* X;
+  zdd* Y;
+  double2* Y64;
+  int32_t n, ld, ldy, ldy64;
+  int32_t e;
+  int32_t* piv;
+  zdd* T;
+  zdd* R;
+};
+// D = sign * op(A) op(B) + beta * C in double-double; D64 (optional) = round(D).
+struct GemmProbDD {
+  const zdd* A;
+  const zdd* B;
+  const zdd* C;
+  zdd* D;
+  double2* D64;
+  int32_t M, N, K;
+  int32_t lda, ldb, ldc, ldd, ldd64;
+  int32_t tiles_n;
+  int32_t tile_off;
+};
+int dd_gemm_tile();
+void launch_dd_gemm(hipStream_t st, int opA, const GemmProbDD* probs, const int32_t* tile_prob, int total_tiles,
+                    int negate, int beta);
+// frontal assembly in double-double (RowJob.dst and ChildRef.U point to zdd)
+void launch_dd_assemble(hipStream_t st, const RowJob* jobs, const int32_t* row_job, int total_rows,
+                        const EnergyScalars* es);
+void launch_dd_inv_panel(hipStream_t st, const InvJobDD* jobs, int njobs, int k0, int nb, int max_n,
+                         int32_t* status);
+void launch_dd_inv_swap(hipStream_t st, const InvJobDD* jobs, int njobs, int k0, int nb, int max_n);
+void launch_dd_inv_unscramble(hipStream_t st, const InvJobDD* jobs, int njobs, int max_n);
+int dd_inv_nb(int max_n);
+
 // debug / unit-test helpers
 void launch_mfma_probe(hipStream_t st, double* out);
 

@@ -16,6 +16,7 @@
 #include <string>
 #include <vector>
 
+#include "dd.h"
 #include "hsc_internal.h"
 #include "kern.h"
 #include "../../include/hsc_kernels.h"
@@ -53,7 +54,8 @@ struct Blob {
   void reloc(size_t field) { relocs.push_back(field); }
 };
 
-enum StepKind { S_ASSEMBLE, S_INV_PANEL, S_INV_SWAP, S_INV_UNSCR, S_GEMM, S_GATHER, S_ASSEMBLE_N, S_DIAG, S_GUARD };
+enum StepKind { S_ASSEMBLE, S_INV_PANEL, S_INV_SWAP, S_INV_UNSCR, S_GEMM, S_GATHER, S_ASSEMBLE_N, S_DIAG, S_GUARD,
+                S_DD_ASSEMBLE, S_DD_INV_PANEL, S_DD_INV_SWAP, S_DD_INV_UNSCR, S_DD_GEMM };
 
 struct Step {
   StepKind kind;
@@ -85,6 +87,7 @@ struct Plan {
   uint64_t uid = 0;
   int B = 0;
   uint32_t want = 0;
+  int prec = 0;
   int64_t n = 0;
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -114,7 +117,7 @@ struct hsc_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
   std::vector<std::pair<int, double>> ev_meta;   // (kind, flops) per recorded launch
   size_t ev_used = 0;
-  double prof[16][3] = {};                        // kind -> launches, ms, flops
+  double prof[16][3] = {};                        // kind -> launches, ms, flops (16 >= number of kinds)
 };
 
 namespace hsc {
@@ -129,6 +132,7 @@ struct Builder {
   int B;
   uint32_t want;
   bool gl;        // any lesser output -> full ancestor rows on contact paths
+  bool ddf = false;   // double-double fold
   size_t ws = 0;  // workspace bytes
   Blob blob;
   std::vector<Step> steps;
@@ -140,6 +144,7 @@ struct Builder {
   // per cluster x slot workspace offsets
   struct CS {
     size_t F, Inv, Psi, GX, GFF, GT, GAF, SD, piv, T, R;
+    size_t Fd, Invd, Psid, Td, Rd;   // double-double fold
     size_t NF[2], NFc[2], M[2], PX[2], PFF[2], PT[2];
   };
   std::vector<CS> cs;   // [cluster * B + slot]
@@ -195,11 +200,20 @@ struct Builder {
       const int nb = inv_nb((int)n);
       for (int e = 0; e < B; ++e) {
         CS& s = cs[(size_t)i * B + e];
-        s.F = wsa((n + f) * (n + f) * 16);
         s.Inv = wsa(n * n * 16);
         s.piv = wsa(n * 4);
-        s.T = wsa(n * nb * 16);
-        s.R = wsa(nb * n * 16);
+        if (ddf) {
+          const size_t nbd = dd_inv_nb((int)n);
+          s.Fd = wsa((n + f) * (n + f) * 32);
+          s.Invd = wsa(n * n * 32);
+          s.Td = wsa(n * nbd * 32);
+          s.Rd = wsa(nbd * n * 32);
+          if (!root(i)) s.Psid = wsa(n * f * 32);
+        } else {
+          s.F = wsa((n + f) * (n + f) * 16);
+          s.T = wsa(n * nb * 16);
+          s.R = wsa(nb * n * 16);
+        }
         if (!root(i)) s.Psi = wsa(n * f * 16);
         if (root(i)) s.GX = s.Inv;
         else if (!leaf(i)) s.GX = wsa((n + f) * gcols(i) * 16);
@@ -415,7 +429,140 @@ struct Builder {
   }
 
   // ---- phases ----
+  zdd* Z(size_t off) const { return reinterpret_cast<zdd*>(wsbase + off); }
+
+  struct GPD { const zdd *A, *B, *C; zdd* D; double2* D64; int M, N, K, lda, ldb, ldc, ldd, ldd64; };
+  void dd_gemm(int opA, const std::vector<GPD>& ps, int negate, int beta) {
+    std::vector<GemmProbDD> probs;
+    std::vector<int32_t> tmap;
+    const int tt = dd_gemm_tile();
+    double fl = 0;
+    for (const GPD& g : ps) {
+      if (g.M <= 0 || g.N <= 0) continue;
+      GemmProbDD p{};
+      p.A = g.A; p.B = g.B; p.C = g.C; p.D = g.D; p.D64 = g.D64;
+      p.M = g.M; p.N = g.N; p.K = g.K;
+      p.lda = g.lda; p.ldb = g.ldb; p.ldc = g.ldc; p.ldd = g.ldd; p.ldd64 = g.ldd64;
+      p.tiles_n = (g.N + tt - 1) / tt;
+      p.tile_off = (int32_t)tmap.size();
+      const int tiles = ((g.M + tt - 1) / tt) * p.tiles_n;
+      for (int k = 0; k < tiles; ++k) tmap.push_back((int32_t)probs.size());
+      probs.push_back(p);
+      fl += 8.0 * g.M * g.N * g.K;
+    }
+    if (probs.empty()) return;
+    Step s;
+    s.kind = S_DD_GEMM;
+    s.jobs = blob.push(probs);
+    s.map = blob.push(tmap);
+    s.count = (int)tmap.size();
+    s.i0 = opA;
+    s.i1 = negate;
+    s.beta = beta;
+    s.flops = fl;
+    steps.push_back(s);
+  }
+
+  void fold_dd(const std::vector<std::vector<int>>& L) {
+    for (int d = (int)L.size() - 1; d >= 0; --d) {
+      std::vector<RJ> jobs;
+      for (int i : L[d])
+        for (int e = 0; e < B; ++e) {
+          const Cluster& c = t->cl[i];
+          const CS& s = cs[(size_t)i * B + e];
+          RJ q{};
+          q.j.rows = q.j.cols = c.n + c.f();
+          q.j.e = e;
+          q.j.dst = reinterpret_cast<double2*>(Z(s.Fd));
+          q.j.ldd = c.n + c.f();
+          for (int k : c.children) {
+            const Cluster& kc = t->cl[k];
+            const CS& ks = cs[(size_t)k * B + e];
+            const int ldk = kc.n + kc.f();
+            ChildRef cr{};
+            cr.U = reinterpret_cast<const double2*>(Z(ks.Fd) + (size_t)kc.n * ldk + kc.n);
+            cr.ldU = ldk;
+            q.kids.push_back(cr);
+            q.kid_invrel.push_back(c_invrel[k]);
+          }
+          q.j.aux0 = (int)c.children.size();
+          q.j.p1 = reinterpret_cast<const void*>(c_fs[i]);
+          q.p1_blob = true;
+          q.j.aux1 = c.n; q.j.aux2 = c.n_left; q.j.aux3 = c.n_right;
+          jobs.push_back(q);
+        }
+      rowstep(S_DD_ASSEMBLE, jobs);
+      int maxn = 0;
+      for (int i : L[d]) maxn = std::max(maxn, n_of(i));
+      const int nb = dd_inv_nb(maxn);
+      std::vector<InvJobDD> ij;
+      for (int i : L[d])
+        for (int e = 0; e < B; ++e) {
+          const CS& s = cs[(size_t)i * B + e];
+          InvJobDD j{};
+          j.X = Z(s.Fd); j.ld = n_of(i) + f_of(i);
+          j.Y = Z(s.Invd); j.ldy = n_of(i);
+          j.Y64 = W(s.Inv); j.ldy64 = n_of(i);
+          j.n = n_of(i); j.e = e;
+          j.piv = reinterpret_cast<int32_t*>(wsbase + s.piv);
+          j.T = Z(s.Td); j.R = Z(s.Rd);
+          ij.push_back(j);
+        }
+      const size_t ijo = blob.push(ij);
+      for (int k0 = 0; k0 < maxn; k0 += nb) {
+        Step p; p.kind = S_DD_INV_PANEL; p.jobs = ijo; p.njobs = (int)ij.size(); p.i0 = k0; p.i1 = nb; p.i2 = maxn;
+        steps.push_back(p);
+        Step w = p; w.kind = S_DD_INV_SWAP;
+        steps.push_back(w);
+        std::vector<GPD> ps;
+        for (const InvJobDD& j : ij) {
+          if (k0 >= j.n) continue;
+          const int kb = std::min(nb, j.n - k0);
+          ps.push_back({j.T, j.R, j.X, j.X, nullptr, j.n, j.n, kb, kb, j.n, j.ld, j.ld, 0});
+        }
+        dd_gemm(0, ps, 0, 1);
+      }
+      Step u; u.kind = S_DD_INV_UNSCR; u.jobs = ijo; u.njobs = (int)ij.size(); u.i2 = maxn;
+      steps.push_back(u);
+      std::vector<GPD> pp, pu;
+      for (int i : L[d]) {
+        if (root(i)) continue;
+        const int n = n_of(i), f = f_of(i), ld = n + f;
+        for (int e = 0; e < B; ++e) {
+          const CS& s = cs[(size_t)i * B + e];
+          pp.push_back({Z(s.Invd), Z(s.Fd) + n, nullptr, Z(s.Psid), W(s.Psi), n, f, n, n, ld, 0, f, f});
+          pu.push_back({Z(s.Fd) + n, Z(s.Psid), Z(s.Fd) + (size_t)n * ld + n, Z(s.Fd) + (size_t)n * ld + n, nullptr,
+                        f, f, n, ld, f, ld, ld, 0});
+        }
+      }
+      dd_gemm(0, pp, 1, 0);
+      dd_gemm(1, pu, 0, 1);
+    }
+    guard_step();
+  }
+
+  void guard_step() {
+    // conditioning / growth indicators of every pivot block
+    std::vector<RowJob> gj;
+    for (int i = 0; i < (int)t->cl.size(); ++i)
+      for (int e = 0; e < B; ++e) {
+        const CS& s = cs[(size_t)i * B + e];
+        RowJob j{};
+        j.e = e;
+        j.src = W(s.Inv); j.lds = n_of(i);
+        j.p0 = root(i) ? nullptr : W(s.Psi);
+        j.aux0 = n_of(i); j.aux1 = f_of(i); j.aux2 = i;
+        gj.push_back(j);
+      }
+    Step g;
+    g.kind = S_GUARD;
+    g.jobs = blob.push(gj);
+    g.njobs = (int)gj.size();
+    steps.push_back(g);
+  }
+
   void fold(const std::vector<std::vector<int>>& L) {
+    if (ddf) { fold_dd(L); return; }
     for (int d = (int)L.size() - 1; d >= 0; --d) {
       // assemble
       std::vector<RJ> jobs;
@@ -492,23 +639,7 @@ struct Builder {
       gemm(OP_N, OP_N, pp, -1.0, 0.0, 0);
       gemm(OP_T, OP_N, pu, 1.0, 0.0, 1);
     }
-    // conditioning / growth indicators of every pivot block
-    std::vector<RowJob> gj;
-    for (int i = 0; i < (int)t->cl.size(); ++i)
-      for (int e = 0; e < B; ++e) {
-        const CS& s = cs[(size_t)i * B + e];
-        RowJob j{};
-        j.e = e;
-        j.src = W(s.Inv); j.lds = n_of(i);
-        j.p0 = root(i) ? nullptr : W(s.Psi);
-        j.aux0 = n_of(i); j.aux1 = f_of(i); j.aux2 = i;
-        gj.push_back(j);
-      }
-    Step g;
-    g.kind = S_GUARD;
-    g.jobs = blob.push(gj);
-    g.njobs = (int)gj.size();
-    steps.push_back(g);
+    guard_step();
   }
 
   void diag_step(const std::vector<int>& ids, int mode, int out, int chan, bool g_phase) {
@@ -789,6 +920,21 @@ int run_steps(hsc_ctx* ctx, Plan* pl, int e_base, int nvalid, void* gr, void* gl
       case S_GUARD:
         launch_guard(st, (const RowJob*)jobs, s.njobs, nclusters, e_base, nvalid, guard);
         break;
+      case S_DD_ASSEMBLE:
+        launch_dd_assemble(st, (const RowJob*)jobs, map, s.count, pl->es);
+        break;
+      case S_DD_INV_PANEL:
+        launch_dd_inv_panel(st, (const InvJobDD*)jobs, s.njobs, s.i0, s.i1, s.i2, pl->status);
+        break;
+      case S_DD_INV_SWAP:
+        launch_dd_inv_swap(st, (const InvJobDD*)jobs, s.njobs, s.i0, s.i1, s.i2);
+        break;
+      case S_DD_INV_UNSCR:
+        launch_dd_inv_unscramble(st, (const InvJobDD*)jobs, s.njobs, s.i2);
+        break;
+      case S_DD_GEMM:
+        launch_dd_gemm(st, s.i0, (const GemmProbDD*)jobs, map, s.count, s.i1, s.beta);
+        break;
       case S_DIAG: {
         void* out = nullptr;
         int kind = OUT_COMPLEX, eb = e_base;
@@ -810,9 +956,10 @@ int run_steps(hsc_ctx* ctx, Plan* pl, int e_base, int nvalid, void* gr, void* gl
   return HSC_OK;
 }
 
-int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, Plan** out) {
+int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, Plan** out) {
   for (size_t k = 0; k < ctx->plans.size(); ++k)
-    if (ctx->plans[k]->uid == t->uid && ctx->plans[k]->B == B && ctx->plans[k]->want == want) {
+    if (ctx->plans[k]->uid == t->uid && ctx->plans[k]->B == B && ctx->plans[k]->want == want &&
+        ctx->plans[k]->prec == prec) {
       // most recently used goes last
       std::unique_ptr<Plan> p = std::move(ctx->plans[k]);
       ctx->plans.erase(ctx->plans.begin() + k);
@@ -836,8 +983,9 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, Plan** out
       return HSC_E_ARG;
     }
   std::unique_ptr<Plan> pl(new Plan());
-  pl->uid = t->uid; pl->B = B; pl->want = want; pl->n = t->n;
+  pl->uid = t->uid; pl->B = B; pl->want = want; pl->n = t->n; pl->prec = prec;
   Builder b{t, B, want, (want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR)) != 0};
+  b.ddf = prec == 1;
   b.channels();
   b.layout();
   // per-plan small buffers at the end of the workspace
@@ -889,8 +1037,9 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, Plan** out
   return HSC_OK;
 }
 
-size_t plan_bytes_per_slot(const hsc_tree* t, uint32_t want) {
+size_t plan_bytes_per_slot(const hsc_tree* t, uint32_t want, int prec) {
   Builder b{t, 1, want, (want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR)) != 0};
+  b.ddf = prec == 1;
   b.channels();
   b.layout();
   return b.ws;
@@ -955,12 +1104,13 @@ static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
   if (B <= 0) {
     size_t freeb = 0, totalb = 0;
     HIPCHK(hipMemGetInfo(&freeb, &totalb));
-    const size_t per = std::max<size_t>(1, plan_bytes_per_slot(tree, want));
+    const size_t per = std::max<size_t>(1, plan_bytes_per_slot(tree, want, opts->precision));
     B = (int)std::max<size_t>(1, std::min<size_t>(64, (size_t)(0.45 * (double)freeb) / per));
   }
   B = std::min(B, n_e);
   Plan* pl = nullptr;
-  int st = build_plan(ctx, tree, B, want, &pl);
+  if (opts->precision != 0 && opts->precision != 1) { set_error("precision must be 0 or 1"); return HSC_E_ARG; }
+  int st = build_plan(ctx, tree, B, want, opts->precision, &pl);
   if (st != HSC_OK) return (hsc_status)st;
   for (int e0 = 0; e0 < n_e; e0 += B) {
     const int nv = std::min(B, n_e - e0);

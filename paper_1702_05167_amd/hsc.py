@@ -42,7 +42,7 @@ class TreeStats(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("eta", C.c_double), ("kT", C.c_double), ("mu_L", C.c_double), ("mu_R", C.c_double),
                 ("want", C.c_uint32), ("batch", C.c_int32), ("guard_tau", C.c_double),
-                ("guard_rounds", C.c_int32)]
+                ("guard_rounds", C.c_int32), ("precision", C.c_int32)]
 
 
 _lib = None
@@ -116,7 +116,8 @@ class Context:
         check(lib().hsc_sync(self.h))
 
     PROFILE_KINDS = ("assemble", "inv_panel", "inv_swap", "inv_unscramble", "gemm", "gather",
-                     "assemble_n", "diag", "guard")
+                     "assemble_n", "diag", "guard", "dd_assemble", "dd_inv_panel", "dd_inv_swap",
+                     "dd_inv_unscramble", "dd_gemm")
 
     def profile(self, enable: bool):
         check(lib().hsc_ctx_profile(self.h, 1 if enable else 0))
@@ -212,7 +213,7 @@ class Tree:
 
 def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1,
           want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, out=None, sync=True, guard=False,
-          guard_tau=0.0, guard_rounds=6):
+          guard_tau=0.0, guard_rounds=6, precision=1):
     """Solve all energies; returns a dict of device tensors (gr, gl, trans, spectral, status)."""
     import torch
     dev = ctx.torch_device
@@ -231,7 +232,7 @@ def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R
         o["status"] = torch.empty(ne, dtype=torch.int32, device=dev)
     if guard and "guard" not in o:
         o["guard"] = torch.zeros((ne, tree.stats()["n_clusters"], 2), dtype=torch.float64, device=dev)
-    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, guard_tau, guard_rounds)
+    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, guard_tau, guard_rounds, precision)
     check(lib().hsc_solve(ctx.h, tree.h, ne, _dptr(e), C.byref(opts), _dptr(o.get("gr")), _dptr(o.get("gl")),
                           _dptr(o.get("trans")), _dptr(o.get("spectral")), _dptr(o.get("status")),
                           _dptr(o.get("guard"))))
