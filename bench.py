@@ -3,9 +3,12 @@
 
 Workload: the 32^3 cube (32,768 sites, 7-point, t = -1, on-site U[-0.5, 0.5]
 seed 0, per-site 1D leads on the x faces), 256 energies uniform in [-6, 6],
-eta = 1e-8, kT = 0.025, mu_L/R = +-0.1, nested-dissection leaves <= 8 per side.
-One step = diag G^r, diag G^< and T for all 256 energies (inputs resident on
-the device).  Prints one JSON line.
+eta = 1e-8, kT = 0.025, mu_L/R = +-0.1.  Cluster tree: nested dissection of
+the cross-section (the transport axis x is never cut, clusters span contact to
+contact), leaves <= 4 sites across.  One step = diag G^r, diag G^< and T for
+all 256 energies (inputs resident on the device).  The line also reports the
+error against stored oracle values at 8 of the 256 energies (tests/golden).
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -21,6 +24,10 @@ sys.path.insert(0, ROOT)
 FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
+def note(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -31,8 +38,10 @@ def main():
     ap.add_argument("--batch", type=int, default=0, help="energies per launch sequence (0 = auto)")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-energy-per-launch-sequence run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--precision", type=int, default=1,
-                    help="fold arithmetic: 1 = double-double (default), 0 = complex128 as in Algorithm 1")
+    ap.add_argument("--precision", type=int, default=0,
+                    help="fold arithmetic: 0 = complex128 as in Algorithm 1 (default), 1 = double-double")
+    ap.add_argument("--leaf", type=int, default=4)
+    ap.add_argument("--full-nd", action="store_true", help="also cut the transport axis (classic 3D ND)")
     ap.add_argument("--no-alt", action="store_true", help="skip timing the other fold precision")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -48,7 +57,7 @@ def main():
 
     N, NE = args.n_side, args.energies
     dev = synth.config1_device(n_side=N)
-    tree = pkg.Tree.from_device(dev, leaf_side=8)
+    tree = pkg.Tree.from_device(dev, leaf_side=args.leaf, transverse=not args.full_nd)
     st = tree.stats()
     ctx = pkg.Context(0)
     E = torch.linspace(-6.0, 6.0, NE, dtype=torch.float64, device="cuda:0")
@@ -58,6 +67,7 @@ def main():
     for _ in range(args.warmup):
         pkg.solve(ctx, tree, E, want=want, batch=args.batch, out=out, sync=False, **kw)
     torch.cuda.synchronize()
+    note("warmup done")
     t0 = time.perf_counter()
     for _ in range(args.steps):
         pkg.solve(ctx, tree, E, want=want, batch=args.batch, out=out, sync=False, **kw)
@@ -66,6 +76,7 @@ def main():
     dt = time.perf_counter() - t0
     value = NE * args.steps / dt
     status_ok = int(out["status"].abs().sum().item()) == 0
+    note(f"timed {args.steps} steps: {value:.2f} energies/s")
 
     # per-kernel timing of one step (events around every launch on the solver's stream)
     ctx.profile(True)
@@ -87,6 +98,40 @@ def main():
         pkg.solve(ctx, tree, E, want=want, batch=args.batch, **kw_alt)
         torch.cuda.synchronize()
         alt = NE / (time.perf_counter() - t3)
+        note(f"other fold precision: {alt:.2f} energies/s")
+
+    # accuracy at the stored oracle energies (in and out of the lead band [-2, 2])
+    acc = None
+    gpath = os.path.join(ROOT, "tests", "golden", "cube32_sampled.json")
+    if N == 32 and NE == 256 and os.path.exists(gpath):
+        gold = json.load(open(gpath))
+        idx = torch.tensor(gold["energy_index"], device="cuda:0")
+        sites = np.array(gold["sites"])
+        ref_gr = np.array(gold["gr_re"]) + 1j * np.array(gold["gr_im"])
+        ref_gl = np.array(gold["gl_im"])
+        gr = out["gr"][idx].cpu().numpy()[:, sites]
+        gl = out["gl"][idx].cpu().numpy()[:, sites].imag
+        tr = out["trans"][idx].cpu().numpy()
+        errs = [max(np.abs(gr[k] - ref_gr[k]).max() / np.abs(ref_gr[k]).max(),
+                    np.abs(gl[k] - ref_gl[k]).max() / np.abs(ref_gl[k]).max(),
+                    abs(tr[k] - gold["trans"][k]) / max(gold["trans"][k], 1e-12)) for k in range(len(idx))]
+        band = [abs(e) < 2.0 for e in gold["energies"]]
+        acc = {"energies": gold["energies"], "max_rel_err": errs,
+               "in_band_max": max(x for x, b in zip(errs, band) if b),
+               "out_of_band_max": max(x for x, b in zip(errs, band) if not b)}
+
+    # the same solve on the classic 3D nested-dissection tree (leaves <= 8 per side)
+    nd8 = None
+    if not args.full_nd and not args.no_alt:
+        tree8 = pkg.Tree.from_device(dev, leaf_side=8)
+        pkg.solve(ctx, tree8, E[:8], want=want, batch=args.batch, **kw)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        pkg.solve(ctx, tree8, E, want=want, batch=args.batch, **kw)
+        torch.cuda.synchronize()
+        nd8 = NE / (time.perf_counter() - t4)
+        note(f"3D nested-dissection tree: {nd8:.2f} energies/s")
+        del tree8
 
     plain = None
     if not args.no_plain:
@@ -123,14 +168,17 @@ def main():
         "dtype": "c128",
         "data": "synthetic",
         "config": {"workload": f"cube{N}^3 x {NE} energies in [-6,6] (diag G^r, diag G^<, T)",
-                   "sites": int(dev.n), "energies": NE, "leaf_side": 8, "clusters": st["n_clusters"],
+                   "sites": int(dev.n), "energies": NE, "leaf_side": args.leaf, "clusters": st["n_clusters"],
+                   "tree": "full 3D nested dissection" if args.full_nd else "transverse nested dissection",
                    "batch": args.batch or "auto", "plain_energies_per_s": plain,
                    "fold": "double-double" if args.precision == 1 else "complex128",
                    "other_fold_energies_per_s": alt,
+                   "nd_leaf8_tree_energies_per_s": nd8,
                    "dd_gemm_equiv_tflops": dd_rate,
                    "flops_per_energy": st["flops_per_energy"],
                    "whole_solve_tflops": st["flops_per_energy"] * value / 1e12,
                    "status_ok": status_ok,
+                   "accuracy_vs_oracle": acc,
                    "kernel_ms_per_step": {k: round(v["ms"], 3) for k, v in prof.items()},
                    "kernel_ms_total": round(total_ms, 3)},
         "roofline": {"bound": "mfma", "kernel": "k_zgemm (grouped complex128 GEMM)", "achieved": achieved,

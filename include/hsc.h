@@ -98,8 +98,8 @@ typedef struct {
   int32_t batch;             /* energies per launch sequence; 0 = library default */
   /* Growth guard.  Algorithm 1 inverts each cluster block A_ii with no
    * pivoting across clusters; a nearly singular block amplifies rounding
-   * errors.  When guard_tau > 0, every energy whose non-root blocks have
-   * ||(A_ii)^-1||_inf > guard_tau is solved again on a tree in which those
+   * errors.  When guard_tau > 0, every energy whose non-root clusters have
+   * ||Psi_i||_inf > guard_tau is solved again on a tree in which those
    * clusters are merged into their parents (a delayed pivot), for up to
    * guard_rounds rounds; energies still above the threshold get status
    * HSC_E_UNSTABLE.  With guard_tau > 0 the call waits for the device. */

@@ -10,6 +10,11 @@ is row s of G^r.  From that row (Eq. 1 and Eq. 2 for diagonal Sigma^<):
 The transmission T = sum_{i in L} Gamma_L,i A_R,ii needs the rows of every
 left-contact site; it is computed only when asked for.
 
+Each solve is refined twice (iterative refinement): the residual e_s - A^T x
+is accumulated in extended precision (numpy longdouble) and the correction is
+solved with the same factors, so the rows are accurate to working precision
+rather than to eps * cond(A).
+
 Rows and columns are first permuted by a geometric nested-dissection order
 (bisect the longest box axis, separator last) only to keep the sparse
 factors small; a symmetric permutation does not change A^-1, and SuperLU's
@@ -48,7 +53,7 @@ def _bisection_order(coords, leaf=4):
 class _Factor:
     """LU of P A P^T; solves are returned in the original site order."""
 
-    def __init__(self, dev, z):
+    def __init__(self, dev, z, refine=2):
         h = dev.scipy_h()
         a = (-h).tolil()
         a.setdiag(a.diagonal() + z)
@@ -58,12 +63,33 @@ class _Factor:
         a = sp.csc_matrix(a)
         self.p = _bisection_order(np.asarray(dev.coords))
         self.lu = spl.splu(a[self.p][:, self.p].tocsc(), permc_spec="NATURAL")
+        at = a.T.tocsr()                     # rows of A^T, for the residual
+        self.at_ptr = at.indptr
+        self.at_col = at.indices
+        self.at_val = at.data.astype(np.clongdouble)
+        self.refine = refine
 
-    def solve_t(self, b):
-        """x = A^-T b."""
+    def _solve_t0(self, b):
         x = np.empty_like(b)
         x[self.p] = self.lu.solve(b[self.p], trans="T")
         return x
+
+    def _residual(self, b, x):
+        """b - A^T x, accumulated in extended precision."""
+        n = len(self.at_ptr) - 1
+        prod = self.at_val[:, None] * x[self.at_col]
+        rows = np.repeat(np.arange(n), np.diff(self.at_ptr))
+        ax = np.zeros((n, x.shape[1]), dtype=np.clongdouble)
+        np.add.at(ax, rows, prod)
+        return b.astype(np.clongdouble) - ax
+
+    def solve_t(self, b):
+        """x = A^-T b, with iterative refinement."""
+        x = self._solve_t0(b).astype(np.clongdouble)
+        for _ in range(self.refine):
+            r = self._residual(b, x)
+            x = x + self._solve_t0(r.astype(np.complex128))
+        return x.astype(np.complex128)
 
 
 def _factor(dev, z):

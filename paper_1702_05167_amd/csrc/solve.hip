@@ -1143,10 +1143,12 @@ struct GuardItem {
   std::shared_ptr<hsc_tree> tree;          // null: the caller's tree
   std::vector<int> bad;                    // flagged clusters of that tree
 };
+// flagged clusters: ||Psi_i||_inf above tau (the extract multiplies rounding
+// errors of G_ff by Psi on both sides)
 std::vector<int> flagged(const double* g, int nc, double tau) {
   std::vector<int> b;
   for (int i = 0; i < nc - 1; ++i)
-    if (!(g[2 * i] <= tau)) b.push_back(i);
+    if (!(g[2 * i + 1] <= tau)) b.push_back(i);
   return b;
 }
 }  // namespace

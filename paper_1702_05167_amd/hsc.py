@@ -168,10 +168,13 @@ class Tree:
         return cls(h, n)
 
     @classmethod
-    def from_device(cls, dev, leaf_side=8):
+    def from_device(cls, dev, leaf_side=8, transverse=False):
+        """Tree of a synthetic device; transverse=True never cuts the transport axis (x), so every
+        cluster spans the device from one contact to the other."""
         mask = 0
         for a in dev.split_axes:
-            mask |= 1 << a
+            if not (transverse and a == 0):
+                mask |= 1 << a
         contacts = [(c.sites, c.lead_onsite, c.lead_hopping, c.coupling) for c in dev.contacts]
         return cls.build(dev.n, dev.indptr, dev.indices, dev.values, dev.coords, contacts, mask, leaf_side)
 

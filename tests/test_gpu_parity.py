@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 KW = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1)
 TOL = 1e-10
 ALL = pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS | pkg.HSC_SPECTRAL_LR
-GUARD = dict(guard_tau=16.0, guard_rounds=8)
+GUARD = dict(guard_tau=100.0, guard_rounds=8)
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
@@ -32,9 +32,9 @@ def t_rel(a, b):
     return abs(a - b) / max(b, 1e-12)
 
 
-def gpu(ctx, dev, energies, leaf, want=ALL, mask=None, **kw):
+def gpu(ctx, dev, energies, leaf, want=ALL, mask=None, transverse=False, **kw):
     if mask is None:
-        tree = pkg.Tree.from_device(dev, leaf_side=leaf)
+        tree = pkg.Tree.from_device(dev, leaf_side=leaf, transverse=transverse)
     else:
         c = [(x.sites, x.lead_onsite, x.lead_hopping, x.coupling) for x in dev.contacts]
         tree = pkg.Tree.build(dev.n, dev.indptr, dev.indices, dev.values, dev.coords, c, mask, leaf)
@@ -145,7 +145,7 @@ def test_clean_cube32_modes_in_band(ctx):
     N = 32
     dev = synth.cuboid(N, N, N)
     E = np.array([-1.5, 0.25, 1.1])
-    g = gpu(ctx, dev, E, 8, **GUARD)
+    g = gpu(ctx, dev, E, 8, precision=1, **GUARD)
     for e, en in enumerate(E):
         gr, al, ar, T = _modes(N, N, N, en)
         errs = (rel(g["gr"][e], gr), rel(g["a_l"][e], al), rel(g["a_r"][e], ar), t_rel(g["trans"][e], T))
@@ -165,23 +165,46 @@ def test_cube16_against_sparse_lu(ctx):
     print("16^3 guarded worst", check_all(gs, ref, E))
 
 
-@pytest.mark.xfail(reason="32^3: unpivoted cluster elimination in FP64 loses up to ~1e-8 at some energies "
-                          "even with the merge guard; needs the extended-precision fold", strict=False)
-def test_cube32_golden_guarded(ctx):
+def _golden32():
     gold = json.load(open(os.path.join(HERE, "golden", "cube32_sampled.json")))
-    dev = synth.config1_device()
-    E = np.array(gold["energies"])
-    sites = np.array(gold["sites"])
     ref = {"gr": np.array(gold["gr_re"]) + 1j * np.array(gold["gr_im"]),
            "gl": np.array(gold["gl_re"]) + 1j * np.array(gold["gl_im"]),
            "a_l": np.array(gold["a_l"]), "a_r": np.array(gold["a_r"]), "trans": np.array(gold["trans"])}
-    g = gpu(ctx, dev, E, 8, **GUARD)
+    return np.array(gold["energies"]), np.array(gold["sites"]), ref
+
+
+def _golden32_check(ctx, pick, **kw):
+    E, sites, ref = _golden32()
+    ref = {k: v[pick] for k, v in ref.items()}
+    E = E[pick]
+    g = gpu(ctx, synth.config1_device(), E, **kw)
     gs = {k: g[k][:, sites] for k in ("gr", "gl", "a_l", "a_r")}
     gs["trans"], gs["status"] = g["trans"], g["status"]
     for e in range(len(E)):
         print("32^3 golden E", E[e], [rel(gs[k][e], ref[k][e]) for k in ("gr", "gl", "a_l", "a_r")],
-              t_rel(gs["trans"][e], ref["trans"][e]))
-    check_all(gs, ref, E)
+              t_rel(gs["trans"][e], ref["trans"][e]), "status", g["status"][e])
+    return check_all(gs, ref, E)
+
+
+IN_BAND = [3, 4, 5]        # golden energies inside the lead band [-2, 2]
+OUT_OF_BAND = [0, 1, 2, 6, 7]
+
+
+def test_cube32_golden_in_band_transverse_tree(ctx):
+    # the 32^3 disordered cube at full size against the sparse-LU oracle; clusters of the
+    # transverse tree span contact to contact, so every pivot block is broadened by both leads
+    print("worst", _golden32_check(ctx, IN_BAND, leaf=4, transverse=True, precision=0))
+
+
+def test_cube32_golden_in_band_nd_tree_guarded(ctx):
+    print("worst", _golden32_check(ctx, IN_BAND, leaf=8, precision=1, **GUARD))
+
+
+@pytest.mark.xfail(reason="out of the lead band the cluster blocks are nearly real and may be nearly singular; "
+                          "the unpivoted elimination loses accuracy in proportion to |Psi|^2 (about 1e-10 to "
+                          "1e-8 here, with the guard and the double-double fold)", strict=False)
+def test_cube32_golden_out_of_band_guarded(ctx):
+    print("worst", _golden32_check(ctx, OUT_OF_BAND, leaf=8, precision=1, **GUARD))
 
 
 def test_full_size_invariants(ctx):
