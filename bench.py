@@ -43,6 +43,8 @@ def main():
     ap.add_argument("--leaf", type=int, default=4)
     ap.add_argument("--full-nd", action="store_true", help="also cut the transport axis (classic 3D ND)")
     ap.add_argument("--no-alt", action="store_true", help="skip timing the other fold precision")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="run one elementwise device copy of MIB MiB first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); energies shard across GPUs "
@@ -54,6 +56,14 @@ def main():
     import torch
     import synth
     import paper_1702_05167_amd as pkg
+
+    if args.calibrate_copy > 0:
+        src = torch.ones(args.calibrate_copy * 131072, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+        note(f"copy calibration: {args.calibrate_copy} MiB read + written")
 
     N, NE = args.n_side, args.energies
     dev = synth.config1_device(n_side=N)
@@ -183,7 +193,8 @@ def main():
                    "kernel_ms_total": round(total_ms, 3)},
         "roofline": {"bound": "mfma", "kernel": "k_zgemm (grouped complex128 GEMM)", "achieved": achieved,
                      "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
-                     "traffic": None, "launches": int(g["launches"])},
+                     "traffic": None, "launches": int(g["launches"]),
+                     "avg_launch_ms": g["ms"] / g["launches"] if g["launches"] else None},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

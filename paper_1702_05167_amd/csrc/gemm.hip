@@ -230,16 +230,14 @@ __global__ void k_mfma_probe(double* out) {
 
 }  // namespace
 
-int gemm_tile_m(int kind) { return kind == 1 ? 128 : 64; }
-int gemm_tile_n(int kind) { return kind == 1 ? 128 : 64; }
+int gemm_tile_m(int) { return 64; }
+int gemm_tile_n(int) { return 64; }
 
 void launch_gemm(hipStream_t st, int opA, int opB, const GemmProb* probs, const int32_t* tile_prob,
                  int total_tiles, double alpha_re, double alpha_im, int beta, int tile_kind) {
   if (total_tiles <= 0) return;
-  if (tile_kind == 1)
-    dispatch<128, 128, 8>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta);
-  else
-    dispatch<64, 64, 16>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta);
+  (void)tile_kind;   // one tile shape: 64 x 64 x 16
+  dispatch<64, 64, 16>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta);
 }
 
 void launch_mfma_probe(hipStream_t st, double* out) {

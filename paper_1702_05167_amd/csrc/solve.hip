@@ -874,13 +874,47 @@ struct Builder {
   }
 };
 
+// Launch timing keeps at most kEventPairs event pairs alive: a full pool is drained (wait for
+// the last recorded launch, add the durations to the per-kind totals) and reused.
+constexpr size_t kEventPairs = 512;
+
+hsc_status fold_events(hsc_ctx* ctx) {
+  if (ctx->ev_used == 0) return HSC_OK;
+  HIPCHK(hipEventSynchronize(ctx->ev_pool[ctx->ev_used - 1].second));
+  for (size_t k = 0; k < ctx->ev_used; ++k) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->ev_pool[k].first, ctx->ev_pool[k].second));
+    const int kind = ctx->ev_meta[k].first;
+    ctx->prof[kind][0] += 1;
+    ctx->prof[kind][1] += ms;
+    ctx->prof[kind][2] += ctx->ev_meta[k].second;
+  }
+  ctx->ev_used = 0;
+  return HSC_OK;
+}
+
+bool step_empty(const Step& s) {
+  switch (s.kind) {
+    case S_INV_PANEL: case S_INV_SWAP: case S_INV_UNSCR: case S_GUARD:
+    case S_DD_INV_PANEL: case S_DD_INV_SWAP: case S_DD_INV_UNSCR:
+      return s.njobs <= 0;
+    default:
+      return s.count <= 0;
+  }
+}
+
 int run_steps(hsc_ctx* ctx, Plan* pl, int e_base, int nvalid, void* gr, void* glo, double* spectral,
               double* guard, int nclusters) {
   hipStream_t st = ctx->stream;
   const int64_t n = pl->n;
   for (const Step& s : pl->steps) {
+    if (step_empty(s)) continue;
     hipEvent_t ev1 = nullptr;
     if (ctx->profile) {
+      if (ctx->ev_used == kEventPairs) {
+        const hsc_status r = fold_events(ctx);
+        if (r != HSC_OK) return r;
+      }
       if (ctx->ev_used == ctx->ev_pool.size()) {
         hipEvent_t a, b;
         HIPCHK(hipEventCreate(&a));
@@ -1312,17 +1346,7 @@ hsc_status hsc_sync(hsc_ctx* ctx) {
   if (ctx->stream) { HIPCHK(hipStreamSynchronize(ctx->stream)); }
   else { HIPCHK(hipDeviceSynchronize()); }
   HIPCHK(hipGetLastError());
-  // fold recorded launch timings into the per-kind totals
-  for (size_t k = 0; k < ctx->ev_used; ++k) {
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, ctx->ev_pool[k].first, ctx->ev_pool[k].second));
-    const int kind = ctx->ev_meta[k].first;
-    ctx->prof[kind][0] += 1;
-    ctx->prof[kind][1] += ms;
-    ctx->prof[kind][2] += ctx->ev_meta[k].second;
-  }
-  ctx->ev_used = 0;
-  return HSC_OK;
+  return fold_events(ctx);   // recorded launch timings into the per-kind totals
 }
 
 hsc_status hsc_ctx_profile(hsc_ctx* ctx, int32_t enable) {
