@@ -43,6 +43,8 @@ def main():
     ap.add_argument("--leaf", type=int, default=4)
     ap.add_argument("--full-nd", action="store_true", help="also cut the transport axis (classic 3D ND)")
     ap.add_argument("--no-alt", action="store_true", help="skip timing the other fold precision")
+    ap.add_argument("--learned-grid", action="store_true",
+                    help="measure the learned energy grid instead (surrogate training + charge on 3 devices)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run one elementwise device copy of MIB MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -56,6 +58,10 @@ def main():
     import torch
     import synth
     import paper_1702_05167_amd as pkg
+
+    if args.learned_grid:
+        learned_grid_study(pkg, synth, np)
+        return
 
     if args.calibrate_copy > 0:
         src = torch.ones(args.calibrate_copy * 131072, dtype=torch.float64, device="cuda:0")
@@ -197,6 +203,52 @@ def main():
                      "avg_launch_ms": g["ms"] / g["launches"] if g["launches"] else None},
         "cpu_baseline": cpu,
     }
+    print(json.dumps(line), flush=True)
+
+
+def learned_grid_study(pkg, synth, np):
+    """Surrogate network trained on solver outputs of 40 disordered cubes (N in 24..32,
+    sigma ~ U[0, 0.5], 50 energies each in [-6, 6]); charge of three N = 32, sigma = 0.3 cubes
+    on 512 of 4096 candidate energies, against the dense grid (every candidate in the lead band)."""
+    from paper_1702_05167_amd import learned_grid as lg
+    ctx = pkg.Context(0)
+    rng = np.random.default_rng(0)
+    t0 = time.perf_counter()
+    items = []
+    for d in range(40):
+        N = int(rng.integers(24, 33))
+        sig = float(rng.uniform(0.0, 0.5))
+        dev = synth.learned_grid_device(N, sig, 1000 + d)
+        items.append(dict(tree=pkg.Tree.from_device(dev, leaf_side=4, transverse=True), n_sites=dev.n, sigma=sig,
+                          nx=N, ny=N))
+    X, Y = lg.dataset(ctx, items, 50, seed=1)
+    del items
+    t_data = time.perf_counter() - t0
+    note(f"training set {X.shape[0]} samples in {t_data:.1f} s")
+    sur = lg.Surrogate(ctx, seed=0)
+    t1 = time.perf_counter()
+    hist = sur.fit(X, Y, epochs=300, batch=200)
+    t_fit = time.perf_counter() - t1
+    note(f"fit {len(hist)} Adam steps in {t_fit:.2f} s, loss {hist[0]:.3f} -> {hist[-1]:.4f}")
+    cand = np.linspace(-6.0, 6.0, 4096)
+    runs = []
+    for seed in (100, 101, 102):
+        dev = synth.learned_grid_device(32, 0.3, seed)
+        it = dict(tree=pkg.Tree.from_device(dev, leaf_side=4, transverse=True), n_sites=dev.n, sigma=0.3, nx=32, ny=32)
+        r = lg.study(ctx, sur, it, cand, 512, (-2.0, 2.0), budget=64)
+        r["seed"] = seed
+        runs.append(r)
+        note(f"device seed {seed}: guided {r['guided']['rel_err']:.2e} ({r['guided']['solves']} solves), "
+             f"uniform {r['uniform']['rel_err']:.2e} ({r['uniform']['solves']}), dense {r['dense']['solves']} solves")
+    worst = max(r["guided"]["rel_err"] for r in runs)
+    line = {"metric": "learned energy grid: charge error vs dense grid (32^3, sigma 0.3, 3 devices)",
+            "value": worst, "unit": "relative error", "higher_is_better": False, "n_gpus": 1, "dtype": "f32 net / c128 solve",
+            "data": "synthetic",
+            "config": {"workload": "MLP 4-256-256-2 trained on 2000 solver samples (40 cubes N 24..32); 512 of 4096 "
+                                   "candidates in [-6, 6]; charge over the open lead band (-2, 2)",
+                       "train_seconds": t_fit, "data_seconds": t_data, "loss_first": float(hist[0]),
+                       "loss_last": float(hist[-1]), "adam_steps": len(hist)},
+            "runs": runs}
     print(json.dumps(line), flush=True)
 
 

@@ -190,6 +190,18 @@ hsc_status hsc_solve_batch(hsc_ctx* ctx, int32_t n_trees, const hsc_tree* const*
 /* Wait for the context's stream; returns HSC_E_HIP on an asynchronous HIP error. */
 hsc_status hsc_sync(hsc_ctx* ctx);
 
+/* Per-energy sums over sites of solve outputs (Section 2: density of states from
+ * G^r, electron density from G^<, hbar = 1, no spin factor):
+ *   totals[e][0] = -(1/pi)  sum_i Im G^r_ii(E_e)              (DOS)
+ *   totals[e][1] =  (1/2pi) sum_i Im G^<_ii(E_e)              (electrons per unit energy)
+ *   totals[e][2] =  (1/2pi) sum_i (A_L + A_R)_ii(E_e)         (DOS injected by the contacts)
+ * diag_gr, diag_gl: device, complex128 [n_e][n]; spectral_lr: device, double
+ * [n_e][2][n]; all as written by hsc_solve.  Any of them may be NULL; its column of
+ * totals (device, double [n_e][3]) is then not written.
+ * Errors: HSC_E_ARG for n_e < 0, n < 0 or a NULL totals with n_e > 0. */
+hsc_status hsc_totals(hsc_ctx* ctx, int32_t n_e, int64_t n, const void* diag_gr, const void* diag_gl,
+                      const double* spectral_lr, double* totals);
+
 /* Launch timing.  While enabled, every kernel launch of a solve is bracketed by
  * HIP events on the context's stream; hsc_sync() folds the elapsed times into
  * per-kind totals.  Enabling (or disabling) resets the totals.  Kinds:

@@ -15,8 +15,10 @@ Modules:
                  mid sizes.
 * ``sampled`` -- sparse LU (partial pivoting) column solves for sampled sites,
                  usable at any size.
+* ``mlp``     -- float64 forward pass, chain-rule gradients and Adam of the
+                 surrogate network of the learned energy grid.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s CPU-baseline leg
 may import this package.  The GPU path never does: it shares no code with it.
 """
-from . import negf, dense, rgf, sampled  # noqa: F401
+from . import negf, dense, rgf, sampled, mlp  # noqa: F401

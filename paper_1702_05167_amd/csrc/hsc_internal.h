@@ -11,6 +11,10 @@ namespace hsc {
 
 void set_error(const std::string& msg);
 
+// the device index and HIP stream (hipStream_t, may be null) of a context
+int ctx_device(const hsc_ctx* ctx);
+void* ctx_stream(const hsc_ctx* ctx);
+
 struct ContactInfo {
   std::vector<int64_t> sites;
   double lead_onsite = 0, lead_hopping = -1, coupling = -1;

@@ -93,6 +93,8 @@ void launch_energy_setup(hipStream_t st, const double* energies, int nvalid, int
                          double kT, double mu_L, double mu_R, LeadParams lp, EnergyScalars* out,
                          int32_t* status);
 void launch_status_out(hipStream_t st, const int32_t* st_slots, int nvalid, int32_t* out);
+void launch_totals(hipStream_t st, int n_e, int64_t n, const double2* gr, const double2* gl, const double* spec,
+                   double* totals);
 
 // Frontal assembly: F = sum of children's update blocks (pull) + sparse A entries.
 void launch_assemble(hipStream_t st, const RowJob* jobs, const int32_t* row_job, int total_rows,

@@ -363,4 +363,44 @@ void launch_combine_gl(hipStream_t st, const double* spec, int nvalid, int e_bas
   hipLaunchKernelGGL(k_combine_gl, grid, dim3(256), 0, st, spec, nvalid, e_base, n, es, gl);
 }
 
+namespace {
+
+// totals[e][0] = -(1/pi) sum_i Im gr[e][i]; totals[e][1] = (1/2pi) sum_i Im gl[e][i];
+// totals[e][2] = (1/2pi) sum_i (A_L + A_R)[e][i] from spec ([e][2][n]);
+// one workgroup per energy, fixed-order reduction
+__global__ __launch_bounds__(256) void k_totals(int64_t n, const double2* __restrict__ gr,
+                                                const double2* __restrict__ gl, const double* __restrict__ spec,
+                                                double* __restrict__ totals) {
+  __shared__ double part[3][256];
+  const int e = blockIdx.x;
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    if (gr) a += gr[(int64_t)e * n + i].y;
+    if (gl) b += gl[(int64_t)e * n + i].y;
+    if (spec) c += spec[(int64_t)e * 2 * n + i] + spec[(int64_t)e * 2 * n + n + i];
+  }
+  part[0][threadIdx.x] = a;
+  part[1][threadIdx.x] = b;
+  part[2][threadIdx.x] = c;
+  __syncthreads();
+  for (int h = 128; h > 0; h /= 2) {
+    if ((int)threadIdx.x < h)
+      for (int q = 0; q < 3; ++q) part[q][threadIdx.x] += part[q][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double pi = 3.141592653589793;
+    if (gr) totals[3 * e] = -part[0][0] / pi;
+    if (gl) totals[3 * e + 1] = part[1][0] / (2.0 * pi);
+    if (spec) totals[3 * e + 2] = part[2][0] / (2.0 * pi);
+  }
+}
+
+}  // namespace
+
+void launch_totals(hipStream_t st, int n_e, int64_t n, const double2* gr, const double2* gl, const double* spec,
+                   double* totals) {
+  hipLaunchKernelGGL(k_totals, dim3(n_e), dim3(256), 0, st, n, gr, gl, spec, totals);
+}
+
 }  // namespace hsc

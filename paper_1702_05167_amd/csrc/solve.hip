@@ -122,6 +122,9 @@ struct hsc_ctx {
 
 namespace hsc {
 
+int ctx_device(const hsc_ctx* ctx) { return ctx->device; }
+void* ctx_stream(const hsc_ctx* ctx) { return reinterpret_cast<void*>(ctx->stream); }
+
 namespace {
 
 // ---------------------------------------------------------------------------------------------
@@ -1347,6 +1350,16 @@ hsc_status hsc_sync(hsc_ctx* ctx) {
   else { HIPCHK(hipDeviceSynchronize()); }
   HIPCHK(hipGetLastError());
   return fold_events(ctx);   // recorded launch timings into the per-kind totals
+}
+
+hsc_status hsc_totals(hsc_ctx* ctx, int32_t n_e, int64_t n, const void* diag_gr, const void* diag_gl,
+                      const double* spectral_lr, double* totals) {
+  if (!ctx || n_e < 0 || n < 0 || (n_e > 0 && !totals)) { set_error("bad arguments to hsc_totals"); return HSC_E_ARG; }
+  if (n_e == 0) return HSC_OK;
+  HIPCHK(hipSetDevice(ctx->device));
+  launch_totals(ctx->stream, n_e, n, (const double2*)diag_gr, (const double2*)diag_gl, spectral_lr, totals);
+  HIPCHK(hipGetLastError());
+  return HSC_OK;
 }
 
 hsc_status hsc_ctx_profile(hsc_ctx* ctx, int32_t enable) {

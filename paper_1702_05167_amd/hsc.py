@@ -74,10 +74,21 @@ def lib():
     L.hsc_kern_zgemm.argtypes = [vp, i32, i32, i32, i32, i32, dbl, dbl, vp, i32, vp, i32, i32, vp, i32, vp, i32]
     L.hsc_kern_zinv_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
     L.hsc_kern_mfma_probe.argtypes = [vp, vp]
+    L.hsc_totals.argtypes = [vp, i32, i64, vp, vp, vp, vp]
+    L.hsc_mlp_create.argtypes = [vp, i32, vp, C.POINTER(vp)]
+    L.hsc_mlp_destroy.argtypes = [vp]
+    L.hsc_mlp_n_params.argtypes = [vp, C.POINTER(i64)]
+    L.hsc_mlp_set_params.argtypes = [vp, vp, vp]
+    L.hsc_mlp_get_params.argtypes = [vp, vp, vp]
+    L.hsc_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+    L.hsc_mlp_grads.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+    L.hsc_mlp_train.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
     for name in ("hsc_ctx_create", "hsc_ctx_destroy", "hsc_tree_build", "hsc_tree_merge", "hsc_tree_stats_get",
                  "hsc_tree_export", "hsc_tree_destroy", "hsc_solve", "hsc_solve_batch", "hsc_sync",
                  "hsc_ctx_profile", "hsc_ctx_profile_read",
-                 "hsc_kern_zgemm", "hsc_kern_zinv_batched", "hsc_kern_mfma_probe"):
+                 "hsc_kern_zgemm", "hsc_kern_zinv_batched", "hsc_kern_mfma_probe", "hsc_totals",
+                 "hsc_mlp_create", "hsc_mlp_destroy", "hsc_mlp_n_params", "hsc_mlp_set_params",
+                 "hsc_mlp_get_params", "hsc_mlp_forward", "hsc_mlp_grads", "hsc_mlp_train"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -242,6 +253,18 @@ def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R
     if sync:
         ctx.sync()
     return o
+
+
+def totals(ctx: Context, out: dict, n: int):
+    """Per-energy (DOS, electrons per unit energy, contact-injected DOS) from solve outputs:
+    device float64 [n_e, 3]; columns whose input is absent stay zero."""
+    import torch
+    ref = next(out[k] for k in ("gr", "gl", "spectral") if k in out)
+    ne = int(ref.shape[0])
+    t = torch.zeros((ne, 3), dtype=torch.float64, device=ref.device)
+    check(lib().hsc_totals(ctx.h, ne, n, _dptr(out.get("gr")), _dptr(out.get("gl")), _dptr(out.get("spectral")),
+                           _dptr(t)))
+    return t
 
 
 # ---- kernel-level entry points -------------------------------------------------------------------
