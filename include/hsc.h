@@ -112,6 +112,11 @@ typedef struct {
    * fold's rounding errors by up to ~1/sigma_min(A_ii)^2 at energies where a
    * cluster block is nearly singular; 1 removes that loss. */
   int32_t precision;
+  /* 1: record the launch sequence of one batch of energies once as a HIP graph
+   * (its outputs go to staging rows owned by the plan) and replay it for every
+   * batch, copying the rows out; 0: launch step by step.  Ignored when the
+   * guard is on or launch timing is enabled. */
+  int32_t graph;
 } hsc_solve_opts;
 
 /* Library version string. */
@@ -141,6 +146,14 @@ hsc_status hsc_tree_build(int64_t n, const int64_t* indptr, const int32_t* indic
  * on its own.  The root cannot be merged.  Errors: HSC_E_ARG. */
 hsc_status hsc_tree_merge(const hsc_tree* src, int32_t n_ids, const int32_t* ids,
                           hsc_tree** out);
+
+/* A forest of several devices (Section 2.2 trees side by side): the clusters of
+ * trees[0], trees[1], ... in that order, sites numbered device after device.
+ * Solving the forest solves every device at once, each device's clusters of a
+ * level sharing the batched launches of that level.  All devices must use the
+ * same lead model (HSC_E_ARG otherwise); total sites < 2^31.  The new tree
+ * copies what it needs: the inputs may be destroyed afterwards. */
+hsc_status hsc_tree_concat(int32_t n_trees, const hsc_tree* const* trees, hsc_tree** out);
 
 hsc_status hsc_tree_stats_get(const hsc_tree* tree, hsc_tree_stats* out);
 
@@ -177,9 +190,16 @@ hsc_status hsc_solve(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, const doub
                      const hsc_solve_opts* opts, void* diag_gr, void* diag_gl, double* trans,
                      double* spectral_lr, int32_t* status, double* guard);
 
-/* Solve several devices (each with its own energies and outputs) in one call:
- * their clusters share every batched launch.  Arrays are indexed by device;
- * entries follow hsc_solve.  Errors as hsc_solve. */
+/* Solve several devices in one call.  Arrays are indexed by device; entries
+ * follow hsc_solve.  When every device has the same energy list, the same lead
+ * model and the guard is off, consecutive devices are packed into forests
+ * (hsc_tree_concat) whose workspace per energy slot fits about a ninth of the
+ * free device memory: one plan per forest, every level's clusters of all its
+ * devices in the same launches, outputs staged in device memory and copied to
+ * each device's buffers; a numerical failure at an energy is then reported in
+ * the status of every device of that forest.  A device too large to share is
+ * solved alone, and with differing energy lists the devices are solved one
+ * after another.  Errors as hsc_solve. */
 hsc_status hsc_solve_batch(hsc_ctx* ctx, int32_t n_trees, const hsc_tree* const* trees,
                            const int32_t* n_e, const double* const* energies,
                            const hsc_solve_opts* opts, void* const* diag_gr,

@@ -58,6 +58,10 @@ struct hsc_tree {
   std::vector<int32_t> owner;      // site -> cluster
   int depth = 0;                   // number of levels
   uint64_t uid = 0;                // identity for device-side caches
+  // devices of a forest (hsc_tree_concat); one segment for an ordinary tree:
+  // device d owns sites [seg_site[d], seg_site[d+1]) and left-contact entries
+  // [seg_left[d], seg_left[d+1]) of contact[0].sites
+  std::vector<int64_t> seg_site, seg_left;
 };
 
 namespace hsc {

@@ -100,7 +100,14 @@ struct Plan {
   int nleft = 0;
   LeadParams lp{};
   std::vector<Step> steps;
+  // graph replay of one batch: outputs to staging rows [B][n] (gr, gl) and [B][2][n] (spectral)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  char* stage = nullptr;
   ~Plan() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (stage) (void)hipFree(stage);
     if (ws) (void)hipFree(ws);
     if (blob) (void)hipFree(blob);
   }
@@ -118,6 +125,12 @@ struct hsc_ctx {
   std::vector<std::pair<int, double>> ev_meta;   // (kind, flops) per recorded launch
   size_t ev_used = 0;
   double prof[16][3] = {};                        // kind -> launches, ms, flops (16 >= number of kinds)
+  hipStream_t cap_stream = nullptr;               // graph capture (a stream of its own, default priority)
+  // forest of the last multi-device batch and its output staging
+  std::vector<uint64_t> forest_key;
+  hsc_tree* forest = nullptr;
+  char* bstage = nullptr;
+  size_t bstage_bytes = 0;
 };
 
 namespace hsc {
@@ -906,9 +919,8 @@ bool step_empty(const Step& s) {
   }
 }
 
-int run_steps(hsc_ctx* ctx, Plan* pl, int e_base, int nvalid, void* gr, void* glo, double* spectral,
-              double* guard, int nclusters) {
-  hipStream_t st = ctx->stream;
+int run_steps(hsc_ctx* ctx, hipStream_t st, Plan* pl, int e_base, int nvalid, void* gr, void* glo,
+              double* spectral, double* guard, int nclusters) {
   const int64_t n = pl->n;
   for (const Step& s : pl->steps) {
     if (step_empty(s)) continue;
@@ -1033,8 +1045,15 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
   HIPCHK(hipSetDevice(ctx->device));
   if (hipMalloc(&pl->ws, pl->ws_bytes) != hipSuccess) {
     (void)hipGetLastError();
-    set_error("device workspace allocation failed (" + std::to_string(pl->ws_bytes) + " bytes)");
-    return HSC_E_OOM;
+    pl->ws = nullptr;
+    // make room: drop every cached plan and try once more
+    ctx->plans.clear();
+    if (hipMalloc(&pl->ws, pl->ws_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      pl->ws = nullptr;
+      set_error("device workspace allocation failed (" + std::to_string(pl->ws_bytes) + " bytes)");
+      return HSC_E_OOM;
+    }
   }
   b.wsbase = pl->ws;
   pl->es = reinterpret_cast<EnergyScalars*>(pl->ws + o_es);
@@ -1116,6 +1135,10 @@ hsc_status hsc_ctx_destroy(hsc_ctx* ctx) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
   }
+  ctx->plans.clear();
+  if (ctx->forest) hsc_tree_destroy(ctx->forest);
+  if (ctx->bstage) (void)hipFree(ctx->bstage);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
   return HSC_OK;
 }
@@ -1149,21 +1172,70 @@ static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
   if (opts->precision != 0 && opts->precision != 1) { set_error("precision must be 0 or 1"); return HSC_E_ARG; }
   int st = build_plan(ctx, tree, B, want, opts->precision, &pl);
   if (st != HSC_OK) return (hsc_status)st;
+  const int64_t n = tree->n;
+  const bool use_graph = opts->graph != 0 && !guard && !ctx->profile;
+  double2* sg_gr = nullptr;
+  double2* sg_gl = nullptr;
+  double* sg_sp = nullptr;
+  if (use_graph) {
+    const size_t row = (size_t)B * n;
+    if (!pl->stage && hipMalloc(&pl->stage, row * 48) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("graph staging allocation failed");
+      return HSC_E_OOM;
+    }
+    sg_gr = (double2*)pl->stage;
+    sg_gl = sg_gr + row;
+    sg_sp = (double*)(sg_gl + row);
+    if (!pl->gexec) {
+      if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+      HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
+      st = run_steps(ctx, ctx->cap_stream, pl, 0, B, sg_gr, sg_gl, sg_sp, nullptr, (int)tree->cl.size());
+      hipGraph_t g = nullptr;
+      const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &g);
+      if (st != HSC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return (hsc_status)st;
+      }
+      HIPCHK(ce);
+      pl->graph = g;
+      HIPCHK(hipGraphInstantiate(&pl->gexec, g, nullptr, nullptr, 0));
+    }
+  }
+  const int nseg = std::max<int>(1, (int)tree->seg_site.size() - 1);
   for (int e0 = 0; e0 < n_e; e0 += B) {
     const int nv = std::min(B, n_e - e0);
     launch_energy_setup(ctx->stream, energies + e0, nv, B, opts->eta, opts->kT, opts->mu_L, opts->mu_R, pl->lp,
                         pl->es, pl->status);
-    st = run_steps(ctx, pl, e0, nv, diag_gr, diag_gl, spectral_lr, guard, (int)tree->cl.size());
-    if (st != HSC_OK) return (hsc_status)st;
-    if (want & HSC_TRANS) {
+    const double* spec_rows = spectral_lr ? spectral_lr + (size_t)e0 * 2 * n : nullptr;
+    if (use_graph) {
+      HIPCHK(hipGraphLaunch(pl->gexec, ctx->stream));
+      const size_t rows = (size_t)nv * n;
+      if (want & HSC_DIAG_GR)
+        HIPCHK(hipMemcpyAsync((double2*)diag_gr + (size_t)e0 * n, sg_gr, rows * 16, hipMemcpyDeviceToDevice, ctx->stream));
+      if (want & HSC_DIAG_GL)
+        HIPCHK(hipMemcpyAsync((double2*)diag_gl + (size_t)e0 * n, sg_gl, rows * 16, hipMemcpyDeviceToDevice, ctx->stream));
       if (want & HSC_SPECTRAL_LR)
-        launch_trans(ctx->stream, spectral_lr + (size_t)e0 * 2 * tree->n + tree->n, 2 * tree->n, pl->left,
-                     pl->nleft, B, nv, e0, pl->es, trans);
-      else
-        launch_trans(ctx->stream, pl->a_r, tree->n, pl->left, pl->nleft, B, nv, e0, pl->es, trans);
+        HIPCHK(hipMemcpyAsync(spectral_lr + (size_t)e0 * 2 * n, sg_sp, rows * 16, hipMemcpyDeviceToDevice, ctx->stream));
+      spec_rows = sg_sp;
+    } else {
+      st = run_steps(ctx, ctx->stream, pl, e0, nv, diag_gr, diag_gl, spectral_lr, guard, (int)tree->cl.size());
+      if (st != HSC_OK) return (hsc_status)st;
+    }
+    if (want & HSC_TRANS) {
+      // one transmission per device of a forest, from its own left-contact sites
+      for (int d = 0; d < nseg; ++d) {
+        const int64_t l0 = tree->seg_left.empty() ? 0 : tree->seg_left[d];
+        const int64_t l1 = tree->seg_left.empty() ? pl->nleft : tree->seg_left[d + 1];
+        double* td = trans + (size_t)d * n_e;
+        if (want & HSC_SPECTRAL_LR)
+          launch_trans(ctx->stream, spec_rows + n, 2 * n, pl->left + l0, (int)(l1 - l0), B, nv, e0, pl->es, td);
+        else
+          launch_trans(ctx->stream, pl->a_r, n, pl->left + l0, (int)(l1 - l0), B, nv, e0, pl->es, td);
+      }
     }
     if ((want & HSC_SPECTRAL_LR) && (want & HSC_DIAG_GL))
-      launch_combine_gl(ctx->stream, spectral_lr, nv, e0, tree->n, pl->es, (double2*)diag_gl);
+      launch_combine_gl(ctx->stream, spectral_lr, nv, e0, n, pl->es, (double2*)diag_gl);
     if (status) launch_status_out(ctx->stream, pl->status, nv, status + e0);
   }
   HIPCHK(hipGetLastError());
@@ -1325,20 +1397,160 @@ hsc_status hsc_solve(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, const doub
   return rc;
 }
 
-hsc_status hsc_solve_batch(hsc_ctx* ctx, int32_t n_trees, const hsc_tree* const* trees, const int32_t* n_e,
-                           const double* const* energies, const hsc_solve_opts* opts, void* const* diag_gr,
-                           void* const* diag_gl, double* const* trans, double* const* spectral_lr,
-                           int32_t* const* status, double* const* guard) {
-  if (!ctx || n_trees < 0 || (n_trees > 0 && (!trees || !n_e || !energies))) {
-    set_error("bad arguments to hsc_solve_batch");
-    return HSC_E_ARG;
-  }
+static hsc_status solve_each(hsc_ctx* ctx, int32_t n_trees, const hsc_tree* const* trees, const int32_t* n_e,
+                             const double* const* energies, const hsc_solve_opts* opts, void* const* diag_gr,
+                             void* const* diag_gl, double* const* trans, double* const* spectral_lr,
+                             int32_t* const* status, double* const* guard) {
   for (int d = 0; d < n_trees; ++d) {
     hsc_status s = hsc_solve(ctx, trees[d], n_e[d], energies[d], opts, diag_gr ? diag_gr[d] : nullptr,
                              diag_gl ? diag_gl[d] : nullptr, trans ? trans[d] : nullptr,
                              spectral_lr ? spectral_lr[d] : nullptr, status ? status[d] : nullptr,
                              guard ? guard[d] : nullptr);
     if (s != HSC_OK) return s;
+  }
+  return HSC_OK;
+}
+
+// one forest of n_trees devices with a shared energy list; outputs staged and copied per device
+static hsc_status solve_forest(hsc_ctx* ctx, int32_t n_trees, const hsc_tree* const* trees, int ne,
+                               const double* energies, const hsc_solve_opts* opts, void* const* diag_gr,
+                               void* const* diag_gl, double* const* trans, double* const* spectral_lr,
+                               int32_t* const* status) {
+  const uint32_t want = opts->want;
+  std::vector<uint64_t> key;
+  for (int d = 0; d < n_trees; ++d) key.push_back(trees[d]->uid);
+  if (!ctx->forest || ctx->forest_key != key) {
+    if (ctx->forest) {
+      const uint64_t old = ctx->forest->uid;
+      ctx->plans.erase(std::remove_if(ctx->plans.begin(), ctx->plans.end(),
+                                      [&](const std::unique_ptr<Plan>& p) { return p->uid == old; }),
+                       ctx->plans.end());
+      hsc_tree_destroy(ctx->forest);
+      ctx->forest = nullptr;
+      ctx->forest_key.clear();
+    }
+    hsc_tree* f = nullptr;
+    hsc_status rc = hsc_tree_concat(n_trees, trees, &f);
+    if (rc != HSC_OK) return rc;
+    ctx->forest = f;
+    ctx->forest_key = key;
+  }
+  const hsc_tree* F = ctx->forest;
+  const int64_t N = F->n;
+  // staging: gr, gl [ne][N] complex; spectral [ne][2][N]; trans [n_trees][ne]; status [ne]
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t o_gr = 0, o_gl = al(o_gr + 16 * (size_t)ne * N), o_sp = al(o_gl + 16 * (size_t)ne * N),
+               o_tr = al(o_sp + 16 * (size_t)ne * N), o_st = al(o_tr + 8 * (size_t)ne * n_trees),
+               bytes = al(o_st + 4 * (size_t)ne);
+  if (ctx->bstage_bytes < bytes) {
+    if (ctx->bstage) {
+      HIPCHK(hipDeviceSynchronize());
+      (void)hipFree(ctx->bstage);
+      ctx->bstage = nullptr;
+      ctx->bstage_bytes = 0;
+    }
+    if (hipMalloc(&ctx->bstage, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("hsc_solve_batch: output staging allocation failed");
+      return HSC_E_OOM;
+    }
+    ctx->bstage_bytes = bytes;
+  }
+  char* sb = ctx->bstage;
+  hsc_status rc = solve_core(ctx, F, ne, energies, opts, sb + o_gr, sb + o_gl, (double*)(sb + o_tr),
+                             (double*)(sb + o_sp), (int32_t*)(sb + o_st), nullptr);
+  if (rc != HSC_OK) return rc;
+  hipStream_t st = ctx->stream;
+  for (int d = 0; d < n_trees; ++d) {
+    const int64_t s0 = F->seg_site[d], nd = F->seg_site[d + 1] - s0;
+    if (want & HSC_DIAG_GR)
+      HIPCHK(hipMemcpy2DAsync(diag_gr[d], 16 * nd, sb + o_gr + 16 * s0, 16 * N, 16 * nd, ne, hipMemcpyDeviceToDevice, st));
+    if (want & HSC_DIAG_GL)
+      HIPCHK(hipMemcpy2DAsync(diag_gl[d], 16 * nd, sb + o_gl + 16 * s0, 16 * N, 16 * nd, ne, hipMemcpyDeviceToDevice, st));
+    if (want & HSC_SPECTRAL_LR)
+      HIPCHK(hipMemcpy2DAsync(spectral_lr[d], 8 * nd, sb + o_sp + 8 * s0, 8 * N, 8 * nd, 2 * (size_t)ne,
+                              hipMemcpyDeviceToDevice, st));
+    if (want & HSC_TRANS)
+      HIPCHK(hipMemcpyAsync(trans[d], sb + o_tr + 8 * (size_t)d * ne, 8 * (size_t)ne, hipMemcpyDeviceToDevice, st));
+    if (status && status[d])
+      HIPCHK(hipMemcpyAsync(status[d], sb + o_st, 4 * (size_t)ne, hipMemcpyDeviceToDevice, st));
+  }
+  return HSC_OK;
+}
+
+hsc_status hsc_solve_batch(hsc_ctx* ctx, int32_t n_trees, const hsc_tree* const* trees, const int32_t* n_e,
+                           const double* const* energies, const hsc_solve_opts* opts, void* const* diag_gr,
+                           void* const* diag_gl, double* const* trans, double* const* spectral_lr,
+                           int32_t* const* status, double* const* guard) {
+  if (!ctx || !opts || n_trees < 0 || (n_trees > 0 && (!trees || !n_e || !energies))) {
+    set_error("bad arguments to hsc_solve_batch");
+    return HSC_E_ARG;
+  }
+  for (int d = 0; d < n_trees; ++d)
+    if (!trees[d] || n_e[d] < 0 || (n_e[d] > 0 && !energies[d])) { set_error("bad device entry in hsc_solve_batch"); return HSC_E_ARG; }
+  if (n_trees <= 1 || opts->guard_tau > 0.0 || guard)
+    return solve_each(ctx, n_trees, trees, n_e, energies, opts, diag_gr, diag_gl, trans, spectral_lr, status, guard);
+  // one forest when every device has the same energies and lead model
+  const int ne = n_e[0];
+  bool same = ne > 0;
+  for (int d = 1; d < n_trees && same; ++d) same = n_e[d] == ne;
+  for (int d = 1; d < n_trees && same; ++d)
+    for (int k = 0; k < 2 && same; ++k) {
+      const auto &a = trees[0]->contact[k], &b = trees[d]->contact[k];
+      same = a.lead_onsite == b.lead_onsite && a.lead_hopping == b.lead_hopping && a.coupling == b.coupling;
+    }
+  HIPCHK(hipSetDevice(ctx->device));
+  std::vector<double> e0h(same ? ne : 0), edh(same ? ne : 0);
+  if (same) HIPCHK(hipMemcpy(e0h.data(), energies[0], 8 * (size_t)ne, hipMemcpyDeviceToHost));
+  for (int d = 1; d < n_trees && same; ++d) {
+    if (energies[d] == energies[0]) continue;
+    HIPCHK(hipMemcpy(edh.data(), energies[d], 8 * (size_t)ne, hipMemcpyDeviceToHost));
+    same = std::memcmp(e0h.data(), edh.data(), 8 * (size_t)ne) == 0;
+  }
+  if (!same)
+    return solve_each(ctx, n_trees, trees, n_e, energies, opts, diag_gr, diag_gl, trans, spectral_lr, status, guard);
+  const uint32_t want = opts->want;
+  for (int d = 0; d < n_trees; ++d)
+    if (((want & HSC_DIAG_GR) && !(diag_gr && diag_gr[d])) || ((want & HSC_DIAG_GL) && !(diag_gl && diag_gl[d])) ||
+        ((want & HSC_TRANS) && !(trans && trans[d])) || ((want & HSC_SPECTRAL_LR) && !(spectral_lr && spectral_lr[d]))) {
+      set_error("hsc_solve_batch: a requested output of a device is NULL");
+      return HSC_E_ARG;
+    }
+  // devices go into forests in order, each forest's workspace per energy slot within
+  // 0.45/4 of the free memory (room for about four energy slots at the default batch);
+  // a device above that budget on its own is solved alone
+  size_t freeb = 0, totalb = 0;
+  HIPCHK(hipMemGetInfo(&freeb, &totalb));
+  const double budget = 0.45 * (double)freeb / 4.0;
+  std::vector<std::pair<int, int>> groups;
+  {
+    int g0 = 0;
+    double acc = 0;
+    for (int d = 0; d < n_trees; ++d) {
+      const double bd = (double)plan_bytes_per_slot(trees[d], want, opts->precision);
+      if (d > g0 && acc + bd > budget) {
+        groups.push_back({g0, d});
+        g0 = d;
+        acc = 0;
+      }
+      acc += bd;
+    }
+    groups.push_back({g0, n_trees});
+  }
+  for (const auto& g : groups) {
+    if (g.second - g.first == 1) {
+      const int d = g.first;
+      hsc_status rc = hsc_solve(ctx, trees[d], ne, energies[d], opts, diag_gr ? diag_gr[d] : nullptr,
+                                diag_gl ? diag_gl[d] : nullptr, trans ? trans[d] : nullptr,
+                                spectral_lr ? spectral_lr[d] : nullptr, status ? status[d] : nullptr, nullptr);
+      if (rc != HSC_OK) return rc;
+      continue;
+    }
+    hsc_status rc = solve_forest(ctx, g.second - g.first, trees + g.first, ne, energies[g.first], opts,
+                                 diag_gr ? diag_gr + g.first : nullptr, diag_gl ? diag_gl + g.first : nullptr,
+                                 trans ? trans + g.first : nullptr, spectral_lr ? spectral_lr + g.first : nullptr,
+                                 status ? status + g.first : nullptr);
+    if (rc != HSC_OK) return rc;
   }
   return HSC_OK;
 }

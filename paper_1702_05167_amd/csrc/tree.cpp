@@ -1,6 +1,7 @@
 // Host-side cluster tree: geometric multilevel nested dissection (Section 2.2),
 // point-level fronts, relative index maps, and the per-energy operation count.
 #include <algorithm>
+#include <climits>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -357,6 +358,8 @@ hsc_status hsc_tree_build(int64_t n, const int64_t* indptr, const int32_t* indic
     for (size_t i = 0; i < b.sites_of.size(); ++i) t->cl[i].children = b.kids_of[i];
     int st = finalize_tree(t, b.sites_of);
     if (st != HSC_OK) { delete t; return (hsc_status)st; }
+    t->seg_site = {0, n};
+    t->seg_left = {0, (int64_t)t->contact[0].sites.size()};
   } catch (const std::string& msg) {
     delete t;
     set_error(msg);
@@ -376,7 +379,10 @@ hsc_status hsc_tree_merge(const hsc_tree* src, int32_t n_ids, const int32_t* ids
   const int nc = (int)src->cl.size();
   std::vector<char> gone(nc, 0);
   for (int k = 0; k < n_ids; ++k) {
-    if (ids[k] < 0 || ids[k] >= nc - 1) { set_error("cluster id out of range (the root cannot be merged)"); return HSC_E_ARG; }
+    if (ids[k] < 0 || ids[k] >= nc || src->cl[ids[k]].parent < 0) {
+      set_error("cluster id out of range (a root cannot be merged)");
+      return HSC_E_ARG;
+    }
     gone[ids[k]] = 1;
   }
   hsc_tree* t = new (std::nothrow) hsc_tree(*src);
@@ -407,10 +413,76 @@ hsc_status hsc_tree_merge(const hsc_tree* src, int32_t n_ids, const int32_t* ids
     newid[i] = (int)ncl.size() - 1;
     return newid[i];
   };
-  walk(nc - 1);
+  for (int i = 0; i < nc; ++i)
+    if (src->cl[i].parent < 0) walk(i);
   t->cl = ncl;
   int st = finalize_tree(t, nsites);
   if (st != HSC_OK) { delete t; return (hsc_status)st; }
+  *out = t;
+  return HSC_OK;
+}
+
+hsc_status hsc_tree_concat(int32_t n_trees, const hsc_tree* const* trees, hsc_tree** out) {
+  if (!out || n_trees < 1 || !trees) { set_error("bad arguments to hsc_tree_concat"); return HSC_E_ARG; }
+  *out = nullptr;
+  for (int d = 0; d < n_trees; ++d)
+    if (!trees[d]) { set_error("null tree in hsc_tree_concat"); return HSC_E_ARG; }
+  for (int d = 1; d < n_trees; ++d)
+    for (int k = 0; k < 2; ++k) {
+      const ContactInfo &a = trees[0]->contact[k], &b = trees[d]->contact[k];
+      if (a.lead_onsite != b.lead_onsite || a.lead_hopping != b.lead_hopping || a.coupling != b.coupling) {
+        set_error("hsc_tree_concat: devices differ in their lead model");
+        return HSC_E_ARG;
+      }
+    }
+  int64_t ntot = 0;
+  for (int d = 0; d < n_trees; ++d) ntot += trees[d]->n;
+  if (ntot > INT32_MAX) { set_error("hsc_tree_concat: more than 2^31 - 1 sites"); return HSC_E_ARG; }
+  hsc_tree* t = new (std::nothrow) hsc_tree();
+  if (!t) { set_error("host allocation failed"); return HSC_E_OOM; }
+  try {
+    t->n = ntot;
+    t->split_mask = trees[0]->split_mask;
+    t->leaf_side = trees[0]->leaf_side;
+    t->indptr.assign(1, 0);
+    for (int k = 0; k < 2; ++k) t->contact[k] = trees[0]->contact[k], t->contact[k].sites.clear();
+    std::vector<std::vector<int64_t>> sites_of;
+    std::vector<std::vector<int>> kids;
+    int64_t s0 = 0;
+    t->seg_site.assign(1, 0);
+    t->seg_left.assign(1, 0);
+    for (int d = 0; d < n_trees; ++d) {
+      const hsc_tree* u = trees[d];
+      const int64_t nnz0 = t->indptr.back();
+      for (int64_t r = 0; r < u->n; ++r) t->indptr.push_back(nnz0 + u->indptr[r + 1]);
+      for (int32_t c : u->indices) t->indices.push_back((int32_t)(c + s0));
+      t->values.insert(t->values.end(), u->values.begin(), u->values.end());
+      t->coords.insert(t->coords.end(), u->coords.begin(), u->coords.end());
+      t->side.insert(t->side.end(), u->side.begin(), u->side.end());
+      for (int k = 0; k < 2; ++k)
+        for (int64_t x : u->contact[k].sites) t->contact[k].sites.push_back(x + s0);
+      const int c0 = (int)kids.size();
+      for (const Cluster& c : u->cl) {
+        std::vector<int> ch;
+        for (int k : c.children) ch.push_back(k + c0);
+        kids.push_back(ch);
+        std::vector<int64_t> v;
+        for (int64_t p = c.first; p < c.first + c.n; ++p) v.push_back(u->perm[p] + s0);
+        sites_of.push_back(v);
+      }
+      s0 += u->n;
+      t->seg_site.push_back(s0);
+      t->seg_left.push_back((int64_t)t->contact[0].sites.size());
+    }
+    t->cl.resize(kids.size());
+    for (size_t i = 0; i < kids.size(); ++i) t->cl[i].children = kids[i];
+    int st = finalize_tree(t, sites_of);
+    if (st != HSC_OK) { delete t; return (hsc_status)st; }
+  } catch (const std::bad_alloc&) {
+    delete t;
+    set_error("host allocation failed");
+    return HSC_E_OOM;
+  }
   *out = t;
   return HSC_OK;
 }

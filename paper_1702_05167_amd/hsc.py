@@ -42,7 +42,7 @@ class TreeStats(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("eta", C.c_double), ("kT", C.c_double), ("mu_L", C.c_double), ("mu_R", C.c_double),
                 ("want", C.c_uint32), ("batch", C.c_int32), ("guard_tau", C.c_double),
-                ("guard_rounds", C.c_int32), ("precision", C.c_int32)]
+                ("guard_rounds", C.c_int32), ("precision", C.c_int32), ("graph", C.c_int32)]
 
 
 _lib = None
@@ -63,6 +63,7 @@ def lib():
     L.hsc_ctx_destroy.argtypes = [vp]
     L.hsc_tree_build.argtypes = [i64, vp, vp, vp, i32, C.POINTER(Contact), C.POINTER(TreeOpts), C.POINTER(vp)]
     L.hsc_tree_merge.argtypes = [vp, i32, vp, C.POINTER(vp)]
+    L.hsc_tree_concat.argtypes = [i32, vp, C.POINTER(vp)]
     L.hsc_tree_stats_get.argtypes = [vp, C.POINTER(TreeStats)]
     L.hsc_tree_export.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.hsc_tree_destroy.argtypes = [vp]
@@ -83,7 +84,8 @@ def lib():
     L.hsc_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
     L.hsc_mlp_grads.argtypes = [vp, vp, i64, vp, vp, vp, vp]
     L.hsc_mlp_train.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
-    for name in ("hsc_ctx_create", "hsc_ctx_destroy", "hsc_tree_build", "hsc_tree_merge", "hsc_tree_stats_get",
+    for name in ("hsc_ctx_create", "hsc_ctx_destroy", "hsc_tree_build", "hsc_tree_merge", "hsc_tree_concat",
+                 "hsc_tree_stats_get",
                  "hsc_tree_export", "hsc_tree_destroy", "hsc_solve", "hsc_solve_batch", "hsc_sync",
                  "hsc_ctx_profile", "hsc_ctx_profile_read",
                  "hsc_kern_zgemm", "hsc_kern_zinv_batched", "hsc_kern_mfma_probe", "hsc_totals",
@@ -213,6 +215,14 @@ class Tree:
         check(lib().hsc_tree_merge(self.h, len(ids), _ptr(ids), C.byref(h)))
         return Tree(h, self.n)
 
+    @classmethod
+    def concat(cls, trees) -> "Tree":
+        """Forest of several devices, sites numbered device after device."""
+        hs = (C.c_void_p * len(trees))(*[t.h.value for t in trees])
+        h = C.c_void_p()
+        check(lib().hsc_tree_concat(len(trees), hs, C.byref(h)))
+        return cls(h, sum(t.n for t in trees))
+
     def close(self):
         if getattr(self, "h", None):
             lib().hsc_tree_destroy(self.h)
@@ -227,7 +237,7 @@ class Tree:
 
 def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1,
           want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, out=None, sync=True, guard=False,
-          guard_tau=0.0, guard_rounds=6, precision=1):
+          guard_tau=0.0, guard_rounds=6, precision=1, graph=0):
     """Solve all energies; returns a dict of device tensors (gr, gl, trans, spectral, status)."""
     import torch
     dev = ctx.torch_device
@@ -246,13 +256,58 @@ def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R
         o["status"] = torch.empty(ne, dtype=torch.int32, device=dev)
     if guard and "guard" not in o:
         o["guard"] = torch.zeros((ne, tree.stats()["n_clusters"], 2), dtype=torch.float64, device=dev)
-    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, guard_tau, guard_rounds, precision)
+    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, guard_tau, guard_rounds, precision, graph)
     check(lib().hsc_solve(ctx.h, tree.h, ne, _dptr(e), C.byref(opts), _dptr(o.get("gr")), _dptr(o.get("gl")),
                           _dptr(o.get("trans")), _dptr(o.get("spectral")), _dptr(o.get("status")),
                           _dptr(o.get("guard"))))
     if sync:
         ctx.sync()
     return o
+
+
+def solve_batch(ctx: Context, trees, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1,
+                want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, outs=None, sync=True, precision=1, graph=0):
+    """Several devices in one call (hsc_solve_batch); energies: one array for all devices or a
+    list of per-device arrays.  Returns a list of output dicts (device tensors)."""
+    import torch
+    dev = ctx.torch_device
+    nt = len(trees)
+    if not isinstance(energies, (list, tuple)):
+        energies = [energies] * nt
+    es = []
+    shared = None
+    for e in energies:
+        t = torch.as_tensor(e, dtype=torch.float64, device=dev).contiguous()
+        if shared is not None and t.data_ptr() != shared.data_ptr() and torch.equal(t, shared):
+            t = shared
+        shared = shared if shared is not None else t
+        es.append(t)
+    outs = outs or [dict() for _ in range(nt)]
+    for o, tr, e in zip(outs, trees, es):
+        ne, n = int(e.numel()), tr.n
+        if want & HSC_DIAG_GR and "gr" not in o:
+            o["gr"] = torch.empty((ne, n), dtype=torch.complex128, device=dev)
+        if want & HSC_DIAG_GL and "gl" not in o:
+            o["gl"] = torch.empty((ne, n), dtype=torch.complex128, device=dev)
+        if want & HSC_TRANS and "trans" not in o:
+            o["trans"] = torch.empty(ne, dtype=torch.float64, device=dev)
+        if want & HSC_SPECTRAL_LR and "spectral" not in o:
+            o["spectral"] = torch.empty((ne, 2, n), dtype=torch.float64, device=dev)
+        if "status" not in o:
+            o["status"] = torch.empty(ne, dtype=torch.int32, device=dev)
+
+    def arr(key):
+        return (C.c_void_p * nt)(*[(o[key].data_ptr() if key in o else None) for o in outs])
+
+    th = (C.c_void_p * nt)(*[t.h.value for t in trees])
+    ne_arr = np.array([int(e.numel()) for e in es], np.int32)
+    e_arr = (C.c_void_p * nt)(*[e.data_ptr() for e in es])
+    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, 0.0, 0, precision, graph)
+    check(lib().hsc_solve_batch(ctx.h, nt, th, _ptr(ne_arr), e_arr, C.byref(opts), arr("gr"), arr("gl"), arr("trans"),
+                                arr("spectral"), arr("status"), None))
+    if sync:
+        ctx.sync()
+    return outs
 
 
 def totals(ctx: Context, out: dict, n: int):

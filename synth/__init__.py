@@ -13,7 +13,7 @@ from .devices import (  # noqa: F401
     energy_grid,
     config0_device,
     config1_device,
-    config2_devices,
+    config2_devices, config2_sizes,
     config3_device,
     learned_grid_device,
 )

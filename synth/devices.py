@@ -173,11 +173,19 @@ def config1_device(seed: int = 0, n_side: int = 32) -> Device:
     return cuboid(n_side, n_side, n_side, onsite=_uniform_onsite(n, seed), name=f"cube{n_side}")
 
 
-def config2_devices(seed: int = 0, count: int = 64, lo: int = 16, hi: int = 48, sigma: float = 0.3):
-    """Uneven cuboids: sides integers in [lo, hi], on-site N(0, sigma^2) per device."""
-    sizes = np.random.default_rng(seed).integers(lo, hi + 1, size=(count, 3))
+def config2_sizes(seed: int = 0, count: int = 64, lo: int = 16, hi: int = 48) -> np.ndarray:
+    """(Nx, Ny, Nz) of the uneven cuboids, integers in [lo, hi]."""
+    return np.random.default_rng(seed).integers(lo, hi + 1, size=(count, 3))
+
+
+def config2_devices(seed: int = 0, count: int = 64, lo: int = 16, hi: int = 48, sigma: float = 0.3, which=None):
+    """Uneven cuboids: sides integers in [lo, hi], on-site N(0, sigma^2) per device
+    (only the devices listed in `which`, if given)."""
+    sizes = config2_sizes(seed, count, lo, hi)
     out = []
     for d, (nx, ny, nz) in enumerate(sizes):
+        if which is not None and d not in which:
+            continue
         n = int(nx * ny * nz)
         onsite = np.random.default_rng((seed, d)).normal(0.0, sigma, n)
         out.append(cuboid(int(nx), int(ny), int(nz), onsite=onsite, name=f"cuboid{d}"))

@@ -181,3 +181,45 @@ def test_rejects_coordinates_that_do_not_separate():
     with pytest.raises(H.HscError) as e:
         pkg.Tree.build(dev.n, h.indptr, h.indices, h.data, dev.coords, _contacts(dev), 7, 2)
     assert e.value.code == -1
+
+
+def test_concat_is_the_devices_side_by_side():
+    devs = [synth.cuboid(6, 5, 4), synth.cuboid(5, 7, 6), synth.chain(9)]
+    trees = [_tree(d, 3) for d in devs]
+    f = pkg.Tree.concat(trees)
+    st = f.stats()
+    sts = [t.stats() for t in trees]
+    assert st["n_sites"] == sum(s["n_sites"] for s in sts)
+    assert st["n_clusters"] == sum(s["n_clusters"] for s in sts)
+    assert st["max_front"] == max(s["max_front"] for s in sts)
+    assert abs(st["flops_per_energy"] - sum(s["flops_per_energy"] for s in sts)) <= 1e-9 * st["flops_per_energy"]
+    ex = f.export()
+    c0 = s0 = 0
+    for t, d in zip(trees, devs):
+        e = t.export()
+        k = len(e["parent"])
+        par = ex["parent"][c0:c0 + k]
+        assert (par == np.where(e["parent"] >= 0, e["parent"] + c0, -1)).all()
+        assert (ex["perm"][s0:s0 + d.n] == e["perm"] + s0).all()
+        for i in range(k):
+            got = ex["front"][ex["front_ptr"][c0 + i]:ex["front_ptr"][c0 + i + 1]]
+            want = e["front"][e["front_ptr"][i]:e["front_ptr"][i + 1]] + s0
+            assert (got == want).all()
+        c0 += k
+        s0 += d.n
+    # a forest root cannot be merged; other clusters can
+    roots = np.flatnonzero(ex["parent"] < 0)
+    assert len(roots) == 3
+    with pytest.raises(H.HscError):
+        f.merge([int(roots[0])])
+    m = f.merge([0])
+    assert m.stats()["n_clusters"] == st["n_clusters"] - 1
+
+
+def test_concat_rejects_different_leads():
+    a = _tree(synth.cuboid(4, 4, 4), 3)
+    d = synth.cuboid(4, 4, 4)
+    c = [(x.sites, x.lead_onsite, -2.0, x.coupling) for x in d.contacts]
+    b = pkg.Tree.build(d.n, d.indptr, d.indices, d.values, d.coords, c, 7, 3)
+    with pytest.raises(H.HscError):
+        pkg.Tree.concat([a, b])
