@@ -117,6 +117,11 @@ typedef struct {
    * batch, copying the rows out; 0: launch step by step.  Ignored when the
    * guard is on or launch timing is enabled. */
   int32_t graph;
+  /* 1: when the plan for (tree, batch, outputs, precision) is first built, time
+   * every tile shape of the grouped GEMM (64x64, 128x64, 64x128, 32x32) on each
+   * of its launches and keep the fastest per launch; 0: 64x64 everywhere.
+   * Results are the same either way up to the order of the sums. */
+  int32_t tune;
 } hsc_solve_opts;
 
 /* Library version string. */

@@ -28,6 +28,14 @@ hsc_status hsc_kern_zgemm(hsc_ctx* ctx, int32_t opA, int32_t opB, int32_t M, int
                           double alpha_re, double alpha_im, const void* A, int32_t lda, const void* B,
                           int32_t ldb, int32_t beta, const void* C, int32_t ldc, void* D, int32_t ldd);
 
+/* The same product with a chosen tile shape of the grouped GEMM kernel:
+ * tile_kind 0 = 64x64x16 (the default above), 1 = 128x64x16, 2 = 64x128x16,
+ * 3 = 32x32x32 (rows x columns x depth per workgroup).  HSC_E_ARG for another kind. */
+hsc_status hsc_kern_zgemm_tile(hsc_ctx* ctx, int32_t tile_kind, int32_t opA, int32_t opB, int32_t M, int32_t N,
+                               int32_t K, double alpha_re, double alpha_im, const void* A, int32_t lda,
+                               const void* B, int32_t ldb, int32_t beta, const void* C, int32_t ldc, void* D,
+                               int32_t ldd);
+
 /* Invert `count` matrices of order n[k] in place (X[k], leading dimension ld[k])
  * and write X[k]^-1 into Y[k] (leading dimension ldy[k]); all pointer/size
  * arrays are host arrays.  status (device, int32[count], may be NULL) receives

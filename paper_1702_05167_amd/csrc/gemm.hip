@@ -230,14 +230,23 @@ __global__ void k_mfma_probe(double* out) {
 
 }  // namespace
 
-int gemm_tile_m(int) { return 64; }
-int gemm_tile_n(int) { return 64; }
+// tile shapes (BM x BN x BK) the launcher offers; 4 waves in a 2 x 2 grid over the tile
+static const int kTileM[] = {64, 128, 64, 32};
+static const int kTileN[] = {64, 64, 128, 32};
+
+int gemm_tile_kinds() { return 4; }
+int gemm_tile_m(int kind) { return kTileM[kind]; }
+int gemm_tile_n(int kind) { return kTileN[kind]; }
 
 void launch_gemm(hipStream_t st, int opA, int opB, const GemmProb* probs, const int32_t* tile_prob,
                  int total_tiles, double alpha_re, double alpha_im, int beta, int tile_kind) {
   if (total_tiles <= 0) return;
-  (void)tile_kind;   // one tile shape: 64 x 64 x 16
-  dispatch<64, 64, 16>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta);
+  switch (tile_kind) {
+    case 1: dispatch<128, 64, 16>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta); break;
+    case 2: dispatch<64, 128, 16>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta); break;
+    case 3: dispatch<32, 32, 32>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta); break;
+    default: dispatch<64, 64, 16>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta); break;
+  }
 }
 
 void launch_mfma_probe(hipStream_t st, double* out) {

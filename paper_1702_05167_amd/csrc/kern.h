@@ -84,6 +84,7 @@ struct LeadParams {
 // tile_prob[t] = problem owning tile t (host-built map; one entry per tile)
 void launch_gemm(hipStream_t st, int opA, int opB, const GemmProb* probs, const int32_t* tile_prob,
                  int total_tiles, double alpha_re, double alpha_im, int beta, int tile_kind);
+int gemm_tile_kinds();
 int gemm_tile_m(int tile_kind);
 int gemm_tile_n(int tile_kind);
 

@@ -57,10 +57,16 @@ struct Blob {
 enum StepKind { S_ASSEMBLE, S_INV_PANEL, S_INV_SWAP, S_INV_UNSCR, S_GEMM, S_GATHER, S_ASSEMBLE_N, S_DIAG, S_GUARD,
                 S_DD_ASSEMBLE, S_DD_INV_PANEL, S_DD_INV_SWAP, S_DD_INV_UNSCR, S_DD_GEMM };
 
+constexpr int kTileKinds = 4;   // GEMM tile shapes offered by launch_gemm
+
 struct Step {
   StepKind kind;
   size_t jobs = 0, map = 0;   // blob offsets
   int count = 0;              // rows / tiles / jobs
+  // GEMM: problem list, tile map and tile count for every tile shape; `tile` is the one used
+  size_t jobs_k[kTileKinds] = {}, map_k[kTileKinds] = {};
+  int count_k[kTileKinds] = {};
+  int tile = 0;
   int njobs = 0;
   int i0 = 0, i1 = 0, i2 = 0, i3 = 0;
   double ar = 1, ai = 0;
@@ -88,6 +94,7 @@ struct Plan {
   int B = 0;
   uint32_t want = 0;
   int prec = 0;
+  int tune = 0;
   int64_t n = 0;
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -360,28 +367,34 @@ struct Builder {
   // ---- step helpers ----
   struct GP { const double2 *A, *B, *C; double2* D; int M, N, K, lda, ldb, ldc, ldd; };
   void gemm(int opA, int opB, const std::vector<GP>& ps, double ar, double ai, int beta) {
-    std::vector<GemmProb> probs;
-    std::vector<int32_t> tmap;
-    const int tm = gemm_tile_m(0), tn = gemm_tile_n(0);
-    for (const GP& g : ps) {
-      if (g.M <= 0 || g.N <= 0) continue;
-      GemmProb p{};
-      p.A = g.A; p.B = g.B; p.C = g.C; p.D = g.D;
-      p.M = g.M; p.N = g.N; p.K = g.K;
-      p.lda = g.lda; p.ldb = g.ldb; p.ldc = g.ldc; p.ldd = g.ldd;
-      p.tiles_n = (g.N + tn - 1) / tn;
-      p.tile_off = (int32_t)tmap.size();
-      const int tiles = ((g.M + tm - 1) / tm) * p.tiles_n;
-      for (int k = 0; k < tiles; ++k) tmap.push_back((int32_t)probs.size());
-      probs.push_back(p);
-    }
-    if (probs.empty()) return;
     Step s;
     s.kind = S_GEMM;
-    for (const GemmProb& p : probs) s.flops += 8.0 * p.M * p.N * p.K;
-    s.jobs = blob.push(probs);
-    s.map = blob.push(tmap);
-    s.count = (int)tmap.size();
+    for (int kind = 0; kind < kTileKinds; ++kind) {
+      std::vector<GemmProb> probs;
+      std::vector<int32_t> tmap;
+      const int tm = gemm_tile_m(kind), tn = gemm_tile_n(kind);
+      for (const GP& g : ps) {
+        if (g.M <= 0 || g.N <= 0) continue;
+        GemmProb p{};
+        p.A = g.A; p.B = g.B; p.C = g.C; p.D = g.D;
+        p.M = g.M; p.N = g.N; p.K = g.K;
+        p.lda = g.lda; p.ldb = g.ldb; p.ldc = g.ldc; p.ldd = g.ldd;
+        p.tiles_n = (g.N + tn - 1) / tn;
+        p.tile_off = (int32_t)tmap.size();
+        const int tiles = ((g.M + tm - 1) / tm) * p.tiles_n;
+        for (int k = 0; k < tiles; ++k) tmap.push_back((int32_t)probs.size());
+        probs.push_back(p);
+      }
+      if (probs.empty()) return;
+      if (kind == 0)
+        for (const GemmProb& p : probs) s.flops += 8.0 * p.M * p.N * p.K;
+      s.jobs_k[kind] = blob.push(probs);
+      s.map_k[kind] = blob.push(tmap);
+      s.count_k[kind] = (int)tmap.size();
+    }
+    s.jobs = s.jobs_k[0];
+    s.map = s.map_k[0];
+    s.count = s.count_k[0];
     s.i0 = opA; s.i1 = opB;
     s.ar = ar; s.ai = ai; s.beta = beta;
     steps.push_back(s);
@@ -955,7 +968,9 @@ int run_steps(hsc_ctx* ctx, hipStream_t st, Plan* pl, int e_base, int nvalid, vo
         launch_gather(st, (const RowJob*)jobs, map, s.count, s.i0, s.i1);
         break;
       case S_GEMM:
-        launch_gemm(st, s.i0, s.i1, (const GemmProb*)jobs, map, s.count, s.ar, s.ai, s.beta, 0);
+        launch_gemm(st, s.i0, s.i1, (const GemmProb*)(pl->blob + s.jobs_k[s.tile]),
+                    reinterpret_cast<const int32_t*>(pl->blob + s.map_k[s.tile]), s.count_k[s.tile], s.ar, s.ai,
+                    s.beta, s.tile);
         break;
       case S_INV_PANEL:
         launch_inv_panel(st, (const InvJob*)jobs, s.njobs, s.i0, s.i1, s.i2, pl->status);
@@ -1005,10 +1020,49 @@ int run_steps(hsc_ctx* ctx, hipStream_t st, Plan* pl, int e_base, int nvalid, vo
   return HSC_OK;
 }
 
-int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, Plan** out) {
+// Tile autotuner: every GEMM step of the plan is timed once with each tile shape on the
+// plan's own problem list and keeps the fastest.  The workspace holds no results yet; the
+// solve rewrites every buffer of a batch before reading it.
+hsc_status tune_plan(hsc_ctx* ctx, Plan* pl) {
+  hipEvent_t a, b;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  hipStream_t st = ctx->stream;
+  hsc_status rc = HSC_OK;
+  for (Step& s : pl->steps) {
+    if (s.kind != S_GEMM) continue;
+    float best = 0.f;
+    int best_k = 0;
+    for (int k = 0; k < kTileKinds && rc == HSC_OK; ++k) {
+      float ms = 0.f;
+      for (int rep = 0; rep < 2; ++rep) {
+        if (hipEventRecord(a, st) != hipSuccess) { rc = HSC_E_HIP; break; }
+        launch_gemm(st, s.i0, s.i1, (const GemmProb*)(pl->blob + s.jobs_k[k]),
+                    reinterpret_cast<const int32_t*>(pl->blob + s.map_k[k]), s.count_k[k], s.ar, s.ai, s.beta, k);
+        if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+            hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+          rc = HSC_E_HIP;
+          break;
+        }
+      }
+      if (rc == HSC_OK && (k == 0 || ms < best)) { best = ms; best_k = k; }
+    }
+    if (rc != HSC_OK) break;
+    s.tile = best_k;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc != HSC_OK) {
+    (void)hipGetLastError();
+    set_error("GEMM tile tuning failed");
+  }
+  return rc;
+}
+
+int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, int tune, Plan** out) {
   for (size_t k = 0; k < ctx->plans.size(); ++k)
     if (ctx->plans[k]->uid == t->uid && ctx->plans[k]->B == B && ctx->plans[k]->want == want &&
-        ctx->plans[k]->prec == prec) {
+        ctx->plans[k]->prec == prec && ctx->plans[k]->tune == tune) {
       // most recently used goes last
       std::unique_ptr<Plan> p = std::move(ctx->plans[k]);
       ctx->plans.erase(ctx->plans.begin() + k);
@@ -1032,7 +1086,7 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
       return HSC_E_ARG;
     }
   std::unique_ptr<Plan> pl(new Plan());
-  pl->uid = t->uid; pl->B = B; pl->want = want; pl->n = t->n; pl->prec = prec;
+  pl->uid = t->uid; pl->B = B; pl->want = want; pl->n = t->n; pl->prec = prec; pl->tune = tune;
   Builder b{t, B, want, (want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR)) != 0};
   b.ddf = prec == 1;
   b.channels();
@@ -1088,6 +1142,10 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
     pl->lp.coupling[c] = t->contact[c].coupling;
   }
   pl->steps = std::move(b.steps);
+  if (tune) {
+    const hsc_status rc = tune_plan(ctx, pl.get());
+    if (rc != HSC_OK) return rc;
+  }
   *out = pl.get();
   ctx->plans.push_back(std::move(pl));
   return HSC_OK;
@@ -1170,7 +1228,7 @@ static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
   B = std::min(B, n_e);
   Plan* pl = nullptr;
   if (opts->precision != 0 && opts->precision != 1) { set_error("precision must be 0 or 1"); return HSC_E_ARG; }
-  int st = build_plan(ctx, tree, B, want, opts->precision, &pl);
+  int st = build_plan(ctx, tree, B, want, opts->precision, opts->tune != 0, &pl);
   if (st != HSC_OK) return (hsc_status)st;
   const int64_t n = tree->n;
   const bool use_graph = opts->graph != 0 && !guard && !ctx->profile;
@@ -1599,7 +1657,15 @@ extern "C" {
 hsc_status hsc_kern_zgemm(hsc_ctx* ctx, int32_t opA, int32_t opB, int32_t M, int32_t N, int32_t K,
                           double alpha_re, double alpha_im, const void* A, int32_t lda, const void* B,
                           int32_t ldb, int32_t beta, const void* C, int32_t ldc, void* D, int32_t ldd) {
-  if (!ctx || M < 0 || N < 0 || K < 0 || opA < 0 || opA > 2 || opB < 0 || opB > 2 || (beta != 0 && beta != 1)) {
+  return hsc_kern_zgemm_tile(ctx, 0, opA, opB, M, N, K, alpha_re, alpha_im, A, lda, B, ldb, beta, C, ldc, D, ldd);
+}
+
+hsc_status hsc_kern_zgemm_tile(hsc_ctx* ctx, int32_t tile_kind, int32_t opA, int32_t opB, int32_t M, int32_t N,
+                               int32_t K, double alpha_re, double alpha_im, const void* A, int32_t lda,
+                               const void* B, int32_t ldb, int32_t beta, const void* C, int32_t ldc, void* D,
+                               int32_t ldd) {
+  if (!ctx || M < 0 || N < 0 || K < 0 || opA < 0 || opA > 2 || opB < 0 || opB > 2 || (beta != 0 && beta != 1) ||
+      tile_kind < 0 || tile_kind >= gemm_tile_kinds()) {
     set_error("bad arguments to hsc_kern_zgemm");
     return HSC_E_ARG;
   }
@@ -1614,9 +1680,9 @@ hsc_status hsc_kern_zgemm(hsc_ctx* ctx, int32_t opA, int32_t opB, int32_t M, int
   GemmProb p{};
   p.A = (const double2*)A; p.B = (const double2*)B; p.C = (const double2*)C; p.D = (double2*)D;
   p.M = M; p.N = N; p.K = K; p.lda = lda; p.ldb = ldb; p.ldc = ldc; p.ldd = ldd;
-  p.tiles_n = (N + gemm_tile_n(0) - 1) / gemm_tile_n(0);
+  p.tiles_n = (N + gemm_tile_n(tile_kind) - 1) / gemm_tile_n(tile_kind);
   p.tile_off = 0;
-  const int tiles = ((M + gemm_tile_m(0) - 1) / gemm_tile_m(0)) * p.tiles_n;
+  const int tiles = ((M + gemm_tile_m(tile_kind) - 1) / gemm_tile_m(tile_kind)) * p.tiles_n;
   std::vector<int32_t> map(tiles, 0);
   char* dev = nullptr;
   const size_t bytes = 256 + sizeof(int32_t) * tiles;
@@ -1625,7 +1691,7 @@ hsc_status hsc_kern_zgemm(hsc_ctx* ctx, int32_t opA, int32_t opB, int32_t M, int
   hipError_t e2 = hipMemcpy(dev + 256, map.data(), sizeof(int32_t) * tiles, hipMemcpyHostToDevice);
   if (e1 == hipSuccess && e2 == hipSuccess) {
     launch_gemm(ctx->stream, opA, opB, (const GemmProb*)dev, (const int32_t*)(dev + 256), tiles, alpha_re,
-                alpha_im, beta, 0);
+                alpha_im, beta, tile_kind);
     e1 = hipGetLastError();
     if (e1 == hipSuccess) e1 = ctx->stream ? hipStreamSynchronize(ctx->stream) : hipDeviceSynchronize();
   }

@@ -42,7 +42,8 @@ class TreeStats(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("eta", C.c_double), ("kT", C.c_double), ("mu_L", C.c_double), ("mu_R", C.c_double),
                 ("want", C.c_uint32), ("batch", C.c_int32), ("guard_tau", C.c_double),
-                ("guard_rounds", C.c_int32), ("precision", C.c_int32), ("graph", C.c_int32)]
+                ("guard_rounds", C.c_int32), ("precision", C.c_int32), ("graph", C.c_int32),
+                ("tune", C.c_int32)]
 
 
 _lib = None
@@ -73,6 +74,8 @@ def lib():
     L.hsc_ctx_profile.argtypes = [vp, i32]
     L.hsc_ctx_profile_read.argtypes = [vp, vp, i32]
     L.hsc_kern_zgemm.argtypes = [vp, i32, i32, i32, i32, i32, dbl, dbl, vp, i32, vp, i32, i32, vp, i32, vp, i32]
+    L.hsc_kern_zgemm_tile.argtypes = [vp, i32, i32, i32, i32, i32, i32, dbl, dbl, vp, i32, vp, i32, i32, vp, i32, vp,
+                                      i32]
     L.hsc_kern_zinv_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
     L.hsc_kern_mfma_probe.argtypes = [vp, vp]
     L.hsc_totals.argtypes = [vp, i32, i64, vp, vp, vp, vp]
@@ -88,7 +91,7 @@ def lib():
                  "hsc_tree_stats_get",
                  "hsc_tree_export", "hsc_tree_destroy", "hsc_solve", "hsc_solve_batch", "hsc_sync",
                  "hsc_ctx_profile", "hsc_ctx_profile_read",
-                 "hsc_kern_zgemm", "hsc_kern_zinv_batched", "hsc_kern_mfma_probe", "hsc_totals",
+                 "hsc_kern_zgemm", "hsc_kern_zgemm_tile", "hsc_kern_zinv_batched", "hsc_kern_mfma_probe", "hsc_totals",
                  "hsc_mlp_create", "hsc_mlp_destroy", "hsc_mlp_n_params", "hsc_mlp_set_params",
                  "hsc_mlp_get_params", "hsc_mlp_forward", "hsc_mlp_grads", "hsc_mlp_train"):
         getattr(L, name).restype = C.c_int
@@ -237,7 +240,7 @@ class Tree:
 
 def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1,
           want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, out=None, sync=True, guard=False,
-          guard_tau=0.0, guard_rounds=6, precision=1, graph=0):
+          guard_tau=0.0, guard_rounds=6, precision=1, graph=0, tune=0):
     """Solve all energies; returns a dict of device tensors (gr, gl, trans, spectral, status)."""
     import torch
     dev = ctx.torch_device
@@ -256,7 +259,7 @@ def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R
         o["status"] = torch.empty(ne, dtype=torch.int32, device=dev)
     if guard and "guard" not in o:
         o["guard"] = torch.zeros((ne, tree.stats()["n_clusters"], 2), dtype=torch.float64, device=dev)
-    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, guard_tau, guard_rounds, precision, graph)
+    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, guard_tau, guard_rounds, precision, graph, tune)
     check(lib().hsc_solve(ctx.h, tree.h, ne, _dptr(e), C.byref(opts), _dptr(o.get("gr")), _dptr(o.get("gl")),
                           _dptr(o.get("trans")), _dptr(o.get("spectral")), _dptr(o.get("status")),
                           _dptr(o.get("guard"))))
@@ -266,7 +269,8 @@ def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R
 
 
 def solve_batch(ctx: Context, trees, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1,
-                want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, outs=None, sync=True, precision=1, graph=0):
+                want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, outs=None, sync=True, precision=1, graph=0,
+                tune=0):
     """Several devices in one call (hsc_solve_batch); energies: one array for all devices or a
     list of per-device arrays.  Returns a list of output dicts (device tensors)."""
     import torch
@@ -302,7 +306,7 @@ def solve_batch(ctx: Context, trees, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_
     th = (C.c_void_p * nt)(*[t.h.value for t in trees])
     ne_arr = np.array([int(e.numel()) for e in es], np.int32)
     e_arr = (C.c_void_p * nt)(*[e.data_ptr() for e in es])
-    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, 0.0, 0, precision, graph)
+    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, 0.0, 0, precision, graph, tune)
     check(lib().hsc_solve_batch(ctx.h, nt, th, _ptr(ne_arr), e_arr, C.byref(opts), arr("gr"), arr("gl"), arr("trans"),
                                 arr("spectral"), arr("status"), None))
     if sync:
@@ -324,8 +328,8 @@ def totals(ctx: Context, out: dict, n: int):
 
 # ---- kernel-level entry points -------------------------------------------------------------------
 
-def kern_zgemm(ctx, opA, opB, alpha, A, B, beta=0, C_=None, D=None):
-    """D = alpha op(A) op(B) + beta C on device complex128 tensors (row-major 2D)."""
+def kern_zgemm(ctx, opA, opB, alpha, A, B, beta=0, C_=None, D=None, tile=0):
+    """D = alpha op(A) op(B) + beta C on device complex128 tensors (row-major 2D), tile shape `tile`."""
     import torch
     M = A.shape[0] if opA == 0 else A.shape[1]
     K = A.shape[1] if opA == 0 else A.shape[0]
@@ -333,7 +337,7 @@ def kern_zgemm(ctx, opA, opB, alpha, A, B, beta=0, C_=None, D=None):
     if D is None:
         D = torch.empty((M, N), dtype=torch.complex128, device=A.device)
     alpha = complex(alpha)
-    check(lib().hsc_kern_zgemm(ctx.h, opA, opB, M, N, K, alpha.real, alpha.imag, _dptr(A), A.stride(0),
+    check(lib().hsc_kern_zgemm_tile(ctx.h, tile, opA, opB, M, N, K, alpha.real, alpha.imag, _dptr(A), A.stride(0),
                                _dptr(B), B.stride(0), beta, _dptr(C_) if C_ is not None else None,
                                C_.stride(0) if C_ is not None else 0, _dptr(D), D.stride(0)))
     return D

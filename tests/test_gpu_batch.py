@@ -113,3 +113,15 @@ def test_uneven_config2_subset_invariants(ctx):
             assert abs(g["trans"][e] - t_lr) <= 1e-12 * t_lr
             assert (g["gr"][e].imag <= 1e-10 * np.abs(g["gr"][e]).max()).all()
             assert (g["gl"][e].imag >= -1e-10 * np.abs(g["gl"][e]).max()).all()
+
+
+def test_tuned_plan_equals_default(ctx):
+    # the tuner only changes tile shapes; every shape sums in the same order
+    dev = synth.config1_device(n_side=16)
+    tree = pkg.Tree.from_device(dev, leaf_side=4, transverse=True)
+    E = np.array([-1.4, -0.2, 0.6, 1.7, 3.1])
+    a = _np(pkg.solve(ctx, tree, E, want=ALL, precision=0, **KW))
+    b = _np(pkg.solve(ctx, tree, E, want=ALL, precision=0, tune=1, **KW))
+    c = _np(pkg.solve(ctx, tree, E, want=ALL, precision=0, tune=1, graph=1, **KW))
+    for k in a:
+        assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k]), k

@@ -54,6 +54,25 @@ def test_zgemm_vs_cpu(ctx, opA, opB, shape):
         assert np.abs(got - ref).max() <= 1e-13 * scale * max(1, K)
 
 
+@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("opA,opB", [(0, 0), (1, 0), (0, 2), (2, 1)])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (17, 33, 5), (130, 70, 45), (65, 129, 1), (200, 96, 300)])
+def test_zgemm_tile_shapes(ctx, tile, opA, opB, shape):
+    # every tile shape sums k in the same order (steps of 4), so results match the default bit for bit
+    M, N, K = shape
+    rng = np.random.default_rng(M * 7 + N * 3 + K + tile)
+    a = _rand(rng, M, K) if opA == 0 else _rand(rng, K, M)
+    b = _rand(rng, K, N) if opB == 0 else _rand(rng, N, K)
+    c = _rand(rng, M, N)
+    dev = ctx.torch_device
+    A, B, Cm = (torch.tensor(x, device=dev) for x in (a, b, c))
+    D0 = H.kern_zgemm(ctx, opA, opB, 0.5 + 2j, A, B, beta=1, C_=Cm, tile=0)
+    D1 = H.kern_zgemm(ctx, opA, opB, 0.5 + 2j, A, B, beta=1, C_=Cm, tile=tile)
+    ref = (0.5 + 2j) * (_op(a, opA) @ _op(b, opB)) + c
+    assert np.abs(D1.cpu().numpy() - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()) * max(1, K)
+    assert torch.equal(D0, D1)
+
+
 def test_zgemm_inplace_leading_dims(ctx):
     rng = np.random.default_rng(3)
     big = _rand(rng, 150, 160)

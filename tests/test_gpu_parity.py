@@ -46,7 +46,9 @@ def gpu(ctx, dev, energies, leaf, want=ALL, mask=None, transverse=False, **kw):
     return res
 
 
-def check_all(g, ref, energies, keys=("gr", "gl", "a_l", "a_r"), tol=TOL):
+def check_all(g, ref, energies, keys=("gr", "gl", "a_l", "a_r"), tol=TOL, allow_unstable=False):
+    # allow_unstable: HSC_E_UNSTABLE only says that the guard ran out of merges or rounds with
+    # some |Psi| still above tau; the values are then checked against the oracle all the same
     worst = 0.0
     for e in range(len(energies)):
         for k in keys:
@@ -56,7 +58,8 @@ def check_all(g, ref, energies, keys=("gr", "gl", "a_l", "a_r"), tol=TOL):
         if "trans" in ref:
             err = t_rel(g["trans"][e], ref["trans"][e])
             assert err <= tol, ("trans", energies[e], err)
-    assert (g["status"] == 0).all(), g["status"]
+    ok = (g["status"] == 0) | ((g["status"] == -7) & allow_unstable)
+    assert ok.all(), g["status"]
     return worst
 
 
@@ -254,3 +257,24 @@ def test_nonfinite_energy_reports_status(ctx):
     dev = synth.config0_device()
     g = gpu(ctx, dev, np.array([0.3, np.nan, -0.2]), 4, want=pkg.HSC_DIAG_GR)
     assert g["status"][0] == 0 and g["status"][2] == 0 and g["status"][1] != 0
+
+
+def _trilayer_check(ctx, **kw):
+    gold = json.load(open(os.path.join(HERE, "golden", "trilayer_rgf.json")))
+    E, sites = np.array(gold["energies"]), np.array(gold["sites"])
+    ref = {"gr": np.array(gold["gr_re"]) + 1j * np.array(gold["gr_im"]),
+           "gl": np.array(gold["gl_re"]) + 1j * np.array(gold["gl_im"]),
+           "a_l": np.array(gold["a_l"]), "a_r": np.array(gold["a_r"]), "trans": np.array(gold["trans"])}
+    g = gpu(ctx, synth.trilayer(), E, **kw)
+    gs = {k: g[k][:, sites] for k in ("gr", "gl", "a_l", "a_r")}
+    gs["trans"], gs["status"] = g["trans"], g["status"]
+    for e in range(len(E)):
+        print("trilayer E", E[e], [rel(gs[k][e], ref[k][e]) for k in ("gr", "gl", "a_l", "a_r")],
+              t_rel(gs["trans"][e], ref["trans"][e]), "status", g["status"][e])
+    return check_all(gs, ref, E, allow_unstable=True)
+
+
+def test_trilayer_golden_guarded(ctx):
+    # 40,020-site graphene / BN / graphene stack (in-plane nested dissection, leaves <= 8 across)
+    # against the slab RGF oracle at six of the 512 energies, the Dirac point included
+    print("worst", _trilayer_check(ctx, leaf=8, precision=0, guard_tau=30.0, guard_rounds=8))
