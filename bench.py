@@ -42,6 +42,9 @@ def main():
                     help="fold arithmetic: 0 = complex128 as in Algorithm 1 (default), 1 = double-double")
     ap.add_argument("--leaf", type=int, default=4)
     ap.add_argument("--full-nd", action="store_true", help="also cut the transport axis (classic 3D ND)")
+    ap.add_argument("--complex3m", type=int, default=1,
+                    help="1 (default): three real products per complex multiply-add in every block product; "
+                         "0: four")
     ap.add_argument("--no-alt", action="store_true", help="skip timing the other fold precision")
     ap.add_argument("--learned-grid", action="store_true",
                     help="measure the learned energy grid instead (surrogate training + charge on 3 devices)")
@@ -77,7 +80,7 @@ def main():
     st = tree.stats()
     ctx = pkg.Context(0)
     E = torch.linspace(-6.0, 6.0, NE, dtype=torch.float64, device="cuda:0")
-    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=args.precision)
+    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=args.precision, complex3m=args.complex3m)
     want = pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS
     out = pkg.solve(ctx, tree, E, want=want, batch=args.batch, **kw)     # buffers + plan
     for _ in range(args.warmup):
@@ -99,6 +102,7 @@ def main():
     pkg.solve(ctx, tree, E, want=want, batch=args.batch, out=out, sync=True, **kw)
     prof = ctx.profile_read()
     ctx.profile(False)
+    mfma_ceiling = pkg.hsc.kern_mfma_rate(ctx)
     g = prof["gemm"]
     achieved = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
     total_ms = sum(v["ms"] for v in prof.values())
@@ -135,6 +139,18 @@ def main():
         acc = {"energies": gold["energies"], "max_rel_err": errs,
                "in_band_max": max(x for x, b in zip(errs, band) if b),
                "out_of_band_max": max(x for x, b in zip(errs, band) if not b)}
+
+    # the other complex-product form on the same tree
+    other_products = None
+    if not args.no_alt:
+        kw_p = dict(kw, complex3m=1 - args.complex3m)
+        pkg.solve(ctx, tree, E[:8], want=want, batch=args.batch, **kw_p)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        pkg.solve(ctx, tree, E, want=want, batch=args.batch, **kw_p)
+        torch.cuda.synchronize()
+        other_products = NE / (time.perf_counter() - t5)
+        note(f"other complex-product form: {other_products:.2f} energies/s")
 
     # the same solve on the classic 3D nested-dissection tree (leaves <= 8 per side)
     nd8 = None
@@ -188,6 +204,8 @@ def main():
                    "tree": "full 3D nested dissection" if args.full_nd else "transverse nested dissection",
                    "batch": args.batch or "auto", "plain_energies_per_s": plain,
                    "fold": "double-double" if args.precision == 1 else "complex128",
+                   "complex_products": "3 real products (Gauss)" if args.complex3m else "4 real products",
+                   "other_complex_products_energies_per_s": other_products,
                    "other_fold_energies_per_s": alt,
                    "nd_leaf8_tree_energies_per_s": nd8,
                    "dd_gemm_equiv_tflops": dd_rate,
@@ -200,7 +218,10 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "k_zgemm (grouped complex128 GEMM)", "achieved": achieved,
                      "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
                      "traffic": None, "launches": int(g["launches"]),
-                     "avg_launch_ms": g["ms"] / g["launches"] if g["launches"] else None},
+                     "avg_launch_ms": g["ms"] / g["launches"] if g["launches"] else None,
+                     "measured_mfma_f64_ceiling": mfma_ceiling,
+                     "real_mfma_flops_per_complex_fma": 6 if args.complex3m else 8,
+                     "frac_of_measured_ceiling": achieved / mfma_ceiling if mfma_ceiling else None},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -122,6 +122,11 @@ typedef struct {
    * of its launches and keep the fastest per launch; 0: 64x64 everywhere.
    * Results are the same either way up to the order of the sums. */
   int32_t tune;
+  /* Complex block products: 0 = four real products per complex multiply-add
+   * (Re = ArBr - AiBi, Im = ArBi + AiBr); 1 = three (Gauss: ArBr, AiBi,
+   * (Ar+Ai)(Br+Bi)), a quarter less matrix-core work with an imaginary-part
+   * error bound proportional to (|Ar| + |Ai|)(|Br| + |Bi|). */
+  int32_t complex3m;
 } hsc_solve_opts;
 
 /* Library version string. */
@@ -237,6 +242,13 @@ hsc_status hsc_totals(hsc_ctx* ctx, int32_t n_e, int64_t n, const void* diag_gr,
  * Errors: HSC_E_ARG. */
 hsc_status hsc_ctx_profile(hsc_ctx* ctx, int32_t enable);
 hsc_status hsc_ctx_profile_read(hsc_ctx* ctx, double* out, int32_t n_kinds);
+
+/* Launch-by-launch record of the timed launches since hsc_ctx_profile(ctx, 1)
+ * (after hsc_sync): out[3k] = kind (as in hsc_ctx_profile_read), out[3k+1] =
+ * algorithmic flops of the launch, out[3k+2] = its duration in ms, for the first
+ * min(count, max_launches) launches (host buffer of 3 * max_launches doubles);
+ * *count receives the number recorded (at most 4,000,000). */
+hsc_status hsc_ctx_profile_launches(hsc_ctx* ctx, int64_t max_launches, double* out, int64_t* count);
 
 #ifdef __cplusplus
 }

@@ -30,7 +30,9 @@ hsc_status hsc_kern_zgemm(hsc_ctx* ctx, int32_t opA, int32_t opB, int32_t M, int
 
 /* The same product with a chosen tile shape of the grouped GEMM kernel:
  * tile_kind 0 = 64x64x16 (the default above), 1 = 128x64x16, 2 = 64x128x16,
- * 3 = 32x32x32 (rows x columns x depth per workgroup).  HSC_E_ARG for another kind. */
+ * 3 = 32x32x32 (rows x columns x depth per workgroup); 4 = 64x64x16 and 5 = 32x32x32
+ * with three real products per complex multiply-add (see hsc_solve_opts.complex3m).
+ * HSC_E_ARG for another kind. */
 hsc_status hsc_kern_zgemm_tile(hsc_ctx* ctx, int32_t tile_kind, int32_t opA, int32_t opB, int32_t M, int32_t N,
                                int32_t K, double alpha_re, double alpha_im, const void* A, int32_t lda,
                                const void* B, int32_t ldb, int32_t beta, const void* C, int32_t ldc, void* D,
@@ -49,6 +51,12 @@ hsc_status hsc_kern_zinv_batched(hsc_ctx* ctx, int32_t count, const int32_t* n, 
  * registers of each lane to out[l*4 + r] (device, 256 doubles); register r of
  * lane l holds D[l/16 + 4r][l%16].  Used to check the lane layout the GEMM
  * kernel assumes. */
+/* The chip's achievable FP64 matrix rate: a kernel issuing only v_mfma_f64_16x16x4_f64
+ * (8 independent accumulators per wave, 4096 workgroups of 4 waves, no memory traffic but one
+ * store per lane) is timed with HIP events; *tflops (host) receives the best of three runs in
+ * TFLOP/s.  Synchronous.  Errors: HSC_E_ARG, HSC_E_OOM, HSC_E_HIP. */
+hsc_status hsc_kern_mfma_rate(hsc_ctx* ctx, double* tflops);
+
 hsc_status hsc_kern_mfma_probe(hsc_ctx* ctx, double* out);
 
 #ifdef __cplusplus

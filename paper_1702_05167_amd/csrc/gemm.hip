@@ -7,7 +7,11 @@
 // map), so uneven sizes share the chip.
 //
 // Complex product on real matrix cores, interleaved (re, im) storage:
-//   Re += Ar*Br + Ai*(-Bi),   Im += Ar*Bi + Ai*Br   (4 real MFMAs per block step).
+//   Re += Ar*Br + Ai*(-Bi),   Im += Ar*Bi + Ai*Br   (4 real MFMAs per block step),
+// or, with the three-multiplication form (Gauss):
+//   T1 += Ar*Br, T2 += Ai*Bi, T3 += (Ar+Ai)*(Br+Bi);  Re = T1 - T2, Im = T3 - T1 - T2
+// (3 real MFMAs per block step; the imaginary part's error bound grows with |A||B| rather
+// than with |Ar||Bi| + |Ai||Br|).
 // Layout of v_mfma_f64_16x16x4_f64 (one wave, 64 lanes):
 //   A 16x4: lane l holds A[l%16][l/16];  B 4x16: lane l holds B[l/16][l%16];
 //   D 16x16: lane l, register r holds D[l/16 + 4*r][l%16].
@@ -89,7 +93,7 @@ struct TileLoader {
   }
 };
 
-template <int BM, int BN, int BK, int OPA, int OPB>
+template <int BM, int BN, int BK, int OPA, int OPB, bool M3>
 __global__ __launch_bounds__(NT) void k_zgemm(const GemmProb* __restrict__ probs,
                                                 const int32_t* __restrict__ tile_prob, int total_tiles,
                                                 double alpha_re, double alpha_im, int beta) {
@@ -113,13 +117,14 @@ __global__ __launch_bounds__(NT) void k_zgemm(const GemmProb* __restrict__ probs
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wm = w >> 1, wn = w & 1;
 
-  v4d cr[MB][NB], ci[MB][NB];
+  v4d cr[MB][NB], ci[MB][NB], cs[M3 ? MB : 1][M3 ? NB : 1];   // cs: T3 of the 3-product form
 #pragma unroll
   for (int i = 0; i < MB; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       cr[i][j] = v4d{0, 0, 0, 0};
       ci[i][j] = v4d{0, 0, 0, 0};
+      if (M3) cs[i][j] = v4d{0, 0, 0, 0};
     }
 
   TileLoader<BM, BK, A_KC> la;
@@ -152,20 +157,32 @@ __global__ __launch_bounds__(NT) void k_zgemm(const GemmProb* __restrict__ probs
         b[j] = bs[k * BS + wn * WTN + j * 16 + (lane & 15)];
         nbi[j] = -b[j].y;
       }
+      if (M3) {
+        // cr = T1 (Ar Br), ci = T2 (Ai Bi), cs = T3 ((Ar + Ai)(Br + Bi))
 #pragma unroll
-      for (int i = 0; i < MB; ++i)
+        for (int i = 0; i < MB; ++i)
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].y, ci[i][j], 0, 0, 0);
-        }
+          for (int j = 0; j < NB; ++j) {
+            cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].y, ci[i][j], 0, 0, 0);
+            cs[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x + a[i].y, b[j].x + b[j].y, cs[i][j], 0, 0, 0);
+          }
+      } else {
 #pragma unroll
-      for (int i = 0; i < MB; ++i)
+        for (int i = 0; i < MB; ++i)
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, nbi[j], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].x, ci[i][j], 0, 0, 0);
-        }
+          for (int j = 0; j < NB; ++j) {
+            cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].y, ci[i][j], 0, 0, 0);
+          }
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, nbi[j], cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].x, ci[i][j], 0, 0, 0);
+          }
+      }
     }
     if (kt + 1 < nk) {
       la.template store<AS>(As[cur ^ 1], t);
@@ -184,7 +201,12 @@ __global__ __launch_bounds__(NT) void k_zgemm(const GemmProb* __restrict__ probs
         const int row = m0 + wm * WTM + i * 16 + (lane >> 4) + 4 * r;
         const int col = n0 + wn * WTN + j * 16 + (lane & 15);
         if (row < M && col < N) {
-          const double xr = cr[i][j][r], xi = ci[i][j][r];
+          double xr = cr[i][j][r], xi = ci[i][j][r];
+          if (M3) {
+            const double t1 = xr, t2 = xi;
+            xr = t1 - t2;
+            xi = cs[i][j][r] - t1 - t2;
+          }
           double2 o = make_double2(alpha_re * xr - alpha_im * xi, alpha_re * xi + alpha_im * xr);
           if (beta) {
             const double2 c = pr.C[(int64_t)row * pr.ldc + col];
@@ -196,16 +218,16 @@ __global__ __launch_bounds__(NT) void k_zgemm(const GemmProb* __restrict__ probs
       }
 }
 
-template <int BM, int BN, int BK>
+template <int BM, int BN, int BK, bool M3>
 void dispatch(hipStream_t st, int opA, int opB, const GemmProb* probs, const int32_t* tile_prob,
               int total, double ar, double ai, int beta) {
   const int per = (total + 7) / 8;
   dim3 grid(per * 8), block(NT);
-#define HSC_GEMM_CASE(OA, OB)                                                                   \
-  if (opA == OA && opB == OB) {                                                                 \
-    hipLaunchKernelGGL((k_zgemm<BM, BN, BK, OA, OB>), grid, block, 0, st, probs, tile_prob, total, \
-                       ar, ai, beta);                                                           \
-    return;                                                                                     \
+#define HSC_GEMM_CASE(OA, OB)                                                                       \
+  if (opA == OA && opB == OB) {                                                                     \
+    hipLaunchKernelGGL((k_zgemm<BM, BN, BK, OA, OB, M3>), grid, block, 0, st, probs, tile_prob, total, \
+                       ar, ai, beta);                                                               \
+    return;                                                                                         \
   }
   HSC_GEMM_CASE(OP_N, OP_N)
   HSC_GEMM_CASE(OP_N, OP_T)
@@ -228,24 +250,49 @@ __global__ void k_mfma_probe(double* out) {
   for (int r = 0; r < 4; ++r) out[l * 4 + r] = c[r];
 }
 
+// MFMA-only stream: 8 independent v_mfma_f64_16x16x4_f64 accumulators per wave, no memory
+// traffic but one store per lane at the end (the achievable FP64 matrix rate of the chip)
+__global__ __launch_bounds__(256) void k_mfma_rate(double* out, int iters) {
+  v4d c[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) c[i] = v4d{0, 0, 0, 0};
+  const double a = 1.0 + threadIdx.x * 1e-9, b = 1e-3;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) c[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c[i], 0, 0, 0);
+  }
+  double s = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) s += c[i][0] + c[i][1] + c[i][2] + c[i][3];
+  out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
 }  // namespace
 
-// tile shapes (BM x BN x BK) the launcher offers; 4 waves in a 2 x 2 grid over the tile
-static const int kTileM[] = {64, 128, 64, 32};
-static const int kTileN[] = {64, 64, 128, 32};
+void launch_mfma_rate(hipStream_t st, double* out, int blocks, int iters) {
+  hipLaunchKernelGGL(k_mfma_rate, dim3(blocks), dim3(256), 0, st, out, iters);
+}
 
-int gemm_tile_kinds() { return 4; }
+// tile shapes (BM x BN x BK) the launcher offers; 4 waves in a 2 x 2 grid over the tile
+static const int kTileM[] = {64, 128, 64, 32, 64, 32};
+static const int kTileN[] = {64, 64, 128, 32, 64, 32};
+
+int gemm_tile_kinds() { return 6; }
 int gemm_tile_m(int kind) { return kTileM[kind]; }
 int gemm_tile_n(int kind) { return kTileN[kind]; }
 
+// tile_kind 0-3 as above with four real products per complex block step; 4 and 5: the 64x64
+// and 32x32 tiles with the three-product form
 void launch_gemm(hipStream_t st, int opA, int opB, const GemmProb* probs, const int32_t* tile_prob,
                  int total_tiles, double alpha_re, double alpha_im, int beta, int tile_kind) {
   if (total_tiles <= 0) return;
   switch (tile_kind) {
-    case 1: dispatch<128, 64, 16>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta); break;
-    case 2: dispatch<64, 128, 16>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta); break;
-    case 3: dispatch<32, 32, 32>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta); break;
-    default: dispatch<64, 64, 16>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta); break;
+    case 1: dispatch<128, 64, 16, false>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta); break;
+    case 2: dispatch<64, 128, 16, false>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta); break;
+    case 3: dispatch<32, 32, 32, false>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta); break;
+    case 4: dispatch<64, 64, 16, true>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta); break;
+    case 5: dispatch<32, 32, 32, true>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta); break;
+    default: dispatch<64, 64, 16, false>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta); break;
   }
 }
 

@@ -167,6 +167,7 @@ void launch_dd_inv_unscramble(hipStream_t st, const InvJobDD* jobs, int njobs, i
 int dd_inv_nb(int max_n);
 
 // debug / unit-test helpers
+void launch_mfma_rate(hipStream_t st, double* out, int blocks, int iters);
 void launch_mfma_probe(hipStream_t st, double* out);
 
 }  // namespace hsc

@@ -57,7 +57,8 @@ struct Blob {
 enum StepKind { S_ASSEMBLE, S_INV_PANEL, S_INV_SWAP, S_INV_UNSCR, S_GEMM, S_GATHER, S_ASSEMBLE_N, S_DIAG, S_GUARD,
                 S_DD_ASSEMBLE, S_DD_INV_PANEL, S_DD_INV_SWAP, S_DD_INV_UNSCR, S_DD_GEMM };
 
-constexpr int kTileKinds = 4;   // GEMM tile shapes offered by launch_gemm
+constexpr int kTileKinds = 4;   // GEMM tile shapes offered by launch_gemm (kinds 4, 5: shapes 0, 3 in the
+                                  // three-product form)
 
 struct Step {
   StepKind kind;
@@ -95,6 +96,7 @@ struct Plan {
   uint32_t want = 0;
   int prec = 0;
   int tune = 0;
+  int m3 = 0;                    // complex products in the three-multiplication form
   int64_t n = 0;
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -133,6 +135,7 @@ struct hsc_ctx {
   size_t ev_used = 0;
   double prof[16][3] = {};                        // kind -> launches, ms, flops (16 >= number of kinds)
   hipStream_t cap_stream = nullptr;               // graph capture (a stream of its own, default priority)
+  std::vector<double> launch_log;                 // (kind, flops, ms) per timed launch since profiling was enabled
   // forest of the last multi-device batch and its output staging
   std::vector<uint64_t> forest_key;
   hsc_tree* forest = nullptr;
@@ -917,10 +920,18 @@ hsc_status fold_events(hsc_ctx* ctx) {
     ctx->prof[kind][0] += 1;
     ctx->prof[kind][1] += ms;
     ctx->prof[kind][2] += ctx->ev_meta[k].second;
+    if (ctx->launch_log.size() < 3 * (size_t)4000000) {
+      ctx->launch_log.push_back(kind);
+      ctx->launch_log.push_back(ctx->ev_meta[k].second);
+      ctx->launch_log.push_back(ms);
+    }
   }
   ctx->ev_used = 0;
   return HSC_OK;
 }
+
+// launch_gemm kind for a tile shape under the plan's complex-product form
+int launch_kind(const Plan* pl, int shape) { return pl->m3 ? (shape == 3 ? 5 : 4) : shape; }
 
 bool step_empty(const Step& s) {
   switch (s.kind) {
@@ -970,7 +981,7 @@ int run_steps(hsc_ctx* ctx, hipStream_t st, Plan* pl, int e_base, int nvalid, vo
       case S_GEMM:
         launch_gemm(st, s.i0, s.i1, (const GemmProb*)(pl->blob + s.jobs_k[s.tile]),
                     reinterpret_cast<const int32_t*>(pl->blob + s.map_k[s.tile]), s.count_k[s.tile], s.ar, s.ai,
-                    s.beta, s.tile);
+                    s.beta, launch_kind(pl, s.tile));
         break;
       case S_INV_PANEL:
         launch_inv_panel(st, (const InvJob*)jobs, s.njobs, s.i0, s.i1, s.i2, pl->status);
@@ -1034,11 +1045,13 @@ hsc_status tune_plan(hsc_ctx* ctx, Plan* pl) {
     float best = 0.f;
     int best_k = 0;
     for (int k = 0; k < kTileKinds && rc == HSC_OK; ++k) {
+      if (pl->m3 && k != 0 && k != 3) continue;   // the three-product form has the 64x64 and 32x32 shapes
       float ms = 0.f;
       for (int rep = 0; rep < 2; ++rep) {
         if (hipEventRecord(a, st) != hipSuccess) { rc = HSC_E_HIP; break; }
         launch_gemm(st, s.i0, s.i1, (const GemmProb*)(pl->blob + s.jobs_k[k]),
-                    reinterpret_cast<const int32_t*>(pl->blob + s.map_k[k]), s.count_k[k], s.ar, s.ai, s.beta, k);
+                    reinterpret_cast<const int32_t*>(pl->blob + s.map_k[k]), s.count_k[k], s.ar, s.ai, s.beta,
+                    launch_kind(pl, k));
         if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
             hipEventElapsedTime(&ms, a, b) != hipSuccess) {
           rc = HSC_E_HIP;
@@ -1059,10 +1072,10 @@ hsc_status tune_plan(hsc_ctx* ctx, Plan* pl) {
   return rc;
 }
 
-int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, int tune, Plan** out) {
+int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, int tune, int m3, Plan** out) {
   for (size_t k = 0; k < ctx->plans.size(); ++k)
     if (ctx->plans[k]->uid == t->uid && ctx->plans[k]->B == B && ctx->plans[k]->want == want &&
-        ctx->plans[k]->prec == prec && ctx->plans[k]->tune == tune) {
+        ctx->plans[k]->prec == prec && ctx->plans[k]->tune == tune && ctx->plans[k]->m3 == m3) {
       // most recently used goes last
       std::unique_ptr<Plan> p = std::move(ctx->plans[k]);
       ctx->plans.erase(ctx->plans.begin() + k);
@@ -1086,7 +1099,7 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
       return HSC_E_ARG;
     }
   std::unique_ptr<Plan> pl(new Plan());
-  pl->uid = t->uid; pl->B = B; pl->want = want; pl->n = t->n; pl->prec = prec; pl->tune = tune;
+  pl->uid = t->uid; pl->B = B; pl->want = want; pl->n = t->n; pl->prec = prec; pl->tune = tune; pl->m3 = m3;
   Builder b{t, B, want, (want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR)) != 0};
   b.ddf = prec == 1;
   b.channels();
@@ -1228,7 +1241,8 @@ static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
   B = std::min(B, n_e);
   Plan* pl = nullptr;
   if (opts->precision != 0 && opts->precision != 1) { set_error("precision must be 0 or 1"); return HSC_E_ARG; }
-  int st = build_plan(ctx, tree, B, want, opts->precision, opts->tune != 0, &pl);
+  if (opts->complex3m != 0 && opts->complex3m != 1) { set_error("complex3m must be 0 or 1"); return HSC_E_ARG; }
+  int st = build_plan(ctx, tree, B, want, opts->precision, opts->tune != 0, opts->complex3m, &pl);
   if (st != HSC_OK) return (hsc_status)st;
   const int64_t n = tree->n;
   const bool use_graph = opts->graph != 0 && !guard && !ctx->profile;
@@ -1637,6 +1651,16 @@ hsc_status hsc_ctx_profile(hsc_ctx* ctx, int32_t enable) {
   ctx->profile = enable != 0;
   ctx->ev_used = 0;
   std::memset(ctx->prof, 0, sizeof(ctx->prof));
+  ctx->launch_log.clear();
+  return HSC_OK;
+}
+
+hsc_status hsc_ctx_profile_launches(hsc_ctx* ctx, int64_t max_launches, double* out, int64_t* count) {
+  if (!ctx || !count || max_launches < 0 || (max_launches > 0 && !out)) { set_error("bad arguments"); return HSC_E_ARG; }
+  const int64_t n = (int64_t)(ctx->launch_log.size() / 3);
+  *count = n;
+  const int64_t m = std::min(n, max_launches);
+  if (m > 0) std::memcpy(out, ctx->launch_log.data(), sizeof(double) * 3 * (size_t)m);
   return HSC_OK;
 }
 
@@ -1700,6 +1724,42 @@ hsc_status hsc_kern_zgemm_tile(hsc_ctx* ctx, int32_t tile_kind, int32_t opA, int
     set_error(std::string("HIP error in hsc_kern_zgemm: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
     return HSC_E_HIP;
   }
+  return HSC_OK;
+}
+
+hsc_status hsc_kern_mfma_rate(hsc_ctx* ctx, double* tflops) {
+  if (!ctx || !tflops) { set_error("bad arguments to hsc_kern_mfma_rate"); return HSC_E_ARG; }
+  HIPCHK(hipSetDevice(ctx->device));
+  const int blocks = 4096, iters = 2048;
+  double* out = nullptr;
+  if (hipMalloc(&out, sizeof(double) * blocks * 256) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("alloc failed");
+    return HSC_E_OOM;
+  }
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  float best = 0.f;
+  for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+    e = hipEventRecord(a, ctx->stream);
+    if (e != hipSuccess) break;
+    launch_mfma_rate(ctx->stream, out, blocks, iters);
+    e = hipEventRecord(b, ctx->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (e == hipSuccess && (rep == 0 || ms < best)) best = ms;
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  (void)hipFree(out);
+  if (e != hipSuccess || !(best > 0.f)) {
+    set_error(std::string("HIP error in hsc_kern_mfma_rate: ") + hipGetErrorString(e));
+    return HSC_E_HIP;
+  }
+  const double flops = (double)blocks * 4 * iters * 8 * 2048.0;   // 4 waves, 8 MFMAs of 16x16x4x2 flops
+  *tflops = flops / (best * 1e-3) / 1e12;
   return HSC_OK;
 }
 

@@ -43,7 +43,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("eta", C.c_double), ("kT", C.c_double), ("mu_L", C.c_double), ("mu_R", C.c_double),
                 ("want", C.c_uint32), ("batch", C.c_int32), ("guard_tau", C.c_double),
                 ("guard_rounds", C.c_int32), ("precision", C.c_int32), ("graph", C.c_int32),
-                ("tune", C.c_int32)]
+                ("tune", C.c_int32), ("complex3m", C.c_int32)]
 
 
 _lib = None
@@ -73,11 +73,13 @@ def lib():
     L.hsc_sync.argtypes = [vp]
     L.hsc_ctx_profile.argtypes = [vp, i32]
     L.hsc_ctx_profile_read.argtypes = [vp, vp, i32]
+    L.hsc_ctx_profile_launches.argtypes = [vp, i64, vp, C.POINTER(i64)]
     L.hsc_kern_zgemm.argtypes = [vp, i32, i32, i32, i32, i32, dbl, dbl, vp, i32, vp, i32, i32, vp, i32, vp, i32]
     L.hsc_kern_zgemm_tile.argtypes = [vp, i32, i32, i32, i32, i32, i32, dbl, dbl, vp, i32, vp, i32, i32, vp, i32, vp,
                                       i32]
     L.hsc_kern_zinv_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
     L.hsc_kern_mfma_probe.argtypes = [vp, vp]
+    L.hsc_kern_mfma_rate.argtypes = [vp, C.POINTER(dbl)]
     L.hsc_totals.argtypes = [vp, i32, i64, vp, vp, vp, vp]
     L.hsc_mlp_create.argtypes = [vp, i32, vp, C.POINTER(vp)]
     L.hsc_mlp_destroy.argtypes = [vp]
@@ -90,8 +92,9 @@ def lib():
     for name in ("hsc_ctx_create", "hsc_ctx_destroy", "hsc_tree_build", "hsc_tree_merge", "hsc_tree_concat",
                  "hsc_tree_stats_get",
                  "hsc_tree_export", "hsc_tree_destroy", "hsc_solve", "hsc_solve_batch", "hsc_sync",
-                 "hsc_ctx_profile", "hsc_ctx_profile_read",
-                 "hsc_kern_zgemm", "hsc_kern_zgemm_tile", "hsc_kern_zinv_batched", "hsc_kern_mfma_probe", "hsc_totals",
+                 "hsc_ctx_profile", "hsc_ctx_profile_read", "hsc_ctx_profile_launches",
+                 "hsc_kern_zgemm", "hsc_kern_zgemm_tile", "hsc_kern_zinv_batched", "hsc_kern_mfma_probe",
+                 "hsc_kern_mfma_rate", "hsc_totals",
                  "hsc_mlp_create", "hsc_mlp_destroy", "hsc_mlp_n_params", "hsc_mlp_set_params",
                  "hsc_mlp_get_params", "hsc_mlp_forward", "hsc_mlp_grads", "hsc_mlp_train"):
         getattr(L, name).restype = C.c_int
@@ -144,6 +147,14 @@ class Context:
         check(lib().hsc_ctx_profile_read(self.h, _ptr(buf), k))
         return {name: dict(launches=buf[3 * i], ms=buf[3 * i + 1], flops=buf[3 * i + 2])
                 for i, name in enumerate(self.PROFILE_KINDS)}
+
+    def profile_launches(self) -> np.ndarray:
+        """[(kind, flops, ms)] of every timed launch since profile(True) (call after sync())."""
+        cnt = C.c_int64()
+        check(lib().hsc_ctx_profile_launches(self.h, 0, None, C.byref(cnt)))
+        buf = np.zeros(3 * max(int(cnt.value), 1))
+        check(lib().hsc_ctx_profile_launches(self.h, cnt.value, _ptr(buf), C.byref(cnt)))
+        return buf[:3 * int(cnt.value)].reshape(-1, 3)
 
     def close(self):
         if getattr(self, "h", None):
@@ -240,7 +251,7 @@ class Tree:
 
 def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1,
           want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, out=None, sync=True, guard=False,
-          guard_tau=0.0, guard_rounds=6, precision=1, graph=0, tune=0):
+          guard_tau=0.0, guard_rounds=6, precision=1, graph=0, tune=0, complex3m=0):
     """Solve all energies; returns a dict of device tensors (gr, gl, trans, spectral, status)."""
     import torch
     dev = ctx.torch_device
@@ -259,7 +270,7 @@ def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R
         o["status"] = torch.empty(ne, dtype=torch.int32, device=dev)
     if guard and "guard" not in o:
         o["guard"] = torch.zeros((ne, tree.stats()["n_clusters"], 2), dtype=torch.float64, device=dev)
-    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, guard_tau, guard_rounds, precision, graph, tune)
+    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, guard_tau, guard_rounds, precision, graph, tune, complex3m)
     check(lib().hsc_solve(ctx.h, tree.h, ne, _dptr(e), C.byref(opts), _dptr(o.get("gr")), _dptr(o.get("gl")),
                           _dptr(o.get("trans")), _dptr(o.get("spectral")), _dptr(o.get("status")),
                           _dptr(o.get("guard"))))
@@ -270,7 +281,7 @@ def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R
 
 def solve_batch(ctx: Context, trees, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1,
                 want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, outs=None, sync=True, precision=1, graph=0,
-                tune=0):
+                tune=0, complex3m=0):
     """Several devices in one call (hsc_solve_batch); energies: one array for all devices or a
     list of per-device arrays.  Returns a list of output dicts (device tensors)."""
     import torch
@@ -306,7 +317,7 @@ def solve_batch(ctx: Context, trees, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_
     th = (C.c_void_p * nt)(*[t.h.value for t in trees])
     ne_arr = np.array([int(e.numel()) for e in es], np.int32)
     e_arr = (C.c_void_p * nt)(*[e.data_ptr() for e in es])
-    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, 0.0, 0, precision, graph, tune)
+    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, 0.0, 0, precision, graph, tune, complex3m)
     check(lib().hsc_solve_batch(ctx.h, nt, th, _ptr(ne_arr), e_arr, C.byref(opts), arr("gr"), arr("gl"), arr("trans"),
                                 arr("spectral"), arr("status"), None))
     if sync:
@@ -363,3 +374,10 @@ def kern_mfma_probe(ctx):
     out = torch.empty(256, dtype=torch.float64, device=ctx.torch_device)
     check(lib().hsc_kern_mfma_probe(ctx.h, _dptr(out)))
     return out
+
+
+def kern_mfma_rate(ctx) -> float:
+    """Achievable FP64 matrix-core rate of the device in TFLOP/s (an MFMA-only kernel, timed)."""
+    r = C.c_double()
+    check(lib().hsc_kern_mfma_rate(ctx.h, C.byref(r)))
+    return float(r.value)
