@@ -109,9 +109,25 @@ __global__ __launch_bounds__(RB) void k_assemble(const RowJob* __restrict__ jobs
     else if (a < nL + nR) { diag_add.x -= s.sig[1].x; diag_add.y -= s.sig[1].y; }
   }
   double2* out = jb.dst + (int64_t)a * jb.ldd;
+  // children whose update has a row for a: that row and the column map, up to four in registers
+  constexpr int KMAX = 4;
+  const double2* urow[KMAX];
+  const int32_t* umap[KMAX];
+  int nu = 0;
+  for (int k = 0; k < nk && k < KMAX; ++k) {
+    const int ia = kids[k].invrel[a];
+    if (ia >= 0) {
+      urow[nu] = kids[k].U + (int64_t)ia * kids[k].ldU;
+      umap[nu++] = kids[k].invrel;
+    }
+  }
   for (int b = threadIdx.x; b < cols; b += RB) {
     double2 v = make_double2(0.0, 0.0);
-    for (int k = 0; k < nk; ++k) {
+    for (int q = 0; q < nu; ++q) {
+      const int ib = umap[q][b];
+      if (ib >= 0) v = cadd(v, urow[q][ib]);
+    }
+    for (int k = KMAX; k < nk; ++k) {
       const int ia = kids[k].invrel[a];
       if (ia < 0) continue;
       const int ib = kids[k].invrel[b];
@@ -159,9 +175,19 @@ __global__ __launch_bounds__(RB) void k_assemble_n(const RowJob* __restrict__ jo
   if (rr < r && a < nL + nR) w = channel_weight(es[jb.e], channel, a < nL ? 0 : 1);
   const double2* grow = jb.src + (int64_t)a * jb.lds;
   double2* out = jb.dst + (int64_t)rr * jb.ldd;
+  // the row of each child's update that lands on row a (same for every column): up to four
+  // children in registers, more through the general loop
+  constexpr int KMAX = 4;
+  const double2* urow[KMAX];
+  int nu = 0;
+  for (int k = 0; k < nk && k < KMAX; ++k) {
+    const int ia = kids[k].invrel[a];
+    if (ia >= 0) urow[nu++] = kids[k].U + (int64_t)ia * kids[k].ldU;
+  }
   for (int b = threadIdx.x; b < jb.cols; b += RB) {
     double2 v = make_double2(0.0, 0.0);
-    for (int k = 0; k < nk; ++k) {
+    for (int q = 0; q < nu; ++q) v = cadd(v, urow[q][b]);
+    for (int k = KMAX; k < nk; ++k) {
       const int ia = kids[k].invrel[a];
       if (ia >= 0) v = cadd(v, kids[k].U[(int64_t)ia * kids[k].ldU + b]);
     }
