@@ -57,8 +57,9 @@ struct Blob {
 enum StepKind { S_ASSEMBLE, S_INV_PANEL, S_INV_SWAP, S_INV_UNSCR, S_GEMM, S_GATHER, S_ASSEMBLE_N, S_DIAG, S_GUARD,
                 S_DD_ASSEMBLE, S_DD_INV_PANEL, S_DD_INV_SWAP, S_DD_INV_UNSCR, S_DD_GEMM };
 
-constexpr int kTileKinds = 4;   // GEMM tile shapes offered by launch_gemm (kinds 4, 5: shapes 0, 3 in the
-                                  // three-product form)
+// GEMM tile shapes a plan keeps maps for: 0 = 64x64, 1 = 128x64, 2 = 64x128, 3 = 32x32 (16x16x4
+// MFMA), 4 = 64x64 on the 4x4x4 MFMA; launch_kind() picks the kernel for the plan's product form
+constexpr int kTileKinds = 5;
 
 struct Step {
   StepKind kind;
@@ -931,7 +932,14 @@ hsc_status fold_events(hsc_ctx* ctx) {
 }
 
 // launch_gemm kind for a tile shape under the plan's complex-product form
-int launch_kind(const Plan* pl, int shape) { return pl->m3 ? (shape == 3 ? 5 : 4) : shape; }
+int launch_kind(const Plan* pl, int shape) {
+  switch (shape) {
+    case 0: return pl->m3 ? 4 : 0;
+    case 3: return pl->m3 ? 5 : 3;
+    case 4: return pl->m3 ? 7 : 6;
+    default: return shape;   // 1, 2: four-product form only
+  }
+}
 
 bool step_empty(const Step& s) {
   switch (s.kind) {
@@ -1045,7 +1053,7 @@ hsc_status tune_plan(hsc_ctx* ctx, Plan* pl) {
     float best = 0.f;
     int best_k = 0;
     for (int k = 0; k < kTileKinds && rc == HSC_OK; ++k) {
-      if (pl->m3 && k != 0 && k != 3) continue;   // the three-product form has the 64x64 and 32x32 shapes
+      if (pl->m3 && (k == 1 || k == 2)) continue;   // no three-product form of the 128-wide tiles
       float ms = 0.f;
       for (int rep = 0; rep < 2; ++rep) {
         if (hipEventRecord(a, st) != hipSuccess) { rc = HSC_E_HIP; break; }

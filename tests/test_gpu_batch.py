@@ -116,7 +116,8 @@ def test_uneven_config2_subset_invariants(ctx):
 
 
 def test_tuned_plan_equals_default(ctx):
-    # the tuner only changes tile shapes; every shape sums in the same order
+    # the tuner only changes tile shapes; the 16x16x4 shapes sum in the same order as the default,
+    # the 4x4x4 shape agrees to rounding
     dev = synth.config1_device(n_side=16)
     tree = pkg.Tree.from_device(dev, leaf_side=4, transverse=True)
     E = np.array([-1.4, -0.2, 0.6, 1.7, 3.1])
@@ -124,4 +125,5 @@ def test_tuned_plan_equals_default(ctx):
     b = _np(pkg.solve(ctx, tree, E, want=ALL, precision=0, tune=1, **KW))
     c = _np(pkg.solve(ctx, tree, E, want=ALL, precision=0, tune=1, graph=1, **KW))
     for k in a:
-        assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k]), k
+        for x in (b[k], c[k]):
+            assert np.allclose(x, a[k], rtol=1e-12, atol=1e-12 * np.abs(a[k]).max()), k
