@@ -118,10 +118,11 @@ typedef struct {
    * guard is on or launch timing is enabled. */
   int32_t graph;
   /* 1: when the plan for (tree, batch, outputs, precision) is first built, time
-   * every tile shape of the grouped GEMM (64x64, 128x64, 64x128, 32x32 on the
-   * 16x16x4 MFMA; 64x64 on the 4x4x4 MFMA) on each of its launches and keep the
-   * fastest per launch; 0: the default shape everywhere.  Results agree to
-   * rounding (the 4x4x4 form may round its partial sums differently). */
+   * every tile shape of the grouped GEMM (64x64, 128x64, 64x128, 32x32 and,
+   * over 8 waves, 128x128 on the 16x16x4 MFMA; 64x64 on the 4x4x4 MFMA) on each
+   * of its launches and keep the fastest per launch; 0: 64x64 everywhere.  With
+   * complex3m = 1 the candidates are the three-product kernels plus the 128x128
+   * four-product one.  Results agree to rounding. */
   int32_t tune;
   /* Complex block products: 0 = four real products per complex multiply-add
    * (Re = ArBr - AiBi, Im = ArBi + AiBr); 1 = three (Gauss: ArBr, AiBi,

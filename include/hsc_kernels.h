@@ -32,8 +32,8 @@ hsc_status hsc_kern_zgemm(hsc_ctx* ctx, int32_t opA, int32_t opB, int32_t M, int
  * tile_kind 0 = 64x64x16 (the default above), 1 = 128x64x16, 2 = 64x128x16,
  * 3 = 32x32x32 (rows x columns x depth per workgroup); 4 = 64x64x16 and 5 = 32x32x32
  * with three real products per complex multiply-add (see hsc_solve_opts.complex3m);
- * 6 and 7 = 64x64x16 built on the 4x4x4 FP64 MFMA with four and three real products.
- * HSC_E_ARG for another kind. */
+ * 6 and 7 = 64x64x16 built on the 4x4x4 FP64 MFMA with four and three real products;
+ * 8 = 128x128x16 over 8 waves (four real products).  HSC_E_ARG for another kind. */
 hsc_status hsc_kern_zgemm_tile(hsc_ctx* ctx, int32_t tile_kind, int32_t opA, int32_t opB, int32_t M, int32_t N,
                                int32_t K, double alpha_re, double alpha_im, const void* A, int32_t lda,
                                const void* B, int32_t ldb, int32_t beta, const void* C, int32_t ldc, void* D,

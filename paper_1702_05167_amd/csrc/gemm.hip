@@ -31,20 +31,20 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int NT = 256;   // 4 waves, arranged 2 x 2 over the tile
+constexpr int NT = 256;   // default: 4 waves, arranged 2 x 2 over the tile
 
 // Load the logical tile X'(r, k), r in [r0, r0+R), k in [k0, k0+KS), into
 // registers.  KCONTIG: X'(r,k) = src[r*ld + k]; otherwise X'(r,k) = src[k*ld + r].
-template <int R, int KS, bool KCONTIG>
+template <int R, int KS, bool KCONTIG, int NTH = NT>
 struct TileLoader {
-  static constexpr int PER = R * KS / NT;   // elements per thread (multiple of 4)
+  static constexpr int PER = R * KS / NTH;   // elements per thread (multiple of 4)
   static_assert(PER % 4 == 0, "tile too small");
   double2 v[PER];
 
   __device__ inline void load(const double2* __restrict__ src, int ld, int r0, int k0, int Rmax,
                               int Kmax, bool conj, int t) {
     if (KCONTIG) {
-      constexpr int TPR = KS / 4, RPP = NT / TPR;
+      constexpr int TPR = KS / 4, RPP = NTH / TPR;
 #pragma unroll
       for (int p = 0; p < PER / 4; ++p) {
         int r = r0 + p * RPP + t / TPR;
@@ -58,7 +58,7 @@ struct TileLoader {
         }
       }
     } else {
-      constexpr int TPK = R / 4, KPP = NT / TPK;
+      constexpr int TPK = R / 4, KPP = NTH / TPK;
 #pragma unroll
       for (int p = 0; p < PER / 4; ++p) {
         int k = k0 + p * KPP + t / TPK;
@@ -78,7 +78,7 @@ struct TileLoader {
   template <int RS>
   __device__ inline void store(double2* S, int t) const {
     if (KCONTIG) {
-      constexpr int TPR = KS / 4, RPP = NT / TPR;
+      constexpr int TPR = KS / 4, RPP = NTH / TPR;
 #pragma unroll
       for (int p = 0; p < PER / 4; ++p) {
         int r = p * RPP + t / TPR;
@@ -87,7 +87,7 @@ struct TileLoader {
         for (int u = 0; u < 4; ++u) S[(k + u) * RS + r] = v[p * 4 + u];
       }
     } else {
-      constexpr int TPK = R / 4, KPP = NT / TPK;
+      constexpr int TPK = R / 4, KPP = NTH / TPK;
 #pragma unroll
       for (int p = 0; p < PER / 4; ++p) {
         int k = p * KPP + t / TPK;
@@ -99,11 +99,12 @@ struct TileLoader {
   }
 };
 
-template <int BM, int BN, int BK, int OPA, int OPB, bool M3, bool MF4 = false>
-__global__ __launch_bounds__(NT) void k_zgemm(const GemmProb* __restrict__ probs,
-                                                const int32_t* __restrict__ tile_prob, int total_tiles,
-                                                double alpha_re, double alpha_im, int beta) {
-  constexpr int WTM = BM / 2, WTN = BN / 2;          // wave tile
+template <int BM, int BN, int BK, int OPA, int OPB, bool M3, bool MF4 = false, int WGM = 2, int WGN = 2>
+__global__ __launch_bounds__(64 * WGM * WGN) void k_zgemm(const GemmProb* __restrict__ probs,
+                                                         const int32_t* __restrict__ tile_prob, int total_tiles,
+                                                         double alpha_re, double alpha_im, int beta) {
+  constexpr int NTH = 64 * WGM * WGN;                // WGM x WGN waves over the tile
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;      // wave tile
   constexpr int MB = WTM / 16, NB = WTN / 16;        // 16x16 blocks per wave
   constexpr int AS = BM + 1, BS = BN + 1;            // padded LDS row strides
   constexpr bool A_KC = (OPA == OP_N);               // A'(m,k) = A[m*lda+k]
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(NT) void k_zgemm(const GemmProb* __restrict__ probs
   const int M = pr.M, N = pr.N, K = pr.K;
 
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wm = w >> 1, wn = w & 1;
+  const int wm = w / WGN, wn = w % WGN;
 
   // 16x16x4 form: v4d accumulators; 4x4x4 form: the same registers as four doubles (one per I)
   v4d cr[MB][NB], ci[MB][NB], cs[M3 ? MB : 1][M3 ? NB : 1];   // cs: T3 of the 3-product form
@@ -134,8 +135,8 @@ __global__ __launch_bounds__(NT) void k_zgemm(const GemmProb* __restrict__ probs
       if (M3) cs[i][j] = v4d{0, 0, 0, 0};
     }
 
-  TileLoader<BM, BK, A_KC> la;
-  TileLoader<BN, BK, B_KC> lb;
+  TileLoader<BM, BK, A_KC, NTH> la;
+  TileLoader<BN, BK, B_KC, NTH> lb;
   const int nk = (K + BK - 1) / BK;
   if (nk > 0) {
     la.load(pr.A, pr.lda, m0, 0, M, K, OPA == OP_C, t);
@@ -253,14 +254,14 @@ __global__ __launch_bounds__(NT) void k_zgemm(const GemmProb* __restrict__ probs
       }
 }
 
-template <int BM, int BN, int BK, bool M3, bool MF4 = false>
+template <int BM, int BN, int BK, bool M3, bool MF4 = false, int WGM = 2, int WGN = 2>
 void dispatch(hipStream_t st, int opA, int opB, const GemmProb* probs, const int32_t* tile_prob,
               int total, double ar, double ai, int beta) {
   const int per = (total + 7) / 8;
-  dim3 grid(per * 8), block(NT);
+  dim3 grid(per * 8), block(64 * WGM * WGN);
 #define HSC_GEMM_CASE(OA, OB)                                                                       \
   if (opA == OA && opB == OB) {                                                                     \
-    hipLaunchKernelGGL((k_zgemm<BM, BN, BK, OA, OB, M3, MF4>), grid, block, 0, st, probs, tile_prob, total, \
+    hipLaunchKernelGGL((k_zgemm<BM, BN, BK, OA, OB, M3, MF4, WGM, WGN>), grid, block, 0, st, probs, tile_prob, total, \
                        ar, ai, beta);                                                               \
     return;                                                                                         \
   }
@@ -309,16 +310,16 @@ void launch_mfma_rate(hipStream_t st, double* out, int blocks, int iters) {
 }
 
 // tile shapes (BM x BN x BK) the launcher offers; 4 waves in a 2 x 2 grid over the tile
-static const int kTileM[] = {64, 128, 64, 32, 64, 32, 64, 64};
-static const int kTileN[] = {64, 64, 128, 32, 64, 32, 64, 64};
+static const int kTileM[] = {64, 128, 64, 32, 64, 32, 64, 64, 128};
+static const int kTileN[] = {64, 64, 128, 32, 64, 32, 64, 64, 128};
 
-int gemm_tile_kinds() { return 8; }
+int gemm_tile_kinds() { return 9; }
 int gemm_tile_m(int kind) { return kTileM[kind]; }
 int gemm_tile_n(int kind) { return kTileN[kind]; }
 
 // tile_kind 0-3 as above with four real products per complex block step; 4 and 5: the 64x64
 // and 32x32 tiles with the three-product form; 6 and 7: the 64x64 tile on the 4x4x4 MFMA with
-// four and three real products
+// four and three real products; 8: a 128x128 tile over 8 waves (2 x 4, 64 x 32 each)
 void launch_gemm(hipStream_t st, int opA, int opB, const GemmProb* probs, const int32_t* tile_prob,
                  int total_tiles, double alpha_re, double alpha_im, int beta, int tile_kind) {
   if (total_tiles <= 0) return;
@@ -330,6 +331,7 @@ void launch_gemm(hipStream_t st, int opA, int opB, const GemmProb* probs, const 
     case 5: dispatch<32, 32, 32, true>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta); break;
     case 6: dispatch<64, 64, 16, false, true>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta); break;
     case 7: dispatch<64, 64, 16, true, true>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta); break;
+    case 8: dispatch<128, 128, 16, false, false, 2, 4>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta); break;
     default: dispatch<64, 64, 16, false>(st, opA, opB, probs, tile_prob, total_tiles, alpha_re, alpha_im, beta); break;
   }
 }

@@ -57,17 +57,19 @@ struct Blob {
 enum StepKind { S_ASSEMBLE, S_INV_PANEL, S_INV_SWAP, S_INV_UNSCR, S_GEMM, S_GATHER, S_ASSEMBLE_N, S_DIAG, S_GUARD,
                 S_DD_ASSEMBLE, S_DD_INV_PANEL, S_DD_INV_SWAP, S_DD_INV_UNSCR, S_DD_GEMM };
 
-// GEMM tile shapes a plan keeps maps for: 0 = 64x64, 1 = 128x64, 2 = 64x128, 3 = 32x32 (16x16x4
-// MFMA), 4 = 64x64 on the 4x4x4 MFMA; launch_kind() picks the kernel for the plan's product form
-constexpr int kTileKinds = 5;
+// Tile sizes a plan keeps GEMM problem lists and tile maps for: 64x64, 128x64, 64x128, 32x32,
+// 128x128.  Every launch kind of launch_gemm uses one of them (tile_dims_of).
+constexpr int kTileDims = 5;
+constexpr int kTileDimM[kTileDims] = {64, 128, 64, 32, 128};
+constexpr int kTileDimN[kTileDims] = {64, 64, 128, 32, 128};
 
 struct Step {
   StepKind kind;
   size_t jobs = 0, map = 0;   // blob offsets
   int count = 0;              // rows / tiles / jobs
-  // GEMM: problem list, tile map and tile count for every tile shape; `tile` is the one used
-  size_t jobs_k[kTileKinds] = {}, map_k[kTileKinds] = {};
-  int count_k[kTileKinds] = {};
+  // GEMM: problem list, tile map and tile count for every tile size; `tile` is the launch kind
+  size_t jobs_k[kTileDims] = {}, map_k[kTileDims] = {};
+  int count_k[kTileDims] = {};
   int tile = 0;
   int njobs = 0;
   int i0 = 0, i1 = 0, i2 = 0, i3 = 0;
@@ -373,10 +375,10 @@ struct Builder {
   void gemm(int opA, int opB, const std::vector<GP>& ps, double ar, double ai, int beta) {
     Step s;
     s.kind = S_GEMM;
-    for (int kind = 0; kind < kTileKinds; ++kind) {
+    for (int kind = 0; kind < kTileDims; ++kind) {
       std::vector<GemmProb> probs;
       std::vector<int32_t> tmap;
-      const int tm = gemm_tile_m(kind), tn = gemm_tile_n(kind);
+      const int tm = kTileDimM[kind], tn = kTileDimN[kind];
       for (const GP& g : ps) {
         if (g.M <= 0 || g.N <= 0) continue;
         GemmProb p{};
@@ -931,15 +933,21 @@ hsc_status fold_events(hsc_ctx* ctx) {
   return HSC_OK;
 }
 
-// launch_gemm kind for a tile shape under the plan's complex-product form
-int launch_kind(const Plan* pl, int shape) {
-  switch (shape) {
-    case 0: return pl->m3 ? 4 : 0;
-    case 3: return pl->m3 ? 5 : 3;
-    case 4: return pl->m3 ? 7 : 6;
-    default: return shape;   // 1, 2: four-product form only
+// tile size used by a launch kind of launch_gemm
+int tile_dims_of(int kind) {
+  switch (kind) {
+    case 1: return 1;
+    case 2: return 2;
+    case 3: case 5: return 3;
+    case 8: return 4;
+    default: return 0;   // 0, 4, 6, 7: 64x64
   }
 }
+
+// launch kinds a plan may use: the four-product kernels, or with the three-product form its
+// kernels plus the 128x128 four-product kernel (which has no three-product variant)
+const int kKinds4[] = {0, 1, 2, 3, 6, 8};
+const int kKinds3[] = {4, 5, 7, 8};
 
 bool step_empty(const Step& s) {
   switch (s.kind) {
@@ -987,9 +995,11 @@ int run_steps(hsc_ctx* ctx, hipStream_t st, Plan* pl, int e_base, int nvalid, vo
         launch_gather(st, (const RowJob*)jobs, map, s.count, s.i0, s.i1);
         break;
       case S_GEMM:
-        launch_gemm(st, s.i0, s.i1, (const GemmProb*)(pl->blob + s.jobs_k[s.tile]),
-                    reinterpret_cast<const int32_t*>(pl->blob + s.map_k[s.tile]), s.count_k[s.tile], s.ar, s.ai,
-                    s.beta, launch_kind(pl, s.tile));
+      {
+        const int d = tile_dims_of(s.tile);
+        launch_gemm(st, s.i0, s.i1, (const GemmProb*)(pl->blob + s.jobs_k[d]),
+                    reinterpret_cast<const int32_t*>(pl->blob + s.map_k[d]), s.count_k[d], s.ar, s.ai, s.beta, s.tile);
+      }
         break;
       case S_INV_PANEL:
         launch_inv_panel(st, (const InvJob*)jobs, s.njobs, s.i0, s.i1, s.i2, pl->status);
@@ -1051,22 +1061,23 @@ hsc_status tune_plan(hsc_ctx* ctx, Plan* pl) {
   for (Step& s : pl->steps) {
     if (s.kind != S_GEMM) continue;
     float best = 0.f;
-    int best_k = 0;
-    for (int k = 0; k < kTileKinds && rc == HSC_OK; ++k) {
-      if (pl->m3 && (k == 1 || k == 2)) continue;   // no three-product form of the 128-wide tiles
+    int best_k = s.tile;
+    const int* kinds = pl->m3 ? kKinds3 : kKinds4;
+    const int nkinds = pl->m3 ? (int)(sizeof(kKinds3) / sizeof(int)) : (int)(sizeof(kKinds4) / sizeof(int));
+    for (int q = 0; q < nkinds && rc == HSC_OK; ++q) {
+      const int k = kinds[q], d = tile_dims_of(k);
       float ms = 0.f;
       for (int rep = 0; rep < 2; ++rep) {
         if (hipEventRecord(a, st) != hipSuccess) { rc = HSC_E_HIP; break; }
-        launch_gemm(st, s.i0, s.i1, (const GemmProb*)(pl->blob + s.jobs_k[k]),
-                    reinterpret_cast<const int32_t*>(pl->blob + s.map_k[k]), s.count_k[k], s.ar, s.ai, s.beta,
-                    launch_kind(pl, k));
+        launch_gemm(st, s.i0, s.i1, (const GemmProb*)(pl->blob + s.jobs_k[d]),
+                    reinterpret_cast<const int32_t*>(pl->blob + s.map_k[d]), s.count_k[d], s.ar, s.ai, s.beta, k);
         if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
             hipEventElapsedTime(&ms, a, b) != hipSuccess) {
           rc = HSC_E_HIP;
           break;
         }
       }
-      if (rc == HSC_OK && (k == 0 || ms < best)) { best = ms; best_k = k; }
+      if (rc == HSC_OK && (q == 0 || ms < best)) { best = ms; best_k = k; }
     }
     if (rc != HSC_OK) break;
     s.tile = best_k;
@@ -1163,6 +1174,8 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
     pl->lp.coupling[c] = t->contact[c].coupling;
   }
   pl->steps = std::move(b.steps);
+  for (Step& s : pl->steps)
+    if (s.kind == S_GEMM) s.tile = m3 ? 4 : 0;   // default kernels: 64x64 tiles, 16x16x4 MFMA
   if (tune) {
     const hsc_status rc = tune_plan(ctx, pl.get());
     if (rc != HSC_OK) return rc;
