@@ -95,7 +95,8 @@ typedef struct {
   double kT;                 /* Fermi temperature, > 0 (same unit as E) */
   double mu_L, mu_R;         /* contact chemical potentials */
   uint32_t want;             /* HSC_* bits */
-  int32_t batch;             /* energies per launch sequence; 0 = library default */
+  int32_t batch;             /* energies per launch sequence; 0 = as many as 70 % of the free
+                              * device memory holds (at most 64), spread evenly over the batches */
   /* Growth guard.  Algorithm 1 inverts each cluster block A_ii with no
    * pivoting across clusters; a nearly singular block amplifies rounding
    * errors.  When guard_tau > 0, every energy whose non-root clusters have

@@ -1254,10 +1254,22 @@ static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
   HIPCHK(hipSetDevice(ctx->device));
   int B = opts->batch;
   if (B <= 0) {
+    // a plan already built for this tree and these options keeps its batch: recomputing it from
+    // the memory that plan now holds would shrink the batch and rebuild the plan on every call
+    for (const auto& p : ctx->plans)
+      if (p->uid == tree->uid && p->want == want && p->prec == opts->precision && p->tune == (opts->tune != 0) &&
+          p->m3 == opts->complex3m && p->B <= n_e)
+        B = std::max(B, p->B);
+  }
+  if (B <= 0) {
+    // as many slots as 70 % of the free memory holds (at most 64), then the energies spread
+    // evenly over the fewest batches that count allows (no mostly empty last batch)
     size_t freeb = 0, totalb = 0;
     HIPCHK(hipMemGetInfo(&freeb, &totalb));
     const size_t per = std::max<size_t>(1, plan_bytes_per_slot(tree, want, opts->precision));
-    B = (int)std::max<size_t>(1, std::min<size_t>(64, (size_t)(0.45 * (double)freeb) / per));
+    const int bmax = (int)std::max<size_t>(1, std::min<size_t>(64, (size_t)(0.70 * (double)freeb) / per));
+    const int chunks = (n_e + bmax - 1) / bmax;
+    B = (n_e + chunks - 1) / chunks;
   }
   B = std::min(B, n_e);
   Plan* pl = nullptr;
@@ -1610,7 +1622,7 @@ hsc_status hsc_solve_batch(hsc_ctx* ctx, int32_t n_trees, const hsc_tree* const*
       return HSC_E_ARG;
     }
   // devices go into forests in order, each forest's workspace per energy slot within
-  // 0.45/4 of the free memory (room for about four energy slots at the default batch);
+  // 0.45/4 of the free memory (room for about six energy slots at the default batch);
   // a device above that budget on its own is solved alone
   size_t freeb = 0, totalb = 0;
   HIPCHK(hipMemGetInfo(&freeb, &totalb));
