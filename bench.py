@@ -47,6 +47,9 @@ def main():
                     help="1 (default): three real products per complex multiply-add in every block product; "
                          "0: four")
     ap.add_argument("--no-alt", action="store_true", help="skip timing the other fold precision")
+    ap.add_argument("--uneven", type=int, default=0, metavar="D",
+                    help="measure D of the 64 uneven cuboids instead: forest batch vs one device at a time")
+    ap.add_argument("--uneven-energies", type=int, default=32)
     ap.add_argument("--learned-grid", action="store_true",
                     help="measure the learned energy grid instead (surrogate training + charge on 3 devices)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -65,6 +68,9 @@ def main():
 
     if args.learned_grid:
         learned_grid_study(pkg, synth, np)
+        return
+    if args.uneven > 0:
+        uneven_study(pkg, synth, np, torch, args)
         return
 
     if args.calibrate_copy > 0:
@@ -228,6 +234,45 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def uneven_study(pkg, synth, np, torch, args):
+    """The first D of the 64 uneven cuboids (sides 16..48, on-site N(0, 0.3^2)) on transverse trees,
+    the same energies (linspace(-6, 6, n)) for all: one hsc_solve_batch call (devices packed into
+    forests sharing launches) against one hsc_solve per device."""
+    D, NE = args.uneven, args.uneven_energies
+    ctx = pkg.Context(0)
+    devs = synth.config2_devices(which=range(D))
+    trees = [pkg.Tree.from_device(d, leaf_side=4, transverse=True) for d in devs]
+    E = torch.linspace(-6.0, 6.0, NE, dtype=torch.float64, device="cuda:0")
+    # no tile tuning here: with more devices than cached plans, plans are rebuilt per call
+    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=0, complex3m=args.complex3m, tune=0,
+              want=pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS)
+    flops = sum(t.stats()["flops_per_energy"] for t in trees) * NE
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    outs = [pkg.solve(ctx, t, E, **kw) for t in trees]
+    t_loop = timed(lambda: [pkg.solve(ctx, t, E, out=o, sync=False, **kw) for t, o in zip(trees, outs)])
+    note(f"one device at a time: {D * NE / t_loop:.2f} device-energies/s")
+    del outs
+    bo = pkg.solve_batch(ctx, trees, E, **kw)
+    t_batch = timed(lambda: pkg.solve_batch(ctx, trees, E, outs=bo, **kw))
+    note(f"forest batch: {D * NE / t_batch:.2f} device-energies/s")
+    ok = all(int(o["status"].abs().sum().item()) == 0 for o in bo)
+    print(json.dumps({"metric": "uneven devices: device-energies/s (diag G^r, G^<, T)", "value": D * NE / t_batch,
+                      "unit": "device-energies/s", "higher_is_better": True, "n_gpus": 1, "dtype": "c128",
+                      "data": "synthetic",
+                      "config": {"workload": f"first {D} of 64 uneven cuboids (sides 16..48) x {NE} energies",
+                                 "sides": [list(map(int, s)) for s in synth.config2_sizes()[:D]],
+                                 "one_device_at_a_time": D * NE / t_loop, "status_ok": ok,
+                                 "whole_solve_tflops": flops / t_batch / 1e12}}), flush=True)
 
 
 def learned_grid_study(pkg, synth, np):
