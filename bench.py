@@ -224,7 +224,8 @@ def main():
                    "accuracy_vs_oracle": acc,
                    "kernel_ms_per_step": {k: round(v["ms"], 3) for k, v in prof.items()},
                    "kernel_ms_total": round(total_ms, 3)},
-        "roofline": {"bound": "mfma", "kernel": "k_zgemm (grouped complex128 GEMM, all tile shapes)", "achieved": achieved,
+        "roofline": {"bound": "mfma", "kernel": "k_zgemm (grouped complex128 GEMM, all tile shapes)",
+                     "achieved": achieved,
                      "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
                      "traffic": None, "launches": int(g["launches"]),
                      "avg_launch_ms": g["ms"] / g["launches"] if g["launches"] else None,
@@ -311,7 +312,8 @@ def learned_grid_study(pkg, synth, np):
              f"uniform {r['uniform']['rel_err']:.2e} ({r['uniform']['solves']}), dense {r['dense']['solves']} solves")
     worst = max(r["guided"]["rel_err"] for r in runs)
     line = {"metric": "learned energy grid: charge error vs dense grid (32^3, sigma 0.3, 3 devices)",
-            "value": worst, "unit": "relative error", "higher_is_better": False, "n_gpus": 1, "dtype": "f32 net / c128 solve",
+            "value": worst, "unit": "relative error", "higher_is_better": False, "n_gpus": 1,
+            "dtype": "f32 net / c128 solve",
             "data": "synthetic",
             "config": {"workload": "MLP 4-256-256-2 trained on 2000 solver samples (40 cubes N 24..32); 512 of 4096 "
                                    "candidates in [-6, 6]; charge over the open lead band (-2, 2)",

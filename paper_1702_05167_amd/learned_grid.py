@@ -276,7 +276,8 @@ def study(ctx, surrogate, item, cand, K, support, budget=64, tol_rel=1e-4, kT=0.
     res["refine_added"] = int(added)
     res["uniform"] = entry(np.arange(0, cand.size, max(cand.size // K, 1)))
     res["uniform_in_support"] = entry(uniform_in(K))
-    res["sweep"] = [{"K": k, "guided": entry(guided(k))["rel_err"], "uniform_in_support": entry(uniform_in(k))["rel_err"]}
+    res["sweep"] = [{"K": k, "guided": entry(guided(k))["rel_err"],
+                     "uniform_in_support": entry(uniform_in(k))["rel_err"]}
                     for k in sweep if k < inside.size]
     res["solves_total"] = integ.solves
     return res

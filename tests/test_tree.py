@@ -20,7 +20,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_library_exports_every_declared_symbol():
     pkg.lib()
     declared = set()
-    for hdr in ("hsc.h", "hsc_kernels.h"):
+    hdrs = sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
+    assert {"hsc.h", "hsc_kernels.h", "hsc_mlp.h"} <= set(hdrs)
+    for hdr in hdrs:
         text = open(os.path.join(ROOT, "include", hdr)).read()
         declared |= set(re.findall(r"\b(hsc_[a-z_0-9]+)\s*\(", text))
     out = subprocess.run(["nm", "-D", "--defined-only", pkg.LIB_PATH], capture_output=True, text=True).stdout
