@@ -239,7 +239,9 @@ hsc_status hsc_totals(hsc_ctx* ctx, int32_t n_e, int64_t n, const void* diag_gr,
  * HIP events on the context's stream; hsc_sync() folds the elapsed times into
  * per-kind totals.  Enabling (or disabling) resets the totals.  Kinds:
  * 0 assemble, 1 inverse panel, 2 inverse swap, 3 inverse unscramble, 4 GEMM,
- * 5 gather, 6 N assembly, 7 diagonal output, 8 growth indicators.
+ * 5 gather, 6 N assembly, 7 diagonal output, 8 growth indicators, 9-13 the
+ * double-double assemble / panel / swap / unscramble / GEMM, 14 inverse
+ * super-panel preparation.
  * hsc_ctx_profile_read writes out[3*k + {0,1,2}] = launches, milliseconds,
  * algorithmic real flops (GEMM: 8 M N K per problem) for k < n_kinds.
  * Errors: HSC_E_ARG. */

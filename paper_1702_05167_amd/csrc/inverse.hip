@@ -12,6 +12,15 @@
 //   3. a grouped GEMM: X += (T - I) * R  (rank-NB update of every row).
 // Finally the column permutation (interchanges undone in reverse order) is
 // applied while copying into the output buffer.
+//
+// Two levels: panels of NB columns are grouped into super-panels of W = 4 NB.
+// Inside a super-panel the rank-NB updates touch only its W columns; the W
+// eliminations together act on every other column as X += U R with
+// U = (the super-panel columns) - I at the pivot rows and R = the W pivot
+// rows before the update (interchanges are applied to all columns at once:
+// each panel pivots only among rows not yet used, so they commute with the
+// deferred update).  One rank-W update replaces W/NB rank-NB updates and
+// reads / writes X a quarter as often.
 #include <hip/hip_runtime.h>
 
 #include "kern.h"
@@ -195,6 +204,36 @@ __global__ __launch_bounds__(256) void k_inv_swap(const InvJob* __restrict__ job
     jb.R[(int64_t)j * n + col] = in_panel ? make_double2(0.0, 0.0) : jb.X[(int64_t)(k0 + j) * jb.ld + col];
 }
 
+// After the NB-panels of a super-panel [s0, s0 + ws):
+//   U[r][c] = X[r][s0 + c] - (r == s0 + c)   (n x ws, row stride W; the T workspace)
+//   R[c][j] = X[s0 + c][j]                     (ws x n; the R workspace)
+__global__ __launch_bounds__(64) void k_inv_super_u(const InvJob* __restrict__ jobs, int s0, int W, int chunks) {
+  const InvJob jb = jobs[blockIdx.x / chunks];
+  const int n = jb.n;
+  if (s0 >= n) return;
+  const int ws = min(W, n - s0);
+  const int c = threadIdx.x;
+  const int r0 = (blockIdx.x % chunks) * 16;
+  if (c >= ws) return;
+  for (int r = r0; r < min(n, r0 + 16); ++r) {
+    double2 v = jb.X[(int64_t)r * jb.ld + s0 + c];
+    if (r == s0 + c) v.x -= 1.0;
+    jb.T[(int64_t)r * W + c] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_inv_super_r(const InvJob* __restrict__ jobs, int s0, int W, int chunks) {
+  const InvJob jb = jobs[blockIdx.x / (W * chunks)];
+  const int n = jb.n;
+  if (s0 >= n) return;
+  const int ws = min(W, n - s0);
+  const int rem = blockIdx.x % (W * chunks);
+  const int c = rem / chunks;
+  const int j = (rem % chunks) * 256 + threadIdx.x;
+  if (c >= ws || j >= n) return;
+  jb.R[(int64_t)c * n + j] = jb.X[(int64_t)(s0 + c) * jb.ld + j];
+}
+
 // Y[r][j] = X[r][idx[j]] where idx undoes the interchanges in reverse order.
 __global__ __launch_bounds__(256) void k_inv_unscramble(const InvJob* __restrict__ jobs, int rows_per_block,
                                                         int chunks) {
@@ -240,6 +279,13 @@ void launch_inv_swap(hipStream_t st, const InvJob* jobs, int njobs, int k0, int 
   if (njobs <= 0) return;
   const int chunks = (max_n + 255) / 256;
   hipLaunchKernelGGL(k_inv_swap, dim3(njobs * chunks), dim3(256), 0, st, jobs, k0, nb, chunks);
+}
+
+void launch_inv_super(hipStream_t st, const InvJob* jobs, int njobs, int s0, int W, int max_n) {
+  if (njobs <= 0 || W <= 0 || W > 64) return;
+  const int cu = (max_n + 15) / 16, cr = (max_n + 255) / 256;
+  hipLaunchKernelGGL(k_inv_super_u, dim3(njobs * cu), dim3(64), 0, st, jobs, s0, W, cu);
+  hipLaunchKernelGGL(k_inv_super_r, dim3(njobs * W * cr), dim3(256), 0, st, jobs, s0, W, cr);
 }
 
 void launch_inv_unscramble(hipStream_t st, const InvJob* jobs, int njobs, int max_n) {

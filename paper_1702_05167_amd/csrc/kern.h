@@ -48,8 +48,8 @@ struct InvJob {
   int32_t n, ld, ldy;
   int32_t e;          // energy slot (status reporting)
   int32_t* piv;       // [n] workspace
-  double2* T;         // [n][nb] workspace (panel columns minus identity)
-  double2* R;         // [nb][n] workspace (pivot rows)
+  double2* T;         // [n][W] workspace (panel / super-panel columns minus identity)
+  double2* R;         // [W][n] workspace (pivot rows)
 };
 
 // Per-energy scalars computed on the device.
@@ -123,6 +123,7 @@ void launch_inv_panel(hipStream_t st, const InvJob* jobs, int njobs, int k0, int
                       int32_t* status);
 void launch_inv_swap(hipStream_t st, const InvJob* jobs, int njobs, int k0, int nb, int max_n);
 void launch_inv_unscramble(hipStream_t st, const InvJob* jobs, int njobs, int max_n);
+void launch_inv_super(hipStream_t st, const InvJob* jobs, int njobs, int s0, int W, int max_n);
 
 // guard[(e_base + slot) * nclusters + cluster][0..1] = ||Inv||_inf, ||Psi||_inf (one block per job)
 void launch_guard(hipStream_t st, const RowJob* jobs, int njobs, int nclusters, int e_base, int nvalid,

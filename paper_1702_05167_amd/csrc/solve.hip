@@ -55,7 +55,7 @@ struct Blob {
 };
 
 enum StepKind { S_ASSEMBLE, S_INV_PANEL, S_INV_SWAP, S_INV_UNSCR, S_GEMM, S_GATHER, S_ASSEMBLE_N, S_DIAG, S_GUARD,
-                S_DD_ASSEMBLE, S_DD_INV_PANEL, S_DD_INV_SWAP, S_DD_INV_UNSCR, S_DD_GEMM };
+                S_DD_ASSEMBLE, S_DD_INV_PANEL, S_DD_INV_SWAP, S_DD_INV_UNSCR, S_DD_GEMM, S_INV_SUPER};
 
 // Tile sizes a plan keeps GEMM problem lists and tile maps for: 64x64, 128x64, 64x128, 32x32,
 // 128x128.  Every launch kind of launch_gemm uses one of them (tile_dims_of).
@@ -240,8 +240,8 @@ struct Builder {
           if (!root(i)) s.Psid = wsa(n * f * 32);
         } else {
           s.F = wsa((n + f) * (n + f) * 16);
-          s.T = wsa(n * nb * 16);
-          s.R = wsa(nb * n * 16);
+          s.T = wsa(n * 4 * nb * 16);   // panel T (n x nb) and super-panel U (n x 4 nb)
+          s.R = wsa(4 * nb * n * 16);   // pivot rows of a panel / super-panel
         }
         if (!root(i)) s.Psi = wsa(n * f * 16);
         if (root(i)) s.GX = s.Inv;
@@ -644,18 +644,35 @@ struct Builder {
           ij.push_back(j);
         }
       const size_t ijo = blob.push(ij);
-      for (int k0 = 0; k0 < maxn; k0 += nb) {
-        Step p; p.kind = S_INV_PANEL; p.jobs = ijo; p.njobs = (int)ij.size(); p.i0 = k0; p.i1 = nb; p.i2 = maxn;
-        steps.push_back(p);
-        Step w = p; w.kind = S_INV_SWAP;
-        steps.push_back(w);
-        std::vector<GP> ps;
-        for (const InvJob& j : ij) {
-          if (k0 >= j.n) continue;
-          const int kb = std::min(nb, j.n - k0);
-          ps.push_back({j.T, j.R, j.X, j.X, j.n, j.n, kb, kb, j.n, j.ld, j.ld});
+      // two-level blocked Gauss-Jordan: super-panels of 4 nb columns; inside one, the rank-nb
+      // updates are confined to its columns; then one rank-4nb update of all other columns
+      const int SW = 4 * nb;
+      for (int s0 = 0; s0 < maxn; s0 += SW) {
+        for (int k0 = s0; k0 < std::min(s0 + SW, maxn); k0 += nb) {
+          Step p; p.kind = S_INV_PANEL; p.jobs = ijo; p.njobs = (int)ij.size(); p.i0 = k0; p.i1 = nb; p.i2 = maxn;
+          steps.push_back(p);
+          Step w = p; w.kind = S_INV_SWAP;
+          steps.push_back(w);
+          std::vector<GP> ps;
+          for (const InvJob& j : ij) {
+            if (k0 >= j.n) continue;
+            const int kb = std::min(nb, j.n - k0);
+            const int ns = std::min(s0 + SW, j.n) - s0;
+            ps.push_back({j.T, j.R + s0, j.X + s0, j.X + s0, j.n, ns, kb, kb, j.n, j.ld, j.ld});
+          }
+          gemm(OP_N, OP_N, ps, 1.0, 0.0, 1);
         }
-        gemm(OP_N, OP_N, ps, 1.0, 0.0, 1);
+        Step sp; sp.kind = S_INV_SUPER; sp.jobs = ijo; sp.njobs = (int)ij.size(); sp.i0 = s0; sp.i1 = SW; sp.i2 = maxn;
+        steps.push_back(sp);
+        std::vector<GP> pt;
+        for (const InvJob& j : ij) {
+          if (s0 >= j.n) continue;
+          const int ws = std::min(SW, j.n - s0);
+          if (s0 > 0) pt.push_back({j.T, j.R, j.X, j.X, j.n, s0, ws, SW, j.n, j.ld, j.ld});
+          if (s0 + ws < j.n)
+            pt.push_back({j.T, j.R + s0 + ws, j.X + s0 + ws, j.X + s0 + ws, j.n, j.n - s0 - ws, ws, SW, j.n, j.ld, j.ld});
+        }
+        gemm(OP_N, OP_N, pt, 1.0, 0.0, 1);
       }
       Step u; u.kind = S_INV_UNSCR; u.jobs = ijo; u.njobs = (int)ij.size(); u.i2 = maxn;
       steps.push_back(u);
@@ -951,7 +968,7 @@ const int kKinds3[] = {4, 5, 7, 8};
 
 bool step_empty(const Step& s) {
   switch (s.kind) {
-    case S_INV_PANEL: case S_INV_SWAP: case S_INV_UNSCR: case S_GUARD:
+    case S_INV_PANEL: case S_INV_SWAP: case S_INV_UNSCR: case S_INV_SUPER: case S_GUARD:
     case S_DD_INV_PANEL: case S_DD_INV_SWAP: case S_DD_INV_UNSCR:
       return s.njobs <= 0;
     default:
@@ -1009,6 +1026,9 @@ int run_steps(hsc_ctx* ctx, hipStream_t st, Plan* pl, int e_base, int nvalid, vo
         break;
       case S_INV_UNSCR:
         launch_inv_unscramble(st, (const InvJob*)jobs, s.njobs, s.i2);
+        break;
+      case S_INV_SUPER:
+        launch_inv_super(st, (const InvJob*)jobs, s.njobs, s.i0, s.i1, s.i2);
         break;
       case S_GUARD:
         launch_guard(st, (const RowJob*)jobs, s.njobs, nclusters, e_base, nvalid, guard);
