@@ -278,3 +278,14 @@ def test_trilayer_golden_guarded(ctx):
     # 40,020-site graphene / BN / graphene stack (in-plane nested dissection, leaves <= 8 across)
     # against the slab RGF oracle at six of the 512 energies, the Dirac point included
     print("worst", _trilayer_check(ctx, leaf=8, precision=0, guard_tau=30.0, guard_rounds=8))
+
+
+@pytest.mark.parametrize("side", [12, 13])
+def test_large_single_block_against_dense(ctx, side):
+    # one cluster of 1728 / 2197 sites: the block inverse runs with 8- / 4-column panels
+    # (super-panels of 32 / 16 columns)
+    dev = synth.cuboid(side, side, side, onsite=np.random.default_rng(side).uniform(-0.5, 0.5, side ** 3))
+    E = np.array([-1.1, 0.35])
+    g = gpu(ctx, dev, E, side, precision=0)
+    assert pkg.Tree.from_device(dev, leaf_side=side).stats()["n_clusters"] == 1
+    print("worst", check_all(g, oracle.dense.solve(dev, E, **KW), E))
