@@ -150,12 +150,27 @@ __global__ __launch_bounds__(RB) void k_gather(const RowJob* __restrict__ jobs, 
   const RowJob& jb = jobs[row_job[g]];
   const int r = g - jb.row_off;
   const int rr = jb.rmap ? jb.rmap[r] : r;
-  double2* out = jb.dst + (int64_t)r * jb.ldd;
-  for (int c = threadIdx.x; c < jb.cols; c += RB) {
-    const int cc = jb.cmap ? jb.cmap[c] : c;
-    double2 v = TRANS ? jb.src[(int64_t)cc * jb.lds + rr] : jb.src[(int64_t)rr * jb.lds + cc];
-    if (OP == 1) v = make_double2(-v.x, v.y);
-    out[c] = v;
+  const int cols = jb.cols;
+  const int64_t lds = jb.lds;
+  const int32_t* __restrict__ cmap = jb.cmap;
+  const double2* __restrict__ src = jb.src;
+  double2* __restrict__ out = jb.dst + (int64_t)r * jb.ldd;
+  // four columns per thread and step: four independent loads in flight
+  for (int c0 = threadIdx.x; c0 < cols; c0 += 4 * RB) {
+    double2 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = c0 + u * RB;
+      if (c < cols) {
+        const int cc = cmap ? cmap[c] : c;
+        v[u] = TRANS ? src[(int64_t)cc * lds + rr] : src[(int64_t)rr * lds + cc];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = c0 + u * RB;
+      if (c < cols) out[c] = OP == 1 ? make_double2(-v[u].x, v[u].y) : v[u];
+    }
   }
 }
 
@@ -184,7 +199,31 @@ __global__ __launch_bounds__(RB) void k_assemble_n(const RowJob* __restrict__ jo
     const int ia = kids[k].invrel[a];
     if (ia >= 0) urow[nu++] = kids[k].U + (int64_t)ia * kids[k].ldU;
   }
-  for (int b = threadIdx.x; b < jb.cols; b += RB) {
+  const int cols = jb.cols;
+  if (nk <= KMAX) {
+    // four columns per thread and step, all loads issued before the stores
+    for (int b0 = threadIdx.x; b0 < cols; b0 += 4 * RB) {
+      double2 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int b = b0 + u * RB;
+        v[u] = make_double2(0.0, 0.0);
+        if (b < cols) {
+          for (int q = 0; q < nu; ++q) v[u] = cadd(v[u], urow[q][b]);
+          if (w != 0.0) {
+            const double2 gv = grow[b];
+            v[u].x += w * gv.y;
+            v[u].y += w * gv.x;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (b0 + u * RB < cols) out[b0 + u * RB] = v[u];
+    }
+    return;
+  }
+  for (int b = threadIdx.x; b < cols; b += RB) {
     double2 v = make_double2(0.0, 0.0);
     for (int q = 0; q < nu; ++q) v = cadd(v, urow[q][b]);
     for (int k = KMAX; k < nk; ++k) {
