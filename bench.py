@@ -110,7 +110,6 @@ def main():
     pkg.solve(ctx, tree, E, want=want, batch=args.batch, out=out, sync=True, **kw)
     prof = ctx.profile_read()
     ctx.profile(False)
-    mfma_ceiling = pkg.hsc.kern_mfma_rate(ctx)
     g = prof["gemm"]
     achieved = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
     total_ms = sum(v["ms"] for v in prof.values())
@@ -229,9 +228,7 @@ def main():
                      "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
                      "traffic": None, "launches": int(g["launches"]),
                      "avg_launch_ms": g["ms"] / g["launches"] if g["launches"] else None,
-                     "measured_mfma_f64_ceiling": mfma_ceiling,
-                     "real_mfma_flops_per_complex_fma": 6 if args.complex3m else 8,
-                     "frac_of_measured_ceiling": achieved / mfma_ceiling if mfma_ceiling else None},
+                     "real_mfma_flops_per_complex_fma": 6 if args.complex3m else 8},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

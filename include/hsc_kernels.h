@@ -52,10 +52,12 @@ hsc_status hsc_kern_zinv_batched(hsc_ctx* ctx, int32_t count, const int32_t* n, 
  * registers of each lane to out[l*4 + r] (device, 256 doubles); register r of
  * lane l holds D[l/16 + 4r][l%16].  Used to check the lane layout the GEMM
  * kernel assumes. */
-/* The chip's achievable FP64 matrix rate: a kernel issuing only v_mfma_f64_16x16x4_f64
- * (8 independent accumulators per wave, 4096 workgroups of 4 waves, no memory traffic but one
- * store per lane) is timed with HIP events; *tflops (host) receives the best of three runs in
- * TFLOP/s.  Synchronous.  Errors: HSC_E_ARG, HSC_E_OOM, HSC_E_HIP. */
+/* Rate of a plain FP64 MFMA stream: a kernel issuing only v_mfma_f64_16x16x4_f64 on 8
+ * independent accumulators per wave (4096 workgroups of 4 waves, no memory traffic but one store
+ * per lane) is timed with HIP events; *tflops (host) receives the best of three runs in TFLOP/s.
+ * This instruction pattern is not the chip's ceiling (a GEMM inner loop with more independent
+ * products per step issues faster); it is a repeatable reference point.  Synchronous.
+ * Errors: HSC_E_ARG, HSC_E_OOM, HSC_E_HIP. */
 hsc_status hsc_kern_mfma_rate(hsc_ctx* ctx, double* tflops);
 
 hsc_status hsc_kern_mfma_probe(hsc_ctx* ctx, double* out);
