@@ -50,6 +50,8 @@ def main():
     ap.add_argument("--uneven", type=int, default=0, metavar="D",
                     help="measure D of the 64 uneven cuboids instead: forest batch vs one device at a time")
     ap.add_argument("--uneven-energies", type=int, default=32)
+    ap.add_argument("--trilayer", action="store_true",
+                    help="measure the 40,020-site trilayer x 512 energies instead (unguarded, with its error)")
     ap.add_argument("--learned-grid", action="store_true",
                     help="measure the learned energy grid instead (surrogate training + charge on 3 devices)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -71,6 +73,9 @@ def main():
         return
     if args.uneven > 0:
         uneven_study(pkg, synth, np, torch, args)
+        return
+    if args.trilayer:
+        trilayer_study(pkg, synth, np, torch, args)
         return
 
     if args.calibrate_copy > 0:
@@ -232,6 +237,38 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def trilayer_study(pkg, synth, np, torch, args):
+    """Graphene / BN / graphene trilayer (116 x 115 x 3 sites, in-plane nested dissection, leaves <= 8
+    across), 512 energies in [-3, 3] eV, unguarded; error against the stored RGF values at 6 energies."""
+    dev = synth.trilayer()
+    tree = pkg.Tree.from_device(dev, leaf_side=8)
+    ctx = pkg.Context(0)
+    E = torch.linspace(-3.0, 3.0, 512, dtype=torch.float64, device="cuda:0")
+    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=args.precision, complex3m=args.complex3m,
+              tune=args.tune, want=pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS)
+    out = pkg.solve(ctx, tree, E, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pkg.solve(ctx, tree, E, out=out, sync=False, **kw)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "trilayer_rgf.json")))
+    sites = np.array(gold["sites"])
+    ref = np.array(gold["gr_re"]) + 1j * np.array(gold["gr_im"])
+    gr = out["gr"].cpu().numpy()
+    errs = [float(np.abs(gr[i][sites] - ref[k]).max() / np.abs(ref[k]).max())
+            for k, i in enumerate(gold["energy_index"])]
+    note(f"trilayer: {512 / dt:.1f} energies/s, max error {max(errs):.1e}")
+    print(json.dumps({"metric": "energies/s (diag G^r, G^<, T), trilayer 40,020 sites", "value": 512 / dt,
+                      "unit": "energies/s", "higher_is_better": True, "n_gpus": 1, "dtype": "c128", "data": "synthetic",
+                      "config": {"workload": "graphene/BN/graphene 116x115x3 x 512 energies in [-3, 3] eV, unguarded",
+                                 "flops_per_energy": tree.stats()["flops_per_energy"],
+                                 "gr_rel_err_at_stored_energies": errs,
+                                 "note": "the unguarded unpivoted elimination; 1e-10 needs the guard (parity tests)"}}),
+          flush=True)
 
 
 def uneven_study(pkg, synth, np, torch, args):
