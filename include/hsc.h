@@ -106,12 +106,21 @@ typedef struct {
    * HSC_E_UNSTABLE.  With guard_tau > 0 the call waits for the device. */
   double guard_tau;          /* 0 disables the guard */
   int32_t guard_rounds;      /* maximum re-planning rounds (e.g. 6) */
-  /* Arithmetic of the fold (block inverses, multipliers Psi, Schur updates):
-   * 0 = complex128 (Algorithm 1 as written, on the FP64 matrix cores);
-   * 1 = double-double (about 106-bit significands, FP64 vector units); the
-   * extracts stay complex128.  The unpivoted cluster elimination amplifies the
-   * fold's rounding errors by up to ~1/sigma_min(A_ii)^2 at energies where a
-   * cluster block is nearly singular; 1 removes that loss. */
+  /* Arithmetic of the solve:
+   * 0 = complex128 throughout (Algorithms 1 and 2 as written, on the FP64
+   *     matrix cores);
+   * 1 = double-double fold (block inverses, multipliers Psi, Schur updates in
+   *     about 106-bit significands on the FP64 vector units); the extraction
+   *     of Algorithm 2 and the lesser channels stay complex128;
+   * 2 = double-double fold and extraction: every block of G, of the lesser
+   *     channels and their products is carried in double-double and only the
+   *     returned diagonals are rounded to complex128.
+   * The unpivoted cluster elimination amplifies rounding errors by up to
+   * ~1/sigma_min(A_ii)^2 at energies where a cluster block A_ii is nearly
+   * singular (outside the lead band, where nothing broadens it): in the fold
+   * (1 removes that share) and in the extraction G_ii = A_ii^-1 + Psi G_fi, a
+   * difference of large terms (2 removes that share as well).  2 needs twice
+   * the workspace of 0 for G. */
   int32_t precision;
   /* 1: record the launch sequence of one batch of energies once as a HIP graph
    * (its outputs go to staging rows owned by the plan) and replay it for every

@@ -6,6 +6,10 @@
 // FP64 level.  Built from the classic error-free transformations:
 //   two_sum (Knuth): s + e == a + b exactly,
 //   two_prod via fused multiply-add: p + e == a * b exactly.
+// Every function body turns floating-point contraction off: hipcc contracts by
+// default, and fusing the product a * b of two_prod into the sum that follows
+// (s = p + e becomes fma(a, b, e)) counts the product's rounding error twice,
+// leaving the result only about as accurate as plain FP64.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,6 +25,7 @@ struct zdd {   // complex double-double, 32 bytes
 };
 
 __device__ __forceinline__ dd two_sum(double a, double b) {
+#pragma clang fp contract(off)
   const double s = a + b;
   const double bb = s - a;
   const double e = (a - (s - bb)) + (b - bb);
@@ -28,11 +33,13 @@ __device__ __forceinline__ dd two_sum(double a, double b) {
 }
 
 __device__ __forceinline__ dd quick_two_sum(double a, double b) {   // |a| >= |b|
+#pragma clang fp contract(off)
   const double s = a + b;
   return dd{s, b - (s - a)};
 }
 
 __device__ __forceinline__ dd two_prod(double a, double b) {
+#pragma clang fp contract(off)
   const double p = a * b;
   return dd{p, fma(a, b, -p)};
 }
@@ -40,6 +47,7 @@ __device__ __forceinline__ dd two_prod(double a, double b) {
 // sum with error bounded by ~2^-104 (|x| + |y|) (the "sloppy" double-double add):
 // absolute accuracy relative to the operands, which is what the fold needs.
 __device__ __forceinline__ dd dd_add(dd x, dd y) {
+#pragma clang fp contract(off)
   dd s = two_sum(x.hi, y.hi);
   s.lo += x.lo + y.lo;
   return quick_two_sum(s.hi, s.lo);
@@ -49,6 +57,7 @@ __device__ __forceinline__ dd dd_neg(dd x) { return dd{-x.hi, -x.lo}; }
 __device__ __forceinline__ dd dd_sub(dd x, dd y) { return dd_add(x, dd_neg(y)); }
 
 __device__ __forceinline__ dd dd_mul(dd x, dd y) {
+#pragma clang fp contract(off)
   dd p = two_prod(x.hi, y.hi);
   p.lo = fma(x.hi, y.lo, p.lo);
   p.lo = fma(x.lo, y.hi, p.lo);
@@ -59,6 +68,7 @@ __device__ __forceinline__ dd dd_from(double a) { return dd{a, 0.0}; }
 
 // x / y: two Newton corrections of the FP64 quotient
 __device__ __forceinline__ dd dd_div(dd x, dd y) {
+#pragma clang fp contract(off)
   const double q1 = x.hi / y.hi;
   dd r = dd_sub(x, dd_mul(dd_from(q1), y));
   const double q2 = r.hi / y.hi;

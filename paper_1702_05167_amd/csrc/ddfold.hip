@@ -1,9 +1,10 @@
-// The fold of Algorithm 1 in double-double: frontal assembly, blocked
-// Gauss-Jordan inversion of the pivot blocks, and the multiplier / Schur-update
-// products.  Same structure as the FP64 kernels (inverse.hip, gemm.hip,
-// kernels.hip); every value is a complex double-double (dd.h) and the products
-// run on the FP64 vector units (on this chip their peak equals the FP64 matrix
-// cores', and double-double needs the error-free fused multiply-add).
+// Algorithms 1 and 2 in double-double: frontal assembly, blocked Gauss-Jordan
+// inversion of the pivot blocks, the multiplier / Schur-update products, and the
+// row kernels of the extraction (gathers, lesser-channel seeds, diagonals).  Same
+// structure as the FP64 kernels (inverse.hip, gemm.hip, kernels.hip); every value
+// is a complex double-double (dd.h) and the products run on the FP64 vector units
+// (on this chip their peak equals the FP64 matrix cores', and double-double needs
+// the error-free fused multiply-add).
 #include <hip/hip_runtime.h>
 
 #include "dd.h"
@@ -238,10 +239,11 @@ __global__ __launch_bounds__(256) void k_dd_inv_unscramble(const InvJobDD* __res
 
 // ---------------------------------------------------------------------------------------------
 // grouped complex double-double GEMM: 32 x 32 output tile, 256 threads, 2 x 2 outputs per thread.
-//   OPA 0: A'(m,k) = A[m*lda + k];  OPA 1: A'(m,k) = A[k*lda + m];  B is never transposed.
+//   OPA 0: A'(m,k) = A[m*lda + k];  OPA 1: A'(m,k) = A[k*lda + m]
+//   OPB 0: B'(k,n) = B[k*ldb + n];  OPB 1: B'(k,n) = B[n*ldb + k]
 constexpr int DT = 32, DK = 8;
 
-template <int OPA>
+template <int OPA, int OPB>
 __global__ __launch_bounds__(256) void k_dd_gemm(const GemmProbDD* __restrict__ probs,
                                                  const int32_t* __restrict__ tile_prob, int total_tiles, int negate,
                                                  int beta) {
@@ -270,10 +272,11 @@ __global__ __launch_bounds__(256) void k_dd_gemm(const GemmProbDD* __restrict__ 
       zdd v = zdd_zero();
       if (gm < M && gk < K) v = OPA == 0 ? pr.A[(int64_t)gm * pr.lda + gk] : pr.A[(int64_t)gk * pr.lda + gm];
       As[kk][mm] = v;
-      const int bk = t / DT, bn = t % DT;
+      const int bk = OPB == 0 ? t / DT : t % DK;
+      const int bn = OPB == 0 ? t % DT : t / DK;
       const int gbk = k0 + bk, gbn = n0 + bn;
       zdd u = zdd_zero();
-      if (gbk < K && gbn < N) u = pr.B[(int64_t)gbk * pr.ldb + gbn];
+      if (gbk < K && gbn < N) u = OPB == 0 ? pr.B[(int64_t)gbk * pr.ldb + gbn] : pr.B[(int64_t)gbn * pr.ldb + gbk];
       Bs[bk][bn] = u;
     }
     __syncthreads();
@@ -302,19 +305,153 @@ __global__ __launch_bounds__(256) void k_dd_gemm(const GemmProbDD* __restrict__ 
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// extraction row kernels (Algorithm 2 and the lesser channels), as in kernels.hip
+
+// dst[r][c] = op(trans ? src[cmap[c]][rmap[r]] : src[rmap[r]][cmap[c]]);  op 1 = -conj
+template <int TRANS, int OP>
+__global__ __launch_bounds__(RB) void k_dd_gather(const RowJob* __restrict__ jobs,
+                                                  const int32_t* __restrict__ row_job) {
+  const int g = blockIdx.x;
+  const RowJob& jb = jobs[row_job[g]];
+  const int r = g - jb.row_off;
+  const int rr = jb.rmap ? jb.rmap[r] : r;
+  const int32_t* __restrict__ cmap = jb.cmap;
+  const zdd* __restrict__ src = reinterpret_cast<const zdd*>(jb.src);
+  zdd* __restrict__ out = reinterpret_cast<zdd*>(jb.dst) + (int64_t)r * jb.ldd;
+  for (int c = threadIdx.x; c < jb.cols; c += RB) {
+    const int cc = cmap ? cmap[c] : c;
+    zdd v = TRANS ? src[(int64_t)cc * jb.lds + rr] : src[(int64_t)rr * jb.lds + cc];
+    if (OP == 1) v.re = dd_neg(v.re);
+    out[c] = v;
+  }
+}
+
+// NF[rr][b] = sum_children U_k[invrel_k[a(rr)]][b] + seed(rr, b), the seed i * w * conj(G[a][b])
+// on the contact rows (argument layout of k_assemble_n)
+__global__ __launch_bounds__(RB) void k_dd_assemble_n(const RowJob* __restrict__ jobs,
+                                                      const int32_t* __restrict__ row_job,
+                                                      const EnergyScalars* __restrict__ es, int channel) {
+  const int g = blockIdx.x;
+  const RowJob& jb = jobs[row_job[g]];
+  const int rr = g - jb.row_off;
+  const ChildRef* kids = reinterpret_cast<const ChildRef*>(jb.p0);
+  const int nk = jb.aux0, r = jb.aux1, row0 = jb.aux2, n = jb.aux3, nL = jb.aux4, nR = jb.aux5;
+  const int a = rr < r ? row0 + rr : n + (rr - r);
+  double w = 0.0;
+  if (rr < r && a < nL + nR) w = channel_weight(es[jb.e], channel, a < nL ? 0 : 1);
+  const zdd* grow = reinterpret_cast<const zdd*>(jb.src) + (int64_t)a * jb.lds;
+  zdd* out = reinterpret_cast<zdd*>(jb.dst) + (int64_t)rr * jb.ldd;
+  for (int b = threadIdx.x; b < jb.cols; b += RB) {
+    zdd v = zdd_zero();
+    for (int k = 0; k < nk; ++k) {
+      const int ia = kids[k].invrel[a];
+      if (ia >= 0) v = zdd_add(v, reinterpret_cast<const zdd*>(kids[k].U)[(int64_t)ia * kids[k].ldU + b]);
+    }
+    if (w != 0.0) {
+      const zdd gv = grow[b];
+      v.re = dd_add(v.re, dd_mul(dd_from(w), gv.im));
+      v.im = dd_add(v.im, dd_mul(dd_from(w), gv.re));
+    }
+    out[b] = v;
+  }
+}
+
+__device__ __forceinline__ double shfl_xor_d(double v, int off) { return __shfl_xor(v, off, 64); }
+
+// diagonal outputs, one wave per row, rounded to complex128 at the store (modes of k_diag)
+template <int MODE>
+__global__ __launch_bounds__(RB) void k_dd_diag(const RowJob* __restrict__ jobs, const int32_t* __restrict__ row_job,
+                                                int total_rows, int out_kind, void* out, int64_t out_stride,
+                                                int e_base, int nvalid) {
+  const int g = blockIdx.x * (RB / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (g >= total_rows) return;
+  const RowJob& jb = jobs[row_job[g]];
+  const int k = g - jb.row_off;
+  if (jb.e >= nvalid) return;
+  const zdd* src = reinterpret_cast<const zdd*>(jb.src);
+  zdd v = zdd_zero();
+  if (MODE == DIAG_SEP) {
+    v = src[(int64_t)k * jb.lds + k];
+  } else {
+    const int f = jb.aux0;
+    const zdd* psi = reinterpret_cast<const zdd*>(jb.p0) + (int64_t)k * f;
+    const zdd* x = src + (int64_t)k * jb.lds;
+    zdd acc = zdd_zero();
+    for (int j = lane; j < f; j += 64) {
+      zdd y = x[j];
+      if (MODE == DIAG_LEAF_P) y.im = dd_neg(y.im);
+      acc = zdd_fma(acc, psi[j], y);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      zdd o;
+      o.re.hi = shfl_xor_d(acc.re.hi, off);
+      o.re.lo = shfl_xor_d(acc.re.lo, off);
+      o.im.hi = shfl_xor_d(acc.im.hi, off);
+      o.im.lo = shfl_xor_d(acc.im.lo, off);
+      acc = zdd_add(acc, o);
+    }
+    const zdd* base = reinterpret_cast<const zdd*>(jb.p1);
+    const zdd d = base ? base[(int64_t)k * jb.aux1 + k] : zdd_zero();
+    v = MODE == DIAG_LEAF_P ? zdd_sub(d, acc) : zdd_add(d, acc);
+  }
+  if (lane != 0) return;
+  const double2 r = zdd_round(v);
+  const int64_t site = reinterpret_cast<const int64_t*>(jb.p2)[k];
+  const int64_t idx = (int64_t)(e_base + jb.e) * out_stride + site;
+  if (out_kind == OUT_COMPLEX) reinterpret_cast<double2*>(out)[idx] = r;
+  else reinterpret_cast<double*>(out)[idx] = r.y;
+}
+
 }  // namespace
 
 int dd_gemm_tile() { return DT; }
 int dd_inv_nb(int max_n) { return max_n <= 512 ? 8 : max_n <= 1024 ? 8 : max_n <= 2048 ? 4 : 2; }
 
-void launch_dd_gemm(hipStream_t st, int opA, const GemmProbDD* probs, const int32_t* tile_prob, int total_tiles,
-                    int negate, int beta) {
+void launch_dd_gemm(hipStream_t st, int opA, int opB, const GemmProbDD* probs, const int32_t* tile_prob,
+                    int total_tiles, int negate, int beta) {
   if (total_tiles <= 0) return;
-  const int per = (total_tiles + 7) / 8;
-  if (opA == 0)
-    hipLaunchKernelGGL((k_dd_gemm<0>), dim3(per * 8), dim3(256), 0, st, probs, tile_prob, total_tiles, negate, beta);
+  const dim3 g(((total_tiles + 7) / 8) * 8), b(256);
+  if (opA == 0 && opB == 0)
+    hipLaunchKernelGGL((k_dd_gemm<0, 0>), g, b, 0, st, probs, tile_prob, total_tiles, negate, beta);
+  else if (opA == 1 && opB == 0)
+    hipLaunchKernelGGL((k_dd_gemm<1, 0>), g, b, 0, st, probs, tile_prob, total_tiles, negate, beta);
+  else if (opA == 0)
+    hipLaunchKernelGGL((k_dd_gemm<0, 1>), g, b, 0, st, probs, tile_prob, total_tiles, negate, beta);
   else
-    hipLaunchKernelGGL((k_dd_gemm<1>), dim3(per * 8), dim3(256), 0, st, probs, tile_prob, total_tiles, negate, beta);
+    hipLaunchKernelGGL((k_dd_gemm<1, 1>), g, b, 0, st, probs, tile_prob, total_tiles, negate, beta);
+}
+
+void launch_dd_gather(hipStream_t st, const RowJob* jobs, const int32_t* row_job, int total_rows, int trans, int op) {
+  if (total_rows <= 0) return;
+  const dim3 g(total_rows), b(RB);
+  if (trans == 0 && op == 0) hipLaunchKernelGGL((k_dd_gather<0, 0>), g, b, 0, st, jobs, row_job);
+  else if (trans == 1 && op == 0) hipLaunchKernelGGL((k_dd_gather<1, 0>), g, b, 0, st, jobs, row_job);
+  else if (trans == 0) hipLaunchKernelGGL((k_dd_gather<0, 1>), g, b, 0, st, jobs, row_job);
+  else hipLaunchKernelGGL((k_dd_gather<1, 1>), g, b, 0, st, jobs, row_job);
+}
+
+void launch_dd_assemble_n(hipStream_t st, const RowJob* jobs, const int32_t* row_job, int total_rows,
+                          const EnergyScalars* es, int channel) {
+  if (total_rows <= 0) return;
+  hipLaunchKernelGGL(k_dd_assemble_n, dim3(total_rows), dim3(RB), 0, st, jobs, row_job, es, channel);
+}
+
+void launch_dd_diag(hipStream_t st, const RowJob* jobs, const int32_t* row_job, int total_rows, int mode,
+                    int out_kind, void* out, int64_t out_stride, int e_base, int nvalid) {
+  if (total_rows <= 0) return;
+  const dim3 grid((total_rows + RB / 64 - 1) / (RB / 64)), block(RB);
+  if (mode == DIAG_SEP)
+    hipLaunchKernelGGL(k_dd_diag<DIAG_SEP>, grid, block, 0, st, jobs, row_job, total_rows, out_kind, out,
+                       out_stride, e_base, nvalid);
+  else if (mode == DIAG_LEAF_G)
+    hipLaunchKernelGGL(k_dd_diag<DIAG_LEAF_G>, grid, block, 0, st, jobs, row_job, total_rows, out_kind, out,
+                       out_stride, e_base, nvalid);
+  else
+    hipLaunchKernelGGL(k_dd_diag<DIAG_LEAF_P>, grid, block, 0, st, jobs, row_job, total_rows, out_kind, out,
+                       out_stride, e_base, nvalid);
 }
 
 void launch_dd_assemble(hipStream_t st, const RowJob* jobs, const int32_t* row_job, int total_rows,

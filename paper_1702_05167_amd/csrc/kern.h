@@ -60,6 +60,14 @@ struct EnergyScalars {
   double fermi[2];    // occupations
 };
 
+// weight of a contact side in a lesser-self-energy channel:
+// 0 = both contacts with occupations, 1 = left only, 2 = right only
+__device__ inline double channel_weight(const EnergyScalars& s, int channel, int side) {
+  if (channel == 0) return s.fermi[side] * s.gam[side];
+  if (channel == 1) return side == 0 ? s.gam[0] : 0.0;
+  return side == 1 ? s.gam[1] : 0.0;
+}
+
 // Child of a frontal matrix: its update block U (rows/cols = child front) and
 // invrel[a] = position of the parent's frontal index a in the child front, or -1.
 struct ChildRef {
@@ -156,8 +164,15 @@ struct GemmProbDD {
   int32_t tile_off;
 };
 int dd_gemm_tile();
-void launch_dd_gemm(hipStream_t st, int opA, const GemmProbDD* probs, const int32_t* tile_prob, int total_tiles,
-                    int negate, int beta);
+void launch_dd_gemm(hipStream_t st, int opA, int opB, const GemmProbDD* probs, const int32_t* tile_prob,
+                    int total_tiles, int negate, int beta);
+// extraction row kernels in double-double: RowJob.src / dst / p0 / p1 and ChildRef.U point to zdd;
+// same arguments as launch_gather, launch_assemble_n and launch_diag (outputs rounded to complex128)
+void launch_dd_gather(hipStream_t st, const RowJob* jobs, const int32_t* row_job, int total_rows, int trans, int op);
+void launch_dd_assemble_n(hipStream_t st, const RowJob* jobs, const int32_t* row_job, int total_rows,
+                          const EnergyScalars* es, int channel);
+void launch_dd_diag(hipStream_t st, const RowJob* jobs, const int32_t* row_job, int total_rows, int mode,
+                    int out_kind, void* out, int64_t out_stride, int e_base, int nvalid);
 // frontal assembly in double-double (RowJob.dst and ChildRef.U point to zdd)
 void launch_dd_assemble(hipStream_t st, const RowJob* jobs, const int32_t* row_job, int total_rows,
                         const EnergyScalars* es);

@@ -71,14 +71,6 @@ __global__ void k_energy_setup(const double* __restrict__ energies, int nvalid, 
   out[e] = s;
 }
 
-// weight of a contact side in a lesser-self-energy channel:
-// 0 = both contacts with occupations, 1 = left only, 2 = right only
-__device__ inline double channel_weight(const EnergyScalars& s, int channel, int side) {
-  if (channel == 0) return s.fermi[side] * s.gam[side];
-  if (channel == 1) return side == 0 ? s.gam[0] : 0.0;
-  return side == 1 ? s.gam[1] : 0.0;
-}
-
 constexpr int RB = 256;
 
 // F[a][b] = sum_children U_k[invrel_k[a]][invrel_k[b]] + (-H)[a][b] + delta_ab (z - Sigma_a)

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "dd.h"
@@ -76,6 +77,7 @@ struct Step {
   double ar = 1, ai = 0;
   int beta = 0;
   int out = 0;                // DIAG destination
+  int dd = 0;                 // row kernels: operands in double-double
   double flops = 0;           // algorithmic real flops of this launch (GEMM: 8 M N K)
 };
 
@@ -162,6 +164,7 @@ struct Builder {
   uint32_t want;
   bool gl;        // any lesser output -> full ancestor rows on contact paths
   bool ddf = false;   // double-double fold
+  bool ddx = false;   // double-double extraction as well (G, the lesser channels)
   size_t ws = 0;  // workspace bytes
   Blob blob;
   std::vector<Step> steps;
@@ -227,6 +230,7 @@ struct Builder {
       const size_t n = n_of(i), f = f_of(i), P = P_of(i);
       const Cluster& c = t->cl[i];
       const int nb = inv_nb((int)n);
+      const size_t ge = ddx ? 32 : 16;   // bytes per element of G and of the lesser channels
       for (int e = 0; e < B; ++e) {
         CS& s = cs[(size_t)i * B + e];
         s.Inv = wsa(n * n * 16);
@@ -244,14 +248,14 @@ struct Builder {
           s.R = wsa(4 * nb * n * 16);   // pivot rows of a panel / super-panel
         }
         if (!root(i)) s.Psi = wsa(n * f * 16);
-        if (root(i)) s.GX = s.Inv;
-        else if (!leaf(i)) s.GX = wsa((n + f) * gcols(i) * 16);
+        if (root(i)) s.GX = ddx ? s.Invd : s.Inv;
+        else if (!leaf(i)) s.GX = wsa((n + f) * gcols(i) * ge);
         else {
-          s.GFF = wsa(f * f * 16);
-          s.GT = wsa(n * f * 16);
+          s.GFF = wsa(f * f * ge);
+          s.GT = wsa(n * f * ge);
           if (cp(i)) {
-            s.GAF = wsa(f * P * 16);
-            s.SD = wsa((size_t)(c.n_left + c.n_right) * (n + P) * 16);
+            s.GAF = wsa(f * P * ge);
+            s.SD = wsa((size_t)(c.n_left + c.n_right) * (n + P) * ge);
           }
         }
         for (size_t k = 0; k < chans.size(); ++k) {
@@ -259,16 +263,16 @@ struct Builder {
           if (in_fold(ch, i)) {
             int row0, r;
             own_rows(ch, i, &row0, &r);
-            s.NF[k] = wsa((r + f) * (n + P) * 16);
-            if (!root(i)) s.NFc[k] = wsa(r * (n + f) * 16);
-            s.M[k] = wsa(n * (n + f) * 16);
+            s.NF[k] = wsa((r + f) * (n + P) * ge);
+            if (!root(i)) s.NFc[k] = wsa(r * (n + f) * ge);
+            s.M[k] = wsa(n * (n + f) * ge);
           }
           if (in_extract(ch, i)) {
             if (root(i)) s.PX[k] = s.M[k];
-            else if (!leaf(i)) s.PX[k] = wsa((n + f) * (n + f) * 16);
+            else if (!leaf(i)) s.PX[k] = wsa((n + f) * (n + f) * ge);
             else {
-              s.PFF[k] = wsa(f * f * 16);
-              s.PT[k] = wsa(n * f * 16);
+              s.PFF[k] = wsa(f * f * ge);
+              s.PT[k] = wsa(n * f * ge);
             }
           }
         }
@@ -371,7 +375,8 @@ struct Builder {
   }
 
   // ---- step helpers ----
-  struct GP { const double2 *A, *B, *C; double2* D; int M, N, K, lda, ldb, ldc, ldd; };
+  template <class T> struct GPT { const T *A, *B, *C; T* D; int M, N, K, lda, ldb, ldc, ldd; };
+  using GP = GPT<double2>;
   void gemm(int opA, int opB, const std::vector<GP>& ps, double ar, double ai, int beta) {
     Step s;
     s.kind = S_GEMM;
@@ -407,7 +412,7 @@ struct Builder {
   }
   // RowJob list: child-ref arrays are given as host vectors to be placed in the blob
   struct RJ { RowJob j; std::vector<ChildRef> kids; std::vector<size_t> kid_invrel; bool p1_blob = false; };
-  void rowstep(StepKind kind, std::vector<RJ>& jobs, int i0 = 0, int i1 = 0, int out = 0) {
+  void rowstep(StepKind kind, std::vector<RJ>& jobs, int i0 = 0, int i1 = 0, int out = 0, int dd = 0) {
     std::vector<int32_t> rmap;
     std::vector<size_t> kid_off(jobs.size(), 0);
     for (size_t q = 0; q < jobs.size(); ++q) {
@@ -452,7 +457,7 @@ struct Builder {
     }
     s.map = blob.push(rmap);
     s.count = (int)rmap.size();
-    s.i0 = i0; s.i1 = i1; s.out = out;
+    s.i0 = i0; s.i1 = i1; s.out = out; s.dd = dd;
     steps.push_back(s);
   }
   static const int32_t* off32(size_t o) { return reinterpret_cast<const int32_t*>(o); }
@@ -465,9 +470,21 @@ struct Builder {
 
   // ---- phases ----
   zdd* Z(size_t off) const { return reinterpret_cast<zdd*>(wsbase + off); }
+  // the extraction is written once for complex128 (T = double2) and double-double (T = zdd)
+  template <class T> static constexpr int kDD = std::is_same<T, zdd>::value ? 1 : 0;
+  template <class T> T* X(size_t off) const { return reinterpret_cast<T*>(wsbase + off); }
+  template <class T> T* inv_p(const CS& s) const { return X<T>(kDD<T> ? s.Invd : s.Inv); }
+  template <class T> T* psi_p(const CS& s) const { return X<T>(kDD<T> ? s.Psid : s.Psi); }
+  template <class T> static double2* d2(const T* p) { return reinterpret_cast<double2*>(const_cast<T*>(p)); }
+  void gemm_x(int opA, int opB, const std::vector<GP>& ps, int beta) { gemm(opA, opB, ps, 1.0, 0.0, beta); }
+  void gemm_x(int opA, int opB, const std::vector<GPT<zdd>>& ps, int beta) {
+    std::vector<GPD> q;
+    for (const GPT<zdd>& g : ps) q.push_back({g.A, g.B, g.C, g.D, nullptr, g.M, g.N, g.K, g.lda, g.ldb, g.ldc, g.ldd, 0});
+    dd_gemm(opA, opB, q, 0, beta);
+  }
 
   struct GPD { const zdd *A, *B, *C; zdd* D; double2* D64; int M, N, K, lda, ldb, ldc, ldd, ldd64; };
-  void dd_gemm(int opA, const std::vector<GPD>& ps, int negate, int beta) {
+  void dd_gemm(int opA, int opB, const std::vector<GPD>& ps, int negate, int beta) {
     std::vector<GemmProbDD> probs;
     std::vector<int32_t> tmap;
     const int tt = dd_gemm_tile();
@@ -493,6 +510,7 @@ struct Builder {
     s.count = (int)tmap.size();
     s.i0 = opA;
     s.i1 = negate;
+    s.i2 = opB;
     s.beta = beta;
     s.flops = fl;
     steps.push_back(s);
@@ -555,7 +573,7 @@ struct Builder {
           const int kb = std::min(nb, j.n - k0);
           ps.push_back({j.T, j.R, j.X, j.X, nullptr, j.n, j.n, kb, kb, j.n, j.ld, j.ld, 0});
         }
-        dd_gemm(0, ps, 0, 1);
+        dd_gemm(0, 0, ps, 0, 1);
       }
       Step u; u.kind = S_DD_INV_UNSCR; u.jobs = ijo; u.njobs = (int)ij.size(); u.i2 = maxn;
       steps.push_back(u);
@@ -570,8 +588,8 @@ struct Builder {
                         f, f, n, ld, f, ld, ld, 0});
         }
       }
-      dd_gemm(0, pp, 1, 0);
-      dd_gemm(1, pu, 0, 1);
+      dd_gemm(0, 0, pp, 1, 0);
+      dd_gemm(1, 0, pu, 0, 1);
     }
     guard_step();
   }
@@ -694,6 +712,7 @@ struct Builder {
     guard_step();
   }
 
+  template <class T>
   void diag_step(const std::vector<int>& ids, int mode, int out, int chan, bool g_phase) {
     std::vector<RJ> jobs;
     for (int i : ids)
@@ -706,32 +725,33 @@ struct Builder {
         q.j.e = e;
         q.j.p2 = reinterpret_cast<const void*>(c_sites[i]);
         if (mode == DIAG_SEP) {
-          if (g_phase) { q.j.src = W(s.GX); q.j.lds = gcols(i); }
-          else { q.j.src = W(s.PX[chan]); q.j.lds = n + f; }
+          if (g_phase) { q.j.src = d2(X<T>(s.GX)); q.j.lds = gcols(i); }
+          else { q.j.src = d2(X<T>(s.PX[chan])); q.j.lds = n + f; }
         } else if (mode == DIAG_LEAF_G) {
-          q.j.src = W(s.GT); q.j.lds = f;
-          q.j.p0 = W(s.Psi); q.j.aux0 = f;
-          q.j.p1 = W(s.Inv); q.j.aux1 = n;
+          q.j.src = d2(X<T>(s.GT)); q.j.lds = f;
+          q.j.p0 = psi_p<T>(s); q.j.aux0 = f;
+          q.j.p1 = inv_p<T>(s); q.j.aux1 = n;
         } else {
-          q.j.src = W(s.PT[chan]); q.j.lds = f;
-          q.j.p0 = W(s.Psi); q.j.aux0 = f;
-          q.j.p1 = in_fold(chans[chan], i) ? W(s.M[chan]) : nullptr;
+          q.j.src = d2(X<T>(s.PT[chan])); q.j.lds = f;
+          q.j.p0 = psi_p<T>(s); q.j.aux0 = f;
+          q.j.p1 = in_fold(chans[chan], i) ? X<T>(s.M[chan]) : nullptr;
           q.j.aux1 = n + f;
         }
         jobs.push_back(q);
       }
-    rowstep(S_DIAG, jobs, mode, 0, out);
+    rowstep(S_DIAG, jobs, mode, 0, out, kDD<T>);
   }
 
+  template <class T>
   void extract_g(const std::vector<std::vector<int>>& L) {
-    diag_step(L[0], DIAG_SEP, O_GR, 0, true);
+    diag_step<T>(L[0], DIAG_SEP, O_GR, 0, true);
     for (size_t d = 1; d < L.size(); ++d) {
       std::vector<int> seps, leaves;
       for (int i : L[d]) (leaf(i) ? leaves : seps).push_back(i);
       // separators
       {
         std::vector<RJ> g1, g2;
-        std::vector<GP> m1, m2;
+        std::vector<GPT<T>> m1, m2;
         for (int i : seps) {
           const Cluster& c = t->cl[i];
           const int n = c.n, f = c.f(), gc = gcols(i), p = c.parent;
@@ -740,31 +760,31 @@ struct Builder {
             const CS& ps = cs[(size_t)p * B + e];
             RJ q{};
             q.j.rows = f; q.j.cols = gc - n; q.j.e = e;
-            q.j.src = W(ps.GX); q.j.lds = gcols(p);
-            q.j.dst = W(s.GX) + (size_t)n * gc + n; q.j.ldd = gc;
+            q.j.src = d2(X<T>(ps.GX)); q.j.lds = gcols(p);
+            q.j.dst = d2(X<T>(s.GX) + (size_t)n * gc + n); q.j.ldd = gc;
             q.j.rmap = off32(c_rel[i]);
             q.j.cmap = cp(i) ? nullptr : off32(c_gcol[i]);
             g1.push_back(q);
-            m1.push_back({W(s.Psi), W(s.GX) + (size_t)n * gc + n, nullptr, W(s.GX) + n, n, gc - n, f, f, gc, 0, gc});
+            m1.push_back({psi_p<T>(s), X<T>(s.GX) + (size_t)n * gc + n, nullptr, X<T>(s.GX) + n, n, gc - n, f, f, gc, 0, gc});
             RJ tq{};
             tq.j.rows = f; tq.j.cols = n; tq.j.e = e;
-            tq.j.src = W(s.GX); tq.j.lds = gc;
-            tq.j.dst = W(s.GX) + (size_t)n * gc; tq.j.ldd = gc;
+            tq.j.src = d2(X<T>(s.GX)); tq.j.lds = gc;
+            tq.j.dst = d2(X<T>(s.GX) + (size_t)n * gc); tq.j.ldd = gc;
             tq.j.rmap = off32(c_trow[i]);
             g2.push_back(tq);
-            m2.push_back({W(s.Psi), W(s.GX) + (size_t)n * gc, W(s.Inv), W(s.GX), n, n, f, f, gc, n, gc});
+            m2.push_back({psi_p<T>(s), X<T>(s.GX) + (size_t)n * gc, inv_p<T>(s), X<T>(s.GX), n, n, f, f, gc, n, gc});
           }
         }
-        rowstep(S_GATHER, g1, 0, 0);
-        gemm(OP_N, OP_N, m1, 1.0, 0.0, 0);
-        rowstep(S_GATHER, g2, 1, 0);
-        gemm(OP_N, OP_N, m2, 1.0, 0.0, 1);
-        diag_step(seps, DIAG_SEP, O_GR, 0, true);
+        rowstep(S_GATHER, g1, 0, 0, 0, kDD<T>);
+        gemm_x(OP_N, OP_N, m1, 0);
+        rowstep(S_GATHER, g2, 1, 0, 0, kDD<T>);
+        gemm_x(OP_N, OP_N, m2, 1);
+        diag_step<T>(seps, DIAG_SEP, O_GR, 0, true);
       }
       // leaves
       {
         std::vector<RJ> g1, g3;
-        std::vector<GP> m1, m3, m4;
+        std::vector<GPT<T>> m1, m3, m4;
         std::vector<int> cpl;
         for (int i : leaves) {
           const Cluster& c = t->cl[i];
@@ -775,40 +795,41 @@ struct Builder {
             const CS& ps = cs[(size_t)p * B + e];
             RJ q{};
             q.j.rows = f; q.j.cols = f; q.j.e = e;
-            q.j.src = W(ps.GX); q.j.lds = gcols(p);
-            q.j.dst = W(s.GFF); q.j.ldd = f;
+            q.j.src = d2(X<T>(ps.GX)); q.j.lds = gcols(p);
+            q.j.dst = d2(X<T>(s.GFF)); q.j.ldd = f;
             q.j.rmap = off32(c_rel[i]);
             q.j.cmap = off32(c_gcol[i]);
             g1.push_back(q);
-            m1.push_back({W(s.Psi), W(s.GFF), nullptr, W(s.GT), n, f, f, f, f, 0, f});
+            m1.push_back({psi_p<T>(s), X<T>(s.GFF), nullptr, X<T>(s.GT), n, f, f, f, f, 0, f});
             if (cp(i)) {
               RJ a{};
               a.j.rows = f; a.j.cols = P; a.j.e = e;
-              a.j.src = W(ps.GX); a.j.lds = gcols(p);
-              a.j.dst = W(s.GAF); a.j.ldd = P;
+              a.j.src = d2(X<T>(ps.GX)); a.j.lds = gcols(p);
+              a.j.dst = d2(X<T>(s.GAF)); a.j.ldd = P;
               a.j.rmap = off32(c_rel[i]);
               g3.push_back(a);
-              m3.push_back({W(s.Psi), W(s.GAF), nullptr, W(s.SD) + n, nc, P, f, f, P, 0, n + P});
-              m4.push_back({W(s.Psi), W(s.GT), W(s.Inv), W(s.SD), nc, n, f, f, f, n, n + P});
+              m3.push_back({psi_p<T>(s), X<T>(s.GAF), nullptr, X<T>(s.SD) + n, nc, P, f, f, P, 0, n + P});
+              m4.push_back({psi_p<T>(s), X<T>(s.GT), inv_p<T>(s), X<T>(s.SD), nc, n, f, f, f, n, n + P});
             }
           }
         }
-        rowstep(S_GATHER, g1, 0, 0);
-        gemm(OP_N, OP_N, m1, 1.0, 0.0, 0);
-        diag_step(leaves, DIAG_LEAF_G, O_GR, 0, true);
-        rowstep(S_GATHER, g3, 0, 0);
-        gemm(OP_N, OP_N, m3, 1.0, 0.0, 0);
-        gemm(OP_N, OP_T, m4, 1.0, 0.0, 1);
+        rowstep(S_GATHER, g1, 0, 0, 0, kDD<T>);
+        gemm_x(OP_N, OP_N, m1, 0);
+        diag_step<T>(leaves, DIAG_LEAF_G, O_GR, 0, true);
+        rowstep(S_GATHER, g3, 0, 0, 0, kDD<T>);
+        gemm_x(OP_N, OP_N, m3, 0);
+        gemm_x(OP_N, OP_T, m4, 1);
       }
     }
   }
 
+  template <class T>
   void channel_steps(const std::vector<std::vector<int>>& L, int k) {
     const Channel& ch = chans[k];
     // N fold, bottom-up
     for (int d = (int)L.size() - 1; d >= 0; --d) {
       std::vector<RJ> asm_jobs, nfc_jobs;
-      std::vector<GP> nu, mm;
+      std::vector<GPT<T>> nu, mm;
       for (int i : L[d]) {
         if (!in_fold(ch, i)) continue;
         const Cluster& c = t->cl[i];
@@ -819,7 +840,7 @@ struct Builder {
           const CS& s = cs[(size_t)i * B + e];
           RJ q{};
           q.j.rows = r + f; q.j.cols = n + P; q.j.e = e;
-          q.j.dst = W(s.NF[k]); q.j.ldd = n + P;
+          q.j.dst = d2(X<T>(s.NF[k])); q.j.ldd = n + P;
           for (int kk : c.children) {
             if (!in_fold(ch, kk)) continue;
             const Cluster& kc = t->cl[kk];
@@ -828,38 +849,38 @@ struct Builder {
             own_rows(ch, kk, &kr0, &kr);
             const int ldk = kc.n + P_of(kk);
             ChildRef cr{};
-            cr.U = W(ks.NF[k]) + (size_t)kr * ldk + kc.n;
+            cr.U = d2(X<T>(ks.NF[k]) + (size_t)kr * ldk + kc.n);
             cr.ldU = ldk;
             q.kids.push_back(cr);
             q.kid_invrel.push_back(c_invrel[kk]);
           }
           q.j.aux0 = (int)q.kids.size();
           q.j.aux1 = r; q.j.aux2 = row0; q.j.aux3 = n; q.j.aux4 = c.n_left; q.j.aux5 = c.n_right;
-          if (leaf(i) && !root(i)) { q.j.src = W(s.SD); q.j.lds = n + P; }
-          else { q.j.src = W(s.GX); q.j.lds = gcols(i); }
+          if (leaf(i) && !root(i)) { q.j.src = d2(X<T>(s.SD)); q.j.lds = n + P; }
+          else { q.j.src = d2(X<T>(s.GX)); q.j.lds = gcols(i); }
           asm_jobs.push_back(q);
           if (!root(i)) {
-            nu.push_back({W(s.Psi) + (size_t)row0 * f, W(s.NF[k]) + n, W(s.NF[k]) + (size_t)r * (n + P) + n,
-                          W(s.NF[k]) + (size_t)r * (n + P) + n, f, P, r, f, n + P, n + P, n + P});
+            nu.push_back({psi_p<T>(s) + (size_t)row0 * f, X<T>(s.NF[k]) + n, X<T>(s.NF[k]) + (size_t)r * (n + P) + n,
+                          X<T>(s.NF[k]) + (size_t)r * (n + P) + n, f, P, r, f, n + P, n + P, n + P});
             RJ g{};
             g.j.rows = r; g.j.cols = n + f; g.j.e = e;
-            g.j.src = W(s.NF[k]); g.j.lds = n + P;
-            g.j.dst = W(s.NFc[k]); g.j.ldd = n + f;
+            g.j.src = d2(X<T>(s.NF[k])); g.j.lds = n + P;
+            g.j.dst = d2(X<T>(s.NFc[k])); g.j.ldd = n + f;
             g.j.cmap = off32(c_nfc[i]);
             nfc_jobs.push_back(g);
-            mm.push_back({W(s.Inv) + row0, W(s.NFc[k]), nullptr, W(s.M[k]), n, n + f, r, n, n + f, 0, n + f});
+            mm.push_back({inv_p<T>(s) + row0, X<T>(s.NFc[k]), nullptr, X<T>(s.M[k]), n, n + f, r, n, n + f, 0, n + f});
           } else {
-            mm.push_back({W(s.Inv) + row0, W(s.NF[k]), nullptr, W(s.M[k]), n, n, r, n, n, 0, n});
+            mm.push_back({inv_p<T>(s) + row0, X<T>(s.NF[k]), nullptr, X<T>(s.M[k]), n, n, r, n, n, 0, n});
           }
         }
       }
-      rowstep(S_ASSEMBLE_N, asm_jobs, ch.type);
-      gemm(OP_T, OP_N, nu, 1.0, 0.0, 1);
-      rowstep(S_GATHER, nfc_jobs, 0, 0);
-      gemm(OP_N, OP_N, mm, 1.0, 0.0, 0);
+      rowstep(S_ASSEMBLE_N, asm_jobs, ch.type, 0, 0, kDD<T>);
+      gemm_x(OP_T, OP_N, nu, 1);
+      rowstep(S_GATHER, nfc_jobs, 0, 0, 0, kDD<T>);
+      gemm_x(OP_N, OP_N, mm, 0);
     }
     // P extract, top-down
-    diag_step(L[0], DIAG_SEP, ch.out, k, false);
+    diag_step<T>(L[0], DIAG_SEP, ch.out, k, false);
     for (size_t d = 1; d < L.size(); ++d) {
       std::vector<int> seps, leaves;
       for (int i : L[d]) {
@@ -867,7 +888,7 @@ struct Builder {
         (leaf(i) ? leaves : seps).push_back(i);
       }
       std::vector<RJ> g1, g2, g3;
-      std::vector<GP> m1a, m1b, m2a, m2b, m3a, m3b;
+      std::vector<GPT<T>> m1a, m1b, m2a, m2b, m3a, m3b;
       for (int i : seps) {
         const Cluster& c = t->cl[i];
         const int n = c.n, f = c.f(), ld = n + f, p = c.parent;
@@ -877,20 +898,20 @@ struct Builder {
           const CS& ps = cs[(size_t)p * B + e];
           RJ q{};
           q.j.rows = f; q.j.cols = f; q.j.e = e;
-          q.j.src = W(ps.PX[k]); q.j.lds = n_of(p) + f_of(p);
-          q.j.dst = W(s.PX[k]) + (size_t)n * ld + n; q.j.ldd = ld;
+          q.j.src = d2(X<T>(ps.PX[k])); q.j.lds = n_of(p) + f_of(p);
+          q.j.dst = d2(X<T>(s.PX[k]) + (size_t)n * ld + n); q.j.ldd = ld;
           q.j.rmap = off32(c_rel[i]); q.j.cmap = off32(c_rel[i]);
           g1.push_back(q);
-          GP a{W(s.Psi), W(s.PX[k]) + (size_t)n * ld + n, fm ? W(s.M[k]) + n : nullptr, W(s.PX[k]) + n, n, f, f, f,
+          GPT<T> a{psi_p<T>(s), X<T>(s.PX[k]) + (size_t)n * ld + n, fm ? X<T>(s.M[k]) + n : nullptr, X<T>(s.PX[k]) + n, n, f, f, f,
                ld, ld, ld};
           (fm ? m1b : m1a).push_back(a);
           RJ tq{};
           tq.j.rows = f; tq.j.cols = n; tq.j.e = e;
-          tq.j.src = W(s.PX[k]); tq.j.lds = ld;
-          tq.j.dst = W(s.PX[k]) + (size_t)n * ld; tq.j.ldd = ld;
+          tq.j.src = d2(X<T>(s.PX[k])); tq.j.lds = ld;
+          tq.j.dst = d2(X<T>(s.PX[k]) + (size_t)n * ld); tq.j.ldd = ld;
           tq.j.rmap = off32(c_trowp[i]);
           g2.push_back(tq);
-          GP b{W(s.Psi), W(s.PX[k]) + (size_t)n * ld, fm ? W(s.M[k]) : nullptr, W(s.PX[k]), n, n, f, f, ld, ld, ld};
+          GPT<T> b{psi_p<T>(s), X<T>(s.PX[k]) + (size_t)n * ld, fm ? X<T>(s.M[k]) : nullptr, X<T>(s.PX[k]), n, n, f, f, ld, ld, ld};
           (fm ? m2b : m2a).push_back(b);
         }
       }
@@ -903,25 +924,25 @@ struct Builder {
           const CS& ps = cs[(size_t)p * B + e];
           RJ q{};
           q.j.rows = f; q.j.cols = f; q.j.e = e;
-          q.j.src = W(ps.PX[k]); q.j.lds = n_of(p) + f_of(p);
-          q.j.dst = W(s.PFF[k]); q.j.ldd = f;
+          q.j.src = d2(X<T>(ps.PX[k])); q.j.lds = n_of(p) + f_of(p);
+          q.j.dst = d2(X<T>(s.PFF[k])); q.j.ldd = f;
           q.j.rmap = off32(c_rel[i]); q.j.cmap = off32(c_rel[i]);
           g3.push_back(q);
-          GP a{W(s.Psi), W(s.PFF[k]), fm ? W(s.M[k]) + n : nullptr, W(s.PT[k]), n, f, f, f, f, n + f, f};
+          GPT<T> a{psi_p<T>(s), X<T>(s.PFF[k]), fm ? X<T>(s.M[k]) + n : nullptr, X<T>(s.PT[k]), n, f, f, f, f, n + f, f};
           (fm ? m3b : m3a).push_back(a);
         }
       }
-      rowstep(S_GATHER, g1, 0, 0);
-      rowstep(S_GATHER, g3, 0, 0);
-      gemm(OP_N, OP_N, m1a, 1.0, 0.0, 0);
-      gemm(OP_N, OP_N, m1b, 1.0, 0.0, 1);
-      gemm(OP_N, OP_N, m3a, 1.0, 0.0, 0);
-      gemm(OP_N, OP_N, m3b, 1.0, 0.0, 1);
-      rowstep(S_GATHER, g2, 1, 1);
-      gemm(OP_N, OP_N, m2a, 1.0, 0.0, 0);
-      gemm(OP_N, OP_N, m2b, 1.0, 0.0, 1);
-      diag_step(seps, DIAG_SEP, ch.out, k, false);
-      diag_step(leaves, DIAG_LEAF_P, ch.out, k, false);
+      rowstep(S_GATHER, g1, 0, 0, 0, kDD<T>);
+      rowstep(S_GATHER, g3, 0, 0, 0, kDD<T>);
+      gemm_x(OP_N, OP_N, m1a, 0);
+      gemm_x(OP_N, OP_N, m1b, 1);
+      gemm_x(OP_N, OP_N, m3a, 0);
+      gemm_x(OP_N, OP_N, m3b, 1);
+      rowstep(S_GATHER, g2, 1, 1, 0, kDD<T>);
+      gemm_x(OP_N, OP_N, m2a, 0);
+      gemm_x(OP_N, OP_N, m2b, 1);
+      diag_step<T>(seps, DIAG_SEP, ch.out, k, false);
+      diag_step<T>(leaves, DIAG_LEAF_P, ch.out, k, false);
     }
   }
 };
@@ -1006,10 +1027,12 @@ int run_steps(hsc_ctx* ctx, hipStream_t st, Plan* pl, int e_base, int nvalid, vo
         launch_assemble(st, (const RowJob*)jobs, map, s.count, pl->es);
         break;
       case S_ASSEMBLE_N:
-        launch_assemble_n(st, (const RowJob*)jobs, map, s.count, pl->es, s.i0);
+        if (s.dd) launch_dd_assemble_n(st, (const RowJob*)jobs, map, s.count, pl->es, s.i0);
+        else launch_assemble_n(st, (const RowJob*)jobs, map, s.count, pl->es, s.i0);
         break;
       case S_GATHER:
-        launch_gather(st, (const RowJob*)jobs, map, s.count, s.i0, s.i1);
+        if (s.dd) launch_dd_gather(st, (const RowJob*)jobs, map, s.count, s.i0, s.i1);
+        else launch_gather(st, (const RowJob*)jobs, map, s.count, s.i0, s.i1);
         break;
       case S_GEMM:
       {
@@ -1046,7 +1069,7 @@ int run_steps(hsc_ctx* ctx, hipStream_t st, Plan* pl, int e_base, int nvalid, vo
         launch_dd_inv_unscramble(st, (const InvJobDD*)jobs, s.njobs, s.i2);
         break;
       case S_DD_GEMM:
-        launch_dd_gemm(st, s.i0, (const GemmProbDD*)jobs, map, s.count, s.i1, s.beta);
+        launch_dd_gemm(st, s.i0, s.i2, (const GemmProbDD*)jobs, map, s.count, s.i1, s.beta);
         break;
       case S_DIAG: {
         void* out = nullptr;
@@ -1059,7 +1082,8 @@ int run_steps(hsc_ctx* ctx, hipStream_t st, Plan* pl, int e_base, int nvalid, vo
           case O_SPEC_R: out = spectral ? spectral + n : nullptr; kind = OUT_IMAG; stride = 2 * n; break;
           case O_AR_TMP: out = pl->a_r; kind = OUT_IMAG; eb = 0; break;
         }
-        if (out) launch_diag(st, (const RowJob*)jobs, map, s.count, s.i0, kind, out, stride, eb, nvalid);
+        if (out && s.dd) launch_dd_diag(st, (const RowJob*)jobs, map, s.count, s.i0, kind, out, stride, eb, nvalid);
+        else if (out) launch_diag(st, (const RowJob*)jobs, map, s.count, s.i0, kind, out, stride, eb, nvalid);
         break;
       }
     }
@@ -1140,7 +1164,8 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
   std::unique_ptr<Plan> pl(new Plan());
   pl->uid = t->uid; pl->B = B; pl->want = want; pl->n = t->n; pl->prec = prec; pl->tune = tune; pl->m3 = m3;
   Builder b{t, B, want, (want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR)) != 0};
-  b.ddf = prec == 1;
+  b.ddf = prec >= 1;
+  b.ddx = prec == 2;
   b.channels();
   b.layout();
   // per-plan small buffers at the end of the workspace
@@ -1171,8 +1196,14 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
   pl->nleft = (int)t->contact[0].sites.size();
   const auto L = b.levels();
   b.fold(L);
-  if (want & (HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR)) b.extract_g(L);
-  for (size_t k = 0; k < b.chans.size(); ++k) b.channel_steps(L, (int)k);
+  if (want & (HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR)) {
+    if (b.ddx) b.extract_g<zdd>(L);
+    else b.extract_g<double2>(L);
+  }
+  for (size_t k = 0; k < b.chans.size(); ++k) {
+    if (b.ddx) b.channel_steps<zdd>(L, (int)k);
+    else b.channel_steps<double2>(L, (int)k);
+  }
   // upload the blob with relocations
   pl->blob_bytes = b.blob.data.size();
   if (hipMalloc(&pl->blob, pl->blob_bytes) != hipSuccess) {
@@ -1207,7 +1238,8 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
 
 size_t plan_bytes_per_slot(const hsc_tree* t, uint32_t want, int prec) {
   Builder b{t, 1, want, (want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR)) != 0};
-  b.ddf = prec == 1;
+  b.ddf = prec >= 1;
+  b.ddx = prec == 2;
   b.channels();
   b.layout();
   return b.ws;
@@ -1293,7 +1325,7 @@ static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
   }
   B = std::min(B, n_e);
   Plan* pl = nullptr;
-  if (opts->precision != 0 && opts->precision != 1) { set_error("precision must be 0 or 1"); return HSC_E_ARG; }
+  if (opts->precision < 0 || opts->precision > 2) { set_error("precision must be 0, 1 or 2"); return HSC_E_ARG; }
   if (opts->complex3m != 0 && opts->complex3m != 1) { set_error("complex3m must be 0 or 1"); return HSC_E_ARG; }
   int st = build_plan(ctx, tree, B, want, opts->precision, opts->tune != 0, opts->complex3m, &pl);
   if (st != HSC_OK) return (hsc_status)st;

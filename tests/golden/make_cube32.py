@@ -4,9 +4,11 @@ The 32^3 cube of the throughput benchmark (t = -1, on-site U[-0.5, 0.5] seed 0,
 per-site 1D leads on the x faces, eta = 1e-8, kT = 0.025, mu_L/R = +-0.1).
 Eight energies of the 256-point grid linspace(-6, 6, 256) (in and out of the
 lead band [-2, 2]) and 64 seeded sites plus the four x-face corner sites:
-  gr, gl, a_l, a_r  -- oracle.sampled (sparse LU rows of G^r),
-  trans             -- oracle.rgf (slab recursive Green's function).
-Run:  python tests/golden/make_cube32.py   (about 10 minutes on 8 cores)
+  gr, gl, a_l, a_r, trans  -- oracle.sampled (refined sparse LU rows of G^r; T from the
+                              rows of every left-contact site).
+The slab recursive Green's function (oracle.rgf) is not used for T here: like every
+unpivoted elimination it loses digits outside the lead band, where T is tiny.
+Run:  python tests/golden/make_cube32.py   (about an hour on 8 cores)
 """
 import json
 import os
@@ -30,15 +32,14 @@ def main():
     rng = np.random.default_rng(2024)
     sites = np.unique(np.concatenate([rng.choice(dev.n, 64, replace=False),
                                       [0, 31 * 32 * 32, 31, 32 ** 3 - 1]])).astype(np.int64)
-    s = oracle.sampled.solve_sites(dev, energies, 1e-8, 0.025, 0.1, -0.1, sites)
-    r = oracle.rgf.solve(dev, energies, 1e-8, 0.025, 0.1, -0.1)
+    s = oracle.sampled.solve_sites(dev, energies, 1e-8, 0.025, 0.1, -0.1, sites, want_trans=True)
     out = {
         "workload": "cube 32^3, t=-1, onsite U[-0.5,0.5] seed 0, eta 1e-8, kT 0.025, mu +-0.1",
         "energy_index": E_INDEX, "energies": energies.tolist(), "sites": sites.tolist(),
         "gr_re": s["gr"].real.tolist(), "gr_im": s["gr"].imag.tolist(),
         "gl_im": s["gl"].imag.tolist(), "gl_re": s["gl"].real.tolist(),
         "a_l": s["a_l"].tolist(), "a_r": s["a_r"].tolist(),
-        "trans": r["trans"].tolist(),
+        "trans": s["trans"].tolist(),
     }
     with open(os.path.join(HERE, "cube32_sampled.json"), "w") as f:
         json.dump(out, f)

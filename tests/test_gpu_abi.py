@@ -23,7 +23,7 @@ def _code(fn):
     return e.value.code
 
 
-@pytest.mark.parametrize("kw", [dict(want=0), dict(precision=2), dict(complex3m=2), dict(eta=0.0),
+@pytest.mark.parametrize("kw", [dict(want=0), dict(precision=3), dict(precision=-1), dict(complex3m=2), dict(eta=0.0),
                                 dict(kT=-1.0), dict(guard=True, guard_tau=10.0, guard_rounds=-1)])
 def test_solve_rejects_bad_options(ctx, tree, kw):
     assert _code(lambda: pkg.solve(ctx, tree, np.array([0.1, 0.2]), **kw)) == -1

@@ -143,12 +143,13 @@ def test_clean_cuboid_modes(ctx):
         assert t_rel(g["trans"][e], T) <= TOL
 
 
-def test_clean_cube32_modes_in_band(ctx):
+@pytest.mark.parametrize("kw", [dict(precision=1, **GUARD), dict(precision=2)], ids=["dd_fold_guarded", "dd"])
+def test_clean_cube32_modes_in_band(ctx, kw):
     # full-size pin: the clean 32^3 cube decomposes into 1024 independent 1D problems
     N = 32
     dev = synth.cuboid(N, N, N)
     E = np.array([-1.5, 0.25, 1.1])
-    g = gpu(ctx, dev, E, 8, precision=1, **GUARD)
+    g = gpu(ctx, dev, E, 8, **kw)
     for e, en in enumerate(E):
         gr, al, ar, T = _modes(N, N, N, en)
         errs = (rel(g["gr"][e], gr), rel(g["a_l"][e], al), rel(g["a_r"][e], ar), t_rel(g["trans"][e], T))
@@ -203,11 +204,37 @@ def test_cube32_golden_in_band_nd_tree_guarded(ctx):
     print("worst", _golden32_check(ctx, IN_BAND, leaf=8, precision=1, **GUARD))
 
 
-@pytest.mark.xfail(reason="out of the lead band the cluster blocks are nearly real and may be nearly singular; "
-                          "the unpivoted elimination loses accuracy in proportion to |Psi|^2 (about 1e-10 to "
-                          "1e-8 here, with the guard and the double-double fold)", strict=False)
-def test_cube32_golden_out_of_band_guarded(ctx):
-    print("worst", _golden32_check(ctx, OUT_OF_BAND, leaf=8, precision=1, **GUARD))
+def test_cube32_golden_out_of_band_double_double(ctx):
+    # out of the lead band nothing broadens the cluster blocks; with the fold and the extraction
+    # in double-double the unpivoted elimination needs no guard
+    print("worst", _golden32_check(ctx, OUT_OF_BAND, leaf=8, precision=2))
+
+
+def test_cube32_golden_all_energies_transverse_double_double(ctx):
+    print("worst", _golden32_check(ctx, IN_BAND + OUT_OF_BAND, leaf=4, transverse=True, precision=2))
+
+
+@pytest.mark.parametrize("transverse,leaf", [(True, 4), (False, 8)])
+def test_cube16_out_of_band_double_double(ctx, transverse, leaf):
+    dev = synth.config1_device(n_side=16)
+    E = np.linspace(-6.0, 6.0, 48)
+    E = E[np.abs(E) > 2.0][::2]
+    g = gpu(ctx, dev, E, leaf, transverse=transverse, precision=2)
+    print("16^3 out of band, double-double worst", check_all(g, oracle.dense.solve(dev, E, **KW), E))
+
+
+def test_double_double_beats_complex128_where_a_block_is_nearly_singular(ctx):
+    # 8^3 cube, 3D tree with 4-site leaves, E = 3: a cluster block close to singular costs the
+    # complex128 solve ~5e-10; the double-double fold and extraction must not lose those digits
+    # (a fused multiply-add contracted into the error-free transformations would)
+    dev = synth.config0_device()
+    E = np.array([2.0 + 1.0 / 3.0, 3.0])
+    ref = oracle.dense.solve(dev, E, **KW)
+    e64 = max(rel(gpu(ctx, dev, E, 4, precision=0)["gr"][1], ref["gr"][1]), 1e-16)
+    g2 = gpu(ctx, dev, E, 4, precision=2)
+    e2 = check_all(g2, ref, E, tol=1e-12)
+    print("complex128", e64, "double-double", e2)
+    assert e64 > 1e-11 and e2 < e64 / 100
 
 
 def test_full_size_invariants(ctx):
@@ -272,6 +299,10 @@ def _trilayer_check(ctx, **kw):
         print("trilayer E", E[e], [rel(gs[k][e], ref[k][e]) for k in ("gr", "gl", "a_l", "a_r")],
               t_rel(gs["trans"][e], ref["trans"][e]), "status", g["status"][e])
     return check_all(gs, ref, E, allow_unstable=True)
+
+
+def test_trilayer_golden_double_double(ctx):
+    print("worst", _trilayer_check(ctx, leaf=8, precision=2))
 
 
 def test_trilayer_golden_guarded(ctx):
