@@ -3,11 +3,14 @@
 
 Workload: the 32^3 cube (32,768 sites, 7-point, t = -1, on-site U[-0.5, 0.5]
 seed 0, per-site 1D leads on the x faces), 256 energies uniform in [-6, 6],
-eta = 1e-8, kT = 0.025, mu_L/R = +-0.1.  Cluster tree: nested dissection of
-the cross-section (the transport axis x is never cut, clusters span contact to
-contact), leaves <= 4 sites across.  One step = diag G^r, diag G^< and T for
-all 256 energies (inputs resident on the device).  The line also reports the
-error against stored oracle values at 8 of the 256 energies (tests/golden).
+eta = 1e-8, kT = 0.025, mu_L/R = +-0.1.  Cluster tree: 3D nested dissection
+with planar separators, leaves <= 8 sites per side.  One step = diag G^r,
+diag G^< and T for all 256 energies (inputs resident on the device), with the
+fold and the extraction in double-double (precision 2: the only setting whose
+results agree with the oracle to 1e-10 at every energy of the grid, out of the
+lead band included).  The line also reports the error against stored oracle
+values at 8 of the 256 energies (tests/golden), and the complex128 path on the
+FP64 matrix cores (its rate, its GEMM roofline and where it is accurate).
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -22,36 +25,63 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_MFMA_PEAK_TFLOPS = 78.6
+# FP64 vector issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one add, multiply or fused
+# multiply-add per lane and clock (the published 78.6 TFLOP/s counts an FMA as two flops)
+FP64_VALU_PEAK_TOPS = 39.3
+# FP64 vector operations of one complex double-double multiply-add in k_dd_gemm (4 products of
+# 1 mul + 3 fma, each accumulated with a 6-operation two-sum and 2 adds): 6 per complex flop-pair
+DD_OPS_PER_CFLOP = 48 / 8
 
 
 def note(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
+def golden_errors(np, gold, out):
+    """max relative error of diag G^r, Im diag G^< (sampled sites) and T at the stored energies"""
+    import torch
+    idx = torch.tensor(gold["energy_index"], device=out["gr"].device)
+    sites = np.array(gold["sites"])
+    ref_gr = np.array(gold["gr_re"]) + 1j * np.array(gold["gr_im"])
+    ref_gl = np.array(gold["gl_im"])
+    gr = out["gr"][idx].cpu().numpy()[:, sites]
+    gl = out["gl"][idx].cpu().numpy()[:, sites].imag
+    tr = out["trans"][idx].cpu().numpy()
+    errs = [max(np.abs(gr[k] - ref_gr[k]).max() / np.abs(ref_gr[k]).max(),
+                np.abs(gl[k] - ref_gl[k]).max() / np.abs(ref_gl[k]).max(),
+                abs(tr[k] - gold["trans"][k]) / max(gold["trans"][k], 1e-12)) for k in range(len(idx))]
+    band = [abs(e) < 2.0 for e in gold["energies"]]
+    return {"energies": gold["energies"], "max_rel_err": errs, "max": max(errs),
+            "in_band_max": max(x for x, b in zip(errs, band) if b),
+            "out_of_band_max": max(x for x, b in zip(errs, band) if not b)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-side", type=int, default=32)
     ap.add_argument("--energies", type=int, default=256)
     ap.add_argument("--batch", type=int, default=0, help="energies per launch sequence (0 = auto)")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-energy-per-launch-sequence run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--precision", type=int, default=0,
-                    help="fold arithmetic: 0 = complex128 as in Algorithm 1 (default), 1 = double-double")
-    ap.add_argument("--leaf", type=int, default=4)
-    ap.add_argument("--full-nd", action="store_true", help="also cut the transport axis (classic 3D ND)")
+    ap.add_argument("--precision", type=int, default=2,
+                    help="2 (default): fold and extraction in double-double; 1: double-double fold only; "
+                         "0: complex128 as in Algorithms 1 and 2")
+    ap.add_argument("--leaf", type=int, default=8)
+    ap.add_argument("--transverse", action="store_true",
+                    help="never cut the transport axis (clusters span contact to contact)")
     ap.add_argument("--tune", type=int, default=1, help="1 (default): autotune the GEMM tile shape per launch")
     ap.add_argument("--complex3m", type=int, default=1,
-                    help="1 (default): three real products per complex multiply-add in every block product; "
-                         "0: four")
-    ap.add_argument("--no-alt", action="store_true", help="skip timing the other fold precision")
+                    help="1 (default): three real products per complex multiply-add in every complex128 block "
+                         "product; 0: four")
+    ap.add_argument("--no-alt", action="store_true", help="skip the complex128 matrix-core runs")
     ap.add_argument("--uneven", type=int, default=0, metavar="D",
                     help="measure D of the 64 uneven cuboids instead: forest batch vs one device at a time")
     ap.add_argument("--uneven-energies", type=int, default=32)
     ap.add_argument("--trilayer", action="store_true",
-                    help="measure the 40,020-site trilayer x 512 energies instead (unguarded, with its error)")
+                    help="measure the 40,020-site trilayer x 512 energies instead, with its error")
     ap.add_argument("--learned-grid", action="store_true",
                     help="measure the learned energy grid instead (surrogate training + charge on 3 devices)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -88,104 +118,100 @@ def main():
 
     N, NE = args.n_side, args.energies
     dev = synth.config1_device(n_side=N)
-    tree = pkg.Tree.from_device(dev, leaf_side=args.leaf, transverse=not args.full_nd)
+    tree = pkg.Tree.from_device(dev, leaf_side=args.leaf, transverse=args.transverse)
     st = tree.stats()
     ctx = pkg.Context(0)
     E = torch.linspace(-6.0, 6.0, NE, dtype=torch.float64, device="cuda:0")
     kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=args.precision, complex3m=args.complex3m,
               tune=args.tune)
     want = pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS
+    gpath = os.path.join(ROOT, "tests", "golden", "cube32_sampled.json")
+    gold = json.load(open(gpath)) if (N == 32 and NE == 256 and os.path.exists(gpath)) else None
+
     out = pkg.solve(ctx, tree, E, want=want, batch=args.batch, **kw)     # buffers + plan
     for _ in range(args.warmup):
         pkg.solve(ctx, tree, E, want=want, batch=args.batch, out=out, sync=False, **kw)
     torch.cuda.synchronize()
     note("warmup done")
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         pkg.solve(ctx, tree, E, want=want, batch=args.batch, out=out, sync=False, **kw)
+        if k + 1 < args.steps:
+            torch.cuda.synchronize()
+            note(f"step {k + 1} done")
     ctx.sync()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = NE * args.steps / dt
     status_ok = int(out["status"].abs().sum().item()) == 0
     note(f"timed {args.steps} steps: {value:.2f} energies/s")
+    acc = golden_errors(np, gold, out) if gold else None
 
-    # per-kernel timing of one step (events around every launch on the solver's stream)
-    ctx.profile(True)
-    pkg.solve(ctx, tree, E, want=want, batch=args.batch, out=out, sync=True, **kw)
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    g = prof["gemm"]
-    achieved = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
+    def profiled(tr, kwp, ne):
+        # per-kernel timing (events around every launch on the solver's stream) over ne energies
+        ctx.profile(True)
+        pkg.solve(ctx, tr, E[:ne], want=want, batch=args.batch, sync=True, **kwp)
+        p = ctx.profile_read()
+        ctx.profile(False)
+        return p
+
+    NP = min(NE, 64)
+    prof = profiled(tree, kw, NP)
     total_ms = sum(v["ms"] for v in prof.values())
-    gd = prof["dd_gemm"]
-    dd_rate = gd["flops"] / (gd["ms"] * 1e-3) / 1e12 if gd["ms"] > 0 else None
+    g, gd = prof["gemm"], prof["dd_gemm"]
+    if args.precision >= 1 and gd["ms"] > 0:
+        ach = DD_OPS_PER_CFLOP * gd["flops"] / (gd["ms"] * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": "k_dd_gemm (grouped complex double-double GEMM, FP64 vector units)",
+                "achieved": ach, "peak": FP64_VALU_PEAK_TOPS, "unit": "TOP/s (FP64 vector operations)",
+                "frac": ach / FP64_VALU_PEAK_TOPS, "traffic": None, "launches": int(gd["launches"]),
+                "avg_launch_ms": gd["ms"] / gd["launches"],
+                "complex_equiv_tflops": gd["flops"] / (gd["ms"] * 1e-3) / 1e12,
+                "fp64_ops_per_complex_multiply_add": 48,
+                "share_of_kernel_time": gd["ms"] / total_ms}
+    else:
+        ach = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
+        roof = {"bound": "mfma", "kernel": "k_zgemm (grouped complex128 GEMM, all tile shapes)",
+                "achieved": ach, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_MFMA_PEAK_TFLOPS,
+                "traffic": None, "launches": int(g["launches"]),
+                "avg_launch_ms": g["ms"] / g["launches"] if g["launches"] else None,
+                "real_mfma_flops_per_complex_fma": 6 if args.complex3m else 8,
+                "share_of_kernel_time": g["ms"] / total_ms if total_ms else None}
 
-    alt = None
+    # the complex128 path on the FP64 matrix cores: the transverse tree (accurate inside the lead
+    # band) and this tree, each with its GEMM roofline and its error at the stored energies
+    mfma = None
     if not args.no_alt:
-        kw_alt = dict(kw, precision=1 - args.precision)
-        pkg.solve(ctx, tree, E[:8], want=want, batch=args.batch, **kw_alt)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        pkg.solve(ctx, tree, E, want=want, batch=args.batch, **kw_alt)
-        torch.cuda.synchronize()
-        alt = NE / (time.perf_counter() - t3)
-        note(f"other fold precision: {alt:.2f} energies/s")
-
-    # accuracy at the stored oracle energies (in and out of the lead band [-2, 2])
-    acc = None
-    gpath = os.path.join(ROOT, "tests", "golden", "cube32_sampled.json")
-    if N == 32 and NE == 256 and os.path.exists(gpath):
-        gold = json.load(open(gpath))
-        idx = torch.tensor(gold["energy_index"], device="cuda:0")
-        sites = np.array(gold["sites"])
-        ref_gr = np.array(gold["gr_re"]) + 1j * np.array(gold["gr_im"])
-        ref_gl = np.array(gold["gl_im"])
-        gr = out["gr"][idx].cpu().numpy()[:, sites]
-        gl = out["gl"][idx].cpu().numpy()[:, sites].imag
-        tr = out["trans"][idx].cpu().numpy()
-        errs = [max(np.abs(gr[k] - ref_gr[k]).max() / np.abs(ref_gr[k]).max(),
-                    np.abs(gl[k] - ref_gl[k]).max() / np.abs(ref_gl[k]).max(),
-                    abs(tr[k] - gold["trans"][k]) / max(gold["trans"][k], 1e-12)) for k in range(len(idx))]
-        band = [abs(e) < 2.0 for e in gold["energies"]]
-        acc = {"energies": gold["energies"], "max_rel_err": errs,
-               "in_band_max": max(x for x, b in zip(errs, band) if b),
-               "out_of_band_max": max(x for x, b in zip(errs, band) if not b)}
-
-    # the other complex-product form on the same tree
-    other_products = None
-    if not args.no_alt:
-        kw_p = dict(kw, complex3m=1 - args.complex3m)
-        pkg.solve(ctx, tree, E[:8], want=want, batch=args.batch, **kw_p)
-        torch.cuda.synchronize()
-        t5 = time.perf_counter()
-        pkg.solve(ctx, tree, E, want=want, batch=args.batch, **kw_p)
-        torch.cuda.synchronize()
-        other_products = NE / (time.perf_counter() - t5)
-        note(f"other complex-product form: {other_products:.2f} energies/s")
-
-    # the same solve on the classic 3D nested-dissection tree (leaves <= 8 per side)
-    nd8 = None
-    if not args.full_nd and not args.no_alt:
-        tree8 = pkg.Tree.from_device(dev, leaf_side=8)
-        pkg.solve(ctx, tree8, E[:8], want=want, batch=args.batch, **kw)
-        torch.cuda.synchronize()
-        t4 = time.perf_counter()
-        pkg.solve(ctx, tree8, E, want=want, batch=args.batch, **kw)
-        torch.cuda.synchronize()
-        nd8 = NE / (time.perf_counter() - t4)
-        note(f"3D nested-dissection tree: {nd8:.2f} energies/s")
-        del tree8
+        mfma = {}
+        kw0 = dict(kw, precision=0)
+        for name, tr in (("transverse_leaf4", pkg.Tree.from_device(dev, leaf_side=4, transverse=True)),
+                         ("this_tree", tree)):
+            o0 = pkg.solve(ctx, tr, E, want=want, batch=args.batch, **kw0)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            pkg.solve(ctx, tr, E, want=want, batch=args.batch, out=o0, **kw0)
+            torch.cuda.synchronize()
+            rate = NE / (time.perf_counter() - t3)
+            p0 = profiled(tr, kw0, NE)
+            g0 = p0["gemm"]
+            a0 = g0["flops"] / (g0["ms"] * 1e-3) / 1e12
+            mfma[name] = {"energies_per_s": rate, "flops_per_energy": tr.stats()["flops_per_energy"],
+                          "k_zgemm_tflops": a0, "k_zgemm_frac_of_fp64_mfma_peak": a0 / FP64_MFMA_PEAK_TFLOPS,
+                          "k_zgemm_avg_launch_ms": g0["ms"] / g0["launches"],
+                          "k_zgemm_share_of_kernel_time": g0["ms"] / sum(v["ms"] for v in p0.values()),
+                          "accuracy_vs_oracle": golden_errors(np, gold, o0) if gold else None}
+            note(f"complex128 on the matrix cores, {name}: {rate:.2f} energies/s, k_zgemm {a0:.1f} TFLOP/s")
+            del o0
 
     plain = None
     if not args.no_plain:
-        sub = E[: min(NE, 32)]
+        sub = E[: min(NE, 16)]
         pkg.solve(ctx, tree, sub[:2], want=want, batch=1, **kw)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         pkg.solve(ctx, tree, sub, want=want, batch=1, **kw)
         torch.cuda.synchronize()
         plain = len(sub) / (time.perf_counter() - t1)
+        note(f"plain (one energy per launch sequence): {plain:.2f} energies/s")
 
     cpu = None
     if not args.no_cpu:
@@ -198,6 +224,8 @@ def main():
         cpu = {"value": 1.0 / cdt, "unit": "energies/s", "cores": threads, "kind": "oracle",
                "sample": f"slab RGF (oracle/rgf.py), one energy (E=0.3) of the same {N}^3 cube, {cdt:.1f} s"}
 
+    prec_name = {0: "complex128", 1: "double-double fold, complex128 extraction",
+                 2: "double-double fold and extraction"}[args.precision]
     line = {
         "metric": "energies/s (diag G^r,G^<), 32^3 cube, batched vs plain; % FP64 MFMA peak",
         "value": value,
@@ -209,31 +237,23 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128",
+        "dtype": "c128" if args.precision == 0 else "c128 in/out, complex double-double inside",
         "data": "synthetic",
         "config": {"workload": f"cube{N}^3 x {NE} energies in [-6,6] (diag G^r, diag G^<, T)",
                    "sites": int(dev.n), "energies": NE, "leaf_side": args.leaf, "clusters": st["n_clusters"],
-                   "tree": "full 3D nested dissection" if args.full_nd else "transverse nested dissection",
+                   "tree": "transverse nested dissection" if args.transverse else
+                           "3D nested dissection, planar separators",
                    "batch": args.batch or "auto", "plain_energies_per_s": plain,
-                   "fold": "double-double" if args.precision == 1 else "complex128",
+                   "precision": prec_name,
                    "complex_products": "3 real products (Gauss)" if args.complex3m else "4 real products",
                    "gemm_tiles": "autotuned per launch" if args.tune else "64x64 (16x16x4 MFMA)",
-                   "other_complex_products_energies_per_s": other_products,
-                   "other_fold_energies_per_s": alt,
-                   "nd_leaf8_tree_energies_per_s": nd8,
-                   "dd_gemm_equiv_tflops": dd_rate,
                    "flops_per_energy": st["flops_per_energy"],
-                   "whole_solve_tflops": st["flops_per_energy"] * value / 1e12,
                    "status_ok": status_ok,
                    "accuracy_vs_oracle": acc,
-                   "kernel_ms_per_step": {k: round(v["ms"], 3) for k, v in prof.items()},
+                   "complex128_matrix_core_path": mfma,
+                   f"kernel_ms_first_{NP}_energies": {k: round(v["ms"], 3) for k, v in prof.items() if v["ms"] > 0},
                    "kernel_ms_total": round(total_ms, 3)},
-        "roofline": {"bound": "mfma", "kernel": "k_zgemm (grouped complex128 GEMM, all tile shapes)",
-                     "achieved": achieved,
-                     "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
-                     "traffic": None, "launches": int(g["launches"]),
-                     "avg_launch_ms": g["ms"] / g["launches"] if g["launches"] else None,
-                     "real_mfma_flops_per_complex_fma": 6 if args.complex3m else 8},
+        "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -241,7 +261,8 @@ def main():
 
 def trilayer_study(pkg, synth, np, torch, args):
     """Graphene / BN / graphene trilayer (116 x 115 x 3 sites, in-plane nested dissection, leaves <= 8
-    across), 512 energies in [-3, 3] eV, unguarded; error against the stored RGF values at 6 energies."""
+    across), 512 energies in [-3, 3] eV, unguarded, at --precision; error against the stored RGF values
+    at 6 energies."""
     dev = synth.trilayer()
     tree = pkg.Tree.from_device(dev, leaf_side=8)
     ctx = pkg.Context(0)
@@ -263,11 +284,13 @@ def trilayer_study(pkg, synth, np, torch, args):
             for k, i in enumerate(gold["energy_index"])]
     note(f"trilayer: {512 / dt:.1f} energies/s, max error {max(errs):.1e}")
     print(json.dumps({"metric": "energies/s (diag G^r, G^<, T), trilayer 40,020 sites", "value": 512 / dt,
-                      "unit": "energies/s", "higher_is_better": True, "n_gpus": 1, "dtype": "c128", "data": "synthetic",
+                      "unit": "energies/s", "higher_is_better": True, "n_gpus": 1,
+                      "dtype": "c128" if args.precision == 0 else "c128 in/out, complex double-double inside",
+                      "data": "synthetic",
                       "config": {"workload": "graphene/BN/graphene 116x115x3 x 512 energies in [-3, 3] eV, unguarded",
+                                 "precision": args.precision,
                                  "flops_per_energy": tree.stats()["flops_per_energy"],
-                                 "gr_rel_err_at_stored_energies": errs,
-                                 "note": "the unguarded unpivoted elimination; 1e-10 needs the guard (parity tests)"}}),
+                                 "gr_rel_err_at_stored_energies": errs}}),
           flush=True)
 
 

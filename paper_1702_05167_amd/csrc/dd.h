@@ -103,6 +103,53 @@ __device__ __forceinline__ zdd zdd_rcp(zdd a) {
   return zdd{dd_mul(qr, inv_s), dd_mul(qi, inv_s)};
 }
 
+// Lazy accumulation of a sum of double-double products (the GEMM inner loop): hi
+// holds the running FP64 sum, lo collects the exact rounding errors of the hi
+// additions (two_sum) and the products' low parts in plain FP64.  renorm() folds
+// lo back into hi; called every few terms it keeps the result double-double
+// accurate while each product-accumulate costs 12 FP64 operations instead of 18.
+struct ddacc {
+  double hi, lo;
+};
+
+struct zddacc {
+  ddacc re, im;
+};
+
+__device__ __forceinline__ void ddacc_add_prod(ddacc& a, dd x, dd y) {
+#pragma clang fp contract(off)
+  const double ph = x.hi * y.hi;
+  double pl = fma(x.hi, y.hi, -ph);
+  pl = fma(x.hi, y.lo, pl);
+  pl = fma(x.lo, y.hi, pl);
+  const double s = a.hi + ph;
+  const double bb = s - a.hi;
+  const double e = (a.hi - (s - bb)) + (ph - bb);
+  a.hi = s;
+  a.lo += e + pl;
+}
+
+__device__ __forceinline__ void ddacc_renorm(ddacc& a) {
+  const dd s = two_sum(a.hi, a.lo);
+  a.hi = s.hi;
+  a.lo = s.lo;
+}
+
+// c += a * b
+__device__ __forceinline__ void zddacc_fma(zddacc& c, zdd a, zdd b) {
+  ddacc_add_prod(c.re, a.re, b.re);
+  ddacc_add_prod(c.re, dd_neg(a.im), b.im);
+  ddacc_add_prod(c.im, a.re, b.im);
+  ddacc_add_prod(c.im, a.im, b.re);
+}
+
+__device__ __forceinline__ void zddacc_renorm(zddacc& c) {
+  ddacc_renorm(c.re);
+  ddacc_renorm(c.im);
+}
+
+__device__ __forceinline__ zdd zddacc_value(zddacc c) { return zdd{two_sum(c.re.hi, c.re.lo), two_sum(c.im.hi, c.im.lo)}; }
+
 __device__ __forceinline__ double zdd_cabs1(zdd a) { return fabs(a.re.hi) + fabs(a.im.hi); }
 
 }  // namespace hsc

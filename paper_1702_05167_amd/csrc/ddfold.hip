@@ -238,7 +238,8 @@ __global__ __launch_bounds__(256) void k_dd_inv_unscramble(const InvJobDD* __res
 }
 
 // ---------------------------------------------------------------------------------------------
-// grouped complex double-double GEMM: 32 x 32 output tile, 256 threads, 2 x 2 outputs per thread.
+// grouped complex double-double GEMM: 32 x 32 output tile, 256 threads, 2 x 2 outputs per thread,
+// lazily accumulated (dd.h: zddacc) and renormalised after every 8-deep k step.
 //   OPA 0: A'(m,k) = A[m*lda + k];  OPA 1: A'(m,k) = A[k*lda + m]
 //   OPB 0: B'(k,n) = B[k*ldb + n];  OPB 1: B'(k,n) = B[n*ldb + k]
 constexpr int DT = 32, DK = 8;
@@ -258,11 +259,11 @@ __global__ __launch_bounds__(256) void k_dd_gemm(const GemmProbDD* __restrict__ 
   const int M = pr.M, N = pr.N, K = pr.K;
   const int t = threadIdx.x;
   const int tm = (t / 16) * 2, tn = (t % 16) * 2;   // this thread's 2 x 2 block
-  zdd acc[2][2];
+  zddacc acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = zdd_zero();
+    for (int j = 0; j < 2; ++j) acc[i][j] = zddacc{{0.0, 0.0}, {0.0, 0.0}};
   for (int k0 = 0; k0 < K; k0 += DK) {
     // stage A' (DT x DK) and B (DK x DT): 256 elements each, one per thread
     {
@@ -284,11 +285,15 @@ __global__ __launch_bounds__(256) void k_dd_gemm(const GemmProbDD* __restrict__ 
     for (int kk = 0; kk < DK; ++kk) {
       const zdd a0 = As[kk][tm], a1 = As[kk][tm + 1];
       const zdd b0 = Bs[kk][tn], b1 = Bs[kk][tn + 1];
-      acc[0][0] = zdd_fma(acc[0][0], a0, b0);
-      acc[0][1] = zdd_fma(acc[0][1], a0, b1);
-      acc[1][0] = zdd_fma(acc[1][0], a1, b0);
-      acc[1][1] = zdd_fma(acc[1][1], a1, b1);
+      zddacc_fma(acc[0][0], a0, b0);
+      zddacc_fma(acc[0][1], a0, b1);
+      zddacc_fma(acc[1][0], a1, b0);
+      zddacc_fma(acc[1][1], a1, b1);
     }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) zddacc_renorm(acc[i][j]);
     __syncthreads();
   }
 #pragma unroll
@@ -297,7 +302,8 @@ __global__ __launch_bounds__(256) void k_dd_gemm(const GemmProbDD* __restrict__ 
     for (int j = 0; j < 2; ++j) {
       const int row = m0 + tm + i, col = n0 + tn + j;
       if (row < M && col < N) {
-        zdd o = negate ? zdd_neg(acc[i][j]) : acc[i][j];
+        const zdd v = zddacc_value(acc[i][j]);
+        zdd o = negate ? zdd_neg(v) : v;
         if (beta) o = zdd_add(o, pr.C[(int64_t)row * pr.ldc + col]);
         pr.D[(int64_t)row * pr.ldd + col] = o;
         if (pr.D64) pr.D64[(int64_t)row * pr.ldd64 + col] = zdd_round(o);

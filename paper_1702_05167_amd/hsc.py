@@ -251,7 +251,7 @@ class Tree:
 
 def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1,
           want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, out=None, sync=True, guard=False,
-          guard_tau=0.0, guard_rounds=6, precision=1, graph=0, tune=0, complex3m=0):
+          guard_tau=0.0, guard_rounds=6, precision=2, graph=0, tune=0, complex3m=0):
     """Solve all energies; returns a dict of device tensors (gr, gl, trans, spectral, status)."""
     import torch
     dev = ctx.torch_device
@@ -280,7 +280,7 @@ def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R
 
 
 def solve_batch(ctx: Context, trees, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1,
-                want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, outs=None, sync=True, precision=1, graph=0,
+                want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, outs=None, sync=True, precision=2, graph=0,
                 tune=0, complex3m=0):
     """Several devices in one call (hsc_solve_batch); energies: one array for all devices or a
     list of per-device arrays.  Returns a list of output dicts (device tensors)."""
