@@ -56,7 +56,7 @@ struct Blob {
 };
 
 enum StepKind { S_ASSEMBLE, S_INV_PANEL, S_INV_SWAP, S_INV_UNSCR, S_GEMM, S_GATHER, S_ASSEMBLE_N, S_DIAG, S_GUARD,
-                S_DD_ASSEMBLE, S_DD_INV_PANEL, S_DD_INV_SWAP, S_DD_INV_UNSCR, S_DD_GEMM, S_INV_SUPER};
+                S_DD_ASSEMBLE, S_DD_INV_PANEL, S_DD_INV_SWAP, S_DD_INV_UNSCR, S_DD_GEMM, S_INV_SUPER, S_MIRROR};
 
 // Tile sizes a plan keeps GEMM problem lists and tile maps for: 64x64, 128x64, 64x128, 32x32,
 // 128x128.  Every launch kind of launch_gemm uses one of them (tile_dims_of).
@@ -377,15 +377,58 @@ struct Builder {
   // ---- step helpers ----
   template <class T> struct GPT { const T *A, *B, *C; T* D; int M, N, K, lda, ldb, ldc, ldd; };
   using GP = GPT<double2>;
-  void gemm(int opA, int opB, const std::vector<GP>& ps, double ar, double ai, int beta) {
+  // rows [r0, r0 + h) of a square product restricted to columns >= r0 (one block-row strip of its
+  // upper triangle): op(A) rows, op(B) columns and the C / D blocks move with the strip
+  template <class G> static G strip(const G& g, int r0, int h, int opA, int opB) {
+    G q = g;
+    q.M = std::min(h, g.M - r0);
+    q.N = g.N - r0;
+    q.A = opA == OP_N ? g.A + (size_t)r0 * g.lda : g.A + r0;
+    q.B = opB == OP_N ? g.B + r0 : g.B + (size_t)r0 * g.ldb;
+    q.C = g.C ? g.C + (size_t)r0 * g.ldc + r0 : nullptr;
+    q.D = g.D + (size_t)r0 * g.ldd + r0;
+    return q;
+  }
+  // copy the strictly lower 32 x 32 tiles of square blocks from their transposes (elem: 16 or 32 bytes)
+  void mirror_step(const std::vector<MirrorJob>& in, int elem) {
+    std::vector<MirrorJob> mj;
+    std::vector<int32_t> tmap;
+    for (MirrorJob m : in) {
+      const int T = (m.n + 31) / 32;
+      const int tiles = T * (T - 1) / 2;
+      if (tiles <= 0) continue;
+      m.tile_off = (int32_t)tmap.size();
+      for (int k = 0; k < tiles; ++k) tmap.push_back((int32_t)mj.size());
+      mj.push_back(m);
+    }
+    if (mj.empty()) return;
+    Step s;
+    s.kind = S_MIRROR;
+    s.jobs = blob.push(mj);
+    s.map = blob.push(tmap);
+    s.count = (int)tmap.size();
+    s.i0 = elem;
+    steps.push_back(s);
+  }
+  // upper: every product is square with a symmetric result (A^T = A makes the Schur updates and the
+  // G_ii blocks complex symmetric): only the block-row strips on and above the diagonal are computed
+  // (strips as tall as the tile kind's rows) and a mirror step fills the rest
+  void gemm(int opA, int opB, const std::vector<GP>& ps, double ar, double ai, int beta, bool upper = false) {
     Step s;
     s.kind = S_GEMM;
     for (int kind = 0; kind < kTileDims; ++kind) {
       std::vector<GemmProb> probs;
       std::vector<int32_t> tmap;
       const int tm = kTileDimM[kind], tn = kTileDimN[kind];
-      for (const GP& g : ps) {
-        if (g.M <= 0 || g.N <= 0) continue;
+      std::vector<GP> parts;
+      for (const GP& g0 : ps) {
+        if (g0.M <= 0 || g0.N <= 0) continue;
+        if (upper && g0.M == g0.N)
+          for (int r0 = 0; r0 < g0.M; r0 += tm) parts.push_back(strip(g0, r0, tm, opA, opB));
+        else
+          parts.push_back(g0);
+      }
+      for (const GP& g : parts) {
         GemmProb p{};
         p.A = g.A; p.B = g.B; p.C = g.C; p.D = g.D;
         p.M = g.M; p.N = g.N; p.K = g.K;
@@ -409,6 +452,12 @@ struct Builder {
     s.i0 = opA; s.i1 = opB;
     s.ar = ar; s.ai = ai; s.beta = beta;
     steps.push_back(s);
+    if (upper) {
+      std::vector<MirrorJob> mj;
+      for (const GP& g : ps)
+        if (g.M > 0 && g.M == g.N) mj.push_back({g.D, g.ldd, g.M, 0, 0});
+      mirror_step(mj, 16);
+    }
   }
   // RowJob list: child-ref arrays are given as host vectors to be placed in the blob
   struct RJ { RowJob j; std::vector<ChildRef> kids; std::vector<size_t> kid_invrel; bool p1_blob = false; };
@@ -476,21 +525,41 @@ struct Builder {
   template <class T> T* inv_p(const CS& s) const { return X<T>(kDD<T> ? s.Invd : s.Inv); }
   template <class T> T* psi_p(const CS& s) const { return X<T>(kDD<T> ? s.Psid : s.Psi); }
   template <class T> static double2* d2(const T* p) { return reinterpret_cast<double2*>(const_cast<T*>(p)); }
-  void gemm_x(int opA, int opB, const std::vector<GP>& ps, int beta) { gemm(opA, opB, ps, 1.0, 0.0, beta); }
-  void gemm_x(int opA, int opB, const std::vector<GPT<zdd>>& ps, int beta) {
+  void gemm_x(int opA, int opB, const std::vector<GP>& ps, int beta, bool upper = false) {
+    gemm(opA, opB, ps, 1.0, 0.0, beta, upper);
+  }
+  void gemm_x(int opA, int opB, const std::vector<GPT<zdd>>& ps, int beta, bool upper = false) {
     std::vector<GPD> q;
     for (const GPT<zdd>& g : ps) q.push_back({g.A, g.B, g.C, g.D, nullptr, g.M, g.N, g.K, g.lda, g.ldb, g.ldc, g.ldd, 0});
-    dd_gemm(opA, opB, q, 0, beta);
+    dd_gemm(opA, opB, q, 0, beta, upper);
   }
 
   struct GPD { const zdd *A, *B, *C; zdd* D; double2* D64; int M, N, K, lda, ldb, ldc, ldd, ldd64; };
-  void dd_gemm(int opA, int opB, const std::vector<GPD>& ps, int negate, int beta) {
+  static GPD strip(const GPD& g, int r0, int h, int opA, int opB) {
+    GPD q = g;
+    q.M = std::min(h, g.M - r0);
+    q.N = g.N - r0;
+    q.A = opA == OP_N ? g.A + (size_t)r0 * g.lda : g.A + r0;
+    q.B = opB == OP_N ? g.B + r0 : g.B + (size_t)r0 * g.ldb;
+    q.C = g.C ? g.C + (size_t)r0 * g.ldc + r0 : nullptr;
+    q.D = g.D + (size_t)r0 * g.ldd + r0;
+    q.D64 = g.D64 ? g.D64 + (size_t)r0 * g.ldd64 + r0 : nullptr;
+    return q;
+  }
+  void dd_gemm(int opA, int opB, const std::vector<GPD>& ps, int negate, int beta, bool upper = false) {
     std::vector<GemmProbDD> probs;
     std::vector<int32_t> tmap;
     const int tt = dd_gemm_tile();
     double fl = 0;
-    for (const GPD& g : ps) {
-      if (g.M <= 0 || g.N <= 0) continue;
+    std::vector<GPD> parts;
+    for (const GPD& g0 : ps) {
+      if (g0.M <= 0 || g0.N <= 0) continue;
+      if (upper && g0.M == g0.N)
+        for (int r0 = 0; r0 < g0.M; r0 += tt) parts.push_back(strip(g0, r0, tt, opA, opB));
+      else
+        parts.push_back(g0);
+    }
+    for (const GPD& g : parts) {
       GemmProbDD p{};
       p.A = g.A; p.B = g.B; p.C = g.C; p.D = g.D; p.D64 = g.D64;
       p.M = g.M; p.N = g.N; p.K = g.K;
@@ -514,6 +583,16 @@ struct Builder {
     s.beta = beta;
     s.flops = fl;
     steps.push_back(s);
+    if (upper) {
+      std::vector<MirrorJob> m32, m16;
+      for (const GPD& g : ps) {
+        if (g.M <= 0 || g.M != g.N) continue;
+        m32.push_back({g.D, g.ldd, g.M, 0, 0});
+        if (g.D64) m16.push_back({g.D64, g.ldd64, g.M, 0, 0});
+      }
+      mirror_step(m32, 32);
+      mirror_step(m16, 16);
+    }
   }
 
   void fold_dd(const std::vector<std::vector<int>>& L) {
@@ -589,7 +668,7 @@ struct Builder {
         }
       }
       dd_gemm(0, 0, pp, 1, 0);
-      dd_gemm(1, 0, pu, 0, 1);
+      dd_gemm(1, 0, pu, 0, 1, true);
     }
     guard_step();
   }
@@ -707,7 +786,7 @@ struct Builder {
         }
       }
       gemm(OP_N, OP_N, pp, -1.0, 0.0, 0);
-      gemm(OP_T, OP_N, pu, 1.0, 0.0, 1);
+      gemm(OP_T, OP_N, pu, 1.0, 0.0, 1, true);   // U = A_ff + A_if^T Psi is complex symmetric
     }
     guard_step();
   }
@@ -778,7 +857,7 @@ struct Builder {
         rowstep(S_GATHER, g1, 0, 0, 0, kDD<T>);
         gemm_x(OP_N, OP_N, m1, 0);
         rowstep(S_GATHER, g2, 1, 0, 0, kDD<T>);
-        gemm_x(OP_N, OP_N, m2, 1);
+        gemm_x(OP_N, OP_N, m2, 1, true);   // G_ii is complex symmetric
         diag_step<T>(seps, DIAG_SEP, O_GR, 0, true);
       }
       // leaves
@@ -1052,6 +1131,9 @@ int run_steps(hsc_ctx* ctx, hipStream_t st, Plan* pl, int e_base, int nvalid, vo
         break;
       case S_INV_SUPER:
         launch_inv_super(st, (const InvJob*)jobs, s.njobs, s.i0, s.i1, s.i2);
+        break;
+      case S_MIRROR:
+        launch_mirror(st, s.i0, (const MirrorJob*)jobs, map, s.count);
         break;
       case S_GUARD:
         launch_guard(st, (const RowJob*)jobs, s.njobs, nclusters, e_base, nvalid, guard);
