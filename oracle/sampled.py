@@ -76,11 +76,9 @@ class _Factor:
 
     def _residual(self, b, x):
         """b - A^T x, accumulated in extended precision."""
-        n = len(self.at_ptr) - 1
         prod = self.at_val[:, None] * x[self.at_col]
-        rows = np.repeat(np.arange(n), np.diff(self.at_ptr))
-        ax = np.zeros((n, x.shape[1]), dtype=np.clongdouble)
-        np.add.at(ax, rows, prod)
+        # every row holds its diagonal entry, so no row segment is empty
+        ax = np.add.reduceat(prod, self.at_ptr[:-1], axis=0)
         return b.astype(np.clongdouble) - ax
 
     def solve_t(self, b):

@@ -238,68 +238,81 @@ __global__ __launch_bounds__(256) void k_dd_inv_unscramble(const InvJobDD* __res
 }
 
 // ---------------------------------------------------------------------------------------------
-// grouped complex double-double GEMM: 32 x 32 output tile, 256 threads, 2 x 2 outputs per thread,
-// lazily accumulated (dd.h: zddacc) and renormalised after every 8-deep k step.
+// grouped complex double-double GEMM: 256 threads as 16 x 16, each with an RM x RN block of outputs
+// (tile BM x BN = 16 RM x 16 RN: 32x32, 64x32 or 64x64), lazily accumulated (dd.h: zddacc) and
+// renormalised after every 8-deep k step.
 //   OPA 0: A'(m,k) = A[m*lda + k];  OPA 1: A'(m,k) = A[k*lda + m]
 //   OPB 0: B'(k,n) = B[k*ldb + n];  OPB 1: B'(k,n) = B[n*ldb + k]
-constexpr int DT = 32, DK = 8;
+constexpr int DK = 8;
+constexpr int kDDConfigs = 3;
+constexpr int kDDRM[kDDConfigs] = {2, 4, 4}, kDDRN[kDDConfigs] = {2, 2, 4};
 
-template <int OPA, int OPB>
+template <int OPA, int OPB, int RM, int RN>
 __global__ __launch_bounds__(256) void k_dd_gemm(const GemmProbDD* __restrict__ probs,
                                                  const int32_t* __restrict__ tile_prob, int total_tiles, int negate,
                                                  int beta) {
-  __shared__ zdd As[DK][DT + 1];
-  __shared__ zdd Bs[DK][DT + 1];
+  constexpr int BM = 16 * RM, BN = 16 * RN;
+  __shared__ zdd As[DK][BM + 1];
+  __shared__ zdd Bs[DK][BN + 1];
   const int per = (total_tiles + 7) >> 3;
   const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (tile >= total_tiles) return;
   const GemmProbDD& pr = probs[tile_prob[tile]];
   const int local = tile - pr.tile_off;
-  const int m0 = (local / pr.tiles_n) * DT, n0 = (local % pr.tiles_n) * DT;
+  const int m0 = (local / pr.tiles_n) * BM, n0 = (local % pr.tiles_n) * BN;
   const int M = pr.M, N = pr.N, K = pr.K;
   const int t = threadIdx.x;
-  const int tm = (t / 16) * 2, tn = (t % 16) * 2;   // this thread's 2 x 2 block
-  zddacc acc[2][2];
+  const int tm = (t / 16) * RM, tn = (t % 16) * RN;   // this thread's RM x RN block
+  zddacc acc[RM][RN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < RM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = zddacc{{0.0, 0.0}, {0.0, 0.0}};
+    for (int j = 0; j < RN; ++j) acc[i][j] = zddacc{{0.0, 0.0}, {0.0, 0.0}};
   for (int k0 = 0; k0 < K; k0 += DK) {
-    // stage A' (DT x DK) and B (DK x DT): 256 elements each, one per thread
-    {
-      const int mm = OPA == 0 ? t / DK : t % DT;
-      const int kk = OPA == 0 ? t % DK : t / DT;
+    // stage A' (BM x DK) and B' (DK x BN), RM / 2 and RN / 2 elements per thread
+#pragma unroll
+    for (int u = 0; u < RM / 2; ++u) {
+      const int idx = t + u * 256;
+      const int mm = OPA == 0 ? idx / DK : idx % BM;
+      const int kk = OPA == 0 ? idx % DK : idx / BM;
       const int gm = m0 + mm, gk = k0 + kk;
       zdd v = zdd_zero();
       if (gm < M && gk < K) v = OPA == 0 ? pr.A[(int64_t)gm * pr.lda + gk] : pr.A[(int64_t)gk * pr.lda + gm];
       As[kk][mm] = v;
-      const int bk = OPB == 0 ? t / DT : t % DK;
-      const int bn = OPB == 0 ? t % DT : t / DK;
+    }
+#pragma unroll
+    for (int u = 0; u < RN / 2; ++u) {
+      const int idx = t + u * 256;
+      const int bk = OPB == 0 ? idx / BN : idx % DK;
+      const int bn = OPB == 0 ? idx % BN : idx / DK;
       const int gbk = k0 + bk, gbn = n0 + bn;
-      zdd u = zdd_zero();
-      if (gbk < K && gbn < N) u = OPB == 0 ? pr.B[(int64_t)gbk * pr.ldb + gbn] : pr.B[(int64_t)gbn * pr.ldb + gbk];
-      Bs[bk][bn] = u;
+      zdd v = zdd_zero();
+      if (gbk < K && gbn < N) v = OPB == 0 ? pr.B[(int64_t)gbk * pr.ldb + gbn] : pr.B[(int64_t)gbn * pr.ldb + gbk];
+      Bs[bk][bn] = v;
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < DK; ++kk) {
-      const zdd a0 = As[kk][tm], a1 = As[kk][tm + 1];
-      const zdd b0 = Bs[kk][tn], b1 = Bs[kk][tn + 1];
-      zddacc_fma(acc[0][0], a0, b0);
-      zddacc_fma(acc[0][1], a0, b1);
-      zddacc_fma(acc[1][0], a1, b0);
-      zddacc_fma(acc[1][1], a1, b1);
+      zdd a[RM], b[RN];
+#pragma unroll
+      for (int i = 0; i < RM; ++i) a[i] = As[kk][tm + i];
+#pragma unroll
+      for (int j = 0; j < RN; ++j) b[j] = Bs[kk][tn + j];
+#pragma unroll
+      for (int i = 0; i < RM; ++i)
+#pragma unroll
+        for (int j = 0; j < RN; ++j) zddacc_fma(acc[i][j], a[i], b[j]);
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < RM; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) zddacc_renorm(acc[i][j]);
+      for (int j = 0; j < RN; ++j) zddacc_renorm(acc[i][j]);
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < RM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < RN; ++j) {
       const int row = m0 + tm + i, col = n0 + tn + j;
       if (row < M && col < N) {
         const zdd v = zddacc_value(acc[i][j]);
@@ -309,6 +322,20 @@ __global__ __launch_bounds__(256) void k_dd_gemm(const GemmProbDD* __restrict__ 
         if (pr.D64) pr.D64[(int64_t)row * pr.ldd64 + col] = zdd_round(o);
       }
     }
+}
+
+template <int RM, int RN>
+void dd_gemm_dispatch(hipStream_t st, int opA, int opB, const GemmProbDD* probs, const int32_t* tile_prob,
+                      int total_tiles, int negate, int beta) {
+  const dim3 g(((total_tiles + 7) / 8) * 8), b(256);
+  if (opA == 0 && opB == 0)
+    hipLaunchKernelGGL((k_dd_gemm<0, 0, RM, RN>), g, b, 0, st, probs, tile_prob, total_tiles, negate, beta);
+  else if (opA == 1 && opB == 0)
+    hipLaunchKernelGGL((k_dd_gemm<1, 0, RM, RN>), g, b, 0, st, probs, tile_prob, total_tiles, negate, beta);
+  else if (opA == 0)
+    hipLaunchKernelGGL((k_dd_gemm<0, 1, RM, RN>), g, b, 0, st, probs, tile_prob, total_tiles, negate, beta);
+  else
+    hipLaunchKernelGGL((k_dd_gemm<1, 1, RM, RN>), g, b, 0, st, probs, tile_prob, total_tiles, negate, beta);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -413,21 +440,17 @@ __global__ __launch_bounds__(RB) void k_dd_diag(const RowJob* __restrict__ jobs,
 
 }  // namespace
 
-int dd_gemm_tile() { return DT; }
+int dd_gemm_configs() { return kDDConfigs; }
+int dd_gemm_tile_m(int config) { return 16 * kDDRM[config]; }
+int dd_gemm_tile_n(int config) { return 16 * kDDRN[config]; }
 int dd_inv_nb(int max_n) { return max_n <= 512 ? 8 : max_n <= 1024 ? 8 : max_n <= 2048 ? 4 : 2; }
 
-void launch_dd_gemm(hipStream_t st, int opA, int opB, const GemmProbDD* probs, const int32_t* tile_prob,
-                    int total_tiles, int negate, int beta) {
+void launch_dd_gemm(hipStream_t st, int opA, int opB, int config, const GemmProbDD* probs,
+                    const int32_t* tile_prob, int total_tiles, int negate, int beta) {
   if (total_tiles <= 0) return;
-  const dim3 g(((total_tiles + 7) / 8) * 8), b(256);
-  if (opA == 0 && opB == 0)
-    hipLaunchKernelGGL((k_dd_gemm<0, 0>), g, b, 0, st, probs, tile_prob, total_tiles, negate, beta);
-  else if (opA == 1 && opB == 0)
-    hipLaunchKernelGGL((k_dd_gemm<1, 0>), g, b, 0, st, probs, tile_prob, total_tiles, negate, beta);
-  else if (opA == 0)
-    hipLaunchKernelGGL((k_dd_gemm<0, 1>), g, b, 0, st, probs, tile_prob, total_tiles, negate, beta);
-  else
-    hipLaunchKernelGGL((k_dd_gemm<1, 1>), g, b, 0, st, probs, tile_prob, total_tiles, negate, beta);
+  if (config == 1) dd_gemm_dispatch<4, 2>(st, opA, opB, probs, tile_prob, total_tiles, negate, beta);
+  else if (config == 2) dd_gemm_dispatch<4, 4>(st, opA, opB, probs, tile_prob, total_tiles, negate, beta);
+  else dd_gemm_dispatch<2, 2>(st, opA, opB, probs, tile_prob, total_tiles, negate, beta);
 }
 
 void launch_dd_gather(hipStream_t st, const RowJob* jobs, const int32_t* row_job, int total_rows, int trans, int op) {

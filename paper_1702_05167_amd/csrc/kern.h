@@ -172,9 +172,12 @@ struct GemmProbDD {
   int32_t tiles_n;
   int32_t tile_off;
 };
-int dd_gemm_tile();
-void launch_dd_gemm(hipStream_t st, int opA, int opB, const GemmProbDD* probs, const int32_t* tile_prob,
-                    int total_tiles, int negate, int beta);
+// tile configurations of the double-double GEMM: 0 = 32x32, 1 = 64x32, 2 = 64x64 (rows x columns)
+int dd_gemm_configs();
+int dd_gemm_tile_m(int config);
+int dd_gemm_tile_n(int config);
+void launch_dd_gemm(hipStream_t st, int opA, int opB, int config, const GemmProbDD* probs,
+                    const int32_t* tile_prob, int total_tiles, int negate, int beta);
 // extraction row kernels in double-double: RowJob.src / dst / p0 / p1 and ChildRef.U point to zdd;
 // same arguments as launch_gather, launch_assemble_n and launch_diag (outputs rounded to complex128)
 void launch_dd_gather(hipStream_t st, const RowJob* jobs, const int32_t* row_job, int total_rows, int trans, int op);

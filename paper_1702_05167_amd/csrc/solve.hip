@@ -546,42 +546,47 @@ struct Builder {
     q.D64 = g.D64 ? g.D64 + (size_t)r0 * g.ldd64 + r0 : nullptr;
     return q;
   }
+  // one problem list and tile map per tile configuration of the double-double GEMM (the tuner picks
+  // one per launch; `tile` is the configuration)
   void dd_gemm(int opA, int opB, const std::vector<GPD>& ps, int negate, int beta, bool upper = false) {
-    std::vector<GemmProbDD> probs;
-    std::vector<int32_t> tmap;
-    const int tt = dd_gemm_tile();
-    double fl = 0;
-    std::vector<GPD> parts;
-    for (const GPD& g0 : ps) {
-      if (g0.M <= 0 || g0.N <= 0) continue;
-      if (upper && g0.M == g0.N)
-        for (int r0 = 0; r0 < g0.M; r0 += tt) parts.push_back(strip(g0, r0, tt, opA, opB));
-      else
-        parts.push_back(g0);
-    }
-    for (const GPD& g : parts) {
-      GemmProbDD p{};
-      p.A = g.A; p.B = g.B; p.C = g.C; p.D = g.D; p.D64 = g.D64;
-      p.M = g.M; p.N = g.N; p.K = g.K;
-      p.lda = g.lda; p.ldb = g.ldb; p.ldc = g.ldc; p.ldd = g.ldd; p.ldd64 = g.ldd64;
-      p.tiles_n = (g.N + tt - 1) / tt;
-      p.tile_off = (int32_t)tmap.size();
-      const int tiles = ((g.M + tt - 1) / tt) * p.tiles_n;
-      for (int k = 0; k < tiles; ++k) tmap.push_back((int32_t)probs.size());
-      probs.push_back(p);
-      fl += 8.0 * g.M * g.N * g.K;
-    }
-    if (probs.empty()) return;
     Step s;
     s.kind = S_DD_GEMM;
-    s.jobs = blob.push(probs);
-    s.map = blob.push(tmap);
-    s.count = (int)tmap.size();
+    for (int cfg = 0; cfg < dd_gemm_configs(); ++cfg) {
+      const int tm = dd_gemm_tile_m(cfg), tn = dd_gemm_tile_n(cfg);
+      std::vector<GemmProbDD> probs;
+      std::vector<int32_t> tmap;
+      std::vector<GPD> parts;
+      for (const GPD& g0 : ps) {
+        if (g0.M <= 0 || g0.N <= 0) continue;
+        if (upper && g0.M == g0.N)
+          for (int r0 = 0; r0 < g0.M; r0 += tm) parts.push_back(strip(g0, r0, tm, opA, opB));
+        else
+          parts.push_back(g0);
+      }
+      for (const GPD& g : parts) {
+        GemmProbDD p{};
+        p.A = g.A; p.B = g.B; p.C = g.C; p.D = g.D; p.D64 = g.D64;
+        p.M = g.M; p.N = g.N; p.K = g.K;
+        p.lda = g.lda; p.ldb = g.ldb; p.ldc = g.ldc; p.ldd = g.ldd; p.ldd64 = g.ldd64;
+        p.tiles_n = (g.N + tn - 1) / tn;
+        p.tile_off = (int32_t)tmap.size();
+        const int tiles = ((g.M + tm - 1) / tm) * p.tiles_n;
+        for (int k = 0; k < tiles; ++k) tmap.push_back((int32_t)probs.size());
+        probs.push_back(p);
+        if (cfg == 0) s.flops += 8.0 * g.M * g.N * g.K;
+      }
+      if (probs.empty()) return;
+      s.jobs_k[cfg] = blob.push(probs);
+      s.map_k[cfg] = blob.push(tmap);
+      s.count_k[cfg] = (int)tmap.size();
+    }
+    s.jobs = s.jobs_k[0];
+    s.map = s.map_k[0];
+    s.count = s.count_k[0];
     s.i0 = opA;
     s.i1 = negate;
     s.i2 = opB;
     s.beta = beta;
-    s.flops = fl;
     steps.push_back(s);
     if (upper) {
       std::vector<MirrorJob> m32, m16;
@@ -1050,6 +1055,9 @@ hsc_status fold_events(hsc_ctx* ctx) {
   return HSC_OK;
 }
 
+// double-double GEMM tile configuration of an untuned plan (64x32)
+constexpr int kDefaultDDConfig = 1;
+
 // tile size used by a launch kind of launch_gemm
 int tile_dims_of(int kind) {
   switch (kind) {
@@ -1151,7 +1159,8 @@ int run_steps(hsc_ctx* ctx, hipStream_t st, Plan* pl, int e_base, int nvalid, vo
         launch_dd_inv_unscramble(st, (const InvJobDD*)jobs, s.njobs, s.i2);
         break;
       case S_DD_GEMM:
-        launch_dd_gemm(st, s.i0, s.i2, (const GemmProbDD*)jobs, map, s.count, s.i1, s.beta);
+        launch_dd_gemm(st, s.i0, s.i2, s.tile, (const GemmProbDD*)(pl->blob + s.jobs_k[s.tile]),
+                       reinterpret_cast<const int32_t*>(pl->blob + s.map_k[s.tile]), s.count_k[s.tile], s.i1, s.beta);
         break;
       case S_DIAG: {
         void* out = nullptr;
@@ -1185,6 +1194,27 @@ hsc_status tune_plan(hsc_ctx* ctx, Plan* pl) {
   hipStream_t st = ctx->stream;
   hsc_status rc = HSC_OK;
   for (Step& s : pl->steps) {
+    if (s.kind == S_DD_GEMM) {
+      float best = 0.f;
+      int best_c = s.tile;
+      for (int c = 0; c < dd_gemm_configs() && rc == HSC_OK; ++c) {
+        float ms = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {
+          if (hipEventRecord(a, st) != hipSuccess) { rc = HSC_E_HIP; break; }
+          launch_dd_gemm(st, s.i0, s.i2, c, (const GemmProbDD*)(pl->blob + s.jobs_k[c]),
+                         reinterpret_cast<const int32_t*>(pl->blob + s.map_k[c]), s.count_k[c], s.i1, s.beta);
+          if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+              hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+            rc = HSC_E_HIP;
+            break;
+          }
+        }
+        if (rc == HSC_OK && (c == 0 || ms < best)) { best = ms; best_c = c; }
+      }
+      if (rc != HSC_OK) break;
+      s.tile = best_c;
+      continue;
+    }
     if (s.kind != S_GEMM) continue;
     float best = 0.f;
     int best_k = s.tile;
@@ -1307,8 +1337,10 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
     pl->lp.coupling[c] = t->contact[c].coupling;
   }
   pl->steps = std::move(b.steps);
-  for (Step& s : pl->steps)
+  for (Step& s : pl->steps) {
     if (s.kind == S_GEMM) s.tile = m3 ? 4 : 0;   // default kernels: 64x64 tiles, 16x16x4 MFMA
+    if (s.kind == S_DD_GEMM) s.tile = kDefaultDDConfig;
+  }
   if (tune) {
     const hsc_status rc = tune_plan(ctx, pl.get());
     if (rc != HSC_OK) return rc;
