@@ -132,7 +132,8 @@ typedef struct {
    * over 8 waves, 128x128 on the 16x16x4 MFMA; 64x64 on the 4x4x4 MFMA) on each
    * of its launches and keep the fastest per launch; 0: 64x64 everywhere.  With
    * complex3m = 1 the candidates are the three-product kernels plus the 128x128
-   * four-product one.  Results agree to rounding. */
+   * four-product one.  Double-double products (precision >= 1) are timed with
+   * 32x32, 64x32 and 64x64 tiles (untuned: 64x32).  Results agree to rounding. */
   int32_t tune;
   /* Complex block products: 0 = four real products per complex multiply-add
    * (Re = ArBr - AiBi, Im = ArBi + AiBr); 1 = three (Gauss: ArBr, AiBi,
