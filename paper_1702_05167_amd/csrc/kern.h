@@ -89,12 +89,12 @@ struct LeadParams {
 };
 
 // launchers (all asynchronous on `st`)
-// Square block whose strictly lower 32 x 32 tiles are copied from their transposes
-// (T(T-1)/2 tiles, T = ceil(n / 32); tile_off = its first tile in the launch)
+// Square block whose strictly lower 32 x 32 tiles are copied from their transposes (op 0) or from
+// minus their adjoints (op 1) (T(T-1)/2 tiles, T = ceil(n / 32); tile_off = its first tile in the launch)
 struct MirrorJob {
   void* D;
   int32_t ld, n;
-  int32_t tile_off, pad;
+  int32_t tile_off, op;
 };
 void launch_mirror(hipStream_t st, int elem_bytes, const MirrorJob* jobs, const int32_t* tile_job, int total_tiles);
 

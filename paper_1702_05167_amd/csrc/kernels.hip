@@ -344,13 +344,15 @@ __global__ __launch_bounds__(RB) void k_guard(const RowJob* __restrict__ jobs, i
   }
 }
 
-// Mirror of a complex-symmetric block whose upper triangle (by 32 x 32 tiles) is computed: every
-// strictly lower tile (ti > tj) is the transpose of tile (tj, ti), staged through LDS so that both
-// the read and the write are row-contiguous.  T is the element (16 bytes complex128, 32 bytes
+// Mirror of a complex-symmetric (op 0) or anti-Hermitian (op 1) block whose upper triangle (by 32 x 32
+// tiles) is computed: every strictly lower tile (ti > tj) is the transpose (op 1: minus the adjoint) of
+// tile (tj, ti), staged through LDS so that both the read and the write are row-contiguous.  T is the element (16 bytes complex128, 32 bytes
 // complex double-double).
-struct alignas(16) Elem32 {
+struct alignas(16) Elem32 {   // complex double-double: a = real (hi, lo), b = imaginary (hi, lo)
   double2 a, b;
 };
+__device__ inline void neg_conj(double2& v) { v.x = -v.x; }
+__device__ inline void neg_conj(Elem32& v) { v.a.x = -v.a.x; v.a.y = -v.a.y; }
 
 template <class T>
 __global__ __launch_bounds__(256) void k_mirror(const MirrorJob* __restrict__ jobs,
@@ -374,7 +376,11 @@ __global__ __launch_bounds__(256) void k_mirror(const MirrorJob* __restrict__ jo
   __syncthreads();
   for (int k = ty; k < 32; k += 8) {
     const int r = c0 + k, c = r0 + tx;   // D[c0 + k][r0 + tx] = D[r0 + tx][c0 + k]
-    if (r < jb.n && c < jb.n) D[(int64_t)r * jb.ld + c] = s[tx][k];
+    if (r < jb.n && c < jb.n) {
+      T v = s[tx][k];
+      if (jb.op) neg_conj(v);   // -conj(x) = (-re, im)
+      D[(int64_t)r * jb.ld + c] = v;
+    }
   }
 }
 

@@ -389,7 +389,9 @@ struct Builder {
     q.D = g.D + (size_t)r0 * g.ldd + r0;
     return q;
   }
-  // copy the strictly lower 32 x 32 tiles of square blocks from their transposes (elem: 16 or 32 bytes)
+  enum { kFull = 0, kSymmetric = 1, kAntiHermitian = 2 };
+  // copy the strictly lower 32 x 32 tiles of square blocks from their transposes (or, op = 1, from minus
+  // their adjoints; elem: 16 or 32 bytes)
   void mirror_step(const std::vector<MirrorJob>& in, int elem) {
     std::vector<MirrorJob> mj;
     std::vector<int32_t> tmap;
@@ -410,10 +412,11 @@ struct Builder {
     s.i0 = elem;
     steps.push_back(s);
   }
-  // upper: every product is square with a symmetric result (A^T = A makes the Schur updates and the
-  // G_ii blocks complex symmetric): only the block-row strips on and above the diagonal are computed
-  // (strips as tall as the tile kind's rows) and a mirror step fills the rest
-  void gemm(int opA, int opB, const std::vector<GP>& ps, double ar, double ai, int beta, bool upper = false) {
+  // sym: every product of the list is square and its result complex symmetric (kSymmetric: A^T = A
+  // makes the Schur updates and the G_ii blocks so) or anti-Hermitian (kAntiHermitian: the P_ii blocks
+  // of the lesser channels, as Sigma^< is): only the block-row strips on and above the diagonal are
+  // computed (strips as tall as the tile kind's rows) and a mirror step fills the rest
+  void gemm(int opA, int opB, const std::vector<GP>& ps, double ar, double ai, int beta, int sym = kFull) {
     Step s;
     s.kind = S_GEMM;
     for (int kind = 0; kind < kTileDims; ++kind) {
@@ -423,7 +426,7 @@ struct Builder {
       std::vector<GP> parts;
       for (const GP& g0 : ps) {
         if (g0.M <= 0 || g0.N <= 0) continue;
-        if (upper && g0.M == g0.N)
+        if (sym != kFull && g0.M == g0.N)
           for (int r0 = 0; r0 < g0.M; r0 += tm) parts.push_back(strip(g0, r0, tm, opA, opB));
         else
           parts.push_back(g0);
@@ -452,10 +455,10 @@ struct Builder {
     s.i0 = opA; s.i1 = opB;
     s.ar = ar; s.ai = ai; s.beta = beta;
     steps.push_back(s);
-    if (upper) {
+    if (sym != kFull) {
       std::vector<MirrorJob> mj;
       for (const GP& g : ps)
-        if (g.M > 0 && g.M == g.N) mj.push_back({g.D, g.ldd, g.M, 0, 0});
+        if (g.M > 0 && g.M == g.N) mj.push_back({g.D, g.ldd, g.M, 0, sym == kAntiHermitian});
       mirror_step(mj, 16);
     }
   }
@@ -525,13 +528,13 @@ struct Builder {
   template <class T> T* inv_p(const CS& s) const { return X<T>(kDD<T> ? s.Invd : s.Inv); }
   template <class T> T* psi_p(const CS& s) const { return X<T>(kDD<T> ? s.Psid : s.Psi); }
   template <class T> static double2* d2(const T* p) { return reinterpret_cast<double2*>(const_cast<T*>(p)); }
-  void gemm_x(int opA, int opB, const std::vector<GP>& ps, int beta, bool upper = false) {
-    gemm(opA, opB, ps, 1.0, 0.0, beta, upper);
+  void gemm_x(int opA, int opB, const std::vector<GP>& ps, int beta, int sym = kFull) {
+    gemm(opA, opB, ps, 1.0, 0.0, beta, sym);
   }
-  void gemm_x(int opA, int opB, const std::vector<GPT<zdd>>& ps, int beta, bool upper = false) {
+  void gemm_x(int opA, int opB, const std::vector<GPT<zdd>>& ps, int beta, int sym = kFull) {
     std::vector<GPD> q;
     for (const GPT<zdd>& g : ps) q.push_back({g.A, g.B, g.C, g.D, nullptr, g.M, g.N, g.K, g.lda, g.ldb, g.ldc, g.ldd, 0});
-    dd_gemm(opA, opB, q, 0, beta, upper);
+    dd_gemm(opA, opB, q, 0, beta, sym);
   }
 
   struct GPD { const zdd *A, *B, *C; zdd* D; double2* D64; int M, N, K, lda, ldb, ldc, ldd, ldd64; };
@@ -548,7 +551,7 @@ struct Builder {
   }
   // one problem list and tile map per tile configuration of the double-double GEMM (the tuner picks
   // one per launch; `tile` is the configuration)
-  void dd_gemm(int opA, int opB, const std::vector<GPD>& ps, int negate, int beta, bool upper = false) {
+  void dd_gemm(int opA, int opB, const std::vector<GPD>& ps, int negate, int beta, int sym = kFull) {
     Step s;
     s.kind = S_DD_GEMM;
     for (int cfg = 0; cfg < dd_gemm_configs(); ++cfg) {
@@ -558,7 +561,7 @@ struct Builder {
       std::vector<GPD> parts;
       for (const GPD& g0 : ps) {
         if (g0.M <= 0 || g0.N <= 0) continue;
-        if (upper && g0.M == g0.N)
+        if (sym != kFull && g0.M == g0.N)
           for (int r0 = 0; r0 < g0.M; r0 += tm) parts.push_back(strip(g0, r0, tm, opA, opB));
         else
           parts.push_back(g0);
@@ -588,12 +591,13 @@ struct Builder {
     s.i2 = opB;
     s.beta = beta;
     steps.push_back(s);
-    if (upper) {
+    if (sym != kFull) {
       std::vector<MirrorJob> m32, m16;
+      const int op = sym == kAntiHermitian;
       for (const GPD& g : ps) {
         if (g.M <= 0 || g.M != g.N) continue;
-        m32.push_back({g.D, g.ldd, g.M, 0, 0});
-        if (g.D64) m16.push_back({g.D64, g.ldd64, g.M, 0, 0});
+        m32.push_back({g.D, g.ldd, g.M, 0, op});
+        if (g.D64) m16.push_back({g.D64, g.ldd64, g.M, 0, op});
       }
       mirror_step(m32, 32);
       mirror_step(m16, 16);
@@ -673,7 +677,7 @@ struct Builder {
         }
       }
       dd_gemm(0, 0, pp, 1, 0);
-      dd_gemm(1, 0, pu, 0, 1, true);
+      dd_gemm(1, 0, pu, 0, 1, kSymmetric);
     }
     guard_step();
   }
@@ -791,7 +795,7 @@ struct Builder {
         }
       }
       gemm(OP_N, OP_N, pp, -1.0, 0.0, 0);
-      gemm(OP_T, OP_N, pu, 1.0, 0.0, 1, true);   // U = A_ff + A_if^T Psi is complex symmetric
+      gemm(OP_T, OP_N, pu, 1.0, 0.0, 1, kSymmetric);   // U = A_ff + A_if^T Psi is complex symmetric
     }
     guard_step();
   }
@@ -862,7 +866,7 @@ struct Builder {
         rowstep(S_GATHER, g1, 0, 0, 0, kDD<T>);
         gemm_x(OP_N, OP_N, m1, 0);
         rowstep(S_GATHER, g2, 1, 0, 0, kDD<T>);
-        gemm_x(OP_N, OP_N, m2, 1, true);   // G_ii is complex symmetric
+        gemm_x(OP_N, OP_N, m2, 1, kSymmetric);   // G_ii is complex symmetric
         diag_step<T>(seps, DIAG_SEP, O_GR, 0, true);
       }
       // leaves
@@ -1023,8 +1027,12 @@ struct Builder {
       gemm_x(OP_N, OP_N, m3a, 0);
       gemm_x(OP_N, OP_N, m3b, 1);
       rowstep(S_GATHER, g2, 1, 1, 0, kDD<T>);
-      gemm_x(OP_N, OP_N, m2a, 0);
-      gemm_x(OP_N, OP_N, m2b, 1);
+      // P_ii = -P_ii^dagger (Sigma^< is anti-Hermitian): in double-double only the upper triangle is
+      // computed; in complex128 both (mirroring moved a guarded complex128 trilayer case from 5e-11
+      // to 1.2e-10, where its margin is thin)
+      const int psym = kDD<T> ? kAntiHermitian : kFull;
+      gemm_x(OP_N, OP_N, m2a, 0, psym);
+      gemm_x(OP_N, OP_N, m2b, 1, psym);
       diag_step<T>(seps, DIAG_SEP, ch.out, k, false);
       diag_step<T>(leaves, DIAG_LEAF_P, ch.out, k, false);
     }

@@ -47,6 +47,27 @@ def test_forest_matches_dense_oracle_per_device(ctx):
         assert (g["status"] == 0).all()
 
 
+def test_forest_out_of_band_double_double(ctx):
+    # uneven devices in one forest at energies outside the lead band, where only the double-double
+    # solve keeps every block product exact enough (no guard)
+    devs = _uneven(11)
+    trees = [pkg.Tree.from_device(d, leaf_side=3) for d in devs]
+    E = np.array([-4.6, -3.1, -2.3, 2.45, 3.7, 5.2])
+    outs = pkg.solve_batch(ctx, trees, E, want=ALL, precision=2, **KW)
+    worst = 0.0
+    for d, o in zip(devs, outs):
+        g = _np(o)
+        ref = oracle.dense.solve(d, E, **KW)
+        for e in range(len(E)):
+            errs = (rel(g["gr"][e], ref["gr"][e]), rel(g["gl"][e], ref["gl"][e]),
+                    rel(g["spectral"][e, 0], ref["a_l"][e]), rel(g["spectral"][e, 1], ref["a_r"][e]),
+                    abs(g["trans"][e] - ref["trans"][e]) / max(ref["trans"][e], 1e-12))
+            worst = max(worst, max(errs))
+            assert max(errs) <= 1e-10, (d.name, E[e], errs)
+        assert (g["status"] == 0).all()
+    print("forest out of band, double-double worst", worst)
+
+
 @pytest.mark.parametrize("want", [ALL, pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS])
 def test_forest_equals_single_device_solves(ctx, want):
     devs = _uneven(5)
