@@ -121,7 +121,8 @@ def main():
     tree = pkg.Tree.from_device(dev, leaf_side=args.leaf, transverse=args.transverse)
     st = tree.stats()
     ctx = pkg.Context(0)
-    E = torch.linspace(-6.0, 6.0, NE, dtype=torch.float64, device="cuda:0")
+    # the grid as numpy builds it (torch.linspace differs from it by an ulp at some points)
+    E = torch.tensor(np.linspace(-6.0, 6.0, NE), dtype=torch.float64, device="cuda:0")
     kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=args.precision, complex3m=args.complex3m,
               tune=args.tune)
     want = pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS
@@ -266,7 +267,7 @@ def trilayer_study(pkg, synth, np, torch, args):
     dev = synth.trilayer()
     tree = pkg.Tree.from_device(dev, leaf_side=8)
     ctx = pkg.Context(0)
-    E = torch.linspace(-3.0, 3.0, 512, dtype=torch.float64, device="cuda:0")
+    E = torch.tensor(np.linspace(-3.0, 3.0, 512), dtype=torch.float64, device="cuda:0")
     kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=args.precision, complex3m=args.complex3m,
               tune=args.tune, want=pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS)
     out = pkg.solve(ctx, tree, E, **kw)
@@ -302,7 +303,8 @@ def uneven_study(pkg, synth, np, torch, args):
     ctx = pkg.Context(0)
     devs = synth.config2_devices(which=range(D))
     trees = [pkg.Tree.from_device(d, leaf_side=4, transverse=True) for d in devs]
-    E = torch.linspace(-6.0, 6.0, NE, dtype=torch.float64, device="cuda:0")
+    # the grid as numpy builds it (torch.linspace differs from it by an ulp at some points)
+    E = torch.tensor(np.linspace(-6.0, 6.0, NE), dtype=torch.float64, device="cuda:0")
     # no tile tuning here: with more devices than cached plans, plans are rebuilt per call
     kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=0, complex3m=args.complex3m, tune=0,
               want=pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS)

@@ -251,12 +251,9 @@ hsc_status hsc_totals(hsc_ctx* ctx, int32_t n_e, int64_t n, const void* diag_gr,
  * 0 assemble, 1 inverse panel, 2 inverse swap, 3 inverse unscramble, 4 GEMM,
  * 5 gather, 6 N assembly, 7 diagonal output, 8 growth indicators, 9-13 the
  * double-double assemble / panel / swap / unscramble / GEMM, 14 inverse
- * super-panel preparation, 15 mirror of a symmetric block (the complex-symmetric
- * products, Schur updates and G_ii blocks, are computed on and above the
- * diagonal only, then mirrored).
+ * super-panel preparation.
  * hsc_ctx_profile_read writes out[3*k + {0,1,2}] = launches, milliseconds,
- * algorithmic real flops (GEMM: 8 M N K per problem, counting the computed
- * part of a symmetric product) for k < n_kinds.
+ * algorithmic real flops (GEMM: 8 M N K per problem) for k < n_kinds.
  * Errors: HSC_E_ARG. */
 hsc_status hsc_ctx_profile(hsc_ctx* ctx, int32_t enable);
 hsc_status hsc_ctx_profile_read(hsc_ctx* ctx, double* out, int32_t n_kinds);

@@ -89,15 +89,6 @@ struct LeadParams {
 };
 
 // launchers (all asynchronous on `st`)
-// Square block whose strictly lower 32 x 32 tiles are copied from their transposes (op 0) or from
-// minus their adjoints (op 1) (T(T-1)/2 tiles, T = ceil(n / 32); tile_off = its first tile in the launch)
-struct MirrorJob {
-  void* D;
-  int32_t ld, n;
-  int32_t tile_off, op;
-};
-void launch_mirror(hipStream_t st, int elem_bytes, const MirrorJob* jobs, const int32_t* tile_job, int total_tiles);
-
 // tile_prob[t] = problem owning tile t (host-built map; one entry per tile)
 void launch_gemm(hipStream_t st, int opA, int opB, const GemmProb* probs, const int32_t* tile_prob,
                  int total_tiles, double alpha_re, double alpha_im, int beta, int tile_kind);

@@ -344,46 +344,6 @@ __global__ __launch_bounds__(RB) void k_guard(const RowJob* __restrict__ jobs, i
   }
 }
 
-// Mirror of a complex-symmetric (op 0) or anti-Hermitian (op 1) block whose upper triangle (by 32 x 32
-// tiles) is computed: every strictly lower tile (ti > tj) is the transpose (op 1: minus the adjoint) of
-// tile (tj, ti), staged through LDS so that both the read and the write are row-contiguous.  T is the element (16 bytes complex128, 32 bytes
-// complex double-double).
-struct alignas(16) Elem32 {   // complex double-double: a = real (hi, lo), b = imaginary (hi, lo)
-  double2 a, b;
-};
-__device__ inline void neg_conj(double2& v) { v.x = -v.x; }
-__device__ inline void neg_conj(Elem32& v) { v.a.x = -v.a.x; v.a.y = -v.a.y; }
-
-template <class T>
-__global__ __launch_bounds__(256) void k_mirror(const MirrorJob* __restrict__ jobs,
-                                                const int32_t* __restrict__ tile_job) {
-  __shared__ T s[32][33];
-  const int tile = blockIdx.x;
-  const MirrorJob& jb = jobs[tile_job[tile]];
-  const int local = tile - jb.tile_off;
-  // local = ti (ti - 1) / 2 + tj, 0 <= tj < ti
-  int ti = (int)((1.0 + sqrt(1.0 + 8.0 * (double)local)) * 0.5);
-  while (ti * (ti - 1) / 2 > local) --ti;
-  while ((ti + 1) * ti / 2 <= local) ++ti;
-  const int tj = local - ti * (ti - 1) / 2;
-  T* D = reinterpret_cast<T*>(jb.D);
-  const int r0 = tj * 32, c0 = ti * 32;   // source tile: rows r0.., columns c0..
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  for (int k = ty; k < 32; k += 8) {
-    const int r = r0 + k, c = c0 + tx;
-    if (r < jb.n && c < jb.n) s[k][tx] = D[(int64_t)r * jb.ld + c];
-  }
-  __syncthreads();
-  for (int k = ty; k < 32; k += 8) {
-    const int r = c0 + k, c = r0 + tx;   // D[c0 + k][r0 + tx] = D[r0 + tx][c0 + k]
-    if (r < jb.n && c < jb.n) {
-      T v = s[tx][k];
-      if (jb.op) neg_conj(v);   // -conj(x) = (-re, im)
-      D[(int64_t)r * jb.ld + c] = v;
-    }
-  }
-}
-
 }  // namespace
 
 void launch_guard(hipStream_t st, const RowJob* jobs, int njobs, int nclusters, int e_base, int nvalid,
@@ -498,14 +458,6 @@ __global__ __launch_bounds__(256) void k_totals(int64_t n, const double2* __rest
 void launch_totals(hipStream_t st, int n_e, int64_t n, const double2* gr, const double2* gl, const double* spec,
                    double* totals) {
   hipLaunchKernelGGL(k_totals, dim3(n_e), dim3(256), 0, st, n, gr, gl, spec, totals);
-}
-
-void launch_mirror(hipStream_t st, int elem_bytes, const MirrorJob* jobs, const int32_t* tile_job, int total_tiles) {
-  if (total_tiles <= 0) return;
-  if (elem_bytes == 32)
-    hipLaunchKernelGGL(k_mirror<Elem32>, dim3(total_tiles), dim3(256), 0, st, jobs, tile_job);
-  else
-    hipLaunchKernelGGL(k_mirror<double2>, dim3(total_tiles), dim3(256), 0, st, jobs, tile_job);
 }
 
 }  // namespace hsc

@@ -56,7 +56,7 @@ struct Blob {
 };
 
 enum StepKind { S_ASSEMBLE, S_INV_PANEL, S_INV_SWAP, S_INV_UNSCR, S_GEMM, S_GATHER, S_ASSEMBLE_N, S_DIAG, S_GUARD,
-                S_DD_ASSEMBLE, S_DD_INV_PANEL, S_DD_INV_SWAP, S_DD_INV_UNSCR, S_DD_GEMM, S_INV_SUPER, S_MIRROR};
+                S_DD_ASSEMBLE, S_DD_INV_PANEL, S_DD_INV_SWAP, S_DD_INV_UNSCR, S_DD_GEMM, S_INV_SUPER};
 
 // Tile sizes a plan keeps GEMM problem lists and tile maps for: 64x64, 128x64, 64x128, 32x32,
 // 128x128.  Every launch kind of launch_gemm uses one of them (tile_dims_of).
@@ -377,61 +377,15 @@ struct Builder {
   // ---- step helpers ----
   template <class T> struct GPT { const T *A, *B, *C; T* D; int M, N, K, lda, ldb, ldc, ldd; };
   using GP = GPT<double2>;
-  // rows [r0, r0 + h) of a square product restricted to columns >= r0 (one block-row strip of its
-  // upper triangle): op(A) rows, op(B) columns and the C / D blocks move with the strip
-  template <class G> static G strip(const G& g, int r0, int h, int opA, int opB) {
-    G q = g;
-    q.M = std::min(h, g.M - r0);
-    q.N = g.N - r0;
-    q.A = opA == OP_N ? g.A + (size_t)r0 * g.lda : g.A + r0;
-    q.B = opB == OP_N ? g.B + r0 : g.B + (size_t)r0 * g.ldb;
-    q.C = g.C ? g.C + (size_t)r0 * g.ldc + r0 : nullptr;
-    q.D = g.D + (size_t)r0 * g.ldd + r0;
-    return q;
-  }
-  enum { kFull = 0, kSymmetric = 1, kAntiHermitian = 2 };
-  // copy the strictly lower 32 x 32 tiles of square blocks from their transposes (or, op = 1, from minus
-  // their adjoints; elem: 16 or 32 bytes)
-  void mirror_step(const std::vector<MirrorJob>& in, int elem) {
-    std::vector<MirrorJob> mj;
-    std::vector<int32_t> tmap;
-    for (MirrorJob m : in) {
-      const int T = (m.n + 31) / 32;
-      const int tiles = T * (T - 1) / 2;
-      if (tiles <= 0) continue;
-      m.tile_off = (int32_t)tmap.size();
-      for (int k = 0; k < tiles; ++k) tmap.push_back((int32_t)mj.size());
-      mj.push_back(m);
-    }
-    if (mj.empty()) return;
-    Step s;
-    s.kind = S_MIRROR;
-    s.jobs = blob.push(mj);
-    s.map = blob.push(tmap);
-    s.count = (int)tmap.size();
-    s.i0 = elem;
-    steps.push_back(s);
-  }
-  // sym: every product of the list is square and its result complex symmetric (kSymmetric: A^T = A
-  // makes the Schur updates and the G_ii blocks so) or anti-Hermitian (kAntiHermitian: the P_ii blocks
-  // of the lesser channels, as Sigma^< is): only the block-row strips on and above the diagonal are
-  // computed (strips as tall as the tile kind's rows) and a mirror step fills the rest
-  void gemm(int opA, int opB, const std::vector<GP>& ps, double ar, double ai, int beta, int sym = kFull) {
+  void gemm(int opA, int opB, const std::vector<GP>& ps, double ar, double ai, int beta) {
     Step s;
     s.kind = S_GEMM;
     for (int kind = 0; kind < kTileDims; ++kind) {
       std::vector<GemmProb> probs;
       std::vector<int32_t> tmap;
       const int tm = kTileDimM[kind], tn = kTileDimN[kind];
-      std::vector<GP> parts;
-      for (const GP& g0 : ps) {
-        if (g0.M <= 0 || g0.N <= 0) continue;
-        if (sym != kFull && g0.M == g0.N)
-          for (int r0 = 0; r0 < g0.M; r0 += tm) parts.push_back(strip(g0, r0, tm, opA, opB));
-        else
-          parts.push_back(g0);
-      }
-      for (const GP& g : parts) {
+      for (const GP& g : ps) {
+        if (g.M <= 0 || g.N <= 0) continue;
         GemmProb p{};
         p.A = g.A; p.B = g.B; p.C = g.C; p.D = g.D;
         p.M = g.M; p.N = g.N; p.K = g.K;
@@ -455,12 +409,6 @@ struct Builder {
     s.i0 = opA; s.i1 = opB;
     s.ar = ar; s.ai = ai; s.beta = beta;
     steps.push_back(s);
-    if (sym != kFull) {
-      std::vector<MirrorJob> mj;
-      for (const GP& g : ps)
-        if (g.M > 0 && g.M == g.N) mj.push_back({g.D, g.ldd, g.M, 0, sym == kAntiHermitian});
-      mirror_step(mj, 16);
-    }
   }
   // RowJob list: child-ref arrays are given as host vectors to be placed in the blob
   struct RJ { RowJob j; std::vector<ChildRef> kids; std::vector<size_t> kid_invrel; bool p1_blob = false; };
@@ -528,45 +476,25 @@ struct Builder {
   template <class T> T* inv_p(const CS& s) const { return X<T>(kDD<T> ? s.Invd : s.Inv); }
   template <class T> T* psi_p(const CS& s) const { return X<T>(kDD<T> ? s.Psid : s.Psi); }
   template <class T> static double2* d2(const T* p) { return reinterpret_cast<double2*>(const_cast<T*>(p)); }
-  void gemm_x(int opA, int opB, const std::vector<GP>& ps, int beta, int sym = kFull) {
-    gemm(opA, opB, ps, 1.0, 0.0, beta, sym);
-  }
-  void gemm_x(int opA, int opB, const std::vector<GPT<zdd>>& ps, int beta, int sym = kFull) {
+  void gemm_x(int opA, int opB, const std::vector<GP>& ps, int beta) { gemm(opA, opB, ps, 1.0, 0.0, beta); }
+  void gemm_x(int opA, int opB, const std::vector<GPT<zdd>>& ps, int beta) {
     std::vector<GPD> q;
     for (const GPT<zdd>& g : ps) q.push_back({g.A, g.B, g.C, g.D, nullptr, g.M, g.N, g.K, g.lda, g.ldb, g.ldc, g.ldd, 0});
-    dd_gemm(opA, opB, q, 0, beta, sym);
+    dd_gemm(opA, opB, q, 0, beta);
   }
 
   struct GPD { const zdd *A, *B, *C; zdd* D; double2* D64; int M, N, K, lda, ldb, ldc, ldd, ldd64; };
-  static GPD strip(const GPD& g, int r0, int h, int opA, int opB) {
-    GPD q = g;
-    q.M = std::min(h, g.M - r0);
-    q.N = g.N - r0;
-    q.A = opA == OP_N ? g.A + (size_t)r0 * g.lda : g.A + r0;
-    q.B = opB == OP_N ? g.B + r0 : g.B + (size_t)r0 * g.ldb;
-    q.C = g.C ? g.C + (size_t)r0 * g.ldc + r0 : nullptr;
-    q.D = g.D + (size_t)r0 * g.ldd + r0;
-    q.D64 = g.D64 ? g.D64 + (size_t)r0 * g.ldd64 + r0 : nullptr;
-    return q;
-  }
   // one problem list and tile map per tile configuration of the double-double GEMM (the tuner picks
   // one per launch; `tile` is the configuration)
-  void dd_gemm(int opA, int opB, const std::vector<GPD>& ps, int negate, int beta, int sym = kFull) {
+  void dd_gemm(int opA, int opB, const std::vector<GPD>& ps, int negate, int beta) {
     Step s;
     s.kind = S_DD_GEMM;
     for (int cfg = 0; cfg < dd_gemm_configs(); ++cfg) {
       const int tm = dd_gemm_tile_m(cfg), tn = dd_gemm_tile_n(cfg);
       std::vector<GemmProbDD> probs;
       std::vector<int32_t> tmap;
-      std::vector<GPD> parts;
-      for (const GPD& g0 : ps) {
-        if (g0.M <= 0 || g0.N <= 0) continue;
-        if (sym != kFull && g0.M == g0.N)
-          for (int r0 = 0; r0 < g0.M; r0 += tm) parts.push_back(strip(g0, r0, tm, opA, opB));
-        else
-          parts.push_back(g0);
-      }
-      for (const GPD& g : parts) {
+      for (const GPD& g : ps) {
+        if (g.M <= 0 || g.N <= 0) continue;
         GemmProbDD p{};
         p.A = g.A; p.B = g.B; p.C = g.C; p.D = g.D; p.D64 = g.D64;
         p.M = g.M; p.N = g.N; p.K = g.K;
@@ -591,17 +519,6 @@ struct Builder {
     s.i2 = opB;
     s.beta = beta;
     steps.push_back(s);
-    if (sym != kFull) {
-      std::vector<MirrorJob> m32, m16;
-      const int op = sym == kAntiHermitian;
-      for (const GPD& g : ps) {
-        if (g.M <= 0 || g.M != g.N) continue;
-        m32.push_back({g.D, g.ldd, g.M, 0, op});
-        if (g.D64) m16.push_back({g.D64, g.ldd64, g.M, 0, op});
-      }
-      mirror_step(m32, 32);
-      mirror_step(m16, 16);
-    }
   }
 
   void fold_dd(const std::vector<std::vector<int>>& L) {
@@ -677,7 +594,7 @@ struct Builder {
         }
       }
       dd_gemm(0, 0, pp, 1, 0);
-      dd_gemm(1, 0, pu, 0, 1, kSymmetric);
+      dd_gemm(1, 0, pu, 0, 1);
     }
     guard_step();
   }
@@ -795,7 +712,7 @@ struct Builder {
         }
       }
       gemm(OP_N, OP_N, pp, -1.0, 0.0, 0);
-      gemm(OP_T, OP_N, pu, 1.0, 0.0, 1, kSymmetric);   // U = A_ff + A_if^T Psi is complex symmetric
+      gemm(OP_T, OP_N, pu, 1.0, 0.0, 1);
     }
     guard_step();
   }
@@ -866,7 +783,7 @@ struct Builder {
         rowstep(S_GATHER, g1, 0, 0, 0, kDD<T>);
         gemm_x(OP_N, OP_N, m1, 0);
         rowstep(S_GATHER, g2, 1, 0, 0, kDD<T>);
-        gemm_x(OP_N, OP_N, m2, 1, kSymmetric);   // G_ii is complex symmetric
+        gemm_x(OP_N, OP_N, m2, 1);
         diag_step<T>(seps, DIAG_SEP, O_GR, 0, true);
       }
       // leaves
@@ -1027,12 +944,8 @@ struct Builder {
       gemm_x(OP_N, OP_N, m3a, 0);
       gemm_x(OP_N, OP_N, m3b, 1);
       rowstep(S_GATHER, g2, 1, 1, 0, kDD<T>);
-      // P_ii = -P_ii^dagger (Sigma^< is anti-Hermitian): in double-double only the upper triangle is
-      // computed; in complex128 both (mirroring moved a guarded complex128 trilayer case from 5e-11
-      // to 1.2e-10, where its margin is thin)
-      const int psym = kDD<T> ? kAntiHermitian : kFull;
-      gemm_x(OP_N, OP_N, m2a, 0, psym);
-      gemm_x(OP_N, OP_N, m2b, 1, psym);
+      gemm_x(OP_N, OP_N, m2a, 0);
+      gemm_x(OP_N, OP_N, m2b, 1);
       diag_step<T>(seps, DIAG_SEP, ch.out, k, false);
       diag_step<T>(leaves, DIAG_LEAF_P, ch.out, k, false);
     }
@@ -1147,9 +1060,6 @@ int run_steps(hsc_ctx* ctx, hipStream_t st, Plan* pl, int e_base, int nvalid, vo
         break;
       case S_INV_SUPER:
         launch_inv_super(st, (const InvJob*)jobs, s.njobs, s.i0, s.i1, s.i2);
-        break;
-      case S_MIRROR:
-        launch_mirror(st, s.i0, (const MirrorJob*)jobs, map, s.count);
         break;
       case S_GUARD:
         launch_guard(st, (const RowJob*)jobs, s.njobs, nclusters, e_base, nvalid, guard);
