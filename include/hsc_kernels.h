@@ -39,6 +39,22 @@ hsc_status hsc_kern_zgemm_tile(hsc_ctx* ctx, int32_t tile_kind, int32_t opA, int
                                const void* B, int32_t ldb, int32_t beta, const void* C, int32_t ldc, void* D,
                                int32_t ldd);
 
+/* The block product of the double-double solve (hsc_solve_opts.precision >= 1;
+ * Algorithm 1's multipliers and Schur updates, Algorithm 2's extraction
+ * products) on its own: D = (-1)^negate op(A) op(B) + beta C in complex
+ * double-double.  Every element is 32 bytes, four doubles (real hi, real lo,
+ * imaginary hi, imaginary lo) with |lo| <= ulp(hi) / 2; row-major, leading
+ * dimensions in elements; device pointers.  op 0 = as is, 1 = transposed.
+ * config: tile of the kernel, 0 = 32x32, 1 = 64x32, 2 = 64x64.  The result
+ * is accurate to about 2^-104 relative to sum_k |op(A)_ik| |op(B)_kj| (products
+ * accumulated lazily, renormalised every 8 terms).  beta is 0 or 1; C may equal
+ * D and may be NULL when beta = 0.  Synchronous.
+ * Errors: HSC_E_ARG (sizes < 0, bad op or config, leading dimension too small),
+ * HSC_E_OOM, HSC_E_HIP. */
+hsc_status hsc_kern_zgemm_dd(hsc_ctx* ctx, int32_t config, int32_t opA, int32_t opB, int32_t M, int32_t N,
+                             int32_t K, int32_t negate, const void* A, int32_t lda, const void* B, int32_t ldb,
+                             int32_t beta, const void* C, int32_t ldc, void* D, int32_t ldd);
+
 /* Invert `count` matrices of order n[k] in place (X[k], leading dimension ld[k])
  * and write X[k]^-1 into Y[k] (leading dimension ldy[k]); all pointer/size
  * arrays are host arrays.  status (device, int32[count], may be NULL) receives

@@ -1844,6 +1844,49 @@ hsc_status hsc_kern_zgemm_tile(hsc_ctx* ctx, int32_t tile_kind, int32_t opA, int
   return HSC_OK;
 }
 
+hsc_status hsc_kern_zgemm_dd(hsc_ctx* ctx, int32_t config, int32_t opA, int32_t opB, int32_t M, int32_t N,
+                             int32_t K, int32_t negate, const void* A, int32_t lda, const void* B, int32_t ldb,
+                             int32_t beta, const void* C, int32_t ldc, void* D, int32_t ldd) {
+  if (!ctx || M < 0 || N < 0 || K < 0 || opA < 0 || opA > 1 || opB < 0 || opB > 1 || (beta != 0 && beta != 1) ||
+      (negate != 0 && negate != 1) || config < 0 || config >= dd_gemm_configs()) {
+    set_error("bad arguments to hsc_kern_zgemm_dd");
+    return HSC_E_ARG;
+  }
+  const int a_cols = opA == OP_N ? K : M, b_cols = opB == OP_N ? N : K;
+  if ((K > 0 && M > 0 && (!A || lda < a_cols)) || (K > 0 && N > 0 && (!B || ldb < b_cols)) || !D ||
+      ldd < N || (beta && (!C || ldc < N))) {
+    set_error("bad pointer or leading dimension in hsc_kern_zgemm_dd");
+    return HSC_E_ARG;
+  }
+  if (M == 0 || N == 0) return HSC_OK;
+  HIPCHK(hipSetDevice(ctx->device));
+  GemmProbDD p{};
+  p.A = (const zdd*)A; p.B = (const zdd*)B; p.C = (const zdd*)C; p.D = (zdd*)D; p.D64 = nullptr;
+  p.M = M; p.N = N; p.K = K; p.lda = lda; p.ldb = ldb; p.ldc = ldc; p.ldd = ldd; p.ldd64 = 0;
+  const int tm = dd_gemm_tile_m(config), tn = dd_gemm_tile_n(config);
+  p.tiles_n = (N + tn - 1) / tn;
+  p.tile_off = 0;
+  const int tiles = ((M + tm - 1) / tm) * p.tiles_n;
+  std::vector<int32_t> map(tiles, 0);
+  char* dev = nullptr;
+  const size_t bytes = 256 + sizeof(int32_t) * tiles;
+  if (hipMalloc(&dev, bytes) != hipSuccess) { (void)hipGetLastError(); set_error("alloc failed"); return HSC_E_OOM; }
+  hipError_t e1 = hipMemcpy(dev, &p, sizeof(p), hipMemcpyHostToDevice);
+  hipError_t e2 = hipMemcpy(dev + 256, map.data(), sizeof(int32_t) * tiles, hipMemcpyHostToDevice);
+  if (e1 == hipSuccess && e2 == hipSuccess) {
+    launch_dd_gemm(ctx->stream, opA, opB, config, (const GemmProbDD*)dev, (const int32_t*)(dev + 256), tiles, negate,
+                   beta);
+    e1 = hipGetLastError();
+    if (e1 == hipSuccess) e1 = ctx->stream ? hipStreamSynchronize(ctx->stream) : hipDeviceSynchronize();
+  }
+  (void)hipFree(dev);
+  if (e1 != hipSuccess || e2 != hipSuccess) {
+    set_error(std::string("HIP error in hsc_kern_zgemm_dd: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    return HSC_E_HIP;
+  }
+  return HSC_OK;
+}
+
 hsc_status hsc_kern_mfma_rate(hsc_ctx* ctx, double* tflops) {
   if (!ctx || !tflops) { set_error("bad arguments to hsc_kern_mfma_rate"); return HSC_E_ARG; }
   HIPCHK(hipSetDevice(ctx->device));

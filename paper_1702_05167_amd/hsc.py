@@ -77,6 +77,7 @@ def lib():
     L.hsc_kern_zgemm.argtypes = [vp, i32, i32, i32, i32, i32, dbl, dbl, vp, i32, vp, i32, i32, vp, i32, vp, i32]
     L.hsc_kern_zgemm_tile.argtypes = [vp, i32, i32, i32, i32, i32, i32, dbl, dbl, vp, i32, vp, i32, i32, vp, i32, vp,
                                       i32]
+    L.hsc_kern_zgemm_dd.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, vp, i32, vp, i32, i32, vp, i32, vp, i32]
     L.hsc_kern_zinv_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
     L.hsc_kern_mfma_probe.argtypes = [vp, vp]
     L.hsc_kern_mfma_rate.argtypes = [vp, C.POINTER(dbl)]
@@ -93,7 +94,8 @@ def lib():
                  "hsc_tree_stats_get",
                  "hsc_tree_export", "hsc_tree_destroy", "hsc_solve", "hsc_solve_batch", "hsc_sync",
                  "hsc_ctx_profile", "hsc_ctx_profile_read", "hsc_ctx_profile_launches",
-                 "hsc_kern_zgemm", "hsc_kern_zgemm_tile", "hsc_kern_zinv_batched", "hsc_kern_mfma_probe",
+                 "hsc_kern_zgemm", "hsc_kern_zgemm_tile", "hsc_kern_zgemm_dd", "hsc_kern_zinv_batched",
+                 "hsc_kern_mfma_probe",
                  "hsc_kern_mfma_rate", "hsc_totals",
                  "hsc_mlp_create", "hsc_mlp_destroy", "hsc_mlp_n_params", "hsc_mlp_set_params",
                  "hsc_mlp_get_params", "hsc_mlp_forward", "hsc_mlp_grads", "hsc_mlp_train"):
@@ -351,6 +353,24 @@ def kern_zgemm(ctx, opA, opB, alpha, A, B, beta=0, C_=None, D=None, tile=0):
     check(lib().hsc_kern_zgemm_tile(ctx.h, tile, opA, opB, M, N, K, alpha.real, alpha.imag, _dptr(A), A.stride(0),
                                _dptr(B), B.stride(0), beta, _dptr(C_) if C_ is not None else None,
                                C_.stride(0) if C_ is not None else 0, _dptr(D), D.stride(0)))
+    return D
+
+
+def kern_zgemm_dd(ctx, opA, opB, A, B, negate=0, beta=0, C_=None, D=None, config=0):
+    """D = (-1)^negate op(A) op(B) + beta C in complex double-double.  A, B, C, D: device float64
+    tensors of shape (rows, cols, 4) holding (re hi, re lo, im hi, im lo) per element."""
+    import torch
+    M = A.shape[0] if opA == 0 else A.shape[1]
+    K = A.shape[1] if opA == 0 else A.shape[0]
+    N = B.shape[1] if opB == 0 else B.shape[0]
+    if D is None:
+        D = torch.empty((M, N, 4), dtype=torch.float64, device=A.device)
+    for t in (A, B, D) + ((C_,) if C_ is not None else ()):
+        if t.dim() != 3 or t.shape[2] != 4 or t.stride(2) != 1 or t.stride(1) != 4:
+            raise ValueError("double-double operands are (rows, cols, 4) tensors with contiguous elements")
+    check(lib().hsc_kern_zgemm_dd(ctx.h, config, opA, opB, M, N, K, negate, _dptr(A), A.stride(0) // 4,
+                                  _dptr(B), B.stride(0) // 4, beta, _dptr(C_) if C_ is not None else None,
+                                  C_.stride(0) // 4 if C_ is not None else 0, _dptr(D), D.stride(0) // 4))
     return D
 
 

@@ -121,3 +121,63 @@ def test_zinv_singular_reports_status(ctx):
     inv, st = H.kern_zinv_batched(ctx, [torch.tensor(h, device=ctx.torch_device)])
     assert int(st[0]) == H.HscError(-3, "").code
     assert np.isfinite(inv[0].cpu().numpy()).all()
+
+
+# ---- the double-double block product (precision >= 1) against exact rational arithmetic ----
+
+def _dd_rand(rng, rows, cols):
+    """(rows, cols, 4) double-double values: hi ~ N(0, 1), lo a random fraction of half an ulp of hi"""
+    hi = rng.standard_normal((rows, cols, 2))
+    lo = (rng.random((rows, cols, 2)) - 0.5) * np.spacing(np.abs(hi))
+    out = np.empty((rows, cols, 4))
+    out[..., 0], out[..., 1], out[..., 2], out[..., 3] = hi[..., 0], lo[..., 0], hi[..., 1], lo[..., 1]
+    return out
+
+
+def _dd_exact(x):
+    """(re, im) as exact rationals of one double-double element"""
+    from fractions import Fraction as F
+    return F(float(x[0])) + F(float(x[1])), F(float(x[2])) + F(float(x[3]))
+
+
+@pytest.mark.parametrize("config", [0, 1, 2])
+@pytest.mark.parametrize("opA,opB,negate,beta", [(0, 0, 0, 0), (1, 0, 1, 1), (0, 1, 0, 1)])
+def test_zgemm_dd_against_exact_arithmetic(ctx, config, opA, opB, negate, beta):
+    # ragged sizes spanning several tiles of every configuration; error measured against the exact
+    # (rational) value, relative to sum_k |a_ik| |b_kj| + |c_ij|: double-double gives ~1e-31 there,
+    # complex128 arithmetic (or error-free transformations broken by contraction) ~1e-16
+    rng = np.random.default_rng(10 * config + 3 * opA + opB)
+    M, N, K = 70, 37, 45
+    A = _dd_rand(rng, *((M, K) if opA == 0 else (K, M)))
+    B = _dd_rand(rng, *((K, N) if opB == 0 else (N, K)))
+    Cm = _dd_rand(rng, M, N)
+    dev = ctx.torch_device
+    D = H.kern_zgemm_dd(ctx, opA, opB, torch.tensor(A, device=dev), torch.tensor(B, device=dev), negate=negate,
+                        beta=beta, C_=torch.tensor(Cm, device=dev) if beta else None, config=config).cpu().numpy()
+    # the stored pairs are normalised: |lo| <= ulp(hi) / 2
+    assert (np.abs(D[..., 1]) <= 0.5 * np.spacing(np.abs(D[..., 0]))).all()
+    assert (np.abs(D[..., 3]) <= 0.5 * np.spacing(np.abs(D[..., 2]))).all()
+    # exact values at the tile corners and at 60 random entries
+    pairs = {(i, j) for i in (0, 31, 32, 63, 64, M - 1) for j in (0, 31, 32, N - 1)}
+    pairs |= {(int(i), int(j)) for i, j in zip(rng.integers(0, M, 60), rng.integers(0, N, 60))}
+    worst = 0.0
+    for i, j in sorted(pairs):
+        re = im = 0
+        scale = 0.0
+        for k in range(K):
+            ar, ai = _dd_exact(A[i, k] if opA == 0 else A[k, i])
+            br, bi = _dd_exact(B[k, j] if opB == 0 else B[j, k])
+            re += ar * br - ai * bi
+            im += ar * bi + ai * br
+            scale += abs(complex(float(ar), float(ai))) * abs(complex(float(br), float(bi)))
+        if negate:
+            re, im = -re, -im
+        if beta:
+            cr, ci = _dd_exact(Cm[i, j])
+            re, im = re + cr, im + ci
+            scale += abs(complex(float(cr), float(ci)))
+        got = _dd_exact(D[i, j])
+        err = max(abs(float(got[0] - re)), abs(float(got[1] - im))) / scale
+        worst = max(worst, err)
+    print("dd GEMM worst relative error", worst)
+    assert worst < 1e-29
