@@ -55,6 +55,15 @@ hsc_status hsc_kern_zgemm_dd(hsc_ctx* ctx, int32_t config, int32_t opA, int32_t 
                              int32_t K, int32_t negate, const void* A, int32_t lda, const void* B, int32_t ldb,
                              int32_t beta, const void* C, int32_t ldc, void* D, int32_t ldd);
 
+/* The pivot-block inverse of the double-double fold (hsc_solve_opts.precision
+ * >= 1, Algorithm 1's A_ii^-1) on its own: blocked Gauss-Jordan with partial
+ * pivoting inside the block, in complex double-double.  X (order n, leading
+ * dimension ld, 32-byte elements as in hsc_kern_zgemm_dd; device) is
+ * overwritten; Y (ldy) receives X^-1.  status (device int32, may be NULL)
+ * receives 0 or HSC_E_SINGULAR.  1 <= n <= 4096.  Synchronous.
+ * Errors: HSC_E_ARG, HSC_E_OOM, HSC_E_HIP. */
+hsc_status hsc_kern_zinv_dd(hsc_ctx* ctx, int32_t n, void* X, int32_t ld, void* Y, int32_t ldy, int32_t* status);
+
 /* Invert `count` matrices of order n[k] in place (X[k], leading dimension ld[k])
  * and write X[k]^-1 into Y[k] (leading dimension ldy[k]); all pointer/size
  * arrays are host arrays.  status (device, int32[count], may be NULL) receives

@@ -1887,6 +1887,66 @@ hsc_status hsc_kern_zgemm_dd(hsc_ctx* ctx, int32_t config, int32_t opA, int32_t 
   return HSC_OK;
 }
 
+hsc_status hsc_kern_zinv_dd(hsc_ctx* ctx, int32_t n, void* X, int32_t ld, void* Y, int32_t ldy, int32_t* status) {
+  if (!ctx || n < 1 || n > kMaxCluster || !X || !Y || ld < n || ldy < n) {
+    set_error("bad arguments to hsc_kern_zinv_dd");
+    return HSC_E_ARG;
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  const int nb = dd_inv_nb(n);
+  const int nsteps = (n + nb - 1) / nb;
+  const int T32 = (n + dd_gemm_tile_m(0) - 1) / dd_gemm_tile_m(0);
+  const int tiles = T32 * ((n + dd_gemm_tile_n(0) - 1) / dd_gemm_tile_n(0));
+  size_t ws = 0;
+  auto wa = [&](size_t b) { size_t o = (ws + 255) / 256 * 256; ws = o + b; return o; };
+  const size_t o_piv = wa(sizeof(int32_t) * n), o_t = wa(32ull * n * nb), o_r = wa(32ull * n * nb);
+  const size_t o_job = wa(sizeof(InvJobDD)), o_st = wa(sizeof(int32_t));
+  const size_t o_probs = wa(sizeof(GemmProbDD) * nsteps), o_map = wa(sizeof(int32_t) * tiles);
+  const size_t o_y64 = wa(16ull * n * n);   // the unscramble step always writes the rounded inverse too
+  char* dev = nullptr;
+  if (hipMalloc(&dev, ws) != hipSuccess) { (void)hipGetLastError(); set_error("alloc failed"); return HSC_E_OOM; }
+  InvJobDD j{};
+  j.X = (zdd*)X; j.ld = ld; j.Y = (zdd*)Y; j.ldy = ldy; j.Y64 = (double2*)(dev + o_y64); j.ldy64 = n; j.n = n;
+  j.e = 0;
+  j.piv = (int32_t*)(dev + o_piv); j.T = (zdd*)(dev + o_t); j.R = (zdd*)(dev + o_r);
+  std::vector<GemmProbDD> probs(nsteps);
+  for (int q = 0; q < nsteps; ++q) {
+    // rank-kb update of the whole block: X += T R (T: n x kb, R: kb x n, as the panel leaves them)
+    const int kb = std::min(nb, n - q * nb);
+    GemmProbDD& p = probs[q];
+    p.A = j.T; p.B = j.R; p.C = j.X; p.D = j.X; p.D64 = nullptr;
+    p.M = n; p.N = n; p.K = kb; p.lda = kb; p.ldb = n; p.ldc = ld; p.ldd = ld; p.ldd64 = 0;
+    p.tiles_n = (n + dd_gemm_tile_n(0) - 1) / dd_gemm_tile_n(0);
+    p.tile_off = 0;
+  }
+  const std::vector<int32_t> map(tiles, 0);
+  const int32_t zero = 0;
+  hipError_t err = hipMemcpy(dev + o_job, &j, sizeof(j), hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = hipMemcpy(dev + o_st, &zero, sizeof(zero), hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = hipMemcpy(dev + o_probs, probs.data(), sizeof(GemmProbDD) * nsteps, hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = hipMemcpy(dev + o_map, map.data(), sizeof(int32_t) * tiles, hipMemcpyHostToDevice);
+  if (err == hipSuccess) {
+    const InvJobDD* dj = (const InvJobDD*)(dev + o_job);
+    int32_t* dst = (int32_t*)(dev + o_st);
+    for (int q = 0; q < nsteps; ++q) {
+      launch_dd_inv_panel(ctx->stream, dj, 1, q * nb, nb, n, dst);
+      launch_dd_inv_swap(ctx->stream, dj, 1, q * nb, nb, n);
+      launch_dd_gemm(ctx->stream, 0, 0, 0, (const GemmProbDD*)(dev + o_probs) + q, (const int32_t*)(dev + o_map),
+                     tiles, 0, 1);
+    }
+    launch_dd_inv_unscramble(ctx->stream, dj, 1, n);
+    err = hipGetLastError();
+    if (err == hipSuccess) err = ctx->stream ? hipStreamSynchronize(ctx->stream) : hipDeviceSynchronize();
+    if (err == hipSuccess && status) err = hipMemcpy(status, dst, sizeof(int32_t), hipMemcpyDeviceToDevice);
+  }
+  (void)hipFree(dev);
+  if (err != hipSuccess) {
+    set_error(std::string("HIP error in hsc_kern_zinv_dd: ") + hipGetErrorString(err));
+    return HSC_E_HIP;
+  }
+  return HSC_OK;
+}
+
 hsc_status hsc_kern_mfma_rate(hsc_ctx* ctx, double* tflops) {
   if (!ctx || !tflops) { set_error("bad arguments to hsc_kern_mfma_rate"); return HSC_E_ARG; }
   HIPCHK(hipSetDevice(ctx->device));

@@ -79,6 +79,7 @@ def lib():
                                       i32]
     L.hsc_kern_zgemm_dd.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, vp, i32, vp, i32, i32, vp, i32, vp, i32]
     L.hsc_kern_zinv_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    L.hsc_kern_zinv_dd.argtypes = [vp, i32, vp, i32, vp, i32, vp]
     L.hsc_kern_mfma_probe.argtypes = [vp, vp]
     L.hsc_kern_mfma_rate.argtypes = [vp, C.POINTER(dbl)]
     L.hsc_totals.argtypes = [vp, i32, i64, vp, vp, vp, vp]
@@ -95,6 +96,7 @@ def lib():
                  "hsc_tree_export", "hsc_tree_destroy", "hsc_solve", "hsc_solve_batch", "hsc_sync",
                  "hsc_ctx_profile", "hsc_ctx_profile_read", "hsc_ctx_profile_launches",
                  "hsc_kern_zgemm", "hsc_kern_zgemm_tile", "hsc_kern_zgemm_dd", "hsc_kern_zinv_batched",
+                 "hsc_kern_zinv_dd",
                  "hsc_kern_mfma_probe",
                  "hsc_kern_mfma_rate", "hsc_totals",
                  "hsc_mlp_create", "hsc_mlp_destroy", "hsc_mlp_n_params", "hsc_mlp_set_params",
@@ -372,6 +374,19 @@ def kern_zgemm_dd(ctx, opA, opB, A, B, negate=0, beta=0, C_=None, D=None, config
                                   _dptr(B), B.stride(0) // 4, beta, _dptr(C_) if C_ is not None else None,
                                   C_.stride(0) // 4 if C_ is not None else 0, _dptr(D), D.stride(0) // 4))
     return D
+
+
+def kern_zinv_dd(ctx, X):
+    """Inverse of a square complex double-double matrix: X is a device float64 tensor (n, n, 4)
+    (re hi, re lo, im hi, im lo), overwritten; returns (inverse, status)."""
+    import torch
+    n = X.shape[0]
+    if X.dim() != 3 or X.shape[1] != n or X.shape[2] != 4 or X.stride(2) != 1 or X.stride(1) != 4:
+        raise ValueError("X must be a (n, n, 4) tensor with contiguous elements")
+    Y = torch.empty_like(X)
+    st = torch.empty(1, dtype=torch.int32, device=X.device)
+    check(lib().hsc_kern_zinv_dd(ctx.h, n, _dptr(X), X.stride(0) // 4, _dptr(Y), Y.stride(0) // 4, _dptr(st)))
+    return Y, st
 
 
 def kern_zinv_batched(ctx, mats):

@@ -181,3 +181,43 @@ def test_zgemm_dd_against_exact_arithmetic(ctx, config, opA, opB, negate, beta):
         worst = max(worst, err)
     print("dd GEMM worst relative error", worst)
     assert worst < 1e-29
+
+
+def test_zinv_dd_nearly_singular_block(ctx):
+    # a complex-symmetric block like the fold's pivot blocks out of the lead band: real symmetric with one
+    # eigenvalue at 1e-10 plus i 1e-12 (condition ~3e10).  The double-double Gauss-Jordan inverse must
+    # satisfy A Y = I to ~kappa 1e-31 in exact arithmetic; the complex128 one only to ~kappa 1e-16
+    from fractions import Fraction as F
+    rng = np.random.default_rng(5)
+    n = 24
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.concatenate([[1e-10], rng.uniform(1.0, 3.0, n - 1) * rng.choice([-1.0, 1.0], n - 1)])
+    R = (Q * lam) @ Q.T
+    R = 0.5 * (R + R.T)
+    A = R + 1j * 1e-12 * np.eye(n)
+    Xd = np.zeros((n, n, 4))
+    Xd[..., 0], Xd[..., 2] = A.real, A.imag
+    Y, st = H.kern_zinv_dd(ctx, torch.tensor(Xd, device=ctx.torch_device))
+    Y = Y.cpu().numpy()
+    assert int(st.cpu()[0]) == 0
+    Ax = [[(F(float(A[i, j].real)), F(float(A[i, j].imag))) for j in range(n)] for i in range(n)]
+    Yx = [[(F(float(Y[i, j, 0])) + F(float(Y[i, j, 1])), F(float(Y[i, j, 2])) + F(float(Y[i, j, 3])))
+           for j in range(n)] for i in range(n)]
+    ynorm = max(abs(complex(float(a), float(b))) for row in Yx for a, b in row)
+    worst = 0.0
+    for i in range(n):
+        for j in range(n):
+            re = im = F(0)
+            for k in range(n):
+                ar, ai = Ax[i][k]
+                yr, yi = Yx[k][j]
+                re += ar * yr - ai * yi
+                im += ar * yi + ai * yr
+            if i == j:
+                re -= 1
+            worst = max(worst, abs(float(re)), abs(float(im)))
+    Y64, _ = H.kern_zinv_batched(ctx, [torch.tensor(A, device=ctx.torch_device)])
+    r64 = np.abs(A @ Y64[0].cpu().numpy() - np.eye(n)).max()
+    print("residual max |A Y - I|: double-double", worst, "complex128", r64, "max |Y|", ynorm)
+    assert ynorm > 1e9                       # the block is as nearly singular as intended
+    assert worst < 1e-18 and worst < r64 * 1e-8
