@@ -220,10 +220,11 @@ def main():
         from threadpoolctl import threadpool_info
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
         t2 = time.perf_counter()
-        oracle.rgf.solve(dev, [0.3], 1e-8, 0.025, 0.1, -0.1)
+        oracle.rgf.solve(dev, [0.3, -2.4], 1e-8, 0.025, 0.1, -0.1)
         cdt = time.perf_counter() - t2
-        cpu = {"value": 1.0 / cdt, "unit": "energies/s", "cores": threads, "kind": "oracle",
-               "sample": f"slab RGF (oracle/rgf.py), one energy (E=0.3) of the same {N}^3 cube, {cdt:.1f} s"}
+        cpu = {"value": 2.0 / cdt, "unit": "energies/s", "cores": threads, "kind": "oracle",
+               "sample": f"slab RGF (oracle/rgf.py), two energies (E=0.3 in the lead band, E=-2.4 outside) "
+                         f"of the same {N}^3 cube, {cdt:.1f} s"}
 
     prec_name = {0: "complex128", 1: "double-double fold, complex128 extraction",
                  2: "double-double fold and extraction"}[args.precision]
