@@ -28,9 +28,11 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 # FP64 vector issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one add, multiply or fused
 # multiply-add per lane and clock (the published 78.6 TFLOP/s counts an FMA as two flops)
 FP64_VALU_PEAK_TOPS = 39.3
-# FP64 vector operations of one complex double-double multiply-add in k_dd_gemm (4 products of
-# 1 mul + 3 fma, each accumulated with a 6-operation two-sum and 2 adds): 6 per complex flop-pair
-DD_OPS_PER_CFLOP = 48 / 8
+# FP64 vector operations of one complex double-double multiply-add in k_dd_gemm (three real products,
+# Gauss form, each 1 mul + 3 fma accumulated with a 6-operation two-sum and 2 adds), per flop of the
+# 8 M N K complex count
+DD_OPS_PER_CMAC = 36
+DD_OPS_PER_CFLOP = DD_OPS_PER_CMAC / 8
 
 
 def note(msg):
@@ -167,7 +169,7 @@ def main():
                 "frac": ach / FP64_VALU_PEAK_TOPS, "traffic": None, "launches": int(gd["launches"]),
                 "avg_launch_ms": gd["ms"] / gd["launches"],
                 "complex_equiv_tflops": gd["flops"] / (gd["ms"] * 1e-3) / 1e12,
-                "fp64_ops_per_complex_multiply_add": 48,
+                "fp64_ops_per_complex_multiply_add": DD_OPS_PER_CMAC,
                 "share_of_kernel_time": gd["ms"] / total_ms}
     else:
         ach = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0

@@ -239,8 +239,9 @@ __global__ __launch_bounds__(256) void k_dd_inv_unscramble(const InvJobDD* __res
 
 // ---------------------------------------------------------------------------------------------
 // grouped complex double-double GEMM: 256 threads as 16 x 16, each with an RM x RN block of outputs
-// (tile BM x BN = 16 RM x 16 RN: 32x32, 64x32 or 64x64), lazily accumulated (dd.h: zddacc) and
-// renormalised after every 8-deep k step.
+// (tile BM x BN = 16 RM x 16 RN: 32x32, 64x32 or 64x64), three real products per complex
+// multiply-add (Gauss; the sums re + im of both operands are formed once, when a tile is staged),
+// lazily accumulated (dd.h: ddacc) and renormalised after every 8-deep k step.
 //   OPA 0: A'(m,k) = A[m*lda + k];  OPA 1: A'(m,k) = A[k*lda + m]
 //   OPB 0: B'(k,n) = B[k*ldb + n];  OPB 1: B'(k,n) = B[n*ldb + k]
 constexpr int DK = 8;
@@ -254,6 +255,8 @@ __global__ __launch_bounds__(256) void k_dd_gemm(const GemmProbDD* __restrict__ 
   constexpr int BM = 16 * RM, BN = 16 * RN;
   __shared__ zdd As[DK][BM + 1];
   __shared__ zdd Bs[DK][BN + 1];
+  __shared__ dd Ass[DK][BM + 1];   // re + im of each staged element (the third product of the Gauss form)
+  __shared__ dd Bss[DK][BN + 1];
   const int per = (total_tiles + 7) >> 3;
   const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (tile >= total_tiles) return;
@@ -263,11 +266,13 @@ __global__ __launch_bounds__(256) void k_dd_gemm(const GemmProbDD* __restrict__ 
   const int M = pr.M, N = pr.N, K = pr.K;
   const int t = threadIdx.x;
   const int tm = (t / 16) * RM, tn = (t % 16) * RN;   // this thread's RM x RN block
-  zddacc acc[RM][RN];
+  // three real products per complex multiply-add (Gauss): t1 = sum ar br, t2 = sum ai bi,
+  // t3 = sum (ar + ai)(br + bi); re = t1 - t2, im = t3 - t1 - t2
+  ddacc t1[RM][RN], t2[RM][RN], t3[RM][RN];
 #pragma unroll
   for (int i = 0; i < RM; ++i)
 #pragma unroll
-    for (int j = 0; j < RN; ++j) acc[i][j] = zddacc{{0.0, 0.0}, {0.0, 0.0}};
+    for (int j = 0; j < RN; ++j) t1[i][j] = t2[i][j] = t3[i][j] = ddacc{0.0, 0.0};
   for (int k0 = 0; k0 < K; k0 += DK) {
     // stage A' (BM x DK) and B' (DK x BN), RM / 2 and RN / 2 elements per thread
 #pragma unroll
@@ -279,6 +284,7 @@ __global__ __launch_bounds__(256) void k_dd_gemm(const GemmProbDD* __restrict__ 
       zdd v = zdd_zero();
       if (gm < M && gk < K) v = OPA == 0 ? pr.A[(int64_t)gm * pr.lda + gk] : pr.A[(int64_t)gk * pr.lda + gm];
       As[kk][mm] = v;
+      Ass[kk][mm] = dd_add(v.re, v.im);
     }
 #pragma unroll
     for (int u = 0; u < RN / 2; ++u) {
@@ -289,24 +295,34 @@ __global__ __launch_bounds__(256) void k_dd_gemm(const GemmProbDD* __restrict__ 
       zdd v = zdd_zero();
       if (gbk < K && gbn < N) v = OPB == 0 ? pr.B[(int64_t)gbk * pr.ldb + gbn] : pr.B[(int64_t)gbn * pr.ldb + gbk];
       Bs[bk][bn] = v;
+      Bss[bk][bn] = dd_add(v.re, v.im);
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < DK; ++kk) {
       zdd a[RM], b[RN];
+      dd sa[RM], sb[RN];
 #pragma unroll
-      for (int i = 0; i < RM; ++i) a[i] = As[kk][tm + i];
+      for (int i = 0; i < RM; ++i) { a[i] = As[kk][tm + i]; sa[i] = Ass[kk][tm + i]; }
 #pragma unroll
-      for (int j = 0; j < RN; ++j) b[j] = Bs[kk][tn + j];
+      for (int j = 0; j < RN; ++j) { b[j] = Bs[kk][tn + j]; sb[j] = Bss[kk][tn + j]; }
 #pragma unroll
       for (int i = 0; i < RM; ++i)
 #pragma unroll
-        for (int j = 0; j < RN; ++j) zddacc_fma(acc[i][j], a[i], b[j]);
+        for (int j = 0; j < RN; ++j) {
+          ddacc_add_prod(t1[i][j], a[i].re, b[j].re);
+          ddacc_add_prod(t2[i][j], a[i].im, b[j].im);
+          ddacc_add_prod(t3[i][j], sa[i], sb[j]);
+        }
     }
 #pragma unroll
     for (int i = 0; i < RM; ++i)
 #pragma unroll
-      for (int j = 0; j < RN; ++j) zddacc_renorm(acc[i][j]);
+      for (int j = 0; j < RN; ++j) {
+        ddacc_renorm(t1[i][j]);
+        ddacc_renorm(t2[i][j]);
+        ddacc_renorm(t3[i][j]);
+      }
     __syncthreads();
   }
 #pragma unroll
@@ -315,7 +331,9 @@ __global__ __launch_bounds__(256) void k_dd_gemm(const GemmProbDD* __restrict__ 
     for (int j = 0; j < RN; ++j) {
       const int row = m0 + tm + i, col = n0 + tn + j;
       if (row < M && col < N) {
-        const zdd v = zddacc_value(acc[i][j]);
+        const dd v1 = two_sum(t1[i][j].hi, t1[i][j].lo), v2 = two_sum(t2[i][j].hi, t2[i][j].lo);
+        const dd v3 = two_sum(t3[i][j].hi, t3[i][j].lo);
+        const zdd v{dd_sub(v1, v2), dd_sub(dd_sub(v3, v1), v2)};
         zdd o = negate ? zdd_neg(v) : v;
         if (beta) o = zdd_add(o, pr.C[(int64_t)row * pr.ldc + col]);
         pr.D[(int64_t)row * pr.ldd + col] = o;
