@@ -4,14 +4,20 @@
 Workload: the 32^3 cube (32,768 sites, 7-point, t = -1, on-site U[-0.5, 0.5]
 seed 0, per-site 1D leads on the x faces), 256 energies uniform in [-6, 6],
 eta = 1e-8, kT = 0.025, mu_L/R = +-0.1.  Cluster tree: 3D nested dissection
-with planar separators, leaves <= 8 sites per side.  One step = diag G^r,
-diag G^< and T for all 256 energies (inputs resident on the device), with the
-fold and the extraction in double-double (precision 2: the only setting whose
-results agree with the oracle to 1e-10 at every energy of the grid, out of the
-lead band included).  The line also reports the error against stored oracle
-values at 8 of the 256 energies (tests/golden), and the complex128 path on the
-FP64 matrix cores (its rate, its GEMM roofline and where it is accurate).
-Prints one JSON line.
+with planar separators, leaves <= 8 sites per side.  The fold and the
+extraction run in double-double (precision 2: the only setting whose results
+agree with the oracle to 1e-10 at every energy of the grid, out of the lead
+band included).
+
+One step = diag G^r, diag G^< and T for one batch of energies (16 by default),
+inputs resident on the device; consecutive steps walk the 256-point grid in
+order, so 16 steps solve every grid energy once.  Besides the timed steps the
+line reports: one-energy-per-launch-sequence ("plain") throughput over a few
+energies, the error against stored oracle values at 8 of the 256 energies
+(tests/golden), the algorithmic roofline of the dominant kernel (HIP events
+around every launch of one step), and the CPU oracle (slab RGF) timed on the
+host.  Opt-in studies: --alt (the complex128 path on the FP64 matrix cores),
+--trilayer, --uneven, --learned-grid.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -39,35 +45,76 @@ def note(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
-def golden_errors(np, gold, out):
-    """max relative error of diag G^r, Im diag G^< (sampled sites) and T at the stored energies"""
-    import torch
-    idx = torch.tensor(gold["energy_index"], device=out["gr"].device)
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def golden_errors(np, gold, gr_all, gl_all, tr_all):
+    """max relative error of diag G^r, Im diag G^< (sampled sites) and T at the stored energies;
+    row k of the arrays belongs to the k-th stored energy"""
     sites = np.array(gold["sites"])
     ref_gr = np.array(gold["gr_re"]) + 1j * np.array(gold["gr_im"])
     ref_gl = np.array(gold["gl_im"])
-    gr = out["gr"][idx].cpu().numpy()[:, sites]
-    gl = out["gl"][idx].cpu().numpy()[:, sites].imag
-    tr = out["trans"][idx].cpu().numpy()
-    errs = [max(np.abs(gr[k] - ref_gr[k]).max() / np.abs(ref_gr[k]).max(),
-                np.abs(gl[k] - ref_gl[k]).max() / np.abs(ref_gl[k]).max(),
-                abs(tr[k] - gold["trans"][k]) / max(gold["trans"][k], 1e-12)) for k in range(len(idx))]
+    errs = []
+    for k in range(len(gold["energies"])):
+        gr, gl, tr = gr_all[k][sites], gl_all[k][sites].imag, tr_all[k]
+        errs.append(max(np.abs(gr - ref_gr[k]).max() / np.abs(ref_gr[k]).max(),
+                        np.abs(gl - ref_gl[k]).max() / np.abs(ref_gl[k]).max(),
+                        abs(tr - gold["trans"][k]) / max(gold["trans"][k], 1e-12)))
     band = [abs(e) < 2.0 for e in gold["energies"]]
     return {"energies": gold["energies"], "max_rel_err": errs, "max": max(errs),
             "in_band_max": max(x for x, b in zip(errs, band) if b),
             "out_of_band_max": max(x for x, b in zip(errs, band) if not b)}
 
 
+def roofline_of(prof, precision):
+    """Algorithmic roofline of the dominant block-product kernel from per-kind launch timing
+    (HIP events on the solver's stream): achieved = sum of 8 M N K over its launches / sum of
+    their durations, against the FP64 matrix-core peak."""
+    total_ms = sum(v["ms"] for v in prof.values())
+    g, gd = prof["gemm"], prof["dd_gemm"]
+    if precision >= 1 and gd["ms"] > 0:
+        ach = gd["flops"] / (gd["ms"] * 1e-3) / 1e12
+        issue = DD_OPS_PER_CFLOP * ach
+        return {"bound": "alu", "kernel": "k_dd_gemm (grouped complex double-double GEMM, FP64 vector units)",
+                "achieved": ach, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_MFMA_PEAK_TFLOPS,
+                "traffic": None, "flop_count": "8 M N K per complex product (algorithmic)",
+                "launches": int(gd["launches"]), "avg_launch_ms": gd["ms"] / gd["launches"],
+                "flops_per_launch": gd["flops"] / gd["launches"],
+                "share_of_kernel_time": gd["ms"] / total_ms,
+                "fp64_vector_issue": {"achieved": issue, "peak": FP64_VALU_PEAK_TOPS,
+                                      "unit": "T FP64 operations/s", "frac": issue / FP64_VALU_PEAK_TOPS,
+                                      "fp64_ops_per_complex_multiply_add": DD_OPS_PER_CMAC}}
+    ach = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
+    return {"bound": "mfma", "kernel": "k_zgemm (grouped complex128 GEMM, all tile shapes)",
+            "achieved": ach, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_MFMA_PEAK_TFLOPS,
+            "traffic": None, "flop_count": "8 M N K per complex product (algorithmic)",
+            "launches": int(g["launches"]),
+            "avg_launch_ms": g["ms"] / g["launches"] if g["launches"] else None,
+            "flops_per_launch": g["flops"] / g["launches"] if g["launches"] else None,
+            "share_of_kernel_time": g["ms"] / total_ms if total_ms else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=16, help="timed steps (one energy batch each)")
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n-side", type=int, default=32)
-    ap.add_argument("--energies", type=int, default=256)
-    ap.add_argument("--batch", type=int, default=0, help="energies per launch sequence (0 = auto)")
+    ap.add_argument("--energies", type=int, default=256, help="points of the energy grid the steps walk")
+    ap.add_argument("--batch", type=int, default=16, help="energies per step (one launch sequence)")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-energy-per-launch-sequence run")
+    ap.add_argument("--plain-energies", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-single", type=int, default=1,
+                    help="also time the oracle on one thread over this many energies (0: skip)")
+    ap.add_argument("--no-golden", action="store_true", help="skip the error against stored oracle values")
     ap.add_argument("--precision", type=int, default=2,
                     help="2 (default): fold and extraction in double-double; 1: double-double fold only; "
                          "0: complex128 as in Algorithms 1 and 2")
@@ -78,7 +125,9 @@ def main():
     ap.add_argument("--complex3m", type=int, default=1,
                     help="1 (default): three real products per complex multiply-add in every complex128 block "
                          "product; 0: four")
-    ap.add_argument("--no-alt", action="store_true", help="skip the complex128 matrix-core runs")
+    ap.add_argument("--alt", action="store_true",
+                    help="also run the complex128 path on the matrix cores (one step each on the transverse "
+                         "leaf-4 tree and on this tree)")
     ap.add_argument("--uneven", type=int, default=0, metavar="D",
                     help="measure D of the 64 uneven cuboids instead: forest batch vs one device at a time")
     ap.add_argument("--uneven-energies", type=int, default=32)
@@ -118,100 +167,116 @@ def main():
         del src, dst
         note(f"copy calibration: {args.calibrate_copy} MiB read + written")
 
-    N, NE = args.n_side, args.energies
+    N, NE, B = args.n_side, args.energies, args.batch
+    if B < 1 or B > NE:
+        sys.exit("--batch must be in [1, --energies]")
     dev = synth.config1_device(n_side=N)
     tree = pkg.Tree.from_device(dev, leaf_side=args.leaf, transverse=args.transverse)
     st = tree.stats()
     ctx = pkg.Context(0)
     # the grid as numpy builds it (torch.linspace differs from it by an ulp at some points)
-    E = torch.tensor(np.linspace(-6.0, 6.0, NE), dtype=torch.float64, device="cuda:0")
+    grid = np.linspace(-6.0, 6.0, NE)
+    E = torch.tensor(grid, dtype=torch.float64, device="cuda:0")
     kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=args.precision, complex3m=args.complex3m,
-              tune=args.tune)
+              tune=args.tune, batch=B)
     want = pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS
     gpath = os.path.join(ROOT, "tests", "golden", "cube32_sampled.json")
     gold = json.load(open(gpath)) if (N == 32 and NE == 256 and os.path.exists(gpath)) else None
 
-    out = pkg.solve(ctx, tree, E, want=want, batch=args.batch, **kw)     # buffers + plan
-    for _ in range(args.warmup):
-        pkg.solve(ctx, tree, E, want=want, batch=args.batch, out=out, sync=False, **kw)
+    def batch_of(k):
+        # energies of step k: the next B points of the grid, wrapping around
+        idx = [(k * B + j) % NE for j in range(B)]
+        return E[idx] if idx[0] + B > NE else E[idx[0]: idx[0] + B]
+
+    t_setup = time.perf_counter()
+    out = pkg.solve(ctx, tree, batch_of(0), want=want, **kw)     # buffers, plan, tile tuning
+    note(f"set-up (plan, tile tuning, first batch): {time.perf_counter() - t_setup:.1f} s")
+    for k in range(args.warmup):
+        pkg.solve(ctx, tree, batch_of(k), want=want, out=out, sync=False, **kw)
     torch.cuda.synchronize()
     note("warmup done")
+    ok = True
     t0 = time.perf_counter()
     for k in range(args.steps):
-        pkg.solve(ctx, tree, E, want=want, batch=args.batch, out=out, sync=False, **kw)
-        if k + 1 < args.steps:
+        pkg.solve(ctx, tree, batch_of(k), want=want, out=out, sync=False, **kw)
+        if (k + 1) % 4 == 0 or k + 1 == args.steps:
             torch.cuda.synchronize()
-            note(f"step {k + 1} done")
+            note(f"step {k + 1} of {args.steps} done")
     ctx.sync()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    value = NE * args.steps / dt
-    status_ok = int(out["status"].abs().sum().item()) == 0
-    note(f"timed {args.steps} steps: {value:.2f} energies/s")
-    acc = golden_errors(np, gold, out) if gold else None
+    ok = int(out["status"].abs().sum().item()) == 0
+    energies_timed = B * args.steps
+    value = energies_timed / dt
+    note(f"timed {args.steps} steps ({energies_timed} energies): {value:.2f} energies/s")
 
-    def profiled(tr, kwp, ne):
-        # per-kernel timing (events around every launch on the solver's stream) over ne energies
-        ctx.profile(True)
-        pkg.solve(ctx, tr, E[:ne], want=want, batch=args.batch, sync=True, **kwp)
-        p = ctx.profile_read()
-        ctx.profile(False)
-        return p
-
-    NP = min(NE, 64)
-    prof = profiled(tree, kw, NP)
+    # launch timing of one step (events around every launch on the solver's stream)
+    ctx.profile(True)
+    pkg.solve(ctx, tree, batch_of(0), want=want, out=out, sync=True, **kw)
+    prof = ctx.profile_read()
+    launches = ctx.profile_launches()
+    ctx.profile(False)
+    roof = roofline_of(prof, args.precision)
+    by_phase = {}
+    for kind, fl, ms, ph in launches:
+        key = f"{ctx.PROFILE_PHASES[int(ph)]}/{ctx.PROFILE_KINDS[int(kind)]}"
+        agg = by_phase.setdefault(key, [0, 0.0, 0.0])
+        agg[0] += 1
+        agg[1] += ms
+        agg[2] += fl
+    by_phase = {k: {"launches": v[0], "ms": round(v[1], 3),
+                    "tflops": round(v[2] / (v[1] * 1e-3) / 1e12, 3) if v[2] > 0 and v[1] > 0 else None}
+                for k, v in sorted(by_phase.items(), key=lambda kv: -kv[1][1])}
     total_ms = sum(v["ms"] for v in prof.values())
-    g, gd = prof["gemm"], prof["dd_gemm"]
-    if args.precision >= 1 and gd["ms"] > 0:
-        ach = DD_OPS_PER_CFLOP * gd["flops"] / (gd["ms"] * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": "k_dd_gemm (grouped complex double-double GEMM, FP64 vector units)",
-                "achieved": ach, "peak": FP64_VALU_PEAK_TOPS, "unit": "TOP/s (FP64 vector operations)",
-                "frac": ach / FP64_VALU_PEAK_TOPS, "traffic": None, "launches": int(gd["launches"]),
-                "avg_launch_ms": gd["ms"] / gd["launches"],
-                "complex_equiv_tflops": gd["flops"] / (gd["ms"] * 1e-3) / 1e12,
-                "fp64_ops_per_complex_multiply_add": DD_OPS_PER_CMAC,
-                "share_of_kernel_time": gd["ms"] / total_ms}
-    else:
-        ach = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
-        roof = {"bound": "mfma", "kernel": "k_zgemm (grouped complex128 GEMM, all tile shapes)",
-                "achieved": ach, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_MFMA_PEAK_TFLOPS,
-                "traffic": None, "launches": int(g["launches"]),
-                "avg_launch_ms": g["ms"] / g["launches"] if g["launches"] else None,
-                "real_mfma_flops_per_complex_fma": 6 if args.complex3m else 8,
-                "share_of_kernel_time": g["ms"] / total_ms if total_ms else None}
+    note(f"dominant kernel: {roof['achieved']:.2f} TFLOP/s algorithmic = {roof['frac']:.3f} of FP64 peak")
 
-    # the complex128 path on the FP64 matrix cores: the transverse tree (accurate inside the lead
-    # band) and this tree, each with its GEMM roofline and its error at the stored energies
+    acc = None
+    if gold and not args.no_golden:
+        # the stored energies, padded to one batch so the same plan serves them
+        idx = list(gold["energy_index"])
+        pad = idx + [idx[-1]] * (B - len(idx) % B if len(idx) % B else 0)
+        og = pkg.solve(ctx, tree, E[pad], want=want, **kw)
+        n8 = len(idx)
+        acc = golden_errors(np, gold, og["gr"][:n8].cpu().numpy(), og["gl"][:n8].cpu().numpy(),
+                            og["trans"][:n8].cpu().numpy())
+        acc["status_ok"] = int(og["status"].abs().sum().item()) == 0
+        note(f"error vs stored oracle values: max {acc['max']:.2e}")
+        del og
+
     mfma = None
-    if not args.no_alt:
+    if args.alt:
         mfma = {}
         kw0 = dict(kw, precision=0)
         for name, tr in (("transverse_leaf4", pkg.Tree.from_device(dev, leaf_side=4, transverse=True)),
                          ("this_tree", tree)):
-            o0 = pkg.solve(ctx, tr, E, want=want, batch=args.batch, **kw0)
+            o0 = pkg.solve(ctx, tr, batch_of(0), want=want, **kw0)
             torch.cuda.synchronize()
             t3 = time.perf_counter()
-            pkg.solve(ctx, tr, E, want=want, batch=args.batch, out=o0, **kw0)
+            for k in range(4):
+                pkg.solve(ctx, tr, batch_of(k), want=want, out=o0, sync=False, **kw0)
             torch.cuda.synchronize()
-            rate = NE / (time.perf_counter() - t3)
-            p0 = profiled(tr, kw0, NE)
+            rate = 4 * B / (time.perf_counter() - t3)
+            ctx.profile(True)
+            pkg.solve(ctx, tr, batch_of(0), want=want, out=o0, sync=True, **kw0)
+            p0 = ctx.profile_read()
+            ctx.profile(False)
             g0 = p0["gemm"]
             a0 = g0["flops"] / (g0["ms"] * 1e-3) / 1e12
             mfma[name] = {"energies_per_s": rate, "flops_per_energy": tr.stats()["flops_per_energy"],
                           "k_zgemm_tflops": a0, "k_zgemm_frac_of_fp64_mfma_peak": a0 / FP64_MFMA_PEAK_TFLOPS,
                           "k_zgemm_avg_launch_ms": g0["ms"] / g0["launches"],
-                          "k_zgemm_share_of_kernel_time": g0["ms"] / sum(v["ms"] for v in p0.values()),
-                          "accuracy_vs_oracle": golden_errors(np, gold, o0) if gold else None}
+                          "k_zgemm_share_of_kernel_time": g0["ms"] / sum(v["ms"] for v in p0.values())}
             note(f"complex128 on the matrix cores, {name}: {rate:.2f} energies/s, k_zgemm {a0:.1f} TFLOP/s")
             del o0
 
     plain = None
     if not args.no_plain:
-        sub = E[: min(NE, 16)]
-        pkg.solve(ctx, tree, sub[:2], want=want, batch=1, **kw)
+        sub = E[: max(1, args.plain_energies)]
+        kw1 = dict(kw, batch=1)
+        pkg.solve(ctx, tree, sub[:1], want=want, **kw1)        # plan for one slot
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        pkg.solve(ctx, tree, sub, want=want, batch=1, **kw)
+        pkg.solve(ctx, tree, sub, want=want, **kw1)
         torch.cuda.synchronize()
         plain = len(sub) / (time.perf_counter() - t1)
         note(f"plain (one energy per launch sequence): {plain:.2f} energies/s")
@@ -219,14 +284,27 @@ def main():
     cpu = None
     if not args.no_cpu:
         import oracle
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        cpu_e = [0.3, -2.4]
         t2 = time.perf_counter()
-        oracle.rgf.solve(dev, [0.3, -2.4], 1e-8, 0.025, 0.1, -0.1)
+        oracle.rgf.solve(dev, cpu_e, 1e-8, 0.025, 0.1, -0.1)
         cdt = time.perf_counter() - t2
-        cpu = {"value": 2.0 / cdt, "unit": "energies/s", "cores": threads, "kind": "oracle",
+        note(f"CPU oracle, {threads} threads: {len(cpu_e) / cdt:.3f} energies/s")
+        single = None
+        if args.cpu_single > 0:
+            e1 = cpu_e[: args.cpu_single]
+            with threadpool_limits(limits=1):
+                t4 = time.perf_counter()
+                oracle.rgf.solve(dev, e1, 1e-8, 0.025, 0.1, -0.1)
+                sdt = time.perf_counter() - t4
+            single = {"value": len(e1) / sdt, "unit": "energies/s", "cores": 1,
+                      "sample": f"{len(e1)} energy (E={e1}), {sdt:.1f} s"}
+            note(f"CPU oracle, 1 thread: {len(e1) / sdt:.4f} energies/s")
+        cpu = {"value": len(cpu_e) / cdt, "unit": "energies/s", "cores": threads, "kind": "oracle",
                "sample": f"slab RGF (oracle/rgf.py), two energies (E=0.3 in the lead band, E=-2.4 outside) "
-                         f"of the same {N}^3 cube, {cdt:.1f} s"}
+                         f"of the same {N}^3 cube, {cdt:.1f} s",
+               "cpu_model": cpu_model(), "host_cpus": os.cpu_count(), "single_thread": single}
 
     prec_name = {0: "complex128", 1: "double-double fold, complex128 extraction",
                  2: "double-double fold and extraction"}[args.precision]
@@ -243,20 +321,25 @@ def main():
         "vs_baseline": None,
         "dtype": "c128" if args.precision == 0 else "c128 in/out, complex double-double inside",
         "data": "synthetic",
-        "config": {"workload": f"cube{N}^3 x {NE} energies in [-6,6] (diag G^r, diag G^<, T)",
-                   "sites": int(dev.n), "energies": NE, "leaf_side": args.leaf, "clusters": st["n_clusters"],
+        "config": {"workload": f"cube{N}^3, energy grid of {NE} points in [-6,6] walked {B} at a time "
+                               f"(diag G^r, diag G^<, T)",
+                   "sites": int(dev.n), "grid_energies": NE, "energies_per_step": B,
+                   "energies_timed": energies_timed, "leaf_side": args.leaf, "clusters": st["n_clusters"],
                    "tree": "transverse nested dissection" if args.transverse else
                            "3D nested dissection, planar separators",
-                   "batch": args.batch or "auto", "plain_energies_per_s": plain,
+                   "plain_energies_per_s": plain,
+                   "batched_over_plain": value / plain if plain else None,
                    "precision": prec_name,
                    "complex_products": "3 real products (Gauss)" if args.complex3m else "4 real products",
-                   "gemm_tiles": "autotuned per launch" if args.tune else "64x64 (16x16x4 MFMA)",
+                   "gemm_tiles": "autotuned per launch" if args.tune else "default",
                    "flops_per_energy": st["flops_per_energy"],
-                   "status_ok": status_ok,
+                   "whole_solve_tflops": value * st["flops_per_energy"] / 1e12,
+                   "status_ok": ok,
                    "accuracy_vs_oracle": acc,
                    "complex128_matrix_core_path": mfma,
-                   f"kernel_ms_first_{NP}_energies": {k: round(v["ms"], 3) for k, v in prof.items() if v["ms"] > 0},
-                   "kernel_ms_total": round(total_ms, 3)},
+                   "kernel_ms_one_step": {k: round(v["ms"], 3) for k, v in prof.items() if v["ms"] > 0},
+                   "kernel_ms_total_one_step": round(total_ms, 3),
+                   "kernel_ms_one_step_by_phase": by_phase},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

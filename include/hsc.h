@@ -259,10 +259,14 @@ hsc_status hsc_ctx_profile(hsc_ctx* ctx, int32_t enable);
 hsc_status hsc_ctx_profile_read(hsc_ctx* ctx, double* out, int32_t n_kinds);
 
 /* Launch-by-launch record of the timed launches since hsc_ctx_profile(ctx, 1)
- * (after hsc_sync): out[3k] = kind (as in hsc_ctx_profile_read), out[3k+1] =
- * algorithmic flops of the launch, out[3k+2] = its duration in ms, for the first
- * min(count, max_launches) launches (host buffer of 3 * max_launches doubles);
- * *count receives the number recorded (at most 4,000,000). */
+ * (after hsc_sync): out[4k] = kind (as in hsc_ctx_profile_read), out[4k+1] =
+ * algorithmic flops of the launch, out[4k+2] = its duration in ms, out[4k+3] =
+ * the part of the method it belongs to (0 other: energy set-up, growth
+ * indicators; 1 pivot-block inverses of Algorithm 1; 2 the rest of the fold of
+ * Algorithm 1: frontal assembly, multipliers, Schur updates; 3 extraction of
+ * G^r; 4 fold of N in Algorithm 2; 5 extraction of P in Algorithm 2), for the
+ * first min(count, max_launches) launches (host buffer of 4 * max_launches
+ * doubles); *count receives the number recorded (at most 4,000,000). */
 hsc_status hsc_ctx_profile_launches(hsc_ctx* ctx, int64_t max_launches, double* out, int64_t* count);
 
 #ifdef __cplusplus

@@ -79,7 +79,11 @@ struct Step {
   int out = 0;                // DIAG destination
   int dd = 0;                 // row kernels: operands in double-double
   double flops = 0;           // algorithmic real flops of this launch (GEMM: 8 M N K)
+  int phase = 0;              // part of the method (Phase), for launch timing
 };
+
+// parts of the method a step belongs to (reported with every timed launch)
+enum Phase { PH_OTHER = 0, PH_INVERSE = 1, PH_FOLD = 2, PH_EXTRACT_G = 3, PH_FOLD_N = 4, PH_EXTRACT_P = 5 };
 
 enum OutSel { O_GR = 0, O_GL = 1, O_SPEC_L = 2, O_SPEC_R = 3, O_AR_TMP = 4 };
 
@@ -136,11 +140,12 @@ struct hsc_ctx {
   // optional per-launch timing: events around every launch, grouped by step kind
   bool profile = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
-  std::vector<std::pair<int, double>> ev_meta;   // (kind, flops) per recorded launch
+  struct EvMeta { int kind; double flops; int phase; };
+  std::vector<EvMeta> ev_meta;                    // per recorded launch
   size_t ev_used = 0;
   double prof[16][3] = {};                        // kind -> launches, ms, flops (16 >= number of kinds)
   hipStream_t cap_stream = nullptr;               // graph capture (a stream of its own, default priority)
-  std::vector<double> launch_log;                 // (kind, flops, ms) per timed launch since profiling was enabled
+  std::vector<double> launch_log;                 // (kind, flops, ms, phase) per timed launch since profiling was enabled
   // forest of the last multi-device batch and its output staging
   std::vector<uint64_t> forest_key;
   hsc_tree* forest = nullptr;
@@ -170,6 +175,11 @@ struct Builder {
   std::vector<Step> steps;
   std::vector<Channel> chans;
   char* wsbase = nullptr;   // device address (known before job pointers are written)
+  int phase = PH_OTHER;     // stamped onto every step (launch timing)
+  void push(Step s) {
+    s.phase = phase;
+    steps.push_back(s);
+  }
 
   // per-cluster tree constants (blob offsets)
   std::vector<size_t> c_invrel, c_rel, c_gcol, c_trow, c_trowp, c_nfc, c_sites, c_fs;
@@ -408,7 +418,7 @@ struct Builder {
     s.count = s.count_k[0];
     s.i0 = opA; s.i1 = opB;
     s.ar = ar; s.ai = ai; s.beta = beta;
-    steps.push_back(s);
+    push(s);
   }
   // RowJob list: child-ref arrays are given as host vectors to be placed in the blob
   struct RJ { RowJob j; std::vector<ChildRef> kids; std::vector<size_t> kid_invrel; bool p1_blob = false; };
@@ -458,7 +468,7 @@ struct Builder {
     s.map = blob.push(rmap);
     s.count = (int)rmap.size();
     s.i0 = i0; s.i1 = i1; s.out = out; s.dd = dd;
-    steps.push_back(s);
+    push(s);
   }
   static const int32_t* off32(size_t o) { return reinterpret_cast<const int32_t*>(o); }
 
@@ -518,11 +528,12 @@ struct Builder {
     s.i1 = negate;
     s.i2 = opB;
     s.beta = beta;
-    steps.push_back(s);
+    push(s);
   }
 
   void fold_dd(const std::vector<std::vector<int>>& L) {
     for (int d = (int)L.size() - 1; d >= 0; --d) {
+      phase = PH_FOLD;
       std::vector<RJ> jobs;
       for (int i : L[d])
         for (int e = 0; e < B; ++e) {
@@ -550,6 +561,7 @@ struct Builder {
           jobs.push_back(q);
         }
       rowstep(S_DD_ASSEMBLE, jobs);
+      phase = PH_INVERSE;
       int maxn = 0;
       for (int i : L[d]) maxn = std::max(maxn, n_of(i));
       const int nb = dd_inv_nb(maxn);
@@ -569,9 +581,9 @@ struct Builder {
       const size_t ijo = blob.push(ij);
       for (int k0 = 0; k0 < maxn; k0 += nb) {
         Step p; p.kind = S_DD_INV_PANEL; p.jobs = ijo; p.njobs = (int)ij.size(); p.i0 = k0; p.i1 = nb; p.i2 = maxn;
-        steps.push_back(p);
+        push(p);
         Step w = p; w.kind = S_DD_INV_SWAP;
-        steps.push_back(w);
+        push(w);
         std::vector<GPD> ps;
         for (const InvJobDD& j : ij) {
           if (k0 >= j.n) continue;
@@ -581,7 +593,8 @@ struct Builder {
         dd_gemm(0, 0, ps, 0, 1);
       }
       Step u; u.kind = S_DD_INV_UNSCR; u.jobs = ijo; u.njobs = (int)ij.size(); u.i2 = maxn;
-      steps.push_back(u);
+      push(u);
+      phase = PH_FOLD;
       std::vector<GPD> pp, pu;
       for (int i : L[d]) {
         if (root(i)) continue;
@@ -600,6 +613,7 @@ struct Builder {
   }
 
   void guard_step() {
+    phase = PH_OTHER;
     // conditioning / growth indicators of every pivot block
     std::vector<RowJob> gj;
     for (int i = 0; i < (int)t->cl.size(); ++i)
@@ -616,12 +630,13 @@ struct Builder {
     g.kind = S_GUARD;
     g.jobs = blob.push(gj);
     g.njobs = (int)gj.size();
-    steps.push_back(g);
+    push(g);
   }
 
   void fold(const std::vector<std::vector<int>>& L) {
     if (ddf) { fold_dd(L); return; }
     for (int d = (int)L.size() - 1; d >= 0; --d) {
+      phase = PH_FOLD;
       // assemble
       std::vector<RJ> jobs;
       for (int i : L[d])
@@ -650,6 +665,7 @@ struct Builder {
           jobs.push_back(q);
         }
       rowstep(S_ASSEMBLE, jobs);
+      phase = PH_INVERSE;
       // inverse of the pivot blocks
       int maxn = 0;
       for (int i : L[d]) maxn = std::max(maxn, n_of(i));
@@ -673,9 +689,9 @@ struct Builder {
       for (int s0 = 0; s0 < maxn; s0 += SW) {
         for (int k0 = s0; k0 < std::min(s0 + SW, maxn); k0 += nb) {
           Step p; p.kind = S_INV_PANEL; p.jobs = ijo; p.njobs = (int)ij.size(); p.i0 = k0; p.i1 = nb; p.i2 = maxn;
-          steps.push_back(p);
+          push(p);
           Step w = p; w.kind = S_INV_SWAP;
-          steps.push_back(w);
+          push(w);
           std::vector<GP> ps;
           for (const InvJob& j : ij) {
             if (k0 >= j.n) continue;
@@ -686,7 +702,7 @@ struct Builder {
           gemm(OP_N, OP_N, ps, 1.0, 0.0, 1);
         }
         Step sp; sp.kind = S_INV_SUPER; sp.jobs = ijo; sp.njobs = (int)ij.size(); sp.i0 = s0; sp.i1 = SW; sp.i2 = maxn;
-        steps.push_back(sp);
+        push(sp);
         std::vector<GP> pt;
         for (const InvJob& j : ij) {
           if (s0 >= j.n) continue;
@@ -698,7 +714,8 @@ struct Builder {
         gemm(OP_N, OP_N, pt, 1.0, 0.0, 1);
       }
       Step u; u.kind = S_INV_UNSCR; u.jobs = ijo; u.njobs = (int)ij.size(); u.i2 = maxn;
-      steps.push_back(u);
+      push(u);
+      phase = PH_FOLD;
       // Psi = -Inv * A_if ;  U = A_ff + A_if^T Psi
       std::vector<GP> pp, pu;
       for (int i : L[d]) {
@@ -749,6 +766,7 @@ struct Builder {
 
   template <class T>
   void extract_g(const std::vector<std::vector<int>>& L) {
+    phase = PH_EXTRACT_G;
     diag_step<T>(L[0], DIAG_SEP, O_GR, 0, true);
     for (size_t d = 1; d < L.size(); ++d) {
       std::vector<int> seps, leaves;
@@ -832,6 +850,7 @@ struct Builder {
   void channel_steps(const std::vector<std::vector<int>>& L, int k) {
     const Channel& ch = chans[k];
     // N fold, bottom-up
+    phase = PH_FOLD_N;
     for (int d = (int)L.size() - 1; d >= 0; --d) {
       std::vector<RJ> asm_jobs, nfc_jobs;
       std::vector<GPT<T>> nu, mm;
@@ -885,6 +904,7 @@ struct Builder {
       gemm_x(OP_N, OP_N, mm, 0);
     }
     // P extract, top-down
+    phase = PH_EXTRACT_P;
     diag_step<T>(L[0], DIAG_SEP, ch.out, k, false);
     for (size_t d = 1; d < L.size(); ++d) {
       std::vector<int> seps, leaves;
@@ -962,14 +982,15 @@ hsc_status fold_events(hsc_ctx* ctx) {
   for (size_t k = 0; k < ctx->ev_used; ++k) {
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, ctx->ev_pool[k].first, ctx->ev_pool[k].second));
-    const int kind = ctx->ev_meta[k].first;
+    const int kind = ctx->ev_meta[k].kind;
     ctx->prof[kind][0] += 1;
     ctx->prof[kind][1] += ms;
-    ctx->prof[kind][2] += ctx->ev_meta[k].second;
-    if (ctx->launch_log.size() < 3 * (size_t)4000000) {
+    ctx->prof[kind][2] += ctx->ev_meta[k].flops;
+    if (ctx->launch_log.size() < 4 * (size_t)4000000) {
       ctx->launch_log.push_back(kind);
-      ctx->launch_log.push_back(ctx->ev_meta[k].second);
+      ctx->launch_log.push_back(ctx->ev_meta[k].flops);
       ctx->launch_log.push_back(ms);
+      ctx->launch_log.push_back(ctx->ev_meta[k].phase);
     }
   }
   ctx->ev_used = 0;
@@ -1021,11 +1042,11 @@ int run_steps(hsc_ctx* ctx, hipStream_t st, Plan* pl, int e_base, int nvalid, vo
         HIPCHK(hipEventCreate(&a));
         HIPCHK(hipEventCreate(&b));
         ctx->ev_pool.push_back({a, b});
-        ctx->ev_meta.push_back({0, 0.0});
+        ctx->ev_meta.push_back({0, 0.0, 0});
       }
       HIPCHK(hipEventRecord(ctx->ev_pool[ctx->ev_used].first, st));
       ev1 = ctx->ev_pool[ctx->ev_used].second;
-      ctx->ev_meta[ctx->ev_used] = {(int)s.kind, s.flops};
+      ctx->ev_meta[ctx->ev_used] = {(int)s.kind, s.flops, s.phase};
       ctx->ev_used++;
     }
     const void* jobs = pl->blob + s.jobs;
@@ -1774,10 +1795,10 @@ hsc_status hsc_ctx_profile(hsc_ctx* ctx, int32_t enable) {
 
 hsc_status hsc_ctx_profile_launches(hsc_ctx* ctx, int64_t max_launches, double* out, int64_t* count) {
   if (!ctx || !count || max_launches < 0 || (max_launches > 0 && !out)) { set_error("bad arguments"); return HSC_E_ARG; }
-  const int64_t n = (int64_t)(ctx->launch_log.size() / 3);
+  const int64_t n = (int64_t)(ctx->launch_log.size() / 4);
   *count = n;
   const int64_t m = std::min(n, max_launches);
-  if (m > 0) std::memcpy(out, ctx->launch_log.data(), sizeof(double) * 3 * (size_t)m);
+  if (m > 0) std::memcpy(out, ctx->launch_log.data(), sizeof(double) * 4 * (size_t)m);
   return HSC_OK;
 }
 

@@ -152,13 +152,16 @@ class Context:
         return {name: dict(launches=buf[3 * i], ms=buf[3 * i + 1], flops=buf[3 * i + 2])
                 for i, name in enumerate(self.PROFILE_KINDS)}
 
+    PROFILE_PHASES = ("other", "inverse", "fold", "extract_g", "fold_n", "extract_p")
+
     def profile_launches(self) -> np.ndarray:
-        """[(kind, flops, ms)] of every timed launch since profile(True) (call after sync())."""
+        """[(kind, flops, ms, phase)] of every timed launch since profile(True) (call after sync());
+        phase indexes PROFILE_PHASES."""
         cnt = C.c_int64()
         check(lib().hsc_ctx_profile_launches(self.h, 0, None, C.byref(cnt)))
-        buf = np.zeros(3 * max(int(cnt.value), 1))
+        buf = np.zeros(4 * max(int(cnt.value), 1))
         check(lib().hsc_ctx_profile_launches(self.h, cnt.value, _ptr(buf), C.byref(cnt)))
-        return buf[:3 * int(cnt.value)].reshape(-1, 3)
+        return buf[:4 * int(cnt.value)].reshape(-1, 4)
 
     def close(self):
         if getattr(self, "h", None):
