@@ -114,7 +114,16 @@ typedef struct {
    *     of Algorithm 2 and the lesser channels stay complex128;
    * 2 = double-double fold and extraction: every block of G, of the lesser
    *     channels and their products is carried in double-double and only the
-   *     returned diagonals are rounded to complex128.
+   *     returned diagonals are rounded to complex128;
+   * 3 = as 2, with every double-double block product of depth K >= 32 formed
+   *     on the integer matrix cores: each operand is split exactly into 16
+   *     signed 8-bit slices scaled by a power of two per row (per column of
+   *     the right operand), the slice products are summed exactly in 32-bit
+   *     integers, and the pairs whose weight is within 2^-105 of the leading
+   *     one are combined in double-double (at most about K 2^-104 times the
+   *     product of the largest row and column entries; products with K < 32, the
+   *     pivot-block inverse updates among them, stay on the vector units).
+   *     Needs a slice scratch of up to 4 GiB besides the workspace.
    * The unpivoted cluster elimination amplifies rounding errors by up to
    * ~1/sigma_min(A_ii)^2 at energies where a cluster block A_ii is nearly
    * singular (outside the lead band, where nothing broadens it): in the fold
@@ -251,7 +260,8 @@ hsc_status hsc_totals(hsc_ctx* ctx, int32_t n_e, int64_t n, const void* diag_gr,
  * 0 assemble, 1 inverse panel, 2 inverse swap, 3 inverse unscramble, 4 GEMM,
  * 5 gather, 6 N assembly, 7 diagonal output, 8 growth indicators, 9-13 the
  * double-double assemble / panel / swap / unscramble / GEMM, 14 inverse
- * super-panel preparation.
+ * super-panel preparation, 15 operand splitting into 8-bit slices, 16 slice
+ * products on the integer matrix cores (precision 3).
  * hsc_ctx_profile_read writes out[3*k + {0,1,2}] = launches, milliseconds,
  * algorithmic real flops (GEMM: 8 M N K per problem) for k < n_kinds.
  * Errors: HSC_E_ARG. */

@@ -45,12 +45,18 @@ hsc_status hsc_kern_zgemm_tile(hsc_ctx* ctx, int32_t tile_kind, int32_t opA, int
  * double-double.  Every element is 32 bytes, four doubles (real hi, real lo,
  * imaginary hi, imaginary lo) with |lo| <= ulp(hi) / 2; row-major, leading
  * dimensions in elements; device pointers.  op 0 = as is, 1 = transposed.
- * config: tile of the kernel, 0 = 32x32, 1 = 64x32, 2 = 64x64.  The result
- * is accurate to about 2^-104 relative to sum_k |op(A)_ik| |op(B)_kj| (products
- * accumulated lazily, renormalised every 8 terms).  beta is 0 or 1; C may equal
- * D and may be NULL when beta = 0.  Synchronous.
- * Errors: HSC_E_ARG (sizes < 0, bad op or config, leading dimension too small),
- * HSC_E_OOM, HSC_E_HIP. */
+ * config 0-2: FP64 vector units with tiles 0 = 32x32, 1 = 64x32, 2 = 64x64; the
+ * result is accurate to about 2^-104 relative to sum_k |op(A)_ik| |op(B)_kj|
+ * (products accumulated lazily, renormalised every 8 terms).  config 3: the
+ * integer matrix cores (the products of hsc_solve_opts.precision = 3): op(A)
+ * split into 16 signed 8-bit slices per element with one power-of-two scale per
+ * row, op(B) likewise per column (the error-free splitting of Ozaki et al.),
+ * exact int32 sums of slice products, the leading 136 of 256 slice pairs
+ * combined in double-double; the error is at most about K 2^-104 max_k
+ * |op(A)_ik| max_k |op(B)_kj| + 2^-104 |C_ij|, K <= 10880.  beta is 0 or 1; C
+ * may equal D and may be NULL when beta = 0.  Synchronous.
+ * Errors: HSC_E_ARG (sizes < 0, bad op or config, leading dimension too small,
+ * K > 10880 with config 3), HSC_E_OOM, HSC_E_HIP. */
 hsc_status hsc_kern_zgemm_dd(hsc_ctx* ctx, int32_t config, int32_t opA, int32_t opB, int32_t M, int32_t N,
                              int32_t K, int32_t negate, const void* A, int32_t lda, const void* B, int32_t ldb,
                              int32_t beta, const void* C, int32_t ldc, void* D, int32_t ldd);

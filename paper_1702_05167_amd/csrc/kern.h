@@ -185,6 +185,41 @@ void launch_dd_inv_swap(hipStream_t st, const InvJobDD* jobs, int njobs, int k0,
 void launch_dd_inv_unscramble(hipStream_t st, const InvJobDD* jobs, int njobs, int max_n);
 int dd_inv_nb(int max_n);
 
+// ---- double-double products from 8-bit slices on the integer matrix cores (ozaki.hip) ----
+// slices per operand: each double-double operand is kept to 2^-112 of its row's (or column's)
+// largest entry
+constexpr int kOzSlices = 16;
+// One operand to split: element (r, k) = X[r * ldr + k * ldk] for r < R, k < K (complex
+// double-double); out = planes [3][kOzSlices][Rp][Kp] int8 (Re, Im, Re + Im), ex = [Rp] row
+// exponents; Rp a multiple of 32 (>= R), Kp of 64 (>= K); zero padding.  Workgroups
+// [blk_off, blk_off + Rp / 64 rounded up) of a split launch belong to this job.
+struct OzSplitJob {
+  const zdd* X;
+  int64_t ldr, ldk;
+  int32_t R, K, Rp, Kp;
+  int8_t* out;
+  int32_t* ex;
+  int32_t blk_off;
+  int32_t pad;
+};
+// One product D = (-1)^negate A' B' + beta C from split operands (A8: rows of A', B8: columns of
+// B'); 32 x 32 output tiles.
+struct GemmProbOZ {
+  const int8_t* A8;
+  const int8_t* B8;
+  const int32_t* ea;
+  const int32_t* eb;
+  const zdd* C;
+  zdd* D;
+  double2* D64;
+  int32_t M, N, Mp, Np, Kp;
+  int32_t ldc, ldd, ldd64;
+  int32_t tiles_n, tile_off;
+};
+void launch_oz_split(hipStream_t st, const OzSplitJob* jobs, const int32_t* blk_job, int total_blocks, int kfast);
+void launch_oz_gemm(hipStream_t st, const GemmProbOZ* probs, const int32_t* tile_prob, int total_tiles, int negate,
+                    int beta);
+
 // debug / unit-test helpers
 void launch_mfma_rate(hipStream_t st, double* out, int blocks, int iters);
 void launch_mfma_probe(hipStream_t st, double* out);

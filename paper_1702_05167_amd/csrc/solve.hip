@@ -12,7 +12,9 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <tuple>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -53,10 +55,15 @@ struct Blob {
   }
   // mark a pointer field (at byte offset `field`) as holding a blob offset
   void reloc(size_t field) { relocs.push_back(field); }
+  // pointer fields holding offsets into the plan's slice scratch (double-double products on the
+  // integer matrix cores), rebased when the scratch is allocated
+  std::vector<size_t> sc_relocs;
 };
 
 enum StepKind { S_ASSEMBLE, S_INV_PANEL, S_INV_SWAP, S_INV_UNSCR, S_GEMM, S_GATHER, S_ASSEMBLE_N, S_DIAG, S_GUARD,
-                S_DD_ASSEMBLE, S_DD_INV_PANEL, S_DD_INV_SWAP, S_DD_INV_UNSCR, S_DD_GEMM, S_INV_SUPER};
+                S_DD_ASSEMBLE, S_DD_INV_PANEL, S_DD_INV_SWAP, S_DD_INV_UNSCR, S_DD_GEMM, S_INV_SUPER,
+                S_OZ_SPLIT, S_OZ_GEMM};
+constexpr int kStepKinds = 17;
 
 // Tile sizes a plan keeps GEMM problem lists and tile maps for: 64x64, 128x64, 64x128, 32x32,
 // 128x128.  Every launch kind of launch_gemm uses one of them (tile_dims_of).
@@ -122,7 +129,10 @@ struct Plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   char* stage = nullptr;
+  char* oz = nullptr;            // slice scratch of the products on the integer matrix cores
+  size_t oz_bytes = 0;
   ~Plan() {
+    if (oz) (void)hipFree(oz);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     if (stage) (void)hipFree(stage);
@@ -143,7 +153,7 @@ struct hsc_ctx {
   struct EvMeta { int kind; double flops; int phase; };
   std::vector<EvMeta> ev_meta;                    // per recorded launch
   size_t ev_used = 0;
-  double prof[16][3] = {};                        // kind -> launches, ms, flops (16 >= number of kinds)
+  double prof[24][3] = {};                        // kind -> launches, ms, flops (24 >= number of kinds)
   hipStream_t cap_stream = nullptr;               // graph capture (a stream of its own, default priority)
   std::vector<double> launch_log;                 // (kind, flops, ms, phase) per timed launch since profiling was enabled
   // forest of the last multi-device batch and its output staging
@@ -170,6 +180,8 @@ struct Builder {
   bool gl;        // any lesser output -> full ancestor rows on contact paths
   bool ddf = false;   // double-double fold
   bool ddx = false;   // double-double extraction as well (G, the lesser channels)
+  bool oz = false;    // double-double products from 8-bit slices on the integer matrix cores
+  size_t oz_need = 0; // largest slice scratch of one such product step
   size_t ws = 0;  // workspace bytes
   Blob blob;
   std::vector<Step> steps;
@@ -494,9 +506,119 @@ struct Builder {
   }
 
   struct GPD { const zdd *A, *B, *C; zdd* D; double2* D64; int M, N, K, lda, ldb, ldc, ldd, ldd64; };
+  // Double-double block products: with `oz`, every problem whose depth K lies in
+  // [kOzMinK, kOzMaxK] runs on the integer matrix cores (split + slice product); the others,
+  // and every product without `oz`, on the FP64 vector units.
+  static constexpr int kOzMinK = 32;
+  static constexpr int kOzMaxK = 10880;   // int32 accumulators: 3 * 16 * 64^2 * Kp < 2^31
+  static constexpr size_t kOzStepCap = size_t(4) << 30;   // slice scratch of one product step
+  void dd_gemm(int opA, int opB, const std::vector<GPD>& ps, int negate, int beta) {
+    if (!oz) { dd_gemm_valu(opA, opB, ps, negate, beta); return; }
+    std::vector<GPD> big, rest;
+    for (const GPD& g : ps) ((g.K >= kOzMinK && g.K <= kOzMaxK) ? big : rest).push_back(g);
+    if (!big.empty()) oz_gemm(opA, opB, big, negate, beta);
+    if (!rest.empty()) dd_gemm_valu(opA, opB, rest, negate, beta);
+  }
+
+  static size_t oz_round(size_t v, size_t a) { return (v + a - 1) / a * a; }
+  static size_t oz_bytes(int R, int K) {
+    return oz_round((size_t)3 * kOzSlices * oz_round(R, 32) * oz_round(K, 64) + 4 * oz_round(R, 32), 256);
+  }
+
+  // split + product steps, the problem list cut into pieces whose slices fit kOzStepCap; an operand
+  // shared by several problems of a piece is split once
+  void oz_gemm(int opA, int opB, const std::vector<GPD>& ps, int negate, int beta) {
+    size_t i0 = 0;
+    while (i0 < ps.size()) {
+      std::vector<OzSplitJob> sj[2];
+      std::vector<int32_t> bj[2];
+      std::vector<GemmProbOZ> gp;
+      std::vector<int32_t> tmap;
+      std::map<std::tuple<const void*, int64_t, int64_t, int, int>, std::pair<size_t, size_t>> seen;
+      size_t cur = 0, i = i0;
+      double flops = 0;
+      auto operand = [&](const zdd* X, int64_t ldr, int64_t ldk, int R, int K) {
+        const auto key = std::make_tuple((const void*)X, ldr, ldk, R, K);
+        auto it = seen.find(key);
+        if (it != seen.end()) return it->second;
+        const int Rp = (int)oz_round(R, 32), Kp = (int)oz_round(K, 64);
+        const size_t off = cur;
+        cur += oz_bytes(R, K);
+        OzSplitJob j{};
+        j.X = X; j.ldr = ldr; j.ldk = ldk; j.R = R; j.K = K; j.Rp = Rp; j.Kp = Kp;
+        j.out = reinterpret_cast<int8_t*>(off);
+        j.ex = reinterpret_cast<int32_t*>(off + (size_t)3 * kOzSlices * Rp * Kp);
+        const int kf = ldk == 1 ? 1 : 0;
+        j.blk_off = (int32_t)bj[kf].size();
+        for (int b = 0; b < (Rp + 63) / 64; ++b) bj[kf].push_back((int32_t)sj[kf].size());
+        sj[kf].push_back(j);
+        const auto r = std::make_pair(off, off + (size_t)3 * kOzSlices * Rp * Kp);
+        seen[key] = r;
+        return r;
+      };
+      for (; i < ps.size(); ++i) {
+        const GPD& g = ps[i];
+        if (g.M <= 0 || g.N <= 0) continue;
+        const size_t need = oz_bytes(g.M, g.K) + oz_bytes(g.N, g.K);
+        if (i > i0 && cur + need > kOzStepCap) break;
+        const auto a = opA == 0 ? operand(g.A, g.lda, 1, g.M, g.K) : operand(g.A, 1, g.lda, g.M, g.K);
+        const auto b = opB == 0 ? operand(g.B, 1, g.ldb, g.N, g.K) : operand(g.B, g.ldb, 1, g.N, g.K);
+        GemmProbOZ p{};
+        p.A8 = reinterpret_cast<const int8_t*>(a.first);
+        p.ea = reinterpret_cast<const int32_t*>(a.second);
+        p.B8 = reinterpret_cast<const int8_t*>(b.first);
+        p.eb = reinterpret_cast<const int32_t*>(b.second);
+        p.C = g.C; p.D = g.D; p.D64 = g.D64;
+        p.M = g.M; p.N = g.N;
+        p.Mp = (int)oz_round(g.M, 32); p.Np = (int)oz_round(g.N, 32); p.Kp = (int)oz_round(g.K, 64);
+        p.ldc = g.ldc; p.ldd = g.ldd; p.ldd64 = g.ldd64;
+        p.tiles_n = p.Np / 32;
+        p.tile_off = (int32_t)tmap.size();
+        const int tiles = (p.Mp / 32) * p.tiles_n;
+        for (int k = 0; k < tiles; ++k) tmap.push_back((int32_t)gp.size());
+        gp.push_back(p);
+        flops += 8.0 * g.M * g.N * g.K;
+      }
+      oz_need = std::max(oz_need, cur);
+      for (int kf = 0; kf < 2; ++kf) {
+        if (sj[kf].empty()) continue;
+        Step s;
+        s.kind = S_OZ_SPLIT;
+        s.jobs = blob.push(sj[kf]);
+        for (size_t q = 0; q < sj[kf].size(); ++q) {
+          blob.sc_relocs.push_back(s.jobs + q * sizeof(OzSplitJob) + offsetof(OzSplitJob, out));
+          blob.sc_relocs.push_back(s.jobs + q * sizeof(OzSplitJob) + offsetof(OzSplitJob, ex));
+        }
+        s.map = blob.push(bj[kf]);
+        s.count = (int)bj[kf].size();
+        s.i0 = kf;
+        push(s);
+      }
+      if (!gp.empty()) {
+        Step s;
+        s.kind = S_OZ_GEMM;
+        s.jobs = blob.push(gp);
+        for (size_t q = 0; q < gp.size(); ++q) {
+          const size_t b0 = s.jobs + q * sizeof(GemmProbOZ);
+          blob.sc_relocs.push_back(b0 + offsetof(GemmProbOZ, A8));
+          blob.sc_relocs.push_back(b0 + offsetof(GemmProbOZ, ea));
+          blob.sc_relocs.push_back(b0 + offsetof(GemmProbOZ, B8));
+          blob.sc_relocs.push_back(b0 + offsetof(GemmProbOZ, eb));
+        }
+        s.map = blob.push(tmap);
+        s.count = (int)tmap.size();
+        s.i1 = negate;
+        s.beta = beta;
+        s.flops = flops;
+        push(s);
+      }
+      i0 = i;
+    }
+  }
+
   // one problem list and tile map per tile configuration of the double-double GEMM (the tuner picks
   // one per launch; `tile` is the configuration)
-  void dd_gemm(int opA, int opB, const std::vector<GPD>& ps, int negate, int beta) {
+  void dd_gemm_valu(int opA, int opB, const std::vector<GPD>& ps, int negate, int beta) {
     Step s;
     s.kind = S_DD_GEMM;
     for (int cfg = 0; cfg < dd_gemm_configs(); ++cfg) {
@@ -1101,6 +1223,12 @@ int run_steps(hsc_ctx* ctx, hipStream_t st, Plan* pl, int e_base, int nvalid, vo
         launch_dd_gemm(st, s.i0, s.i2, s.tile, (const GemmProbDD*)(pl->blob + s.jobs_k[s.tile]),
                        reinterpret_cast<const int32_t*>(pl->blob + s.map_k[s.tile]), s.count_k[s.tile], s.i1, s.beta);
         break;
+      case S_OZ_SPLIT:
+        launch_oz_split(st, (const OzSplitJob*)jobs, map, s.count, s.i0);
+        break;
+      case S_OZ_GEMM:
+        launch_oz_gemm(st, (const GemmProbOZ*)jobs, map, s.count, s.i1, s.beta);
+        break;
       case S_DIAG: {
         void* out = nullptr;
         int kind = OUT_COMPLEX, eb = e_base;
@@ -1216,7 +1344,8 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
   pl->uid = t->uid; pl->B = B; pl->want = want; pl->n = t->n; pl->prec = prec; pl->tune = tune; pl->m3 = m3;
   Builder b{t, B, want, (want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR)) != 0};
   b.ddf = prec >= 1;
-  b.ddx = prec == 2;
+  b.ddx = prec >= 2;
+  b.oz = prec == 3;
   b.channels();
   b.layout();
   // per-plan small buffers at the end of the workspace
@@ -1255,6 +1384,22 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
     if (b.ddx) b.channel_steps<zdd>(L, (int)k);
     else b.channel_steps<double2>(L, (int)k);
   }
+  // slice scratch of the products on the integer matrix cores
+  if (b.oz_need > 0) {
+    pl->oz_bytes = b.oz_need;
+    if (hipMalloc(&pl->oz, pl->oz_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      pl->oz = nullptr;
+      set_error("slice scratch allocation failed (" + std::to_string(pl->oz_bytes) + " bytes)");
+      return HSC_E_OOM;
+    }
+    for (size_t f : b.blob.sc_relocs) {
+      uint64_t v;
+      std::memcpy(&v, b.blob.data.data() + f, 8);
+      v += reinterpret_cast<uint64_t>(pl->oz);
+      std::memcpy(b.blob.data.data() + f, &v, 8);
+    }
+  }
   // upload the blob with relocations
   pl->blob_bytes = b.blob.data.size();
   if (hipMalloc(&pl->blob, pl->blob_bytes) != hipSuccess) {
@@ -1292,7 +1437,7 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
 size_t plan_bytes_per_slot(const hsc_tree* t, uint32_t want, int prec) {
   Builder b{t, 1, want, (want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR)) != 0};
   b.ddf = prec >= 1;
-  b.ddx = prec == 2;
+  b.ddx = prec >= 2;
   b.channels();
   b.layout();
   return b.ws;
@@ -1378,7 +1523,7 @@ static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
   }
   B = std::min(B, n_e);
   Plan* pl = nullptr;
-  if (opts->precision < 0 || opts->precision > 2) { set_error("precision must be 0, 1 or 2"); return HSC_E_ARG; }
+  if (opts->precision < 0 || opts->precision > 3) { set_error("precision must be 0, 1, 2 or 3"); return HSC_E_ARG; }
   if (opts->complex3m != 0 && opts->complex3m != 1) { set_error("complex3m must be 0 or 1"); return HSC_E_ARG; }
   int st = build_plan(ctx, tree, B, want, opts->precision, opts->tune != 0, opts->complex3m, &pl);
   if (st != HSC_OK) return (hsc_status)st;
@@ -1804,7 +1949,7 @@ hsc_status hsc_ctx_profile_launches(hsc_ctx* ctx, int64_t max_launches, double* 
 
 hsc_status hsc_ctx_profile_read(hsc_ctx* ctx, double* out, int32_t n_kinds) {
   if (!ctx || !out || n_kinds < 0) { set_error("bad arguments"); return HSC_E_ARG; }
-  for (int k = 0; k < n_kinds && k < 16; ++k)
+  for (int k = 0; k < n_kinds && k < kStepKinds; ++k)
     for (int q = 0; q < 3; ++q) out[3 * k + q] = ctx->prof[k][q];
   return HSC_OK;
 }
@@ -1813,6 +1958,62 @@ hsc_status hsc_ctx_profile_read(hsc_ctx* ctx, double* out, int32_t n_kinds) {
 
 // ---------------------------------------------------------------------------------------------
 // kernel-level entry points (synchronous: they return after the work is done)
+
+namespace hsc {
+namespace {
+
+constexpr int kOzMaxDepth = 10880;   // int32 accumulators of the slice products
+
+size_t oz_pad(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// one product on the integer matrix cores (split A', split B', slice product), synchronous
+hsc_status kern_zgemm_oz(hsc_ctx* ctx, int opA, int opB, int M, int N, int K, int negate, const void* A, int lda,
+                         const void* B, int ldb, int beta, const void* C, int ldc, void* D, int ldd) {
+  const int Mp = (int)oz_pad(M, 32), Np = (int)oz_pad(N, 32), Kp = (int)oz_pad(K, 64);
+  const size_t sa = (size_t)3 * kOzSlices * Mp * Kp, sb = (size_t)3 * kOzSlices * Np * Kp;
+  const int ba = (Mp + 63) / 64, bb = (Np + 63) / 64;
+  const int tiles = (Mp / 32) * (Np / 32);
+  // layout: [jobs: A split, B split, product][maps: A blocks, B blocks, tiles][A8][B8][ea][eb]
+  const size_t o_map = 1024, o_a8 = oz_pad(o_map + 4 * (size_t)(ba + bb + tiles), 256);
+  const size_t o_b8 = oz_pad(o_a8 + sa, 256), o_ea = oz_pad(o_b8 + sb, 256), o_eb = oz_pad(o_ea + 4 * (size_t)Mp, 256);
+  const size_t bytes = o_eb + 4 * (size_t)Np;
+  char* dev = nullptr;
+  if (hipMalloc(&dev, bytes) != hipSuccess) { (void)hipGetLastError(); set_error("alloc failed"); return HSC_E_OOM; }
+  OzSplitJob ja{}, jb{};
+  ja.X = (const zdd*)A; ja.R = M; ja.K = K; ja.Rp = Mp; ja.Kp = Kp;
+  if (opA == 0) { ja.ldr = lda; ja.ldk = 1; } else { ja.ldr = 1; ja.ldk = lda; }
+  ja.out = (int8_t*)(dev + o_a8); ja.ex = (int32_t*)(dev + o_ea);
+  jb.X = (const zdd*)B; jb.R = N; jb.K = K; jb.Rp = Np; jb.Kp = Kp;
+  if (opB == 0) { jb.ldr = 1; jb.ldk = ldb; } else { jb.ldr = ldb; jb.ldk = 1; }
+  jb.out = (int8_t*)(dev + o_b8); jb.ex = (int32_t*)(dev + o_eb);
+  GemmProbOZ p{};
+  p.A8 = ja.out; p.B8 = jb.out; p.ea = ja.ex; p.eb = jb.ex;
+  p.C = (const zdd*)C; p.D = (zdd*)D; p.D64 = nullptr;
+  p.M = M; p.N = N; p.Mp = Mp; p.Np = Np; p.Kp = Kp; p.ldc = ldc; p.ldd = ldd; p.ldd64 = 0;
+  p.tiles_n = Np / 32; p.tile_off = 0;
+  std::vector<char> host(1024 + 4 * (size_t)(ba + bb + tiles), 0);
+  std::memcpy(host.data(), &ja, sizeof(ja));
+  std::memcpy(host.data() + 256, &jb, sizeof(jb));
+  std::memcpy(host.data() + 512, &p, sizeof(p));   // every map entry is 0 (one job / problem)
+  hipError_t e = hipMemcpy(dev, host.data(), host.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    const int32_t* m = (const int32_t*)(dev + o_map);
+    launch_oz_split(ctx->stream, (const OzSplitJob*)dev, m, ba, ja.ldk == 1 ? 1 : 0);
+    launch_oz_split(ctx->stream, (const OzSplitJob*)(dev + 256), m + ba, bb, jb.ldk == 1 ? 1 : 0);
+    launch_oz_gemm(ctx->stream, (const GemmProbOZ*)(dev + 512), m + ba + bb, tiles, negate, beta);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = ctx->stream ? hipStreamSynchronize(ctx->stream) : hipDeviceSynchronize();
+  }
+  (void)hipFree(dev);
+  if (e != hipSuccess) {
+    set_error(std::string("HIP error in hsc_kern_zgemm_dd: ") + hipGetErrorString(e));
+    return HSC_E_HIP;
+  }
+  return HSC_OK;
+}
+
+}  // namespace
+}  // namespace hsc
 
 extern "C" {
 
@@ -1869,7 +2070,8 @@ hsc_status hsc_kern_zgemm_dd(hsc_ctx* ctx, int32_t config, int32_t opA, int32_t 
                              int32_t K, int32_t negate, const void* A, int32_t lda, const void* B, int32_t ldb,
                              int32_t beta, const void* C, int32_t ldc, void* D, int32_t ldd) {
   if (!ctx || M < 0 || N < 0 || K < 0 || opA < 0 || opA > 1 || opB < 0 || opB > 1 || (beta != 0 && beta != 1) ||
-      (negate != 0 && negate != 1) || config < 0 || config >= dd_gemm_configs()) {
+      (negate != 0 && negate != 1) || config < 0 || config > dd_gemm_configs() ||
+      (config == dd_gemm_configs() && K > kOzMaxDepth)) {
     set_error("bad arguments to hsc_kern_zgemm_dd");
     return HSC_E_ARG;
   }
@@ -1881,6 +2083,7 @@ hsc_status hsc_kern_zgemm_dd(hsc_ctx* ctx, int32_t config, int32_t opA, int32_t 
   }
   if (M == 0 || N == 0) return HSC_OK;
   HIPCHK(hipSetDevice(ctx->device));
+  if (config == dd_gemm_configs()) return kern_zgemm_oz(ctx, opA, opB, M, N, K, negate, A, lda, B, ldb, beta, C, ldc, D, ldd);
   GemmProbDD p{};
   p.A = (const zdd*)A; p.B = (const zdd*)B; p.C = (const zdd*)C; p.D = (zdd*)D; p.D64 = nullptr;
   p.M = M; p.N = N; p.K = K; p.lda = lda; p.ldb = ldb; p.ldc = ldc; p.ldd = ldd; p.ldd64 = 0;

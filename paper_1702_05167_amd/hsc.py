@@ -140,7 +140,7 @@ class Context:
 
     PROFILE_KINDS = ("assemble", "inv_panel", "inv_swap", "inv_unscramble", "gemm", "gather",
                      "assemble_n", "diag", "guard", "dd_assemble", "dd_inv_panel", "dd_inv_swap",
-                     "dd_inv_unscramble", "dd_gemm", "inv_super")
+                     "dd_inv_unscramble", "dd_gemm", "inv_super", "oz_split", "oz_gemm")
 
     def profile(self, enable: bool):
         check(lib().hsc_ctx_profile(self.h, 1 if enable else 0))
@@ -363,7 +363,8 @@ def kern_zgemm(ctx, opA, opB, alpha, A, B, beta=0, C_=None, D=None, tile=0):
 
 def kern_zgemm_dd(ctx, opA, opB, A, B, negate=0, beta=0, C_=None, D=None, config=0):
     """D = (-1)^negate op(A) op(B) + beta C in complex double-double.  A, B, C, D: device float64
-    tensors of shape (rows, cols, 4) holding (re hi, re lo, im hi, im lo) per element."""
+    tensors of shape (rows, cols, 4) holding (re hi, re lo, im hi, im lo) per element.  config 0-2:
+    tiles of the FP64 vector-unit kernel; 3: 8-bit slices on the integer matrix cores."""
     import torch
     M = A.shape[0] if opA == 0 else A.shape[1]
     K = A.shape[1] if opA == 0 else A.shape[0]

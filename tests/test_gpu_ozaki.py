@@ -1,0 +1,232 @@
+"""Double-double block products from 8-bit slices on the integer matrix cores (precision 3).
+
+Kernel level: hsc_kern_zgemm_dd with config 3 against exact rational arithmetic.  Solve level:
+precision 3 against the oracle (dense LU, the stored sparse-LU rows of the 32^3 cube, the stored
+RGF values of the trilayer) to 1e-10, and against the precision-2 solve.
+"""
+import json
+import os
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+import oracle
+import paper_1702_05167_amd.hsc as H
+
+pytestmark = pytest.mark.gpu
+
+KW = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1)
+ALL = H.HSC_DIAG_GR | H.HSC_DIAG_GL | H.HSC_TRANS | H.HSC_SPECTRAL_LR
+HERE = os.path.dirname(os.path.abspath(__file__))
+OZ = 3          # hsc_kern_zgemm_dd config of the integer matrix cores
+
+
+def _dd_rand(rng, rows, cols, row_scale=None):
+    """(rows, cols, 4) double-double values: hi ~ N(0, 1) (times row_scale[r]), lo a random fraction
+    of half an ulp of hi"""
+    hi = rng.standard_normal((rows, cols, 2))
+    if row_scale is not None:
+        hi *= np.asarray(row_scale)[:, None, None]
+    lo = (rng.random((rows, cols, 2)) - 0.5) * np.spacing(np.abs(hi))
+    out = np.empty((rows, cols, 4))
+    out[..., 0], out[..., 1], out[..., 2], out[..., 3] = hi[..., 0], lo[..., 0], hi[..., 1], lo[..., 1]
+    return out
+
+
+def _ex(x):
+    return F(float(x[0])) + F(float(x[1])), F(float(x[2])) + F(float(x[3]))
+
+
+def _exact_entry(A, B, Cm, i, j, K, opA, opB, negate, beta):
+    re = im = F(0)
+    for k in range(K):
+        ar, ai = _ex(A[i, k] if opA == 0 else A[k, i])
+        br, bi = _ex(B[k, j] if opB == 0 else B[j, k])
+        re += ar * br - ai * bi
+        im += ar * bi + ai * br
+    if negate:
+        re, im = -re, -im
+    if beta:
+        cr, ci = _ex(Cm[i, j])
+        re, im = re + cr, im + ci
+    return re, im
+
+
+def _row_max(X, op, i, K):
+    """max over k of |Re| + |Im| of row i of op(X) (column i of X when op = 1)"""
+    v = X[i, :K] if op == 0 else X[:K, i]
+    return float(np.max(np.abs(v[..., 0]) + np.abs(v[..., 2])))
+
+
+@pytest.mark.parametrize("shape", [(70, 37, 45), (33, 65, 200)], ids=["k45", "k200"])
+@pytest.mark.parametrize("opA,opB,negate,beta", [(0, 0, 0, 0), (1, 0, 1, 1), (0, 1, 0, 1), (1, 1, 0, 0)])
+def test_zgemm_oz_against_exact_arithmetic(ctx, shape, opA, opB, negate, beta):
+    # ragged sizes spanning several 32 x 32 tiles and 64-deep steps; the error bound of the slice
+    # product is relative to the largest entries of the row of op(A) and the column of op(B)
+    M, N, K = shape
+    rng = np.random.default_rng(100 + 10 * opA + 3 * opB + K)
+    A = _dd_rand(rng, *((M, K) if opA == 0 else (K, M)))
+    B = _dd_rand(rng, *((K, N) if opB == 0 else (N, K)))
+    Cm = _dd_rand(rng, M, N)
+    dev = ctx.torch_device
+    D = H.kern_zgemm_dd(ctx, opA, opB, torch.tensor(A, device=dev), torch.tensor(B, device=dev), negate=negate,
+                        beta=beta, C_=torch.tensor(Cm, device=dev) if beta else None, config=OZ).cpu().numpy()
+    assert (np.abs(D[..., 1]) <= 0.5 * np.spacing(np.abs(D[..., 0]))).all()
+    assert (np.abs(D[..., 3]) <= 0.5 * np.spacing(np.abs(D[..., 2]))).all()
+    pairs = {(i, j) for i in (0, 15, 16, 31, 32, M - 1) for j in (0, 31, 32, N - 1)}
+    pairs |= {(int(i), int(j)) for i, j in zip(rng.integers(0, M, 40), rng.integers(0, N, 40))}
+    worst = 0.0
+    for i, j in sorted(pairs):
+        re, im = _exact_entry(A, B, Cm, i, j, K, opA, opB, negate, beta)
+        got = _ex(D[i, j])
+        bound = K * 2.0 ** -104 * _row_max(A, opA, i, K) * _row_max(B, 1 - opB, j, K)
+        if beta:
+            bound += 2.0 ** -102 * (abs(float(_ex(Cm[i, j])[0])) + abs(float(_ex(Cm[i, j])[1])))
+        err = max(abs(float(got[0] - re)), abs(float(got[1] - im)))
+        worst = max(worst, err / bound)
+    print("slice product: worst error / bound", worst)
+    assert worst < 1.0
+
+
+def test_zgemm_oz_wide_dynamic_range(ctx):
+    # rows of A and columns of B scaled over 16 decades, plus single entries far below their
+    # row's largest: the fixed-point slices keep each entry to 2^-112 of its row's maximum
+    M, N, K = 40, 36, 96
+    rng = np.random.default_rng(7)
+    A = _dd_rand(rng, M, K, row_scale=10.0 ** rng.uniform(-8, 8, M))
+    Bt = _dd_rand(rng, N, K, row_scale=10.0 ** rng.uniform(-8, 8, N))    # op(B) = Bt^T (opB = 1)
+    A[3, 5] *= 1e-12
+    Bt[7, 11] *= 1e-9
+    dev = ctx.torch_device
+    D = H.kern_zgemm_dd(ctx, 0, 1, torch.tensor(A, device=dev), torch.tensor(Bt, device=dev), config=OZ)
+    D = D.cpu().numpy()
+    worst = 0.0
+    for i, j in [(3, 7), (0, 0), (M - 1, N - 1)] + [(int(a), int(b)) for a, b in
+                                                    zip(rng.integers(0, M, 25), rng.integers(0, N, 25))]:
+        re, im = _exact_entry(A, Bt, None, i, j, K, 0, 1, 0, 0)
+        got = _ex(D[i, j])
+        bound = K * 2.0 ** -104 * _row_max(A, 0, i, K) * _row_max(Bt, 0, j, K)
+        worst = max(worst, max(abs(float(got[0] - re)), abs(float(got[1] - im))) / bound)
+    print("wide range: worst error / bound", worst)
+    assert worst < 1.0
+
+
+def test_zgemm_oz_empty_depth_and_in_place(ctx):
+    rng = np.random.default_rng(3)
+    dev = ctx.torch_device
+    M, N = 20, 33
+    Cm = torch.tensor(_dd_rand(rng, M, N), device=dev)
+    A = torch.zeros((M, 0, 4), dtype=torch.float64, device=dev)
+    B = torch.zeros((0, N, 4), dtype=torch.float64, device=dev)
+    D = H.kern_zgemm_dd(ctx, 0, 0, A, B, beta=1, C_=Cm, config=OZ)
+    assert torch.equal(D, Cm)
+    # D = C in place: C + A B
+    A = torch.tensor(_dd_rand(rng, M, 70), device=dev)
+    B = torch.tensor(_dd_rand(rng, 70, N), device=dev)
+    ref = H.kern_zgemm_dd(ctx, 0, 0, A, B, beta=1, C_=Cm.clone(), config=1).cpu().numpy()
+    C2 = Cm.clone()
+    H.kern_zgemm_dd(ctx, 0, 0, A, B, beta=1, C_=C2, D=C2, config=OZ)
+    got = C2.cpu().numpy()
+    scale = np.abs(ref[..., 0]).max()
+    assert np.abs((got[..., 0] - ref[..., 0]) + (got[..., 1] - ref[..., 1])).max() <= 1e-28 * 70 * scale
+
+
+def test_zgemm_oz_rejects_deep_products(ctx):
+    dev = ctx.torch_device
+    A = torch.zeros((1, 10881, 4), dtype=torch.float64, device=dev)
+    B = torch.zeros((10881, 1, 4), dtype=torch.float64, device=dev)
+    with pytest.raises(H.HscError) as e:
+        H.kern_zgemm_dd(ctx, 0, 0, A, B, config=OZ)
+    assert e.value.code == -1
+
+
+# ---- solve level ---------------------------------------------------------------------------------
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def t_rel(a, b):
+    return abs(a - b) / max(b, 1e-12)
+
+
+def _solve(ctx, dev, E, leaf, transverse=False, want=ALL, **kw):
+    tree = H.Tree.from_device(dev, leaf_side=leaf, transverse=transverse)
+    out = H.solve(ctx, tree, torch.tensor(np.asarray(E, float), device=ctx.torch_device), want=want, **KW, **kw)
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    if "spectral" in res:
+        res["a_l"], res["a_r"] = res["spectral"][:, 0], res["spectral"][:, 1]
+    return res
+
+
+def _check(g, ref, E, keys=("gr", "gl", "a_l", "a_r"), tol=1e-10):
+    worst = 0.0
+    for e in range(len(E)):
+        for k in keys:
+            err = rel(g[k][e], ref[k][e])
+            worst = max(worst, err)
+            assert err <= tol, (k, E[e], err)
+        if "trans" in ref:
+            err = t_rel(g["trans"][e], ref["trans"][e])
+            worst = max(worst, err)
+            assert err <= tol, ("trans", E[e], err)
+    assert (g["status"] == 0).all(), g["status"]
+    return worst
+
+
+@pytest.mark.parametrize("leaf", [4, 2])
+def test_config0_all_energies_unguarded(ctx, leaf):
+    # 8^3 cube, the 16 energies of [-5, 5], no growth guard: in and out of the lead band
+    dev = synth.config0_device()
+    E = synth.energy_grid(-5.0, 5.0, 16)
+    g = _solve(ctx, dev, E, leaf, precision=3)
+    ref = oracle.dense.solve(dev, E, **KW)
+    print("8^3 precision 3 worst", _check(g, ref, E))
+    g2 = _solve(ctx, dev, E, leaf, precision=2)
+    for k in ("gr", "gl", "a_l", "a_r"):
+        assert max(rel(g[k][e], g2[k][e]) for e in range(len(E))) <= 1e-11, k
+
+
+@pytest.mark.parametrize("transverse,leaf", [(True, 4), (False, 8)])
+def test_cube16_out_of_band(ctx, transverse, leaf):
+    dev = synth.config1_device(n_side=16)
+    E = np.linspace(-6.0, 6.0, 48)
+    E = E[np.abs(E) > 2.0][::2]
+    g = _solve(ctx, dev, E, leaf, transverse=transverse, precision=3)
+    print("16^3 out of band, precision 3 worst", _check(g, oracle.dense.solve(dev, E, **KW), E))
+
+
+@pytest.mark.parametrize("precision", [2, 3])
+def test_cube32_golden_benchmark_configuration(ctx, precision):
+    # the throughput benchmark's configuration (3D nested dissection, leaves <= 8, batches of 16,
+    # tuned tiles) at all eight stored energies of the 256-point grid, three in the lead band
+    gold = json.load(open(os.path.join(HERE, "golden", "cube32_sampled.json")))
+    E, sites = np.array(gold["energies"]), np.array(gold["sites"])
+    ref = {"gr": np.array(gold["gr_re"]) + 1j * np.array(gold["gr_im"]),
+           "gl": np.array(gold["gl_re"]) + 1j * np.array(gold["gl_im"]),
+           "a_l": np.array(gold["a_l"]), "a_r": np.array(gold["a_r"]), "trans": np.array(gold["trans"])}
+    Ep = np.concatenate([E, E])        # one batch of 16
+    g = _solve(ctx, synth.config1_device(), Ep, 8, precision=precision, tune=1, batch=16)
+    gs = {k: g[k][:8, sites] for k in ("gr", "gl", "a_l", "a_r")}
+    gs["trans"], gs["status"] = g["trans"][:8], g["status"][:8]
+    for e in range(len(E)):
+        print("32^3 golden E", E[e], [rel(gs[k][e], ref[k][e]) for k in ("gr", "gl", "a_l", "a_r")],
+              t_rel(gs["trans"][e], ref["trans"][e]))
+    print("worst", _check(gs, ref, E))
+    for k in ("gr", "gl", "trans"):          # both halves of the batch solve the same energies
+        assert np.array_equal(g[k][:8], g[k][8:]), k
+
+
+def test_trilayer_golden(ctx):
+    gold = json.load(open(os.path.join(HERE, "golden", "trilayer_rgf.json")))
+    E, sites = np.array(gold["energies"]), np.array(gold["sites"])
+    ref = {"gr": np.array(gold["gr_re"]) + 1j * np.array(gold["gr_im"]),
+           "gl": np.array(gold["gl_re"]) + 1j * np.array(gold["gl_im"]),
+           "a_l": np.array(gold["a_l"]), "a_r": np.array(gold["a_r"]), "trans": np.array(gold["trans"])}
+    g = _solve(ctx, synth.trilayer(), E, 8, precision=3)
+    gs = {k: g[k][:, sites] for k in ("gr", "gl", "a_l", "a_r")}
+    gs["trans"], gs["status"] = g["trans"], g["status"]
+    print("trilayer precision 3 worst", _check(gs, ref, E))
