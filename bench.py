@@ -39,6 +39,11 @@ FP64_VALU_PEAK_TOPS = 39.3
 # 8 M N K complex count
 DD_OPS_PER_CMAC = 36
 DD_OPS_PER_CFLOP = DD_OPS_PER_CMAC / 8
+# dense int8 matrix-core peak of the chip (5.0 P int8 ops/s) and the int8 operations of one complex
+# double-double multiply-add in k_oz_gemm: 3 real products (Gauss) x 136 slice pairs x 2
+INT8_MFMA_PEAK_TOPS = 5000.0
+OZ_INT8_OPS_PER_CMAC = 3 * 136 * 2
+OZ_INT8_OPS_PER_CFLOP = OZ_INT8_OPS_PER_CMAC / 8
 
 
 def note(msg):
@@ -78,7 +83,21 @@ def roofline_of(prof, precision):
     (HIP events on the solver's stream): achieved = sum of 8 M N K over its launches / sum of
     their durations, against the FP64 matrix-core peak."""
     total_ms = sum(v["ms"] for v in prof.values())
-    g, gd = prof["gemm"], prof["dd_gemm"]
+    g, gd, go = prof["gemm"], prof["dd_gemm"], prof["oz_gemm"]
+    if go["ms"] > max(gd["ms"], g["ms"]):
+        ach = go["flops"] / (go["ms"] * 1e-3) / 1e12
+        i8 = ach * OZ_INT8_OPS_PER_CFLOP
+        return {"bound": "mfma", "kernel": "k_oz_gemm (complex double-double products from 8-bit slices, "
+                                           "integer matrix cores)",
+                "achieved": ach, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_MFMA_PEAK_TFLOPS,
+                "traffic": None, "flop_count": "8 M N K per complex product (algorithmic)",
+                "launches": int(go["launches"]), "avg_launch_ms": go["ms"] / go["launches"],
+                "flops_per_launch": go["flops"] / go["launches"],
+                "share_of_kernel_time": go["ms"] / total_ms,
+                "int8_matrix_cores": {"achieved": i8, "peak": INT8_MFMA_PEAK_TOPS, "unit": "T int8 ops/s",
+                                      "frac": i8 / INT8_MFMA_PEAK_TOPS,
+                                      "int8_ops_per_complex_multiply_add": OZ_INT8_OPS_PER_CMAC,
+                                      "note": "unpadded M N K; padding to 32 x 32 x 64 tiles not counted"}}
     if precision >= 1 and gd["ms"] > 0:
         ach = gd["flops"] / (gd["ms"] * 1e-3) / 1e12
         issue = DD_OPS_PER_CFLOP * ach
@@ -307,7 +326,9 @@ def main():
                "cpu_model": cpu_model(), "host_cpus": os.cpu_count(), "single_thread": single}
 
     prec_name = {0: "complex128", 1: "double-double fold, complex128 extraction",
-                 2: "double-double fold and extraction"}[args.precision]
+                 2: "double-double fold and extraction",
+                 3: "double-double fold and extraction, products of depth >= 32 from 8-bit slices on the "
+                    "integer matrix cores"}[args.precision]
     line = {
         "metric": "energies/s (diag G^r,G^<), 32^3 cube, batched vs plain; % FP64 MFMA peak",
         "value": value,

@@ -190,17 +190,17 @@ int dd_inv_nb(int max_n);
 // largest entry
 constexpr int kOzSlices = 16;
 // One operand to split: element (r, k) = X[r * ldr + k * ldk] for r < R, k < K (complex
-// double-double); out = planes [3][kOzSlices][Rp][Kp] int8 (Re, Im, Re + Im), ex = [Rp] row
-// exponents; Rp a multiple of 32 (>= R), Kp of 64 (>= K); zero padding.  Workgroups
-// [blk_off, blk_off + Rp / 64 rounded up) of a split launch belong to this job.
+// double-double); out = 3 x kOzSlices planes (Re, Im, Re + Im) of Rp x Kp int8 in 1 KB fragments of
+// 16 rows x 64 k (matrix-core operand order), ex = [Rp] row exponents; Rp a multiple of 32 (>= R),
+// Kp of 64 (>= K); zero padding.  Row-scale workgroups [blk_off, blk_off + ceil(Rp / 64)) and digit
+// workgroups [tile_off, tile_off + ceil(Rp / 64) * Kp / 32) of a split launch belong to this job.
 struct OzSplitJob {
   const zdd* X;
   int64_t ldr, ldk;
   int32_t R, K, Rp, Kp;
   int8_t* out;
   int32_t* ex;
-  int32_t blk_off;
-  int32_t pad;
+  int32_t blk_off, tile_off;
 };
 // One product D = (-1)^negate A' B' + beta C from split operands (A8: rows of A', B8: columns of
 // B'); 32 x 32 output tiles.
@@ -216,7 +216,8 @@ struct GemmProbOZ {
   int32_t ldc, ldd, ldd64;
   int32_t tiles_n, tile_off;
 };
-void launch_oz_split(hipStream_t st, const OzSplitJob* jobs, const int32_t* blk_job, int total_blocks, int kfast);
+void launch_oz_split(hipStream_t st, const OzSplitJob* jobs, const int32_t* blk_job, int total_blocks,
+                     const int32_t* tile_job, int total_tiles);
 void launch_oz_gemm(hipStream_t st, const GemmProbOZ* probs, const int32_t* tile_prob, int total_tiles, int negate,
                     int beta);
 

@@ -28,12 +28,13 @@
 // bound is relative to the largest entries of the row and column, not to
 // sum_k |a_ik| |b_kj|.
 //
-// Layout: the slices of one operand are planes [3][S][Rp][Kp] of int8 (operand
-// part 0 = Re, 1 = Im, 2 = Re + Im; rows padded to the 32-row tile, K padded to
-// 64 with zeros), row scales int32 [Rp].  The GEMM kernel stages the slices of
-// a 32 x 32 output tile through LDS with direct global-to-LDS loads laid out in
-// the matrix-core operand order, and each of its four waves holds the 3 x S
-// integer accumulators of one 16 x 16 block.
+// Layout: the slices of one operand are 3 x S planes of int8 (operand part
+// 0 = Re, 1 = Im, 2 = Re + Im; rows padded to the 32-row tile, K padded to 64
+// with zeros), each stored as 1 KB fragments of 16 rows x 64 k in the order in
+// which the matrix cores take an operand; row scales int32 [Rp].  The GEMM
+// kernel stages the fragments of a 32 x 32 output tile into LDS with direct
+// global-to-LDS loads (one contiguous kilobyte per wave instruction), and each
+// of its four waves holds the 3 x S integer accumulators of one 16 x 16 block.
 #include <hip/hip_runtime.h>
 
 #include "dd.h"
@@ -49,7 +50,8 @@ constexpr int OZ_TILE = 32;   // rows and columns of the output tile of one work
 constexpr int OZ_KC = 64;     // k depth of one matrix-core step (v_mfma_i32_16x16x64_i8)
 
 // ---------------------------------------------------------------------------------------------
-// splitting: rows [r0, r0 + 64) of one operand per workgroup
+// splitting, in two launches: row scales (64 rows per workgroup), then digits (tiles of 64 rows x
+// 32 k per workgroup, written through LDS in the operand order of the matrix cores)
 
 // element (r, k) of the operand as stored: X[r * ldr + k * ldk]; zero outside R x K
 __device__ inline zdd oz_elem(const OzSplitJob& jb, int r, int k) {
@@ -57,85 +59,124 @@ __device__ inline zdd oz_elem(const OzSplitJob& jb, int r, int k) {
   return jb.X[(int64_t)r * jb.ldr + (int64_t)k * jb.ldk];
 }
 
-// digits of x (|x| < 2^6 after scaling, x exact as a double-double) into d[0..S)
+__device__ inline double oz_mag(const zdd& v) {
+  return (fabs(v.re.hi) + fabs(v.re.lo)) + (fabs(v.im.hi) + fabs(v.im.lo));
+}
+
+// ex[r] = e with max_k (|Re| + |Im|) of row r < 2^e (0 for a zero row)
+__global__ __launch_bounds__(256) void k_oz_scale(const OzSplitJob* __restrict__ jobs,
+                                                  const int32_t* __restrict__ blk_job) {
+  const OzSplitJob& jb = jobs[blk_job[blockIdx.x]];
+  const int r0 = (blockIdx.x - jb.blk_off) * 64;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  __shared__ double red[4][64];
+  if (jb.ldk == 1) {
+    // k contiguous: one wave per row, lanes along k
+    for (int rr = w; rr < 64; rr += 4) {
+      double m = 0.0;
+      for (int k = lane; k < jb.K; k += 64) m = fmax(m, oz_mag(oz_elem(jb, r0 + rr, k)));
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+      if (lane == 0) red[0][rr] = m;
+    }
+    __syncthreads();
+    if (t < 64) {
+      int e = 0;
+      const double mx = red[0][t];
+      if (mx > 0.0 && isfinite(mx)) (void)frexp(mx, &e);
+      if (r0 + t < jb.Rp) jb.ex[r0 + t] = e;
+    }
+  } else {
+    // rows contiguous (or general strides): lanes along rows, four k phases
+    double m = 0.0;
+    for (int k = w; k < jb.K; k += 4) m = fmax(m, oz_mag(oz_elem(jb, r0 + lane, k)));
+    red[w][lane] = m;
+    __syncthreads();
+    if (t < 64) {
+      int e = 0;
+      const double mx = fmax(fmax(red[0][t], red[1][t]), fmax(red[2][t], red[3][t]));
+      if (mx > 0.0 && isfinite(mx)) (void)frexp(mx, &e);
+      if (r0 + t < jb.Rp) jb.ex[r0 + t] = e;
+    }
+  }
+}
+
+// S digits of y (a double-double with |y.lo| <= ulp(y.hi) / 2 and |y| < 2^6 + 2^-40):
+// d_s = rint of the current leading part, the remainder (exact: y.hi - d_s is a multiple of
+// ulp(y.hi), so at least twice |y.lo| unless zero) times 2^7 gives the next; every d_s lies in
+// [-64, 64].  Digit s goes to byte `shift` of word[s].
 template <int S>
-__device__ inline void oz_digits(dd y, int* d) {
+__device__ inline void oz_digits(dd y, uint32_t* word, int shift) {
 #pragma clang fp contract(off)
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const double q = rint(y.hi);
-    d[s] = (int)q;
-    const dd r = two_sum(y.hi - q, y.lo);   // y.hi - q is exact (|y.hi - q| <= 1/2)
-    y = dd{r.hi * 128.0, r.lo * 128.0};
+    word[s] |= (uint32_t)((int)q & 0xff) << shift;
+    const double t = y.hi - q;
+    const double hi = t + y.lo;
+    const double lo = y.lo - (hi - t);
+    y = dd{hi * 128.0, lo * 128.0};
   }
 }
 
-template <int S, bool KFAST>
-__global__ __launch_bounds__(256) void k_oz_split(const OzSplitJob* __restrict__ jobs,
-                                                  const int32_t* __restrict__ blk_job) {
-  const OzSplitJob& jb = jobs[blk_job[blockIdx.x]];
-  const int r0 = (blockIdx.x - jb.blk_off) * 64;
+// Tile (64 rows from r0, 32 k from k0) of one job: each thread splits two quads of four
+// consecutive k, packs each quad's digits into one word per (part, slice), and the words go to
+// LDS in the order of the global planes, which the block then writes out 16 bytes per thread.
+// Global layout of a part / slice plane: fragments of 16 rows x 64 k (1 KB), row blocks of the
+// plane in order, each row block's 64-k steps in order; inside a fragment, byte 16 l + b holds
+// row l & 15, k = 16 (l >> 4) + b (the operand order of v_mfma_i32_16x16x64_i8).
+template <int S>
+__global__ __launch_bounds__(256) void k_oz_digits(const OzSplitJob* __restrict__ jobs,
+                                                   const int32_t* __restrict__ tile_job) {
+  // [part][slice][row block of 16][lane 0..31 of the half fragment][4 words]
+  __shared__ uint32_t lw[3 * S * 4 * 32 * 4];
+  const OzSplitJob& jb = jobs[tile_job[blockIdx.x]];
+  const int local = blockIdx.x - jb.tile_off;
+  const int nk = jb.Kp / 32;
+  const int r0 = (local / nk) * 64, k0 = (local % nk) * 32;
   const int t = threadIdx.x;
-  __shared__ double red[4][64];
-  __shared__ int ex[64];
-  // pass 1: row scales (max over k of |Re| + |Im|, hi and lo parts)
-  {
-    const int rr = t & 63, kq = t >> 6;
-    double m = 0.0;
-    for (int k = kq; k < jb.K; k += 4) {
-      const zdd v = oz_elem(jb, r0 + rr, k);
-      m = fmax(m, (fabs(v.re.hi) + fabs(v.re.lo)) + (fabs(v.im.hi) + fabs(v.im.lo)));
-    }
-    red[kq][rr] = m;
-    __syncthreads();
-    if (t < 64) {
-      const double mx = fmax(fmax(red[0][t], red[1][t]), fmax(red[2][t], red[3][t]));
-      int e = 0;
-      if (mx > 0.0 && isfinite(mx)) (void)frexp(mx, &e);   // mx < 2^e
-      ex[t] = e;
-      if (r0 + t < jb.Rp) jb.ex[r0 + t] = e;
-    }
-    __syncthreads();
-  }
-  // pass 2: digits, four consecutive k per thread, packed into one int32 per (part, slice)
-  const int nq = jb.Kp / 4;
-  const int64_t plane = (int64_t)jb.Rp * jb.Kp;
-  for (int q = t; q < 64 * nq; q += 256) {
-    const int rr = KFAST ? q / nq : q % 64;
-    const int kq = KFAST ? q % nq : q / 64;
+  const bool kfast = jb.ldk == 1;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    // this thread's quad: row rr, k = 4 kq .. 4 kq + 3 (kq < 8)
+    const int rr = kfast ? (t >> 3) + 32 * j : (t & 63);
+    const int kq = kfast ? (t & 7) : (t >> 6) + 4 * j;
     const int r = r0 + rr;
-    if (r >= jb.Rp) continue;
-    const int e = ex[rr];
-    uint32_t packed[3][S];
+    uint32_t wd[3][S];
 #pragma unroll
     for (int p = 0; p < 3; ++p)
 #pragma unroll
-      for (int s = 0; s < S; ++s) packed[p][s] = 0;
+      for (int q = 0; q < S; ++q) wd[p][q] = 0;
+    const int e = r < jb.Rp ? jb.ex[r] : 0;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const zdd v = oz_elem(jb, r, 4 * kq + u);
-      // scale by 2^(6 - e): exact
-      const int sh = 6 - e;
-      const dd xr{ldexp(v.re.hi, sh), ldexp(v.re.lo, sh)};
-      const dd xi{ldexp(v.im.hi, sh), ldexp(v.im.lo, sh)};
-      const dd xs = dd_add(xr, xi);
-      int d[S];
-      oz_digits<S>(xr, d);
-#pragma unroll
-      for (int s = 0; s < S; ++s) packed[0][s] |= (uint32_t)(d[s] & 0xff) << (8 * u);
-      oz_digits<S>(xi, d);
-#pragma unroll
-      for (int s = 0; s < S; ++s) packed[1][s] |= (uint32_t)(d[s] & 0xff) << (8 * u);
-      oz_digits<S>(xs, d);
-#pragma unroll
-      for (int s = 0; s < S; ++s) packed[2][s] |= (uint32_t)(d[s] & 0xff) << (8 * u);
+      const zdd v = oz_elem(jb, r, k0 + 4 * kq + u);
+      const int sh = 6 - e;   // scale by 2^(6 - e): exact
+      const dd nr = two_sum(v.re.hi, v.re.lo), ni = two_sum(v.im.hi, v.im.lo);
+      const dd xr{ldexp(nr.hi, sh), ldexp(nr.lo, sh)};
+      const dd xi{ldexp(ni.hi, sh), ldexp(ni.lo, sh)};
+      oz_digits<S>(xr, wd[0], 8 * u);
+      oz_digits<S>(xi, wd[1], 8 * u);
+      oz_digits<S>(dd_add(xr, xi), wd[2], 8 * u);
     }
-    uint32_t* out = reinterpret_cast<uint32_t*>(jb.out);
+    // word (k % 16) / 4 of half-fragment lane (row & 15) + 16 ((k % 32) / 16), row block row / 16
+    const int kk = 4 * kq;
+    const int l = (rr & 15) + 16 * (kk >> 4), wq = (kk & 15) >> 2, rb = rr >> 4;
 #pragma unroll
     for (int p = 0; p < 3; ++p)
 #pragma unroll
-      for (int s = 0; s < S; ++s)
-        out[((p * S + s) * plane + (int64_t)r * jb.Kp) / 4 + kq] = packed[p][s];
+      for (int q = 0; q < S; ++q) lw[((((p * S + q) * 4 + rb) * 32 + l) * 4) + wq] = wd[p][q];
+  }
+  __syncthreads();
+  // write out: 16 bytes per (part, slice, row block, half-fragment lane)
+  const int rbs = jb.Rp / 16, kcs = jb.Kp / 64, half = (k0 >> 5) & 1, kc = k0 >> 6;
+  const uint4* src = reinterpret_cast<const uint4*>(lw);
+  for (int c = t; c < 3 * S * 4 * 32; c += 256) {
+    const int l = c & 31, rb = (c >> 5) & 3, ps = c >> 7;   // ps = part * S + slice
+    const int rbg = r0 / 16 + rb;
+    if (rbg >= rbs) continue;
+    uint4* dst = reinterpret_cast<uint4*>(jb.out + (((int64_t)ps * rbs + rbg) * kcs + kc) * 1024) + 32 * half + l;
+    *dst = src[c];
   }
 }
 
@@ -150,17 +191,17 @@ typedef __attribute__((address_space(3))) void* lds_ptr;
 // v_mfma_i32_16x16x64_i8 takes its operands (lane l: row l & 15, k group l >> 4)
 template <int S>
 __device__ inline void oz_stage(const GemmProbOZ& pr, v4i* buf, int m0, int n0, int p, int kc, int w, int lane) {
-  const int64_t planeA = (int64_t)pr.Mp * pr.Kp, planeB = (int64_t)pr.Np * pr.Kp;
-  const int64_t koff = (int64_t)kc * OZ_KC + 16 * (lane >> 4);
+  const int kcs = pr.Kp / OZ_KC;
+  const int rbsA = pr.Mp / 16, rbsB = pr.Np / 16;
 #pragma unroll
   for (int q = 0; q < S; ++q) {
     const int f = w * S + q;           // fragment index, 4 S per stage, S per wave
     const int g = f / S, s = f % S;
     const int8_t* src;
     if (g < 2)
-      src = pr.A8 + (p * S + s) * planeA + (int64_t)(m0 + 16 * g + (lane & 15)) * pr.Kp + koff;
+      src = pr.A8 + (((int64_t)(p * S + s) * rbsA + m0 / 16 + g) * kcs + kc) * 1024 + 16 * lane;
     else
-      src = pr.B8 + (p * S + s) * planeB + (int64_t)(n0 + 16 * (g - 2) + (lane & 15)) * pr.Kp + koff;
+      src = pr.B8 + (((int64_t)(p * S + s) * rbsB + n0 / 16 + (g - 2)) * kcs + kc) * 1024 + 16 * lane;
     __builtin_amdgcn_global_load_lds(src, (lds_ptr)(buf + (size_t)f * 64), 16, 0, 0);
   }
 }
@@ -249,12 +290,12 @@ __global__ __launch_bounds__(256) void k_oz_gemm(const GemmProbOZ* __restrict__ 
 
 }  // namespace
 
-void launch_oz_split(hipStream_t st, const OzSplitJob* jobs, const int32_t* blk_job, int total_blocks, int kfast) {
+void launch_oz_split(hipStream_t st, const OzSplitJob* jobs, const int32_t* blk_job, int total_blocks,
+                     const int32_t* tile_job, int total_tiles) {
   if (total_blocks <= 0) return;
-  if (kfast)
-    hipLaunchKernelGGL((k_oz_split<kOzSlices, true>), dim3(total_blocks), dim3(256), 0, st, jobs, blk_job);
-  else
-    hipLaunchKernelGGL((k_oz_split<kOzSlices, false>), dim3(total_blocks), dim3(256), 0, st, jobs, blk_job);
+  hipLaunchKernelGGL(k_oz_scale, dim3(total_blocks), dim3(256), 0, st, jobs, blk_job);
+  if (total_tiles > 0)   // none when K = 0
+    hipLaunchKernelGGL((k_oz_digits<kOzSlices>), dim3(total_tiles), dim3(256), 0, st, jobs, tile_job);
 }
 
 void launch_oz_gemm(hipStream_t st, const GemmProbOZ* probs, const int32_t* tile_prob, int total_tiles, int negate,

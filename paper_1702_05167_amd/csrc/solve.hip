@@ -530,8 +530,8 @@ struct Builder {
   void oz_gemm(int opA, int opB, const std::vector<GPD>& ps, int negate, int beta) {
     size_t i0 = 0;
     while (i0 < ps.size()) {
-      std::vector<OzSplitJob> sj[2];
-      std::vector<int32_t> bj[2];
+      std::vector<OzSplitJob> sj;
+      std::vector<int32_t> bmap, tmap_s;
       std::vector<GemmProbOZ> gp;
       std::vector<int32_t> tmap;
       std::map<std::tuple<const void*, int64_t, int64_t, int, int>, std::pair<size_t, size_t>> seen;
@@ -548,10 +548,12 @@ struct Builder {
         j.X = X; j.ldr = ldr; j.ldk = ldk; j.R = R; j.K = K; j.Rp = Rp; j.Kp = Kp;
         j.out = reinterpret_cast<int8_t*>(off);
         j.ex = reinterpret_cast<int32_t*>(off + (size_t)3 * kOzSlices * Rp * Kp);
-        const int kf = ldk == 1 ? 1 : 0;
-        j.blk_off = (int32_t)bj[kf].size();
-        for (int b = 0; b < (Rp + 63) / 64; ++b) bj[kf].push_back((int32_t)sj[kf].size());
-        sj[kf].push_back(j);
+        const int rblocks = (Rp + 63) / 64;
+        j.blk_off = (int32_t)bmap.size();
+        for (int b = 0; b < rblocks; ++b) bmap.push_back((int32_t)sj.size());
+        j.tile_off = (int32_t)tmap_s.size();
+        for (int b = 0; b < rblocks * (Kp / 32); ++b) tmap_s.push_back((int32_t)sj.size());
+        sj.push_back(j);
         const auto r = std::make_pair(off, off + (size_t)3 * kOzSlices * Rp * Kp);
         seen[key] = r;
         return r;
@@ -580,18 +582,18 @@ struct Builder {
         flops += 8.0 * g.M * g.N * g.K;
       }
       oz_need = std::max(oz_need, cur);
-      for (int kf = 0; kf < 2; ++kf) {
-        if (sj[kf].empty()) continue;
+      if (!sj.empty()) {
         Step s;
         s.kind = S_OZ_SPLIT;
-        s.jobs = blob.push(sj[kf]);
-        for (size_t q = 0; q < sj[kf].size(); ++q) {
+        s.jobs = blob.push(sj);
+        for (size_t q = 0; q < sj.size(); ++q) {
           blob.sc_relocs.push_back(s.jobs + q * sizeof(OzSplitJob) + offsetof(OzSplitJob, out));
           blob.sc_relocs.push_back(s.jobs + q * sizeof(OzSplitJob) + offsetof(OzSplitJob, ex));
         }
-        s.map = blob.push(bj[kf]);
-        s.count = (int)bj[kf].size();
-        s.i0 = kf;
+        s.map = blob.push(bmap);
+        s.count = (int)bmap.size();
+        s.map_k[0] = blob.push(tmap_s);
+        s.count_k[0] = (int)tmap_s.size();
         push(s);
       }
       if (!gp.empty()) {
@@ -1224,7 +1226,8 @@ int run_steps(hsc_ctx* ctx, hipStream_t st, Plan* pl, int e_base, int nvalid, vo
                        reinterpret_cast<const int32_t*>(pl->blob + s.map_k[s.tile]), s.count_k[s.tile], s.i1, s.beta);
         break;
       case S_OZ_SPLIT:
-        launch_oz_split(st, (const OzSplitJob*)jobs, map, s.count, s.i0);
+        launch_oz_split(st, (const OzSplitJob*)jobs, map, s.count,
+                        reinterpret_cast<const int32_t*>(pl->blob + s.map_k[0]), s.count_k[0]);
         break;
       case S_OZ_GEMM:
         launch_oz_gemm(st, (const GemmProbOZ*)jobs, map, s.count, s.i1, s.beta);
@@ -1972,35 +1975,43 @@ hsc_status kern_zgemm_oz(hsc_ctx* ctx, int opA, int opB, int M, int N, int K, in
   const int Mp = (int)oz_pad(M, 32), Np = (int)oz_pad(N, 32), Kp = (int)oz_pad(K, 64);
   const size_t sa = (size_t)3 * kOzSlices * Mp * Kp, sb = (size_t)3 * kOzSlices * Np * Kp;
   const int ba = (Mp + 63) / 64, bb = (Np + 63) / 64;
+  const int ta = ba * (Kp / 32), tb = bb * (Kp / 32);
   const int tiles = (Mp / 32) * (Np / 32);
-  // layout: [jobs: A split, B split, product][maps: A blocks, B blocks, tiles][A8][B8][ea][eb]
-  const size_t o_map = 1024, o_a8 = oz_pad(o_map + 4 * (size_t)(ba + bb + tiles), 256);
+  // layout: [jobs: A, B split; product][maps: scale blocks, digit tiles, product tiles][A8][B8][ea][eb]
+  const size_t nmap = (size_t)(ba + bb) + (size_t)(ta + tb) + (size_t)tiles;
+  const size_t o_map = 1024, o_a8 = oz_pad(o_map + 4 * nmap, 256);
   const size_t o_b8 = oz_pad(o_a8 + sa, 256), o_ea = oz_pad(o_b8 + sb, 256), o_eb = oz_pad(o_ea + 4 * (size_t)Mp, 256);
   const size_t bytes = o_eb + 4 * (size_t)Np;
   char* dev = nullptr;
   if (hipMalloc(&dev, bytes) != hipSuccess) { (void)hipGetLastError(); set_error("alloc failed"); return HSC_E_OOM; }
-  OzSplitJob ja{}, jb{};
+  OzSplitJob job[2] = {};
+  OzSplitJob& ja = job[0];
+  OzSplitJob& jb = job[1];
   ja.X = (const zdd*)A; ja.R = M; ja.K = K; ja.Rp = Mp; ja.Kp = Kp;
   if (opA == 0) { ja.ldr = lda; ja.ldk = 1; } else { ja.ldr = 1; ja.ldk = lda; }
   ja.out = (int8_t*)(dev + o_a8); ja.ex = (int32_t*)(dev + o_ea);
+  ja.blk_off = 0; ja.tile_off = 0;
   jb.X = (const zdd*)B; jb.R = N; jb.K = K; jb.Rp = Np; jb.Kp = Kp;
   if (opB == 0) { jb.ldr = 1; jb.ldk = ldb; } else { jb.ldr = ldb; jb.ldk = 1; }
   jb.out = (int8_t*)(dev + o_b8); jb.ex = (int32_t*)(dev + o_eb);
+  jb.blk_off = ba; jb.tile_off = ta;
   GemmProbOZ p{};
   p.A8 = ja.out; p.B8 = jb.out; p.ea = ja.ex; p.eb = jb.ex;
   p.C = (const zdd*)C; p.D = (zdd*)D; p.D64 = nullptr;
   p.M = M; p.N = N; p.Mp = Mp; p.Np = Np; p.Kp = Kp; p.ldc = ldc; p.ldd = ldd; p.ldd64 = 0;
   p.tiles_n = Np / 32; p.tile_off = 0;
-  std::vector<char> host(1024 + 4 * (size_t)(ba + bb + tiles), 0);
-  std::memcpy(host.data(), &ja, sizeof(ja));
-  std::memcpy(host.data() + 256, &jb, sizeof(jb));
-  std::memcpy(host.data() + 512, &p, sizeof(p));   // every map entry is 0 (one job / problem)
+  std::vector<char> host(o_map + 4 * nmap, 0);
+  std::memcpy(host.data(), job, sizeof(job));
+  std::memcpy(host.data() + 512, &p, sizeof(p));
+  int32_t* m = reinterpret_cast<int32_t*>(host.data() + o_map);
+  for (int b = 0; b < ba + bb; ++b) m[b] = b < ba ? 0 : 1;                        // scale blocks
+  for (int b = 0; b < ta + tb; ++b) m[ba + bb + b] = b < ta ? 0 : 1;              // digit tiles
+  // product tiles: all 0 (one problem)
   hipError_t e = hipMemcpy(dev, host.data(), host.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) {
-    const int32_t* m = (const int32_t*)(dev + o_map);
-    launch_oz_split(ctx->stream, (const OzSplitJob*)dev, m, ba, ja.ldk == 1 ? 1 : 0);
-    launch_oz_split(ctx->stream, (const OzSplitJob*)(dev + 256), m + ba, bb, jb.ldk == 1 ? 1 : 0);
-    launch_oz_gemm(ctx->stream, (const GemmProbOZ*)(dev + 512), m + ba + bb, tiles, negate, beta);
+    const int32_t* dm = (const int32_t*)(dev + o_map);
+    launch_oz_split(ctx->stream, (const OzSplitJob*)dev, dm, ba + bb, dm + ba + bb, ta + tb);
+    launch_oz_gemm(ctx->stream, (const GemmProbOZ*)(dev + 512), dm + ba + bb + ta + tb, tiles, negate, beta);
     e = hipGetLastError();
     if (e == hipSuccess) e = ctx->stream ? hipStreamSynchronize(ctx->stream) : hipDeviceSynchronize();
   }
