@@ -261,7 +261,8 @@ hsc_status hsc_totals(hsc_ctx* ctx, int32_t n_e, int64_t n, const void* diag_gr,
  * 5 gather, 6 N assembly, 7 diagonal output, 8 growth indicators, 9-13 the
  * double-double assemble / panel / swap / unscramble / GEMM, 14 inverse
  * super-panel preparation, 15 operand splitting into 8-bit slices, 16 slice
- * products on the integer matrix cores (precision 3).
+ * products on the integer matrix cores (precision 3), 17 double-double inverse
+ * super-panel preparation.
  * hsc_ctx_profile_read writes out[3*k + {0,1,2}] = launches, milliseconds,
  * algorithmic real flops (GEMM: 8 M N K per problem) for k < n_kinds.
  * Errors: HSC_E_ARG. */

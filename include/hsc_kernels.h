@@ -62,13 +62,18 @@ hsc_status hsc_kern_zgemm_dd(hsc_ctx* ctx, int32_t config, int32_t opA, int32_t 
                              int32_t beta, const void* C, int32_t ldc, void* D, int32_t ldd);
 
 /* The pivot-block inverse of the double-double fold (hsc_solve_opts.precision
- * >= 1, Algorithm 1's A_ii^-1) on its own: blocked Gauss-Jordan with partial
- * pivoting inside the block, in complex double-double.  X (order n, leading
- * dimension ld, 32-byte elements as in hsc_kern_zgemm_dd; device) is
- * overwritten; Y (ldy) receives X^-1.  status (device int32, may be NULL)
- * receives 0 or HSC_E_SINGULAR.  1 <= n <= 4096.  Synchronous.
+ * >= 1, Algorithm 1's A_ii^-1) on its own, with the solver's own launch
+ * sequence: two-level blocked Gauss-Jordan with partial pivoting inside the
+ * block, in complex double-double (panels of 8, 4 or 2 columns inside
+ * super-panels of 64; each super-panel's pivot rows update the other columns in
+ * one rank-64 product, on the integer matrix cores when matrix_cores = 1 as with
+ * precision 3, else on the vector units).  X (order n, leading dimension ld,
+ * 32-byte elements as in hsc_kern_zgemm_dd; device) is overwritten; Y (ldy)
+ * receives X^-1.  status (device int32, may be NULL) receives 0 or
+ * HSC_E_SINGULAR.  1 <= n <= 4096.  Synchronous.
  * Errors: HSC_E_ARG, HSC_E_OOM, HSC_E_HIP. */
-hsc_status hsc_kern_zinv_dd(hsc_ctx* ctx, int32_t n, void* X, int32_t ld, void* Y, int32_t ldy, int32_t* status);
+hsc_status hsc_kern_zinv_dd(hsc_ctx* ctx, int32_t n, void* X, int32_t ld, void* Y, int32_t ldy, int32_t* status,
+                            int32_t matrix_cores);
 
 /* Invert `count` matrices of order n[k] in place (X[k], leading dimension ld[k])
  * and write X[k]^-1 into Y[k] (leading dimension ldy[k]); all pointer/size

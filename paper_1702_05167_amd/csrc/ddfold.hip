@@ -210,6 +210,36 @@ __global__ __launch_bounds__(256) void k_dd_inv_swap(const InvJobDD* __restrict_
     jb.R[(int64_t)j * n + col] = in_panel ? zdd_zero() : jb.X[(int64_t)(k0 + j) * jb.ld + col];
 }
 
+// After the panels of a super-panel [s0, s0 + ws) (two-level Gauss-Jordan, as inverse.hip):
+//   U[r][c] = X[r][s0 + c] - (r == s0 + c)   (n x ws, row stride W; the T workspace)
+//   R[c][j] = X[s0 + c][j]                     (ws x n; the R workspace)
+__global__ __launch_bounds__(64) void k_dd_inv_super_u(const InvJobDD* __restrict__ jobs, int s0, int W, int chunks) {
+  const InvJobDD jb = jobs[blockIdx.x / chunks];
+  const int n = jb.n;
+  if (s0 >= n) return;
+  const int ws = min(W, n - s0);
+  const int c = threadIdx.x;
+  const int r0 = (blockIdx.x % chunks) * 16;
+  if (c >= ws) return;
+  for (int r = r0; r < min(n, r0 + 16); ++r) {
+    zdd v = jb.X[(int64_t)r * jb.ld + s0 + c];
+    if (r == s0 + c) v.re = dd_add(v.re, dd_from(-1.0));
+    jb.T[(int64_t)r * W + c] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_dd_inv_super_r(const InvJobDD* __restrict__ jobs, int s0, int W, int chunks) {
+  const InvJobDD jb = jobs[blockIdx.x / (W * chunks)];
+  const int n = jb.n;
+  if (s0 >= n) return;
+  const int ws = min(W, n - s0);
+  const int rem = blockIdx.x % (W * chunks);
+  const int c = rem / chunks;
+  const int j = (rem % chunks) * 256 + threadIdx.x;
+  if (c >= ws || j >= n) return;
+  jb.R[(int64_t)c * n + j] = jb.X[(int64_t)(s0 + c) * jb.ld + j];
+}
+
 __global__ __launch_bounds__(256) void k_dd_inv_unscramble(const InvJobDD* __restrict__ jobs, int rows_per_block,
                                                            int chunks) {
   extern __shared__ int idx[];
@@ -521,6 +551,13 @@ void launch_dd_inv_swap(hipStream_t st, const InvJobDD* jobs, int njobs, int k0,
   if (njobs <= 0) return;
   const int chunks = (max_n + 255) / 256;
   hipLaunchKernelGGL(k_dd_inv_swap, dim3(njobs * chunks), dim3(256), 0, st, jobs, k0, nb, chunks);
+}
+
+void launch_dd_inv_super(hipStream_t st, const InvJobDD* jobs, int njobs, int s0, int W, int max_n) {
+  if (njobs <= 0 || W <= 0 || W > 64) return;
+  const int cu = (max_n + 15) / 16, cr = (max_n + 255) / 256;
+  hipLaunchKernelGGL(k_dd_inv_super_u, dim3(njobs * cu), dim3(64), 0, st, jobs, s0, W, cu);
+  hipLaunchKernelGGL(k_dd_inv_super_r, dim3(njobs * W * cr), dim3(256), 0, st, jobs, s0, W, cr);
 }
 
 void launch_dd_inv_unscramble(hipStream_t st, const InvJobDD* jobs, int njobs, int max_n) {

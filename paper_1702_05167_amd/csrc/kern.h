@@ -183,7 +183,11 @@ void launch_dd_inv_panel(hipStream_t st, const InvJobDD* jobs, int njobs, int k0
                          int32_t* status);
 void launch_dd_inv_swap(hipStream_t st, const InvJobDD* jobs, int njobs, int k0, int nb, int max_n);
 void launch_dd_inv_unscramble(hipStream_t st, const InvJobDD* jobs, int njobs, int max_n);
+// two-level Gauss-Jordan: T = super-panel columns minus identity (row stride W), R = its pivot rows
+void launch_dd_inv_super(hipStream_t st, const InvJobDD* jobs, int njobs, int s0, int W, int max_n);
 int dd_inv_nb(int max_n);
+// columns of a super-panel of the double-double Gauss-Jordan (its pivot rows update the rest at once)
+constexpr int kDDSuper = 64;
 
 // ---- double-double products from 8-bit slices on the integer matrix cores (ozaki.hip) ----
 // slices per operand: each double-double operand is kept to 2^-112 of its row's (or column's)

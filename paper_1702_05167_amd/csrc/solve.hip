@@ -62,8 +62,8 @@ struct Blob {
 
 enum StepKind { S_ASSEMBLE, S_INV_PANEL, S_INV_SWAP, S_INV_UNSCR, S_GEMM, S_GATHER, S_ASSEMBLE_N, S_DIAG, S_GUARD,
                 S_DD_ASSEMBLE, S_DD_INV_PANEL, S_DD_INV_SWAP, S_DD_INV_UNSCR, S_DD_GEMM, S_INV_SUPER,
-                S_OZ_SPLIT, S_OZ_GEMM};
-constexpr int kStepKinds = 17;
+                S_OZ_SPLIT, S_OZ_GEMM, S_DD_INV_SUPER};
+constexpr int kStepKinds = 18;
 
 // Tile sizes a plan keeps GEMM problem lists and tile maps for: 64x64, 128x64, 64x128, 32x32,
 // 128x128.  Every launch kind of launch_gemm uses one of them (tile_dims_of).
@@ -261,8 +261,8 @@ struct Builder {
           const size_t nbd = dd_inv_nb((int)n);
           s.Fd = wsa((n + f) * (n + f) * 32);
           s.Invd = wsa(n * n * 32);
-          s.Td = wsa(n * nbd * 32);
-          s.Rd = wsa(nbd * n * 32);
+          s.Td = wsa(n * std::max<size_t>(nbd, kDDSuper) * 32);
+          s.Rd = wsa(std::max<size_t>(nbd, kDDSuper) * n * 32);
           if (!root(i)) s.Psid = wsa(n * f * 32);
         } else {
           s.F = wsa((n + f) * (n + f) * 16);
@@ -655,6 +655,47 @@ struct Builder {
     push(s);
   }
 
+  // Batched Gauss-Jordan inverses in double-double (the pivot blocks A_ii^-1 of Algorithm 1), two
+  // levels: panels of nb columns inside super-panels of kDDSuper columns; a panel's rank-nb update
+  // touches only its super-panel's columns (vector units), and each super-panel then updates every
+  // other column at once with its pivot rows (a rank-kDDSuper product, on the integer matrix cores
+  // with `oz`).  Jobs need T (n x kDDSuper) and R (kDDSuper x n) workspaces.
+  void dd_inverse(const std::vector<InvJobDD>& ij, int maxn) {
+    const int nb = dd_inv_nb(maxn);
+    const size_t ijo = blob.push(ij);
+    const int SW = kDDSuper;
+    for (int s0 = 0; s0 < maxn; s0 += SW) {
+      for (int k0 = s0; k0 < std::min(s0 + SW, maxn); k0 += nb) {
+        Step p; p.kind = S_DD_INV_PANEL; p.jobs = ijo; p.njobs = (int)ij.size(); p.i0 = k0; p.i1 = nb; p.i2 = maxn;
+        push(p);
+        Step w = p; w.kind = S_DD_INV_SWAP;
+        push(w);
+        std::vector<GPD> ps;
+        for (const InvJobDD& j : ij) {
+          if (k0 >= j.n) continue;
+          const int kb = std::min(nb, j.n - k0);
+          const int ns = std::min(s0 + SW, j.n) - s0;
+          ps.push_back({j.T, j.R + s0, j.X + s0, j.X + s0, nullptr, j.n, ns, kb, kb, j.n, j.ld, j.ld, 0});
+        }
+        dd_gemm_valu(0, 0, ps, 0, 1);
+      }
+      Step sp; sp.kind = S_DD_INV_SUPER; sp.jobs = ijo; sp.njobs = (int)ij.size(); sp.i0 = s0; sp.i1 = SW; sp.i2 = maxn;
+      push(sp);
+      std::vector<GPD> pt;
+      for (const InvJobDD& j : ij) {
+        if (s0 >= j.n) continue;
+        const int ws = std::min(SW, j.n - s0);
+        if (s0 > 0) pt.push_back({j.T, j.R, j.X, j.X, nullptr, j.n, s0, ws, SW, j.n, j.ld, j.ld, 0});
+        if (s0 + ws < j.n)
+          pt.push_back({j.T, j.R + s0 + ws, j.X + s0 + ws, j.X + s0 + ws, nullptr, j.n, j.n - s0 - ws, ws, SW, j.n,
+                        j.ld, j.ld, 0});
+      }
+      dd_gemm(0, 0, pt, 0, 1);
+    }
+    Step u; u.kind = S_DD_INV_UNSCR; u.jobs = ijo; u.njobs = (int)ij.size(); u.i2 = maxn;
+    push(u);
+  }
+
   void fold_dd(const std::vector<std::vector<int>>& L) {
     for (int d = (int)L.size() - 1; d >= 0; --d) {
       phase = PH_FOLD;
@@ -688,7 +729,6 @@ struct Builder {
       phase = PH_INVERSE;
       int maxn = 0;
       for (int i : L[d]) maxn = std::max(maxn, n_of(i));
-      const int nb = dd_inv_nb(maxn);
       std::vector<InvJobDD> ij;
       for (int i : L[d])
         for (int e = 0; e < B; ++e) {
@@ -702,22 +742,7 @@ struct Builder {
           j.T = Z(s.Td); j.R = Z(s.Rd);
           ij.push_back(j);
         }
-      const size_t ijo = blob.push(ij);
-      for (int k0 = 0; k0 < maxn; k0 += nb) {
-        Step p; p.kind = S_DD_INV_PANEL; p.jobs = ijo; p.njobs = (int)ij.size(); p.i0 = k0; p.i1 = nb; p.i2 = maxn;
-        push(p);
-        Step w = p; w.kind = S_DD_INV_SWAP;
-        push(w);
-        std::vector<GPD> ps;
-        for (const InvJobDD& j : ij) {
-          if (k0 >= j.n) continue;
-          const int kb = std::min(nb, j.n - k0);
-          ps.push_back({j.T, j.R, j.X, j.X, nullptr, j.n, j.n, kb, kb, j.n, j.ld, j.ld, 0});
-        }
-        dd_gemm(0, 0, ps, 0, 1);
-      }
-      Step u; u.kind = S_DD_INV_UNSCR; u.jobs = ijo; u.njobs = (int)ij.size(); u.i2 = maxn;
-      push(u);
+      dd_inverse(ij, maxn);
       phase = PH_FOLD;
       std::vector<GPD> pp, pu;
       for (int i : L[d]) {
@@ -1143,7 +1168,7 @@ const int kKinds3[] = {4, 5, 7, 8};
 bool step_empty(const Step& s) {
   switch (s.kind) {
     case S_INV_PANEL: case S_INV_SWAP: case S_INV_UNSCR: case S_INV_SUPER: case S_GUARD:
-    case S_DD_INV_PANEL: case S_DD_INV_SWAP: case S_DD_INV_UNSCR:
+    case S_DD_INV_PANEL: case S_DD_INV_SWAP: case S_DD_INV_UNSCR: case S_DD_INV_SUPER:
       return s.njobs <= 0;
     default:
       return s.count <= 0;
@@ -1220,6 +1245,9 @@ int run_steps(hsc_ctx* ctx, hipStream_t st, Plan* pl, int e_base, int nvalid, vo
         break;
       case S_DD_INV_UNSCR:
         launch_dd_inv_unscramble(st, (const InvJobDD*)jobs, s.njobs, s.i2);
+        break;
+      case S_DD_INV_SUPER:
+        launch_dd_inv_super(st, (const InvJobDD*)jobs, s.njobs, s.i0, s.i1, s.i2);
         break;
       case S_DD_GEMM:
         launch_dd_gemm(st, s.i0, s.i2, s.tile, (const GemmProbDD*)(pl->blob + s.jobs_k[s.tile]),
@@ -1317,6 +1345,45 @@ hsc_status tune_plan(hsc_ctx* ctx, Plan* pl) {
   return rc;
 }
 
+// Allocate the slice scratch, rebase the blob's pointer fields, upload it and take the steps.
+hsc_status upload_plan(Builder& b, Plan* pl) {
+  if (b.oz_need > 0) {
+    pl->oz_bytes = b.oz_need;
+    if (hipMalloc(&pl->oz, pl->oz_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      pl->oz = nullptr;
+      set_error("slice scratch allocation failed (" + std::to_string(pl->oz_bytes) + " bytes)");
+      return HSC_E_OOM;
+    }
+    for (size_t f : b.blob.sc_relocs) {
+      uint64_t v;
+      std::memcpy(&v, b.blob.data.data() + f, 8);
+      v += reinterpret_cast<uint64_t>(pl->oz);
+      std::memcpy(b.blob.data.data() + f, &v, 8);
+    }
+  }
+  pl->blob_bytes = b.blob.data.size();
+  if (hipMalloc(&pl->blob, pl->blob_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    pl->blob = nullptr;
+    set_error("device plan allocation failed");
+    return HSC_E_OOM;
+  }
+  for (size_t f : b.blob.relocs) {
+    uint64_t v;
+    std::memcpy(&v, b.blob.data.data() + f, 8);
+    v += reinterpret_cast<uint64_t>(pl->blob);
+    std::memcpy(b.blob.data.data() + f, &v, 8);
+  }
+  HIPCHK(hipMemcpy(pl->blob, b.blob.data.data(), pl->blob_bytes, hipMemcpyHostToDevice));
+  pl->steps = std::move(b.steps);
+  for (Step& s : pl->steps) {
+    if (s.kind == S_GEMM) s.tile = pl->m3 ? 4 : 0;   // default kernels: 64x64 tiles, 16x16x4 MFMA
+    if (s.kind == S_DD_GEMM) s.tile = kDefaultDDConfig;
+  }
+  return HSC_OK;
+}
+
 int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, int tune, int m3, Plan** out) {
   for (size_t k = 0; k < ctx->plans.size(); ++k)
     if (ctx->plans[k]->uid == t->uid && ctx->plans[k]->B == B && ctx->plans[k]->want == want &&
@@ -1387,46 +1454,15 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
     if (b.ddx) b.channel_steps<zdd>(L, (int)k);
     else b.channel_steps<double2>(L, (int)k);
   }
-  // slice scratch of the products on the integer matrix cores
-  if (b.oz_need > 0) {
-    pl->oz_bytes = b.oz_need;
-    if (hipMalloc(&pl->oz, pl->oz_bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      pl->oz = nullptr;
-      set_error("slice scratch allocation failed (" + std::to_string(pl->oz_bytes) + " bytes)");
-      return HSC_E_OOM;
-    }
-    for (size_t f : b.blob.sc_relocs) {
-      uint64_t v;
-      std::memcpy(&v, b.blob.data.data() + f, 8);
-      v += reinterpret_cast<uint64_t>(pl->oz);
-      std::memcpy(b.blob.data.data() + f, &v, 8);
-    }
+  {
+    const hsc_status rc = upload_plan(b, pl.get());
+    if (rc != HSC_OK) return rc;
   }
-  // upload the blob with relocations
-  pl->blob_bytes = b.blob.data.size();
-  if (hipMalloc(&pl->blob, pl->blob_bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    set_error("device plan allocation failed");
-    return HSC_E_OOM;
-  }
-  for (size_t f : b.blob.relocs) {
-    uint64_t v;
-    std::memcpy(&v, b.blob.data.data() + f, 8);
-    v += reinterpret_cast<uint64_t>(pl->blob);
-    std::memcpy(b.blob.data.data() + f, &v, 8);
-  }
-  HIPCHK(hipMemcpy(pl->blob, b.blob.data.data(), pl->blob_bytes, hipMemcpyHostToDevice));
   pl->left = reinterpret_cast<int64_t*>(pl->blob + o_left);
   for (int c = 0; c < 2; ++c) {
     pl->lp.onsite[c] = t->contact[c].lead_onsite;
     pl->lp.hopping[c] = t->contact[c].lead_hopping;
     pl->lp.coupling[c] = t->contact[c].coupling;
-  }
-  pl->steps = std::move(b.steps);
-  for (Step& s : pl->steps) {
-    if (s.kind == S_GEMM) s.tile = m3 ? 4 : 0;   // default kernels: 64x64 tiles, 16x16x4 MFMA
-    if (s.kind == S_DD_GEMM) s.tile = kDefaultDDConfig;
   }
   if (tune) {
     const hsc_status rc = tune_plan(ctx, pl.get());
@@ -2122,63 +2158,45 @@ hsc_status hsc_kern_zgemm_dd(hsc_ctx* ctx, int32_t config, int32_t opA, int32_t 
   return HSC_OK;
 }
 
-hsc_status hsc_kern_zinv_dd(hsc_ctx* ctx, int32_t n, void* X, int32_t ld, void* Y, int32_t ldy, int32_t* status) {
-  if (!ctx || n < 1 || n > kMaxCluster || !X || !Y || ld < n || ldy < n) {
+hsc_status hsc_kern_zinv_dd(hsc_ctx* ctx, int32_t n, void* X, int32_t ld, void* Y, int32_t ldy, int32_t* status,
+                            int32_t matrix_cores) {
+  if (!ctx || n < 1 || n > kMaxCluster || !X || !Y || ld < n || ldy < n || (matrix_cores != 0 && matrix_cores != 1)) {
     set_error("bad arguments to hsc_kern_zinv_dd");
     return HSC_E_ARG;
   }
   HIPCHK(hipSetDevice(ctx->device));
-  const int nb = dd_inv_nb(n);
-  const int nsteps = (n + nb - 1) / nb;
-  const int T32 = (n + dd_gemm_tile_m(0) - 1) / dd_gemm_tile_m(0);
-  const int tiles = T32 * ((n + dd_gemm_tile_n(0) - 1) / dd_gemm_tile_n(0));
+  // the solver's own inverse steps (Builder::dd_inverse) for one block
+  const size_t W = std::max<size_t>(dd_inv_nb(n), kDDSuper);
   size_t ws = 0;
   auto wa = [&](size_t b) { size_t o = (ws + 255) / 256 * 256; ws = o + b; return o; };
-  const size_t o_piv = wa(sizeof(int32_t) * n), o_t = wa(32ull * n * nb), o_r = wa(32ull * n * nb);
-  const size_t o_job = wa(sizeof(InvJobDD)), o_st = wa(sizeof(int32_t));
-  const size_t o_probs = wa(sizeof(GemmProbDD) * nsteps), o_map = wa(sizeof(int32_t) * tiles);
+  const size_t o_piv = wa(sizeof(int32_t) * n), o_t = wa(32 * W * n), o_r = wa(32 * W * n);
+  const size_t o_st = wa(sizeof(int32_t));
   const size_t o_y64 = wa(16ull * n * n);   // the unscramble step always writes the rounded inverse too
-  char* dev = nullptr;
-  if (hipMalloc(&dev, ws) != hipSuccess) { (void)hipGetLastError(); set_error("alloc failed"); return HSC_E_OOM; }
+  Plan pl;
+  if (hipMalloc(&pl.ws, ws) != hipSuccess) {
+    (void)hipGetLastError();
+    pl.ws = nullptr;
+    set_error("alloc failed");
+    return HSC_E_OOM;
+  }
+  pl.B = 1;
+  pl.status = reinterpret_cast<int32_t*>(pl.ws + o_st);
+  Builder b{nullptr, 1, 0, false};
+  b.oz = matrix_cores != 0;
+  b.wsbase = pl.ws;
+  b.blob.alloc(64);
   InvJobDD j{};
-  j.X = (zdd*)X; j.ld = ld; j.Y = (zdd*)Y; j.ldy = ldy; j.Y64 = (double2*)(dev + o_y64); j.ldy64 = n; j.n = n;
+  j.X = (zdd*)X; j.ld = ld; j.Y = (zdd*)Y; j.ldy = ldy; j.Y64 = (double2*)(pl.ws + o_y64); j.ldy64 = n; j.n = n;
   j.e = 0;
-  j.piv = (int32_t*)(dev + o_piv); j.T = (zdd*)(dev + o_t); j.R = (zdd*)(dev + o_r);
-  std::vector<GemmProbDD> probs(nsteps);
-  for (int q = 0; q < nsteps; ++q) {
-    // rank-kb update of the whole block: X += T R (T: n x kb, R: kb x n, as the panel leaves them)
-    const int kb = std::min(nb, n - q * nb);
-    GemmProbDD& p = probs[q];
-    p.A = j.T; p.B = j.R; p.C = j.X; p.D = j.X; p.D64 = nullptr;
-    p.M = n; p.N = n; p.K = kb; p.lda = kb; p.ldb = n; p.ldc = ld; p.ldd = ld; p.ldd64 = 0;
-    p.tiles_n = (n + dd_gemm_tile_n(0) - 1) / dd_gemm_tile_n(0);
-    p.tile_off = 0;
-  }
-  const std::vector<int32_t> map(tiles, 0);
-  const int32_t zero = 0;
-  hipError_t err = hipMemcpy(dev + o_job, &j, sizeof(j), hipMemcpyHostToDevice);
-  if (err == hipSuccess) err = hipMemcpy(dev + o_st, &zero, sizeof(zero), hipMemcpyHostToDevice);
-  if (err == hipSuccess) err = hipMemcpy(dev + o_probs, probs.data(), sizeof(GemmProbDD) * nsteps, hipMemcpyHostToDevice);
-  if (err == hipSuccess) err = hipMemcpy(dev + o_map, map.data(), sizeof(int32_t) * tiles, hipMemcpyHostToDevice);
-  if (err == hipSuccess) {
-    const InvJobDD* dj = (const InvJobDD*)(dev + o_job);
-    int32_t* dst = (int32_t*)(dev + o_st);
-    for (int q = 0; q < nsteps; ++q) {
-      launch_dd_inv_panel(ctx->stream, dj, 1, q * nb, nb, n, dst);
-      launch_dd_inv_swap(ctx->stream, dj, 1, q * nb, nb, n);
-      launch_dd_gemm(ctx->stream, 0, 0, 0, (const GemmProbDD*)(dev + o_probs) + q, (const int32_t*)(dev + o_map),
-                     tiles, 0, 1);
-    }
-    launch_dd_inv_unscramble(ctx->stream, dj, 1, n);
-    err = hipGetLastError();
-    if (err == hipSuccess) err = ctx->stream ? hipStreamSynchronize(ctx->stream) : hipDeviceSynchronize();
-    if (err == hipSuccess && status) err = hipMemcpy(status, dst, sizeof(int32_t), hipMemcpyDeviceToDevice);
-  }
-  (void)hipFree(dev);
-  if (err != hipSuccess) {
-    set_error(std::string("HIP error in hsc_kern_zinv_dd: ") + hipGetErrorString(err));
-    return HSC_E_HIP;
-  }
+  j.piv = (int32_t*)(pl.ws + o_piv); j.T = (zdd*)(pl.ws + o_t); j.R = (zdd*)(pl.ws + o_r);
+  b.dd_inverse(std::vector<InvJobDD>{j}, n);
+  hsc_status rc = upload_plan(b, &pl);
+  if (rc != HSC_OK) return rc;
+  HIPCHK(hipMemsetAsync(pl.status, 0, sizeof(int32_t), ctx->stream));
+  rc = (hsc_status)run_steps(ctx, ctx->stream, &pl, 0, 1, nullptr, nullptr, nullptr, nullptr, 0);
+  if (rc != HSC_OK) return rc;
+  HIPCHK(ctx->stream ? hipStreamSynchronize(ctx->stream) : hipDeviceSynchronize());
+  if (status) HIPCHK(hipMemcpy(status, pl.status, sizeof(int32_t), hipMemcpyDeviceToDevice));
   return HSC_OK;
 }
 

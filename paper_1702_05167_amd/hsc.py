@@ -79,7 +79,7 @@ def lib():
                                       i32]
     L.hsc_kern_zgemm_dd.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, vp, i32, vp, i32, i32, vp, i32, vp, i32]
     L.hsc_kern_zinv_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
-    L.hsc_kern_zinv_dd.argtypes = [vp, i32, vp, i32, vp, i32, vp]
+    L.hsc_kern_zinv_dd.argtypes = [vp, i32, vp, i32, vp, i32, vp, i32]
     L.hsc_kern_mfma_probe.argtypes = [vp, vp]
     L.hsc_kern_mfma_rate.argtypes = [vp, C.POINTER(dbl)]
     L.hsc_totals.argtypes = [vp, i32, i64, vp, vp, vp, vp]
@@ -140,7 +140,7 @@ class Context:
 
     PROFILE_KINDS = ("assemble", "inv_panel", "inv_swap", "inv_unscramble", "gemm", "gather",
                      "assemble_n", "diag", "guard", "dd_assemble", "dd_inv_panel", "dd_inv_swap",
-                     "dd_inv_unscramble", "dd_gemm", "inv_super", "oz_split", "oz_gemm")
+                     "dd_inv_unscramble", "dd_gemm", "inv_super", "oz_split", "oz_gemm", "dd_inv_super")
 
     def profile(self, enable: bool):
         check(lib().hsc_ctx_profile(self.h, 1 if enable else 0))
@@ -380,16 +380,18 @@ def kern_zgemm_dd(ctx, opA, opB, A, B, negate=0, beta=0, C_=None, D=None, config
     return D
 
 
-def kern_zinv_dd(ctx, X):
+def kern_zinv_dd(ctx, X, matrix_cores=0):
     """Inverse of a square complex double-double matrix: X is a device float64 tensor (n, n, 4)
-    (re hi, re lo, im hi, im lo), overwritten; returns (inverse, status)."""
+    (re hi, re lo, im hi, im lo), overwritten; returns (inverse, status).  matrix_cores=1: the
+    super-panel updates on the integer matrix cores (as the precision-3 solve)."""
     import torch
     n = X.shape[0]
     if X.dim() != 3 or X.shape[1] != n or X.shape[2] != 4 or X.stride(2) != 1 or X.stride(1) != 4:
         raise ValueError("X must be a (n, n, 4) tensor with contiguous elements")
     Y = torch.empty_like(X)
     st = torch.empty(1, dtype=torch.int32, device=X.device)
-    check(lib().hsc_kern_zinv_dd(ctx.h, n, _dptr(X), X.stride(0) // 4, _dptr(Y), Y.stride(0) // 4, _dptr(st)))
+    check(lib().hsc_kern_zinv_dd(ctx.h, n, _dptr(X), X.stride(0) // 4, _dptr(Y), Y.stride(0) // 4, _dptr(st),
+                                 matrix_cores))
     return Y, st
 
 

@@ -23,10 +23,25 @@ def _code(fn):
     return e.value.code
 
 
-@pytest.mark.parametrize("kw", [dict(want=0), dict(precision=3), dict(precision=-1), dict(complex3m=2), dict(eta=0.0),
+@pytest.mark.parametrize("kw", [dict(want=0), dict(precision=4), dict(precision=-1), dict(complex3m=2), dict(eta=0.0),
                                 dict(kT=-1.0), dict(guard=True, guard_tau=10.0, guard_rounds=-1)])
 def test_solve_rejects_bad_options(ctx, tree, kw):
     assert _code(lambda: pkg.solve(ctx, tree, np.array([0.1, 0.2]), **kw)) == -1
+
+
+def test_solve_rejects_clusters_beyond_the_dense_block_limit(ctx):
+    # a 17^3 cube as one cluster (4913 sites > 4096, the largest block the batched inverses cover):
+    # the plan is refused with HSC_E_ARG before anything is allocated or launched, the outputs
+    # stay untouched
+    tree = pkg.Tree.from_device(synth.cuboid(17, 17, 17), leaf_side=17)
+    assert tree.stats()["max_cluster"] == 4913
+    gr = torch.full((1, tree.n), 7.0, dtype=torch.complex128, device="cuda")
+    for precision in (0, 2, 3):
+        assert _code(lambda: pkg.solve(ctx, tree, np.array([0.3]), want=pkg.HSC_DIAG_GR, out={"gr": gr},
+                                       precision=precision)) == -1
+        assert b"dense-block limit" in H.lib().hsc_last_error()
+    torch.cuda.synchronize()
+    assert bool((gr == 7.0).all())
 
 
 def test_solve_with_no_energies_is_a_no_op(ctx, tree):
@@ -53,6 +68,9 @@ def test_kernel_entry_points_reject_bad_arguments(ctx):
     A = torch.zeros((4, 4), dtype=torch.complex128, device="cuda")
     assert _code(lambda: H.kern_zgemm(ctx, 0, 0, 1.0, A, A, tile=9)) == -1
     assert _code(lambda: H.kern_zgemm(ctx, 3, 0, 1.0, A, A)) == -1
+    X = torch.zeros((4, 4, 4), dtype=torch.float64, device="cuda")
+    assert _code(lambda: H.kern_zgemm_dd(ctx, 0, 0, X, X, config=4)) == -1
+    assert _code(lambda: H.kern_zinv_dd(ctx, X, matrix_cores=2)) == -1
     rc = H.lib().hsc_totals(ctx.h, 2, 10, None, None, None, None)
     assert rc == -1
 

@@ -183,7 +183,8 @@ def test_zgemm_dd_against_exact_arithmetic(ctx, config, opA, opB, negate, beta):
     assert worst < 1e-29
 
 
-def test_zinv_dd_nearly_singular_block(ctx):
+@pytest.mark.parametrize("matrix_cores", [0, 1])
+def test_zinv_dd_nearly_singular_block(ctx, matrix_cores):
     # a complex-symmetric block like the fold's pivot blocks out of the lead band: real symmetric with one
     # eigenvalue at 1e-10 plus i 1e-12 (condition ~3e10).  The double-double Gauss-Jordan inverse must
     # satisfy A Y = I to ~kappa 1e-31 in exact arithmetic; the complex128 one only to ~kappa 1e-16
@@ -197,7 +198,7 @@ def test_zinv_dd_nearly_singular_block(ctx):
     A = R + 1j * 1e-12 * np.eye(n)
     Xd = np.zeros((n, n, 4))
     Xd[..., 0], Xd[..., 2] = A.real, A.imag
-    Y, st = H.kern_zinv_dd(ctx, torch.tensor(Xd, device=ctx.torch_device))
+    Y, st = H.kern_zinv_dd(ctx, torch.tensor(Xd, device=ctx.torch_device), matrix_cores=matrix_cores)
     Y = Y.cpu().numpy()
     assert int(st.cpu()[0]) == 0
     Ax = [[(F(float(A[i, j].real)), F(float(A[i, j].imag))) for j in range(n)] for i in range(n)]

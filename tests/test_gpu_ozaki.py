@@ -143,6 +143,40 @@ def test_zgemm_oz_rejects_deep_products(ctx):
     assert e.value.code == -1
 
 
+@pytest.mark.parametrize("matrix_cores", [0, 1])
+def test_zinv_dd_super_panels_exact_residual(ctx, matrix_cores):
+    # a 160 x 160 complex-symmetric block with an eigenvalue at 1e-11 (condition ~3e11): three
+    # super-panels (64, 64, 32 columns), whose rank-64 updates run on the integer matrix cores with
+    # matrix_cores = 1.  Residual A Y - I in exact integer arithmetic on sampled columns.
+    rng = np.random.default_rng(11)
+    n = 160
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.concatenate([[1e-11], rng.uniform(1.0, 3.0, n - 1) * rng.choice([-1.0, 1.0], n - 1)])
+    R = (Q * lam) @ Q.T
+    R = 0.5 * (R + R.T)
+    A = R + 1j * 1e-13 * np.eye(n)
+    Xd = np.zeros((n, n, 4))
+    Xd[..., 0], Xd[..., 2] = A.real, A.imag
+    Y, st = H.kern_zinv_dd(ctx, torch.tensor(Xd, device=ctx.torch_device), matrix_cores=matrix_cores)
+    Y = Y.cpu().numpy()
+    assert int(st.cpu()[0]) == 0
+    ynorm = np.abs(Y[..., 0] + 1j * Y[..., 2]).max()
+    assert ynorm > 1e9
+    cols = sorted({0, 63, 64, 127, 128, n - 1} | set(rng.integers(0, n, 6).tolist()))
+    Ar = [[F(float(v)) for v in row] for row in A.real]
+    Ai = [[F(float(v)) for v in row] for row in A.imag]
+    worst = 0.0
+    for j in cols:
+        yr = [F(float(Y[k, j, 0])) + F(float(Y[k, j, 1])) for k in range(n)]
+        yi = [F(float(Y[k, j, 2])) + F(float(Y[k, j, 3])) for k in range(n)]
+        for i in range(n):
+            re = sum(Ar[i][k] * yr[k] - Ai[i][k] * yi[k] for k in range(n)) - (1 if i == j else 0)
+            im = sum(Ar[i][k] * yi[k] + Ai[i][k] * yr[k] for k in range(n))
+            worst = max(worst, abs(float(re)), abs(float(im)))
+    print("super-panel dd inverse: max |A Y - I|", worst, "max |Y|", ynorm)
+    assert worst < 1e-17
+
+
 # ---- solve level ---------------------------------------------------------------------------------
 
 def rel(a, b):
