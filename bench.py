@@ -5,9 +5,11 @@ Workload: the 32^3 cube (32,768 sites, 7-point, t = -1, on-site U[-0.5, 0.5]
 seed 0, per-site 1D leads on the x faces), 256 energies uniform in [-6, 6],
 eta = 1e-8, kT = 0.025, mu_L/R = +-0.1.  Cluster tree: 3D nested dissection
 with planar separators, leaves <= 8 sites per side.  The fold and the
-extraction run in double-double (precision 2: the only setting whose results
+extraction run in double-double (precision 2 and 3: the settings whose results
 agree with the oracle to 1e-10 at every energy of the grid, out of the lead
-band included).
+band included); with precision 3, the default, every double-double block
+product of depth >= 32 is formed from 8-bit slices on the integer matrix
+cores.
 
 One step = diag G^r, diag G^< and T for one batch of energies (16 by default),
 inputs resident on the device; consecutive steps walk the 256-point grid in
@@ -134,9 +136,10 @@ def main():
     ap.add_argument("--cpu-single", type=int, default=1,
                     help="also time the oracle on one thread over this many energies (0: skip)")
     ap.add_argument("--no-golden", action="store_true", help="skip the error against stored oracle values")
-    ap.add_argument("--precision", type=int, default=2,
-                    help="2 (default): fold and extraction in double-double; 1: double-double fold only; "
-                         "0: complex128 as in Algorithms 1 and 2")
+    ap.add_argument("--precision", type=int, default=3,
+                    help="3 (default): fold and extraction in double-double, block products of depth >= 32 from "
+                         "8-bit slices on the integer matrix cores; 2: the same on the FP64 vector units; "
+                         "1: double-double fold only; 0: complex128 as in Algorithms 1 and 2")
     ap.add_argument("--leaf", type=int, default=8)
     ap.add_argument("--transverse", action="store_true",
                     help="never cut the transport axis (clusters span contact to contact)")

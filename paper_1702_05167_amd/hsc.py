@@ -95,7 +95,8 @@ def lib():
                  "hsc_tree_stats_get",
                  "hsc_tree_export", "hsc_tree_destroy", "hsc_solve", "hsc_solve_batch", "hsc_sync",
                  "hsc_ctx_profile", "hsc_ctx_profile_read", "hsc_ctx_profile_launches",
-                 "hsc_kern_zgemm", "hsc_kern_zgemm_tile", "hsc_kern_zgemm_dd", "hsc_kern_zinv_batched",
+                 "hsc_kern_zgemm", "hsc_kern_zgemm_tile", "hsc_kern_zgemm_dd",
+                 "hsc_kern_zinv_batched",
                  "hsc_kern_zinv_dd",
                  "hsc_kern_mfma_probe",
                  "hsc_kern_mfma_rate", "hsc_totals",
@@ -258,7 +259,7 @@ class Tree:
 
 def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1,
           want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, out=None, sync=True, guard=False,
-          guard_tau=0.0, guard_rounds=6, precision=2, graph=0, tune=0, complex3m=0):
+          guard_tau=0.0, guard_rounds=6, precision=3, graph=0, tune=0, complex3m=0):
     """Solve all energies; returns a dict of device tensors (gr, gl, trans, spectral, status)."""
     import torch
     dev = ctx.torch_device
@@ -287,7 +288,7 @@ def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R
 
 
 def solve_batch(ctx: Context, trees, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1,
-                want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, outs=None, sync=True, precision=2, graph=0,
+                want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, outs=None, sync=True, precision=3, graph=0,
                 tune=0, complex3m=0):
     """Several devices in one call (hsc_solve_batch); energies: one array for all devices or a
     list of per-device arrays.  Returns a list of output dicts (device tensors)."""
