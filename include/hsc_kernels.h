@@ -61,6 +61,25 @@ hsc_status hsc_kern_zgemm_dd(hsc_ctx* ctx, int32_t config, int32_t opA, int32_t 
                              int32_t K, int32_t negate, const void* A, int32_t lda, const void* B, int32_t ldb,
                              int32_t beta, const void* C, int32_t ldc, void* D, int32_t ldd);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the double-double
+ * product of hsc_kern_zgemm_dd with config 3 (8-bit slices on the integer
+ * matrix cores), same arguments, same kernels, same results, with every
+ * descriptor, slice plane and scale in one static device array of 64 MiB per
+ * GPU (held from the first context on that GPU until the process ends); the
+ * call allocates nothing and does not wait: it enqueues four kernels on the
+ * context's stream and returns (D is valid after hsc_sync or a stream
+ * synchronisation).  Limit: the scratch of one product, 48 (Mp + Np) Kp bytes
+ * plus maps (Mp, Np = M, N rounded up to 32, Kp = K rounded up to 64), must fit
+ * 64 MiB (e.g. M = N = 1024 with K <= 640); larger products return HSC_E_ARG.
+ * Every call on one GPU shares that array and leaves it holding its own
+ * intermediates: calls that overlap on one GPU (other streams, other contexts,
+ * other threads) race and must be serialised by the caller.
+ * Errors: HSC_E_ARG (as hsc_kern_zgemm_dd, or too large), HSC_E_HIP. */
+hsc_status hsc_kern_zgemm_dd_noalloc(hsc_ctx* ctx, int32_t opA, int32_t opB, int32_t M, int32_t N, int32_t K,
+                                     int32_t negate, const void* A, int32_t lda, const void* B, int32_t ldb,
+                                     int32_t beta, const void* C, int32_t ldc, void* D, int32_t ldd);
+
 /* The pivot-block inverse of the double-double fold (hsc_solve_opts.precision
  * >= 1, Algorithm 1's A_ii^-1) on its own, with the solver's own launch
  * sequence: two-level blocked Gauss-Jordan with partial pivoting inside the

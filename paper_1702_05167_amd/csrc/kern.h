@@ -224,6 +224,14 @@ void launch_oz_split(hipStream_t st, const OzSplitJob* jobs, const int32_t* blk_
                      const int32_t* tile_job, int total_tiles);
 void launch_oz_gemm(hipStream_t st, const GemmProbOZ* probs, const int32_t* tile_prob, int total_tiles, int negate,
                     int beta);
+// the allocation-free product: a static device array of kOzNoAllocScratch bytes per device holds
+// descriptors, maps, slices and exponents of one problem (oz_noalloc_bytes of them)
+constexpr size_t kOzNoAllocScratch = size_t(64) << 20;
+void* oz_noalloc_scratch_address();
+size_t oz_noalloc_bytes(int M, int N, int K);
+int launch_oz_gemm_noalloc(hipStream_t st, char* ws, int opA, int opB, int M, int N, int K, int negate,
+                           const void* A, int lda, const void* B, int ldb, int beta, const void* C, int ldc, void* D,
+                           int ldd);
 
 // debug / unit-test helpers
 void launch_mfma_rate(hipStream_t st, double* out, int blocks, int iters);

@@ -288,7 +288,86 @@ __global__ __launch_bounds__(256) void k_oz_gemm(const GemmProbOZ* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// the allocation-free product: descriptors and maps of one problem written on the device
+
+// jobs A, B at ws (an array of two), the product at ws + 256, maps at ws + 1024: scale blocks (ba of job 0,
+// bb of job 1), digit tiles (ta, tb), product tiles (all 0); slices and exponents at the given
+// offsets
+__global__ __launch_bounds__(256) void k_oz_setup(char* ws, OzSplitJob ja, OzSplitJob jb, GemmProbOZ p, int ba,
+                                                  int bb, int ta, int tb, int tiles) {
+  if (threadIdx.x == 0) {
+    *reinterpret_cast<OzSplitJob*>(ws) = ja;
+    reinterpret_cast<OzSplitJob*>(ws)[1] = jb;
+    *reinterpret_cast<GemmProbOZ*>(ws + 256) = p;
+  }
+  int32_t* m = reinterpret_cast<int32_t*>(ws + 1024);
+  const int n = ba + bb + ta + tb + tiles;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    int v = 0;
+    if (i < ba + bb) v = i < ba ? 0 : 1;
+    else if (i < ba + bb + ta + tb) v = i - ba - bb < ta ? 0 : 1;
+    m[i] = v;
+  }
+}
+
+// Scratch of the allocation-free product: one array per device, allocated with the code object;
+// host code uses the address obtained from hipGetSymbolAddress, never the array's name.
+__device__ __align__(256) char scratch[kOzNoAllocScratch];
+
 }  // namespace
+
+// Device address of `scratch` on the current device (looked up once per device by the caller and
+// kept); nullptr if the runtime cannot resolve it.
+void* oz_noalloc_scratch_address() {
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return ptr;
+}
+
+size_t oz_noalloc_bytes(int M, int N, int K) {
+  const size_t Mp = (M + 31) / 32 * 32, Np = (N + 31) / 32 * 32, Kp = (K + 63) / 64 * 64;
+  const size_t ba = (Mp + 63) / 64, bb = (Np + 63) / 64, ta = ba * (Kp / 32), tb = bb * (Kp / 32);
+  const size_t tiles = (Mp / 32) * (Np / 32);
+  auto pad = [](size_t v) { return (v + 255) / 256 * 256; };
+  return pad(1024 + 4 * (ba + bb + ta + tb + tiles)) + pad(3 * kOzSlices * Mp * Kp) + pad(3 * kOzSlices * Np * Kp) +
+         pad(4 * Mp) + pad(4 * Np);
+}
+
+int launch_oz_gemm_noalloc(hipStream_t st, char* ws, int opA, int opB, int M, int N, int K, int negate,
+                           const void* A, int lda, const void* B, int ldb, int beta, const void* C, int ldc, void* D,
+                           int ldd) {
+  const int Mp = (M + 31) / 32 * 32, Np = (N + 31) / 32 * 32, Kp = (K + 63) / 64 * 64;
+  const int ba = (Mp + 63) / 64, bb = (Np + 63) / 64, ta = ba * (Kp / 32), tb = bb * (Kp / 32);
+  const int tiles = (Mp / 32) * (Np / 32);
+  auto pad = [](size_t v) { return (v + 255) / 256 * 256; };
+  const size_t o_a8 = pad(1024 + 4 * (size_t)(ba + bb + ta + tb + tiles));
+  const size_t o_b8 = o_a8 + pad((size_t)3 * kOzSlices * Mp * Kp);
+  const size_t o_ea = o_b8 + pad((size_t)3 * kOzSlices * Np * Kp);
+  const size_t o_eb = o_ea + pad(4 * (size_t)Mp);
+  OzSplitJob ja{}, jb{};
+  ja.X = (const zdd*)A; ja.R = M; ja.K = K; ja.Rp = Mp; ja.Kp = Kp;
+  if (opA == 0) { ja.ldr = lda; ja.ldk = 1; } else { ja.ldr = 1; ja.ldk = lda; }
+  ja.out = (int8_t*)(ws + o_a8); ja.ex = (int32_t*)(ws + o_ea);
+  ja.blk_off = 0; ja.tile_off = 0;
+  jb.X = (const zdd*)B; jb.R = N; jb.K = K; jb.Rp = Np; jb.Kp = Kp;
+  if (opB == 0) { jb.ldr = 1; jb.ldk = ldb; } else { jb.ldr = ldb; jb.ldk = 1; }
+  jb.out = (int8_t*)(ws + o_b8); jb.ex = (int32_t*)(ws + o_eb);
+  jb.blk_off = ba; jb.tile_off = ta;
+  GemmProbOZ p{};
+  p.A8 = ja.out; p.B8 = jb.out; p.ea = ja.ex; p.eb = jb.ex;
+  p.C = (const zdd*)C; p.D = (zdd*)D; p.D64 = nullptr;
+  p.M = M; p.N = N; p.Mp = Mp; p.Np = Np; p.Kp = Kp; p.ldc = ldc; p.ldd = ldd; p.ldd64 = 0;
+  p.tiles_n = Np / 32; p.tile_off = 0;
+  hipLaunchKernelGGL(k_oz_setup, dim3(1), dim3(256), 0, st, ws, ja, jb, p, ba, bb, ta, tb, tiles);
+  const int32_t* m = reinterpret_cast<const int32_t*>(ws + 1024);
+  launch_oz_split(st, reinterpret_cast<const OzSplitJob*>(ws), m, ba + bb, m + ba + bb, ta + tb);
+  launch_oz_gemm(st, reinterpret_cast<const GemmProbOZ*>(ws + 256), m + ba + bb + ta + tb, tiles, negate, beta);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
 
 void launch_oz_split(hipStream_t st, const OzSplitJob* jobs, const int32_t* blk_job, int total_blocks,
                      const int32_t* tile_job, int total_tiles) {

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <tuple>
 #include <string>
 #include <type_traits>
@@ -146,6 +147,7 @@ struct Plan {
 struct hsc_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  char* noalloc = nullptr;   // this device's allocation-free product scratch (static device array)
   std::vector<std::unique_ptr<hsc::Plan>> plans;
   // optional per-launch timing: events around every launch, grouped by step kind
   bool profile = false;
@@ -1503,6 +1505,18 @@ hsc_status hsc_ctx_create(int32_t device, void* hip_stream, hsc_ctx** out) {
   hsc_ctx* c = new hsc_ctx();
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  {
+    // address of the allocation-free product's scratch array on this device, looked up once per
+    // device (with the device current) and kept for every later context
+    static std::mutex mu;
+    static std::vector<char*> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)addr.size() < count) addr.resize(count, nullptr);
+    if (!addr[device] && hipSetDevice(device) == hipSuccess)
+      addr[device] = static_cast<char*>(oz_noalloc_scratch_address());
+    (void)hipGetLastError();
+    c->noalloc = addr[device];
+  }
   *out = c;
   return HSC_OK;
 }
@@ -2153,6 +2167,40 @@ hsc_status hsc_kern_zgemm_dd(hsc_ctx* ctx, int32_t config, int32_t opA, int32_t 
   (void)hipFree(dev);
   if (e1 != hipSuccess || e2 != hipSuccess) {
     set_error(std::string("HIP error in hsc_kern_zgemm_dd: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    return HSC_E_HIP;
+  }
+  return HSC_OK;
+}
+
+hsc_status hsc_kern_zgemm_dd_noalloc(hsc_ctx* ctx, int32_t opA, int32_t opB, int32_t M, int32_t N, int32_t K,
+                                     int32_t negate, const void* A, int32_t lda, const void* B, int32_t ldb,
+                                     int32_t beta, const void* C, int32_t ldc, void* D, int32_t ldd) {
+  if (!ctx || M < 0 || N < 0 || K < 0 || opA < 0 || opA > 1 || opB < 0 || opB > 1 || (beta != 0 && beta != 1) ||
+      (negate != 0 && negate != 1) || K > kOzMaxDepth) {
+    set_error("bad arguments to hsc_kern_zgemm_dd_noalloc");
+    return HSC_E_ARG;
+  }
+  const int a_cols = opA == OP_N ? K : M, b_cols = opB == OP_N ? N : K;
+  if ((K > 0 && M > 0 && (!A || lda < a_cols)) || (K > 0 && N > 0 && (!B || ldb < b_cols)) || !D ||
+      ldd < N || (beta && (!C || ldc < N))) {
+    set_error("bad pointer or leading dimension in hsc_kern_zgemm_dd_noalloc");
+    return HSC_E_ARG;
+  }
+  if (M == 0 || N == 0) return HSC_OK;
+  const size_t need = oz_noalloc_bytes(M, N, K);
+  if (need > kOzNoAllocScratch) {
+    set_error("hsc_kern_zgemm_dd_noalloc: the product needs " + std::to_string(need) + " bytes of scratch, more than the " +
+              std::to_string(kOzNoAllocScratch) + " of the static device array");
+    return HSC_E_ARG;
+  }
+  if (!ctx->noalloc) {
+    set_error("hsc_kern_zgemm_dd_noalloc: the scratch array's device address is unknown");
+    return HSC_E_HIP;
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  if (launch_oz_gemm_noalloc(ctx->stream, ctx->noalloc, opA, opB, M, N, K, negate, A, lda, B, ldb, beta, C, ldc, D,
+                             ldd) != 0) {
+    set_error("launch failed in hsc_kern_zgemm_dd_noalloc");
     return HSC_E_HIP;
   }
   return HSC_OK;

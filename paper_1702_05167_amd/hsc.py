@@ -78,6 +78,8 @@ def lib():
     L.hsc_kern_zgemm_tile.argtypes = [vp, i32, i32, i32, i32, i32, i32, dbl, dbl, vp, i32, vp, i32, i32, vp, i32, vp,
                                       i32]
     L.hsc_kern_zgemm_dd.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32, vp, i32, vp, i32, i32, vp, i32, vp, i32]
+    L.hsc_kern_zgemm_dd_noalloc.argtypes = [vp, i32, i32, i32, i32, i32, i32, vp, i32, vp, i32, i32, vp, i32, vp,
+                                            i32]
     L.hsc_kern_zinv_batched.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
     L.hsc_kern_zinv_dd.argtypes = [vp, i32, vp, i32, vp, i32, vp, i32]
     L.hsc_kern_mfma_probe.argtypes = [vp, vp]
@@ -95,7 +97,7 @@ def lib():
                  "hsc_tree_stats_get",
                  "hsc_tree_export", "hsc_tree_destroy", "hsc_solve", "hsc_solve_batch", "hsc_sync",
                  "hsc_ctx_profile", "hsc_ctx_profile_read", "hsc_ctx_profile_launches",
-                 "hsc_kern_zgemm", "hsc_kern_zgemm_tile", "hsc_kern_zgemm_dd",
+                 "hsc_kern_zgemm", "hsc_kern_zgemm_tile", "hsc_kern_zgemm_dd", "hsc_kern_zgemm_dd_noalloc",
                  "hsc_kern_zinv_batched",
                  "hsc_kern_zinv_dd",
                  "hsc_kern_mfma_probe",
@@ -378,6 +380,26 @@ def kern_zgemm_dd(ctx, opA, opB, A, B, negate=0, beta=0, C_=None, D=None, config
     check(lib().hsc_kern_zgemm_dd(ctx.h, config, opA, opB, M, N, K, negate, _dptr(A), A.stride(0) // 4,
                                   _dptr(B), B.stride(0) // 4, beta, _dptr(C_) if C_ is not None else None,
                                   C_.stride(0) // 4 if C_ is not None else 0, _dptr(D), D.stride(0) // 4))
+    return D
+
+
+def kern_zgemm_dd_noalloc(ctx, opA, opB, A, B, D, negate=0, beta=0, C_=None, sync=True):
+    """hsc_kern_zgemm_dd_noalloc: the config-3 double-double product into the caller's D, with the
+    library's static device scratch (no allocation, asynchronous; sync=True waits on the stream).
+    Tensors as in kern_zgemm_dd."""
+    M = A.shape[0] if opA == 0 else A.shape[1]
+    K = A.shape[1] if opA == 0 else A.shape[0]
+    N = B.shape[1] if opB == 0 else B.shape[0]
+    for t in (A, B, D) + ((C_,) if C_ is not None else ()):
+        if t.dim() != 3 or t.shape[2] != 4 or t.stride(2) != 1 or t.stride(1) != 4:
+            raise ValueError("double-double operands are (rows, cols, 4) tensors with contiguous elements")
+    if tuple(D.shape[:2]) != (M, N):
+        raise ValueError("D must be (M, N, 4)")
+    check(lib().hsc_kern_zgemm_dd_noalloc(ctx.h, opA, opB, M, N, K, negate, _dptr(A), A.stride(0) // 4, _dptr(B),
+                                          B.stride(0) // 4, beta, _dptr(C_) if C_ is not None else None,
+                                          C_.stride(0) // 4 if C_ is not None else 0, _dptr(D), D.stride(0) // 4))
+    if sync:
+        ctx.sync()
     return D
 
 
