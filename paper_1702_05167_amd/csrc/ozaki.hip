@@ -119,64 +119,72 @@ __device__ inline void oz_digits(dd y, uint32_t* word, int shift) {
   }
 }
 
-// Tile (64 rows from r0, 32 k from k0) of one job: each thread splits two quads of four
-// consecutive k, packs each quad's digits into one word per (part, slice), and the words go to
-// LDS in the order of the global planes, which the block then writes out 16 bytes per thread.
-// Global layout of a part / slice plane: fragments of 16 rows x 64 k (1 KB), row blocks of the
-// plane in order, each row block's 64-k steps in order; inside a fragment, byte 16 l + b holds
-// row l & 15, k = 16 (l >> 4) + b (the operand order of v_mfma_i32_16x16x64_i8).
+// Tile (64 rows from r0, 32 k from k0) of one job: each thread holds two quads of four
+// consecutive k; for each operand part in turn it packs each quad's digits into one word per
+// slice, the words go to LDS in the order of the global planes, and the block writes them out 16
+// bytes per thread.  Global layout of a part / slice plane: fragments of 16 rows x 64 k (1 KB),
+// row blocks of the plane in order, each row block's 64-k steps in order; inside a fragment,
+// byte 16 l + b holds row l & 15, k = 16 (l >> 4) + b (the operand order of
+// v_mfma_i32_16x16x64_i8).
 template <int S>
 __global__ __launch_bounds__(256) void k_oz_digits(const OzSplitJob* __restrict__ jobs,
                                                    const int32_t* __restrict__ tile_job) {
-  // [part][slice][row block of 16][lane 0..31 of the half fragment][4 words]
-  __shared__ uint32_t lw[3 * S * 4 * 32 * 4];
+  // [slice][row block of 16][lane 0..31 of the half fragment][4 words] of one part
+  __shared__ uint32_t lw[S * 4 * 32 * 4];
   const OzSplitJob& jb = jobs[tile_job[blockIdx.x]];
   const int local = blockIdx.x - jb.tile_off;
   const int nk = jb.Kp / 32;
   const int r0 = (local / nk) * 64, k0 = (local % nk) * 32;
   const int t = threadIdx.x;
   const bool kfast = jb.ldk == 1;
+  // the thread's elements, scaled by 2^(6 - e) (exact) and normalised: quad j, element u
+  dd xr[2][4], xi[2][4];
+  int rr[2], kq[2];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    // this thread's quad: row rr, k = 4 kq .. 4 kq + 3 (kq < 8)
-    const int rr = kfast ? (t >> 3) + 32 * j : (t & 63);
-    const int kq = kfast ? (t & 7) : (t >> 6) + 4 * j;
-    const int r = r0 + rr;
-    uint32_t wd[3][S];
-#pragma unroll
-    for (int p = 0; p < 3; ++p)
-#pragma unroll
-      for (int q = 0; q < S; ++q) wd[p][q] = 0;
-    const int e = r < jb.Rp ? jb.ex[r] : 0;
+    rr[j] = kfast ? (t >> 3) + 32 * j : (t & 63);
+    kq[j] = kfast ? (t & 7) : (t >> 6) + 4 * j;
+    const int r = r0 + rr[j];
+    const int sh = 6 - (r < jb.Rp ? jb.ex[r] : 0);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const zdd v = oz_elem(jb, r, k0 + 4 * kq + u);
-      const int sh = 6 - e;   // scale by 2^(6 - e): exact
+      const zdd v = oz_elem(jb, r, k0 + 4 * kq[j] + u);
       const dd nr = two_sum(v.re.hi, v.re.lo), ni = two_sum(v.im.hi, v.im.lo);
-      const dd xr{ldexp(nr.hi, sh), ldexp(nr.lo, sh)};
-      const dd xi{ldexp(ni.hi, sh), ldexp(ni.lo, sh)};
-      oz_digits<S>(xr, wd[0], 8 * u);
-      oz_digits<S>(xi, wd[1], 8 * u);
-      oz_digits<S>(dd_add(xr, xi), wd[2], 8 * u);
+      xr[j][u] = dd{ldexp(nr.hi, sh), ldexp(nr.lo, sh)};
+      xi[j][u] = dd{ldexp(ni.hi, sh), ldexp(ni.lo, sh)};
     }
-    // word (k % 16) / 4 of half-fragment lane (row & 15) + 16 ((k % 32) / 16), row block row / 16
-    const int kk = 4 * kq;
-    const int l = (rr & 15) + 16 * (kk >> 4), wq = (kk & 15) >> 2, rb = rr >> 4;
-#pragma unroll
-    for (int p = 0; p < 3; ++p)
-#pragma unroll
-      for (int q = 0; q < S; ++q) lw[((((p * S + q) * 4 + rb) * 32 + l) * 4) + wq] = wd[p][q];
   }
-  __syncthreads();
-  // write out: 16 bytes per (part, slice, row block, half-fragment lane)
   const int rbs = jb.Rp / 16, kcs = jb.Kp / 64, half = (k0 >> 5) & 1, kc = k0 >> 6;
   const uint4* src = reinterpret_cast<const uint4*>(lw);
-  for (int c = t; c < 3 * S * 4 * 32; c += 256) {
-    const int l = c & 31, rb = (c >> 5) & 3, ps = c >> 7;   // ps = part * S + slice
-    const int rbg = r0 / 16 + rb;
-    if (rbg >= rbs) continue;
-    uint4* dst = reinterpret_cast<uint4*>(jb.out + (((int64_t)ps * rbs + rbg) * kcs + kc) * 1024) + 32 * half + l;
-    *dst = src[c];
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      uint32_t wd[S];
+#pragma unroll
+      for (int q = 0; q < S; ++q) wd[q] = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const dd x = p == 0 ? xr[j][u] : p == 1 ? xi[j][u] : dd_add(xr[j][u], xi[j][u]);
+        oz_digits<S>(x, wd, 8 * u);
+      }
+      // word (k % 16) / 4 of half-fragment lane (row & 15) + 16 ((k % 32) / 16), row block row / 16
+      const int kk = 4 * kq[j];
+      const int l = (rr[j] & 15) + 16 * (kk >> 4), wq = (kk & 15) >> 2, rb = rr[j] >> 4;
+#pragma unroll
+      for (int q = 0; q < S; ++q) lw[(((q * 4 + rb) * 32 + l) * 4) + wq] = wd[q];
+    }
+    __syncthreads();
+    // write out: 16 bytes per (slice, row block, half-fragment lane)
+    for (int c = t; c < S * 4 * 32; c += 256) {
+      const int l = c & 31, rb = (c >> 5) & 3, q = c >> 7;
+      const int rbg = r0 / 16 + rb;
+      if (rbg >= rbs) continue;
+      uint4* dst = reinterpret_cast<uint4*>(jb.out + (((int64_t)(p * S + q) * rbs + rbg) * kcs + kc) * 1024) +
+                   32 * half + l;
+      *dst = src[c];
+    }
+    __syncthreads();
   }
 }
 
@@ -219,12 +227,22 @@ __device__ inline void oz_mma(const v4i* __restrict__ buf, int wm, int wn, int l
   }
 }
 
-// sum_d x_d 2^(-12 - 7 d) in double-double, smallest terms first (every term is exact)
+// sum_d x_d 2^(-12 - 7 d) in double-double: weights in groups of five summed exactly in int64
+// (|x_d| < 2^31, so x_d 2^(7 (last - d)) < 2^59 per group), each group split exactly into a
+// normalised double pair, groups added smallest first
 template <int S>
 __device__ inline dd oz_sum(const int (&x)[S]) {
   dd v{0.0, 0.0};
 #pragma unroll
-  for (int d = S - 1; d >= 0; --d) v = dd_add(v, dd{ldexp((double)x[d], -12 - 7 * d), 0.0});
+  for (int g0 = ((S - 1) / 5) * 5; g0 >= 0; g0 -= 5) {
+    const int g1 = g0 + 4 < S - 1 ? g0 + 4 : S - 1;
+    int64_t acc = 0;
+#pragma unroll
+    for (int d = g0; d <= g1; ++d) acc += (int64_t)x[d] * ((int64_t)1 << (7 * (g1 - d)));
+    const double hi = (double)acc;
+    const double lo = (double)(acc - (int64_t)hi);
+    v = dd_add(v, dd{ldexp(hi, -12 - 7 * g1), ldexp(lo, -12 - 7 * g1)});
+  }
   return v;
 }
 

@@ -202,6 +202,9 @@ struct Builder {
     size_t F, Inv, Psi, GX, GFF, GT, GAF, SD, piv, T, R;
     size_t Fd, Invd, Psid, Td, Rd;   // double-double fold
     size_t NF[2], NFc[2], M[2], PX[2], PFF[2], PT[2];
+    // 8-bit slices of operands used by several products (precision 3): Psi (rows n, depth f),
+    // Psi^T and A_ii^-1 of separators (rows f / n, depth n); 0 = none
+    size_t PsiS, PsiTS, InvS;
   };
   std::vector<CS> cs;   // [cluster * B + slot]
 
@@ -266,6 +269,11 @@ struct Builder {
           s.Td = wsa(n * std::max<size_t>(nbd, kDDSuper) * 32);
           s.Rd = wsa(std::max<size_t>(nbd, kDDSuper) * n * 32);
           if (!root(i)) s.Psid = wsa(n * f * 32);
+          if (oz && !root(i) && (int)f >= kOzMinK) s.PsiS = wsa(oz_bytes((int)n, (int)f));
+          if (oz && !root(i) && !leaf(i) && (int)n >= kOzMinK) {
+            s.PsiTS = wsa(oz_bytes((int)f, (int)n));
+            s.InvS = wsa(oz_bytes((int)n, (int)n));
+          }
         } else {
           s.F = wsa((n + f) * (n + f) * 16);
           s.T = wsa(n * 4 * nb * 16);   // panel T (n x nb) and super-panel U (n x 4 nb)
@@ -399,7 +407,10 @@ struct Builder {
   }
 
   // ---- step helpers ----
-  template <class T> struct GPT { const T *A, *B, *C; T* D; int M, N, K, lda, ldb, ldc, ldd; };
+  template <class T> struct GPT {
+    const T *A, *B, *C; T* D; int M, N, K, lda, ldb, ldc, ldd;
+    size_t sa = 0;   // workspace offset of op(A)'s slices when they are kept for other products (0: none)
+  };
   using GP = GPT<double2>;
   void gemm(int opA, int opB, const std::vector<GP>& ps, double ar, double ai, int beta) {
     Step s;
@@ -503,21 +514,36 @@ struct Builder {
   void gemm_x(int opA, int opB, const std::vector<GP>& ps, int beta) { gemm(opA, opB, ps, 1.0, 0.0, beta); }
   void gemm_x(int opA, int opB, const std::vector<GPT<zdd>>& ps, int beta) {
     std::vector<GPD> q;
-    for (const GPT<zdd>& g : ps) q.push_back({g.A, g.B, g.C, g.D, nullptr, g.M, g.N, g.K, g.lda, g.ldb, g.ldc, g.ldd, 0});
+    for (const GPT<zdd>& g : ps) q.push_back({g.A, g.B, g.C, g.D, nullptr, g.M, g.N, g.K, g.lda, g.ldb, g.ldc, g.ldd, 0,
+                                             g.sa});
     dd_gemm(opA, opB, q, 0, beta);
   }
 
-  struct GPD { const zdd *A, *B, *C; zdd* D; double2* D64; int M, N, K, lda, ldb, ldc, ldd, ldd64; };
+  struct GPD {
+    const zdd *A, *B, *C; zdd* D; double2* D64; int M, N, K, lda, ldb, ldc, ldd, ldd64;
+    size_t sa = 0;   // workspace offset of op(A)'s kept slices (0: split into the step's scratch)
+  };
+  std::vector<size_t> oz_kept;   // kept slice buffers already split by an earlier step
   // Double-double block products: with `oz`, every problem whose depth K lies in
-  // [kOzMinK, kOzMaxK] runs on the integer matrix cores (split + slice product); the others,
-  // and every product without `oz`, on the FP64 vector units.
+  // [kOzMinK, kOzMaxK] and whose estimated time (splitting + slice product) beats the vector units
+  // runs on the integer matrix cores; the others, and every product without `oz`, on the FP64
+  // vector units.
   static constexpr int kOzMinK = 32;
   static constexpr int kOzMaxK = 10880;   // int32 accumulators: 3 * 16 * 64^2 * Kp < 2^31
   static constexpr size_t kOzStepCap = size_t(4) << 30;   // slice scratch of one product step
+  // Measured costs on the target (seconds): splitting one complex double-double element into
+  // slices, one padded multiply-add of the slice product, one multiply-add on the vector units.
+  static constexpr double kOzSplitCost = 40e-12, kOzMacCost = 0.55e-12, kValuMacCost = 1.5e-12;
+  static bool oz_pays(const GPD& g) {
+    if (g.K < kOzMinK || g.K > kOzMaxK) return false;
+    const double Mp = oz_round(g.M, 32), Np = oz_round(g.N, 32), Kp = oz_round(g.K, 64);
+    const double t_oz = kOzSplitCost * ((g.sa ? 0.0 : Mp) + Np) * Kp + kOzMacCost * Mp * Np * Kp;
+    return t_oz < kValuMacCost * (double)g.M * g.N * g.K;
+  }
   void dd_gemm(int opA, int opB, const std::vector<GPD>& ps, int negate, int beta) {
     if (!oz) { dd_gemm_valu(opA, opB, ps, negate, beta); return; }
     std::vector<GPD> big, rest;
-    for (const GPD& g : ps) ((g.K >= kOzMinK && g.K <= kOzMaxK) ? big : rest).push_back(g);
+    for (const GPD& g : ps) (oz_pays(g) ? big : rest).push_back(g);
     if (!big.empty()) oz_gemm(opA, opB, big, negate, beta);
     if (!rest.empty()) dd_gemm_valu(opA, opB, rest, negate, beta);
   }
@@ -539,17 +565,30 @@ struct Builder {
       std::map<std::tuple<const void*, int64_t, int64_t, int, int>, std::pair<size_t, size_t>> seen;
       size_t cur = 0, i = i0;
       double flops = 0;
-      auto operand = [&](const zdd* X, int64_t ldr, int64_t ldk, int R, int K) {
+      // slices of one operand: in the step's scratch (offsets rebased later, `kept` false) or in a
+      // workspace buffer kept for later products (absolute addresses, split by the first step using it)
+      std::vector<char> kept_job;   // per split job: writes a kept buffer
+      auto operand = [&](const zdd* X, int64_t ldr, int64_t ldk, int R, int K, size_t keep) {
         const auto key = std::make_tuple((const void*)X, ldr, ldk, R, K);
         auto it = seen.find(key);
         if (it != seen.end()) return it->second;
         const int Rp = (int)oz_round(R, 32), Kp = (int)oz_round(K, 64);
-        const size_t off = cur;
-        cur += oz_bytes(R, K);
+        size_t off;
+        if (keep) {
+          off = reinterpret_cast<size_t>(wsbase + keep);
+          const auto r = std::make_pair(off, off + (size_t)3 * kOzSlices * Rp * Kp);
+          seen[key] = r;
+          if (std::find(oz_kept.begin(), oz_kept.end(), keep) != oz_kept.end()) return r;
+          oz_kept.push_back(keep);
+        } else {
+          off = cur;
+          cur += oz_bytes(R, K);
+        }
         OzSplitJob j{};
         j.X = X; j.ldr = ldr; j.ldk = ldk; j.R = R; j.K = K; j.Rp = Rp; j.Kp = Kp;
         j.out = reinterpret_cast<int8_t*>(off);
         j.ex = reinterpret_cast<int32_t*>(off + (size_t)3 * kOzSlices * Rp * Kp);
+        kept_job.push_back(keep ? 1 : 0);
         const int rblocks = (Rp + 63) / 64;
         j.blk_off = (int32_t)bmap.size();
         for (int b = 0; b < rblocks; ++b) bmap.push_back((int32_t)sj.size());
@@ -560,13 +599,15 @@ struct Builder {
         seen[key] = r;
         return r;
       };
+      std::vector<char> kept_a;   // per product: A's slices in a kept buffer
       for (; i < ps.size(); ++i) {
         const GPD& g = ps[i];
         if (g.M <= 0 || g.N <= 0) continue;
-        const size_t need = oz_bytes(g.M, g.K) + oz_bytes(g.N, g.K);
+        const size_t need = (g.sa ? 0 : oz_bytes(g.M, g.K)) + oz_bytes(g.N, g.K);
         if (i > i0 && cur + need > kOzStepCap) break;
-        const auto a = opA == 0 ? operand(g.A, g.lda, 1, g.M, g.K) : operand(g.A, 1, g.lda, g.M, g.K);
-        const auto b = opB == 0 ? operand(g.B, 1, g.ldb, g.N, g.K) : operand(g.B, g.ldb, 1, g.N, g.K);
+        const auto a = opA == 0 ? operand(g.A, g.lda, 1, g.M, g.K, g.sa) : operand(g.A, 1, g.lda, g.M, g.K, g.sa);
+        const auto b = opB == 0 ? operand(g.B, 1, g.ldb, g.N, g.K, 0) : operand(g.B, g.ldb, 1, g.N, g.K, 0);
+        kept_a.push_back(g.sa ? 1 : 0);
         GemmProbOZ p{};
         p.A8 = reinterpret_cast<const int8_t*>(a.first);
         p.ea = reinterpret_cast<const int32_t*>(a.second);
@@ -589,6 +630,7 @@ struct Builder {
         s.kind = S_OZ_SPLIT;
         s.jobs = blob.push(sj);
         for (size_t q = 0; q < sj.size(); ++q) {
+          if (kept_job[q]) continue;
           blob.sc_relocs.push_back(s.jobs + q * sizeof(OzSplitJob) + offsetof(OzSplitJob, out));
           blob.sc_relocs.push_back(s.jobs + q * sizeof(OzSplitJob) + offsetof(OzSplitJob, ex));
         }
@@ -604,8 +646,10 @@ struct Builder {
         s.jobs = blob.push(gp);
         for (size_t q = 0; q < gp.size(); ++q) {
           const size_t b0 = s.jobs + q * sizeof(GemmProbOZ);
-          blob.sc_relocs.push_back(b0 + offsetof(GemmProbOZ, A8));
-          blob.sc_relocs.push_back(b0 + offsetof(GemmProbOZ, ea));
+          if (!kept_a[q]) {
+            blob.sc_relocs.push_back(b0 + offsetof(GemmProbOZ, A8));
+            blob.sc_relocs.push_back(b0 + offsetof(GemmProbOZ, ea));
+          }
           blob.sc_relocs.push_back(b0 + offsetof(GemmProbOZ, B8));
           blob.sc_relocs.push_back(b0 + offsetof(GemmProbOZ, eb));
         }
@@ -752,7 +796,7 @@ struct Builder {
         const int n = n_of(i), f = f_of(i), ld = n + f;
         for (int e = 0; e < B; ++e) {
           const CS& s = cs[(size_t)i * B + e];
-          pp.push_back({Z(s.Invd), Z(s.Fd) + n, nullptr, Z(s.Psid), W(s.Psi), n, f, n, n, ld, 0, f, f});
+          pp.push_back({Z(s.Invd), Z(s.Fd) + n, nullptr, Z(s.Psid), W(s.Psi), n, f, n, n, ld, 0, f, f, s.InvS});
           pu.push_back({Z(s.Fd) + n, Z(s.Psid), Z(s.Fd) + (size_t)n * ld + n, Z(s.Fd) + (size_t)n * ld + n, nullptr,
                         f, f, n, ld, f, ld, ld, 0});
         }
@@ -939,14 +983,15 @@ struct Builder {
             q.j.rmap = off32(c_rel[i]);
             q.j.cmap = cp(i) ? nullptr : off32(c_gcol[i]);
             g1.push_back(q);
-            m1.push_back({psi_p<T>(s), X<T>(s.GX) + (size_t)n * gc + n, nullptr, X<T>(s.GX) + n, n, gc - n, f, f, gc, 0, gc});
+            m1.push_back({psi_p<T>(s), X<T>(s.GX) + (size_t)n * gc + n, nullptr, X<T>(s.GX) + n, n, gc - n, f, f, gc, 0, gc,
+                          s.PsiS});
             RJ tq{};
             tq.j.rows = f; tq.j.cols = n; tq.j.e = e;
             tq.j.src = d2(X<T>(s.GX)); tq.j.lds = gc;
             tq.j.dst = d2(X<T>(s.GX) + (size_t)n * gc); tq.j.ldd = gc;
             tq.j.rmap = off32(c_trow[i]);
             g2.push_back(tq);
-            m2.push_back({psi_p<T>(s), X<T>(s.GX) + (size_t)n * gc, inv_p<T>(s), X<T>(s.GX), n, n, f, f, gc, n, gc});
+            m2.push_back({psi_p<T>(s), X<T>(s.GX) + (size_t)n * gc, inv_p<T>(s), X<T>(s.GX), n, n, f, f, gc, n, gc, s.PsiS});
           }
         }
         rowstep(S_GATHER, g1, 0, 0, 0, kDD<T>);
@@ -974,7 +1019,7 @@ struct Builder {
             q.j.rmap = off32(c_rel[i]);
             q.j.cmap = off32(c_gcol[i]);
             g1.push_back(q);
-            m1.push_back({psi_p<T>(s), X<T>(s.GFF), nullptr, X<T>(s.GT), n, f, f, f, f, 0, f});
+            m1.push_back({psi_p<T>(s), X<T>(s.GFF), nullptr, X<T>(s.GT), n, f, f, f, f, 0, f, s.PsiS});
             if (cp(i)) {
               RJ a{};
               a.j.rows = f; a.j.cols = P; a.j.e = e;
@@ -1036,14 +1081,16 @@ struct Builder {
           asm_jobs.push_back(q);
           if (!root(i)) {
             nu.push_back({psi_p<T>(s) + (size_t)row0 * f, X<T>(s.NF[k]) + n, X<T>(s.NF[k]) + (size_t)r * (n + P) + n,
-                          X<T>(s.NF[k]) + (size_t)r * (n + P) + n, f, P, r, f, n + P, n + P, n + P});
+                          X<T>(s.NF[k]) + (size_t)r * (n + P) + n, f, P, r, f, n + P, n + P, n + P,
+                          (row0 == 0 && r == n) ? s.PsiTS : 0});
             RJ g{};
             g.j.rows = r; g.j.cols = n + f; g.j.e = e;
             g.j.src = d2(X<T>(s.NF[k])); g.j.lds = n + P;
             g.j.dst = d2(X<T>(s.NFc[k])); g.j.ldd = n + f;
             g.j.cmap = off32(c_nfc[i]);
             nfc_jobs.push_back(g);
-            mm.push_back({inv_p<T>(s) + row0, X<T>(s.NFc[k]), nullptr, X<T>(s.M[k]), n, n + f, r, n, n + f, 0, n + f});
+            mm.push_back({inv_p<T>(s) + row0, X<T>(s.NFc[k]), nullptr, X<T>(s.M[k]), n, n + f, r, n, n + f, 0, n + f,
+                          (row0 == 0 && r == n) ? s.InvS : 0});
           } else {
             mm.push_back({inv_p<T>(s) + row0, X<T>(s.NF[k]), nullptr, X<T>(s.M[k]), n, n, r, n, n, 0, n});
           }
@@ -1079,7 +1126,7 @@ struct Builder {
           q.j.rmap = off32(c_rel[i]); q.j.cmap = off32(c_rel[i]);
           g1.push_back(q);
           GPT<T> a{psi_p<T>(s), X<T>(s.PX[k]) + (size_t)n * ld + n, fm ? X<T>(s.M[k]) + n : nullptr, X<T>(s.PX[k]) + n, n, f, f, f,
-               ld, ld, ld};
+               ld, ld, ld, s.PsiS};
           (fm ? m1b : m1a).push_back(a);
           RJ tq{};
           tq.j.rows = f; tq.j.cols = n; tq.j.e = e;
@@ -1087,7 +1134,8 @@ struct Builder {
           tq.j.dst = d2(X<T>(s.PX[k]) + (size_t)n * ld); tq.j.ldd = ld;
           tq.j.rmap = off32(c_trowp[i]);
           g2.push_back(tq);
-          GPT<T> b{psi_p<T>(s), X<T>(s.PX[k]) + (size_t)n * ld, fm ? X<T>(s.M[k]) : nullptr, X<T>(s.PX[k]), n, n, f, f, ld, ld, ld};
+          GPT<T> b{psi_p<T>(s), X<T>(s.PX[k]) + (size_t)n * ld, fm ? X<T>(s.M[k]) : nullptr, X<T>(s.PX[k]), n, n, f, f, ld, ld, ld,
+                   s.PsiS};
           (fm ? m2b : m2a).push_back(b);
         }
       }
@@ -1104,7 +1152,8 @@ struct Builder {
           q.j.dst = d2(X<T>(s.PFF[k])); q.j.ldd = f;
           q.j.rmap = off32(c_rel[i]); q.j.cmap = off32(c_rel[i]);
           g3.push_back(q);
-          GPT<T> a{psi_p<T>(s), X<T>(s.PFF[k]), fm ? X<T>(s.M[k]) + n : nullptr, X<T>(s.PT[k]), n, f, f, f, f, n + f, f};
+          GPT<T> a{psi_p<T>(s), X<T>(s.PFF[k]), fm ? X<T>(s.M[k]) + n : nullptr, X<T>(s.PT[k]), n, f, f, f, f, n + f, f,
+                   s.PsiS};
           (fm ? m3b : m3a).push_back(a);
         }
       }
@@ -1479,6 +1528,7 @@ size_t plan_bytes_per_slot(const hsc_tree* t, uint32_t want, int prec) {
   Builder b{t, 1, want, (want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR)) != 0};
   b.ddf = prec >= 1;
   b.ddx = prec >= 2;
+  b.oz = prec == 3;
   b.channels();
   b.layout();
   return b.ws;
