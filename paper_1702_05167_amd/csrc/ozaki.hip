@@ -48,6 +48,7 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int OZ_TILE = 32;   // rows and columns of the output tile of one workgroup
 constexpr int OZ_KC = 64;     // k depth of one matrix-core step (v_mfma_i32_16x16x64_i8)
+constexpr int OZ_GROUP = 8;   // tile rows per group of the tile order
 
 // ---------------------------------------------------------------------------------------------
 // splitting, in two launches: row scales (64 rows per workgroup), then digits (tiles of 64 rows x
@@ -256,7 +257,12 @@ __global__ __launch_bounds__(256) void k_oz_gemm(const GemmProbOZ* __restrict__ 
   if (tile >= total_tiles) return;
   const GemmProbOZ& pr = probs[tile_prob[tile]];
   const int local = tile - pr.tile_off;
-  const int m0 = (local / pr.tiles_n) * OZ_TILE, n0 = (local % pr.tiles_n) * OZ_TILE;
+  // tiles of a problem in groups of OZ_GROUP tile rows, column by column inside a group: the tiles
+  // an XCD runs at once share a few row and column blocks of the slices in its L2
+  const int tm = pr.Mp / OZ_TILE, tn = pr.tiles_n;
+  const int grp = local / (OZ_GROUP * tn), idx = local % (OZ_GROUP * tn);
+  const int rows = min(OZ_GROUP, tm - grp * OZ_GROUP);
+  const int m0 = (grp * OZ_GROUP + idx % rows) * OZ_TILE, n0 = (idx / rows) * OZ_TILE;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wm = w >> 1, wn = w & 1;
 
