@@ -491,7 +491,7 @@ __global__ __launch_bounds__(RB) void k_dd_diag(const RowJob* __restrict__ jobs,
 int dd_gemm_configs() { return kDDConfigs; }
 int dd_gemm_tile_m(int config) { return 16 * kDDRM[config]; }
 int dd_gemm_tile_n(int config) { return 16 * kDDRN[config]; }
-int dd_inv_nb(int max_n) { return max_n <= 512 ? 8 : max_n <= 1024 ? 8 : max_n <= 2048 ? 4 : 2; }
+int dd_inv_nb(int max_n) { return max_n <= 1024 ? 8 : max_n <= 2048 ? 4 : 2; }
 
 void launch_dd_gemm(hipStream_t st, int opA, int opB, int config, const GemmProbDD* probs,
                     const int32_t* tile_prob, int total_tiles, int negate, int beta) {

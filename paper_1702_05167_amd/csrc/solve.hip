@@ -533,7 +533,7 @@ struct Builder {
   static constexpr size_t kOzStepCap = size_t(4) << 30;   // slice scratch of one product step
   // Measured costs on the target (seconds): splitting one complex double-double element into
   // slices, one padded multiply-add of the slice product, one multiply-add on the vector units.
-  static constexpr double kOzSplitCost = 40e-12, kOzMacCost = 0.55e-12, kValuMacCost = 1.5e-12;
+  static constexpr double kOzSplitCost = 25e-12, kOzMacCost = 0.55e-12, kValuMacCost = 1.5e-12;
   static bool oz_pays(const GPD& g) {
     if (g.K < kOzMinK || g.K > kOzMaxK) return false;
     const double Mp = oz_round(g.M, 32), Np = oz_round(g.N, 32), Kp = oz_round(g.K, 64);
