@@ -476,9 +476,23 @@ def learned_grid_study(pkg, synth, np):
         it = dict(tree=pkg.Tree.from_device(dev, leaf_side=4, transverse=True), n_sites=dev.n, sigma=0.3, nx=32, ny=32)
         r = lg.study(ctx, sur, it, cand, 512, (-2.0, 2.0), budget=64)
         r["seed"] = seed
+        # solves needed to reach the 1e-4 charge tolerance: guided (proposal + refinement), the same
+        # refinement from evenly spaced points, evenly spaced in-band points, and the plain grid
+        ec = lg.equal_cost(ctx, sur, it, cand, (-2.0, 2.0), (64, 96, 128, 192, 256, 384, 512, 768))
+        r["equal_cost"] = ec
+        plain = {}
+        for K in (64, 128, 256, 512, 1024, 2048):
+            g = np.arange(0, cand.size, max(cand.size // K, 1))
+            e = lg.Integrator(ctx, it["tree"], it["n_sites"], cand, (-2.0, 2.0))
+            q = e.charge(g)
+            plain[K] = {"in_band_solves": e.cost(g), "rel_err": abs(q - r["dense"]["charge"]) / abs(r["dense"]["charge"])}
+        r["plain_grid"] = plain
+        ok_plain = [v["in_band_solves"] for v in plain.values() if v["rel_err"] <= 1e-4]
+        r["solves_to_1e-4"] = dict(ec["solves_to_tol"], plain=min(ok_plain) if ok_plain else None)
         runs.append(r)
         note(f"device seed {seed}: guided {r['guided']['rel_err']:.2e} ({r['guided']['solves']} solves), "
-             f"uniform {r['uniform']['rel_err']:.2e} ({r['uniform']['solves']}), dense {r['dense']['solves']} solves")
+             f"uniform {r['uniform']['rel_err']:.2e} ({r['uniform']['solves']}), dense {r['dense']['solves']} solves; "
+             f"solves to 1e-4: {r['solves_to_1e-4']}")
     worst = max(r["guided"]["rel_err"] for r in runs)
     line = {"metric": "learned energy grid: charge error vs dense grid (32^3, sigma 0.3, 3 devices)",
             "value": worst, "unit": "relative error", "higher_is_better": False, "n_gpus": 1,

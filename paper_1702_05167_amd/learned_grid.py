@@ -246,6 +246,61 @@ def predicted_integrand(surrogate, item, cand, kT=0.025, mu_L=0.1, mu_R=-0.1):
     return np.exp(pred[:, 0]) * item["n_sites"] * 0.5 * (fermi(cand, mu_L, kT) + fermi(cand, mu_R, kT))
 
 
+def equal_cost(ctx, surrogate, item, cand, support, totals_, refine_frac=0.25, tol_rel=1e-4, kT=0.025, mu_L=0.1,
+               mu_R=-0.1, floor=1.0):
+    """Charge errors at equal numbers S of in-support solves (S in totals_), every grid judged by
+    the solver:
+      guided          S (1 - refine_frac) points from the surrogate's proposal, then the worst
+                      intervals of the solved values split until S solves are spent;
+      uniform_refined the same refinement from S (1 - refine_frac) evenly spaced points (the method
+                      without the network);
+      uniform         S evenly spaced points in the support (the plain grid).
+    Returns the per-S errors and, per method, the fewest solves among totals_ that reach tol_rel."""
+    cand = np.asarray(cand, dtype=np.float64)
+    integ = Integrator(ctx, item["tree"], item["n_sites"], cand, support, kT=kT, mu_L=mu_L, mu_R=mu_R)
+    inside = integ.inside
+    q_dense = integ.charge(inside)
+    g = predicted_integrand(surrogate, item, cand[inside], kT, mu_L, mu_R)
+
+    def uniform_in(k):
+        return inside[np.unique(np.round(np.linspace(0, inside.size - 1, k)).astype(int))]
+
+    def err(idx):
+        return abs(integ.charge(idx) - q_dense) / abs(q_dense)
+
+    rows = []
+    for S in totals_:
+        if S >= inside.size:
+            continue
+        K0 = max(3, int(round(S * (1.0 - refine_frac))))
+        gi = inside[proposal(cand[inside], g, K0, floor=floor)]
+        gi, _ = integ.refine(gi, 0.0, S - integ.cost(gi))
+        ui = uniform_in(K0)
+        ui, _ = integ.refine(ui, 0.0, S - integ.cost(ui))
+        un = uniform_in(S)
+        rows.append({"solves": S, "guided": err(gi), "guided_solves": integ.cost(gi),
+                     "uniform_refined": err(ui), "uniform_refined_solves": integ.cost(ui),
+                     "uniform": err(un), "uniform_solves": integ.cost(un)})
+
+    def first(key):
+        ok = [r["solves"] for r in rows if r[key] <= tol_rel]
+        return min(ok) if ok else None
+
+    def stays(key):
+        # fewest solves from which every larger budget of the sweep stays within tol_rel (the
+        # error of a grid over a spiky integrand is not monotone in its size)
+        s = None
+        for r in reversed(rows):
+            if r[key] > tol_rel:
+                break
+            s = r["solves"]
+        return s
+
+    keys = ("guided", "uniform_refined", "uniform")
+    return {"dense_solves": int(inside.size), "rows": rows, "tol_rel": tol_rel,
+            "solves_to_tol": {k: stays(k) for k in keys}, "first_within_tol": {k: first(k) for k in keys}}
+
+
 def study(ctx, surrogate, item, cand, K, support, budget=64, tol_rel=1e-4, kT=0.025, mu_L=0.1, mu_R=-0.1,
           sweep=(16, 24, 32, 48, 64, 96, 128, 256)):
     """Charge of one device on several grids of the candidate energies, all judged by the solver:
