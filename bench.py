@@ -157,6 +157,9 @@ def main():
                     help="measure the 40,020-site trilayer x 512 energies instead, with its error")
     ap.add_argument("--learned-grid", action="store_true",
                     help="measure the learned energy grid instead (surrogate training + charge on 3 devices)")
+    ap.add_argument("--guard-study", action="store_true",
+                    help="measure the complex128 solve with the growth guard instead (256 energies in chunks of 32, "
+                         "3D tree, leaf 8, tau 100), with its error at the stored energies")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run one elementwise device copy of MIB MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -179,6 +182,9 @@ def main():
         return
     if args.trilayer:
         trilayer_study(pkg, synth, np, torch, args)
+        return
+    if args.guard_study:
+        guard_study(pkg, synth, np, torch, args)
         return
 
     if args.calibrate_copy > 0:
@@ -403,6 +409,36 @@ def trilayer_study(pkg, synth, np, torch, args):
                                  "flops_per_energy": tree.stats()["flops_per_energy"],
                                  "gr_rel_err_at_stored_energies": errs}}),
           flush=True)
+
+
+def guard_study(pkg, synth, np, torch, args):
+    """32^3 cube, 256 energies in [-6, 6], complex128 on the matrix cores (precision 0) on the 3D tree
+    (leaf 8) with the growth guard (tau 100, up to 8 rounds of merges), in chunks of 32 energies with
+    a progress line each; error at the stored oracle energies."""
+    dev = synth.config1_device()
+    tree = pkg.Tree.from_device(dev, leaf_side=8)
+    ctx = pkg.Context(0)
+    grid = np.linspace(-6.0, 6.0, 256)
+    E = torch.tensor(grid, dtype=torch.float64, device="cuda:0")
+    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=0, complex3m=args.complex3m, tune=0,
+              want=pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS, guard=True, guard_tau=100.0, guard_rounds=8)
+    t0 = time.perf_counter()
+    gr, gl, tr, stv = [], [], [], []
+    for c in range(0, 256, 32):
+        o = pkg.solve(ctx, tree, E[c:c + 32], **kw)
+        gr.append(o["gr"].cpu().numpy()); gl.append(o["gl"].cpu().numpy()); tr.append(o["trans"].cpu().numpy())
+        stv.append(o["status"].cpu().numpy())
+        note(f"guarded energies {c}..{c + 31} done, {time.perf_counter() - t0:.1f} s, "
+             f"unstable {int((stv[-1] == -7).sum())}")
+    dt = time.perf_counter() - t0
+    gr, gl, tr, stv = (np.concatenate(x) for x in (gr, gl, tr, stv))
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "cube32_sampled.json")))
+    idx = gold["energy_index"]
+    acc = golden_errors(np, gold, gr[idx], gl[idx], tr[idx])
+    print(json.dumps({"metric": "guarded complex128 solve, 32^3 x 256 energies", "value": 256 / dt,
+                      "unit": "energies/s", "higher_is_better": True, "n_gpus": 1, "dtype": "c128", "data": "synthetic",
+                      "config": {"seconds": dt, "unstable": int((stv == -7).sum()), "failed": int((stv < 0).sum()),
+                                 "accuracy_vs_oracle": acc}}), flush=True)
 
 
 def uneven_study(pkg, synth, np, torch, args):

@@ -158,6 +158,8 @@ struct hsc_ctx {
   double prof[24][3] = {};                        // kind -> launches, ms, flops (24 >= number of kinds)
   hipStream_t cap_stream = nullptr;               // graph capture (a stream of its own, default priority)
   std::vector<double> launch_log;                 // (kind, flops, ms, phase) per timed launch since profiling was enabled
+  // merged trees of the growth guard: key (tree uid, merged cluster ids), most recent last
+  std::vector<std::pair<std::vector<int64_t>, std::shared_ptr<hsc_tree>>> guard_trees;
   // forest of the last multi-device batch and its output staging
   std::vector<uint64_t> forest_key;
   hsc_tree* forest = nullptr;
@@ -1701,15 +1703,22 @@ static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
 }
 
 // Growth guard: re-solve flagged energies on merged trees (delayed pivots).
-// Energies are grouped by (current tree, set of flagged clusters); each group
-// merges its flagged clusters into their parents (never beyond the dense-block
-// limit) and is solved again, until no block is flagged or the rounds run out.
+// Each round, the flagged energies of one tree are grouped by their set of
+// flagged clusters, and each group is solved again on a tree in which those
+// clusters are merged into their parents (never beyond the dense-block limit).
+// When one tree has more than kGuardSets different sets in a round, its energies
+// are solved together on one tree merging the union of their sets instead: one
+// plan per round and tree however many energies are flagged.  Merged trees (and
+// so their plans) are kept in the context, keyed by the tree and the merged
+// clusters, for later calls.  Rounds repeat until no block is flagged or the
+// rounds run out.
 namespace {
 struct GuardItem {
   int e;                                   // index into the caller's arrays
   std::shared_ptr<hsc_tree> tree;          // null: the caller's tree
   std::vector<int> bad;                    // flagged clusters of that tree
 };
+constexpr int kGuardSets = 8;
 // flagged clusters: ||Psi_i||_inf above tau (the extract multiplies rounding
 // errors of G_ff by Psi on both sides)
 std::vector<int> flagged(const double* g, int nc, double tau) {
@@ -1737,19 +1746,32 @@ static hsc_status guard_loop(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
   }
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   for (int round = 0; round < opts->guard_rounds && !items.empty(); ++round) {
-    // group by (tree, flagged set)
+    // group by (tree, flagged set); a tree with more than kGuardSets sets: one group, union of the sets
     std::sort(items.begin(), items.end(), [](const GuardItem& a, const GuardItem& b) {
       if (a.tree.get() != b.tree.get()) return a.tree.get() < b.tree.get();
       return a.bad < b.bad;
     });
+    std::vector<char> unite(items.size(), 0);
+    for (size_t t0 = 0; t0 < items.size();) {
+      size_t t1 = t0;
+      int sets = 0;
+      for (; t1 < items.size() && items[t1].tree.get() == items[t0].tree.get(); ++t1)
+        if (t1 == t0 || items[t1].bad != items[t1 - 1].bad) ++sets;
+      if (sets > kGuardSets)
+        for (size_t q = t0; q < t1; ++q) unite[q] = 1;
+      t0 = t1;
+    }
     std::vector<GuardItem> next;
     for (size_t g0 = 0; g0 < items.size();) {
       size_t g1 = g0;
-      while (g1 < items.size() && items[g1].tree.get() == items[g0].tree.get() && items[g1].bad == items[g0].bad) ++g1;
+      while (g1 < items.size() && items[g1].tree.get() == items[g0].tree.get() &&
+             (unite[g0] || items[g1].bad == items[g0].bad))
+        ++g1;
       const hsc_tree* t = items[g0].tree ? items[g0].tree.get() : tree;
       // merge the flagged clusters, parents first, within the block-size limit
       std::vector<char> mark(t->cl.size(), 0);
-      for (int i : items[g0].bad) mark[i] = 1;
+      for (size_t q = g0; q < g1; ++q)
+        for (int i : items[q].bad) mark[i] = 1;
       std::vector<int64_t> size(t->cl.size());
       for (size_t i = 0; i < t->cl.size(); ++i) size[i] = t->cl[i].n;
       std::vector<int32_t> ids;
@@ -1767,10 +1789,27 @@ static hsc_status guard_loop(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
         g0 = g1;
         continue;
       }
-      hsc_tree* m = nullptr;
-      hsc_status rc = hsc_tree_merge(t, (int32_t)ids.size(), ids.data(), &m);
-      if (rc != HSC_OK) return rc;
-      std::shared_ptr<hsc_tree> mt(m, hsc_tree_destroy);
+      std::vector<int64_t> key{(int64_t)t->uid};
+      key.insert(key.end(), ids.begin(), ids.end());
+      std::shared_ptr<hsc_tree> mt;
+      for (size_t c = 0; c < ctx->guard_trees.size(); ++c)
+        if (ctx->guard_trees[c].first == key) {
+          mt = ctx->guard_trees[c].second;
+          auto kept = ctx->guard_trees[c];
+          ctx->guard_trees.erase(ctx->guard_trees.begin() + c);
+          ctx->guard_trees.push_back(kept);
+          break;
+        }
+      hsc_status rc = HSC_OK;
+      if (!mt) {
+        hsc_tree* mm = nullptr;
+        rc = hsc_tree_merge(t, (int32_t)ids.size(), ids.data(), &mm);
+        if (rc != HSC_OK) return rc;
+        mt = std::shared_ptr<hsc_tree>(mm, hsc_tree_destroy);
+        ctx->guard_trees.push_back({key, mt});
+        while (ctx->guard_trees.size() > 4) ctx->guard_trees.erase(ctx->guard_trees.begin());
+      }
+      hsc_tree* m = mt.get();
       const int nc = (int)m->cl.size();
       const int k = (int)(g1 - g0);
       std::vector<double> eh(k);
@@ -1810,10 +1849,6 @@ static hsc_status guard_loop(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
         std::vector<int> b = flagged(&gk[(size_t)q * nc * 2], nc, opts->guard_tau);
         if (!b.empty()) next.push_back({items[g0 + q].e, mt, b});
       }
-      const uint64_t uid = m->uid;   // merged plans are temporary
-      ctx->plans.erase(std::remove_if(ctx->plans.begin(), ctx->plans.end(),
-                                      [&](const std::unique_ptr<Plan>& p) { return p->uid == uid; }),
-                       ctx->plans.end());
       g0 = g1;
     }
     items.swap(next);
