@@ -10,6 +10,8 @@ Modules:
 
 * ``negf``    -- lead self-energy (closed-form 1D chain), broadening, Fermi
                  function, and the per-energy quantities built from them.
+* ``face``    -- DENSE contact self-energy of a whole face (lead continuing the
+                 face lattice), and Sancho-Rubio decimation as its independent check.
 * ``dense``   -- the definition itself: dense partial-pivot LU inverse (small n).
 * ``rgf``     -- slab-wise recursive Green's function sweeps (Section 2.1), for
                  mid sizes.
@@ -21,4 +23,4 @@ Modules:
 Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s CPU-baseline leg
 may import this package.  The GPU path never does: it shares no code with it.
 """
-from . import negf, dense, rgf, sampled, mlp  # noqa: F401
+from . import negf, face, dense, rgf, sampled, mlp  # noqa: F401

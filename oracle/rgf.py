@@ -14,13 +14,16 @@ left-/right-connected recurrences are used:
 
 From the column blocks: A_L,ii = sum_{k in L} Gamma_L,k |G_ik|^2 (slab 0),
 A_R,ii likewise with slab N, and T = sum_{k in L} Gamma_L,k A_R,kk.
-Contacts must lie in the first (left) and last (right) layer.
+Contacts must lie in the first (left) and last (right) layer.  With dense=True
+the contacts are whole faces with the dense blocks of face.face_sigma
+(Gamma_c = V_c V_c^T): A_c,ii = ||G_i,c V_c||^2 and T = ||V_L^T G_0N V_R||_F^2.
 """
 from __future__ import annotations
 
 import numpy as np
 
 from .negf import contact_sigmas, gamma_of, fermi
+from .face import face_sigma
 
 
 def _layers(dev):
@@ -30,7 +33,7 @@ def _layers(dev):
     return [order[bounds[k]:bounds[k + 1]] for k in range(x.max() + 1)]
 
 
-def solve(dev, energies, eta, kT, mu_L, mu_R):
+def solve(dev, energies, eta, kT, mu_L, mu_R, dense=False):
     energies = np.asarray(energies, dtype=np.float64)
     ne, n = len(energies), dev.n
     layers = _layers(dev)
@@ -56,14 +59,20 @@ def solve(dev, energies, eta, kT, mu_L, mu_R):
     fr = fermi(energies, mu_R, kT)
     for e, en in enumerate(energies):
         z = en + 1j * eta
-        (ls, sl), (rs, sr) = contact_sigmas(dev, z)
         diag = []
         for k in range(nl):
             d = -hb[k, k].astype(np.complex128)
             d[np.diag_indices(len(layers[k]))] += z
             diag.append(d)
-        diag[0][pos[ls], pos[ls]] -= sl
-        diag[nl - 1][pos[rs], pos[rs]] -= sr
+        if dense:
+            ls, rs = np.asarray(left, dtype=np.int64), np.asarray(right, dtype=np.int64)
+            (s_l, v_l), (s_r, v_r) = face_sigma(dev, 0, z), face_sigma(dev, 1, z)
+            diag[0][np.ix_(pos[ls], pos[ls])] -= s_l
+            diag[nl - 1][np.ix_(pos[rs], pos[rs])] -= s_r
+        else:
+            (ls, sl), (rs, sr) = contact_sigmas(dev, z)
+            diag[0][pos[ls], pos[ls]] -= sl
+            diag[nl - 1][pos[rs], pos[rs]] -= sr
         off = {key: -v for key, v in hb.items() if key[0] != key[1]}   # A_ab = -H_ab
         gl = [None] * nl
         gl[0] = np.linalg.inv(diag[0])
@@ -85,6 +94,16 @@ def solve(dev, energies, eta, kT, mu_L, mu_R):
         col_l[0] = gr[0]
         for k in range(1, nl):
             col_l[k] = -gr[k] @ off[k, k - 1] @ col_l[k - 1]
+        if dense:
+            for k in range(nl):
+                s = layers[k]
+                out["gr"][e, s] = np.diag(gdiag[k])
+                out["a_l"][e, s] = (np.abs(col_l[k][:, pos[ls]] @ v_l) ** 2).sum(axis=1)
+                out["a_r"][e, s] = (np.abs(col_r[k][:, pos[rs]] @ v_r) ** 2).sum(axis=1)
+            g_lr = col_r[0][np.ix_(pos[ls], pos[rs])]
+            out["trans"][e] = (np.abs(v_l.T @ g_lr @ v_r) ** 2).sum()
+            out["gl"][e] = 1j * (fl[e] * out["a_l"][e] + fr[e] * out["a_r"][e])
+            continue
         gam_l, gam_r = gamma_of(sl), gamma_of(sr)
         for k in range(nl):
             s = layers[k]
