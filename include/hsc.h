@@ -56,9 +56,19 @@ enum {
 typedef struct hsc_ctx hsc_ctx;   /* one HIP device + one stream + workspaces; not thread-safe */
 typedef struct hsc_tree hsc_tree; /* cluster tree of one device; immutable after build        */
 
-/* One contact: a list of device sites, each coupled (hopping `coupling`) to its
- * own semi-infinite 1D lead with on-site `lead_onsite` and hopping
- * `lead_hopping` (the diagonal contact self-energy of the paper's SPARSE case). */
+/* One contact: a list of device sites and the parameters of its lead.
+ * Per-site leads (tree option dense_contacts = 0): each site couples (hopping
+ * `coupling`) to its own semi-infinite 1D lead with on-site `lead_onsite` and
+ * hopping `lead_hopping` -- the diagonal contact self-energy of the paper's
+ * SPARSE case (Section 3.1.1).
+ * Whole-face leads (dense_contacts = 1): the sites are one whole face of the
+ * device, a full rectangle of a plane normal to the transport axis, and the
+ * lead is the semi-infinite continuation of that face: every lead layer is a
+ * copy of the face lattice (on-site `lead_onsite`, nearest-neighbour hopping
+ * `lead_hopping` inside the layer and to the next layer), each face site
+ * coupled to its copy by `coupling`.  The self-energy is then a dense
+ * |face| x |face| block -- the paper's DENSE case (Section 3.1.2; the
+ * open-boundary caveat of Section 2.3). */
 typedef struct {
   int64_t n_sites;
   const int64_t* sites;      /* host, [n_sites] site indices in [0, n) */
@@ -76,6 +86,13 @@ typedef struct {
   const int32_t* coords;     /* host, [n][3] integer site coordinates */
   int32_t split_mask;        /* e.g. 7 for x|y|z, 3 for in-plane only */
   int32_t leaf_side;         /* >= 1 */
+  int32_t dense_contacts;    /* 0: per-site leads; 1: whole-face leads (dense self-energy).
+                              * With 1 the two contacts must be the two end planes of the
+                              * device along one axis (every site between them), each a full
+                              * rectangle in the other two axes; each face becomes a cluster of
+                              * its own, above the dissection of its half: the root is the middle
+                              * plane (devices at least 4 planes long), else the left face heads
+                              * a chain.  Such trees are not merged or put into forests. */
 } hsc_tree_opts;
 
 typedef struct {

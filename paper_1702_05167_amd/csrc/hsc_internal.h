@@ -20,6 +20,15 @@ struct ContactInfo {
   double lead_onsite = 0, lead_hopping = -1, coupling = -1;
 };
 
+// A whole-face contact (dense self-energy): transverse axes, the face's lowest coordinate and
+// extent on each, and the cluster that holds exactly the face's sites.
+struct FaceInfo {
+  int32_t ax[2] = {1, 2};
+  int32_t lo[2] = {0, 0};
+  int32_t dim[2] = {1, 1};
+  int cluster = -1;
+};
+
 // One cluster of the binary tree (Section 2.2: clusters organised in a binary
 // tree; P_i = ancestors).  Ids are post-order: children before parents, the
 // root is the last cluster, and the subtree of i is the id range [lo, i].
@@ -51,6 +60,8 @@ struct hsc_tree {
   std::vector<int32_t> coords;     // [n][3]
   int32_t split_mask = 7, leaf_side = 8;
   hsc::ContactInfo contact[2];
+  int32_t dense = 0;               // whole-face contacts with dense self-energy blocks
+  hsc::FaceInfo face[2];
   std::vector<int8_t> side;        // -1 none, 0 left, 1 right
   std::vector<hsc::Cluster> cl;    // post-order
   std::vector<int64_t> perm;       // position -> site

@@ -72,6 +72,95 @@ struct NDBuilder {
   }
 };
 
+// Whole-face contacts (dense self-energy blocks): each face must sit inside one cluster that is an
+// ancestor of every cluster touching it, or the dense block would couple sibling clusters.  With
+// d(s) the distance of site s from the left face along the normal axis and N planes in all:
+//   N >= 4: root = plane d = N/2; its children are the two faces, each the parent of the nested
+//           dissection of the planes between it and the root (the right face is a leaf when no
+//           plane lies between them);
+//   N = 2, 3: the left face is the root of a chain (middle plane, if any, then the right face).
+// The left face is never a leaf, so its full diagonal block of every lesser channel is formed.
+void build_dense(hsc_tree* t, NDBuilder& b) {
+  const int64_t n = t->n;
+  auto crd = [&](int64_t s, int a) { return t->coords[3 * s + a]; };
+  int ax = -1;
+  for (int a = 0; a < 3 && ax < 0; ++a) {
+    bool flat = true;
+    for (int k = 0; k < 2 && flat; ++k) {
+      const auto& v = t->contact[k].sites;
+      for (int64_t s : v) flat = flat && crd(s, a) == crd(v[0], a);
+    }
+    if (flat && crd(t->contact[0].sites[0], a) != crd(t->contact[1].sites[0], a)) ax = a;
+  }
+  if (ax < 0) throw std::string("dense contacts: the two contacts are not parallel faces");
+  const int32_t x0 = crd(t->contact[0].sites[0], ax), x1 = crd(t->contact[1].sites[0], ax);
+  const int32_t sgn = x1 > x0 ? 1 : -1;
+  const int64_t planes = (int64_t)(x1 - x0) * sgn + 1;
+  std::vector<int32_t> dist(n);
+  std::vector<int64_t> per_plane(planes, 0);
+  for (int64_t s = 0; s < n; ++s) {
+    const int64_t d = (int64_t)(crd(s, ax) - x0) * sgn;
+    if (d < 0 || d >= planes) throw std::string("dense contacts: a site lies outside the slab between the faces");
+    dist[s] = (int32_t)d;
+    per_plane[d]++;
+  }
+  for (int k = 0; k < 2; ++k) {
+    const auto& v = t->contact[k].sites;
+    FaceInfo& f = t->face[k];
+    int q = 0;
+    for (int a = 0; a < 3; ++a)
+      if (a != ax) f.ax[q++] = a;
+    int32_t hi[2];
+    for (int q2 = 0; q2 < 2; ++q2) {
+      f.lo[q2] = INT32_MAX;
+      hi[q2] = INT32_MIN;
+      for (int64_t s : v) {
+        f.lo[q2] = std::min(f.lo[q2], crd(s, f.ax[q2]));
+        hi[q2] = std::max(hi[q2], crd(s, f.ax[q2]));
+      }
+      f.dim[q2] = hi[q2] - f.lo[q2] + 1;
+    }
+    if ((int64_t)f.dim[0] * f.dim[1] != (int64_t)v.size() || per_plane[k == 0 ? 0 : planes - 1] != (int64_t)v.size())
+      throw std::string("dense contacts: a contact is not a whole rectangular end plane of the device");
+    std::vector<char> seen((size_t)f.dim[0] * f.dim[1], 0);
+    for (int64_t s : v) {
+      char& c = seen[(size_t)(crd(s, f.ax[0]) - f.lo[0]) * f.dim[1] + (crd(s, f.ax[1]) - f.lo[1])];
+      if (c) throw std::string("dense contacts: two sites of a face share a position");
+      c = 1;
+    }
+  }
+  auto slab = [&](int64_t a, int64_t bnd) {   // sites with a <= d < bnd
+    std::vector<int64_t> v;
+    for (int64_t s = 0; s < n; ++s)
+      if (dist[s] >= a && dist[s] < bnd) v.push_back(s);
+    return v;
+  };
+  auto push = [&](std::vector<int64_t> sites, std::vector<int> kids) {
+    b.sites_of.push_back(std::move(sites));
+    b.kids_of.push_back(std::move(kids));
+    return (int)b.sites_of.size() - 1;
+  };
+  if (planes <= 3) {
+    const int r = push(slab(planes - 1, planes), {});
+    t->face[1].cluster = r;
+    int top = r;
+    if (planes == 3) top = push(slab(1, 2), {r});
+    t->face[0].cluster = push(slab(0, 1), {top});
+    return;
+  }
+  const int64_t cut = planes / 2;
+  std::vector<int64_t> inner = slab(1, cut);
+  const int li = b.rec(inner);
+  t->face[0].cluster = push(slab(0, 1), {li});
+  std::vector<int> rk;
+  if (cut + 1 < planes - 1) {
+    std::vector<int64_t> rin = slab(cut + 1, planes - 1);
+    rk.push_back(b.rec(rin));
+  }
+  t->face[1].cluster = push(slab(planes - 1, planes), rk);
+  push(slab(cut, cut + 1), {t->face[0].cluster, t->face[1].cluster});
+}
+
 }  // namespace
 
 int finalize_tree(hsc_tree* t, std::vector<std::vector<int64_t>>& sites_of) {
@@ -217,6 +306,16 @@ double flops_per_energy(const hsc_tree* t, uint32_t want) {
       fl += leaf ? 8 * n * f * f + 8 * n * f : 8 * n * f * f + 8 * n * n * f;
     }
   }
+  if (t->dense)
+    for (int k = 0; k < 2; ++k) {
+      // dense face self-energy in two separable mode sums (5 flops per term: one real product of
+      // two sine factors, then a real-times-complex multiply-add)
+      const double d1 = t->face[k].dim[0], d2 = t->face[k].dim[1], F = d1 * d2;
+      fl += 5 * d1 * d2 * d2 * d2 + 5 * F * F * d1;
+      // Gamma times the face's G rows, once per energy for every lesser channel
+      const Cluster& c = t->cl[t->face[k].cluster];
+      if (need_gl) fl += 8 * F * F * (c.n + (double)c.n_anc);
+    }
   if (!need_gl) return fl;
   // channels: (fold-set, extract-set) as chosen by the solver
   struct Ch { int fold; int extract; };   // 0 = both sides, 1 = left, 2 = right, 3 = none
@@ -351,9 +450,15 @@ hsc_status hsc_tree_build(int64_t n, const int64_t* indptr, const int32_t* indic
       }
     }
     NDBuilder b{t, {}, {}};
-    std::vector<int64_t> all(n);
-    for (int64_t s = 0; s < n; ++s) all[s] = s;
-    b.rec(all);
+    if (opts->dense_contacts != 0 && opts->dense_contacts != 1) throw std::string("dense_contacts must be 0 or 1");
+    t->dense = opts->dense_contacts;
+    if (t->dense) {
+      build_dense(t, b);
+    } else {
+      std::vector<int64_t> all(n);
+      for (int64_t s = 0; s < n; ++s) all[s] = s;
+      b.rec(all);
+    }
     t->cl.resize(b.sites_of.size());
     for (size_t i = 0; i < b.sites_of.size(); ++i) t->cl[i].children = b.kids_of[i];
     int st = finalize_tree(t, b.sites_of);
@@ -376,6 +481,7 @@ hsc_status hsc_tree_build(int64_t n, const int64_t* indptr, const int32_t* indic
 hsc_status hsc_tree_merge(const hsc_tree* src, int32_t n_ids, const int32_t* ids, hsc_tree** out) {
   if (!src || !out || n_ids < 0 || (n_ids > 0 && !ids)) { set_error("bad arguments to hsc_tree_merge"); return HSC_E_ARG; }
   *out = nullptr;
+  if (src->dense) { set_error("trees with whole-face contacts cannot be merged"); return HSC_E_ARG; }
   const int nc = (int)src->cl.size();
   std::vector<char> gone(nc, 0);
   for (int k = 0; k < n_ids; ++k) {
@@ -425,8 +531,10 @@ hsc_status hsc_tree_merge(const hsc_tree* src, int32_t n_ids, const int32_t* ids
 hsc_status hsc_tree_concat(int32_t n_trees, const hsc_tree* const* trees, hsc_tree** out) {
   if (!out || n_trees < 1 || !trees) { set_error("bad arguments to hsc_tree_concat"); return HSC_E_ARG; }
   *out = nullptr;
-  for (int d = 0; d < n_trees; ++d)
+  for (int d = 0; d < n_trees; ++d) {
     if (!trees[d]) { set_error("null tree in hsc_tree_concat"); return HSC_E_ARG; }
+    if (trees[d]->dense) { set_error("hsc_tree_concat: trees with whole-face contacts cannot form a forest"); return HSC_E_ARG; }
+  }
   for (int d = 1; d < n_trees; ++d)
     for (int k = 0; k < 2; ++k) {
       const ContactInfo &a = trees[0]->contact[k], &b = trees[d]->contact[k];

@@ -30,7 +30,8 @@ class Contact(C.Structure):
 
 
 class TreeOpts(C.Structure):
-    _fields_ = [("coords", C.POINTER(C.c_int32)), ("split_mask", C.c_int32), ("leaf_side", C.c_int32)]
+    _fields_ = [("coords", C.POINTER(C.c_int32)), ("split_mask", C.c_int32), ("leaf_side", C.c_int32),
+                ("dense_contacts", C.c_int32)]
 
 
 class TreeStats(C.Structure):
@@ -186,8 +187,10 @@ class Tree:
         self.n = n
 
     @classmethod
-    def build(cls, n, indptr, indices, values, coords, contacts, split_mask=7, leaf_side=8):
-        """contacts: [(sites, lead_onsite, lead_hopping, coupling)] for left, right."""
+    def build(cls, n, indptr, indices, values, coords, contacts, split_mask=7, leaf_side=8, dense=False):
+        """contacts: [(sites, lead_onsite, lead_hopping, coupling)] for left, right.  dense=True:
+        each contact is a whole end face with a lead continuing the face lattice (dense
+        self-energy block); otherwise every contact site has its own 1D lead."""
         indptr = np.ascontiguousarray(indptr, dtype=np.int64)
         indices = np.ascontiguousarray(indices, dtype=np.int32)
         vals = np.ascontiguousarray(np.asarray(values, dtype=np.complex128)).view(np.float64)
@@ -198,22 +201,22 @@ class Tree:
             s = np.ascontiguousarray(sites, dtype=np.int64)
             keep.append(s)
             carr[k] = Contact(len(s), s.ctypes.data_as(C.POINTER(C.c_int64)), eps0, tl, tc)
-        opts = TreeOpts(coords.ctypes.data_as(C.POINTER(C.c_int32)), split_mask, leaf_side)
+        opts = TreeOpts(coords.ctypes.data_as(C.POINTER(C.c_int32)), split_mask, leaf_side, int(bool(dense)))
         h = C.c_void_p()
         check(lib().hsc_tree_build(n, _ptr(indptr), _ptr(indices), _ptr(vals), len(contacts), carr,
                                    C.byref(opts), C.byref(h)))
         return cls(h, n)
 
     @classmethod
-    def from_device(cls, dev, leaf_side=8, transverse=False):
+    def from_device(cls, dev, leaf_side=8, transverse=False, dense=False):
         """Tree of a synthetic device; transverse=True never cuts the transport axis (x), so every
-        cluster spans the device from one contact to the other."""
+        cluster spans the device from one contact to the other; dense=True: whole-face leads."""
         mask = 0
         for a in dev.split_axes:
             if not (transverse and a == 0):
                 mask |= 1 << a
         contacts = [(c.sites, c.lead_onsite, c.lead_hopping, c.coupling) for c in dev.contacts]
-        return cls.build(dev.n, dev.indptr, dev.indices, dev.values, dev.coords, contacts, mask, leaf_side)
+        return cls.build(dev.n, dev.indptr, dev.indices, dev.values, dev.coords, contacts, mask, leaf_side, dense)
 
     def stats(self) -> dict:
         s = TreeStats()

@@ -225,3 +225,67 @@ def test_concat_rejects_different_leads():
     b = pkg.Tree.build(d.n, d.indptr, d.indices, d.values, d.coords, c, 7, 3)
     with pytest.raises(H.HscError):
         pkg.Tree.concat([a, b])
+
+
+@pytest.mark.parametrize("shape,leaf", [((2, 3, 4), 2), ((3, 4, 4), 2), ((4, 5, 3), 2), ((5, 4, 4), 2),
+                                        ((9, 6, 5), 3), ((12, 12, 12), 4), ((7, 5, 1), 2)])
+def test_dense_contact_tree(shape, leaf):
+    # whole-face contacts: each face is one cluster, above every cluster that touches it
+    dev = synth.cuboid(*shape)
+    t = pkg.Tree.from_device(dev, leaf_side=leaf, dense=True)
+    ex = _check_tree(dev, t)
+    perm, parent, first, size = ex["perm"], ex["parent"], ex["first"], ex["size"]
+    nc = len(parent)
+    owner = np.empty(dev.n, np.int64)
+    for i in range(nc):
+        owner[perm[first[i]:first[i] + size[i]]] = i
+    nx = shape[0]
+    face_cl = []
+    for c in dev.contacts:
+        o = set(owner[c.sites].tolist())
+        assert len(o) == 1
+        k = o.pop()
+        assert size[k] == len(c.sites)                     # the cluster is exactly the face
+        face_cl.append(k)
+    assert face_cl[0] in set(parent.tolist())              # the left face is never a leaf
+    x = dev.coords[:, 0]
+    root = nc - 1
+    if nx >= 4:
+        assert (x[perm[first[root]:first[root] + size[root]]] == nx // 2).all()
+        assert parent[face_cl[0]] == root and parent[face_cl[1]] == root
+        # every cluster of the left half lies below the left face, of the right half below the right face
+        for i in range(nc):
+            xs = x[perm[first[i]:first[i] + size[i]]]
+            p, anc = parent[i], set()
+            while p >= 0:
+                anc.add(p)
+                p = parent[p]
+            if xs.max() < nx // 2 and i != face_cl[0]:
+                assert face_cl[0] in anc
+            if xs.min() > nx // 2 and i != face_cl[1]:
+                assert face_cl[1] in anc
+    else:
+        assert face_cl[0] == root
+
+
+def test_dense_contact_tree_rejections():
+    dev = synth.cuboid(6, 4, 3)
+    contacts = [(c.sites, c.lead_onsite, c.lead_hopping, c.coupling) for c in dev.contacts]
+
+    def build(cs):
+        return pkg.Tree.build(dev.n, dev.indptr, dev.indices, dev.values, dev.coords, cs, 7, 2, dense=True)
+
+    part = [(contacts[0][0][:-1],) + contacts[0][1:], contacts[1]]          # not the whole plane
+    with pytest.raises(H.HscError):
+        build(part)
+    ymin = np.flatnonzero(dev.coords[:, 1] == 0)                              # faces not parallel
+    with pytest.raises(H.HscError):
+        build([(ymin,) + contacts[0][1:], contacts[1]])
+    t = build(contacts)
+    with pytest.raises(H.HscError):
+        t.merge([0])
+    with pytest.raises(H.HscError):
+        pkg.Tree.concat([t, t])
+    # the left contact may be the higher end: the tree is mirrored, the left face still heads its half
+    t2 = build([contacts[1], contacts[0]])
+    assert t2.stats()["n_clusters"] == t.stats()["n_clusters"]
