@@ -279,7 +279,8 @@ hsc_status hsc_totals(hsc_ctx* ctx, int32_t n_e, int64_t n, const void* diag_gr,
  * double-double assemble / panel / swap / unscramble / GEMM, 14 inverse
  * super-panel preparation, 15 operand splitting into 8-bit slices, 16 slice
  * products on the integer matrix cores (precision 3), 17 double-double inverse
- * super-panel preparation.
+ * super-panel preparation, 18-19 the dense self-energy of whole-face contacts
+ * (partial mode sums, then the face block).
  * hsc_ctx_profile_read writes out[3*k + {0,1,2}] = launches, milliseconds,
  * algorithmic real flops (GEMM: 8 M N K per problem) for k < n_kinds.
  * Errors: HSC_E_ARG. */

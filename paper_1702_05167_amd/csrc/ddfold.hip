@@ -48,6 +48,9 @@ __global__ __launch_bounds__(RB) void k_dd_assemble(const RowJob* __restrict__ j
     }
   }
   zdd* out = reinterpret_cast<zdd*>(jb.dst) + (int64_t)a * jb.ldd;
+  // whole-face contact cluster: minus its dense self-energy block (rows and columns < nface)
+  const int nface = jb.aux4;
+  const double2* dsig = a < nface ? reinterpret_cast<const double2*>(jb.p2) : nullptr;
   for (int b = threadIdx.x; b < cols; b += RB) {
     zdd v = zdd_zero();
     for (int k = 0; k < nk; ++k) {
@@ -62,6 +65,10 @@ __global__ __launch_bounds__(RB) void k_dd_assemble(const RowJob* __restrict__ j
     for (int q = q0 + 64; q < q1; ++q)
       if (fs->col[q] == b) v = zdd_add(v, zdd_from(fs->val[q]));
     if (b == a) v = zdd_add(v, diag_add);
+    if (dsig && b < nface) {
+      const double2 sv = dsig[(int64_t)a * nface + b];
+      v = zdd_sub(v, zdd_from(sv));
+    }
     out[b] = v;
   }
 }
@@ -419,9 +426,12 @@ __global__ __launch_bounds__(RB) void k_dd_assemble_n(const RowJob* __restrict__
   const ChildRef* kids = reinterpret_cast<const ChildRef*>(jb.p0);
   const int nk = jb.aux0, r = jb.aux1, row0 = jb.aux2, n = jb.aux3, nL = jb.aux4, nR = jb.aux5;
   const int a = rr < r ? row0 + rr : n + (rr - r);
+  // whole-face contact: p1 holds Gamma G (same leading dimension) and w is the occupation alone
+  const zdd* gam_g = reinterpret_cast<const zdd*>(jb.p1);
   double w = 0.0;
-  if (rr < r && a < nL + nR) w = channel_weight(es[jb.e], channel, a < nL ? 0 : 1);
-  const zdd* grow = reinterpret_cast<const zdd*>(jb.src) + (int64_t)a * jb.lds;
+  if (rr < r && a < nL + nR)
+    w = gam_g ? channel_occ(es[jb.e], channel, a < nL ? 0 : 1) : channel_weight(es[jb.e], channel, a < nL ? 0 : 1);
+  const zdd* grow = (gam_g ? gam_g : reinterpret_cast<const zdd*>(jb.src)) + (int64_t)a * jb.lds;
   zdd* out = reinterpret_cast<zdd*>(jb.dst) + (int64_t)rr * jb.ldd;
   for (int b = threadIdx.x; b < jb.cols; b += RB) {
     zdd v = zdd_zero();

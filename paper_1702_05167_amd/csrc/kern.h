@@ -68,6 +68,14 @@ __device__ inline double channel_weight(const EnergyScalars& s, int channel, int
   return side == 1 ? s.gam[1] : 0.0;
 }
 
+// lesser-channel weight of a contact side without its broadening (whole-face contacts carry
+// Gamma as a matrix): occupation in channel 0, 1 for the channel's own side, else 0
+__device__ inline double channel_occ(const EnergyScalars& s, int channel, int side) {
+  if (channel == 0) return s.fermi[side];
+  if (channel == 1) return side == 0 ? 1.0 : 0.0;
+  return side == 1 ? 1.0 : 0.0;
+}
+
 // Child of a frontal matrix: its update block U (rows/cols = child front) and
 // invrel[a] = position of the parent's frontal index a in the child front, or -1.
 struct ChildRef {
@@ -125,6 +133,37 @@ void launch_trans(hipStream_t st, const double* a_r, int64_t ld, const int64_t* 
 // diag G^< = i (f_L A_L + f_R A_R) from spectral [e][2][n]
 void launch_combine_gl(hipStream_t st, const double* spec, int nvalid, int e_base, int64_t n,
                        const EnergyScalars* es, double2* gl);
+
+// ---- whole-face contacts (dense self-energy blocks) ----
+// One (energy slot, contact) job.  The face is a d1 x d2 rectangle; its lead continues the face
+// lattice (on-site eps, hopping tl inside a layer and between layers, coupling tc per site).
+// Mode p of an axis of extent d: phi_p(j) = sqrt(2 / (d + 1)) sin(pi (p+1) (j+1) / (d + 1)),
+// 0-based p, j; tab[j * d + p].
+struct FaceJob {
+  int32_t e;                 // energy slot
+  int32_t d1, d2, F;         // F = d1 d2 = rows of the face cluster
+  double eps, tl, tc;
+  const double* tab1;        // [d1][d1]
+  const double* tab2;        // [d2][d2]
+  const int32_t* jk;         // [F] row of the face cluster -> j * d2 + k
+  double2* half;             // [d1][d2][d2] partial mode sums
+  double2* sigma;            // [F][F] self-energy, rows/cols in the face cluster's order
+  void* gamma;               // [F][F] Gamma = -2 Im Sigma: double2 (re, 0) or zdd
+  int32_t gamma_dd;
+};
+// half[p][k][k'] = sum_q phi_q(k) phi_q(k') g_pq(z)   (g_pq: surface function of mode (p, q))
+void launch_face_half(hipStream_t st, const FaceJob* jobs, int njobs, int max_d1, int max_d2,
+                      const EnergyScalars* es);
+// sigma[a][b] = tc^2 sum_p phi_p(j_a) phi_p(j_b) half[p][k_a][k_b]; gamma = -2 Im sigma
+void launch_face_sigma(hipStream_t st, const FaceJob* jobs, int njobs, int max_f);
+// T[e_base + slot] = sum_{a,b} Gamma_L[a][b] Im P[a][b] over the left face block of the right
+// channel's lesser block P (= i A_R there); accumulated in double-double
+struct FaceTransJob {
+  const void* gamma;         // Gamma_L of the slot (layout as FaceJob::gamma)
+  const void* P;             // left face's diagonal block of i A_R (double2 or zdd), leading dim ldp
+  int32_t F, ldp, dd;
+};
+void launch_face_trans(hipStream_t st, const FaceTransJob* jobs, int nvalid, int e_base, double* trans);
 
 // Batched blocked Gauss-Jordan inversion.
 void launch_inv_panel(hipStream_t st, const InvJob* jobs, int njobs, int k0, int nb, int max_n,

@@ -5,6 +5,7 @@
 // the diagonal / transmission outputs.
 #include <hip/hip_runtime.h>
 
+#include "dd.h"
 #include "kern.h"
 
 namespace hsc {
@@ -101,6 +102,9 @@ __global__ __launch_bounds__(RB) void k_assemble(const RowJob* __restrict__ jobs
     else if (a < nL + nR) { diag_add.x -= s.sig[1].x; diag_add.y -= s.sig[1].y; }
   }
   double2* out = jb.dst + (int64_t)a * jb.ldd;
+  // whole-face contact cluster: minus its dense self-energy block (rows and columns < nface)
+  const double2* dsig = a < jb.aux4 ? reinterpret_cast<const double2*>(jb.p2) : nullptr;
+  const int nface = jb.aux4;
   // children whose update has a row for a: that row and the column map, up to four in registers
   constexpr int KMAX = 4;
   const double2* urow[KMAX];
@@ -131,6 +135,11 @@ __global__ __launch_bounds__(RB) void k_assemble(const RowJob* __restrict__ jobs
     for (int q = q0 + 64; q < q1; ++q)
       if (fs->col[q] == b) v = cadd(v, fs->val[q]);
     if (b == a) v = cadd(v, diag_add);
+    if (dsig && b < nface) {
+      const double2 sv = dsig[(int64_t)a * nface + b];
+      v.x -= sv.x;
+      v.y -= sv.y;
+    }
     out[b] = v;
   }
 }
@@ -178,9 +187,13 @@ __global__ __launch_bounds__(RB) void k_assemble_n(const RowJob* __restrict__ jo
   const ChildRef* kids = reinterpret_cast<const ChildRef*>(jb.p0);
   const int nk = jb.aux0, r = jb.aux1, row0 = jb.aux2, n = jb.aux3, nL = jb.aux4, nR = jb.aux5;
   const int a = rr < r ? row0 + rr : n + (rr - r);
+  // seed rows: i w conj(G row a); for a whole-face contact p1 holds Gamma G (the face's Gamma
+  // times its G rows, same leading dimension) and w is the occupation alone
+  const double2* gam_g = reinterpret_cast<const double2*>(jb.p1);
   double w = 0.0;
-  if (rr < r && a < nL + nR) w = channel_weight(es[jb.e], channel, a < nL ? 0 : 1);
-  const double2* grow = jb.src + (int64_t)a * jb.lds;
+  if (rr < r && a < nL + nR)
+    w = gam_g ? channel_occ(es[jb.e], channel, a < nL ? 0 : 1) : channel_weight(es[jb.e], channel, a < nL ? 0 : 1);
+  const double2* grow = (gam_g ? gam_g : jb.src) + (int64_t)a * jb.lds;
   double2* out = jb.dst + (int64_t)rr * jb.ldd;
   // the row of each child's update that lands on row a (same for every column): up to four
   // children in registers, more through the general loop
@@ -352,6 +365,102 @@ void launch_guard(hipStream_t st, const RowJob* jobs, int njobs, int nclusters, 
   hipLaunchKernelGGL(k_guard, dim3(njobs), dim3(RB), 0, st, jobs, nclusters, e_base, nvalid, out);
 }
 
+// ---- whole-face contacts: dense self-energy (Section 3.1.2's DENSE case) ----
+// Each transverse mode (p, q) of the face is a semi-infinite chain with on-site
+// eps + 2 tl (cos(pi (p+1) / (d1+1)) + cos(pi (q+1) / (d2+1))) and hopping tl; the face block is
+// Sigma = tc^2 sum_{p,q} g_pq (phi_p x phi_q)(phi_p x phi_q)^T, summed over q first (one block per
+// (job, p)), then over p (one thread per entry).
+constexpr double kPi = 3.14159265358979323846;
+
+__global__ __launch_bounds__(256) void k_face_half(const FaceJob* __restrict__ jobs,
+                                                   const EnergyScalars* __restrict__ es) {
+  extern __shared__ double2 s_g[];   // [d2] surface functions of the modes (p, 0..d2-1)
+  const FaceJob& j = jobs[blockIdx.y];
+  const int p = blockIdx.x;
+  if (p >= j.d1) return;
+  const int d2 = j.d2;
+  const double2 z = es[j.e].z;
+  const double cp = cos(kPi * (p + 1) / (j.d1 + 1));
+  for (int q = threadIdx.x; q < d2; q += blockDim.x)
+    s_g[q] = lead_sigma(z, j.eps + 2.0 * j.tl * (cp + cos(kPi * (q + 1) / (d2 + 1))), j.tl, 1.0);
+  __syncthreads();
+  double2* out = j.half + (int64_t)p * d2 * d2;
+  for (int idx = threadIdx.x; idx < d2 * d2; idx += blockDim.x) {
+    const int k = idx / d2, k2 = idx - k * d2;
+    const double* r1 = j.tab2 + (int64_t)k * d2;
+    const double* r2 = j.tab2 + (int64_t)k2 * d2;
+    double re = 0.0, im = 0.0;
+    for (int q = 0; q < d2; ++q) {
+      const double w = r1[q] * r2[q];
+      re = fma(w, s_g[q].x, re);
+      im = fma(w, s_g[q].y, im);
+    }
+    out[idx] = make_double2(re, im);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_face_sigma(const FaceJob* __restrict__ jobs) {
+  const FaceJob& j = jobs[blockIdx.y];
+  const int64_t F = j.F;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= F * F) return;
+  const int a = (int)(idx / F), b = (int)(idx - (int64_t)a * F);
+  const int d1 = j.d1, d2 = j.d2;
+  const int ja = j.jk[a] / d2, ka = j.jk[a] - ja * d2;
+  const int jb = j.jk[b] / d2, kb = j.jk[b] - jb * d2;
+  const double* r1 = j.tab1 + (int64_t)ja * d1;
+  const double* r2 = j.tab1 + (int64_t)jb * d1;
+  const double2* h = j.half + (int64_t)ka * d2 + kb;
+  const int64_t hs = (int64_t)d2 * d2;
+  double re = 0.0, im = 0.0;
+  for (int p = 0; p < d1; ++p) {
+    const double w = r1[p] * r2[p];
+    const double2 hv = h[p * hs];
+    re = fma(w, hv.x, re);
+    im = fma(w, hv.y, im);
+  }
+  const double t2 = j.tc * j.tc;
+  const double2 sg = make_double2(t2 * re, t2 * im);
+  j.sigma[idx] = sg;
+  const double gam = -2.0 * sg.y;
+  if (j.gamma_dd) reinterpret_cast<zdd*>(j.gamma)[idx] = zdd{dd{gam, 0.0}, dd{0.0, 0.0}};
+  else reinterpret_cast<double2*>(j.gamma)[idx] = make_double2(gam, 0.0);
+}
+
+// The lesser-type block of the right channel is P = G (i Gamma_R) G^dagger = i A_R, so
+// T = Tr(Gamma_L A_R) over the left face = sum_{a,b} Gamma_L[a][b] Im P[a][b].
+__global__ __launch_bounds__(256) void k_face_trans(const FaceTransJob* __restrict__ jobs, int nvalid, int e_base,
+                                                    double* __restrict__ trans) {
+  const int e = blockIdx.x;
+  if (e >= nvalid) return;
+  const FaceTransJob& j = jobs[e];
+  const int64_t F = j.F;
+  dd acc{0.0, 0.0};
+  for (int64_t idx = threadIdx.x; idx < F * F; idx += blockDim.x) {
+    const int64_t a = idx / F, b = idx - a * F;
+    if (j.dd) {
+      const double g = reinterpret_cast<const zdd*>(j.gamma)[idx].re.hi;
+      acc = dd_add(acc, dd_mul(dd_from(g), reinterpret_cast<const zdd*>(j.P)[a * j.ldp + b].im));
+    } else {
+      const double g = reinterpret_cast<const double2*>(j.gamma)[idx].x;
+      acc = dd_add(acc, two_prod(g, reinterpret_cast<const double2*>(j.P)[a * j.ldp + b].y));
+    }
+  }
+  __shared__ double sh[256], sl[256];
+  sh[threadIdx.x] = acc.hi;
+  sl[threadIdx.x] = acc.lo;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      const dd v = dd_add(dd{sh[threadIdx.x], sl[threadIdx.x]}, dd{sh[threadIdx.x + s], sl[threadIdx.x + s]});
+      sh[threadIdx.x] = v.hi;
+      sl[threadIdx.x] = v.lo;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) trans[e_base + e] = sh[0] + sl[0];
+}
+
 void launch_energy_setup(hipStream_t st, const double* energies, int nvalid, int nslots, double eta,
                          double kT, double mu_L, double mu_R, LeadParams lp, EnergyScalars* out,
                          int32_t* status) {
@@ -411,6 +520,23 @@ void launch_trans(hipStream_t st, const double* a_r, int64_t ld, const int64_t* 
   if (nslots <= 0) return;
   hipLaunchKernelGGL(k_trans, dim3(nslots), dim3(RB), 0, st, a_r, ld, left_sites, nleft, nvalid, e_base, es,
                      trans);
+}
+
+void launch_face_half(hipStream_t st, const FaceJob* jobs, int njobs, int max_d1, int max_d2,
+                      const EnergyScalars* es) {
+  if (njobs <= 0 || max_d1 <= 0) return;
+  hipLaunchKernelGGL(k_face_half, dim3(max_d1, njobs), dim3(256), (size_t)max_d2 * sizeof(double2), st, jobs, es);
+}
+
+void launch_face_sigma(hipStream_t st, const FaceJob* jobs, int njobs, int max_f) {
+  if (njobs <= 0 || max_f <= 0) return;
+  const int64_t cells = (int64_t)max_f * max_f;
+  hipLaunchKernelGGL(k_face_sigma, dim3((unsigned)((cells + 255) / 256), njobs), dim3(256), 0, st, jobs);
+}
+
+void launch_face_trans(hipStream_t st, const FaceTransJob* jobs, int nvalid, int e_base, double* trans) {
+  if (nvalid <= 0) return;
+  hipLaunchKernelGGL(k_face_trans, dim3(nvalid), dim3(256), 0, st, jobs, nvalid, e_base, trans);
 }
 
 void launch_combine_gl(hipStream_t st, const double* spec, int nvalid, int e_base, int64_t n,

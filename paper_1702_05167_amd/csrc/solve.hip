@@ -63,8 +63,8 @@ struct Blob {
 
 enum StepKind { S_ASSEMBLE, S_INV_PANEL, S_INV_SWAP, S_INV_UNSCR, S_GEMM, S_GATHER, S_ASSEMBLE_N, S_DIAG, S_GUARD,
                 S_DD_ASSEMBLE, S_DD_INV_PANEL, S_DD_INV_SWAP, S_DD_INV_UNSCR, S_DD_GEMM, S_INV_SUPER,
-                S_OZ_SPLIT, S_OZ_GEMM, S_DD_INV_SUPER};
-constexpr int kStepKinds = 18;
+                S_OZ_SPLIT, S_OZ_GEMM, S_DD_INV_SUPER, S_FACE_HALF, S_FACE_SIGMA};
+constexpr int kStepKinds = 20;
 
 // Tile sizes a plan keeps GEMM problem lists and tile maps for: 64x64, 128x64, 64x128, 32x32,
 // 128x128.  Every launch kind of launch_gemm uses one of them (tile_dims_of).
@@ -132,6 +132,7 @@ struct Plan {
   char* stage = nullptr;
   char* oz = nullptr;            // slice scratch of the products on the integer matrix cores
   size_t oz_bytes = 0;
+  const FaceTransJob* face_tj = nullptr;   // [B] transmission over the left face (whole-face contacts)
   ~Plan() {
     if (oz) (void)hipFree(oz);
     if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -209,6 +210,15 @@ struct Builder {
     size_t PsiS, PsiTS, InvS;
   };
   std::vector<CS> cs;   // [cluster * B + slot]
+  // whole-face contacts: per (contact, slot) the partial mode sums, the dense self-energy block,
+  // Gamma (in the extraction's element type) and Gamma times the face's G rows
+  struct FS { size_t half, sigma, gamma, gg; };
+  std::vector<FS> fsl;  // [contact * B + slot]
+  size_t f_tab1[2] = {}, f_tab2[2] = {}, f_jk[2] = {};   // blob: sine tables, face positions
+  int face_of(int i) const {
+    if (!t->dense) return -1;
+    return i == t->face[0].cluster ? 0 : i == t->face[1].cluster ? 1 : -1;
+  }
 
   size_t wsa(size_t bytes) {
     size_t off = (ws + 255) / 256 * 256;
@@ -314,11 +324,50 @@ struct Builder {
     }
   }
 
+  void layout_faces() {
+    if (!t->dense) return;
+    fsl.assign((size_t)2 * B, FS{});
+    const size_t ge = ddx ? 32 : 16;
+    for (int c = 0; c < 2; ++c) {
+      const FaceInfo& fi = t->face[c];
+      const size_t d1 = fi.dim[0], d2 = fi.dim[1], F = d1 * d2;
+      const Cluster& fc = t->cl[fi.cluster];
+      for (int e = 0; e < B; ++e) {
+        FS& f = fsl[(size_t)c * B + e];
+        f.half = wsa(d1 * d2 * d2 * 16);
+        f.sigma = wsa(F * F * 16);
+        f.gamma = wsa(F * F * ge);
+        if (gl) f.gg = wsa(F * (size_t)(fc.n + fc.n_anc) * ge);
+      }
+    }
+  }
+
   // tree constants
   void constants() {
     const int nc = (int)t->cl.size();
     c_invrel.assign(nc, 0); c_rel.assign(nc, 0); c_gcol.assign(nc, 0); c_trow.assign(nc, 0);
     c_trowp.assign(nc, 0); c_nfc.assign(nc, 0); c_sites.assign(nc, 0); c_fs.assign(nc, 0);
+    if (t->dense)
+      for (int c = 0; c < 2; ++c) {
+        // transverse sine modes of the face (the lead layer's eigenvectors) and each face row's
+        // position in the rectangle
+        const FaceInfo& fi = t->face[c];
+        for (int q = 0; q < 2; ++q) {
+          const int d = fi.dim[q];
+          std::vector<double> tab((size_t)d * d);
+          for (int j = 0; j < d; ++j)
+            for (int m = 0; m < d; ++m)
+              tab[(size_t)j * d + m] = std::sqrt(2.0 / (d + 1)) * std::sin(M_PI * (double)(m + 1) * (j + 1) / (d + 1));
+          (q == 0 ? f_tab1 : f_tab2)[c] = blob.push(tab);
+        }
+        const Cluster& fc = t->cl[fi.cluster];
+        std::vector<int32_t> jk(fc.n);
+        for (int a = 0; a < fc.n; ++a) {
+          const int64_t site = t->perm[fc.first + a];
+          jk[a] = (t->coords[3 * site + fi.ax[0]] - fi.lo[0]) * fi.dim[1] + (t->coords[3 * site + fi.ax[1]] - fi.lo[1]);
+        }
+        f_jk[c] = blob.push(jk);
+      }
     for (int i = 0; i < nc; ++i) {
       const Cluster& c = t->cl[i];
       const int n = c.n, f = c.f();
@@ -448,7 +497,7 @@ struct Builder {
     push(s);
   }
   // RowJob list: child-ref arrays are given as host vectors to be placed in the blob
-  struct RJ { RowJob j; std::vector<ChildRef> kids; std::vector<size_t> kid_invrel; bool p1_blob = false; };
+  struct RJ { RowJob j; std::vector<ChildRef> kids; std::vector<size_t> kid_invrel; bool p1_blob = false; bool p2_raw = false; };
   void rowstep(StepKind kind, std::vector<RJ>& jobs, int i0 = 0, int i1 = 0, int out = 0, int dd = 0) {
     std::vector<int32_t> rmap;
     std::vector<size_t> kid_off(jobs.size(), 0);
@@ -489,7 +538,7 @@ struct Builder {
       if (jobs[q].j.cmap) blob.reloc(base + offsetof(RowJob, cmap));
       if (!jobs[q].kids.empty()) blob.reloc(base + offsetof(RowJob, p0));
       if (jobs[q].p1_blob) blob.reloc(base + offsetof(RowJob, p1));
-      if (jobs[q].j.p2) blob.reloc(base + offsetof(RowJob, p2));
+      if (jobs[q].j.p2 && !jobs[q].p2_raw) blob.reloc(base + offsetof(RowJob, p2));
       ++qi;
     }
     s.map = blob.push(rmap);
@@ -771,6 +820,7 @@ struct Builder {
           q.j.p1 = reinterpret_cast<const void*>(c_fs[i]);
           q.p1_blob = true;
           q.j.aux1 = c.n; q.j.aux2 = c.n_left; q.j.aux3 = c.n_right;
+          face_block(q, i, e);
           jobs.push_back(q);
         }
       rowstep(S_DD_ASSEMBLE, jobs);
@@ -807,6 +857,102 @@ struct Builder {
       dd_gemm(1, 0, pu, 0, 1);
     }
     guard_step();
+  }
+
+  // the face cluster of a whole-face contact takes its dense self-energy block instead of the
+  // per-site scalars
+  void face_block(RJ& q, int i, int e) const {
+    const int c = face_of(i);
+    if (c < 0) return;
+    q.j.p2 = W(fsl[(size_t)c * B + e].sigma);
+    q.p2_raw = true;
+    q.j.aux4 = t->cl[i].n;
+    q.j.aux2 = q.j.aux3 = 0;
+  }
+
+  // dense self-energy blocks of both faces for every slot (before any assembly)
+  void face_steps() {
+    if (!t->dense) return;
+    phase = PH_OTHER;
+    std::vector<FaceJob> fj;
+    int md1 = 0, md2 = 0, mf = 0;
+    double fl_half = 0, fl_sig = 0;
+    for (int c = 0; c < 2; ++c) {
+      const FaceInfo& fi = t->face[c];
+      for (int e = 0; e < B; ++e) {
+        const FS& f = fsl[(size_t)c * B + e];
+        FaceJob j{};
+        j.e = e;
+        j.d1 = fi.dim[0]; j.d2 = fi.dim[1]; j.F = j.d1 * j.d2;
+        j.eps = t->contact[c].lead_onsite; j.tl = t->contact[c].lead_hopping; j.tc = t->contact[c].coupling;
+        j.tab1 = reinterpret_cast<const double*>(f_tab1[c]);
+        j.tab2 = reinterpret_cast<const double*>(f_tab2[c]);
+        j.jk = reinterpret_cast<const int32_t*>(f_jk[c]);
+        j.half = W(f.half);
+        j.sigma = W(f.sigma);
+        j.gamma = wsbase + f.gamma;
+        j.gamma_dd = ddx ? 1 : 0;
+        fj.push_back(j);
+        md1 = std::max(md1, j.d1); md2 = std::max(md2, j.d2); mf = std::max(mf, j.F);
+        fl_half += 5.0 * j.d1 * (double)j.d2 * j.d2 * j.d2;
+        fl_sig += 5.0 * (double)j.F * j.F * j.d1;
+      }
+    }
+    const size_t off = blob.push(fj);
+    for (size_t q = 0; q < fj.size(); ++q) {
+      const size_t base = off + q * sizeof(FaceJob);
+      blob.reloc(base + offsetof(FaceJob, tab1));
+      blob.reloc(base + offsetof(FaceJob, tab2));
+      blob.reloc(base + offsetof(FaceJob, jk));
+    }
+    Step h;
+    h.kind = S_FACE_HALF; h.jobs = off; h.njobs = (int)fj.size(); h.i0 = md1; h.i1 = md2; h.flops = fl_half;
+    push(h);
+    Step g;
+    g.kind = S_FACE_SIGMA; g.jobs = off; g.njobs = (int)fj.size(); g.i0 = mf; g.flops = fl_sig;
+    push(g);
+  }
+
+  // Gamma times the face's G rows (own sites and ancestors), the seed of every lesser channel
+  template <class T>
+  void face_gg() {
+    if (!t->dense || !gl) return;
+    phase = PH_EXTRACT_G;
+    std::vector<GPT<T>> ps;
+    for (int c = 0; c < 2; ++c) {
+      const int i = t->face[c].cluster;
+      const int n = n_of(i), P = P_of(i);
+      for (int e = 0; e < B; ++e) {
+        const CS& s = cs[(size_t)i * B + e];
+        const FS& f = fsl[(size_t)c * B + e];
+        const bool lf = leaf(i) && !root(i);
+        ps.push_back({X<T>(f.gamma), lf ? X<T>(s.SD) : X<T>(s.GX), nullptr, X<T>(f.gg), n, n + P, n, n,
+                      lf ? n + P : gcols(i), 0, n + P});
+      }
+    }
+    gemm_x(OP_N, OP_N, ps, 0);
+  }
+
+  // per slot: Gamma_L and the left face's diagonal block of the right channel (A_R there)
+  template <class T>
+  size_t face_trans_jobs() {
+    int k = -1;
+    for (size_t q = 0; q < chans.size(); ++q)
+      if (chans[q].type == 2) k = (int)q;
+    if (!t->dense || k < 0) return 0;
+    const int i = t->face[0].cluster;
+    std::vector<FaceTransJob> tj;
+    for (int e = 0; e < B; ++e) {
+      const CS& s = cs[(size_t)i * B + e];
+      FaceTransJob j{};
+      j.gamma = wsbase + fsl[e].gamma;
+      j.P = X<T>(s.PX[k]);
+      j.F = n_of(i);
+      j.ldp = n_of(i) + f_of(i);
+      j.dd = kDD<T>;
+      tj.push_back(j);
+    }
+    return blob.push(tj);
   }
 
   void guard_step() {
@@ -859,6 +1005,7 @@ struct Builder {
           q.j.p1 = reinterpret_cast<const void*>(c_fs[i]);
           q.p1_blob = true;
           q.j.aux1 = c.n; q.j.aux2 = c.n_left; q.j.aux3 = c.n_right;
+          face_block(q, i, e);
           jobs.push_back(q);
         }
       rowstep(S_ASSEMBLE, jobs);
@@ -1080,6 +1227,7 @@ struct Builder {
           q.j.aux1 = r; q.j.aux2 = row0; q.j.aux3 = n; q.j.aux4 = c.n_left; q.j.aux5 = c.n_right;
           if (leaf(i) && !root(i)) { q.j.src = d2(X<T>(s.SD)); q.j.lds = n + P; }
           else { q.j.src = d2(X<T>(s.GX)); q.j.lds = gcols(i); }
+          if (face_of(i) >= 0) q.j.p1 = d2(X<T>(fsl[(size_t)face_of(i) * B + e].gg));
           asm_jobs.push_back(q);
           if (!root(i)) {
             nu.push_back({psi_p<T>(s) + (size_t)row0 * f, X<T>(s.NF[k]) + n, X<T>(s.NF[k]) + (size_t)r * (n + P) + n,
@@ -1222,6 +1370,7 @@ bool step_empty(const Step& s) {
   switch (s.kind) {
     case S_INV_PANEL: case S_INV_SWAP: case S_INV_UNSCR: case S_INV_SUPER: case S_GUARD:
     case S_DD_INV_PANEL: case S_DD_INV_SWAP: case S_DD_INV_UNSCR: case S_DD_INV_SUPER:
+    case S_FACE_HALF: case S_FACE_SIGMA:
       return s.njobs <= 0;
     default:
       return s.count <= 0;
@@ -1312,6 +1461,12 @@ int run_steps(hsc_ctx* ctx, hipStream_t st, Plan* pl, int e_base, int nvalid, vo
         break;
       case S_OZ_GEMM:
         launch_oz_gemm(st, (const GemmProbOZ*)jobs, map, s.count, s.i1, s.beta);
+        break;
+      case S_FACE_HALF:
+        launch_face_half(st, (const FaceJob*)jobs, s.njobs, s.i0, s.i1, pl->es);
+        break;
+      case S_FACE_SIGMA:
+        launch_face_sigma(st, (const FaceJob*)jobs, s.njobs, s.i0);
         break;
       case S_DIAG: {
         void* out = nullptr;
@@ -1471,6 +1626,7 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
   b.oz = prec == 3;
   b.channels();
   b.layout();
+  b.layout_faces();
   // per-plan small buffers at the end of the workspace
   const size_t o_es = b.wsa(sizeof(EnergyScalars) * B);
   const size_t o_st = b.wsa(sizeof(int32_t) * B);
@@ -1498,20 +1654,25 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
   const size_t o_left = b.blob.push(t->contact[0].sites);
   pl->nleft = (int)t->contact[0].sites.size();
   const auto L = b.levels();
+  b.face_steps();
   b.fold(L);
   if (want & (HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR)) {
     if (b.ddx) b.extract_g<zdd>(L);
     else b.extract_g<double2>(L);
   }
+  if (b.ddx) b.face_gg<zdd>();
+  else b.face_gg<double2>();
   for (size_t k = 0; k < b.chans.size(); ++k) {
     if (b.ddx) b.channel_steps<zdd>(L, (int)k);
     else b.channel_steps<double2>(L, (int)k);
   }
+  const size_t o_ftj = b.ddx ? b.face_trans_jobs<zdd>() : b.face_trans_jobs<double2>();
   {
     const hsc_status rc = upload_plan(b, pl.get());
     if (rc != HSC_OK) return rc;
   }
   pl->left = reinterpret_cast<int64_t*>(pl->blob + o_left);
+  if (o_ftj) pl->face_tj = reinterpret_cast<const FaceTransJob*>(pl->blob + o_ftj);
   for (int c = 0; c < 2; ++c) {
     pl->lp.onsite[c] = t->contact[c].lead_onsite;
     pl->lp.hopping[c] = t->contact[c].lead_hopping;
@@ -1533,6 +1694,7 @@ size_t plan_bytes_per_slot(const hsc_tree* t, uint32_t want, int prec) {
   b.oz = prec == 3;
   b.channels();
   b.layout();
+  b.layout_faces();
   return b.ws;
 }
 
@@ -1682,7 +1844,9 @@ static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
       st = run_steps(ctx, ctx->stream, pl, e0, nv, diag_gr, diag_gl, spectral_lr, guard, (int)tree->cl.size());
       if (st != HSC_OK) return (hsc_status)st;
     }
-    if (want & HSC_TRANS) {
+    if ((want & HSC_TRANS) && tree->dense) {
+      launch_face_trans(ctx->stream, pl->face_tj, nv, e0, trans);
+    } else if (want & HSC_TRANS) {
       // one transmission per device of a forest, from its own left-contact sites
       for (int d = 0; d < nseg; ++d) {
         const int64_t l0 = tree->seg_left.empty() ? 0 : tree->seg_left[d];
@@ -1866,6 +2030,7 @@ hsc_status hsc_solve(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, const doub
   if (!opts || !(opts->guard_tau > 0.0))
     return solve_core(ctx, tree, n_e, energies, opts, diag_gr, diag_gl, trans, spectral_lr, status, guard);
   if (!ctx || !tree || n_e < 0 || opts->guard_rounds < 0) { set_error("bad arguments to hsc_solve"); return HSC_E_ARG; }
+  if (tree->dense) { set_error("the growth guard merges clusters: not available with whole-face contacts"); return HSC_E_ARG; }
   if (n_e == 0) return HSC_OK;
   HIPCHK(hipSetDevice(ctx->device));
   double* gd = guard;
@@ -1983,9 +2148,10 @@ hsc_status hsc_solve_batch(hsc_ctx* ctx, int32_t n_trees, const hsc_tree* const*
     if (!trees[d] || n_e[d] < 0 || (n_e[d] > 0 && !energies[d])) { set_error("bad device entry in hsc_solve_batch"); return HSC_E_ARG; }
   if (n_trees <= 1 || opts->guard_tau > 0.0 || guard)
     return solve_each(ctx, n_trees, trees, n_e, energies, opts, diag_gr, diag_gl, trans, spectral_lr, status, guard);
-  // one forest when every device has the same energies and lead model
+  // one forest when every device has the same energies and lead model (and per-site leads)
   const int ne = n_e[0];
   bool same = ne > 0;
+  for (int d = 0; d < n_trees && same; ++d) same = !trees[d]->dense;
   for (int d = 1; d < n_trees && same; ++d) same = n_e[d] == ne;
   for (int d = 1; d < n_trees && same; ++d)
     for (int k = 0; k < 2 && same; ++k) {

@@ -144,7 +144,8 @@ class Context:
 
     PROFILE_KINDS = ("assemble", "inv_panel", "inv_swap", "inv_unscramble", "gemm", "gather",
                      "assemble_n", "diag", "guard", "dd_assemble", "dd_inv_panel", "dd_inv_swap",
-                     "dd_inv_unscramble", "dd_gemm", "inv_super", "oz_split", "oz_gemm", "dd_inv_super")
+                     "dd_inv_unscramble", "dd_gemm", "inv_super", "oz_split", "oz_gemm", "dd_inv_super",
+                     "face_half", "face_sigma")
 
     def profile(self, enable: bool):
         check(lib().hsc_ctx_profile(self.h, 1 if enable else 0))
