@@ -160,6 +160,11 @@ def main():
     ap.add_argument("--guard-study", action="store_true",
                     help="measure the complex128 solve with the growth guard instead (256 energies in chunks of 32, "
                          "3D tree, leaf 8, tau 100), with its error at the stored energies")
+    ap.add_argument("--dense-steps", type=int, default=2,
+                    help="timed steps of the same cube with whole-face contacts (dense self-energy); 0 skips")
+    ap.add_argument("--dense-study", action="store_true",
+                    help="time per energy with whole-face (dense) and per-site (diagonal) contacts: cubes N^3 and "
+                         "elongated Nx x 16 x 16 devices")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run one elementwise device copy of MIB MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -185,6 +190,9 @@ def main():
         return
     if args.guard_study:
         guard_study(pkg, synth, np, torch, args)
+        return
+    if args.dense_study:
+        dense_study(pkg, synth, np, torch, args)
         return
 
     if args.calibrate_copy > 0:
@@ -297,6 +305,10 @@ def main():
             note(f"complex128 on the matrix cores, {name}: {rate:.2f} energies/s, k_zgemm {a0:.1f} TFLOP/s")
             del o0
 
+    dense = None
+    if args.dense_steps > 0:
+        dense = dense_leg(pkg, np, torch, ctx, dev, E, batch_of, want, kw, args, st)
+
     plain = None
     if not args.no_plain:
         sub = E[: max(1, args.plain_energies)]
@@ -369,11 +381,100 @@ def main():
                    "complex128_matrix_core_path": mfma,
                    "kernel_ms_one_step": {k: round(v["ms"], 3) for k, v in prof.items() if v["ms"] > 0},
                    "kernel_ms_total_one_step": round(total_ms, 3),
-                   "kernel_ms_one_step_by_phase": by_phase},
+                   "kernel_ms_one_step_by_phase": by_phase,
+                   "dense_contacts": dense},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def dense_leg(pkg, np, torch, ctx, dev, E, batch_of, want, kw, args, st):
+    """The same cube and energy walk with whole-face contacts: each x face couples to a semi-infinite
+    lead continuing the face lattice, so the contact self-energy is a dense face block."""
+    tree = pkg.Tree.from_device(dev, leaf_side=args.leaf, dense=True)
+    sd = tree.stats()
+    t_setup = time.perf_counter()
+    out = pkg.solve(ctx, tree, batch_of(0), want=want, **kw)
+    note(f"dense contacts: set-up {time.perf_counter() - t_setup:.1f} s")
+    pkg.solve(ctx, tree, batch_of(1), want=want, out=out, sync=True, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.dense_steps):
+        pkg.solve(ctx, tree, batch_of(k), want=want, out=out, sync=False, **kw)
+    ctx.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rate = args.batch * args.dense_steps / dt
+    ok = int(out["status"].abs().sum().item()) == 0
+    ctx.profile(True)
+    pkg.solve(ctx, tree, batch_of(0), want=want, out=out, sync=True, **kw)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    note(f"dense contacts: {rate:.2f} energies/s ({args.dense_steps} steps)")
+    acc = None
+    gpath = os.path.join(ROOT, "tests", "golden", "dense32_rgf.json")
+    if dev.n == 32 ** 3 and os.path.exists(gpath) and not args.no_golden:
+        gold = json.load(open(gpath))
+        grid = E.cpu().numpy()
+        idx = list(gold["energy_index"])
+        pad = idx + [idx[-1]] * (args.batch - len(idx) % args.batch if len(idx) % args.batch else 0)
+        og = pkg.solve(ctx, tree, E[pad], want=want, **kw)
+        n4 = len(idx)
+        acc = golden_errors(np, gold, og["gr"][:n4].cpu().numpy(), og["gl"][:n4].cpu().numpy(),
+                            og["trans"][:n4].cpu().numpy())
+        acc["status_ok"] = int(og["status"].abs().sum().item()) == 0
+        acc["oracle"] = "slab recursion with the dense face blocks (oracle/rgf.py), energies " + \
+                        ", ".join(f"{grid[i]:.4f}" for i in idx)
+        note(f"dense contacts: error vs stored oracle values: max {acc['max']:.2e}")
+        del og
+    return {"energies_per_s": rate, "energies_timed": args.batch * args.dense_steps, "status_ok": ok,
+            "flops_per_energy": sd["flops_per_energy"],
+            "flops_over_per_site_leads": sd["flops_per_energy"] / st["flops_per_energy"],
+            "whole_solve_tflops": rate * sd["flops_per_energy"] / 1e12,
+            "max_front": sd["max_front"], "clusters": sd["n_clusters"],
+            "kernel_ms_one_step": {k: round(v["ms"], 3) for k, v in prof.items() if v["ms"] > 0},
+            "accuracy_vs_oracle": acc}
+
+
+def dense_study(pkg, synth, np, torch, args):
+    """Time per energy with whole-face (dense) and per-site (diagonal) contact self-energies, the
+    cuboid experiments of Section 3.1.2: cubes N^3 (N = 16 .. 36) and elongated devices with fixed
+    16 x 16 faces and growing length (Nx = 16 .. 128), at --precision, batches of --batch energies."""
+    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=args.precision, complex3m=args.complex3m,
+              tune=0, batch=args.batch)
+    want = pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS
+    E = torch.tensor(np.linspace(-1.9, 1.9, args.batch), dtype=torch.float64, device="cuda:0")
+    rows = []
+    shapes = [(n, n, n) for n in (16, 24, 32, 36)] + [(nx, 16, 16) for nx in (16, 32, 64, 128)]
+    for shape in shapes:
+        dev = synth.cuboid(*shape, onsite=np.random.default_rng(0).uniform(-0.5, 0.5, shape[0] * shape[1] * shape[2]))
+        row = {"shape": list(shape), "sites": dev.n}
+        for name, dense in (("per_site", False), ("dense", True)):
+            ctx = pkg.Context(0)     # a context of its own: its plans (device memory) go with it
+            tree = pkg.Tree.from_device(dev, leaf_side=args.leaf, dense=dense)
+            out = pkg.solve(ctx, tree, E, want=want, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps = 2
+            for _ in range(reps):
+                pkg.solve(ctx, tree, E, want=want, out=out, sync=False, **kw)
+            ctx.sync()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / (reps * args.batch)
+            row[name] = {"ms_per_energy": dt * 1e3, "flops_per_energy": tree.stats()["flops_per_energy"],
+                         "tflops": tree.stats()["flops_per_energy"] / dt / 1e12,
+                         "status_ok": int(out["status"].abs().sum().item()) == 0}
+            del out, tree
+            ctx.close()
+        note(f"{shape}: per-site {row['per_site']['ms_per_energy']:.2f} ms, dense {row['dense']['ms_per_energy']:.2f} ms "
+             "per energy")
+        rows.append(row)
+    print(json.dumps({"metric": "ms per energy, whole-face vs per-site contacts", "value": rows[3]["dense"]["ms_per_energy"],
+                      "unit": "ms per energy (36^3, dense)", "higher_is_better": False, "n_gpus": 1,
+                      "dtype": "c128 in/out, complex double-double inside", "data": "synthetic",
+                      "config": {"energies_per_batch": args.batch, "precision": args.precision, "leaf_side": args.leaf},
+                      "rows": rows}), flush=True)
 
 
 def trilayer_study(pkg, synth, np, torch, args):

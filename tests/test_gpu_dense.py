@@ -140,3 +140,26 @@ def test_dense_guard_rejected(ctx):
     dev = _disordered((6, 4, 4), 1)
     with pytest.raises(pkg.hsc.HscError):
         gpu(ctx, dev, E_MIX[:2], 2, 1, guard_tau=100.0)
+
+
+@pytest.mark.parametrize("precision", [2, 3])
+def test_dense_cube32_golden_benchmark_configuration(ctx, precision):
+    # the 32^3 benchmark cube with whole-face contacts, in the benchmark's launch configuration
+    # (3D nested dissection, leaves <= 8, batches of 16, tuned tiles), against the slab recursion
+    # with the dense face blocks at four energies of the 256-point grid (all sites' diagonals were
+    # computed there; 68 are stored)
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "dense32_rgf.json")))
+    E, sites = np.array(gold["energies"]), np.array(gold["sites"])
+    ref = {"gr": np.array(gold["gr_re"]) + 1j * np.array(gold["gr_im"]),
+           "gl": np.array(gold["gl_re"]) + 1j * np.array(gold["gl_im"]),
+           "a_l": np.array(gold["a_l"]), "a_r": np.array(gold["a_r"]), "trans": np.array(gold["trans"])}
+    print(f"[dense cube32 golden precision {precision}]", flush=True)
+    Ep = np.tile(E, 4)                 # one batch of 16
+    g = gpu(ctx, synth.config1_device(), Ep, 8, precision, tune=1, batch=16)
+    gs = {k: g[k][:4, sites] for k in ("gr", "gl", "a_l", "a_r")}
+    gs["trans"], gs["status"] = g["trans"][:4], g["status"][:4]
+    print("dense 32^3 golden worst", check(gs, ref, E, TOL[precision]))
+    for k in ("gr", "gl", "trans"):    # every quarter of the batch solves the same energies
+        assert np.array_equal(g[k][:4], g[k][4:8]) and np.array_equal(g[k][:4], g[k][12:]), k
