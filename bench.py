@@ -46,6 +46,24 @@ DD_OPS_PER_CFLOP = DD_OPS_PER_CMAC / 8
 INT8_MFMA_PEAK_TOPS = 5000.0
 OZ_INT8_OPS_PER_CMAC = 3 * 136 * 2
 OZ_INT8_OPS_PER_CFLOP = OZ_INT8_OPS_PER_CMAC / 8
+# HBM traffic of k_oz_gemm per launch from two rocprofv3 --pmc passes over the same workload (the
+# benchmark cube, one set-up batch and one step of 16 energies, through the native driver
+# paper_1702_05167_amd/hsc_run; profiles/k_oz_gemm_cube32_nd8_counters.md), each scaled by what the
+# counter reads for a plain copy of 64 MiB (FETCH_SIZE 32781.5 KiB for 65536 KiB read, WRITE_SIZE
+# 65536 KiB for 65536 KiB written).  Valid only for the kernel source they were taken on.
+OZ_TRAFFIC = {"source": "paper_1702_05167_amd/csrc/ozaki.hip", "sha256": "b9d5f3451ba8877ecf056d7e00a56831e74e682ed7704fe211d6b99714da5942",
+              "fetch_kib_per_launch": 2425339.1, "write_kib_per_launch": 958349.1, "launches": 268,
+              "fetch_scale": 65536.0 / 32781.5, "write_scale": 65536.0 / 65536.0}
+
+
+def oz_traffic():
+    """Measured bytes per k_oz_gemm launch, or None when the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, OZ_TRAFFIC["source"])
+    if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != OZ_TRAFFIC["sha256"]:
+        return None
+    return 1024.0 * (OZ_TRAFFIC["fetch_kib_per_launch"] * OZ_TRAFFIC["fetch_scale"] +
+                     OZ_TRAFFIC["write_kib_per_launch"] * OZ_TRAFFIC["write_scale"])
 
 
 def note(msg):
@@ -80,7 +98,7 @@ def golden_errors(np, gold, gr_all, gl_all, tr_all):
             "out_of_band_max": max(x for x, b in zip(errs, band) if not b)}
 
 
-def roofline_of(prof, precision):
+def roofline_of(prof, precision, prof_bytes=None):
     """Algorithmic roofline of the dominant block-product kernel from per-kind launch timing
     (HIP events on the solver's stream): achieved = sum of 8 M N K over its launches / sum of
     their durations, against the FP64 matrix-core peak."""
@@ -89,10 +107,14 @@ def roofline_of(prof, precision):
     if go["ms"] > max(gd["ms"], g["ms"]):
         ach = go["flops"] / (go["ms"] * 1e-3) / 1e12
         i8 = ach * OZ_INT8_OPS_PER_CFLOP
+        alg_bytes = prof_bytes["oz_gemm"] / go["launches"] if prof_bytes and go["launches"] else None
+        traffic = oz_traffic()
         return {"bound": "mfma", "kernel": "k_oz_gemm (complex double-double products from 8-bit slices, "
                                            "integer matrix cores)",
                 "achieved": ach, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_MFMA_PEAK_TFLOPS,
-                "traffic": None, "flop_count": "8 M N K per complex product (algorithmic)",
+                "traffic": traffic, "flop_count": "8 M N K per complex product (algorithmic)",
+                "algorithmic_bytes_per_launch": alg_bytes,
+                "traffic_over_algorithmic": traffic / alg_bytes if traffic and alg_bytes else None,
                 "launches": int(go["launches"]), "avg_launch_ms": go["ms"] / go["launches"],
                 "flops_per_launch": go["flops"] / go["launches"],
                 "share_of_kernel_time": go["ms"] / total_ms,
@@ -165,6 +187,9 @@ def main():
     ap.add_argument("--dense-study", action="store_true",
                     help="time per energy with whole-face (dense) and per-site (diagonal) contacts: cubes N^3 and "
                          "elongated Nx x 16 x 16 devices")
+    ap.add_argument("--write-device", metavar="PATH",
+                    help="write the benchmark cube (--n-side) and its energy grid (--energies) as a device file "
+                         "for the native driver paper_1702_05167_amd/hsc_run, then exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run one elementwise device copy of MIB MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -175,8 +200,12 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
     import synth
+    if args.write_device:
+        write_device(np, synth.config1_device(n_side=args.n_side), np.linspace(-6.0, 6.0, args.energies),
+                     args.write_device)
+        return
+    import torch
     import paper_1702_05167_amd as pkg
 
     if args.learned_grid:
@@ -250,9 +279,10 @@ def main():
     ctx.profile(True)
     pkg.solve(ctx, tree, batch_of(0), want=want, out=out, sync=True, **kw)
     prof = ctx.profile_read()
+    prof_bytes = ctx.profile_bytes()
     launches = ctx.profile_launches()
     ctx.profile(False)
-    roof = roofline_of(prof, args.precision)
+    roof = roofline_of(prof, args.precision, prof_bytes)
     by_phase = {}
     for kind, fl, ms, ph in launches:
         key = f"{ctx.PROFILE_PHASES[int(ph)]}/{ctx.PROFILE_KINDS[int(kind)]}"
@@ -387,6 +417,24 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def write_device(np, dev, energies, path):
+    """Device file of the native driver (layout documented in csrc/hsc_run.cpp)."""
+    with open(path, "wb") as f:
+        f.write(b"HSCDEV1\0")
+        np.array([dev.n, len(dev.indices)], np.int64).tofile(f)
+        np.asarray(dev.indptr, np.int64).tofile(f)
+        np.asarray(dev.indices, np.int32).tofile(f)
+        np.ascontiguousarray(np.asarray(dev.values, np.complex128)).view(np.float64).tofile(f)
+        np.ascontiguousarray(dev.coords, np.int32).tofile(f)
+        for c in dev.contacts:
+            np.array([len(c.sites)], np.int64).tofile(f)
+            np.asarray(c.sites, np.int64).tofile(f)
+            np.array([c.lead_onsite, c.lead_hopping, c.coupling], np.float64).tofile(f)
+        np.array([len(energies)], np.int64).tofile(f)
+        np.asarray(energies, np.float64).tofile(f)
+    note(f"device file {path}: {dev.n} sites, {len(energies)} energies")
 
 
 def dense_leg(pkg, np, torch, ctx, dev, E, batch_of, want, kw, args, st):

@@ -240,8 +240,8 @@ hsc_status hsc_solve(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, const doub
                      double* spectral_lr, int32_t* status, double* guard);
 
 /* Solve several devices in one call.  Arrays are indexed by device; entries
- * follow hsc_solve.  When every device has the same energy list, the same lead
- * model and the guard is off, consecutive devices are packed into forests
+ * follow hsc_solve.  When every device has the same energy list, the same
+ * per-site lead model and the guard is off, consecutive devices are packed into forests
  * (hsc_tree_concat) whose workspace per energy slot fits about a ninth of the
  * free device memory: one plan per forest, every level's clusters of all its
  * devices in the same launches, outputs staged in device memory and copied to
@@ -286,6 +286,11 @@ hsc_status hsc_totals(hsc_ctx* ctx, int32_t n_e, int64_t n, const void* diag_gr,
  * Errors: HSC_E_ARG. */
 hsc_status hsc_ctx_profile(hsc_ctx* ctx, int32_t enable);
 hsc_status hsc_ctx_profile_read(hsc_ctx* ctx, double* out, int32_t n_kinds);
+/* out[k] = algorithmic bytes of the timed launches of kind k since profiling was enabled (so far
+ * counted for the slice products, kind 16: slices of both operands read, 48 B per complex
+ * element; row and column scales; the double-double result written, its rounded copy, and C when
+ * accumulating); 0 for kinds not counted.  Errors: HSC_E_ARG. */
+hsc_status hsc_ctx_profile_bytes(hsc_ctx* ctx, double* out, int32_t n_kinds);
 
 /* Launch-by-launch record of the timed launches since hsc_ctx_profile(ctx, 1)
  * (after hsc_sync): out[4k] = kind (as in hsc_ctx_profile_read), out[4k+1] =

@@ -37,6 +37,14 @@ def build(verbose: bool = False) -> str:
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    # the native driver of the C ABI (hardware-counter passes without a Python process)
+    run = os.path.join(HERE, "hsc_run")
+    cmd = [hipcc, *FLAGS, "-x", "hip", os.path.join(CSRC, "hsc_run.cpp"), "-L", HERE, "-lhsc",
+           "-Wl,-rpath,$ORIGIN", "-o", run + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(run + ".tmp", run)
     return LIB
 
 

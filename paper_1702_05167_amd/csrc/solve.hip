@@ -87,6 +87,7 @@ struct Step {
   int out = 0;                // DIAG destination
   int dd = 0;                 // row kernels: operands in double-double
   double flops = 0;           // algorithmic real flops of this launch (GEMM: 8 M N K)
+  double bytes = 0;           // algorithmic bytes of this launch (slice products: operands read, result written)
   int phase = 0;              // part of the method (Phase), for launch timing
 };
 
@@ -153,10 +154,11 @@ struct hsc_ctx {
   // optional per-launch timing: events around every launch, grouped by step kind
   bool profile = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
-  struct EvMeta { int kind; double flops; int phase; };
+  struct EvMeta { int kind; double flops; int phase; double bytes; };
   std::vector<EvMeta> ev_meta;                    // per recorded launch
   size_t ev_used = 0;
   double prof[24][3] = {};                        // kind -> launches, ms, flops (24 >= number of kinds)
+  double prof_bytes[24] = {};                     // kind -> algorithmic bytes
   hipStream_t cap_stream = nullptr;               // graph capture (a stream of its own, default priority)
   std::vector<double> launch_log;                 // (kind, flops, ms, phase) per timed launch since profiling was enabled
   // merged trees of the growth guard: key (tree uid, merged cluster ids), most recent last
@@ -615,7 +617,7 @@ struct Builder {
       std::vector<int32_t> tmap;
       std::map<std::tuple<const void*, int64_t, int64_t, int, int>, std::pair<size_t, size_t>> seen;
       size_t cur = 0, i = i0;
-      double flops = 0;
+      double flops = 0, bytes = 0;
       // slices of one operand: in the step's scratch (offsets rebased later, `kept` false) or in a
       // workspace buffer kept for later products (absolute addresses, split by the first step using it)
       std::vector<char> kept_job;   // per split job: writes a kept buffer
@@ -674,6 +676,10 @@ struct Builder {
         for (int k = 0; k < tiles; ++k) tmap.push_back((int32_t)gp.size());
         gp.push_back(p);
         flops += 8.0 * g.M * g.N * g.K;
+        // slices of op(A) and op(B) (3 parts x 16 slices of one byte per complex element), their
+        // scales, the double-double result (and its rounded copy), C when accumulating
+        bytes += 48.0 * ((double)g.M * g.K + (double)g.K * g.N) + 4.0 * (g.M + g.N) +
+                 (double)g.M * g.N * (32.0 + (g.D64 ? 16.0 : 0.0) + (beta ? 32.0 : 0.0));
       }
       oz_need = std::max(oz_need, cur);
       if (!sj.empty()) {
@@ -709,6 +715,7 @@ struct Builder {
         s.i1 = negate;
         s.beta = beta;
         s.flops = flops;
+        s.bytes = bytes;
         push(s);
       }
       i0 = i;
@@ -1336,6 +1343,7 @@ hsc_status fold_events(hsc_ctx* ctx) {
     ctx->prof[kind][0] += 1;
     ctx->prof[kind][1] += ms;
     ctx->prof[kind][2] += ctx->ev_meta[k].flops;
+    ctx->prof_bytes[kind] += ctx->ev_meta[k].bytes;
     if (ctx->launch_log.size() < 4 * (size_t)4000000) {
       ctx->launch_log.push_back(kind);
       ctx->launch_log.push_back(ctx->ev_meta[k].flops);
@@ -1393,11 +1401,11 @@ int run_steps(hsc_ctx* ctx, hipStream_t st, Plan* pl, int e_base, int nvalid, vo
         HIPCHK(hipEventCreate(&a));
         HIPCHK(hipEventCreate(&b));
         ctx->ev_pool.push_back({a, b});
-        ctx->ev_meta.push_back({0, 0.0, 0});
+        ctx->ev_meta.push_back({0, 0.0, 0, 0.0});
       }
       HIPCHK(hipEventRecord(ctx->ev_pool[ctx->ev_used].first, st));
       ev1 = ctx->ev_pool[ctx->ev_used].second;
-      ctx->ev_meta[ctx->ev_used] = {(int)s.kind, s.flops, s.phase};
+      ctx->ev_meta[ctx->ev_used] = {(int)s.kind, s.flops, s.phase, s.bytes};
       ctx->ev_used++;
     }
     const void* jobs = pl->blob + s.jobs;
@@ -2238,7 +2246,14 @@ hsc_status hsc_ctx_profile(hsc_ctx* ctx, int32_t enable) {
   ctx->profile = enable != 0;
   ctx->ev_used = 0;
   std::memset(ctx->prof, 0, sizeof(ctx->prof));
+  std::memset(ctx->prof_bytes, 0, sizeof(ctx->prof_bytes));
   ctx->launch_log.clear();
+  return HSC_OK;
+}
+
+hsc_status hsc_ctx_profile_bytes(hsc_ctx* ctx, double* out, int32_t n_kinds) {
+  if (!ctx || !out || n_kinds < 0) { set_error("bad arguments"); return HSC_E_ARG; }
+  for (int k = 0; k < n_kinds && k < kStepKinds; ++k) out[k] = ctx->prof_bytes[k];
   return HSC_OK;
 }
 

@@ -74,6 +74,7 @@ def lib():
     L.hsc_sync.argtypes = [vp]
     L.hsc_ctx_profile.argtypes = [vp, i32]
     L.hsc_ctx_profile_read.argtypes = [vp, vp, i32]
+    L.hsc_ctx_profile_bytes.argtypes = [vp, vp, i32]
     L.hsc_ctx_profile_launches.argtypes = [vp, i64, vp, C.POINTER(i64)]
     L.hsc_kern_zgemm.argtypes = [vp, i32, i32, i32, i32, i32, dbl, dbl, vp, i32, vp, i32, i32, vp, i32, vp, i32]
     L.hsc_kern_zgemm_tile.argtypes = [vp, i32, i32, i32, i32, i32, i32, dbl, dbl, vp, i32, vp, i32, i32, vp, i32, vp,
@@ -97,7 +98,7 @@ def lib():
     for name in ("hsc_ctx_create", "hsc_ctx_destroy", "hsc_tree_build", "hsc_tree_merge", "hsc_tree_concat",
                  "hsc_tree_stats_get",
                  "hsc_tree_export", "hsc_tree_destroy", "hsc_solve", "hsc_solve_batch", "hsc_sync",
-                 "hsc_ctx_profile", "hsc_ctx_profile_read", "hsc_ctx_profile_launches",
+                 "hsc_ctx_profile", "hsc_ctx_profile_read", "hsc_ctx_profile_bytes", "hsc_ctx_profile_launches",
                  "hsc_kern_zgemm", "hsc_kern_zgemm_tile", "hsc_kern_zgemm_dd", "hsc_kern_zgemm_dd_noalloc",
                  "hsc_kern_zinv_batched",
                  "hsc_kern_zinv_dd",
@@ -146,6 +147,13 @@ class Context:
                      "assemble_n", "diag", "guard", "dd_assemble", "dd_inv_panel", "dd_inv_swap",
                      "dd_inv_unscramble", "dd_gemm", "inv_super", "oz_split", "oz_gemm", "dd_inv_super",
                      "face_half", "face_sigma")
+
+    def profile_bytes(self) -> dict:
+        """Algorithmic bytes per launch kind since profiling was enabled (slice products only)."""
+        k = len(self.PROFILE_KINDS)
+        buf = np.zeros(k)
+        check(lib().hsc_ctx_profile_bytes(self.h, _ptr(buf), k))
+        return {name: float(buf[i]) for i, name in enumerate(self.PROFILE_KINDS)}
 
     def profile(self, enable: bool):
         check(lib().hsc_ctx_profile(self.h, 1 if enable else 0))
