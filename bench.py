@@ -187,6 +187,8 @@ def main():
     ap.add_argument("--dense-study", action="store_true",
                     help="time per energy with whole-face (dense) and per-site (diagonal) contacts: cubes N^3 and "
                          "elongated Nx x 16 x 16 devices")
+    ap.add_argument("--orbital-study", action="store_true",
+                    help="time per energy of 10-orbital wires (4 x 4 and 6 x 6 sites across, lengths 32 .. 128)")
     ap.add_argument("--write-device", metavar="PATH",
                     help="write the benchmark cube (--n-side) and its energy grid (--energies) as a device file "
                          "for the native driver paper_1702_05167_amd/hsc_run, then exit")
@@ -222,6 +224,9 @@ def main():
         return
     if args.dense_study:
         dense_study(pkg, synth, np, torch, args)
+        return
+    if args.orbital_study:
+        orbital_study(pkg, synth, np, torch, args)
         return
 
     if args.calibrate_copy > 0:
@@ -523,6 +528,44 @@ def dense_study(pkg, synth, np, torch, args):
                       "dtype": "c128 in/out, complex double-double inside", "data": "synthetic",
                       "config": {"energies_per_batch": args.batch, "precision": args.precision, "leaf_side": args.leaf},
                       "rows": rows}), flush=True)
+
+
+def orbital_study(pkg, synth, np, torch, args):
+    """Multi-orbital site blocks (10 orbitals per site, random blocks: the block structure of the
+    paper's sp3d5s* nanowires): wires of 4 x 4 and 6 x 6 sites across and 32 .. 128 sites long, per-site
+    leads on every orbital of the end faces, at --precision, batches of --batch energies in [-4, 4]."""
+    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=args.precision, complex3m=args.complex3m,
+              tune=0, batch=args.batch)
+    want = pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS
+    E = torch.tensor(np.linspace(-4.0, 4.0, args.batch), dtype=torch.float64, device="cuda:0")
+    rows = []
+    for cross in (4, 6):
+        for length in (32, 64, 128):
+            dev = synth.orbital_cuboid(length, cross, cross, 10, seed=length + cross)
+            ctx = pkg.Context(0)
+            tree = pkg.Tree.from_device(dev, leaf_side=2)
+            st = tree.stats()
+            out = pkg.solve(ctx, tree, E, want=want, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(2):
+                pkg.solve(ctx, tree, E, want=want, out=out, sync=False, **kw)
+            ctx.sync()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / (2 * args.batch)
+            rows.append({"sites": [length, cross, cross], "orbitals": 10, "unknowns": dev.n,
+                         "ms_per_energy": dt * 1e3, "flops_per_energy": st["flops_per_energy"],
+                         "tflops": st["flops_per_energy"] / dt / 1e12, "max_cluster": st["max_cluster"],
+                         "status_ok": int(out["status"].abs().sum().item()) == 0})
+            note(f"10-orbital wire {length} x {cross} x {cross} ({dev.n} unknowns): {dt * 1e3:.2f} ms per energy, "
+                 f"{rows[-1]['tflops']:.2f} TFLOP/s")
+            del out, tree
+            ctx.close()
+    print(json.dumps({"metric": "ms per energy, 10-orbital wires", "value": rows[-1]["ms_per_energy"],
+                      "unit": "ms per energy (128 x 6 x 6 sites x 10 orbitals)", "higher_is_better": False,
+                      "n_gpus": 1, "dtype": "c128 in/out, complex double-double inside", "data": "synthetic",
+                      "config": {"energies_per_batch": args.batch, "precision": args.precision}, "rows": rows}),
+          flush=True)
 
 
 def trilayer_study(pkg, synth, np, torch, args):

@@ -8,6 +8,7 @@ functions).  Everything is deterministic given the seed.
 from .devices import (  # noqa: F401
     Device,
     cuboid,
+    orbital_cuboid,
     chain,
     trilayer,
     energy_grid,

@@ -98,6 +98,51 @@ def cuboid(nx: int, ny: int, nz: int, t: float = -1.0, onsite=None,
                   contacts, (0, 1, 2), {"grid": (nx, ny, nz), "t": t})
 
 
+def orbital_cuboid(nx: int, ny: int, nz: int, b: int, seed: int = 0, spread: float = 3.0,
+                   mix: float = 0.3, hop: float = 1.0, name: str | None = None) -> Device:
+    """Cuboid of sites with b orbitals each (multi-orbital site blocks, the shape of the paper's
+    sp3d5s* nanowire Hamiltonians; the blocks are random since the parameter set is not given).
+
+    Unknown index s = o + b * (x + Nx (y + Ny z)) (orbitals of a site consecutive); every orbital
+    carries its site's coordinates.  On-site block: orbital energies linspace(-spread, spread, b)
+    on the diagonal plus a symmetric N(0, mix^2) off-diagonal part; nearest-neighbour coupling along
+    axis d: a random b x b block T_d with N(0, (hop / sqrt(b))^2) entries from site i to site i + e_d,
+    and T_d^T back, so H is real symmetric.  Contacts: every orbital of the x = 0 / x = Nx-1 sites
+    couples to its own 1D lead (on-site 0, hopping -1, coupling -1)."""
+    rng = np.random.default_rng(seed)
+    nsite = nx * ny * nz
+    n = nsite * b
+    site = np.arange(nsite, dtype=np.int64)
+    x, y, z = site % nx, (site // nx) % ny, site // (nx * ny)
+    oo, pp = np.meshgrid(np.arange(b), np.arange(b), indexing="ij")
+    rows, cols, vals = [], [], []
+    for i in range(nsite):
+        m = rng.normal(0.0, mix, (b, b))
+        blk = np.triu(m, 1) + np.triu(m, 1).T + np.diag(np.linspace(-spread, spread, b))
+        rows.append(i * b + oo.ravel())
+        cols.append(i * b + pp.ravel())
+        vals.append(blk.ravel())
+    tblk = [rng.normal(0.0, hop / np.sqrt(b), (b, b)) for _ in range(3)]
+    for d, (stride, coord, size) in enumerate(((1, x, nx), (nx, y, ny), (nx * ny, z, nz))):
+        ok = coord + 1 < size
+        for i in site[ok]:
+            j = i + stride
+            rows.append(i * b + oo.ravel())
+            cols.append(j * b + pp.ravel())
+            vals.append(tblk[d].ravel())
+            rows.append(j * b + pp.ravel())
+            cols.append(i * b + oo.ravel())
+            vals.append(tblk[d].ravel())
+    indptr, indices, values = _csr_from_lists(n, np.concatenate(rows), np.concatenate(cols),
+                                              np.concatenate(vals).astype(np.complex128))
+    coords = np.repeat(np.stack([x, y, z], axis=1).astype(np.int32), b, axis=0)
+    left = (site[x == 0][:, None] * b + np.arange(b)).ravel()
+    right = (site[x == nx - 1][:, None] * b + np.arange(b)).ravel()
+    contacts = [Contact(left, 0.0, -1.0, -1.0), Contact(right, 0.0, -1.0, -1.0)]
+    return Device(name or f"orbital{nx}x{ny}x{nz}b{b}", n, indptr, indices, values, coords, contacts,
+                  (0, 1, 2), {"grid": (nx, ny, nz), "orbitals": b})
+
+
 def chain(m: int, t: float = -1.0, onsite=None) -> Device:
     """An m-site 1D chain; each end site couples to a semi-infinite lead."""
     return cuboid(m, 1, 1, t=t, onsite=onsite, name=f"chain{m}")

@@ -289,3 +289,16 @@ def test_dense_contact_tree_rejections():
     # the left contact may be the higher end: the tree is mirrored, the left face still heads its half
     t2 = build([contacts[1], contacts[0]])
     assert t2.stats()["n_clusters"] == t.stats()["n_clusters"]
+
+
+@pytest.mark.parametrize("shape,b,leaf", [((6, 4, 3), 4, 2), ((7, 3, 3), 10, 2), ((5, 5, 5), 2, 2)])
+def test_multi_orbital_tree(shape, b, leaf):
+    # b orbitals per site share the site's coordinates: every cluster holds whole sites
+    dev = synth.orbital_cuboid(*shape, b, seed=3)
+    ex = _check_tree(dev, pkg.Tree.from_device(dev, leaf_side=leaf))
+    perm, first, size = ex["perm"], ex["first"], ex["size"]
+    owner = np.empty(dev.n, np.int64)
+    for i in range(len(size)):
+        owner[perm[first[i]:first[i] + size[i]]] = i
+    assert (owner.reshape(-1, b) == owner.reshape(-1, b)[:, :1]).all()
+    assert (size % b == 0).all()
