@@ -19,7 +19,11 @@ import os
 import sys
 import time
 
-import numpy as np
+# one BLAS thread per worker process (forked workers of a threaded BLAS can spin)
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ[_v] = "1"
+
+import numpy as np  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))

@@ -148,3 +148,39 @@ def test_tuned_plan_equals_default(ctx):
     for k in a:
         for x in (b[k], c[k]):
             assert np.allclose(x, a[k], rtol=1e-12, atol=1e-12 * np.abs(a[k]).max()), k
+
+
+@pytest.mark.parametrize("precision", [2, 3])
+def test_config2_devices_against_stored_oracle(ctx, precision):
+    # four of the 64 uneven cuboids (the smallest, 16 x 20 x 16, to the largest, 48 x 43 x 47 =
+    # 97,008 sites) in one hsc_solve_batch call on 3D trees with leaves <= 8, at two energies of the
+    # 128-point grid in the lead band and two outside it, against refined sparse-LU rows of G^r
+    # at 66 sites per device (tests/golden/make_config2.py)
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                       "config2_sampled.json")))
+    E = np.array(gold["energies"])
+    ids = [d["device"] for d in gold["devices"]]
+    devs = [synth.config2_devices(which=[i])[0] for i in ids]      # in the stored order
+    trees = [pkg.Tree.from_device(d, leaf_side=8) for d in devs]
+    print(f"[config2 precision {precision}]", flush=True)
+    outs = pkg.solve_batch(ctx, trees, torch.tensor(E, device=ctx.torch_device), precision=precision,
+                           want=pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS, **KW)
+    worst = 0.0
+    for d, o in zip(gold["devices"], outs):
+        sites = np.array(d["sites"])
+        ne = len(E)
+        ref_gr = (np.array(d["gr_re"]) + 1j * np.array(d["gr_im"])).reshape(ne, -1)
+        ref_gl = (np.array(d["gl_re"]) + 1j * np.array(d["gl_im"])).reshape(ne, -1)
+        gr = o["gr"].cpu().numpy()[:, sites]
+        gl = o["gl"].cpu().numpy()[:, sites]
+        tr = o["trans"].cpu().numpy()
+        assert (o["status"].cpu().numpy() == 0).all()
+        for e in range(ne):
+            errs = (rel(gr[e], ref_gr[e]), rel(gl[e], ref_gl[e]),
+                    abs(tr[e] - d["trans"][e]) / max(d["trans"][e], 1e-12))
+            worst = max(worst, *errs)
+            print("device", d["device"], d["sides"], "E", E[e], errs)
+            assert max(errs) <= 1e-10, (d["device"], E[e], errs)
+    print("config2 worst", worst)
