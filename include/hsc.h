@@ -50,7 +50,13 @@ enum {
   HSC_DIAG_GR = 1,        /* diag G^r                                          */
   HSC_DIAG_GL = 2,        /* diag G^< for Sigma^< = i(f_L Gamma_L + f_R Gamma_R) */
   HSC_TRANS = 4,          /* transmission T(E)                                 */
-  HSC_SPECTRAL_LR = 8     /* diag of A_L = G Gamma_L G^dagger and A_R, separately */
+  HSC_SPECTRAL_LR = 8,    /* diag of A_L = G Gamma_L G^dagger and A_R, separately */
+  /* The desired off-diagonal entries (Section 3: the timed quantities are the diagonal and the
+   * desired off-diagonal entries of G^r and G^<): the entries on every bond of H, i.e. every
+   * pair (i, j), i < j, with H_ij != 0, in the order of hsc_tree_bonds.  Bond currents follow
+   * from G^<_ij and H_ij.  Requested through hsc_solve_ex. */
+  HSC_BOND_GR = 16,       /* G^r_ij on every bond                              */
+  HSC_BOND_GL = 32        /* G^<_ij on every bond (G^<_ji = -conj(G^<_ij))      */
 };
 
 typedef struct hsc_ctx hsc_ctx;   /* one HIP device + one stream + workspaces; not thread-safe */
@@ -206,6 +212,12 @@ hsc_status hsc_tree_concat(int32_t n_trees, const hsc_tree* const* trees, hsc_tr
 
 hsc_status hsc_tree_stats_get(const hsc_tree* tree, hsc_tree_stats* out);
 
+/* Bonds of H: every pair (i, j), i < j, with a stored entry H_ij, ordered by i then j
+ * (duplicates of a pair count once).  With pairs == NULL only *count is set; otherwise pairs
+ * (host, int64[count][2]) receives them and *count must hold its capacity in pairs on entry.
+ * Errors: HSC_E_ARG (NULL tree or count, capacity too small). */
+hsc_status hsc_tree_bonds(const hsc_tree* tree, int64_t* pairs, int64_t* count);
+
 /* Export the tree (host buffers, sized from hsc_tree_stats_get):
  *   perm[n]            site at position p of the cluster ordering (post-order)
  *   cl_parent[nc]      parent cluster id (-1 for the root); ids are post-order
@@ -238,6 +250,30 @@ hsc_status hsc_tree_destroy(hsc_tree* tree);
 hsc_status hsc_solve(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, const double* energies,
                      const hsc_solve_opts* opts, void* diag_gr, void* diag_gl, double* trans,
                      double* spectral_lr, int32_t* status, double* guard);
+
+/* Outputs of hsc_solve_ex: the buffers of hsc_solve plus the bond entries.
+ *   bond_gr, bond_gl  device, complex[n_e][n_bonds] (HSC_BOND_GR / HSC_BOND_GL) or NULL; entry
+ *                     b of row e belongs to bond b of hsc_tree_bonds. */
+typedef struct {
+  void* diag_gr;
+  void* diag_gl;
+  double* trans;
+  double* spectral_lr;
+  int32_t* status;
+  double* guard;
+  void* bond_gr;
+  void* bond_gl;
+} hsc_outputs;
+
+/* hsc_solve with every output, the bond entries included.  Bond outputs are read from the blocks
+ * the two algorithms already form: a bond inside a separator (or root) from its diagonal block
+ * of G^r (Algorithm 1 extract) or of the combined lesser channel (Algorithm 2 extract); a bond
+ * between a cluster and an ancestor from the cluster's (own, front) block; a bond inside a leaf
+ * from A_ii^-1 + Psi G_f,i (resp. A_ii^-1 N_ii - Psi P_i,f^dagger) evaluated for that entry.
+ * Bond outputs do not combine with the growth guard (HSC_E_ARG) and switch graph replay off.
+ * Errors as hsc_solve. */
+hsc_status hsc_solve_ex(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, const double* energies,
+                        const hsc_solve_opts* opts, const hsc_outputs* out);
 
 /* Solve several devices in one call.  Arrays are indexed by device; entries
  * follow hsc_solve.  When every device has the same energy list, the same

@@ -7,6 +7,9 @@ Per energy E:
   G^<_ii = i (f_L A_L,ii + f_R A_R,ii)                             (Eq. 2)
   T = sum_{i in L, j in R} Gamma_L,i |G_ij|^2 Gamma_R,j            (Caroli)
   A_eta,ii = 2 eta sum_k |G_ik|^2   (the broadening that eta itself adds)
+Bond entries (bonds(): the desired off-diagonal entries, pairs (i, j) with H_ij != 0):
+  G^r_ij from the same inverse; G^<_ij = i sum_c f_c (G_i,c V_c) . conj(G_j,c V_c)   (Eq. 2 entrywise)
+with Gamma_c = V_c V_c^T (V_c = diag(sqrt(Gamma_c,k)) for per-site leads).
 With dense=True each contact is a whole face with the dense self-energy block
 of face.face_sigma (the DENSE case); then, with Gamma_c = V_c V_c^T,
   A_c,ii = || G_i,c V_c ||^2,    T = || V_L^T G_LR V_R ||_F^2  (= Tr Gamma_L G Gamma_R G^dagger)
@@ -95,4 +98,31 @@ def _solve_dense(dev, energies, eta, kT, mu_L, mu_R):
         out["a_eta"][e] = 2.0 * eta * (np.abs(g) ** 2).sum(axis=1)
         out["gl"][e] = 1j * (fl[e] * a_l + fr[e] * a_r)
         out["trans"][e] = (np.abs(v_l.T @ g[np.ix_(ls, rs)] @ v_r) ** 2).sum()
+    return out
+
+
+def bonds(dev, energies, eta, kT, mu_L, mu_R, pairs, dense=False):
+    """G^r and G^< at the given (i, j) pairs for each energy (complex [n_e, n_pairs] each)."""
+    energies = np.asarray(energies, dtype=np.float64)
+    pairs = np.asarray(pairs, dtype=np.int64)
+    h = dev.dense_h()
+    fl = fermi(energies, mu_L, kT)
+    fr = fermi(energies, mu_R, kT)
+    out = {"gr": np.zeros((len(energies), len(pairs)), np.complex128),
+           "gl": np.zeros((len(energies), len(pairs)), np.complex128)}
+    i, j = pairs[:, 0], pairs[:, 1]
+    for e, en in enumerate(energies):
+        z = en + 1j * eta
+        g = np.linalg.inv(system_matrix(dev, z, h, dense))
+        out["gr"][e] = g[i, j]
+        acc = np.zeros(len(pairs), np.complex128)
+        for k, (c, f) in enumerate(zip(dev.contacts, (fl[e], fr[e]))):
+            cs = np.asarray(c.sites, dtype=np.int64)
+            if dense:
+                v = face_sigma(dev, k, z)[1]
+            else:
+                v = np.diag(np.sqrt(gamma_of(contact_sigmas(dev, z)[k][1])))
+            gv = g[:, cs] @ v
+            acc += f * np.sum(gv[i] * np.conj(gv[j]), axis=1)
+        out["gl"][e] = 1j * acc
     return out

@@ -80,5 +80,7 @@ namespace hsc {
 // `sites_of[i]` are the original site ids of cluster i (any order).
 int finalize_tree(hsc_tree* t, std::vector<std::vector<int64_t>>& sites_of);
 double flops_per_energy(const hsc_tree* t, uint32_t want);
+// bonds of H: pairs (i, j), i < j, with a stored H_ij, by i then j, duplicates once
+std::vector<int64_t> tree_bonds(const hsc_tree* t);
 double bytes_per_energy(const hsc_tree* t, uint32_t want);
 }  // namespace hsc

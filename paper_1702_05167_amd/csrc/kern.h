@@ -165,6 +165,30 @@ struct FaceTransJob {
 };
 void launch_face_trans(hipStream_t st, const FaceTransJob* jobs, int nvalid, int e_base, double* trans);
 
+// ---- bond entries of G^r and G^< (off-diagonal entries on the bonds of H) ----
+// Source of one bond entry, fixed per plan: cluster c, own row a, and
+//   mode 0 (separator or root): X[a][col] of its G block (GX, columns colg) or lesser block
+//          (PX, columns colp);
+//   mode 1 (leaf, both sites its own, col = b): G = Inv_ab + sum_j Psi_aj GT_bj,
+//          P = M_ab - sum_j Psi_aj conj(PT_bj)  (M absent: 0);
+//   mode 2 (leaf, front site k = col): G = GT_ak, P = PT_ak.
+// flip: the bond (i, j) is the transpose of the stored (row, col): G^r is symmetric (same value),
+// G^< anti-Hermitian (-conj).
+struct BondRef {
+  int32_t c, a, colg, colp, mode, flip;
+};
+// blocks of one (cluster, slot) a bond entry reads (element type double2 or zdd)
+struct BondSrc {
+  const void* X;      // mode 0: GX / PX; leaves: unused
+  const void* d;      // leaves: A_ii^-1 (G) or M (P, may be null)
+  const void* psi;    // leaves: Psi (n x f)
+  const void* xt;     // leaves: GT / PT (n x f)
+  int32_t ld, n, f, ldd;
+};
+// out[(e_base + slot) * nbonds + b] for slots < nvalid; lesser = 1 applies the anti-Hermitian flip
+void launch_bonds(hipStream_t st, const BondRef* refs, int nbonds, const BondSrc* src, int nslots, int nvalid,
+                  int e_base, int lesser, int dd, double2* out);
+
 // Batched blocked Gauss-Jordan inversion.
 void launch_inv_panel(hipStream_t st, const InvJob* jobs, int njobs, int k0, int nb, int max_n,
                       int32_t* status);

@@ -522,6 +522,48 @@ void launch_trans(hipStream_t st, const double* a_r, int64_t ld, const int64_t* 
                      trans);
 }
 
+// bond entries (see BondRef); one thread per (bond, slot)
+__device__ inline double2 bz_mul(double2 a, double2 b) { return cmul(a, b); }
+__device__ inline zdd bz_mul(zdd a, zdd b) { return zdd_mul(a, b); }
+__device__ inline double2 bz_add(double2 a, double2 b) { return cadd(a, b); }
+__device__ inline zdd bz_add(zdd a, zdd b) { return zdd_add(a, b); }
+__device__ inline double2 bz_conj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ inline zdd bz_conj(zdd a) { return zdd{a.re, dd_neg(a.im)}; }
+__device__ inline double2 bz_neg(double2 a) { return make_double2(-a.x, -a.y); }
+__device__ inline zdd bz_neg(zdd a) { return zdd_neg(a); }
+__device__ inline double2 bz_round(double2 a) { return a; }
+__device__ inline double2 bz_round(zdd a) { return zdd_round(a); }
+template <class T> __device__ inline T bz_zero();
+template <> __device__ inline double2 bz_zero<double2>() { return make_double2(0.0, 0.0); }
+template <> __device__ inline zdd bz_zero<zdd>() { return zdd_zero(); }
+
+template <class T, int LESSER>
+__global__ __launch_bounds__(256) void k_bonds(const BondRef* __restrict__ refs, int nbonds,
+                                               const BondSrc* __restrict__ src, int nslots, int nvalid, int e_base,
+                                               double2* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = blockIdx.y;
+  if (b >= nbonds || e >= nvalid) return;
+  const BondRef r = refs[b];
+  const BondSrc& s = src[(int64_t)r.c * nslots + e];
+  const int col = LESSER ? r.colp : r.colg;
+  T v;
+  if (r.mode == 0) {
+    v = reinterpret_cast<const T*>(s.X)[(int64_t)r.a * s.ld + col];
+  } else if (r.mode == 2) {
+    v = reinterpret_cast<const T*>(s.xt)[(int64_t)r.a * s.f + col];
+  } else {
+    const T* psi = reinterpret_cast<const T*>(s.psi) + (int64_t)r.a * s.f;
+    const T* xt = reinterpret_cast<const T*>(s.xt) + (int64_t)col * s.f;
+    T acc = bz_zero<T>();
+    for (int j = 0; j < s.f; ++j) acc = bz_add(acc, bz_mul(psi[j], LESSER ? bz_conj(xt[j]) : xt[j]));
+    const T d = s.d ? reinterpret_cast<const T*>(s.d)[(int64_t)r.a * s.ldd + col] : bz_zero<T>();
+    v = LESSER ? bz_add(d, bz_neg(acc)) : bz_add(d, acc);
+  }
+  if (LESSER && r.flip) v = bz_neg(bz_conj(v));
+  out[(int64_t)(e_base + e) * nbonds + b] = bz_round(v);
+}
+
 void launch_face_half(hipStream_t st, const FaceJob* jobs, int njobs, int max_d1, int max_d2,
                       const EnergyScalars* es) {
   if (njobs <= 0 || max_d1 <= 0) return;
@@ -537,6 +579,19 @@ void launch_face_sigma(hipStream_t st, const FaceJob* jobs, int njobs, int max_f
 void launch_face_trans(hipStream_t st, const FaceTransJob* jobs, int nvalid, int e_base, double* trans) {
   if (nvalid <= 0) return;
   hipLaunchKernelGGL(k_face_trans, dim3(nvalid), dim3(256), 0, st, jobs, nvalid, e_base, trans);
+}
+
+void launch_bonds(hipStream_t st, const BondRef* refs, int nbonds, const BondSrc* src, int nslots, int nvalid,
+                  int e_base, int lesser, int dd, double2* out) {
+  if (nbonds <= 0 || nvalid <= 0 || !out) return;
+  const dim3 grid((unsigned)((nbonds + 255) / 256), nvalid);
+  if (dd) {
+    if (lesser) hipLaunchKernelGGL((k_bonds<zdd, 1>), grid, dim3(256), 0, st, refs, nbonds, src, nslots, nvalid, e_base, out);
+    else hipLaunchKernelGGL((k_bonds<zdd, 0>), grid, dim3(256), 0, st, refs, nbonds, src, nslots, nvalid, e_base, out);
+  } else {
+    if (lesser) hipLaunchKernelGGL((k_bonds<double2, 1>), grid, dim3(256), 0, st, refs, nbonds, src, nslots, nvalid, e_base, out);
+    else hipLaunchKernelGGL((k_bonds<double2, 0>), grid, dim3(256), 0, st, refs, nbonds, src, nslots, nvalid, e_base, out);
+  }
 }
 
 void launch_combine_gl(hipStream_t st, const double* spec, int nvalid, int e_base, int64_t n,

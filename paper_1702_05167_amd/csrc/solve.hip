@@ -63,8 +63,8 @@ struct Blob {
 
 enum StepKind { S_ASSEMBLE, S_INV_PANEL, S_INV_SWAP, S_INV_UNSCR, S_GEMM, S_GATHER, S_ASSEMBLE_N, S_DIAG, S_GUARD,
                 S_DD_ASSEMBLE, S_DD_INV_PANEL, S_DD_INV_SWAP, S_DD_INV_UNSCR, S_DD_GEMM, S_INV_SUPER,
-                S_OZ_SPLIT, S_OZ_GEMM, S_DD_INV_SUPER, S_FACE_HALF, S_FACE_SIGMA};
-constexpr int kStepKinds = 20;
+                S_OZ_SPLIT, S_OZ_GEMM, S_DD_INV_SUPER, S_FACE_HALF, S_FACE_SIGMA, S_BONDS};
+constexpr int kStepKinds = 21;
 
 // Tile sizes a plan keeps GEMM problem lists and tile maps for: 64x64, 128x64, 64x128, 32x32,
 // 128x128.  Every launch kind of launch_gemm uses one of them (tile_dims_of).
@@ -94,7 +94,10 @@ struct Step {
 // parts of the method a step belongs to (reported with every timed launch)
 enum Phase { PH_OTHER = 0, PH_INVERSE = 1, PH_FOLD = 2, PH_EXTRACT_G = 3, PH_FOLD_N = 4, PH_EXTRACT_P = 5 };
 
-enum OutSel { O_GR = 0, O_GL = 1, O_SPEC_L = 2, O_SPEC_R = 3, O_AR_TMP = 4 };
+enum OutSel { O_GR = 0, O_GL = 1, O_SPEC_L = 2, O_SPEC_R = 3, O_AR_TMP = 4, O_NONE = 5 };
+
+// at most three lesser channels per plan (spectral L and R plus the combined one for bonds)
+constexpr int kMaxChannels = 3;
 
 // largest dense cluster block the batched inversion handles (512 threads x 8 rows)
 constexpr int kMaxCluster = 4096;
@@ -206,7 +209,8 @@ struct Builder {
   struct CS {
     size_t F, Inv, Psi, GX, GFF, GT, GAF, SD, piv, T, R;
     size_t Fd, Invd, Psid, Td, Rd;   // double-double fold
-    size_t NF[2], NFc[2], M[2], PX[2], PFF[2], PT[2];
+    size_t NF[kMaxChannels], NFc[kMaxChannels], M[kMaxChannels], PX[kMaxChannels], PFF[kMaxChannels],
+        PT[kMaxChannels];
     // 8-bit slices of operands used by several products (precision 3): Psi (rows n, depth f),
     // Psi^T and A_ii^-1 of separators (rows f / n, depth n); 0 = none
     size_t PsiS, PsiTS, InvS;
@@ -258,8 +262,10 @@ struct Builder {
     if (want & HSC_SPECTRAL_LR) {
       chans.push_back({1, 1, 0, O_SPEC_L});
       chans.push_back({2, 2, 0, O_SPEC_R});
+      // bond entries of G^< come from the combined channel's blocks
+      if (want & HSC_BOND_GL) chans.push_back({0, 0, 0, O_NONE});
     } else {
-      if (want & HSC_DIAG_GL) chans.push_back({0, 0, 0, O_GL});
+      if (want & (HSC_DIAG_GL | HSC_BOND_GL)) chans.push_back({0, 0, 0, (want & HSC_DIAG_GL) ? O_GL : O_NONE});
       if (want & HSC_TRANS) chans.push_back({2, 2, 1, O_AR_TMP});
     }
   }
@@ -962,6 +968,97 @@ struct Builder {
     return blob.push(tj);
   }
 
+  // bond entries of G^r (lesser = 0, after the extraction of Algorithm 1) or of the combined
+  // lesser channel chan (lesser = 1, after its extraction): BondRef per bond, BondSrc per
+  // (cluster, slot)
+  size_t bond_refs = 0;
+  int nbonds = 0;
+  void make_bond_refs() {
+    const std::vector<int64_t> bl = tree_bonds(t);
+    nbonds = (int)(bl.size() / 2);
+    std::vector<BondRef> refs(nbonds);
+    std::vector<std::vector<std::pair<int64_t, int>>> fidx(t->cl.size());   // sorted (site, front index)
+    for (size_t i = 0; i < t->cl.size(); ++i) {
+      const Cluster& c = t->cl[i];
+      for (int k = 0; k < c.f(); ++k) fidx[i].push_back({c.front[k], k});
+      std::sort(fidx[i].begin(), fidx[i].end());
+    }
+    for (int q = 0; q < nbonds; ++q) {
+      const int64_t si = bl[2 * q], sj = bl[2 * q + 1];
+      const int ci = t->owner[si], cj = t->owner[sj];
+      BondRef r{};
+      if (ci == cj) {
+        const Cluster& c = t->cl[ci];
+        r.c = ci;
+        r.a = (int)(t->pos[si] - c.first);
+        r.colg = r.colp = (int)(t->pos[sj] - c.first);
+        r.mode = (leaf(ci) && !root(ci)) ? 1 : 0;
+      } else {
+        // the descendant cluster holds the other site in its front (post-order: lower id)
+        const int c = std::min(ci, cj);
+        const int64_t own = c == ci ? si : sj, other = c == ci ? sj : si;
+        const Cluster& cl = t->cl[c];
+        auto it = std::lower_bound(fidx[c].begin(), fidx[c].end(), std::make_pair(other, -1));
+        const int k = it->second;
+        r.c = c;
+        r.a = (int)(t->pos[own] - cl.first);
+        r.flip = c == ci ? 0 : 1;
+        if (leaf(c) && !root(c)) {
+          r.mode = 2;
+          r.colg = r.colp = k;
+        } else {
+          r.mode = 0;
+          r.colg = cl.n + (cp(c) ? cl.frontpos[k] : k);
+          r.colp = cl.n + k;
+        }
+      }
+      refs[q] = r;
+    }
+    bond_refs = blob.push(refs);
+  }
+  template <class T>
+  void bond_step(int lesser, int chan) {
+    if (!(want & (lesser ? HSC_BOND_GL : HSC_BOND_GR))) return;
+    if (!bond_refs) make_bond_refs();
+    const int nc = (int)t->cl.size();
+    std::vector<BondSrc> tab((size_t)nc * B);
+    for (int i = 0; i < nc; ++i) {
+      const int n = n_of(i), f = f_of(i);
+      for (int e = 0; e < B; ++e) {
+        const CS& s = cs[(size_t)i * B + e];
+        BondSrc b{};
+        b.n = n; b.f = f;
+        if (leaf(i) && !root(i)) {
+          b.psi = psi_p<T>(s);
+          if (lesser) {
+            b.d = in_fold(chans[chan], i) ? X<T>(s.M[chan]) : nullptr;
+            b.ldd = n + f;
+            b.xt = X<T>(s.PT[chan]);
+          } else {
+            b.d = inv_p<T>(s);
+            b.ldd = n;
+            b.xt = X<T>(s.GT);
+          }
+        } else if (lesser) {
+          b.X = X<T>(s.PX[chan]);
+          b.ld = n + f;
+        } else {
+          b.X = X<T>(s.GX);
+          b.ld = gcols(i);
+        }
+        tab[(size_t)i * B + e] = b;
+      }
+    }
+    Step st;
+    st.kind = S_BONDS;
+    st.jobs = bond_refs;
+    st.map = blob.push(tab);
+    st.count = nbonds;
+    st.i0 = lesser;
+    st.dd = kDD<T>;
+    push(st);
+  }
+
   void guard_step() {
     phase = PH_OTHER;
     // conditioning / growth indicators of every pivot block
@@ -1087,6 +1184,7 @@ struct Builder {
 
   template <class T>
   void diag_step(const std::vector<int>& ids, int mode, int out, int chan, bool g_phase) {
+    if (out == O_NONE || (g_phase && out == O_GR && !(want & HSC_DIAG_GR))) return;
     std::vector<RJ> jobs;
     for (int i : ids)
       for (int e = 0; e < B; ++e) {
@@ -1196,6 +1294,7 @@ struct Builder {
         gemm_x(OP_N, OP_T, m4, 1);
       }
     }
+    bond_step<T>(0, 0);
   }
 
   template <class T>
@@ -1326,6 +1425,7 @@ struct Builder {
       diag_step<T>(seps, DIAG_SEP, ch.out, k, false);
       diag_step<T>(leaves, DIAG_LEAF_P, ch.out, k, false);
     }
+    if (ch.type == 0) bond_step<T>(1, k);
   }
 };
 
@@ -1380,13 +1480,15 @@ bool step_empty(const Step& s) {
     case S_DD_INV_PANEL: case S_DD_INV_SWAP: case S_DD_INV_UNSCR: case S_DD_INV_SUPER:
     case S_FACE_HALF: case S_FACE_SIGMA:
       return s.njobs <= 0;
+    case S_BONDS:
+      return s.count <= 0;
     default:
       return s.count <= 0;
   }
 }
 
 int run_steps(hsc_ctx* ctx, hipStream_t st, Plan* pl, int e_base, int nvalid, void* gr, void* glo,
-              double* spectral, double* guard, int nclusters) {
+              double* spectral, double* guard, int nclusters, void* bond_gr = nullptr, void* bond_gl = nullptr) {
   const int64_t n = pl->n;
   for (const Step& s : pl->steps) {
     if (step_empty(s)) continue;
@@ -1475,6 +1577,10 @@ int run_steps(hsc_ctx* ctx, hipStream_t st, Plan* pl, int e_base, int nvalid, vo
         break;
       case S_FACE_SIGMA:
         launch_face_sigma(st, (const FaceJob*)jobs, s.njobs, s.i0);
+        break;
+      case S_BONDS:
+        launch_bonds(st, (const BondRef*)jobs, s.count, reinterpret_cast<const BondSrc*>(map), pl->B, nvalid, e_base,
+                     s.i0, s.dd, static_cast<double2*>(s.i0 ? bond_gl : bond_gr));
         break;
       case S_DIAG: {
         void* out = nullptr;
@@ -1628,7 +1734,7 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
     }
   std::unique_ptr<Plan> pl(new Plan());
   pl->uid = t->uid; pl->B = B; pl->want = want; pl->n = t->n; pl->prec = prec; pl->tune = tune; pl->m3 = m3;
-  Builder b{t, B, want, (want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR)) != 0};
+  Builder b{t, B, want, (want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR | HSC_BOND_GL)) != 0};
   b.ddf = prec >= 1;
   b.ddx = prec >= 2;
   b.oz = prec == 3;
@@ -1664,7 +1770,7 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
   const auto L = b.levels();
   b.face_steps();
   b.fold(L);
-  if (want & (HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR)) {
+  if (want & (HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR | HSC_BOND_GR | HSC_BOND_GL)) {
     if (b.ddx) b.extract_g<zdd>(L);
     else b.extract_g<double2>(L);
   }
@@ -1696,7 +1802,7 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
 }
 
 size_t plan_bytes_per_slot(const hsc_tree* t, uint32_t want, int prec) {
-  Builder b{t, 1, want, (want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR)) != 0};
+  Builder b{t, 1, want, (want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR | HSC_BOND_GL)) != 0};
   b.ddf = prec >= 1;
   b.ddx = prec >= 2;
   b.oz = prec == 3;
@@ -1762,7 +1868,8 @@ hsc_status hsc_ctx_destroy(hsc_ctx* ctx) {
 
 static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, const double* energies,
                              const hsc_solve_opts* opts, void* diag_gr, void* diag_gl, double* trans,
-                             double* spectral_lr, int32_t* status, double* guard) {
+                             double* spectral_lr, int32_t* status, double* guard, void* bond_gr = nullptr,
+                             void* bond_gl = nullptr) {
   if (!ctx || !tree || !opts || n_e < 0) { set_error("null argument to hsc_solve"); return HSC_E_ARG; }
   if (n_e == 0) return HSC_OK;
   if (!energies) { set_error("energies is NULL"); return HSC_E_ARG; }
@@ -1772,7 +1879,9 @@ static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
   if ((want & HSC_DIAG_GL) && !diag_gl) { set_error("diag_gl requested but NULL"); return HSC_E_ARG; }
   if ((want & HSC_TRANS) && !trans) { set_error("trans requested but NULL"); return HSC_E_ARG; }
   if ((want & HSC_SPECTRAL_LR) && !spectral_lr) { set_error("spectral_lr requested but NULL"); return HSC_E_ARG; }
-  if ((want & (HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR)) == 0) {
+  if ((want & HSC_BOND_GR) && !bond_gr) { set_error("bond_gr requested but NULL (bond outputs go through hsc_solve_ex)"); return HSC_E_ARG; }
+  if ((want & HSC_BOND_GL) && !bond_gl) { set_error("bond_gl requested but NULL (bond outputs go through hsc_solve_ex)"); return HSC_E_ARG; }
+  if ((want & (HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR | HSC_BOND_GR | HSC_BOND_GL)) == 0) {
     set_error("nothing requested");
     return HSC_E_ARG;
   }
@@ -1803,7 +1912,7 @@ static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
   int st = build_plan(ctx, tree, B, want, opts->precision, opts->tune != 0, opts->complex3m, &pl);
   if (st != HSC_OK) return (hsc_status)st;
   const int64_t n = tree->n;
-  const bool use_graph = opts->graph != 0 && !guard && !ctx->profile;
+  const bool use_graph = opts->graph != 0 && !guard && !ctx->profile && !(want & (HSC_BOND_GR | HSC_BOND_GL));
   double2* sg_gr = nullptr;
   double2* sg_gl = nullptr;
   double* sg_sp = nullptr;
@@ -1849,7 +1958,8 @@ static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
         HIPCHK(hipMemcpyAsync(spectral_lr + (size_t)e0 * 2 * n, sg_sp, rows * 16, hipMemcpyDeviceToDevice, ctx->stream));
       spec_rows = sg_sp;
     } else {
-      st = run_steps(ctx, ctx->stream, pl, e0, nv, diag_gr, diag_gl, spectral_lr, guard, (int)tree->cl.size());
+      st = run_steps(ctx, ctx->stream, pl, e0, nv, diag_gr, diag_gl, spectral_lr, guard, (int)tree->cl.size(),
+                     bond_gr, bond_gl);
       if (st != HSC_OK) return (hsc_status)st;
     }
     if ((want & HSC_TRANS) && tree->dense) {
@@ -2030,6 +2140,17 @@ static hsc_status guard_loop(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
     for (const GuardItem& it : items) HIPCHK(hipMemcpy(status + it.e, &code, 4, hipMemcpyHostToDevice));
   }
   return HSC_OK;
+}
+
+hsc_status hsc_solve_ex(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, const double* energies,
+                        const hsc_solve_opts* opts, const hsc_outputs* out) {
+  if (!out || !opts) { set_error("null argument to hsc_solve_ex"); return HSC_E_ARG; }
+  if ((opts->want & (HSC_BOND_GR | HSC_BOND_GL)) == 0)
+    return hsc_solve(ctx, tree, n_e, energies, opts, out->diag_gr, out->diag_gl, out->trans, out->spectral_lr,
+                     out->status, out->guard);
+  if (opts->guard_tau > 0.0) { set_error("bond outputs do not combine with the growth guard"); return HSC_E_ARG; }
+  return solve_core(ctx, tree, n_e, energies, opts, out->diag_gr, out->diag_gl, out->trans, out->spectral_lr,
+                    out->status, out->guard, out->bond_gr, out->bond_gl);
 }
 
 hsc_status hsc_solve(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, const double* energies,

@@ -292,7 +292,7 @@ int finalize_tree(hsc_tree* t, std::vector<std::vector<int64_t>>& sites_of) {
 // the solver executes for the requested outputs.
 double flops_per_energy(const hsc_tree* t, uint32_t want) {
   double fl = 0;
-  const bool need_gl = want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR);
+  const bool need_gl = want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR | HSC_BOND_GL);
   for (const auto& c : t->cl) {
     double n = c.n, f = c.f(), P = (double)c.n_anc;
     bool leaf = c.children.empty();
@@ -320,9 +320,12 @@ double flops_per_energy(const hsc_tree* t, uint32_t want) {
   // channels: (fold-set, extract-set) as chosen by the solver
   struct Ch { int fold; int extract; };   // 0 = both sides, 1 = left, 2 = right, 3 = none
   std::vector<Ch> chans;
-  if (want & HSC_SPECTRAL_LR) { chans.push_back({1, 0}); chans.push_back({2, 0}); }
-  else {
-    if (want & HSC_DIAG_GL) chans.push_back({0, 0});
+  if (want & HSC_SPECTRAL_LR) {
+    chans.push_back({1, 0});
+    chans.push_back({2, 0});
+    if (want & HSC_BOND_GL) chans.push_back({0, 0});
+  } else {
+    if (want & (HSC_DIAG_GL | HSC_BOND_GL)) chans.push_back({0, 0});
     if (want & HSC_TRANS) chans.push_back({2, 1});
   }
   for (auto ch : chans)
@@ -340,9 +343,26 @@ double flops_per_energy(const hsc_tree* t, uint32_t want) {
   return fl;
 }
 
+std::vector<int64_t> tree_bonds(const hsc_tree* t) {
+  std::vector<int64_t> out;
+  std::vector<int32_t> cols;
+  for (int64_t r = 0; r < t->n; ++r) {
+    cols.clear();
+    for (int64_t q = t->indptr[r]; q < t->indptr[r + 1]; ++q)
+      if (t->indices[q] > r) cols.push_back(t->indices[q]);
+    std::sort(cols.begin(), cols.end());
+    cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+    for (int32_t c : cols) {
+      out.push_back(r);
+      out.push_back(c);
+    }
+  }
+  return out;
+}
+
 double bytes_per_energy(const hsc_tree* t, uint32_t want) {
   double b = 0;
-  const bool need_gl = want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR);
+  const bool need_gl = want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR | HSC_BOND_GL);
   for (const auto& c : t->cl) {
     double n = c.n, f = c.f(), P = (double)c.n_anc;
     b += 16 * ((n + f) * (n + f) + n * n + n * f);               // frontal, inverse, Psi
@@ -475,6 +495,18 @@ hsc_status hsc_tree_build(int64_t n, const int64_t* indptr, const int32_t* indic
     return HSC_E_OOM;
   }
   *out = t;
+  return HSC_OK;
+}
+
+hsc_status hsc_tree_bonds(const hsc_tree* tree, int64_t* pairs, int64_t* count) {
+  if (!tree || !count) { set_error("bad arguments to hsc_tree_bonds"); return HSC_E_ARG; }
+  const std::vector<int64_t> b = tree_bonds(tree);
+  const int64_t nb = (int64_t)b.size() / 2;
+  if (pairs) {
+    if (*count < nb) { set_error("hsc_tree_bonds: capacity below the number of bonds"); return HSC_E_ARG; }
+    std::copy(b.begin(), b.end(), pairs);
+  }
+  *count = nb;
   return HSC_OK;
 }
 

@@ -14,6 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhsc.so")
 
 HSC_DIAG_GR, HSC_DIAG_GL, HSC_TRANS, HSC_SPECTRAL_LR = 1, 2, 4, 8
+HSC_BOND_GR, HSC_BOND_GL = 16, 32
 STATUS = {0: "HSC_OK", -1: "HSC_E_ARG", -2: "HSC_E_NOT_SYMMETRIC", -3: "HSC_E_SINGULAR",
           -4: "HSC_E_NONFINITE", -5: "HSC_E_OOM", -6: "HSC_E_HIP", -7: "HSC_E_UNSTABLE"}
 
@@ -32,6 +33,11 @@ class Contact(C.Structure):
 class TreeOpts(C.Structure):
     _fields_ = [("coords", C.POINTER(C.c_int32)), ("split_mask", C.c_int32), ("leaf_side", C.c_int32),
                 ("dense_contacts", C.c_int32)]
+
+
+class Outputs(C.Structure):
+    _fields_ = [("diag_gr", C.c_void_p), ("diag_gl", C.c_void_p), ("trans", C.c_void_p), ("spectral_lr", C.c_void_p),
+                ("status", C.c_void_p), ("guard", C.c_void_p), ("bond_gr", C.c_void_p), ("bond_gl", C.c_void_p)]
 
 
 class TreeStats(C.Structure):
@@ -70,6 +76,8 @@ def lib():
     L.hsc_tree_export.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.hsc_tree_destroy.argtypes = [vp]
     L.hsc_solve.argtypes = [vp, vp, i32, vp, C.POINTER(SolveOpts), vp, vp, vp, vp, vp, vp]
+    L.hsc_solve_ex.argtypes = [vp, vp, i32, vp, C.POINTER(SolveOpts), C.POINTER(Outputs)]
+    L.hsc_tree_bonds.argtypes = [vp, vp, vp]
     L.hsc_solve_batch.argtypes = [vp, i32, vp, vp, vp, C.POINTER(SolveOpts), vp, vp, vp, vp, vp, vp]
     L.hsc_sync.argtypes = [vp]
     L.hsc_ctx_profile.argtypes = [vp, i32]
@@ -97,7 +105,8 @@ def lib():
     L.hsc_mlp_train.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
     for name in ("hsc_ctx_create", "hsc_ctx_destroy", "hsc_tree_build", "hsc_tree_merge", "hsc_tree_concat",
                  "hsc_tree_stats_get",
-                 "hsc_tree_export", "hsc_tree_destroy", "hsc_solve", "hsc_solve_batch", "hsc_sync",
+                 "hsc_tree_export", "hsc_tree_destroy", "hsc_solve", "hsc_solve_ex", "hsc_solve_batch", "hsc_sync",
+                 "hsc_tree_bonds",
                  "hsc_ctx_profile", "hsc_ctx_profile_read", "hsc_ctx_profile_bytes", "hsc_ctx_profile_launches",
                  "hsc_kern_zgemm", "hsc_kern_zgemm_tile", "hsc_kern_zgemm_dd", "hsc_kern_zgemm_dd_noalloc",
                  "hsc_kern_zinv_batched",
@@ -245,6 +254,14 @@ class Tree:
         check(lib().hsc_tree_export(self.h, None, None, None, None, None, _ptr(fs)))
         return dict(perm=perm, parent=parent, first=first, size=size, front_ptr=fptr, front=fs[:fptr[-1]])
 
+    def bonds(self) -> np.ndarray:
+        """int64 [n_bonds, 2]: the pairs (i, j), i < j, with H_ij != 0, in the solver's bond order."""
+        cnt = C.c_int64(0)
+        check(lib().hsc_tree_bonds(self.h, None, C.byref(cnt)))
+        out = np.empty((max(cnt.value, 1), 2), np.int64)
+        check(lib().hsc_tree_bonds(self.h, _ptr(out), C.byref(cnt)))
+        return out[:cnt.value]
+
     def merge(self, ids) -> "Tree":
         ids = np.ascontiguousarray(ids, dtype=np.int32)
         h = C.c_void_p()
@@ -293,9 +310,18 @@ def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R
     if guard and "guard" not in o:
         o["guard"] = torch.zeros((ne, tree.stats()["n_clusters"], 2), dtype=torch.float64, device=dev)
     opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, guard_tau, guard_rounds, precision, graph, tune, complex3m)
-    check(lib().hsc_solve(ctx.h, tree.h, ne, _dptr(e), C.byref(opts), _dptr(o.get("gr")), _dptr(o.get("gl")),
-                          _dptr(o.get("trans")), _dptr(o.get("spectral")), _dptr(o.get("status")),
-                          _dptr(o.get("guard"))))
+    if want & (HSC_BOND_GR | HSC_BOND_GL):
+        nb = len(tree.bonds())
+        for bit, key in ((HSC_BOND_GR, "bond_gr"), (HSC_BOND_GL, "bond_gl")):
+            if want & bit and key not in o:
+                o[key] = torch.empty((ne, nb), dtype=torch.complex128, device=dev)
+        outs = Outputs(*[_dptr(o.get(k)) for k in ("gr", "gl", "trans", "spectral", "status", "guard", "bond_gr",
+                                                  "bond_gl")])
+        check(lib().hsc_solve_ex(ctx.h, tree.h, ne, _dptr(e), C.byref(opts), C.byref(outs)))
+    else:
+        check(lib().hsc_solve(ctx.h, tree.h, ne, _dptr(e), C.byref(opts), _dptr(o.get("gr")), _dptr(o.get("gl")),
+                              _dptr(o.get("trans")), _dptr(o.get("spectral")), _dptr(o.get("status")),
+                              _dptr(o.get("guard"))))
     if sync:
         ctx.sync()
     return o

@@ -221,3 +221,49 @@ def test_hamiltonian_builders_are_symmetric():
         oracle.negf.check_symmetric(dev)
         h = dev.scipy_h()
         assert (abs(h - h.conj().T)).max() == 0          # real symmetric (Hermitian too)
+
+
+def _bond_pairs(dev):
+    h = dev.scipy_h().tocoo()
+    m = h.row < h.col
+    return np.unique(np.stack([h.row[m], h.col[m]], 1), axis=0)
+
+
+@pytest.mark.parametrize("dense", [False, True])
+def test_bond_lesser_continuity(dense):
+    # steady state: at a site with no lead, sum_j (H_ij G^<_ji - G^<_ij H_ji) = 2 i eta G^<_ii
+    # (the eta broadening is the only sink) -- an identity of the Dyson equation, independent of
+    # how G^< is formed
+    rng = np.random.default_rng(5)
+    dev = synth.cuboid(5, 4, 3, onsite=rng.normal(0, 0.3, 60))
+    eta = 1e-3
+    pairs = _bond_pairs(dev)
+    E = [-1.3, 0.4, 2.2]
+    b = oracle.dense.bonds(dev, E, eta, 0.025, 0.3, -0.2, pairs, dense=dense)
+    d = oracle.dense.solve(dev, E, eta, 0.025, 0.3, -0.2, dense=dense)
+    h = dev.dense_h()
+    contact = set(np.concatenate([c.sites for c in dev.contacts]).tolist())
+    for e in range(len(E)):
+        gl = np.zeros((dev.n, dev.n), np.complex128)
+        gl[pairs[:, 0], pairs[:, 1]] = b["gl"][e]
+        gl[pairs[:, 1], pairs[:, 0]] = -np.conj(b["gl"][e])           # anti-Hermitian
+        gl[np.arange(dev.n), np.arange(dev.n)] = d["gl"][e]
+        lhs = np.diag(h @ gl - gl @ h)
+        for s in range(dev.n):
+            if s in contact:
+                continue
+            assert abs(lhs[s] - 2j * eta * gl[s, s]) < 1e-12 * np.abs(gl).max(), (s, lhs[s])
+
+
+def test_bond_lesser_equilibrium():
+    # equal occupations: G^< = f (G^a - G^r) - 2 eta f G G^dagger; with eta -> 0 the bond entries
+    # of G^< follow from those of G^r alone (G symmetric): G^<_ij = -2 i f Im G^r_ij
+    rng = np.random.default_rng(6)
+    dev = synth.cuboid(6, 3, 3, onsite=rng.normal(0, 0.3, 54))
+    pairs = _bond_pairs(dev)
+    E = [-1.7, -0.2, 1.1]
+    b = oracle.dense.bonds(dev, E, 1e-12, 0.025, 0.05, 0.05, pairs)
+    f = oracle.negf.fermi(np.array(E), 0.05, 0.025)
+    for e in range(len(E)):
+        ref = -2j * f[e] * b["gr"][e].imag
+        assert np.abs(b["gl"][e] - ref).max() < 1e-9 * max(np.abs(ref).max(), 1e-300)
