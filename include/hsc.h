@@ -92,6 +92,11 @@ typedef struct {
   const int32_t* coords;     /* host, [n][3] integer site coordinates */
   int32_t split_mask;        /* e.g. 7 for x|y|z, 3 for in-plane only */
   int32_t leaf_side;         /* >= 1 */
+  int32_t method;            /* 0: geometric nested dissection from coords (above);
+                              * 1: graph nested dissection from the sparsity of H alone, for
+                              * unstructured H (coords may be NULL): breadth-first level sets
+                              * from a pseudo-peripheral site, the level that best balances the two
+                              * sides is the separator; leaf_side is then the largest leaf in sites */
   int32_t dense_contacts;    /* 0: per-site leads; 1: whole-face leads (dense self-energy).
                               * With 1 the two contacts must be the two end planes of the
                               * device along one axis (every site between them), each a full
@@ -194,6 +199,19 @@ hsc_status hsc_tree_build(int64_t n, const int64_t* indptr, const int32_t* indic
                           const double* values_ri, int32_t n_contacts,
                           const hsc_contact* contacts, const hsc_tree_opts* opts,
                           hsc_tree** out);
+
+/* A tree of the caller's own partition (Section 2.2: any cluster tree whose separators separate;
+ * a chain of slabs makes the method the recursive Green's function of Section 2.1; the DNA study's
+ * customised partitions): cluster_of_site[s] in [0, n_clusters) and parent[c] (-1 for the one
+ * root).  Clusters are renumbered children-first (hsc_tree_export gives the new order), every
+ * cluster must be non-empty, and every bond of H must join a cluster and one of its ancestors
+ * (checked).  Contacts as in hsc_tree_build with per-site leads.
+ * Errors: HSC_E_ARG (bad partition, not a tree, not separating), HSC_E_NOT_SYMMETRIC,
+ * HSC_E_NONFINITE, HSC_E_OOM. */
+hsc_status hsc_tree_build_custom(int64_t n, const int64_t* indptr, const int32_t* indices,
+                                 const double* values_ri, int32_t n_contacts, const hsc_contact* contacts,
+                                 int32_t n_clusters, const int32_t* cluster_of_site, const int32_t* parent,
+                                 hsc_tree** out);
 
 /* A copy of `src` in which every listed cluster (ids as numbered by
  * hsc_tree_export) is merged into its parent: the parent takes its sites and

@@ -109,7 +109,7 @@ int main(int argc, char** argv) {
     fflush(stdout);
   }
 
-  hsc_tree_opts topts{coords.data(), 7, leaf, dense};
+  hsc_tree_opts topts{coords.data(), 7, leaf, 0, dense};
   hsc_tree* tree = nullptr;
   if (hsc_tree_build(n, indptr.data(), indices.data(), values.data(), 2, contacts, &topts, &tree) != HSC_OK)
     return fail("tree build");

@@ -72,6 +72,87 @@ struct NDBuilder {
   }
 };
 
+// Graph nested dissection (for H without usable coordinates): bisect a site set by breadth-first
+// level sets of its graph.  From a pseudo-peripheral site (the last site reached from the set's
+// first site, then the last one reached from it) the levels L_0, L_1, ... of the set's component
+// are formed; the separator is the level that best balances the sites below and above it (every
+// path between the two sides crosses it), sites of other components join the lower side (no
+// edge reaches them).  Stop at sets of at most `leaf` sites, or when no level separates.
+struct GraphND {
+  const hsc_tree* t;
+  int64_t leaf;
+  std::vector<std::vector<int64_t>> sites_of;
+  std::vector<std::vector<int>> kids_of;
+  std::vector<int32_t> mark, level;
+  int32_t stamp = 0;
+  GraphND(const hsc_tree* t_, int64_t leaf_) : t(t_), leaf(leaf_), mark(t_->n, 0), level(t_->n, -1) {}
+
+  // levels from src inside the current mark; returns the sites in visiting order
+  std::vector<int64_t> bfs(int64_t src) {
+    std::vector<int64_t> order{src};
+    level[src] = 0;
+    for (size_t h = 0; h < order.size(); ++h) {
+      const int64_t r = order[h];
+      for (int64_t q = t->indptr[r]; q < t->indptr[r + 1]; ++q) {
+        const int64_t c = t->indices[q];
+        if (mark[c] != stamp || level[c] >= 0) continue;
+        level[c] = level[r] + 1;
+        order.push_back(c);
+      }
+    }
+    return order;
+  }
+
+  int leaf_of(std::vector<int64_t>& sites) {
+    sites_of.push_back(std::move(sites));
+    kids_of.push_back({});
+    return (int)sites_of.size() - 1;
+  }
+
+  int rec(std::vector<int64_t>& sites) {
+    if ((int64_t)sites.size() <= leaf) return leaf_of(sites);
+    ++stamp;
+    for (int64_t s : sites) { mark[s] = stamp; level[s] = -1; }
+    std::vector<int64_t> order = bfs(sites[0]);
+    for (int pass = 0; pass < 2; ++pass) {
+      const int64_t far = order.back();
+      for (int64_t s : order) level[s] = -1;
+      order = bfs(far);
+    }
+    const int depth = level[order.back()];
+    if (depth < 2) {   // no level has sites on both sides
+      for (int64_t s : sites) level[s] = -1;
+      return leaf_of(sites);
+    }
+    std::vector<int64_t> count(depth + 1, 0);
+    for (int64_t s : order) count[level[s]]++;
+    const int64_t others = (int64_t)sites.size() - (int64_t)order.size();
+    int best = 1;
+    int64_t best_cost = INT64_MAX, below = others + count[0];
+    for (int m = 1; m < depth; ++m) {
+      const int64_t above = (int64_t)sites.size() - below - count[m];
+      const int64_t cost = std::max(below, above) + count[m];
+      if (cost < best_cost) { best_cost = cost; best = m; }
+      below += count[m];
+    }
+    std::vector<int64_t> lo, hi, sep;
+    for (int64_t s : sites) {
+      const int l = level[s];
+      if (l == best) sep.push_back(s);
+      else if (l > best) hi.push_back(s);
+      else lo.push_back(s);   // lower levels and the unreached components
+      level[s] = -1;
+    }
+    std::vector<int64_t>().swap(sites);
+    std::vector<int> kids;
+    if (!lo.empty()) kids.push_back(rec(lo));
+    if (!hi.empty()) kids.push_back(rec(hi));
+    sites_of.push_back(std::move(sep));
+    kids_of.push_back(std::move(kids));
+    return (int)sites_of.size() - 1;
+  }
+};
+
 // Whole-face contacts (dense self-energy blocks): each face must sit inside one cluster that is an
 // ancestor of every cluster touching it, or the dense block would couple sibling clusters.  With
 // d(s) the distance of site s from the left face along the normal axis and N planes in all:
@@ -214,7 +295,7 @@ int finalize_tree(hsc_tree* t, std::vector<std::vector<int64_t>>& sites_of) {
       if (a == b) continue;
       int lo_ = std::min(a, b), hi_ = std::max(a, b);
       if (!(t->cl[hi_].lo <= lo_)) {
-        set_error("coordinates do not separate the graph of H (edge " + std::to_string(r) + "-" +
+        set_error("the clusters do not separate the graph of H (edge " + std::to_string(r) + "-" +
                   std::to_string(c) + " crosses a separator)");
         return HSC_E_ARG;
       }
@@ -382,92 +463,123 @@ extern "C" {
 const char* hsc_version(void) { return "hsc-mi355x 0.1"; }
 const char* hsc_last_error(void) { return hsc::last_error(); }
 
+// H (CSR, checked: indices in range, finite, exactly symmetric) and the contacts into t; argument
+// errors throw a message, the other failures return their status
+static int ingest(hsc_tree* t, int64_t n, const int64_t* indptr, const int32_t* indices, const double* values_ri,
+                  int32_t n_contacts, const hsc_contact* contacts) {
+  if (n_contacts != 2) throw std::string("exactly two contacts are required");
+  t->n = n;
+  if (indptr[0] != 0) throw std::string("indptr[0] != 0");
+  for (int64_t r = 0; r < n; ++r)
+    if (indptr[r + 1] < indptr[r]) throw std::string("indptr not monotone");
+  int64_t nnz = indptr[n];
+  t->indptr.assign(indptr, indptr + n + 1);
+  t->indices.assign(indices, indices + nnz);
+  t->values.assign(values_ri, values_ri + 2 * nnz);
+  for (int64_t q = 0; q < nnz; ++q) {
+    if (indices[q] < 0 || indices[q] >= n) throw std::string("column index out of range");
+    if (!std::isfinite(values_ri[2 * q]) || !std::isfinite(values_ri[2 * q + 1])) {
+      set_error("non-finite value in H");
+      return HSC_E_NONFINITE;
+    }
+  }
+  // symmetry H^T == H (exact): sort each row's (col, value) pairs
+  {
+    std::vector<int64_t> ord(nnz);
+    for (int64_t r = 0; r < n; ++r) {
+      for (int64_t q = indptr[r]; q < indptr[r + 1]; ++q) ord[q] = q;
+      std::sort(ord.begin() + indptr[r], ord.begin() + indptr[r + 1],
+                [&](int64_t a, int64_t b) { return indices[a] < indices[b]; });
+    }
+    auto find = [&](int64_t r, int32_t c, double* re, double* im) {
+      int64_t a = indptr[r], b = indptr[r + 1];
+      double sr = 0, si = 0;
+      bool hit = false;
+      auto it = std::lower_bound(ord.begin() + a, ord.begin() + b, c,
+                                 [&](int64_t q, int32_t v) { return indices[q] < v; });
+      for (; it != ord.begin() + b && indices[*it] == c; ++it) {
+        sr += values_ri[2 * *it];
+        si += values_ri[2 * *it + 1];
+        hit = true;
+      }
+      *re = sr; *im = si;
+      return hit;
+    };
+    for (int64_t r = 0; r < n; ++r)
+      for (int64_t q = indptr[r]; q < indptr[r + 1]; ++q) {
+        int32_t c = indices[q];
+        double ar, ai, br, bi;
+        find(r, c, &ar, &ai);
+        bool ok = find(c, (int32_t)r, &br, &bi);
+        if (!ok || ar != br || ai != bi) {
+          set_error("H is not symmetric at (" + std::to_string(r) + "," + std::to_string(c) + ")");
+          return HSC_E_NOT_SYMMETRIC;
+        }
+      }
+  }
+  t->side.assign(n, -1);
+  for (int k = 0; k < 2; ++k) {
+    const hsc_contact& c = contacts[k];
+    if (c.n_sites <= 0 || !c.sites) throw std::string("empty contact");
+    if (!(c.lead_hopping != 0.0) || !std::isfinite(c.lead_hopping) || !std::isfinite(c.coupling) ||
+        !std::isfinite(c.lead_onsite))
+      throw std::string("bad lead parameters");
+    t->contact[k].sites.assign(c.sites, c.sites + c.n_sites);
+    t->contact[k].lead_onsite = c.lead_onsite;
+    t->contact[k].lead_hopping = c.lead_hopping;
+    t->contact[k].coupling = c.coupling;
+    for (int64_t j = 0; j < c.n_sites; ++j) {
+      int64_t s = c.sites[j];
+      if (s < 0 || s >= n) throw std::string("contact site out of range");
+      if (t->side[s] >= 0) throw std::string("site listed in two contacts (or twice)");
+      t->side[s] = (int8_t)k;
+    }
+  }
+  return HSC_OK;
+}
+
 hsc_status hsc_tree_build(int64_t n, const int64_t* indptr, const int32_t* indices,
                           const double* values_ri, int32_t n_contacts,
                           const hsc_contact* contacts, const hsc_tree_opts* opts,
                           hsc_tree** out) {
   if (!out) { set_error("out is NULL"); return HSC_E_ARG; }
   *out = nullptr;
-  if (n <= 0 || !indptr || !indices || !values_ri || !contacts || !opts || !opts->coords) {
+  if (n <= 0 || !indptr || !indices || !values_ri || !contacts || !opts) {
     set_error("null or empty argument to hsc_tree_build");
     return HSC_E_ARG;
   }
-  if (n_contacts != 2) { set_error("exactly two contacts are required"); return HSC_E_ARG; }
-  if (opts->leaf_side < 1 || (opts->split_mask & 7) == 0) { set_error("bad tree options"); return HSC_E_ARG; }
+  if (opts->method != 0 && opts->method != 1) { set_error("method must be 0 (geometric) or 1 (graph)"); return HSC_E_ARG; }
+  if (opts->method == 0 && !opts->coords) { set_error("geometric nested dissection needs coordinates"); return HSC_E_ARG; }
+  if (opts->method == 1 && opts->dense_contacts) {
+    set_error("whole-face contacts need the geometric dissection (coordinates)");
+    return HSC_E_ARG;
+  }
+  if (opts->leaf_side < 1 || (opts->method == 0 && (opts->split_mask & 7) == 0)) {
+    set_error("bad tree options");
+    return HSC_E_ARG;
+  }
   hsc_tree* t = new (std::nothrow) hsc_tree();
   if (!t) { set_error("host allocation failed"); return HSC_E_OOM; }
   try {
-    t->n = n;
-    if (indptr[0] != 0) throw std::string("indptr[0] != 0");
-    for (int64_t r = 0; r < n; ++r)
-      if (indptr[r + 1] < indptr[r]) throw std::string("indptr not monotone");
-    int64_t nnz = indptr[n];
-    t->indptr.assign(indptr, indptr + n + 1);
-    t->indices.assign(indices, indices + nnz);
-    t->values.assign(values_ri, values_ri + 2 * nnz);
-    for (int64_t q = 0; q < nnz; ++q) {
-      if (indices[q] < 0 || indices[q] >= n) throw std::string("column index out of range");
-      if (!std::isfinite(values_ri[2 * q]) || !std::isfinite(values_ri[2 * q + 1])) {
-        delete t;
-        set_error("non-finite value in H");
-        return HSC_E_NONFINITE;
-      }
-    }
-    // symmetry H^T == H (exact): sort each row's (col, value) pairs
-    {
-      std::vector<int64_t> ord(nnz);
-      for (int64_t r = 0; r < n; ++r) {
-        for (int64_t q = indptr[r]; q < indptr[r + 1]; ++q) ord[q] = q;
-        std::sort(ord.begin() + indptr[r], ord.begin() + indptr[r + 1],
-                  [&](int64_t a, int64_t b) { return indices[a] < indices[b]; });
-      }
-      auto find = [&](int64_t r, int32_t c, double* re, double* im) {
-        int64_t a = indptr[r], b = indptr[r + 1];
-        double sr = 0, si = 0;
-        bool hit = false;
-        auto it = std::lower_bound(ord.begin() + a, ord.begin() + b, c,
-                                   [&](int64_t q, int32_t v) { return indices[q] < v; });
-        for (; it != ord.begin() + b && indices[*it] == c; ++it) {
-          sr += values_ri[2 * *it];
-          si += values_ri[2 * *it + 1];
-          hit = true;
-        }
-        *re = sr; *im = si;
-        return hit;
-      };
-      for (int64_t r = 0; r < n; ++r)
-        for (int64_t q = indptr[r]; q < indptr[r + 1]; ++q) {
-          int32_t c = indices[q];
-          double ar, ai, br, bi;
-          find(r, c, &ar, &ai);
-          bool ok = find(c, (int32_t)r, &br, &bi);
-          if (!ok || ar != br || ai != bi) {
-            delete t;
-            set_error("H is not symmetric at (" + std::to_string(r) + "," + std::to_string(c) + ")");
-            return HSC_E_NOT_SYMMETRIC;
-          }
-        }
-    }
-    t->coords.assign(opts->coords, opts->coords + 3 * n);
+    const int rc = ingest(t, n, indptr, indices, values_ri, n_contacts, contacts);
+    if (rc != HSC_OK) { delete t; return (hsc_status)rc; }
+    if (opts->coords) t->coords.assign(opts->coords, opts->coords + 3 * n);
+    else t->coords.assign(3 * n, 0);
     t->split_mask = opts->split_mask & 7;
     t->leaf_side = opts->leaf_side;
-    t->side.assign(n, -1);
-    for (int k = 0; k < 2; ++k) {
-      const hsc_contact& c = contacts[k];
-      if (c.n_sites <= 0 || !c.sites) throw std::string("empty contact");
-      if (!(c.lead_hopping != 0.0) || !std::isfinite(c.lead_hopping) || !std::isfinite(c.coupling) ||
-          !std::isfinite(c.lead_onsite))
-        throw std::string("bad lead parameters");
-      t->contact[k].sites.assign(c.sites, c.sites + c.n_sites);
-      t->contact[k].lead_onsite = c.lead_onsite;
-      t->contact[k].lead_hopping = c.lead_hopping;
-      t->contact[k].coupling = c.coupling;
-      for (int64_t j = 0; j < c.n_sites; ++j) {
-        int64_t s = c.sites[j];
-        if (s < 0 || s >= n) throw std::string("contact site out of range");
-        if (t->side[s] >= 0) throw std::string("site listed in two contacts (or twice)");
-        t->side[s] = (int8_t)k;
-      }
+    if (opts->method == 1) {
+      GraphND g(t, opts->leaf_side);
+      std::vector<int64_t> all(n);
+      for (int64_t s = 0; s < n; ++s) all[s] = s;
+      g.rec(all);
+      t->cl.resize(g.sites_of.size());
+      for (size_t i = 0; i < g.sites_of.size(); ++i) t->cl[i].children = g.kids_of[i];
+      int st = finalize_tree(t, g.sites_of);
+      if (st != HSC_OK) { delete t; return (hsc_status)st; }
+      t->seg_site = {0, n};
+      t->seg_left = {0, (int64_t)t->contact[0].sites.size()};
+      *out = t;
+      return HSC_OK;
     }
     NDBuilder b{t, {}, {}};
     if (opts->dense_contacts != 0 && opts->dense_contacts != 1) throw std::string("dense_contacts must be 0 or 1");
@@ -482,6 +594,83 @@ hsc_status hsc_tree_build(int64_t n, const int64_t* indptr, const int32_t* indic
     t->cl.resize(b.sites_of.size());
     for (size_t i = 0; i < b.sites_of.size(); ++i) t->cl[i].children = b.kids_of[i];
     int st = finalize_tree(t, b.sites_of);
+    if (st != HSC_OK) { delete t; return (hsc_status)st; }
+    t->seg_site = {0, n};
+    t->seg_left = {0, (int64_t)t->contact[0].sites.size()};
+  } catch (const std::string& msg) {
+    delete t;
+    set_error(msg);
+    return HSC_E_ARG;
+  } catch (const std::bad_alloc&) {
+    delete t;
+    set_error("host allocation failed");
+    return HSC_E_OOM;
+  }
+  *out = t;
+  return HSC_OK;
+}
+
+hsc_status hsc_tree_build_custom(int64_t n, const int64_t* indptr, const int32_t* indices,
+                                 const double* values_ri, int32_t n_contacts, const hsc_contact* contacts,
+                                 int32_t n_clusters, const int32_t* cluster_of_site, const int32_t* parent,
+                                 hsc_tree** out) {
+  if (!out) { set_error("out is NULL"); return HSC_E_ARG; }
+  *out = nullptr;
+  if (n <= 0 || !indptr || !indices || !values_ri || !contacts || n_clusters < 1 || !cluster_of_site || !parent) {
+    set_error("null or empty argument to hsc_tree_build_custom");
+    return HSC_E_ARG;
+  }
+  hsc_tree* t = new (std::nothrow) hsc_tree();
+  if (!t) { set_error("host allocation failed"); return HSC_E_OOM; }
+  try {
+    const int rc = ingest(t, n, indptr, indices, values_ri, n_contacts, contacts);
+    if (rc != HSC_OK) { delete t; return (hsc_status)rc; }
+    t->coords.assign(3 * n, 0);
+    std::vector<std::vector<int64_t>> members(n_clusters);
+    for (int64_t s = 0; s < n; ++s) {
+      const int32_t c = cluster_of_site[s];
+      if (c < 0 || c >= n_clusters) throw std::string("cluster_of_site out of range");
+      members[c].push_back(s);
+    }
+    int root = -1;
+    std::vector<std::vector<int>> kids(n_clusters);
+    for (int c = 0; c < n_clusters; ++c) {
+      if (members[c].empty()) throw std::string("empty cluster " + std::to_string(c));
+      const int p = parent[c];
+      if (p < -1 || p >= n_clusters || p == c) throw std::string("bad parent of cluster " + std::to_string(c));
+      if (p < 0) {
+        if (root >= 0) throw std::string("more than one root");
+        root = c;
+      } else {
+        kids[p].push_back(c);
+      }
+    }
+    if (root < 0) throw std::string("no root");
+    // children-first numbering from the root (children in increasing given id); a cluster not
+    // reached lies on a cycle
+    std::vector<std::vector<int64_t>> sites_of;
+    std::vector<std::vector<int>> kids_of;
+    std::vector<int> newid(n_clusters, -1);
+    std::vector<std::pair<int, size_t>> stack{{root, 0}};
+    while (!stack.empty()) {
+      auto& top = stack.back();
+      if (top.second < kids[top.first].size()) {
+        const int k = kids[top.first][top.second++];
+        stack.push_back({k, 0});
+        continue;
+      }
+      const int c = top.first;
+      std::vector<int> ch;
+      for (int k : kids[c]) ch.push_back(newid[k]);
+      newid[c] = (int)sites_of.size();
+      sites_of.push_back(members[c]);
+      kids_of.push_back(ch);
+      stack.pop_back();
+    }
+    if ((int)sites_of.size() != n_clusters) throw std::string("the parent links do not form one tree");
+    t->cl.resize(sites_of.size());
+    for (size_t i = 0; i < sites_of.size(); ++i) t->cl[i].children = kids_of[i];
+    const int st = finalize_tree(t, sites_of);
     if (st != HSC_OK) { delete t; return (hsc_status)st; }
     t->seg_site = {0, n};
     t->seg_left = {0, (int64_t)t->contact[0].sites.size()};

@@ -32,7 +32,7 @@ class Contact(C.Structure):
 
 class TreeOpts(C.Structure):
     _fields_ = [("coords", C.POINTER(C.c_int32)), ("split_mask", C.c_int32), ("leaf_side", C.c_int32),
-                ("dense_contacts", C.c_int32)]
+                ("method", C.c_int32), ("dense_contacts", C.c_int32)]
 
 
 class Outputs(C.Structure):
@@ -78,6 +78,7 @@ def lib():
     L.hsc_solve.argtypes = [vp, vp, i32, vp, C.POINTER(SolveOpts), vp, vp, vp, vp, vp, vp]
     L.hsc_solve_ex.argtypes = [vp, vp, i32, vp, C.POINTER(SolveOpts), C.POINTER(Outputs)]
     L.hsc_tree_bonds.argtypes = [vp, vp, vp]
+    L.hsc_tree_build_custom.argtypes = [i64, vp, vp, vp, i32, C.POINTER(Contact), i32, vp, vp, C.POINTER(vp)]
     L.hsc_solve_batch.argtypes = [vp, i32, vp, vp, vp, C.POINTER(SolveOpts), vp, vp, vp, vp, vp, vp]
     L.hsc_sync.argtypes = [vp]
     L.hsc_ctx_profile.argtypes = [vp, i32]
@@ -106,7 +107,7 @@ def lib():
     for name in ("hsc_ctx_create", "hsc_ctx_destroy", "hsc_tree_build", "hsc_tree_merge", "hsc_tree_concat",
                  "hsc_tree_stats_get",
                  "hsc_tree_export", "hsc_tree_destroy", "hsc_solve", "hsc_solve_ex", "hsc_solve_batch", "hsc_sync",
-                 "hsc_tree_bonds",
+                 "hsc_tree_bonds", "hsc_tree_build_custom",
                  "hsc_ctx_profile", "hsc_ctx_profile_read", "hsc_ctx_profile_bytes", "hsc_ctx_profile_launches",
                  "hsc_kern_zgemm", "hsc_kern_zgemm_tile", "hsc_kern_zgemm_dd", "hsc_kern_zgemm_dd_noalloc",
                  "hsc_kern_zinv_batched",
@@ -205,36 +206,73 @@ class Tree:
         self.n = n
 
     @classmethod
-    def build(cls, n, indptr, indices, values, coords, contacts, split_mask=7, leaf_side=8, dense=False):
+    def build(cls, n, indptr, indices, values, coords, contacts, split_mask=7, leaf_side=8, dense=False,
+              graph=False):
         """contacts: [(sites, lead_onsite, lead_hopping, coupling)] for left, right.  dense=True:
         each contact is a whole end face with a lead continuing the face lattice (dense
-        self-energy block); otherwise every contact site has its own 1D lead."""
+        self-energy block); otherwise every contact site has its own 1D lead.  graph=True: nested
+        dissection from the sparsity of H alone (coords unused, leaf_side = largest leaf in sites)."""
         indptr = np.ascontiguousarray(indptr, dtype=np.int64)
         indices = np.ascontiguousarray(indices, dtype=np.int32)
         vals = np.ascontiguousarray(np.asarray(values, dtype=np.complex128)).view(np.float64)
-        coords = np.ascontiguousarray(coords, dtype=np.int32)
+        coords = np.ascontiguousarray(np.zeros((n, 3)) if coords is None else coords, dtype=np.int32)
         keep = [indptr, indices, vals, coords]
         carr = (Contact * len(contacts))()
         for k, (sites, eps0, tl, tc) in enumerate(contacts):
             s = np.ascontiguousarray(sites, dtype=np.int64)
             keep.append(s)
             carr[k] = Contact(len(s), s.ctypes.data_as(C.POINTER(C.c_int64)), eps0, tl, tc)
-        opts = TreeOpts(coords.ctypes.data_as(C.POINTER(C.c_int32)), split_mask, leaf_side, int(bool(dense)))
+        opts = TreeOpts(coords.ctypes.data_as(C.POINTER(C.c_int32)), split_mask, leaf_side, int(bool(graph)),
+                        int(bool(dense)))
         h = C.c_void_p()
         check(lib().hsc_tree_build(n, _ptr(indptr), _ptr(indices), _ptr(vals), len(contacts), carr,
                                    C.byref(opts), C.byref(h)))
         return cls(h, n)
 
     @classmethod
-    def from_device(cls, dev, leaf_side=8, transverse=False, dense=False):
+    def from_device(cls, dev, leaf_side=8, transverse=False, dense=False, graph=False):
         """Tree of a synthetic device; transverse=True never cuts the transport axis (x), so every
-        cluster spans the device from one contact to the other; dense=True: whole-face leads."""
+        cluster spans the device from one contact to the other; dense=True: whole-face leads;
+        graph=True: graph nested dissection (leaf_side = largest leaf in sites)."""
         mask = 0
         for a in dev.split_axes:
             if not (transverse and a == 0):
                 mask |= 1 << a
         contacts = [(c.sites, c.lead_onsite, c.lead_hopping, c.coupling) for c in dev.contacts]
-        return cls.build(dev.n, dev.indptr, dev.indices, dev.values, dev.coords, contacts, mask, leaf_side, dense)
+        return cls.build(dev.n, dev.indptr, dev.indices, dev.values, dev.coords, contacts, mask, leaf_side, dense,
+                         graph)
+
+    @classmethod
+    def build_custom(cls, n, indptr, indices, values, contacts, cluster_of_site, parent):
+        """Tree of the caller's partition: cluster_of_site [n], parent [n_clusters] (-1: the root)."""
+        indptr = np.ascontiguousarray(indptr, dtype=np.int64)
+        indices = np.ascontiguousarray(indices, dtype=np.int32)
+        vals = np.ascontiguousarray(np.asarray(values, dtype=np.complex128)).view(np.float64)
+        cos = np.ascontiguousarray(cluster_of_site, dtype=np.int32)
+        par = np.ascontiguousarray(parent, dtype=np.int32)
+        keep = [indptr, indices, vals, cos, par]
+        carr = (Contact * len(contacts))()
+        for k, (sites, eps0, tl, tc) in enumerate(contacts):
+            s = np.ascontiguousarray(sites, dtype=np.int64)
+            keep.append(s)
+            carr[k] = Contact(len(s), s.ctypes.data_as(C.POINTER(C.c_int64)), eps0, tl, tc)
+        h = C.c_void_p()
+        check(lib().hsc_tree_build_custom(n, _ptr(indptr), _ptr(indices), _ptr(vals), len(contacts), carr,
+                                          len(par), _ptr(cos), _ptr(par), C.byref(h)))
+        return cls(h, n)
+
+    @classmethod
+    def slab_chain(cls, dev, axis=0):
+        """The degenerate tree of Section 2.2: one cluster per plane along `axis`, each the child of
+        the next (the root is the last plane), which makes the method the slab recursion of
+        Section 2.1."""
+        x = np.asarray(dev.coords)[:, axis].astype(np.int64)
+        planes = np.unique(x)
+        cos = np.searchsorted(planes, x)
+        parent = np.arange(1, len(planes) + 1)
+        parent[-1] = -1
+        contacts = [(c.sites, c.lead_onsite, c.lead_hopping, c.coupling) for c in dev.contacts]
+        return cls.build_custom(dev.n, dev.indptr, dev.indices, dev.values, contacts, cos, parent)
 
     def stats(self) -> dict:
         s = TreeStats()

@@ -9,6 +9,8 @@ from .devices import (  # noqa: F401
     Device,
     cuboid,
     orbital_cuboid,
+    random_graph_device,
+    dna_ladder,
     chain,
     trilayer,
     energy_grid,

@@ -143,6 +143,76 @@ def orbital_cuboid(nx: int, ny: int, nz: int, b: int, seed: int = 0, spread: flo
                   (0, 1, 2), {"grid": (nx, ny, nz), "orbitals": b})
 
 
+def random_graph_device(n: int, k: int = 6, seed: int = 0, sigma: float = 0.3) -> Device:
+    """Unstructured device: n points uniform in the unit cube, each bonded to its k nearest
+    neighbours (bonds symmetrised), hopping N(-1, 0.2^2) per bond, on-site N(0, sigma^2).  Per-site
+    leads on the points with x < 0.08 (left) and x > 0.92 (right).  The integer coordinates are the
+    points' cells on a 4 x 4 x 4 grid, which need not separate the graph: the device is meant for
+    graph nested dissection and custom partitions."""
+    rng = np.random.default_rng(seed)
+    pts = rng.uniform(0.0, 1.0, (n, 3))
+    d2 = ((pts[:, None, :] - pts[None, :, :]) ** 2).sum(-1)
+    np.fill_diagonal(d2, np.inf)
+    nb = np.argsort(d2, axis=1)[:, :k]
+    pairs = set()
+    for i in range(n):
+        for j in nb[i]:
+            pairs.add((min(i, int(j)), max(i, int(j))))
+    pairs = sorted(pairs)
+    hop = rng.normal(-1.0, 0.2, len(pairs))
+    rows = [np.arange(n)] + [np.array([p[0] for p in pairs]), np.array([p[1] for p in pairs])]
+    cols = [np.arange(n)] + [np.array([p[1] for p in pairs]), np.array([p[0] for p in pairs])]
+    vals = [rng.normal(0.0, sigma, n), hop, hop]
+    indptr, indices, values = _csr_from_lists(n, np.concatenate(rows), np.concatenate(cols),
+                                              np.concatenate(vals).astype(np.complex128))
+    coords = np.minimum((pts * 4).astype(np.int32), 3)
+    left = np.flatnonzero(pts[:, 0] < 0.08).astype(np.int64)
+    right = np.flatnonzero(pts[:, 0] > 0.92).astype(np.int64)
+    contacts = [Contact(left, 0.0, -1.0, -1.0), Contact(right, 0.0, -1.0, -1.0)]
+    return Device(f"graph{n}k{k}", n, indptr, indices, values, coords, contacts, (0, 1, 2), {"points": pts})
+
+
+def dna_ladder(n_pairs: int, b: int = 8, seed: int = 0, spread: float = 2.0, mix: float = 0.4,
+               along: float = 0.6, across: float = 0.4) -> Device:
+    """Ladder of base pairs with dense blocks (the block structure of the paper's DNA Hamiltonians:
+    fully dense diagonal and nearest-neighbour blocks; random since the DFT Hamiltonians are not
+    given): bases (strand s in {0, 1}, position p), b orbitals each, index o + b (s + 2 p); dense
+    symmetric on-site blocks (energies linspace(-spread, spread, b) plus N(0, mix^2)), dense random
+    couplings N(0, (along / sqrt(b))^2) to the next base on the strand and N(0, (across / sqrt(b))^2)
+    to the partner base.  Per-orbital leads on strand 0's first (left) and last (right) base.
+    Coordinates (p, s, 0) per orbital."""
+    rng = np.random.default_rng(seed)
+    nb = 2 * n_pairs
+    n = nb * b
+    oo, pp = np.meshgrid(np.arange(b), np.arange(b), indexing="ij")
+    rows, cols, vals = [], [], []
+
+    def block(i, j, m):
+        rows.append(i * b + oo.ravel()); cols.append(j * b + pp.ravel()); vals.append(m.ravel())
+
+    for base in range(nb):
+        m = rng.normal(0.0, mix, (b, b))
+        block(base, base, np.triu(m, 1) + np.triu(m, 1).T + np.diag(np.linspace(-spread, spread, b)))
+    for p in range(n_pairs):
+        t = rng.normal(0.0, across / np.sqrt(b), (b, b))
+        block(2 * p, 2 * p + 1, t)
+        block(2 * p + 1, 2 * p, t.T)
+        if p + 1 < n_pairs:
+            for s in range(2):
+                t = rng.normal(0.0, along / np.sqrt(b), (b, b))
+                block(2 * p + s, 2 * (p + 1) + s, t)
+                block(2 * (p + 1) + s, 2 * p + s, t.T)
+    indptr, indices, values = _csr_from_lists(n, np.concatenate(rows), np.concatenate(cols),
+                                              np.concatenate(vals).astype(np.complex128))
+    base_of = np.arange(n) // b
+    coords = np.stack([base_of // 2, base_of % 2, np.zeros(n, np.int64)], 1).astype(np.int32)
+    left = np.arange(b, dtype=np.int64)
+    right = (2 * (n_pairs - 1)) * b + np.arange(b, dtype=np.int64)
+    contacts = [Contact(left, 0.0, -1.0, -1.0), Contact(right, 0.0, -1.0, -1.0)]
+    return Device(f"dna{n_pairs}b{b}", n, indptr, indices, values, coords, contacts, (0,),
+                  {"pairs": n_pairs, "orbitals": b})
+
+
 def chain(m: int, t: float = -1.0, onsite=None) -> Device:
     """An m-site 1D chain; each end site couples to a semi-infinite lead."""
     return cuboid(m, 1, 1, t=t, onsite=onsite, name=f"chain{m}")

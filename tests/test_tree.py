@@ -302,3 +302,58 @@ def test_multi_orbital_tree(shape, b, leaf):
         owner[perm[first[i]:first[i] + size[i]]] = i
     assert (owner.reshape(-1, b) == owner.reshape(-1, b)[:, :1]).all()
     assert (size % b == 0).all()
+
+
+@pytest.mark.parametrize("dev,leaf", [
+    (synth.random_graph_device(600, 6, 1), 40),
+    (synth.random_graph_device(300, 4, 2), 10),
+    (synth.cuboid(9, 6, 5), 30),
+    (synth.trilayer(12, 9), 50),
+    (synth.dna_ladder(9, 8), 16),
+    (synth.chain(40), 3),
+])
+def test_graph_nested_dissection(dev, leaf):
+    # dissection from the sparsity of H alone: same invariants as the geometric tree
+    t = pkg.Tree.from_device(dev, leaf_side=leaf, graph=True)
+    ex = _check_tree(dev, t)
+    assert t.stats()["n_clusters"] > 1
+    # leaves are at most leaf sites unless no level of their set separated it
+    parents = set(ex["parent"].tolist())
+    leaves = [i for i in range(len(ex["parent"])) if i not in parents]
+    assert max(ex["size"][leaves]) <= max(leaf, 3 * leaf)
+
+
+def test_slab_chain_is_the_recursive_green_function_tree():
+    dev = synth.cuboid(7, 4, 3)
+    t = pkg.Tree.slab_chain(dev)
+    ex = _check_tree(dev, t)
+    nc = len(ex["parent"])
+    assert nc == 7 and (ex["size"] == 12).all()
+    assert (ex["parent"][:-1] == np.arange(1, nc)).all()              # a chain, one child each
+    x = dev.coords[:, 0]
+    for i in range(nc):
+        assert (x[ex["perm"][ex["first"][i]:ex["first"][i] + 12]] == i).all()
+
+
+def test_custom_partition_and_rejections():
+    dev = synth.dna_ladder(9, 4)
+    contacts = [(c.sites, c.lead_onsite, c.lead_hopping, c.coupling) for c in dev.contacts]
+    pair = dev.coords[:, 0].astype(np.int64)
+    # nested dissection over base pairs by hand: root pair 4, then pairs 1 and 6, leaves of the rest
+    groups = {4: 0, 1: 1, 6: 2, 0: 3, 2: 4, 3: 4, 5: 5, 7: 6, 8: 6}
+    parent = [-1, 0, 0, 1, 1, 2, 2]
+    cos = np.array([groups[p] for p in pair])
+    t = pkg.Tree.build_custom(dev.n, dev.indptr, dev.indices, dev.values, contacts, cos, parent)
+    ex = _check_tree(dev, t)
+    assert len(ex["parent"]) == 7
+    args = (dev.n, dev.indptr, dev.indices, dev.values, contacts)
+    bad = [
+        (np.where(pair == 0, 0, np.where(pair <= 4, 1, 2)), [-1, 0, 0]),  # siblings 1..4 and 5..8 are bonded
+        (cos, [-1, 0, 0, 1, 1, 6, 5]),                                      # a cycle (5 <-> 6)
+        (cos, [-1, -1, 0, 1, 1, 2, 2]),                                     # two roots
+        (cos, [-1, 0, 0, 1, 1, 2, 2, 0]),                                   # an empty cluster
+        (np.where(pair == 8, 9, cos), parent),                              # cluster id out of range
+    ]
+    for cs, par in bad:
+        with pytest.raises(H.HscError):
+            pkg.Tree.build_custom(*args, cs, par)
