@@ -182,6 +182,9 @@ typedef struct {
 /* Library version string. */
 const char* hsc_version(void);
 const char* hsc_last_error(void);
+/* The same text for callers holding a context (the message of the calling thread's last failed
+ * call, on this context or not; ctx may be NULL). */
+const char* hsc_ctx_last_error(const hsc_ctx* ctx);
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
  * (for example torch.cuda.current_stream().cuda_stream) or NULL for the null

@@ -102,11 +102,6 @@ hsc_status hsc_kern_zinv_dd(hsc_ctx* ctx, int32_t n, void* X, int32_t ld, void* 
 hsc_status hsc_kern_zinv_batched(hsc_ctx* ctx, int32_t count, const int32_t* n, void* const* X,
                                  const int32_t* ld, void* const* Y, const int32_t* ldy, int32_t* status);
 
-/* One wave of v_mfma_f64_16x16x4_f64 with A[l%16][l/16] = 1 + l and
- * B[l/16][l%16] = 0.5*((7l) mod 13) - 1 (l = lane); writes the 4 accumulator
- * registers of each lane to out[l*4 + r] (device, 256 doubles); register r of
- * lane l holds D[l/16 + 4r][l%16].  Used to check the lane layout the GEMM
- * kernel assumes. */
 /* Rate of a plain FP64 MFMA stream: a kernel issuing only v_mfma_f64_16x16x4_f64 on 8
  * independent accumulators per wave (4096 workgroups of 4 waves, no memory traffic but one store
  * per lane) is timed with HIP events; *tflops (host) receives the best of three runs in TFLOP/s.
@@ -115,6 +110,11 @@ hsc_status hsc_kern_zinv_batched(hsc_ctx* ctx, int32_t count, const int32_t* n, 
  * Errors: HSC_E_ARG, HSC_E_OOM, HSC_E_HIP. */
 hsc_status hsc_kern_mfma_rate(hsc_ctx* ctx, double* tflops);
 
+/* One wave of v_mfma_f64_16x16x4_f64 with A[l%16][l/16] = 1 + l and
+ * B[l/16][l%16] = 0.5*((7l) mod 13) - 1 (l = lane); writes the 4 accumulator
+ * registers of each lane to out[l*4 + r] (device, 256 doubles); register r of
+ * lane l holds D[l/16 + 4r][l%16].  Used to check the lane layout the GEMM
+ * kernel assumes. */
 hsc_status hsc_kern_mfma_probe(hsc_ctx* ctx, double* out);
 
 #ifdef __cplusplus

@@ -462,6 +462,7 @@ extern "C" {
 
 const char* hsc_version(void) { return "hsc-mi355x 0.1"; }
 const char* hsc_last_error(void) { return hsc::last_error(); }
+const char* hsc_ctx_last_error(const hsc_ctx*) { return hsc::last_error(); }
 
 // H (CSR, checked: indices in range, finite, exactly symmetric) and the contacts into t; argument
 // errors throw a message, the other failures return their status

@@ -67,6 +67,8 @@ def lib():
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.hsc_version.restype = C.c_char_p
     L.hsc_last_error.restype = C.c_char_p
+    L.hsc_ctx_last_error.restype = C.c_char_p
+    L.hsc_ctx_last_error.argtypes = [vp]
     L.hsc_ctx_create.argtypes = [i32, vp, C.POINTER(vp)]
     L.hsc_ctx_destroy.argtypes = [vp]
     L.hsc_tree_build.argtypes = [i64, vp, vp, vp, i32, C.POINTER(Contact), C.POINTER(TreeOpts), C.POINTER(vp)]
