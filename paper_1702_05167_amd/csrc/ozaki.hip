@@ -215,43 +215,56 @@ __device__ inline void oz_stage(const GemmProbOZ& pr, v4i* buf, int m0, int n0, 
   }
 }
 
+// the slice pairs s + t <= S - 1 of one staged operand part: the B slices in two halves held in
+// registers, the A slices read from LDS for each half
 template <int S>
 __device__ inline void oz_mma(const v4i* __restrict__ buf, int wm, int wn, int lane, v4i (&acc)[S]) {
-  v4i b[S];
+  constexpr int H = S / 2;
 #pragma unroll
-  for (int t = 0; t < S; ++t) b[t] = buf[(size_t)((2 + wn) * S + t) * 64 + lane];
+  for (int h = 0; h < 2; ++h) {
+    v4i b[H];
 #pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const v4i a = buf[(size_t)(wm * S + s) * 64 + lane];
+    for (int t = 0; t < H; ++t) b[t] = buf[(size_t)((2 + wn) * S + h * H + t) * 64 + lane];
 #pragma unroll
-    for (int t = 0; t < S - s; ++t) acc[s + t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b[t], acc[s + t], 0, 0, 0);
+    for (int s = 0; s < S - h * H; ++s) {
+      const v4i a = buf[(size_t)(wm * S + s) * 64 + lane];
+#pragma unroll
+      for (int t = 0; t < H; ++t)
+        if (s + h * H + t <= S - 1)
+          acc[s + h * H + t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b[t], acc[s + h * H + t], 0, 0, 0);
+    }
   }
 }
 
-// sum_d x_d 2^(-12 - 7 d) in double-double: weights in groups of five summed exactly in int64
-// (|x_d| < 2^31, so x_d 2^(7 (last - d)) < 2^59 per group), each group split exactly into a
-// normalised double pair, groups added smallest first
+// sum_d x_d 2^(-12 - 7 d) in double-double.  |x_d| < 2^31, so four consecutive weights summed as
+// x_d 2^21 + x_(d+1) 2^14 + x_(d+2) 2^7 + x_(d+3) stay integers below 2^53: each group is formed
+// exactly in FP64 by three exact fused multiply-adds, scaled exactly by its power of two, and the
+// groups are added in double-double, smallest first
 template <int S>
 __device__ inline dd oz_sum(const int (&x)[S]) {
+  static_assert(S % 4 == 0, "groups of four weights");
   dd v{0.0, 0.0};
 #pragma unroll
-  for (int g0 = ((S - 1) / 5) * 5; g0 >= 0; g0 -= 5) {
-    const int g1 = g0 + 4 < S - 1 ? g0 + 4 : S - 1;
-    int64_t acc = 0;
-#pragma unroll
-    for (int d = g0; d <= g1; ++d) acc += (int64_t)x[d] * ((int64_t)1 << (7 * (g1 - d)));
-    const double hi = (double)acc;
-    const double lo = (double)(acc - (int64_t)hi);
-    v = dd_add(v, dd{ldexp(hi, -12 - 7 * g1), ldexp(lo, -12 - 7 * g1)});
+  for (int g0 = S - 4; g0 >= 0; g0 -= 4) {
+    double acc = (double)x[g0];
+    acc = fma(acc, 128.0, (double)x[g0 + 1]);
+    acc = fma(acc, 128.0, (double)x[g0 + 2]);
+    acc = fma(acc, 128.0, (double)x[g0 + 3]);
+    v = dd_add(v, dd{ldexp(acc, -12 - 7 * (g0 + 3)), 0.0});
   }
   return v;
 }
 
+// One 32 x 32 output tile per workgroup of four waves (a 16 x 16 block each), one staged operand
+// part (64 KB) at a time and two workgroups per CU, so that one computes while the other waits for
+// its loads.  The parts run one after the other with two accumulator sets: T1 = Re A Re B into acc0,
+// T2 = Im A Im B into acc1; then acc0 = T1 - T2 (the real part) and acc1 = -(T1 + T2), onto which
+// part 2 adds T3 = (Re A + Im A)(Re B + Im B) (the imaginary part); integer sums are exact.
 template <int S>
-__global__ __launch_bounds__(256) void k_oz_gemm(const GemmProbOZ* __restrict__ probs,
-                                                 const int32_t* __restrict__ tile_prob, int total_tiles, int negate,
-                                                 int beta) {
-  __shared__ v4i lds[2][4 * S * 64];
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_oz_gemm(
+    const GemmProbOZ* __restrict__ probs, const int32_t* __restrict__ tile_prob, int total_tiles, int negate,
+    int beta) {
+  __shared__ v4i lds[4 * S * 64];
   const int per = (total_tiles + 7) >> 3;
   const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);   // XCD-aware order
   if (tile >= total_tiles) return;
@@ -266,25 +279,33 @@ __global__ __launch_bounds__(256) void k_oz_gemm(const GemmProbOZ* __restrict__ 
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wm = w >> 1, wn = w & 1;
 
-  v4i acc0[S], acc1[S], acc2[S];
+  v4i acc0[S], acc1[S];
 #pragma unroll
-  for (int d = 0; d < S; ++d) acc0[d] = acc1[d] = acc2[d] = v4i{0, 0, 0, 0};
+  for (int d = 0; d < S; ++d) acc0[d] = acc1[d] = v4i{0, 0, 0, 0};
 
   const int nkc = pr.Kp / OZ_KC;
-  if (nkc > 0) oz_stage<S>(pr, lds[0], m0, n0, 0, 0, w, lane);
-  for (int kc = 0; kc < nkc; ++kc) {
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
-      const int it = 3 * kc + p;
-      __builtin_amdgcn_s_waitcnt(0);   // this wave's loads into the current buffer are in LDS
-      __syncthreads();                 // ... and every wave's; the other buffer is no longer read
-      if (p < 2) oz_stage<S>(pr, lds[(it + 1) & 1], m0, n0, p + 1, kc, w, lane);
-      else if (kc + 1 < nkc) oz_stage<S>(pr, lds[(it + 1) & 1], m0, n0, 0, kc + 1, w, lane);
-      const v4i* buf = lds[it & 1];
-      if (p == 0) oz_mma<S>(buf, wm, wn, lane, acc0);
-      else if (p == 1) oz_mma<S>(buf, wm, wn, lane, acc1);
-      else oz_mma<S>(buf, wm, wn, lane, acc2);
+  for (int p = 0; p < 3; ++p) {
+    if (p == 2) {
+#pragma unroll
+      for (int d = 0; d < S; ++d) {
+        const v4i t1 = acc0[d], t2 = acc1[d];
+        acc0[d] = t1 - t2;
+        acc1[d] = -(t1 + t2);
+      }
     }
+    for (int kc = 0; kc < nkc; ++kc) {
+      oz_stage<S>(pr, lds, m0, n0, p, kc, w, lane);
+      __builtin_amdgcn_s_waitcnt(0);   // this wave's loads are in LDS
+      __syncthreads();                 // ... and every wave's
+      if (p == 0) oz_mma<S>(lds, wm, wn, lane, acc0);
+      else oz_mma<S>(lds, wm, wn, lane, acc1);
+      __syncthreads();                 // every wave has read the stage before the next overwrites it
+    }
+  }
+  if (nkc == 0) {
+#pragma unroll
+    for (int d = 0; d < S; ++d) acc0[d] = acc1[d] = v4i{0, 0, 0, 0};
   }
 
   // epilogue: lane l, register r holds output row 4 (l >> 4) + r, column l & 15 of the wave's block
@@ -296,9 +317,8 @@ __global__ __launch_bounds__(256) void k_oz_gemm(const GemmProbOZ* __restrict__ 
     int xr[S], xi[S];
 #pragma unroll
     for (int d = 0; d < S; ++d) {
-      const int t1 = acc0[d][r], t2 = acc1[d][r], t3 = acc2[d][r];
-      xr[d] = t1 - t2;
-      xi[d] = t3 - t1 - t2;
+      xr[d] = acc0[d][r];
+      xi[d] = acc1[d][r];
     }
     const int sc = pr.ea[row] + pr.eb[col];
     dd re = oz_sum<S>(xr), im = oz_sum<S>(xi);
