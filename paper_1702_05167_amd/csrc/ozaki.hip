@@ -276,7 +276,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int grp = local / (OZ_GROUP * tn), idx = local % (OZ_GROUP * tn);
   const int rows = min(OZ_GROUP, tm - grp * OZ_GROUP);
   const int m0 = (grp * OZ_GROUP + idx % rows) * OZ_TILE, n0 = (idx / rows) * OZ_TILE;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  // the wave index is uniform across the wave: kept in scalar registers, so that every address but
+  // the lane's own offset is scalar arithmetic
+  const int t = threadIdx.x, lane = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int wm = w >> 1, wn = w & 1;
 
   v4i acc0[S], acc1[S];
