@@ -49,11 +49,11 @@ OZ_INT8_OPS_PER_CFLOP = OZ_INT8_OPS_PER_CMAC / 8
 # HBM traffic of k_oz_gemm per launch from two rocprofv3 --pmc passes over the same workload (the
 # benchmark cube, one set-up batch and one step of 16 energies, through the native driver
 # paper_1702_05167_amd/hsc_run; profiles/k_oz_gemm_cube32_nd8_counters.md), each scaled by what the
-# counter reads for a plain copy of 64 MiB (FETCH_SIZE 32781.5 KiB for 65536 KiB read, WRITE_SIZE
+# counter reads for a plain copy of 64 MiB (FETCH_SIZE 32781.6 KiB for 65536 KiB read, WRITE_SIZE
 # 65536 KiB for 65536 KiB written).  Valid only for the kernel source they were taken on.
-OZ_TRAFFIC = {"source": "paper_1702_05167_amd/csrc/ozaki.hip", "sha256": "b9d5f3451ba8877ecf056d7e00a56831e74e682ed7704fe211d6b99714da5942",
-              "fetch_kib_per_launch": 2425339.1, "write_kib_per_launch": 958349.1, "launches": 268,
-              "fetch_scale": 65536.0 / 32781.5, "write_scale": 65536.0 / 65536.0}
+OZ_TRAFFIC = {"source": "paper_1702_05167_amd/csrc/ozaki.hip", "sha256": "1615e25dfa5a606d6f1f4eb19a6195a23c4a1b9010053725f0b730493bc1162d",
+              "fetch_kib_per_launch": 2777493.0, "write_kib_per_launch": 1455720.2, "launches": 268,
+              "fetch_scale": 65536.0 / 32781.6, "write_scale": 65536.0 / 65536.0}
 
 
 def oz_traffic():
