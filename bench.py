@@ -175,6 +175,9 @@ def main():
     ap.add_argument("--uneven", type=int, default=0, metavar="D",
                     help="measure D of the 64 uneven cuboids instead: forest batch vs one device at a time")
     ap.add_argument("--uneven-energies", type=int, default=32)
+    ap.add_argument("--config2-full", action="store_true",
+                    help="all 64 uneven cuboids x 128 energies at --precision on 3D trees (leaves <= 8), "
+                         "through hsc_solve_batch four devices at a time, one progress line per call")
     ap.add_argument("--trilayer", action="store_true",
                     help="measure the 40,020-site trilayer x 512 energies instead, with its error")
     ap.add_argument("--learned-grid", action="store_true",
@@ -212,6 +215,9 @@ def main():
 
     if args.learned_grid:
         learned_grid_study(pkg, synth, np)
+        return
+    if args.config2_full:
+        config2_full(pkg, synth, np, torch, args)
         return
     if args.uneven > 0:
         uneven_study(pkg, synth, np, torch, args)
@@ -671,6 +677,38 @@ def uneven_study(pkg, synth, np, torch, args):
                                  "sides": [list(map(int, s)) for s in synth.config2_sizes()[:D]],
                                  "one_device_at_a_time": D * NE / t_loop, "status_ok": ok,
                                  "whole_solve_tflops": flops / t_batch / 1e12}}), flush=True)
+
+
+def config2_full(pkg, synth, np, torch, args):
+    """The uneven-device workload at its size: 64 cuboids (sides 16..48, on-site N(0, 0.3^2)) x 128
+    energies in [-6, 6], every device on its 3D nested-dissection tree (leaves <= 8), at --precision;
+    hsc_solve_batch over four devices per call (plans built inside the timed pass)."""
+    NE = 128
+    ctx = pkg.Context(0)
+    E = torch.tensor(np.linspace(-6.0, 6.0, NE), dtype=torch.float64, device="cuda:0")
+    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=args.precision, complex3m=args.complex3m, tune=0,
+              want=pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS)
+    sizes = synth.config2_sizes()
+    flops, ok, t0 = 0.0, True, time.perf_counter()
+    for g in range(0, 64, 4):
+        devs = [synth.config2_devices(which=[d])[0] for d in range(g, g + 4)]
+        trees = [pkg.Tree.from_device(d, leaf_side=8) for d in devs]
+        flops += sum(t.stats()["flops_per_energy"] for t in trees) * NE
+        outs = pkg.solve_batch(ctx, trees, E, **kw)
+        torch.cuda.synchronize()
+        ok = ok and all(int(o["status"].abs().sum().item()) == 0 for o in outs)
+        note(f"devices {g}..{g + 3} done ({sum(d.n for d in devs)} sites), {time.perf_counter() - t0:.1f} s")
+        del outs, trees, devs
+    dt = time.perf_counter() - t0
+    note(f"64 devices x {NE} energies: {64 * NE / dt:.2f} device-energies/s, {flops / dt / 1e12:.2f} TFLOP/s")
+    print(json.dumps({"metric": "uneven devices at full size: device-energies/s (diag G^r, G^<, T)",
+                      "value": 64 * NE / dt, "unit": "device-energies/s", "higher_is_better": True, "n_gpus": 1,
+                      "dtype": "c128 in/out, complex double-double inside" if args.precision else "c128",
+                      "data": "synthetic",
+                      "config": {"workload": "64 uneven cuboids (sides 16..48, N(0, 0.3^2)) x 128 energies in [-6, 6]",
+                                 "sites_total": int(sum(int(np.prod(s)) for s in sizes)), "seconds": dt,
+                                 "precision": args.precision, "tree": "3D nested dissection, leaves <= 8",
+                                 "whole_solve_tflops": flops / dt / 1e12, "status_ok": ok}}), flush=True)
 
 
 def learned_grid_study(pkg, synth, np):

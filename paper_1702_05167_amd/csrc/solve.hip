@@ -1782,7 +1782,13 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
   }
   const size_t o_ftj = b.ddx ? b.face_trans_jobs<zdd>() : b.face_trans_jobs<double2>();
   {
-    const hsc_status rc = upload_plan(b, pl.get());
+    hsc_status rc = upload_plan(b, pl.get());
+    if (rc == HSC_E_OOM && b.oz_need > 0 && !pl->oz && !ctx->plans.empty()) {
+      // the slice scratch did not fit beside the cached plans (nothing of this plan was uploaded
+      // yet): drop them and try once more
+      ctx->plans.clear();
+      rc = upload_plan(b, pl.get());
+    }
     if (rc != HSC_OK) return rc;
   }
   pl->left = reinterpret_cast<int64_t*>(pl->blob + o_left);
