@@ -42,25 +42,37 @@ FP64_VALU_PEAK_TOPS = 39.3
 DD_OPS_PER_CMAC = 36
 DD_OPS_PER_CFLOP = DD_OPS_PER_CMAC / 8
 # dense int8 matrix-core peak of the chip (5.0 P int8 ops/s) and the int8 operations of one complex
-# double-double multiply-add in k_oz_gemm: 3 real products (Gauss) x 136 slice pairs x 2
+# double-double multiply-add in k_oz_gemm: 3 real products (Gauss) x 120 slice pairs (15 slices,
+# s + t <= 14) x 2
 INT8_MFMA_PEAK_TOPS = 5000.0
-OZ_INT8_OPS_PER_CMAC = 3 * 136 * 2
+OZ_INT8_OPS_PER_CMAC = 3 * 120 * 2
 OZ_INT8_OPS_PER_CFLOP = OZ_INT8_OPS_PER_CMAC / 8
 # HBM traffic of k_oz_gemm per launch from two rocprofv3 --pmc passes over the same workload (the
 # benchmark cube, one set-up batch and one step of 16 energies, through the native driver
 # paper_1702_05167_amd/hsc_run; profiles/k_oz_gemm_cube32_nd8_counters.md), each scaled by what the
-# counter reads for a plain copy of 64 MiB (FETCH_SIZE 32781.6 KiB for 65536 KiB read, WRITE_SIZE
-# 65536 KiB for 65536 KiB written).  Valid only for the kernel source they were taken on.
-OZ_TRAFFIC = {"source": "paper_1702_05167_amd/csrc/ozaki.hip", "sha256": "1615e25dfa5a606d6f1f4eb19a6195a23c4a1b9010053725f0b730493bc1162d",
-              "fetch_kib_per_launch": 2777493.0, "write_kib_per_launch": 1455720.2, "launches": 268,
-              "fetch_scale": 65536.0 / 32781.6, "write_scale": 65536.0 / 65536.0}
+# counter reads for a plain copy of 64 MiB (FETCH_SIZE 32781.2 KiB for 65536 KiB read, WRITE_SIZE
+# 65536 KiB for 65536 KiB written).  Valid only for the kernel sources they were taken on.
+OZ_TRAFFIC = {"sources": ["paper_1702_05167_amd/csrc/ozaki.hip", "paper_1702_05167_amd/csrc/kern.h"],
+              "sha256": "608f305c450c5ad973495a30b2a8f16486532fec7e6fc86d505033e06eb49dfe",
+              "fetch_kib_per_launch": 2301620.2, "write_kib_per_launch": 972883.9, "launches": 264,
+              "fetch_scale": 65536.0 / 32781.1875, "write_scale": 65536.0 / 65536.0}
+
+
+def oz_sources_sha256():
+    """SHA-256 over the sources that define k_oz_gemm (the kernel and its slice count)."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in OZ_TRAFFIC["sources"]:
+        path = os.path.join(ROOT, rel)
+        if not os.path.exists(path):
+            return None
+        h.update(open(path, "rb").read())
+    return h.hexdigest()
 
 
 def oz_traffic():
-    """Measured bytes per k_oz_gemm launch, or None when the kernel source changed since."""
-    import hashlib
-    path = os.path.join(ROOT, OZ_TRAFFIC["source"])
-    if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != OZ_TRAFFIC["sha256"]:
+    """Measured bytes per k_oz_gemm launch, or None when the kernel sources changed since."""
+    if oz_sources_sha256() != OZ_TRAFFIC["sha256"]:
         return None
     return 1024.0 * (OZ_TRAFFIC["fetch_kib_per_launch"] * OZ_TRAFFIC["fetch_scale"] +
                      OZ_TRAFFIC["write_kib_per_launch"] * OZ_TRAFFIC["write_scale"])

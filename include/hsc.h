@@ -144,12 +144,13 @@ typedef struct {
    *     channels and their products is carried in double-double and only the
    *     returned diagonals are rounded to complex128;
    * 3 = as 2, with every double-double block product of depth K >= 32 formed
-   *     on the integer matrix cores: each operand is split exactly into 16
-   *     signed 8-bit slices scaled by a power of two per row (per column of
-   *     the right operand), the slice products are summed exactly in 32-bit
-   *     integers, and the pairs whose weight is within 2^-105 of the leading
-   *     one are combined in double-double (at most about K 2^-104 times the
-   *     product of the largest row and column entries; products with K < 32, the
+   *     on the integer matrix cores: each operand is split into 15 signed
+   *     8-bit slices scaled by a power of two per row (per column of the right
+   *     operand), to 2^-105 of the row's largest entry, the slice products are
+   *     summed exactly in 32-bit integers, and the pairs whose weight is within
+   *     2^-98 of the leading one are combined in double-double (at most about
+   *     K 2^-97 times the product of the largest row and column entries, some
+   *     44 bits beyond complex128; products with K < 32, the
    *     pivot-block inverse updates among them, stay on the vector units).
    *     Needs a slice scratch of up to 4 GiB besides the workspace.
    * The unpivoted cluster elimination amplifies rounding errors by up to

@@ -253,9 +253,12 @@ int dd_inv_nb(int max_n);
 constexpr int kDDSuper = 64;
 
 // ---- double-double products from 8-bit slices on the integer matrix cores (ozaki.hip) ----
-// slices per operand: each double-double operand is kept to 2^-112 of its row's (or column's)
+// slices per operand: each double-double operand is kept to 2^-105 of its row's (or column's)
 // largest entry
-constexpr int kOzSlices = 16;
+constexpr int kOzSlices = 15;
+// deepest slice product: the int32 accumulator of one weight sums up to 3 Gauss parts x kOzSlices
+// pairs x 64^2 x Kp, which must stay below 2^31
+constexpr int kOzMaxDepth = (int)(((1ll << 31) - 1) / (3ll * kOzSlices * 64 * 64) / 64 * 64);
 // One operand to split: element (r, k) = X[r * ldr + k * ldk] for r < R, k < K (complex
 // double-double); out = 3 x kOzSlices planes (Re, Im, Re + Im) of Rp x Kp int8 in 1 KB fragments of
 // 16 rows x 64 k (matrix-core operand order), ex = [Rp] row exponents; Rp a multiple of 32 (>= R),

@@ -19,14 +19,18 @@
 // integer sums combine exactly into Re = T1 - T2 and Im = T3 - T1 - T2, and the
 // S weighted partial sums of each are added in double-double only at the end.
 //
-// Error (S = 16): the dropped pairs (weights 2^-124 and below, at most 64^2 K
-// per pair and slice) and the slice remainders (2^-113 of the row scale) give,
-// for each output, at most about K 2^-106 * 2^(e_i + f_j) <= K 2^-104 max_k
-// |op(A)_ik| max_k |op(B)_kj| (row scale of op(A) times column scale of op(B)),
-// plus the double-double rounding of the final sums and of beta C (2^-104
-// relative); with digits of random sign it is typically far smaller.  Unlike an emulated double-double product, the
-// bound is relative to the largest entries of the row and column, not to
-// sum_k |a_ik| |b_kj|.
+// Error (S = 15): per k and real part product, the dropped pairs (S - 1 of
+// weight 2^-117, fewer below, each at most 64^2) and the slice remainders
+// (2^-105 of the scale) miss at most about (S + 1) 2^-105 of 2^(e_i + f_j);
+// Im = T3 - T1 - T2 sums three such products, so each output is off by at most
+// about 3 (S + 1) K 2^-105 * 2^(e_i + f_j) <= K 2^-97 max_k (|Re| + |Im|)
+// of row i of op(A) times the same of column j of op(B) (2^e <= twice that
+// maximum), plus the double-double rounding of the final sums and of beta C
+// (2^-104 relative); with digits of random sign it is typically far smaller.
+// Fifteen slices keep every product some 44 bits beyond complex128, which the
+// unpivoted cluster elimination needs; a sixteenth would cost 16 more pairs.
+// Unlike an emulated double-double product, the bound is relative to the
+// largest entries of the row and column, not to sum_k |a_ik| |b_kj|.
 //
 // Layout: the slices of one operand are 3 x S planes of int8 (operand part
 // 0 = Re, 1 = Im, 2 = Re + Im; rows padded to the 32-row tile, K padded to 64
@@ -219,38 +223,38 @@ __device__ inline void oz_stage(const GemmProbOZ& pr, v4i* buf, int m0, int n0, 
 // registers, the A slices read from LDS for each half
 template <int S>
 __device__ inline void oz_mma(const v4i* __restrict__ buf, int wm, int wn, int lane, v4i (&acc)[S]) {
-  constexpr int H = S / 2;
+  constexpr int H = (S + 1) / 2;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     v4i b[H];
 #pragma unroll
-    for (int t = 0; t < H; ++t) b[t] = buf[(size_t)((2 + wn) * S + h * H + t) * 64 + lane];
+    for (int t = 0; t < H; ++t)
+      if (h * H + t < S) b[t] = buf[(size_t)((2 + wn) * S + h * H + t) * 64 + lane];
 #pragma unroll
     for (int s = 0; s < S - h * H; ++s) {
       const v4i a = buf[(size_t)(wm * S + s) * 64 + lane];
 #pragma unroll
       for (int t = 0; t < H; ++t)
-        if (s + h * H + t <= S - 1)
+        if (h * H + t < S && s + h * H + t <= S - 1)
           acc[s + h * H + t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b[t], acc[s + h * H + t], 0, 0, 0);
     }
   }
 }
 
-// sum_d x_d 2^(-12 - 7 d) in double-double.  |x_d| < 2^31, so four consecutive weights summed as
-// x_d 2^21 + x_(d+1) 2^14 + x_(d+2) 2^7 + x_(d+3) stay integers below 2^53: each group is formed
-// exactly in FP64 by three exact fused multiply-adds, scaled exactly by its power of two, and the
-// groups are added in double-double, smallest first
+// sum_d x_d 2^(-12 - 7 d) in double-double.  |x_d| < 2^31, so up to four consecutive weights summed
+// as x_d 2^21 + x_(d+1) 2^14 + x_(d+2) 2^7 + x_(d+3) stay integers below 2^53: each group is formed
+// exactly in FP64 by exact fused multiply-adds, scaled exactly by its power of two, and the groups
+// are added in double-double, smallest first
 template <int S>
 __device__ inline dd oz_sum(const int (&x)[S]) {
-  static_assert(S % 4 == 0, "groups of four weights");
   dd v{0.0, 0.0};
 #pragma unroll
-  for (int g0 = S - 4; g0 >= 0; g0 -= 4) {
+  for (int g1 = S - 1; g1 >= 0; g1 -= 4) {
+    const int g0 = g1 >= 3 ? g1 - 3 : 0;
     double acc = (double)x[g0];
-    acc = fma(acc, 128.0, (double)x[g0 + 1]);
-    acc = fma(acc, 128.0, (double)x[g0 + 2]);
-    acc = fma(acc, 128.0, (double)x[g0 + 3]);
-    v = dd_add(v, dd{ldexp(acc, -12 - 7 * (g0 + 3)), 0.0});
+#pragma unroll
+    for (int d = g0 + 1; d <= g1; ++d) acc = fma(acc, 128.0, (double)x[d]);
+    v = dd_add(v, dd{ldexp(acc, -12 - 7 * g1), 0.0});
   }
   return v;
 }

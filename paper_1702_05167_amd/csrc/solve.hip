@@ -588,7 +588,7 @@ struct Builder {
   // runs on the integer matrix cores; the others, and every product without `oz`, on the FP64
   // vector units.
   static constexpr int kOzMinK = 32;
-  static constexpr int kOzMaxK = 10880;   // int32 accumulators: 3 * 16 * 64^2 * Kp < 2^31
+  static constexpr int kOzMaxK = kOzMaxDepth;
   static constexpr size_t kOzStepCap = size_t(4) << 30;   // slice scratch of one product step
   // Measured costs on the target (seconds): splitting one complex double-double element into
   // slices, one padded multiply-add of the slice product, one multiply-add on the vector units.
@@ -682,9 +682,9 @@ struct Builder {
         for (int k = 0; k < tiles; ++k) tmap.push_back((int32_t)gp.size());
         gp.push_back(p);
         flops += 8.0 * g.M * g.N * g.K;
-        // slices of op(A) and op(B) (3 parts x 16 slices of one byte per complex element), their
+        // slices of op(A) and op(B) (3 parts x kOzSlices slices of one byte per complex element), their
         // scales, the double-double result (and its rounded copy), C when accumulating
-        bytes += 48.0 * ((double)g.M * g.K + (double)g.K * g.N) + 4.0 * (g.M + g.N) +
+        bytes += 3.0 * kOzSlices * ((double)g.M * g.K + (double)g.K * g.N) + 4.0 * (g.M + g.N) +
                  (double)g.M * g.N * (32.0 + (g.D64 ? 16.0 : 0.0) + (beta ? 32.0 : 0.0));
       }
       oz_need = std::max(oz_need, cur);
@@ -2407,8 +2407,6 @@ hsc_status hsc_ctx_profile_read(hsc_ctx* ctx, double* out, int32_t n_kinds) {
 
 namespace hsc {
 namespace {
-
-constexpr int kOzMaxDepth = 10880;   // int32 accumulators of the slice products
 
 size_t oz_pad(size_t v, size_t a) { return (v + a - 1) / a * a; }
 

@@ -22,6 +22,12 @@ KW = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1)
 ALL = H.HSC_DIAG_GR | H.HSC_DIAG_GL | H.HSC_TRANS | H.HSC_SPECTRAL_LR
 HERE = os.path.dirname(os.path.abspath(__file__))
 OZ = 3          # hsc_kern_zgemm_dd config of the integer matrix cores
+# error of a config-3 product per unit of K, relative to the row maximum of |Re| + |Im| of op(A)
+# times the column maximum of op(B): each real part product misses at most about (S + 1) 2^-7S of
+# the power-of-two scales (dropped pairs and slice remainders), Im sums three of them, and each
+# scale is below twice its maximum
+SLICES = 15
+OZ_REL = 3 * (SLICES + 1) * 2.0 ** (-7 * SLICES) * 4
 
 
 def _dd_rand(rng, rows, cols, row_scale=None):
@@ -82,7 +88,7 @@ def test_zgemm_oz_against_exact_arithmetic(ctx, shape, opA, opB, negate, beta):
     for i, j in sorted(pairs):
         re, im = _exact_entry(A, B, Cm, i, j, K, opA, opB, negate, beta)
         got = _ex(D[i, j])
-        bound = K * 2.0 ** -104 * _row_max(A, opA, i, K) * _row_max(B, 1 - opB, j, K)
+        bound = K * OZ_REL * _row_max(A, opA, i, K) * _row_max(B, 1 - opB, j, K)
         if beta:
             bound += 2.0 ** -102 * (abs(float(_ex(Cm[i, j])[0])) + abs(float(_ex(Cm[i, j])[1])))
         err = max(abs(float(got[0] - re)), abs(float(got[1] - im)))
@@ -93,7 +99,7 @@ def test_zgemm_oz_against_exact_arithmetic(ctx, shape, opA, opB, negate, beta):
 
 def test_zgemm_oz_wide_dynamic_range(ctx):
     # rows of A and columns of B scaled over 16 decades, plus single entries far below their
-    # row's largest: the fixed-point slices keep each entry to 2^-112 of its row's maximum
+    # row's largest: the fixed-point slices keep each entry to 2^-105 of its row's maximum
     M, N, K = 40, 36, 96
     rng = np.random.default_rng(7)
     A = _dd_rand(rng, M, K, row_scale=10.0 ** rng.uniform(-8, 8, M))
@@ -108,7 +114,7 @@ def test_zgemm_oz_wide_dynamic_range(ctx):
                                                     zip(rng.integers(0, M, 25), rng.integers(0, N, 25))]:
         re, im = _exact_entry(A, Bt, None, i, j, K, 0, 1, 0, 0)
         got = _ex(D[i, j])
-        bound = K * 2.0 ** -104 * _row_max(A, 0, i, K) * _row_max(Bt, 0, j, K)
+        bound = K * OZ_REL * _row_max(A, 0, i, K) * _row_max(Bt, 0, j, K)
         worst = max(worst, max(abs(float(got[0] - re)), abs(float(got[1] - im))) / bound)
     print("wide range: worst error / bound", worst)
     assert worst < 1.0
@@ -135,12 +141,20 @@ def test_zgemm_oz_empty_depth_and_in_place(ctx):
 
 
 def test_zgemm_oz_rejects_deep_products(ctx):
+    # the int32 sum of one weight takes up to 3 x 15 pairs x 64^2 x K: K <= 11648 (a multiple of 64)
     dev = ctx.torch_device
-    A = torch.zeros((1, 10881, 4), dtype=torch.float64, device=dev)
-    B = torch.zeros((10881, 1, 4), dtype=torch.float64, device=dev)
-    with pytest.raises(H.HscError) as e:
-        H.kern_zgemm_dd(ctx, 0, 0, A, B, config=OZ)
-    assert e.value.code == -1
+    for K, ok in ((11648, True), (11649, False)):
+        A = torch.ones((1, K, 4), dtype=torch.float64, device=dev)
+        B = torch.ones((K, 1, 4), dtype=torch.float64, device=dev)
+        A[..., 1::2] = 0.0
+        B[..., 1::2] = 0.0
+        if ok:
+            D = H.kern_zgemm_dd(ctx, 0, 0, A, B, config=OZ).cpu().numpy()
+            assert D[0, 0, 0] == 0.0 and D[0, 0, 2] == 2.0 * K, D    # (1 + i)^2 = 2i per term
+        else:
+            with pytest.raises(H.HscError) as e:
+                H.kern_zgemm_dd(ctx, 0, 0, A, B, config=OZ)
+            assert e.value.code == -1
 
 
 @pytest.mark.parametrize("matrix_cores", [0, 1])
