@@ -42,20 +42,26 @@ FP64_VALU_PEAK_TOPS = 39.3
 DD_OPS_PER_CMAC = 36
 DD_OPS_PER_CFLOP = DD_OPS_PER_CMAC / 8
 # dense int8 matrix-core peak of the chip (5.0 P int8 ops/s) and the int8 operations of one complex
-# double-double multiply-add in k_oz_gemm: 3 real products (Gauss) x 120 slice pairs (15 slices,
-# s + t <= 14) x 2
+# double-double multiply-add in k_oz_gemm: 3 real products (Gauss) x S (S + 1) / 2 slice pairs
+# (s + t <= S - 1) x 2; S = 16 slices per operand unless --slices 15
 INT8_MFMA_PEAK_TOPS = 5000.0
-OZ_INT8_OPS_PER_CMAC = 3 * 120 * 2
-OZ_INT8_OPS_PER_CFLOP = OZ_INT8_OPS_PER_CMAC / 8
+OZ_DEFAULT_SLICES = 16
+
+
+def oz_int8_ops_per_cmac(slices):
+    s = slices or OZ_DEFAULT_SLICES
+    return 3 * (s * (s + 1) // 2) * 2
+
+
 # HBM traffic of k_oz_gemm per launch from two rocprofv3 --pmc passes over the same workload (the
 # benchmark cube, one set-up batch and one step of 16 energies, through the native driver
 # paper_1702_05167_amd/hsc_run; profiles/k_oz_gemm_cube32_nd8_counters.md), each scaled by what the
-# counter reads for a plain copy of 64 MiB (FETCH_SIZE 32781.2 KiB for 65536 KiB read, WRITE_SIZE
+# counter reads for a plain copy of 64 MiB (FETCH_SIZE 32780.9 KiB for 65536 KiB read, WRITE_SIZE
 # 65536 KiB for 65536 KiB written).  Valid only for the kernel sources they were taken on.
 OZ_TRAFFIC = {"sources": ["paper_1702_05167_amd/csrc/ozaki.hip", "paper_1702_05167_amd/csrc/kern.h"],
-              "sha256": "608f305c450c5ad973495a30b2a8f16486532fec7e6fc86d505033e06eb49dfe",
-              "fetch_kib_per_launch": 2301620.2, "write_kib_per_launch": 972883.9, "launches": 264,
-              "fetch_scale": 65536.0 / 32781.1875, "write_scale": 65536.0 / 65536.0}
+              "sha256": "0e6b27ce380b29b27c1ed7760b04177ae8cea03317a5cbce1903a44cdfa75efa",
+              "fetch_kib_per_launch": 2768459.3, "write_kib_per_launch": 1455712.0, "launches": 268,
+              "fetch_scale": 65536.0 / 32780.875, "write_scale": 65536.0 / 65536.0}
 
 
 def oz_sources_sha256():
@@ -110,7 +116,7 @@ def golden_errors(np, gold, gr_all, gl_all, tr_all):
             "out_of_band_max": max(x for x, b in zip(errs, band) if not b)}
 
 
-def roofline_of(prof, precision, prof_bytes=None):
+def roofline_of(prof, precision, prof_bytes=None, slices=0):
     """Algorithmic roofline of the dominant block-product kernel from per-kind launch timing
     (HIP events on the solver's stream): achieved = sum of 8 M N K over its launches / sum of
     their durations, against the FP64 matrix-core peak."""
@@ -118,9 +124,10 @@ def roofline_of(prof, precision, prof_bytes=None):
     g, gd, go = prof["gemm"], prof["dd_gemm"], prof["oz_gemm"]
     if go["ms"] > max(gd["ms"], g["ms"]):
         ach = go["flops"] / (go["ms"] * 1e-3) / 1e12
-        i8 = ach * OZ_INT8_OPS_PER_CFLOP
+        i8 = ach * oz_int8_ops_per_cmac(slices) / 8
         alg_bytes = prof_bytes["oz_gemm"] / go["launches"] if prof_bytes and go["launches"] else None
-        traffic = oz_traffic()
+        # the counters were taken with the default slice count
+        traffic = oz_traffic() if (slices or OZ_DEFAULT_SLICES) == OZ_DEFAULT_SLICES else None
         return {"bound": "mfma", "kernel": "k_oz_gemm (complex double-double products from 8-bit slices, "
                                            "integer matrix cores)",
                 "achieved": ach, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_MFMA_PEAK_TFLOPS,
@@ -132,7 +139,7 @@ def roofline_of(prof, precision, prof_bytes=None):
                 "share_of_kernel_time": go["ms"] / total_ms,
                 "int8_matrix_cores": {"achieved": i8, "peak": INT8_MFMA_PEAK_TOPS, "unit": "T int8 ops/s",
                                       "frac": i8 / INT8_MFMA_PEAK_TOPS,
-                                      "int8_ops_per_complex_multiply_add": OZ_INT8_OPS_PER_CMAC,
+                                      "int8_ops_per_complex_multiply_add": oz_int8_ops_per_cmac(slices),
                                       "note": "unpadded M N K; padding to 32 x 32 x 64 tiles not counted"}}
     if precision >= 1 and gd["ms"] > 0:
         ach = gd["flops"] / (gd["ms"] * 1e-3) / 1e12
@@ -178,6 +185,8 @@ def main():
     ap.add_argument("--transverse", action="store_true",
                     help="never cut the transport axis (clusters span contact to contact)")
     ap.add_argument("--tune", type=int, default=1, help="1 (default): autotune the GEMM tile shape per launch")
+    ap.add_argument("--slices", type=int, default=0,
+                    help="8-bit slices per operand of the precision-3 products: 0 (the library's 16) or 15")
     ap.add_argument("--complex3m", type=int, default=1,
                     help="1 (default): three real products per complex multiply-add in every complex128 block "
                          "product; 0: four")
@@ -265,7 +274,8 @@ def main():
     # the grid as numpy builds it (torch.linspace differs from it by an ulp at some points)
     grid = np.linspace(-6.0, 6.0, NE)
     E = torch.tensor(grid, dtype=torch.float64, device="cuda:0")
-    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=args.precision, complex3m=args.complex3m,
+    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=args.precision, slices=args.slices,
+              complex3m=args.complex3m,
               tune=args.tune, batch=B)
     want = pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS
     gpath = os.path.join(ROOT, "tests", "golden", "cube32_sampled.json")
@@ -305,7 +315,7 @@ def main():
     prof_bytes = ctx.profile_bytes()
     launches = ctx.profile_launches()
     ctx.profile(False)
-    roof = roofline_of(prof, args.precision, prof_bytes)
+    roof = roofline_of(prof, args.precision, prof_bytes, args.slices)
     by_phase = {}
     for kind, fl, ms, ph in launches:
         key = f"{ctx.PROFILE_PHASES[int(ph)]}/{ctx.PROFILE_KINDS[int(kind)]}"
@@ -401,8 +411,8 @@ def main():
 
     prec_name = {0: "complex128", 1: "double-double fold, complex128 extraction",
                  2: "double-double fold and extraction",
-                 3: "double-double fold and extraction, products of depth >= 32 from 8-bit slices on the "
-                    "integer matrix cores"}[args.precision]
+                 3: f"double-double fold and extraction, products of depth >= 32 from 8-bit slices "
+                    f"({args.slices or OZ_DEFAULT_SLICES} per operand) on the integer matrix cores"}[args.precision]
     line = {
         "metric": "energies/s (diag G^r,G^<), 32^3 cube, batched vs plain; % FP64 MFMA peak",
         "value": value,
@@ -512,7 +522,8 @@ def dense_study(pkg, synth, np, torch, args):
     """Time per energy with whole-face (dense) and per-site (diagonal) contact self-energies, the
     cuboid experiments of Section 3.1.2: cubes N^3 (N = 16 .. 36) and elongated devices with fixed
     16 x 16 faces and growing length (Nx = 16 .. 128), at --precision, batches of --batch energies."""
-    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=args.precision, complex3m=args.complex3m,
+    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=args.precision, slices=args.slices,
+              complex3m=args.complex3m,
               tune=0, batch=args.batch)
     want = pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS
     E = torch.tensor(np.linspace(-1.9, 1.9, args.batch), dtype=torch.float64, device="cuda:0")
@@ -552,7 +563,8 @@ def orbital_study(pkg, synth, np, torch, args):
     """Multi-orbital site blocks (10 orbitals per site, random blocks: the block structure of the
     paper's sp3d5s* nanowires): wires of 4 x 4 and 6 x 6 sites across and 32 .. 128 sites long, per-site
     leads on every orbital of the end faces, at --precision, batches of --batch energies in [-4, 4]."""
-    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=args.precision, complex3m=args.complex3m,
+    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=args.precision, slices=args.slices,
+              complex3m=args.complex3m,
               tune=0, batch=args.batch)
     want = pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS
     E = torch.tensor(np.linspace(-4.0, 4.0, args.batch), dtype=torch.float64, device="cuda:0")
@@ -594,7 +606,8 @@ def trilayer_study(pkg, synth, np, torch, args):
     tree = pkg.Tree.from_device(dev, leaf_side=8)
     ctx = pkg.Context(0)
     E = torch.tensor(np.linspace(-3.0, 3.0, 512), dtype=torch.float64, device="cuda:0")
-    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=args.precision, complex3m=args.complex3m,
+    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=args.precision, slices=args.slices,
+              complex3m=args.complex3m,
               tune=args.tune, want=pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS)
     out = pkg.solve(ctx, tree, E, **kw)
     torch.cuda.synchronize()
@@ -698,7 +711,8 @@ def config2_full(pkg, synth, np, torch, args):
     NE = 128
     ctx = pkg.Context(0)
     E = torch.tensor(np.linspace(-6.0, 6.0, NE), dtype=torch.float64, device="cuda:0")
-    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=args.precision, complex3m=args.complex3m, tune=0,
+    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, precision=args.precision, slices=args.slices,
+              complex3m=args.complex3m, tune=0,
               want=pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS)
     sizes = synth.config2_sizes()
     flops, ok, t0 = 0.0, True, time.perf_counter()

@@ -144,13 +144,13 @@ typedef struct {
    *     channels and their products is carried in double-double and only the
    *     returned diagonals are rounded to complex128;
    * 3 = as 2, with every double-double block product of depth K >= 32 formed
-   *     on the integer matrix cores: each operand is split into 15 signed
-   *     8-bit slices scaled by a power of two per row (per column of the right
-   *     operand), to 2^-105 of the row's largest entry, the slice products are
-   *     summed exactly in 32-bit integers, and the pairs whose weight is within
-   *     2^-98 of the leading one are combined in double-double (at most about
-   *     K 2^-97 times the product of the largest row and column entries, some
-   *     44 bits beyond complex128; products with K < 32, the
+   *     on the integer matrix cores: each operand is split into 16 signed
+   *     8-bit slices (`slices` below) scaled by a power of two per row (per
+   *     column of the right operand), to 2^-112 of the row's largest entry,
+   *     the slice products are summed exactly in 32-bit integers, and the pairs
+   *     whose weight is within 2^-105 of the leading one are combined in
+   *     double-double (at most about K 2^-104 times the product of the largest
+   *     row and column entries; products with K < 32, the
    *     pivot-block inverse updates among them, stay on the vector units).
    *     Needs a slice scratch of up to 4 GiB besides the workspace.
    * The unpivoted cluster elimination amplifies rounding errors by up to
@@ -178,6 +178,14 @@ typedef struct {
    * (Ar+Ai)(Br+Bi)), a quarter less matrix-core work with an imaginary-part
    * error bound proportional to (|Ar| + |Ai|)(|Br| + |Bi|). */
   int32_t complex3m;
+  /* precision 3: 8-bit slices per operand of the integer-matrix-core products.
+   * 0 = 16 (the default), or 16 or 15: fifteen keep every operand to 2^-105
+   * instead of 2^-112 of its row's largest entry (a product bound of about
+   * K 2^-97 instead of K 2^-104 times the row and column maxima) for 120
+   * instead of 136 slice pairs, about 6 % less solve time; entries far below
+   * their row's largest (large devices out of the lead band) then lose up to
+   * two more digits.  Ignored with precision 0-2.  Other values: HSC_E_ARG. */
+  int32_t slices;
 } hsc_solve_opts;
 
 /* Library version string. */
@@ -338,15 +346,15 @@ hsc_status hsc_totals(hsc_ctx* ctx, int32_t n_e, int64_t n, const void* diag_gr,
  * super-panel preparation, 15 operand splitting into 8-bit slices, 16 slice
  * products on the integer matrix cores (precision 3), 17 double-double inverse
  * super-panel preparation, 18-19 the dense self-energy of whole-face contacts
- * (partial mode sums, then the face block).
+ * (partial mode sums, then the face block), 20 bond entries (HSC_BOND_GR/GL).
  * hsc_ctx_profile_read writes out[3*k + {0,1,2}] = launches, milliseconds,
  * algorithmic real flops (GEMM: 8 M N K per problem) for k < n_kinds.
  * Errors: HSC_E_ARG. */
 hsc_status hsc_ctx_profile(hsc_ctx* ctx, int32_t enable);
 hsc_status hsc_ctx_profile_read(hsc_ctx* ctx, double* out, int32_t n_kinds);
 /* out[k] = algorithmic bytes of the timed launches of kind k since profiling was enabled (so far
- * counted for the slice products, kind 16: slices of both operands read, 48 B per complex
- * element; row and column scales; the double-double result written, its rounded copy, and C when
+ * counted for the slice products, kind 16: slices of both operands read, 3 S B per complex
+ * element with S slices per operand; row and column scales; the double-double result written, its rounded copy, and C when
  * accumulating); 0 for kinds not counted.  Errors: HSC_E_ARG. */
 hsc_status hsc_ctx_profile_bytes(hsc_ctx* ctx, double* out, int32_t n_kinds);
 

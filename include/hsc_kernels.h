@@ -49,15 +49,17 @@ hsc_status hsc_kern_zgemm_tile(hsc_ctx* ctx, int32_t tile_kind, int32_t opA, int
  * result is accurate to about 2^-104 relative to sum_k |op(A)_ik| |op(B)_kj|
  * (products accumulated lazily, renormalised every 8 terms).  config 3: the
  * integer matrix cores (the products of hsc_solve_opts.precision = 3): op(A)
- * split into 15 signed 8-bit slices per element with one power-of-two scale per
+ * split into 16 signed 8-bit slices per element with one power-of-two scale per
  * row, op(B) likewise per column (the error-free splitting of Ozaki et al.),
- * exact int32 sums of slice products, the leading 120 of 225 slice pairs
- * combined in double-double; the error is at most about K 2^-97 max_k
+ * exact int32 sums of slice products, the leading 136 of 256 slice pairs
+ * combined in double-double; the error is at most about K 2^-104 max_k
  * (|Re| + |Im|) of row i of op(A) times the same of column j of op(B), plus
- * 2^-104 |C_ij|, K <= 11648.  beta is 0 or 1; C
+ * 2^-104 |C_ij|, K <= 10880.  config 4: as 3 with 15 slices (120 pairs, the
+ * products of hsc_solve_opts.slices = 15): K 2^-97 instead of K 2^-104,
+ * K <= 11648.  beta is 0 or 1; C
  * may equal D and may be NULL when beta = 0.  Synchronous.
  * Errors: HSC_E_ARG (sizes < 0, bad op or config, leading dimension too small,
- * K > 11648 with config 3), HSC_E_OOM, HSC_E_HIP. */
+ * K beyond the limit of config 3 or 4), HSC_E_OOM, HSC_E_HIP. */
 hsc_status hsc_kern_zgemm_dd(hsc_ctx* ctx, int32_t config, int32_t opA, int32_t opB, int32_t M, int32_t N,
                              int32_t K, int32_t negate, const void* A, int32_t lda, const void* B, int32_t ldb,
                              int32_t beta, const void* C, int32_t ldc, void* D, int32_t ldd);
@@ -70,9 +72,9 @@ hsc_status hsc_kern_zgemm_dd(hsc_ctx* ctx, int32_t config, int32_t opA, int32_t 
  * GPU (held from the first context on that GPU until the process ends); the
  * call allocates nothing and does not wait: it enqueues four kernels on the
  * context's stream and returns (D is valid after hsc_sync or a stream
- * synchronisation).  Limit: the scratch of one product, 45 (Mp + Np) Kp bytes
+ * synchronisation).  Limit: the scratch of one product, 48 (Mp + Np) Kp bytes
  * plus maps (Mp, Np = M, N rounded up to 32, Kp = K rounded up to 64), must fit
- * 64 MiB (e.g. M = N = 1024 with K <= 704); larger products return HSC_E_ARG.
+ * 64 MiB (e.g. M = N = 1024 with K <= 640); larger products return HSC_E_ARG.
  * Every call on one GPU shares that array and leaves it holding its own
  * intermediates: calls that overlap on one GPU (other streams, other contexts,
  * other threads) race and must be serialised by the caller.

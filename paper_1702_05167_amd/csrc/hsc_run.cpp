@@ -3,7 +3,7 @@
 // energy grid in steps of one batch, exactly as the throughput benchmark walks it.
 //
 //   hsc_run DEVICE_FILE [--batch B] [--steps K] [--warmup W] [--precision P] [--leaf L]
-//                       [--dense 0|1] [--tune 0|1] [--copy-mib M]
+//                       [--dense 0|1] [--tune 0|1] [--slices S] [--copy-mib M]
 //
 // --copy-mib M first runs one elementwise copy kernel of M MiB (read M, write M), whose counter
 // readings calibrate the HBM byte counters.
@@ -46,10 +46,10 @@ int fail(const char* what) {
 int main(int argc, char** argv) {
   if (argc < 2) {
     fprintf(stderr, "usage: hsc_run DEVICE_FILE [--batch B] [--steps K] [--warmup W] [--precision P] "
-                    "[--leaf L] [--dense 0|1] [--tune 0|1] [--copy-mib M]\n");
+                    "[--leaf L] [--dense 0|1] [--tune 0|1] [--slices S] [--copy-mib M]\n");
     return 2;
   }
-  int batch = 16, steps = 1, warmup = 1, precision = 3, leaf = 8, dense = 0, tune = 1, copy_mib = 0;
+  int batch = 16, steps = 1, warmup = 1, precision = 3, leaf = 8, dense = 0, tune = 1, slices = 0, copy_mib = 0;
   for (int a = 2; a + 1 < argc; a += 2) {
     const std::string k = argv[a];
     const int v = atoi(argv[a + 1]);
@@ -60,6 +60,7 @@ int main(int argc, char** argv) {
     else if (k == "--leaf") leaf = v;
     else if (k == "--dense") dense = v;
     else if (k == "--tune") tune = v;
+    else if (k == "--slices") slices = v;
     else if (k == "--copy-mib") copy_mib = v;
     else { fprintf(stderr, "hsc_run: unknown option %s\n", k.c_str()); return 2; }
   }
@@ -127,7 +128,7 @@ int main(int argc, char** argv) {
   hsc_solve_opts o{};
   o.eta = 1e-8; o.kT = 0.025; o.mu_L = 0.1; o.mu_R = -0.1;
   o.want = HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS;
-  o.batch = batch; o.precision = precision; o.tune = tune; o.complex3m = 1;
+  o.batch = batch; o.precision = precision; o.tune = tune; o.complex3m = 1; o.slices = slices;
   // step k solves the next `batch` grid points (wrapping around), as the benchmark does
   std::vector<double> e_step(batch);
   double* d_step = nullptr;

@@ -253,14 +253,15 @@ int dd_inv_nb(int max_n);
 constexpr int kDDSuper = 64;
 
 // ---- double-double products from 8-bit slices on the integer matrix cores (ozaki.hip) ----
-// slices per operand: each double-double operand is kept to 2^-105 of its row's (or column's)
-// largest entry
-constexpr int kOzSlices = 15;
-// deepest slice product: the int32 accumulator of one weight sums up to 3 Gauss parts x kOzSlices
-// pairs x 64^2 x Kp, which must stay below 2^31
-constexpr int kOzMaxDepth = (int)(((1ll << 31) - 1) / (3ll * kOzSlices * 64 * 64) / 64 * 64);
+// slices per operand: S = 16 (the default) keeps each double-double operand to 2^-112 of its row's
+// (or column's) largest entry, S = 15 to 2^-105
+constexpr int kOzSlices = 16;
+constexpr int kOzSlicesMin = 15, kOzSlicesMax = 16;
+// deepest slice product: the int32 accumulator of one weight sums up to 3 Gauss parts x S pairs x
+// 64^2 x Kp, which must stay below 2^31
+constexpr int oz_max_depth(int slices) { return (int)(((1ll << 31) - 1) / (3ll * slices * 64 * 64) / 64 * 64); }
 // One operand to split: element (r, k) = X[r * ldr + k * ldk] for r < R, k < K (complex
-// double-double); out = 3 x kOzSlices planes (Re, Im, Re + Im) of Rp x Kp int8 in 1 KB fragments of
+// double-double); out = 3 x S planes (Re, Im, Re + Im) of Rp x Kp int8 in 1 KB fragments of
 // 16 rows x 64 k (matrix-core operand order), ex = [Rp] row exponents; Rp a multiple of 32 (>= R),
 // Kp of 64 (>= K); zero padding.  Row-scale workgroups [blk_off, blk_off + ceil(Rp / 64)) and digit
 // workgroups [tile_off, tile_off + ceil(Rp / 64) * Kp / 32) of a split launch belong to this job.
@@ -286,10 +287,11 @@ struct GemmProbOZ {
   int32_t ldc, ldd, ldd64;
   int32_t tiles_n, tile_off;
 };
-void launch_oz_split(hipStream_t st, const OzSplitJob* jobs, const int32_t* blk_job, int total_blocks,
+// slices: kOzSlicesMin..kOzSlicesMax, the same for the split and the product of one operand pair
+void launch_oz_split(hipStream_t st, int slices, const OzSplitJob* jobs, const int32_t* blk_job, int total_blocks,
                      const int32_t* tile_job, int total_tiles);
-void launch_oz_gemm(hipStream_t st, const GemmProbOZ* probs, const int32_t* tile_prob, int total_tiles, int negate,
-                    int beta);
+void launch_oz_gemm(hipStream_t st, int slices, const GemmProbOZ* probs, const int32_t* tile_prob, int total_tiles,
+                    int negate, int beta);
 // the allocation-free product: a static device array of kOzNoAllocScratch bytes per device holds
 // descriptors, maps, slices and exponents of one problem (oz_noalloc_bytes of them)
 constexpr size_t kOzNoAllocScratch = size_t(64) << 20;

@@ -19,18 +19,18 @@
 // integer sums combine exactly into Re = T1 - T2 and Im = T3 - T1 - T2, and the
 // S weighted partial sums of each are added in double-double only at the end.
 //
-// Error (S = 15): per k and real part product, the dropped pairs (S - 1 of
-// weight 2^-117, fewer below, each at most 64^2) and the slice remainders
-// (2^-105 of the scale) miss at most about (S + 1) 2^-105 of 2^(e_i + f_j);
+// Error: per k and real part product, the dropped pairs (S - 1 of weight
+// 2^(-12-7S), fewer below, each at most 64^2) and the slice remainders
+// (2^-7S of the scale) miss at most about (S + 1) 2^-7S of 2^(e_i + f_j);
 // Im = T3 - T1 - T2 sums three such products, so each output is off by at most
-// about 3 (S + 1) K 2^-105 * 2^(e_i + f_j) <= K 2^-97 max_k (|Re| + |Im|)
-// of row i of op(A) times the same of column j of op(B) (2^e <= twice that
-// maximum), plus the double-double rounding of the final sums and of beta C
-// (2^-104 relative); with digits of random sign it is typically far smaller.
-// Fifteen slices keep every product some 44 bits beyond complex128, which the
-// unpivoted cluster elimination needs; a sixteenth would cost 16 more pairs.
-// Unlike an emulated double-double product, the bound is relative to the
-// largest entries of the row and column, not to sum_k |a_ik| |b_kj|.
+// about 3 (S + 1) K 2^-7S * 2^(e_i + f_j), i.e. K 2^-104 (S = 16) or K 2^-97
+// (S = 15) times max_k (|Re| + |Im|) of row i of op(A) times the same of
+// column j of op(B) (2^e <= twice that maximum), plus the double-double
+// rounding of the final sums and of beta C (2^-104 relative); with digits of
+// random sign it is typically far smaller.  Unlike an emulated double-double
+// product, the bound is relative to the largest entries of the row and column,
+// not to sum_k |a_ik| |b_kj|: entries far below their row's largest keep fewer
+// bits, which is why 16 slices are the default (15 save 16 of 136 pairs).
 //
 // Layout: the slices of one operand are 3 x S planes of int8 (operand part
 // 0 = Re, 1 = Im, 2 = Re + Im; rows padded to the 32-row tile, K padded to 64
@@ -414,24 +414,27 @@ int launch_oz_gemm_noalloc(hipStream_t st, char* ws, int opA, int opB, int M, in
   p.tiles_n = Np / 32; p.tile_off = 0;
   hipLaunchKernelGGL(k_oz_setup, dim3(1), dim3(256), 0, st, ws, ja, jb, p, ba, bb, ta, tb, tiles);
   const int32_t* m = reinterpret_cast<const int32_t*>(ws + 1024);
-  launch_oz_split(st, reinterpret_cast<const OzSplitJob*>(ws), m, ba + bb, m + ba + bb, ta + tb);
-  launch_oz_gemm(st, reinterpret_cast<const GemmProbOZ*>(ws + 256), m + ba + bb + ta + tb, tiles, negate, beta);
+  launch_oz_split(st, kOzSlices, reinterpret_cast<const OzSplitJob*>(ws), m, ba + bb, m + ba + bb, ta + tb);
+  launch_oz_gemm(st, kOzSlices, reinterpret_cast<const GemmProbOZ*>(ws + 256), m + ba + bb + ta + tb, tiles, negate,
+                 beta);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-void launch_oz_split(hipStream_t st, const OzSplitJob* jobs, const int32_t* blk_job, int total_blocks,
+void launch_oz_split(hipStream_t st, int slices, const OzSplitJob* jobs, const int32_t* blk_job, int total_blocks,
                      const int32_t* tile_job, int total_tiles) {
   if (total_blocks <= 0) return;
   hipLaunchKernelGGL(k_oz_scale, dim3(total_blocks), dim3(256), 0, st, jobs, blk_job);
-  if (total_tiles > 0)   // none when K = 0
-    hipLaunchKernelGGL((k_oz_digits<kOzSlices>), dim3(total_tiles), dim3(256), 0, st, jobs, tile_job);
+  if (total_tiles <= 0) return;   // none when K = 0
+  if (slices == 15) hipLaunchKernelGGL((k_oz_digits<15>), dim3(total_tiles), dim3(256), 0, st, jobs, tile_job);
+  else hipLaunchKernelGGL((k_oz_digits<16>), dim3(total_tiles), dim3(256), 0, st, jobs, tile_job);
 }
 
-void launch_oz_gemm(hipStream_t st, const GemmProbOZ* probs, const int32_t* tile_prob, int total_tiles, int negate,
-                    int beta) {
+void launch_oz_gemm(hipStream_t st, int slices, const GemmProbOZ* probs, const int32_t* tile_prob, int total_tiles,
+                    int negate, int beta) {
   if (total_tiles <= 0) return;
   const dim3 g(((total_tiles + 7) / 8) * 8), b(256);
-  hipLaunchKernelGGL((k_oz_gemm<kOzSlices>), g, b, 0, st, probs, tile_prob, total_tiles, negate, beta);
+  if (slices == 15) hipLaunchKernelGGL((k_oz_gemm<15>), g, b, 0, st, probs, tile_prob, total_tiles, negate, beta);
+  else hipLaunchKernelGGL((k_oz_gemm<16>), g, b, 0, st, probs, tile_prob, total_tiles, negate, beta);
 }
 
 }  // namespace hsc

@@ -118,6 +118,7 @@ struct Plan {
   int prec = 0;
   int tune = 0;
   int m3 = 0;                    // complex products in the three-multiplication form
+  int slices = kOzSlices;        // 8-bit slices per operand of the products on the integer matrix cores
   int64_t n = 0;
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -191,6 +192,7 @@ struct Builder {
   bool ddf = false;   // double-double fold
   bool ddx = false;   // double-double extraction as well (G, the lesser channels)
   bool oz = false;    // double-double products from 8-bit slices on the integer matrix cores
+  int slices = kOzSlices;   // slices per operand of those products
   size_t oz_need = 0; // largest slice scratch of one such product step
   size_t ws = 0;  // workspace bytes
   Blob blob;
@@ -588,13 +590,12 @@ struct Builder {
   // runs on the integer matrix cores; the others, and every product without `oz`, on the FP64
   // vector units.
   static constexpr int kOzMinK = 32;
-  static constexpr int kOzMaxK = kOzMaxDepth;
   static constexpr size_t kOzStepCap = size_t(4) << 30;   // slice scratch of one product step
   // Measured costs on the target (seconds): splitting one complex double-double element into
   // slices, one padded multiply-add of the slice product, one multiply-add on the vector units.
   static constexpr double kOzSplitCost = 25e-12, kOzMacCost = 0.55e-12, kValuMacCost = 1.5e-12;
-  static bool oz_pays(const GPD& g) {
-    if (g.K < kOzMinK || g.K > kOzMaxK) return false;
+  bool oz_pays(const GPD& g) const {
+    if (g.K < kOzMinK || g.K > oz_max_depth(slices)) return false;
     const double Mp = oz_round(g.M, 32), Np = oz_round(g.N, 32), Kp = oz_round(g.K, 64);
     const double t_oz = kOzSplitCost * ((g.sa ? 0.0 : Mp) + Np) * Kp + kOzMacCost * Mp * Np * Kp;
     return t_oz < kValuMacCost * (double)g.M * g.N * g.K;
@@ -608,8 +609,8 @@ struct Builder {
   }
 
   static size_t oz_round(size_t v, size_t a) { return (v + a - 1) / a * a; }
-  static size_t oz_bytes(int R, int K) {
-    return oz_round((size_t)3 * kOzSlices * oz_round(R, 32) * oz_round(K, 64) + 4 * oz_round(R, 32), 256);
+  size_t oz_bytes(int R, int K) const {
+    return oz_round((size_t)3 * slices * oz_round(R, 32) * oz_round(K, 64) + 4 * oz_round(R, 32), 256);
   }
 
   // split + product steps, the problem list cut into pieces whose slices fit kOzStepCap; an operand
@@ -635,7 +636,7 @@ struct Builder {
         size_t off;
         if (keep) {
           off = reinterpret_cast<size_t>(wsbase + keep);
-          const auto r = std::make_pair(off, off + (size_t)3 * kOzSlices * Rp * Kp);
+          const auto r = std::make_pair(off, off + (size_t)3 * slices * Rp * Kp);
           seen[key] = r;
           if (std::find(oz_kept.begin(), oz_kept.end(), keep) != oz_kept.end()) return r;
           oz_kept.push_back(keep);
@@ -646,7 +647,7 @@ struct Builder {
         OzSplitJob j{};
         j.X = X; j.ldr = ldr; j.ldk = ldk; j.R = R; j.K = K; j.Rp = Rp; j.Kp = Kp;
         j.out = reinterpret_cast<int8_t*>(off);
-        j.ex = reinterpret_cast<int32_t*>(off + (size_t)3 * kOzSlices * Rp * Kp);
+        j.ex = reinterpret_cast<int32_t*>(off + (size_t)3 * slices * Rp * Kp);
         kept_job.push_back(keep ? 1 : 0);
         const int rblocks = (Rp + 63) / 64;
         j.blk_off = (int32_t)bmap.size();
@@ -654,7 +655,7 @@ struct Builder {
         j.tile_off = (int32_t)tmap_s.size();
         for (int b = 0; b < rblocks * (Kp / 32); ++b) tmap_s.push_back((int32_t)sj.size());
         sj.push_back(j);
-        const auto r = std::make_pair(off, off + (size_t)3 * kOzSlices * Rp * Kp);
+        const auto r = std::make_pair(off, off + (size_t)3 * slices * Rp * Kp);
         seen[key] = r;
         return r;
       };
@@ -682,9 +683,9 @@ struct Builder {
         for (int k = 0; k < tiles; ++k) tmap.push_back((int32_t)gp.size());
         gp.push_back(p);
         flops += 8.0 * g.M * g.N * g.K;
-        // slices of op(A) and op(B) (3 parts x kOzSlices slices of one byte per complex element), their
+        // slices of op(A) and op(B) (3 parts x S slices of one byte per complex element), their
         // scales, the double-double result (and its rounded copy), C when accumulating
-        bytes += 3.0 * kOzSlices * ((double)g.M * g.K + (double)g.K * g.N) + 4.0 * (g.M + g.N) +
+        bytes += 3.0 * slices * ((double)g.M * g.K + (double)g.K * g.N) + 4.0 * (g.M + g.N) +
                  (double)g.M * g.N * (32.0 + (g.D64 ? 16.0 : 0.0) + (beta ? 32.0 : 0.0));
       }
       oz_need = std::max(oz_need, cur);
@@ -1566,11 +1567,11 @@ int run_steps(hsc_ctx* ctx, hipStream_t st, Plan* pl, int e_base, int nvalid, vo
                        reinterpret_cast<const int32_t*>(pl->blob + s.map_k[s.tile]), s.count_k[s.tile], s.i1, s.beta);
         break;
       case S_OZ_SPLIT:
-        launch_oz_split(st, (const OzSplitJob*)jobs, map, s.count,
+        launch_oz_split(st, pl->slices, (const OzSplitJob*)jobs, map, s.count,
                         reinterpret_cast<const int32_t*>(pl->blob + s.map_k[0]), s.count_k[0]);
         break;
       case S_OZ_GEMM:
-        launch_oz_gemm(st, (const GemmProbOZ*)jobs, map, s.count, s.i1, s.beta);
+        launch_oz_gemm(st, pl->slices, (const GemmProbOZ*)jobs, map, s.count, s.i1, s.beta);
         break;
       case S_FACE_HALF:
         launch_face_half(st, (const FaceJob*)jobs, s.njobs, s.i0, s.i1, pl->es);
@@ -1706,10 +1707,14 @@ hsc_status upload_plan(Builder& b, Plan* pl) {
   return HSC_OK;
 }
 
-int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, int tune, int m3, Plan** out) {
+// slices: 8-bit slices per operand of the integer-matrix-core products (precision 3), kOzSlices
+// for the other precisions
+int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, int tune, int m3, int slices,
+               Plan** out) {
   for (size_t k = 0; k < ctx->plans.size(); ++k)
     if (ctx->plans[k]->uid == t->uid && ctx->plans[k]->B == B && ctx->plans[k]->want == want &&
-        ctx->plans[k]->prec == prec && ctx->plans[k]->tune == tune && ctx->plans[k]->m3 == m3) {
+        ctx->plans[k]->prec == prec && ctx->plans[k]->tune == tune && ctx->plans[k]->m3 == m3 &&
+        ctx->plans[k]->slices == slices) {
       // most recently used goes last
       std::unique_ptr<Plan> p = std::move(ctx->plans[k]);
       ctx->plans.erase(ctx->plans.begin() + k);
@@ -1734,10 +1739,12 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
     }
   std::unique_ptr<Plan> pl(new Plan());
   pl->uid = t->uid; pl->B = B; pl->want = want; pl->n = t->n; pl->prec = prec; pl->tune = tune; pl->m3 = m3;
+  pl->slices = slices;
   Builder b{t, B, want, (want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR | HSC_BOND_GL)) != 0};
   b.ddf = prec >= 1;
   b.ddx = prec >= 2;
   b.oz = prec == 3;
+  b.slices = slices;
   b.channels();
   b.layout();
   b.layout_faces();
@@ -1807,11 +1814,12 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
   return HSC_OK;
 }
 
-size_t plan_bytes_per_slot(const hsc_tree* t, uint32_t want, int prec) {
+size_t plan_bytes_per_slot(const hsc_tree* t, uint32_t want, int prec, int slices) {
   Builder b{t, 1, want, (want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR | HSC_BOND_GL)) != 0};
   b.ddf = prec >= 1;
   b.ddx = prec >= 2;
   b.oz = prec == 3;
+  b.slices = slices;
   b.channels();
   b.layout();
   b.layout_faces();
@@ -1823,6 +1831,23 @@ size_t plan_bytes_per_slot(const hsc_tree* t, uint32_t want, int prec) {
 }  // namespace hsc
 
 using namespace hsc;
+
+namespace {
+struct GuardItem {
+  int e;                                   // index into the caller's arrays
+  std::shared_ptr<hsc_tree> tree;          // null: the caller's tree
+  std::vector<int> bad;                    // flagged clusters of that tree
+};
+constexpr int kGuardSets = 8;
+// flagged clusters: ||Psi_i||_inf above tau (the extract multiplies rounding
+// errors of G_ff by Psi on both sides)
+std::vector<int> flagged(const double* g, int nc, double tau) {
+  std::vector<int> b;
+  for (int i = 0; i < nc - 1; ++i)
+    if (!(g[2 * i + 1] <= tau)) b.push_back(i);
+  return b;
+}
+}  // namespace
 
 extern "C" {
 
@@ -1872,6 +1897,13 @@ hsc_status hsc_ctx_destroy(hsc_ctx* ctx) {
   return HSC_OK;
 }
 
+// slices per operand of a solve's integer-matrix-core products: the option (0 = kOzSlices) with
+// precision 3, kOzSlices otherwise (no such products); -1 when the option is out of range
+static int opts_slices(const hsc_solve_opts* o) {
+  if (o->slices != 0 && (o->slices < kOzSlicesMin || o->slices > kOzSlicesMax)) return -1;
+  return o->precision == 3 && o->slices != 0 ? o->slices : kOzSlices;
+}
+
 static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, const double* energies,
                              const hsc_solve_opts* opts, void* diag_gr, void* diag_gl, double* trans,
                              double* spectral_lr, int32_t* status, double* guard, void* bond_gr = nullptr,
@@ -1891,6 +1923,8 @@ static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
     set_error("nothing requested");
     return HSC_E_ARG;
   }
+  const int slices = opts_slices(opts);
+  if (slices < 0) { set_error("slices must be 0, 15 or 16"); return HSC_E_ARG; }
   HIPCHK(hipSetDevice(ctx->device));
   int B = opts->batch;
   if (B <= 0) {
@@ -1898,7 +1932,7 @@ static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
     // the memory that plan now holds would shrink the batch and rebuild the plan on every call
     for (const auto& p : ctx->plans)
       if (p->uid == tree->uid && p->want == want && p->prec == opts->precision && p->tune == (opts->tune != 0) &&
-          p->m3 == opts->complex3m && p->B <= n_e)
+          p->m3 == opts->complex3m && p->slices == slices && p->B <= n_e)
         B = std::max(B, p->B);
   }
   if (B <= 0) {
@@ -1906,7 +1940,7 @@ static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
     // evenly over the fewest batches that count allows (no mostly empty last batch)
     size_t freeb = 0, totalb = 0;
     HIPCHK(hipMemGetInfo(&freeb, &totalb));
-    const size_t per = std::max<size_t>(1, plan_bytes_per_slot(tree, want, opts->precision));
+    const size_t per = std::max<size_t>(1, plan_bytes_per_slot(tree, want, opts->precision, slices));
     const int bmax = (int)std::max<size_t>(1, std::min<size_t>(64, (size_t)(0.70 * (double)freeb) / per));
     const int chunks = (n_e + bmax - 1) / bmax;
     B = (n_e + chunks - 1) / chunks;
@@ -1915,7 +1949,7 @@ static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
   Plan* pl = nullptr;
   if (opts->precision < 0 || opts->precision > 3) { set_error("precision must be 0, 1, 2 or 3"); return HSC_E_ARG; }
   if (opts->complex3m != 0 && opts->complex3m != 1) { set_error("complex3m must be 0 or 1"); return HSC_E_ARG; }
-  int st = build_plan(ctx, tree, B, want, opts->precision, opts->tune != 0, opts->complex3m, &pl);
+  int st = build_plan(ctx, tree, B, want, opts->precision, opts->tune != 0, opts->complex3m, slices, &pl);
   if (st != HSC_OK) return (hsc_status)st;
   const int64_t n = tree->n;
   const bool use_graph = opts->graph != 0 && !guard && !ctx->profile && !(want & (HSC_BOND_GR | HSC_BOND_GL));
@@ -2000,22 +2034,6 @@ static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
 // so their plans) are kept in the context, keyed by the tree and the merged
 // clusters, for later calls.  Rounds repeat until no block is flagged or the
 // rounds run out.
-namespace {
-struct GuardItem {
-  int e;                                   // index into the caller's arrays
-  std::shared_ptr<hsc_tree> tree;          // null: the caller's tree
-  std::vector<int> bad;                    // flagged clusters of that tree
-};
-constexpr int kGuardSets = 8;
-// flagged clusters: ||Psi_i||_inf above tau (the extract multiplies rounding
-// errors of G_ff by Psi on both sides)
-std::vector<int> flagged(const double* g, int nc, double tau) {
-  std::vector<int> b;
-  for (int i = 0; i < nc - 1; ++i)
-    if (!(g[2 * i + 1] <= tau)) b.push_back(i);
-  return b;
-}
-}  // namespace
 
 static hsc_status guard_loop(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, const double* energies,
                              const hsc_solve_opts* opts, void* diag_gr, void* diag_gl, double* trans,
@@ -2281,6 +2299,7 @@ hsc_status hsc_solve_batch(hsc_ctx* ctx, int32_t n_trees, const hsc_tree* const*
   }
   for (int d = 0; d < n_trees; ++d)
     if (!trees[d] || n_e[d] < 0 || (n_e[d] > 0 && !energies[d])) { set_error("bad device entry in hsc_solve_batch"); return HSC_E_ARG; }
+  if (opts_slices(opts) < 0) { set_error("slices must be 0, 15 or 16"); return HSC_E_ARG; }
   if (n_trees <= 1 || opts->guard_tau > 0.0 || guard)
     return solve_each(ctx, n_trees, trees, n_e, energies, opts, diag_gr, diag_gl, trans, spectral_lr, status, guard);
   // one forest when every device has the same energies and lead model (and per-site leads)
@@ -2321,7 +2340,7 @@ hsc_status hsc_solve_batch(hsc_ctx* ctx, int32_t n_trees, const hsc_tree* const*
     int g0 = 0;
     double acc = 0;
     for (int d = 0; d < n_trees; ++d) {
-      const double bd = (double)plan_bytes_per_slot(trees[d], want, opts->precision);
+      const double bd = (double)plan_bytes_per_slot(trees[d], want, opts->precision, opts_slices(opts));
       if (d > g0 && acc + bd > budget) {
         groups.push_back({g0, d});
         g0 = d;
@@ -2411,10 +2430,10 @@ namespace {
 size_t oz_pad(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // one product on the integer matrix cores (split A', split B', slice product), synchronous
-hsc_status kern_zgemm_oz(hsc_ctx* ctx, int opA, int opB, int M, int N, int K, int negate, const void* A, int lda,
-                         const void* B, int ldb, int beta, const void* C, int ldc, void* D, int ldd) {
+hsc_status kern_zgemm_oz(hsc_ctx* ctx, int slices, int opA, int opB, int M, int N, int K, int negate, const void* A,
+                         int lda, const void* B, int ldb, int beta, const void* C, int ldc, void* D, int ldd) {
   const int Mp = (int)oz_pad(M, 32), Np = (int)oz_pad(N, 32), Kp = (int)oz_pad(K, 64);
-  const size_t sa = (size_t)3 * kOzSlices * Mp * Kp, sb = (size_t)3 * kOzSlices * Np * Kp;
+  const size_t sa = (size_t)3 * slices * Mp * Kp, sb = (size_t)3 * slices * Np * Kp;
   const int ba = (Mp + 63) / 64, bb = (Np + 63) / 64;
   const int ta = ba * (Kp / 32), tb = bb * (Kp / 32);
   const int tiles = (Mp / 32) * (Np / 32);
@@ -2451,8 +2470,8 @@ hsc_status kern_zgemm_oz(hsc_ctx* ctx, int opA, int opB, int M, int N, int K, in
   hipError_t e = hipMemcpy(dev, host.data(), host.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) {
     const int32_t* dm = (const int32_t*)(dev + o_map);
-    launch_oz_split(ctx->stream, (const OzSplitJob*)dev, dm, ba + bb, dm + ba + bb, ta + tb);
-    launch_oz_gemm(ctx->stream, (const GemmProbOZ*)(dev + 512), dm + ba + bb + ta + tb, tiles, negate, beta);
+    launch_oz_split(ctx->stream, slices, (const OzSplitJob*)dev, dm, ba + bb, dm + ba + bb, ta + tb);
+    launch_oz_gemm(ctx->stream, slices, (const GemmProbOZ*)(dev + 512), dm + ba + bb + ta + tb, tiles, negate, beta);
     e = hipGetLastError();
     if (e == hipSuccess) e = ctx->stream ? hipStreamSynchronize(ctx->stream) : hipDeviceSynchronize();
   }
@@ -2521,9 +2540,11 @@ hsc_status hsc_kern_zgemm_tile(hsc_ctx* ctx, int32_t tile_kind, int32_t opA, int
 hsc_status hsc_kern_zgemm_dd(hsc_ctx* ctx, int32_t config, int32_t opA, int32_t opB, int32_t M, int32_t N,
                              int32_t K, int32_t negate, const void* A, int32_t lda, const void* B, int32_t ldb,
                              int32_t beta, const void* C, int32_t ldc, void* D, int32_t ldd) {
+  // configs past the vector-unit tiles: the slice product with 16 slices (3) or 15 (4)
+  const int oz_slices = config == dd_gemm_configs() ? 16 : config == dd_gemm_configs() + 1 ? 15 : 0;
   if (!ctx || M < 0 || N < 0 || K < 0 || opA < 0 || opA > 1 || opB < 0 || opB > 1 || (beta != 0 && beta != 1) ||
-      (negate != 0 && negate != 1) || config < 0 || config > dd_gemm_configs() ||
-      (config == dd_gemm_configs() && K > kOzMaxDepth)) {
+      (negate != 0 && negate != 1) || config < 0 || config > dd_gemm_configs() + 1 ||
+      (oz_slices && K > oz_max_depth(oz_slices))) {
     set_error("bad arguments to hsc_kern_zgemm_dd");
     return HSC_E_ARG;
   }
@@ -2535,7 +2556,8 @@ hsc_status hsc_kern_zgemm_dd(hsc_ctx* ctx, int32_t config, int32_t opA, int32_t 
   }
   if (M == 0 || N == 0) return HSC_OK;
   HIPCHK(hipSetDevice(ctx->device));
-  if (config == dd_gemm_configs()) return kern_zgemm_oz(ctx, opA, opB, M, N, K, negate, A, lda, B, ldb, beta, C, ldc, D, ldd);
+  if (oz_slices)
+    return kern_zgemm_oz(ctx, oz_slices, opA, opB, M, N, K, negate, A, lda, B, ldb, beta, C, ldc, D, ldd);
   GemmProbDD p{};
   p.A = (const zdd*)A; p.B = (const zdd*)B; p.C = (const zdd*)C; p.D = (zdd*)D; p.D64 = nullptr;
   p.M = M; p.N = N; p.K = K; p.lda = lda; p.ldb = ldb; p.ldc = ldc; p.ldd = ldd; p.ldd64 = 0;
@@ -2567,7 +2589,7 @@ hsc_status hsc_kern_zgemm_dd_noalloc(hsc_ctx* ctx, int32_t opA, int32_t opB, int
                                      int32_t negate, const void* A, int32_t lda, const void* B, int32_t ldb,
                                      int32_t beta, const void* C, int32_t ldc, void* D, int32_t ldd) {
   if (!ctx || M < 0 || N < 0 || K < 0 || opA < 0 || opA > 1 || opB < 0 || opB > 1 || (beta != 0 && beta != 1) ||
-      (negate != 0 && negate != 1) || K > kOzMaxDepth) {
+      (negate != 0 && negate != 1) || K > oz_max_depth(kOzSlices)) {
     set_error("bad arguments to hsc_kern_zgemm_dd_noalloc");
     return HSC_E_ARG;
   }

@@ -50,7 +50,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("eta", C.c_double), ("kT", C.c_double), ("mu_L", C.c_double), ("mu_R", C.c_double),
                 ("want", C.c_uint32), ("batch", C.c_int32), ("guard_tau", C.c_double),
                 ("guard_rounds", C.c_int32), ("precision", C.c_int32), ("graph", C.c_int32),
-                ("tune", C.c_int32), ("complex3m", C.c_int32)]
+                ("tune", C.c_int32), ("complex3m", C.c_int32), ("slices", C.c_int32)]
 
 
 _lib = None
@@ -158,7 +158,7 @@ class Context:
     PROFILE_KINDS = ("assemble", "inv_panel", "inv_swap", "inv_unscramble", "gemm", "gather",
                      "assemble_n", "diag", "guard", "dd_assemble", "dd_inv_panel", "dd_inv_swap",
                      "dd_inv_unscramble", "dd_gemm", "inv_super", "oz_split", "oz_gemm", "dd_inv_super",
-                     "face_half", "face_sigma")
+                     "face_half", "face_sigma", "bonds")
 
     def profile_bytes(self) -> dict:
         """Algorithmic bytes per launch kind since profiling was enabled (slice products only)."""
@@ -330,8 +330,9 @@ class Tree:
 
 def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1,
           want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, out=None, sync=True, guard=False,
-          guard_tau=0.0, guard_rounds=6, precision=3, graph=0, tune=0, complex3m=0):
-    """Solve all energies; returns a dict of device tensors (gr, gl, trans, spectral, status)."""
+          guard_tau=0.0, guard_rounds=6, precision=3, graph=0, tune=0, complex3m=0, slices=0):
+    """Solve all energies; returns a dict of device tensors (gr, gl, trans, spectral, status).
+    slices: 8-bit slices per operand of the precision-3 products (0 = the library's 16, or 15)."""
     import torch
     dev = ctx.torch_device
     e = torch.as_tensor(energies, dtype=torch.float64, device=dev).contiguous()
@@ -349,7 +350,8 @@ def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R
         o["status"] = torch.empty(ne, dtype=torch.int32, device=dev)
     if guard and "guard" not in o:
         o["guard"] = torch.zeros((ne, tree.stats()["n_clusters"], 2), dtype=torch.float64, device=dev)
-    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, guard_tau, guard_rounds, precision, graph, tune, complex3m)
+    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, guard_tau, guard_rounds, precision, graph, tune, complex3m,
+                     slices)
     if want & (HSC_BOND_GR | HSC_BOND_GL):
         nb = len(tree.bonds())
         for bit, key in ((HSC_BOND_GR, "bond_gr"), (HSC_BOND_GL, "bond_gl")):
@@ -369,7 +371,7 @@ def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R
 
 def solve_batch(ctx: Context, trees, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1,
                 want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, outs=None, sync=True, precision=3, graph=0,
-                tune=0, complex3m=0):
+                tune=0, complex3m=0, slices=0):
     """Several devices in one call (hsc_solve_batch); energies: one array for all devices or a
     list of per-device arrays.  Returns a list of output dicts (device tensors)."""
     import torch
@@ -405,7 +407,7 @@ def solve_batch(ctx: Context, trees, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_
     th = (C.c_void_p * nt)(*[t.h.value for t in trees])
     ne_arr = np.array([int(e.numel()) for e in es], np.int32)
     e_arr = (C.c_void_p * nt)(*[e.data_ptr() for e in es])
-    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, 0.0, 0, precision, graph, tune, complex3m)
+    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, 0.0, 0, precision, graph, tune, complex3m, slices)
     check(lib().hsc_solve_batch(ctx.h, nt, th, _ptr(ne_arr), e_arr, C.byref(opts), arr("gr"), arr("gl"), arr("trans"),
                                 arr("spectral"), arr("status"), None))
     if sync:
@@ -445,7 +447,8 @@ def kern_zgemm(ctx, opA, opB, alpha, A, B, beta=0, C_=None, D=None, tile=0):
 def kern_zgemm_dd(ctx, opA, opB, A, B, negate=0, beta=0, C_=None, D=None, config=0):
     """D = (-1)^negate op(A) op(B) + beta C in complex double-double.  A, B, C, D: device float64
     tensors of shape (rows, cols, 4) holding (re hi, re lo, im hi, im lo) per element.  config 0-2:
-    tiles of the FP64 vector-unit kernel; 3: 8-bit slices on the integer matrix cores."""
+    tiles of the FP64 vector-unit kernel; 3: 16 8-bit slices per operand on the integer matrix cores;
+    4: 15 slices."""
     import torch
     M = A.shape[0] if opA == 0 else A.shape[1]
     K = A.shape[1] if opA == 0 else A.shape[0]

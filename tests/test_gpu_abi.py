@@ -69,7 +69,7 @@ def test_kernel_entry_points_reject_bad_arguments(ctx):
     assert _code(lambda: H.kern_zgemm(ctx, 0, 0, 1.0, A, A, tile=9)) == -1
     assert _code(lambda: H.kern_zgemm(ctx, 3, 0, 1.0, A, A)) == -1
     X = torch.zeros((4, 4, 4), dtype=torch.float64, device="cuda")
-    assert _code(lambda: H.kern_zgemm_dd(ctx, 0, 0, X, X, config=4)) == -1
+    assert _code(lambda: H.kern_zgemm_dd(ctx, 0, 0, X, X, config=5)) == -1
     assert _code(lambda: H.kern_zinv_dd(ctx, X, matrix_cores=2)) == -1
     rc = H.lib().hsc_totals(ctx.h, 2, 10, None, None, None, None)
     assert rc == -1

@@ -150,8 +150,8 @@ def test_tuned_plan_equals_default(ctx):
             assert np.allclose(x, a[k], rtol=1e-12, atol=1e-12 * np.abs(a[k]).max()), k
 
 
-@pytest.mark.parametrize("precision", [2, 3])
-def test_config2_devices_against_stored_oracle(ctx, precision):
+@pytest.mark.parametrize("precision,slices", [(2, 0), (3, 0), (3, 15)])
+def test_config2_devices_against_stored_oracle(ctx, precision, slices):
     # four of the 64 uneven cuboids (the smallest, 16 x 20 x 16, to the largest, 48 x 43 x 47 =
     # 97,008 sites) in one hsc_solve_batch call on 3D trees with leaves <= 8, at two energies of the
     # 128-point grid in the lead band and two outside it, against refined sparse-LU rows of G^r
@@ -164,9 +164,9 @@ def test_config2_devices_against_stored_oracle(ctx, precision):
     ids = [d["device"] for d in gold["devices"]]
     devs = [synth.config2_devices(which=[i])[0] for i in ids]      # in the stored order
     trees = [pkg.Tree.from_device(d, leaf_side=8) for d in devs]
-    print(f"[config2 precision {precision}]", flush=True)
+    print(f"[config2 precision {precision} slices {slices}]", flush=True)
     outs = pkg.solve_batch(ctx, trees, torch.tensor(E, device=ctx.torch_device), precision=precision,
-                           want=pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS, **KW)
+                           want=pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS, slices=slices, **KW)
     worst = 0.0
     for d, o in zip(gold["devices"], outs):
         sites = np.array(d["sites"])

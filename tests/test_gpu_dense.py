@@ -142,8 +142,8 @@ def test_dense_guard_rejected(ctx):
         gpu(ctx, dev, E_MIX[:2], 2, 1, guard_tau=100.0)
 
 
-@pytest.mark.parametrize("precision", [2, 3])
-def test_dense_cube32_golden_benchmark_configuration(ctx, precision):
+@pytest.mark.parametrize("precision,slices", [(2, 0), (3, 0), (3, 15)])
+def test_dense_cube32_golden_benchmark_configuration(ctx, precision, slices):
     # the 32^3 benchmark cube with whole-face contacts, in the benchmark's launch configuration
     # (3D nested dissection, leaves <= 8, batches of 16, tuned tiles), against the slab recursion
     # with the dense face blocks at four energies of the 256-point grid (all sites' diagonals were
@@ -155,9 +155,9 @@ def test_dense_cube32_golden_benchmark_configuration(ctx, precision):
     ref = {"gr": np.array(gold["gr_re"]) + 1j * np.array(gold["gr_im"]),
            "gl": np.array(gold["gl_re"]) + 1j * np.array(gold["gl_im"]),
            "a_l": np.array(gold["a_l"]), "a_r": np.array(gold["a_r"]), "trans": np.array(gold["trans"])}
-    print(f"[dense cube32 golden precision {precision}]", flush=True)
+    print(f"[dense cube32 golden precision {precision} slices {slices}]", flush=True)
     Ep = np.tile(E, 4)                 # one batch of 16
-    g = gpu(ctx, synth.config1_device(), Ep, 8, precision, tune=1, batch=16)
+    g = gpu(ctx, synth.config1_device(), Ep, 8, precision, tune=1, batch=16, slices=slices)
     gs = {k: g[k][:4, sites] for k in ("gr", "gl", "a_l", "a_r")}
     gs["trans"], gs["status"] = g["trans"][:4], g["status"][:4]
     print("dense 32^3 golden worst", check(gs, ref, E, TOL[precision]))

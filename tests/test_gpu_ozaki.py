@@ -21,13 +21,17 @@ pytestmark = pytest.mark.gpu
 KW = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1)
 ALL = H.HSC_DIAG_GR | H.HSC_DIAG_GL | H.HSC_TRANS | H.HSC_SPECTRAL_LR
 HERE = os.path.dirname(os.path.abspath(__file__))
-OZ = 3          # hsc_kern_zgemm_dd config of the integer matrix cores
-# error of a config-3 product per unit of K, relative to the row maximum of |Re| + |Im| of op(A)
-# times the column maximum of op(B): each real part product misses at most about (S + 1) 2^-7S of
-# the power-of-two scales (dropped pairs and slice remainders), Im sums three of them, and each
-# scale is below twice its maximum
-SLICES = 15
-OZ_REL = 3 * (SLICES + 1) * 2.0 ** (-7 * SLICES) * 4
+OZ = 3          # hsc_kern_zgemm_dd config of the integer matrix cores (16 slices)
+OZ15 = 4        # the same with 15 slices
+SLICES = {OZ: 16, OZ15: 15}
+
+
+def oz_rel(slices):
+    """Error of a slice product per unit of K, relative to the row maximum of |Re| + |Im| of op(A)
+    times the column maximum of op(B): each real part product misses at most about (S + 1) 2^-7S of
+    the power-of-two scales (dropped pairs and slice remainders), Im sums three of them, and each
+    scale is below twice its maximum."""
+    return 3 * (slices + 1) * 2.0 ** (-7 * slices) * 4
 
 
 def _dd_rand(rng, rows, cols, row_scale=None):
@@ -67,9 +71,10 @@ def _row_max(X, op, i, K):
     return float(np.max(np.abs(v[..., 0]) + np.abs(v[..., 2])))
 
 
+@pytest.mark.parametrize("config", [OZ, OZ15], ids=["s16", "s15"])
 @pytest.mark.parametrize("shape", [(70, 37, 45), (33, 65, 200)], ids=["k45", "k200"])
 @pytest.mark.parametrize("opA,opB,negate,beta", [(0, 0, 0, 0), (1, 0, 1, 1), (0, 1, 0, 1), (1, 1, 0, 0)])
-def test_zgemm_oz_against_exact_arithmetic(ctx, shape, opA, opB, negate, beta):
+def test_zgemm_oz_against_exact_arithmetic(ctx, shape, opA, opB, negate, beta, config):
     # ragged sizes spanning several 32 x 32 tiles and 64-deep steps; the error bound of the slice
     # product is relative to the largest entries of the row of op(A) and the column of op(B)
     M, N, K = shape
@@ -79,7 +84,7 @@ def test_zgemm_oz_against_exact_arithmetic(ctx, shape, opA, opB, negate, beta):
     Cm = _dd_rand(rng, M, N)
     dev = ctx.torch_device
     D = H.kern_zgemm_dd(ctx, opA, opB, torch.tensor(A, device=dev), torch.tensor(B, device=dev), negate=negate,
-                        beta=beta, C_=torch.tensor(Cm, device=dev) if beta else None, config=OZ).cpu().numpy()
+                        beta=beta, C_=torch.tensor(Cm, device=dev) if beta else None, config=config).cpu().numpy()
     assert (np.abs(D[..., 1]) <= 0.5 * np.spacing(np.abs(D[..., 0]))).all()
     assert (np.abs(D[..., 3]) <= 0.5 * np.spacing(np.abs(D[..., 2]))).all()
     pairs = {(i, j) for i in (0, 15, 16, 31, 32, M - 1) for j in (0, 31, 32, N - 1)}
@@ -88,7 +93,7 @@ def test_zgemm_oz_against_exact_arithmetic(ctx, shape, opA, opB, negate, beta):
     for i, j in sorted(pairs):
         re, im = _exact_entry(A, B, Cm, i, j, K, opA, opB, negate, beta)
         got = _ex(D[i, j])
-        bound = K * OZ_REL * _row_max(A, opA, i, K) * _row_max(B, 1 - opB, j, K)
+        bound = K * oz_rel(SLICES[config]) * _row_max(A, opA, i, K) * _row_max(B, 1 - opB, j, K)
         if beta:
             bound += 2.0 ** -102 * (abs(float(_ex(Cm[i, j])[0])) + abs(float(_ex(Cm[i, j])[1])))
         err = max(abs(float(got[0] - re)), abs(float(got[1] - im)))
@@ -97,9 +102,11 @@ def test_zgemm_oz_against_exact_arithmetic(ctx, shape, opA, opB, negate, beta):
     assert worst < 1.0
 
 
-def test_zgemm_oz_wide_dynamic_range(ctx):
+@pytest.mark.parametrize("config", [OZ, OZ15], ids=["s16", "s15"])
+def test_zgemm_oz_wide_dynamic_range(ctx, config):
     # rows of A and columns of B scaled over 16 decades, plus single entries far below their
-    # row's largest: the fixed-point slices keep each entry to 2^-105 of its row's maximum
+    # row's largest: the fixed-point slices keep each entry to 2^-112 (15 slices: 2^-105) of its
+    # row's maximum
     M, N, K = 40, 36, 96
     rng = np.random.default_rng(7)
     A = _dd_rand(rng, M, K, row_scale=10.0 ** rng.uniform(-8, 8, M))
@@ -107,14 +114,14 @@ def test_zgemm_oz_wide_dynamic_range(ctx):
     A[3, 5] *= 1e-12
     Bt[7, 11] *= 1e-9
     dev = ctx.torch_device
-    D = H.kern_zgemm_dd(ctx, 0, 1, torch.tensor(A, device=dev), torch.tensor(Bt, device=dev), config=OZ)
+    D = H.kern_zgemm_dd(ctx, 0, 1, torch.tensor(A, device=dev), torch.tensor(Bt, device=dev), config=config)
     D = D.cpu().numpy()
     worst = 0.0
     for i, j in [(3, 7), (0, 0), (M - 1, N - 1)] + [(int(a), int(b)) for a, b in
                                                     zip(rng.integers(0, M, 25), rng.integers(0, N, 25))]:
         re, im = _exact_entry(A, Bt, None, i, j, K, 0, 1, 0, 0)
         got = _ex(D[i, j])
-        bound = K * OZ_REL * _row_max(A, 0, i, K) * _row_max(Bt, 0, j, K)
+        bound = K * oz_rel(SLICES[config]) * _row_max(A, 0, i, K) * _row_max(Bt, 0, j, K)
         worst = max(worst, max(abs(float(got[0] - re)), abs(float(got[1] - im))) / bound)
     print("wide range: worst error / bound", worst)
     assert worst < 1.0
@@ -140,20 +147,22 @@ def test_zgemm_oz_empty_depth_and_in_place(ctx):
     assert np.abs((got[..., 0] - ref[..., 0]) + (got[..., 1] - ref[..., 1])).max() <= 1e-28 * 70 * scale
 
 
-def test_zgemm_oz_rejects_deep_products(ctx):
-    # the int32 sum of one weight takes up to 3 x 15 pairs x 64^2 x K: K <= 11648 (a multiple of 64)
+@pytest.mark.parametrize("config,kmax", [(OZ, 10880), (OZ15, 11648)], ids=["s16", "s15"])
+def test_zgemm_oz_rejects_deep_products(ctx, config, kmax):
+    # the int32 sum of one weight takes up to 3 x S pairs x 64^2 x K: K <= 10880 with 16 slices,
+    # 11648 with 15 (multiples of 64)
     dev = ctx.torch_device
-    for K, ok in ((11648, True), (11649, False)):
+    for K, ok in ((kmax, True), (kmax + 1, False)):
         A = torch.ones((1, K, 4), dtype=torch.float64, device=dev)
         B = torch.ones((K, 1, 4), dtype=torch.float64, device=dev)
         A[..., 1::2] = 0.0
         B[..., 1::2] = 0.0
         if ok:
-            D = H.kern_zgemm_dd(ctx, 0, 0, A, B, config=OZ).cpu().numpy()
+            D = H.kern_zgemm_dd(ctx, 0, 0, A, B, config=config).cpu().numpy()
             assert D[0, 0, 0] == 0.0 and D[0, 0, 2] == 2.0 * K, D    # (1 + i)^2 = 2i per term
         else:
             with pytest.raises(H.HscError) as e:
-                H.kern_zgemm_dd(ctx, 0, 0, A, B, config=OZ)
+                H.kern_zgemm_dd(ctx, 0, 0, A, B, config=config)
             assert e.value.code == -1
 
 
@@ -236,6 +245,32 @@ def test_config0_all_energies_unguarded(ctx, leaf):
     g2 = _solve(ctx, dev, E, leaf, precision=2)
     for k in ("gr", "gl", "a_l", "a_r"):
         assert max(rel(g[k][e], g2[k][e]) for e in range(len(E))) <= 1e-11, k
+
+
+def test_slices_option(ctx):
+    # precision 3 with 15 slices per operand on the 16^3 cube (3D tree, leaves <= 8, where the deep
+    # products run on the integer matrix cores): the same oracle bar in and out of the lead band,
+    # results not bit-identical to the 16-slice default (the other kernels ran), a precision-2
+    # solve ignores the option, and out-of-range slice counts are rejected
+    dev = synth.config1_device(n_side=16)
+    E = np.array([-4.7, -2.9, -1.1, 0.35, 1.6, 3.8])
+    ref = oracle.dense.solve(dev, E, **KW)
+    ctx.profile(True)
+    g16 = _solve(ctx, dev, E, 8, precision=3)
+    ctx.sync()
+    assert ctx.profile_read()["oz_gemm"]["launches"] > 0
+    ctx.profile(False)
+    g15 = _solve(ctx, dev, E, 8, precision=3, slices=15)
+    print("16^3 precision 3: 16 slices worst", _check(g16, ref, E), "15 slices worst", _check(g15, ref, E))
+    assert not np.array_equal(g15["gr"], g16["gr"])
+    assert np.array_equal(_solve(ctx, dev, E, 8, precision=3, slices=16)["gr"], g16["gr"])
+    p2 = _solve(ctx, dev, E[:2], 8, precision=2)
+    assert np.array_equal(_solve(ctx, dev, E[:2], 8, precision=2, slices=15)["gr"], p2["gr"])
+    dev = synth.config0_device()
+    for bad in (14, 17, -1):
+        with pytest.raises(H.HscError) as e:
+            _solve(ctx, dev, E[:2], 4, precision=3, slices=bad)
+        assert e.value.code == -1
 
 
 @pytest.mark.parametrize("transverse,leaf", [(True, 4), (False, 8)])

@@ -37,7 +37,7 @@ def test_noalloc_rejects_products_beyond_the_scratch(ctx):
     A = torch.zeros((1024, 1024, 4), dtype=torch.float64, device=dev)
     D = torch.zeros((1024, 1024, 4), dtype=torch.float64, device=dev)
     with pytest.raises(H.HscError) as e:
-        H.kern_zgemm_dd_noalloc(ctx, 0, 0, A, A, D)          # 45 * 2048 * 1024 bytes of slices > 64 MiB
+        H.kern_zgemm_dd_noalloc(ctx, 0, 0, A, A, D)          # 48 * 2048 * 1024 bytes of slices > 64 MiB
     assert e.value.code == -1 and b"static device array" in H.lib().hsc_last_error()
     small = torch.zeros((1024, 640, 4), dtype=torch.float64, device=dev)
     Bm = torch.zeros((640, 1024, 4), dtype=torch.float64, device=dev)
