@@ -19,8 +19,10 @@ Modules:
                  usable at any size.
 * ``mlp``     -- float64 forward pass, chain-rule gradients and Adam of the
                  surrogate network of the learned energy grid.
+* ``scf``     -- the self-consistent NEGF-Poisson loop: 7-point Poisson on the device
+                 grid (sparse direct solve), electron density from diag G^<, mixing.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s CPU-baseline leg
 may import this package.  The GPU path never does: it shares no code with it.
 """
-from . import negf, face, dense, rgf, sampled, mlp  # noqa: F401
+from . import negf, face, dense, rgf, sampled, mlp, scf  # noqa: F401

@@ -13,6 +13,8 @@ with Gamma_c = V_c V_c^T (V_c = diag(sqrt(Gamma_c,k)) for per-site leads).
 With dense=True each contact is a whole face with the dense self-energy block
 of face.face_sigma (the DENSE case); then, with Gamma_c = V_c V_c^T,
   A_c,ii = || G_i,c V_c ||^2,    T = || V_L^T G_LR V_R ||_F^2  (= Tr Gamma_L G Gamma_R G^dagger)
+With potential U (one value per site) the device Hamiltonian is H + diag(U): the on-site shift
+of the self-consistent loop (scf.py).
 Meant for n up to a few thousand sites.
 """
 from __future__ import annotations
@@ -43,13 +45,20 @@ def green(dev, energy: float, eta: float, h=None, dense=False):
     return np.linalg.inv(system_matrix(dev, energy + 1j * eta, h, dense))
 
 
-def solve(dev, energies, eta, kT, mu_L, mu_R, dense=False):
+def _h_of(dev, potential):
+    h = dev.dense_h()
+    if potential is not None:
+        h[np.diag_indices(dev.n)] += np.asarray(potential, dtype=np.float64)
+    return h
+
+
+def solve(dev, energies, eta, kT, mu_L, mu_R, dense=False, potential=None):
     """Diagonals of G^r and G^<, spectral functions, transmission for each energy."""
     if dense:
-        return _solve_dense(dev, energies, eta, kT, mu_L, mu_R)
+        return _solve_dense(dev, energies, eta, kT, mu_L, mu_R, potential)
     energies = np.asarray(energies, dtype=np.float64)
     ne, n = len(energies), dev.n
-    h = dev.dense_h()
+    h = _h_of(dev, potential)
     out = {k: np.zeros((ne, n), np.complex128) for k in ("gr", "gl")}
     for k in ("a_l", "a_r", "a_eta"):
         out[k] = np.zeros((ne, n))
@@ -73,10 +82,10 @@ def solve(dev, energies, eta, kT, mu_L, mu_R, dense=False):
     return out
 
 
-def _solve_dense(dev, energies, eta, kT, mu_L, mu_R):
+def _solve_dense(dev, energies, eta, kT, mu_L, mu_R, potential=None):
     energies = np.asarray(energies, dtype=np.float64)
     ne, n = len(energies), dev.n
-    h = dev.dense_h()
+    h = _h_of(dev, potential)
     out = {k: np.zeros((ne, n), np.complex128) for k in ("gr", "gl")}
     for k in ("a_l", "a_r", "a_eta"):
         out[k] = np.zeros((ne, n))
