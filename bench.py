@@ -213,6 +213,8 @@ def main():
                          "elongated Nx x 16 x 16 devices")
     ap.add_argument("--orbital-study", action="store_true",
                     help="time per energy of 10-orbital wires (4 x 4 and 6 x 6 sites across, lengths 32 .. 128)")
+    ap.add_argument("--scf-study", action="store_true",
+                    help="time the self-consistent NEGF-Poisson loop on the --n-side cube (64 energies, 4 iterations)")
     ap.add_argument("--write-device", metavar="PATH",
                     help="write the benchmark cube (--n-side) and its energy grid (--energies) as a device file "
                          "for the native driver paper_1702_05167_amd/hsc_run, then exit")
@@ -254,6 +256,9 @@ def main():
         return
     if args.orbital_study:
         orbital_study(pkg, synth, np, torch, args)
+        return
+    if args.scf_study:
+        scf_study(pkg, synth, np, torch, args)
         return
 
     if args.calibrate_copy > 0:
@@ -557,6 +562,45 @@ def dense_study(pkg, synth, np, torch, args):
                       "dtype": "c128 in/out, complex double-double inside", "data": "synthetic",
                       "config": {"energies_per_batch": args.batch, "precision": args.precision, "leaf_side": args.leaf},
                       "rows": rows}), flush=True)
+
+
+def scf_study(pkg, synth, np, torch, args):
+    """Self-consistent NEGF-Poisson loop on the benchmark cube: 64 energies in [-6, 0.5] (trapezoid
+    weights), lead planes at +-0.05, coupling 0.05, mixing 0.5, 4 iterations at --precision; reports
+    seconds per iteration and the share of the Poisson solve (timed on its own)."""
+    N = args.n_side
+    dev = synth.config1_device(n_side=N)
+    ctx = pkg.Context(0)
+    tree = pkg.Tree.from_device(dev, leaf_side=args.leaf)
+    E = np.linspace(-6.0, 0.5, 64)
+    w = np.full(64, E[1] - E[0])
+    w[0] = w[-1] = 0.5 * w[0]
+    kw = dict(eta=1e-8, kT=0.025, mu_L=0.05, mu_R=-0.05, precision=args.precision, slices=args.slices,
+              complex3m=args.complex3m, tune=args.tune, batch=args.batch)
+    pkg.scf(ctx, tree, (N, N, N), E, w, u_left=0.05, u_right=-0.05, coupling=0.05, mixing=0.5, max_iter=1, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, dens, res = pkg.scf(ctx, tree, (N, N, N), E, w, u_left=0.05, u_right=-0.05, coupling=0.05, mixing=0.5,
+                           max_iter=4, **kw)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / len(res)
+    rho = torch.randn(dev.n, dtype=torch.float64, device="cuda:0")
+    pkg.poisson_solve(ctx, (N, N, N), rho, 0.05, -0.05)
+    t1 = time.perf_counter()
+    for _ in range(10):
+        pkg.poisson_solve(ctx, (N, N, N), rho, 0.05, -0.05)
+    tp = (time.perf_counter() - t1) / 10
+    note(f"self-consistent loop on the {N}^3 cube: {dt:.3f} s per iteration (64 energies), Poisson solve "
+         f"{tp * 1e3:.3f} ms ({tp / dt:.2e} of an iteration), residuals {np.array2string(res, precision=3)}")
+    print(json.dumps({"metric": "seconds per self-consistent iteration", "value": dt, "unit": "s",
+                      "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+                      "dtype": "c128 in/out, complex double-double inside",
+                      "config": {"workload": f"cube{N}^3, 64 energies in [-6, 0.5], 4 iterations",
+                                 "precision": args.precision, "leaf_side": args.leaf},
+                      "poisson_ms": tp * 1e3, "residuals": res.tolist(),
+                      "u_range": [float(u.min()), float(u.max())], "density_mean": float(dens.mean())}),
+          flush=True)
+    ctx.close()
 
 
 def orbital_study(pkg, synth, np, torch, args):

@@ -186,6 +186,12 @@ typedef struct {
    * their row's largest (large devices out of the lead band) then lose up to
    * two more digits.  Ignored with precision 0-2.  Other values: HSC_E_ARG. */
   int32_t slices;
+  /* On-site potential energy U (device, double[n], site order of the tree's H),
+   * or NULL: the device Hamiltonian becomes H + diag(U) (the electrostatic
+   * potential of a self-consistent NEGF-Poisson loop; the leads keep their own
+   * on-site energies).  Read when the call enqueues its first launch; single-
+   * device solves only (hsc_solve_batch returns HSC_E_ARG for a non-NULL U). */
+  const double* potential;
 } hsc_solve_opts;
 
 /* Library version string. */
@@ -336,6 +342,61 @@ hsc_status hsc_sync(hsc_ctx* ctx);
  * Errors: HSC_E_ARG for n_e < 0, n < 0 or a NULL totals with n_e > 0. */
 hsc_status hsc_totals(hsc_ctx* ctx, int32_t n_e, int64_t n, const void* diag_gr, const void* diag_gl,
                       const double* spectral_lr, double* totals);
+
+/* ---- self-consistent NEGF-Poisson loop ----
+ * The paper presents the method as the costly half of self-consistent NEGF-Poisson
+ * simulations (abstract, Section 1) without fixing the electrostatics; these
+ * calls supply a plain one on the device grid.
+ *
+ * Grid: site (x, y, z) of an nx x ny x nz cuboid has index x + nx (y + ny z) (the
+ * layout of the benchmark cuboids); x is the transport axis.  Poisson operator,
+ * unit spacing, 7 points: sum over the three axes of (2 U_i - U_prev - U_next);
+ * the outside neighbour along x is a lead plane (x = -1 at u_left, x = nx at
+ * u_right: Dirichlet), along y and z the site itself (zero normal derivative). */
+typedef struct {
+  int32_t nx, ny, nz;        /* each in [1, 1024] */
+  double u_left, u_right;    /* potential energy of the lead planes */
+} hsc_grid;
+
+/* u = the solution of (Poisson operator) u = rho + lead-plane terms, by the
+ * closed-form eigenbases of the three 1D operators (exact up to FP64 rounding).
+ * rho, u: device double[nx ny nz] (may not overlap).  Synchronous.
+ * Errors: HSC_E_ARG (sides out of range, non-finite lead values, NULL arrays),
+ * HSC_E_OOM, HSC_E_HIP. */
+hsc_status hsc_poisson_solve(hsc_ctx* ctx, const hsc_grid* grid, const double* rho, double* u);
+
+/* Electron density per site (no spin factor, hbar = 1) from the diagonal of
+ * G^< (Eq. 2): density[i] = sum_e weights[e] Im G^<_ii(E_e) / (2 pi), the
+ * energies summed in order.  weights: device double[n_e] (the caller's
+ * quadrature weights); diag_gl: device complex128 [n_e][n] as hsc_solve writes
+ * it; density: device double[n].  Asynchronous on the context's stream.
+ * Errors: HSC_E_ARG. */
+hsc_status hsc_density(hsc_ctx* ctx, int32_t n_e, int64_t n, const double* weights, const void* diag_gl,
+                       double* density);
+
+typedef struct {
+  double coupling;           /* c of the source rho = c (n - n0) (e^2 / epsilon in model units), >= 0 */
+  const double* n0;          /* device double[n] background density, or NULL (zero) */
+  double mixing;             /* beta in (0, 1]: U <- U + beta (U_new - U) */
+  int32_t max_iter;          /* >= 1 */
+  double tol;                /* stop after the iteration whose residual max|U_new - U| < tol; 0: max_iter */
+} hsc_scf_opts;
+
+/* The loop: for each iteration, solve every energy with potential u (hsc_solve
+ * with opts, diag G^< only), density as hsc_density, source c (n - n0),
+ * U_new = hsc_poisson_solve(source), residual max_i |U_new - u|, then
+ * u <- u + beta (U_new - u).  u: device double[n], the starting potential on
+ * entry and the last mixed one on return; density: device double[n], the density
+ * of the last solve (at the potential before the last mixing); energies,
+ * weights: device double[n_e]; *iterations (host) = iterations run; residuals
+ * (host double[max_iter], may be NULL) = residual of each.  The tree must have
+ * one site per grid point (n = nx ny nz).  opts->want and opts->potential are
+ * ignored.  Synchronous.  Errors: HSC_E_ARG; a solve's per-energy status
+ * (HSC_E_SINGULAR, HSC_E_NONFINITE, HSC_E_UNSTABLE) stops the loop and is
+ * returned; HSC_E_OOM, HSC_E_HIP. */
+hsc_status hsc_scf(hsc_ctx* ctx, const hsc_tree* tree, const hsc_grid* grid, int32_t n_e, const double* energies,
+                   const double* weights, const hsc_solve_opts* opts, const hsc_scf_opts* scf, double* u,
+                   double* density, int32_t* iterations, double* residuals);
 
 /* Launch timing.  While enabled, every kernel launch of a solve is bracketed by
  * HIP events on the context's stream; hsc_sync() folds the elapsed times into

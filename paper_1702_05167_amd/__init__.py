@@ -5,6 +5,6 @@ C ABI in include/hsc.h; ``hsc`` is its ctypes binding.
 """
 from .hsc import (  # noqa: F401
     HSC_DIAG_GR, HSC_DIAG_GL, HSC_TRANS, HSC_SPECTRAL_LR, HSC_BOND_GR, HSC_BOND_GL, Context, Tree, solve, solve_batch, totals, HscError, lib,
-    LIB_PATH,
+    LIB_PATH, poisson_solve, density, scf,
 )
 from .mlp import MLP  # noqa: F401

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhsc.so")
-SOURCES = ["tree.cpp", "gemm.hip", "inverse.hip", "kernels.hip", "ddfold.hip", "ozaki.hip", "solve.hip", "mlp.hip"]
+SOURCES = ["tree.cpp", "gemm.hip", "inverse.hip", "kernels.hip", "ddfold.hip", "ozaki.hip", "solve.hip", "mlp.hip",
+           "poisson.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

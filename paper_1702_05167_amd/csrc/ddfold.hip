@@ -17,7 +17,7 @@ namespace {
 constexpr int RB = 256;
 
 // ---------------------------------------------------------------------------------------------
-// assembly: F[a][b] = sum_children U_k[invrel_k[a]][invrel_k[b]] + (-H)[a][b] + delta_ab (z - Sigma_a)
+// assembly: F[a][b] = sum_children U_k[invrel_k[a]][invrel_k[b]] + (-H)[a][b] + delta_ab (z - Sigma_a - U_a)
 __global__ __launch_bounds__(RB) void k_dd_assemble(const RowJob* __restrict__ jobs,
                                                     const int32_t* __restrict__ row_job,
                                                     const EnergyScalars* __restrict__ es) {
@@ -46,6 +46,7 @@ __global__ __launch_bounds__(RB) void k_dd_assemble(const RowJob* __restrict__ j
     } else {
       diag_add = zdd_from(s.z);
     }
+    if (fs->pot) diag_add.re = dd_add(diag_add.re, dd{-fs->pot[a], 0.0});
   }
   zdd* out = reinterpret_cast<zdd*>(jb.dst) + (int64_t)a * jb.ldd;
   // whole-face contact cluster: minus its dense self-energy block (rows and columns < nface)

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <string>
 
 #include "../../include/hsc.h"
 
@@ -85,11 +86,14 @@ struct ChildRef {
   int32_t pad;
 };
 
-// Sparse entries of A = -H restricted to a frontal matrix, CSR over its rows.
+// Sparse entries of A = -H restricted to a frontal matrix, CSR over its rows; pot: the on-site
+// potential of the cluster's own rows (plan workspace, cluster order), subtracted on the diagonal
+// (A = z I - (H + diag U) - Sigma), or null.
 struct FrontSparse {
   const int32_t* ptr;
   const int32_t* col;
   const double2* val;
+  const double* pot;
 };
 
 struct LeadParams {
@@ -304,5 +308,32 @@ int launch_oz_gemm_noalloc(hipStream_t st, char* ws, int opA, int opB, int M, in
 // debug / unit-test helpers
 void launch_mfma_rate(hipStream_t st, double* out, int blocks, int iters);
 void launch_mfma_probe(hipStream_t st, double* out);
+
+// ---- self-consistent NEGF-Poisson loop (poisson.hip) ----
+// pot[p] = U[perm[p]] (U in site order, pot in cluster order), zeros without U
+void launch_potential(hipStream_t st, int64_t n, const int64_t* perm, const double* U, double* pot);
+// dens[i] = sum_e w[e] Im G^<_ii(E_e) / (2 pi); gl: complex128 [ne][n]
+void launch_density(hipStream_t st, int ne, int64_t n, const double* w, const void* gl, double* dens);
+// *r = max_i |u_new - u| (bits of a non-negative double), then u += beta (u_new - u)
+void launch_mix(hipStream_t st, int64_t n, double* u, const double* u_new, double beta, unsigned long long* r);
+constexpr int kPoissonMaxSide = 1024;
+// 0 when the grid is usable (sides in [1, kPoissonMaxSide], finite lead-plane values), else -1
+// with the reason
+int poisson_check(const hsc_grid* g, std::string* why);
+// device workspace of the fast Poisson solve on one grid: two arrays of n doubles, the three
+// closed-form bases and their eigenvalues
+struct PoissonWork {
+  hsc_grid grid{};
+  int64_t n = 0;
+  double* buf = nullptr;
+  double *t1 = nullptr, *t2 = nullptr;
+  const double* Q[3] = {};
+  const double* lam[3] = {};
+  int create(const hsc_grid& g);   // 0 or -1 (allocation or copy failed)
+  void destroy();
+  // u = the solution for the source rho, or, when dens is given, for coupling (dens - n0)
+  // (n0 may be null); enqueued on st
+  void run(hipStream_t st, const double* rho, const double* dens, const double* n0, double coupling, double* u) const;
+};
 
 }  // namespace hsc

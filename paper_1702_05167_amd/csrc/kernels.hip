@@ -74,7 +74,7 @@ __global__ void k_energy_setup(const double* __restrict__ energies, int nvalid, 
 
 constexpr int RB = 256;
 
-// F[a][b] = sum_children U_k[invrel_k[a]][invrel_k[b]] + (-H)[a][b] + delta_ab (z - Sigma_a)
+// F[a][b] = sum_children U_k[invrel_k[a]][invrel_k[b]] + (-H)[a][b] + delta_ab (z - Sigma_a - U_a)
 //   jobs: rows = cols = n+f; p0 = ChildRef[aux0]; p1 = FrontSparse*; aux1 = n, aux2 = nL, aux3 = nR
 __global__ __launch_bounds__(RB) void k_assemble(const RowJob* __restrict__ jobs, const int32_t* __restrict__ row_job,
                                                  const EnergyScalars* __restrict__ es) {
@@ -100,6 +100,7 @@ __global__ __launch_bounds__(RB) void k_assemble(const RowJob* __restrict__ jobs
     diag_add = s.z;
     if (a < nL) { diag_add.x -= s.sig[0].x; diag_add.y -= s.sig[0].y; }
     else if (a < nL + nR) { diag_add.x -= s.sig[1].x; diag_add.y -= s.sig[1].y; }
+    if (fs->pot) diag_add.x -= fs->pot[a];
   }
   double2* out = jb.dst + (int64_t)a * jb.ldd;
   // whole-face contact cluster: minus its dense self-energy block (rows and columns < nface)

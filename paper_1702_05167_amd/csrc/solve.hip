@@ -138,6 +138,9 @@ struct Plan {
   char* oz = nullptr;            // slice scratch of the products on the integer matrix cores
   size_t oz_bytes = 0;
   const FaceTransJob* face_tj = nullptr;   // [B] transmission over the left face (whole-face contacts)
+  double* pot = nullptr;          // [n] on-site potential in cluster order (workspace)
+  const int64_t* perm = nullptr;  // [n] site at each cluster-order position (blob)
+  bool pot_dirty = true;          // pot may hold non-zero values (or was never written)
   ~Plan() {
     if (oz) (void)hipFree(oz);
     if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -199,6 +202,7 @@ struct Builder {
   std::vector<Step> steps;
   std::vector<Channel> chans;
   char* wsbase = nullptr;   // device address (known before job pointers are written)
+  size_t pot_off = 0;       // workspace offset of the on-site potential, cluster order
   int phase = PH_OTHER;     // stamped onto every step (launch timing)
   void push(Step s) {
     s.phase = phase;
@@ -460,6 +464,7 @@ struct Builder {
       fs->ptr = reinterpret_cast<const int32_t*>(o_ptr);
       fs->col = reinterpret_cast<const int32_t*>(o_col);
       fs->val = reinterpret_cast<const double2*>(o_val);
+      fs->pot = reinterpret_cast<const double*>(wsbase + pot_off) + c.first;
       blob.reloc(o_fs + offsetof(FrontSparse, ptr));
       blob.reloc(o_fs + offsetof(FrontSparse, col));
       blob.reloc(o_fs + offsetof(FrontSparse, val));
@@ -1752,6 +1757,7 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
   const size_t o_es = b.wsa(sizeof(EnergyScalars) * B);
   const size_t o_st = b.wsa(sizeof(int32_t) * B);
   const size_t o_ar = b.wsa(sizeof(double) * (size_t)B * t->n);
+  b.pot_off = b.wsa(sizeof(double) * (size_t)t->n);
   pl->ws_bytes = b.ws;
   HIPCHK(hipSetDevice(ctx->device));
   if (hipMalloc(&pl->ws, pl->ws_bytes) != hipSuccess) {
@@ -1770,9 +1776,11 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
   pl->es = reinterpret_cast<EnergyScalars*>(pl->ws + o_es);
   pl->status = reinterpret_cast<int32_t*>(pl->ws + o_st);
   pl->a_r = reinterpret_cast<double*>(pl->ws + o_ar);
+  pl->pot = reinterpret_cast<double*>(pl->ws + b.pot_off);
   b.blob.alloc(64);   // offset 0 stays unused: a zero field means "null", not "blob start"
   b.constants();
   const size_t o_left = b.blob.push(t->contact[0].sites);
+  const size_t o_perm = b.blob.push(t->perm);
   pl->nleft = (int)t->contact[0].sites.size();
   const auto L = b.levels();
   b.face_steps();
@@ -1799,6 +1807,7 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
     if (rc != HSC_OK) return rc;
   }
   pl->left = reinterpret_cast<int64_t*>(pl->blob + o_left);
+  pl->perm = reinterpret_cast<const int64_t*>(pl->blob + o_perm);
   if (o_ftj) pl->face_tj = reinterpret_cast<const FaceTransJob*>(pl->blob + o_ftj);
   for (int c = 0; c < 2; ++c) {
     pl->lp.onsite[c] = t->contact[c].lead_onsite;
@@ -1952,6 +1961,14 @@ static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
   int st = build_plan(ctx, tree, B, want, opts->precision, opts->tune != 0, opts->complex3m, slices, &pl);
   if (st != HSC_OK) return (hsc_status)st;
   const int64_t n = tree->n;
+  // the on-site potential of this call (cluster order), or zeros once after a call that had one
+  if (opts->potential) {
+    launch_potential(ctx->stream, n, pl->perm, opts->potential, pl->pot);
+    pl->pot_dirty = true;
+  } else if (pl->pot_dirty) {
+    launch_potential(ctx->stream, n, pl->perm, nullptr, pl->pot);
+    pl->pot_dirty = false;
+  }
   const bool use_graph = opts->graph != 0 && !guard && !ctx->profile && !(want & (HSC_BOND_GR | HSC_BOND_GL));
   double2* sg_gr = nullptr;
   double2* sg_gl = nullptr;
@@ -2300,6 +2317,7 @@ hsc_status hsc_solve_batch(hsc_ctx* ctx, int32_t n_trees, const hsc_tree* const*
   for (int d = 0; d < n_trees; ++d)
     if (!trees[d] || n_e[d] < 0 || (n_e[d] > 0 && !energies[d])) { set_error("bad device entry in hsc_solve_batch"); return HSC_E_ARG; }
   if (opts_slices(opts) < 0) { set_error("slices must be 0, 15 or 16"); return HSC_E_ARG; }
+  if (opts->potential) { set_error("an on-site potential applies to single-device solves"); return HSC_E_ARG; }
   if (n_trees <= 1 || opts->guard_tau > 0.0 || guard)
     return solve_each(ctx, n_trees, trees, n_e, energies, opts, diag_gr, diag_gl, trans, spectral_lr, status, guard);
   // one forest when every device has the same energies and lead model (and per-site leads)
@@ -2385,6 +2403,81 @@ hsc_status hsc_totals(hsc_ctx* ctx, int32_t n_e, int64_t n, const void* diag_gr,
   launch_totals(ctx->stream, n_e, n, (const double2*)diag_gr, (const double2*)diag_gl, spectral_lr, totals);
   HIPCHK(hipGetLastError());
   return HSC_OK;
+}
+
+hsc_status hsc_scf(hsc_ctx* ctx, const hsc_tree* tree, const hsc_grid* grid, int32_t n_e, const double* energies,
+                   const double* weights, const hsc_solve_opts* opts, const hsc_scf_opts* scf, double* u,
+                   double* density, int32_t* iterations, double* residuals) {
+  std::string why;
+  if (!ctx || !tree || !opts || !scf || n_e < 1 || !energies || !weights || !u || !density || !iterations ||
+      poisson_check(grid, &why) != 0 || scf->max_iter < 1 || !(scf->mixing > 0.0 && scf->mixing <= 1.0) ||
+      !(scf->coupling >= 0.0) || !(scf->tol >= 0.0)) {
+    set_error(why.empty() ? std::string("bad arguments to hsc_scf") : "hsc_scf: " + why);
+    return HSC_E_ARG;
+  }
+  const int64_t n = tree->n;
+  if ((int64_t)grid->nx * grid->ny * grid->nz != n) {
+    set_error("hsc_scf: the grid has " + std::to_string((int64_t)grid->nx * grid->ny * grid->nz) +
+              " points, the tree " + std::to_string(n) + " sites");
+    return HSC_E_ARG;
+  }
+  *iterations = 0;
+  HIPCHK(hipSetDevice(ctx->device));
+  PoissonWork pw;
+  if (pw.create(*grid) != 0) { set_error("hsc_scf: Poisson workspace allocation failed"); return HSC_E_OOM; }
+  char* buf = nullptr;
+  // diag G^< [n_e][n], U_new [n], per-energy status [n_e], residual bits
+  auto pad = [](size_t v) { return (v + 255) / 256 * 256; };
+  const size_t o_un = pad((size_t)n_e * n * 16), o_st = o_un + pad((size_t)n * 8), o_r = o_st + pad((size_t)n_e * 4),
+               total = o_r + 256;
+  if (hipMalloc(&buf, total) != hipSuccess) {
+    (void)hipGetLastError();
+    pw.destroy();
+    set_error("hsc_scf: buffer allocation failed (" + std::to_string(total) + " bytes)");
+    return HSC_E_OOM;
+  }
+  void* gl = buf;
+  double* u_new = reinterpret_cast<double*>(buf + o_un);
+  int32_t* status = reinterpret_cast<int32_t*>(buf + o_st);
+  unsigned long long* rbits = reinterpret_cast<unsigned long long*>(buf + o_r);
+  hsc_solve_opts o = *opts;
+  o.want = HSC_DIAG_GL;
+  o.potential = u;
+  hsc_status rc = HSC_OK;
+  std::vector<int32_t> st_h(n_e);
+  for (int it = 0; it < scf->max_iter && rc == HSC_OK; ++it) {
+    rc = hsc_solve(ctx, tree, n_e, energies, &o, nullptr, gl, nullptr, nullptr, status, nullptr);
+    if (rc != HSC_OK) break;
+    launch_density(ctx->stream, n_e, n, weights, gl, density);
+    pw.run(ctx->stream, nullptr, density, scf->n0, scf->coupling, u_new);
+    launch_mix(ctx->stream, n, u, u_new, scf->mixing, rbits);
+    unsigned long long rb = 0;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(st_h.data(), status, 4 * (size_t)n_e, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&rb, rbits, 8, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = ctx->stream ? hipStreamSynchronize(ctx->stream) : hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      set_error(std::string("HIP error in hsc_scf: ") + hipGetErrorString(e));
+      rc = HSC_E_HIP;
+      break;
+    }
+    for (int k = 0; k < n_e; ++k)
+      if (st_h[k] != 0) {
+        set_error("hsc_scf: energy " + std::to_string(k) + " of iteration " + std::to_string(it) + " has status " +
+                  std::to_string(st_h[k]));
+        rc = (hsc_status)st_h[k];
+        break;
+      }
+    if (rc != HSC_OK) break;
+    double r;
+    std::memcpy(&r, &rb, 8);
+    if (residuals) residuals[it] = r;
+    *iterations = it + 1;
+    if (r < scf->tol) break;
+  }
+  (void)hipFree(buf);
+  pw.destroy();
+  return rc;
 }
 
 hsc_status hsc_ctx_profile(hsc_ctx* ctx, int32_t enable) {

@@ -50,7 +50,18 @@ class SolveOpts(C.Structure):
     _fields_ = [("eta", C.c_double), ("kT", C.c_double), ("mu_L", C.c_double), ("mu_R", C.c_double),
                 ("want", C.c_uint32), ("batch", C.c_int32), ("guard_tau", C.c_double),
                 ("guard_rounds", C.c_int32), ("precision", C.c_int32), ("graph", C.c_int32),
-                ("tune", C.c_int32), ("complex3m", C.c_int32), ("slices", C.c_int32)]
+                ("tune", C.c_int32), ("complex3m", C.c_int32), ("slices", C.c_int32),
+                ("potential", C.c_void_p)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("u_left", C.c_double),
+                ("u_right", C.c_double)]
+
+
+class ScfOpts(C.Structure):
+    _fields_ = [("coupling", C.c_double), ("n0", C.c_void_p), ("mixing", C.c_double), ("max_iter", C.c_int32),
+                ("tol", C.c_double)]
 
 
 _lib = None
@@ -98,6 +109,10 @@ def lib():
     L.hsc_kern_mfma_probe.argtypes = [vp, vp]
     L.hsc_kern_mfma_rate.argtypes = [vp, C.POINTER(dbl)]
     L.hsc_totals.argtypes = [vp, i32, i64, vp, vp, vp, vp]
+    L.hsc_poisson_solve.argtypes = [vp, C.POINTER(Grid), vp, vp]
+    L.hsc_density.argtypes = [vp, i32, i64, vp, vp, vp]
+    L.hsc_scf.argtypes = [vp, vp, C.POINTER(Grid), i32, vp, vp, C.POINTER(SolveOpts), C.POINTER(ScfOpts), vp, vp,
+                          C.POINTER(i32), vp]
     L.hsc_mlp_create.argtypes = [vp, i32, vp, C.POINTER(vp)]
     L.hsc_mlp_destroy.argtypes = [vp]
     L.hsc_mlp_n_params.argtypes = [vp, C.POINTER(i64)]
@@ -115,7 +130,7 @@ def lib():
                  "hsc_kern_zinv_batched",
                  "hsc_kern_zinv_dd",
                  "hsc_kern_mfma_probe",
-                 "hsc_kern_mfma_rate", "hsc_totals",
+                 "hsc_kern_mfma_rate", "hsc_totals", "hsc_poisson_solve", "hsc_density", "hsc_scf",
                  "hsc_mlp_create", "hsc_mlp_destroy", "hsc_mlp_n_params", "hsc_mlp_set_params",
                  "hsc_mlp_get_params", "hsc_mlp_forward", "hsc_mlp_grads", "hsc_mlp_train"):
         getattr(L, name).restype = C.c_int
@@ -330,9 +345,10 @@ class Tree:
 
 def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1,
           want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, out=None, sync=True, guard=False,
-          guard_tau=0.0, guard_rounds=6, precision=3, graph=0, tune=0, complex3m=0, slices=0):
+          guard_tau=0.0, guard_rounds=6, precision=3, graph=0, tune=0, complex3m=0, slices=0, potential=None):
     """Solve all energies; returns a dict of device tensors (gr, gl, trans, spectral, status).
-    slices: 8-bit slices per operand of the precision-3 products (0 = the library's 16, or 15)."""
+    slices: 8-bit slices per operand of the precision-3 products (0 = the library's 16, or 15).
+    potential: device float64 [n] on-site potential energy added to H (site order), or None."""
     import torch
     dev = ctx.torch_device
     e = torch.as_tensor(energies, dtype=torch.float64, device=dev).contiguous()
@@ -350,8 +366,10 @@ def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R
         o["status"] = torch.empty(ne, dtype=torch.int32, device=dev)
     if guard and "guard" not in o:
         o["guard"] = torch.zeros((ne, tree.stats()["n_clusters"], 2), dtype=torch.float64, device=dev)
+    if potential is not None:
+        _check_vec(potential, n, "potential")
     opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, guard_tau, guard_rounds, precision, graph, tune, complex3m,
-                     slices)
+                     slices, _dptr(potential) if potential is not None else None)
     if want & (HSC_BOND_GR | HSC_BOND_GL):
         nb = len(tree.bonds())
         for bit, key in ((HSC_BOND_GR, "bond_gr"), (HSC_BOND_GL, "bond_gl")):
@@ -413,6 +431,63 @@ def solve_batch(ctx: Context, trees, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_
     if sync:
         ctx.sync()
     return outs
+
+
+def _check_vec(t, n, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.is_cuda and t.is_contiguous() and
+            t.numel() == n):
+        raise ValueError(f"{name} must be a contiguous float64 device tensor of {n} values")
+
+
+def poisson_solve(ctx: Context, grid, rho, u_left=0.0, u_right=0.0, out=None):
+    """hsc_poisson_solve: U on the (nx, ny, nz) grid for the source rho (device float64 [n]) with
+    lead planes at u_left (x = -1) and u_right (x = nx)."""
+    import torch
+    n = int(grid[0]) * int(grid[1]) * int(grid[2])
+    _check_vec(rho, n, "rho")
+    u = torch.empty(n, dtype=torch.float64, device=rho.device) if out is None else out
+    _check_vec(u, n, "out")
+    g = Grid(int(grid[0]), int(grid[1]), int(grid[2]), float(u_left), float(u_right))
+    check(lib().hsc_poisson_solve(ctx.h, C.byref(g), _dptr(rho), _dptr(u)))
+    return u
+
+
+def density(ctx: Context, weights, gl):
+    """hsc_density: sum_e w_e Im G^<_ii / (2 pi) from diag G^< (device complex128 [n_e, n])."""
+    import torch
+    ne, n = int(gl.shape[0]), int(gl.shape[1])
+    _check_vec(weights, ne, "weights")
+    d = torch.empty(n, dtype=torch.float64, device=gl.device)
+    check(lib().hsc_density(ctx.h, ne, n, _dptr(weights), _dptr(gl.contiguous()), _dptr(d)))
+    ctx.sync()
+    return d
+
+
+def scf(ctx: Context, tree: Tree, grid, energies, weights, u_left=0.0, u_right=0.0, coupling=0.0, n0=None,
+        mixing=0.5, max_iter=10, tol=0.0, u0=None, eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, batch=0,
+        precision=3, tune=0, complex3m=0, slices=0):
+    """hsc_scf: the self-consistent NEGF-Poisson loop; returns (u, density, residuals) with u and
+    density device float64 [n] and residuals a numpy array (one per iteration run)."""
+    import torch
+    dev = ctx.torch_device
+    n = tree.n
+    e = torch.as_tensor(energies, dtype=torch.float64, device=dev).contiguous()
+    w = torch.as_tensor(weights, dtype=torch.float64, device=dev).contiguous()
+    u = (torch.zeros(n, dtype=torch.float64, device=dev) if u0 is None else
+         torch.as_tensor(u0, dtype=torch.float64, device=dev).clone().contiguous())
+    if n0 is not None:
+        n0 = torch.as_tensor(n0, dtype=torch.float64, device=dev).contiguous()
+        _check_vec(n0, n, "n0")
+    dens = torch.empty(n, dtype=torch.float64, device=dev)
+    g = Grid(int(grid[0]), int(grid[1]), int(grid[2]), float(u_left), float(u_right))
+    opts = SolveOpts(eta, kT, mu_L, mu_R, HSC_DIAG_GL, batch, 0.0, 0, precision, 0, tune, complex3m, slices, None)
+    so = ScfOpts(float(coupling), _dptr(n0) if n0 is not None else None, float(mixing), int(max_iter), float(tol))
+    its = C.c_int32(0)
+    res = np.zeros(max(int(max_iter), 1))
+    check(lib().hsc_scf(ctx.h, tree.h, C.byref(g), int(e.numel()), _dptr(e), _dptr(w), C.byref(opts), C.byref(so),
+                        _dptr(u), _dptr(dens), C.byref(its), _ptr(res)))
+    return u, dens, res[:its.value]
 
 
 def totals(ctx: Context, out: dict, n: int):
