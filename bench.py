@@ -57,22 +57,26 @@ def oz_int8_ops_per_cmac(slices):
 # benchmark cube, one set-up batch and one step of 16 energies, through the native driver
 # paper_1702_05167_amd/hsc_run; profiles/k_oz_gemm_cube32_nd8_counters.md), each scaled by what the
 # counter reads for a plain copy of 64 MiB (FETCH_SIZE 32780.9 KiB for 65536 KiB read, WRITE_SIZE
-# 65536 KiB for 65536 KiB written).  Valid only for the kernel sources they were taken on.
+# 65536 KiB for 65536 KiB written).  Valid only for the kernel source and slice count they were
+# taken on.
 OZ_TRAFFIC = {"sources": ["paper_1702_05167_amd/csrc/ozaki.hip", "paper_1702_05167_amd/csrc/kern.h"],
-              "sha256": "0e6b27ce380b29b27c1ed7760b04177ae8cea03317a5cbce1903a44cdfa75efa",
+              "sha256": "6df200c49bd0bdbd338922a50cfeeb06fc850be4a1bcc1ed5309bcd7aebd24de",
               "fetch_kib_per_launch": 2768459.3, "write_kib_per_launch": 1455712.0, "launches": 268,
               "fetch_scale": 65536.0 / 32780.875, "write_scale": 65536.0 / 65536.0}
 
 
 def oz_sources_sha256():
-    """SHA-256 over the sources that define k_oz_gemm (the kernel and its slice count)."""
+    """SHA-256 over what defines k_oz_gemm: its source file and the slice-count lines of kern.h."""
     import hashlib
     h = hashlib.sha256()
     for rel in OZ_TRAFFIC["sources"]:
         path = os.path.join(ROOT, rel)
         if not os.path.exists(path):
             return None
-        h.update(open(path, "rb").read())
+        data = open(path, "rb").read()
+        if rel.endswith("kern.h"):
+            data = b"".join(line for line in data.splitlines(keepends=True) if b"constexpr int kOzSlices" in line)
+        h.update(data)
     return h.hexdigest()
 
 
