@@ -276,34 +276,31 @@ struct Builder {
     }
   }
 
+  // Workspace: blocks that live for the whole solve first; then the frontal matrices and Gauss-Jordan
+  // work (read only by the fold) and the lesser channels' blocks (written only after the fold) from
+  // one base, since every fold step precedes every channel step on the stream.  With per-site leads
+  // nothing reads a channel's blocks once the next channel starts (the transmission and the bond
+  // entries are taken inside their channel), so the channels share that region too; whole-face
+  // leads read the right channel's face block at the end, so there each channel keeps its own.
   void layout() {
     const int nc = (int)t->cl.size();
     cs.assign((size_t)nc * B, CS{});
+    const size_t ge = ddx ? 32 : 16;   // bytes per element of G and of the lesser channels
     for (int i = 0; i < nc; ++i) {
       const size_t n = n_of(i), f = f_of(i), P = P_of(i);
       const Cluster& c = t->cl[i];
-      const int nb = inv_nb((int)n);
-      const size_t ge = ddx ? 32 : 16;   // bytes per element of G and of the lesser channels
       for (int e = 0; e < B; ++e) {
         CS& s = cs[(size_t)i * B + e];
         s.Inv = wsa(n * n * 16);
         s.piv = wsa(n * 4);
         if (ddf) {
-          const size_t nbd = dd_inv_nb((int)n);
-          s.Fd = wsa((n + f) * (n + f) * 32);
           s.Invd = wsa(n * n * 32);
-          s.Td = wsa(n * std::max<size_t>(nbd, kDDSuper) * 32);
-          s.Rd = wsa(std::max<size_t>(nbd, kDDSuper) * n * 32);
           if (!root(i)) s.Psid = wsa(n * f * 32);
           if (oz && !root(i) && (int)f >= kOzMinK) s.PsiS = wsa(oz_bytes((int)n, (int)f));
           if (oz && !root(i) && !leaf(i) && (int)n >= kOzMinK) {
             s.PsiTS = wsa(oz_bytes((int)f, (int)n));
             s.InvS = wsa(oz_bytes((int)n, (int)n));
           }
-        } else {
-          s.F = wsa((n + f) * (n + f) * 16);
-          s.T = wsa(n * 4 * nb * 16);   // panel T (n x nb) and super-panel U (n x 4 nb)
-          s.R = wsa(4 * nb * n * 16);   // pivot rows of a panel / super-panel
         }
         if (!root(i)) s.Psi = wsa(n * f * 16);
         if (root(i)) s.GX = ddx ? s.Invd : s.Inv;
@@ -316,8 +313,37 @@ struct Builder {
             s.SD = wsa((size_t)(c.n_left + c.n_right) * (n + P) * ge);
           }
         }
-        for (size_t k = 0; k < chans.size(); ++k) {
-          const Channel& ch = chans[k];
+      }
+    }
+    const size_t base = ws;
+    for (int i = 0; i < nc; ++i) {
+      const size_t n = n_of(i), f = f_of(i);
+      const int nb = inv_nb((int)n);
+      for (int e = 0; e < B; ++e) {
+        CS& s = cs[(size_t)i * B + e];
+        if (ddf) {
+          const size_t nbd = dd_inv_nb((int)n);
+          s.Fd = wsa((n + f) * (n + f) * 32);
+          s.Td = wsa(n * std::max<size_t>(nbd, kDDSuper) * 32);
+          s.Rd = wsa(std::max<size_t>(nbd, kDDSuper) * n * 32);
+        } else {
+          s.F = wsa((n + f) * (n + f) * 16);
+          s.T = wsa(n * 4 * nb * 16);   // panel T (n x nb) and super-panel U (n x 4 nb)
+          s.R = wsa(4 * nb * n * 16);   // pivot rows of a panel / super-panel
+        }
+      }
+    }
+    const size_t fold_end = ws;
+    const bool share = !t->dense;
+    size_t chan_end = base;
+    ws = base;
+    for (size_t k = 0; k < chans.size(); ++k) {
+      if (share) ws = base;
+      const Channel& ch = chans[k];
+      for (int i = 0; i < nc; ++i) {
+        const size_t n = n_of(i), f = f_of(i), P = P_of(i);
+        for (int e = 0; e < B; ++e) {
+          CS& s = cs[(size_t)i * B + e];
           if (in_fold(ch, i)) {
             int row0, r;
             own_rows(ch, i, &row0, &r);
@@ -335,7 +361,9 @@ struct Builder {
           }
         }
       }
+      chan_end = std::max(chan_end, ws);
     }
+    ws = std::max(fold_end, chan_end);
   }
 
   void layout_faces() {
