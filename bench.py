@@ -56,13 +56,13 @@ def oz_int8_ops_per_cmac(slices):
 # HBM traffic of k_oz_gemm per launch from two rocprofv3 --pmc passes over the same workload (the
 # benchmark cube, one set-up batch and one step of 16 energies, through the native driver
 # paper_1702_05167_amd/hsc_run; profiles/k_oz_gemm_cube32_nd8_counters.md), each scaled by what the
-# counter reads for a plain copy of 64 MiB (FETCH_SIZE 32780.9 KiB for 65536 KiB read, WRITE_SIZE
+# counter reads for a plain copy of 64 MiB (FETCH_SIZE 32781.3 KiB for 65536 KiB read, WRITE_SIZE
 # 65536 KiB for 65536 KiB written).  Valid only for the kernel source and slice count they were
 # taken on.
 OZ_TRAFFIC = {"sources": ["paper_1702_05167_amd/csrc/ozaki.hip", "paper_1702_05167_amd/csrc/kern.h"],
               "sha256": "593ccb11464d5d8e0e8d93acd64e3e56a31e5f11cb9ab49fbf1c6df4caa12a5c",
-              "fetch_kib_per_launch": 2768459.3, "write_kib_per_launch": 1455712.0, "launches": 268,
-              "fetch_scale": 65536.0 / 32780.875, "write_scale": 65536.0 / 65536.0}
+              "fetch_kib_per_launch": 2763533.9, "write_kib_per_launch": 1455739.6, "launches": 268,
+              "fetch_scale": 65536.0 / 32781.25, "write_scale": 65536.0 / 65536.0}
 
 
 def oz_sources_sha256():
