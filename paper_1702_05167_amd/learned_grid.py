@@ -10,7 +10,7 @@ log D(E) (D = DOS injected by the contacts) and log T(E); from it
     rho(E) ~ |g''(E)|^(1/3) + floor                (point density minimising the trapezoid error)
 
 and the chosen energies are the candidates at equal steps of the cumulative density.  The HSC
-solve stays the judge: the integrand is computed by the solver at every chosen energy, the
+solve stays the arbiter: the integrand is computed by the solver at every chosen energy, the
 trapezoid error of each interval is estimated from divided differences of the solved values,
 and the worst intervals get extra solves (bounded budget).
 
