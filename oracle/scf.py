@@ -79,15 +79,16 @@ def density(weights, gl):
 
 
 def scf(dev, grid, energies, weights, eta, kT, mu_L, mu_R, u_left, u_right, coupling, n0=None,
-        mixing=0.5, iterations=10, tol=0.0, u0=None):
-    """The loop of the module docstring on the dense oracle; returns u, density, residuals."""
+        mixing=0.5, iterations=10, tol=0.0, u0=None, dense=False):
+    """The loop of the module docstring on the dense oracle (dense=True: whole-face leads); returns
+    u, density, residuals."""
     n = dev.n
     u = np.zeros(n) if u0 is None else np.array(u0, dtype=np.float64)
     n0 = np.zeros(n) if n0 is None else np.asarray(n0, dtype=np.float64)
     residuals = []
     dens = np.zeros(n)
     for _ in range(iterations):
-        out = _dense.solve(dev, energies, eta, kT, mu_L, mu_R, potential=u)
+        out = _dense.solve(dev, energies, eta, kT, mu_L, mu_R, dense=dense, potential=u)
         dens = density(weights, out["gl"])
         u_new = poisson_solve(grid, coupling * (dens - n0), u_left, u_right)
         r = float(np.abs(u_new - u).max())

@@ -164,6 +164,20 @@ def test_scf_iterations_against_oracle(ctx, precision, coupling, mixing):
     assert np.abs(res - ref["residuals"]).max() <= 1e-10 * ref["residuals"].max()
 
 
+def test_scf_with_whole_face_leads_against_oracle(ctx):
+    # three iterations on a 5 x 4 x 3 device whose contacts are whole faces (dense self-energies)
+    dev, grid, E, w = _scf_case()
+    kw = dict(eta=1e-8, kT=0.05, mu_L=0.1, mu_R=-0.1)
+    tree = pkg.Tree.from_device(dev, leaf_side=2, dense=True)
+    u, dens, res = pkg.scf(ctx, tree, grid, E, w, u_left=0.1, u_right=-0.1, coupling=0.2, mixing=0.4, max_iter=3,
+                           **kw)
+    ref = oracle.scf.scf(dev, grid, E, w, u_left=0.1, u_right=-0.1, coupling=0.2, mixing=0.4, iterations=3,
+                         dense=True, **kw)
+    print("scf whole-face residuals", res, ref["residuals"])
+    assert rel(u.cpu().numpy(), ref["u"]) <= 1e-10
+    assert rel(dens.cpu().numpy(), ref["density"]) <= 1e-10
+
+
 def test_scf_converges_to_a_fixed_point(ctx):
     # run to a tolerance on a 6 x 5 x 4 device; the converged U solves Poisson with the density it
     # produces, checked with the oracle's sparse Poisson solve on the GPU density
