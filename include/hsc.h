@@ -190,7 +190,9 @@ typedef struct {
    * or NULL: the device Hamiltonian becomes H + diag(U) (the electrostatic
    * potential of a self-consistent NEGF-Poisson loop; the leads keep their own
    * on-site energies).  Read when the call enqueues its first launch; single-
-   * device solves only (hsc_solve_batch returns HSC_E_ARG for a non-NULL U). */
+   * device solves only (hsc_solve_batch returns HSC_E_ARG for a non-NULL U).
+   * The values must be finite (they are not checked; a NaN typically ends as
+   * HSC_E_SINGULAR in the energy's status). */
   const double* potential;
 } hsc_solve_opts;
 
