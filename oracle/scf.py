@@ -16,6 +16,12 @@ mixing.  The readings used here, step by step:
   the site itself (zero normal derivative, Neumann).
 * Source rho = c (n - n0): coupling c (e^2 / epsilon in model units), background n0.
 * Linear mixing: U <- U + beta (U_new - U); residual r = max_i |U_new - U|, taken before mixing.
+  Optionally Anderson mixing over the last m iterations (Anderson, J. ACM 12, 1965; the form of
+  Walker and Ni, SIAM J. Numer. Anal. 49, 2011): with f_k = U_new - U_k, the differences
+  dX_j = U_j+1 - U_j and dF_j = f_j+1 - f_j of the last m steps, gamma = argmin || f_k - dF gamma ||_2
+  (Householder QR of dF), U_k+1 = U_k + beta f_k - (dX + beta dF) gamma; when R has a diagonal entry
+  below 1e-12 of its largest the history is cleared (plain linear mixing for that step).  m = 0 is
+  linear mixing.
 
 One iteration: NEGF solve at U, density, source, Poisson solve -> U_new, residual, mix; the loop
 stops after the iteration whose residual falls below tol (tol = 0: exactly `iterations` steps).
@@ -78,8 +84,39 @@ def density(weights, gl):
     return np.asarray(weights, dtype=np.float64) @ np.imag(np.asarray(gl)) / (2.0 * np.pi)
 
 
+class Anderson:
+    """Mixing of the fixed-point iteration U <- g(U): step(U, g(U)) returns the next U."""
+
+    def __init__(self, history: int, beta: float):
+        self.m, self.beta = int(history), float(beta)
+        self.dX, self.dF = [], []
+        self.x_prev = self.f_prev = None
+
+    def step(self, x, gx):
+        x = np.asarray(x, dtype=np.float64)
+        f = np.asarray(gx, dtype=np.float64) - x
+        if self.m > 0 and self.x_prev is not None:
+            self.dX.append(x - self.x_prev)
+            self.dF.append(f - self.f_prev)
+            if len(self.dF) > self.m:
+                self.dX.pop(0)
+                self.dF.pop(0)
+        self.x_prev, self.f_prev = x.copy(), f.copy()
+        x_new = x + self.beta * f
+        if self.dF:
+            dF = np.stack(self.dF, axis=1)
+            q, r = np.linalg.qr(dF)
+            d = np.abs(np.diag(r))
+            if d.min() < 1e-12 * d.max():
+                self.dX, self.dF = [], []
+                return x_new
+            gamma = np.linalg.solve(r, q.T @ f)
+            x_new = x_new - (np.stack(self.dX, axis=1) + self.beta * dF) @ gamma
+        return x_new
+
+
 def scf(dev, grid, energies, weights, eta, kT, mu_L, mu_R, u_left, u_right, coupling, n0=None,
-        mixing=0.5, iterations=10, tol=0.0, u0=None, dense=False):
+        mixing=0.5, iterations=10, tol=0.0, u0=None, dense=False, history=0):
     """The loop of the module docstring on the dense oracle (dense=True: whole-face leads); returns
     u, density, residuals."""
     n = dev.n
@@ -87,13 +124,14 @@ def scf(dev, grid, energies, weights, eta, kT, mu_L, mu_R, u_left, u_right, coup
     n0 = np.zeros(n) if n0 is None else np.asarray(n0, dtype=np.float64)
     residuals = []
     dens = np.zeros(n)
+    mixer = Anderson(history, mixing)
     for _ in range(iterations):
         out = _dense.solve(dev, energies, eta, kT, mu_L, mu_R, dense=dense, potential=u)
         dens = density(weights, out["gl"])
         u_new = poisson_solve(grid, coupling * (dens - n0), u_left, u_right)
         r = float(np.abs(u_new - u).max())
         residuals.append(r)
-        u = u + mixing * (u_new - u)
+        u = mixer.step(u, u_new)
         if r < tol:
             break
     return {"u": u, "density": dens, "residuals": np.array(residuals)}

@@ -129,3 +129,49 @@ def test_scf_fixed_point_and_screening_sign():
     assert r["u"].min() > 0
     r2 = oracle.scf.scf(dev, grid, E, w, n0=np.full(36, 0.05), **kw)
     assert (r2["u"] < r["u"]).all()
+
+
+def test_anderson_without_history_is_linear_mixing():
+    rng = np.random.default_rng(3)
+    a = oracle.scf.Anderson(0, 0.4)
+    x = rng.normal(size=7)
+    for _ in range(4):
+        gx = np.tanh(x) + 0.3
+        nxt = a.step(x, gx)
+        assert np.array_equal(nxt, x + 0.4 * (gx - x))
+        x = nxt
+
+
+def test_anderson_solves_an_affine_map_in_dimension_plus_one_steps():
+    # for g(x) = M x + c Anderson mixing with enough history is GMRES on (I - M) x = c: it reaches the
+    # fixed point (I - M)^-1 c after at most dim + 1 evaluations of g (here 6 unknowns)
+    rng = np.random.default_rng(5)
+    n = 6
+    M = rng.normal(size=(n, n))
+    M = 0.9 * M / np.abs(np.linalg.eigvals(M)).max()
+    c = rng.normal(size=n)
+    ref = np.linalg.solve(np.eye(n) - M, c)
+    a = oracle.scf.Anderson(n, 1.0)
+    x = np.zeros(n)
+    for _ in range(n + 2):
+        x = a.step(x, M @ x + c)
+    assert np.abs(x - ref).max() < 1e-10 * np.abs(ref).max()
+    # linear mixing needs far more steps for the same map
+    y = np.zeros(n)
+    lin = oracle.scf.Anderson(0, 1.0)
+    for _ in range(n + 2):
+        y = lin.step(y, M @ y + c)
+    assert np.abs(y - ref).max() > 1e-3 * np.abs(ref).max()
+
+
+def test_scf_with_anderson_mixing_reaches_the_same_fixed_point_sooner():
+    dev = synth.cuboid(4, 3, 3, onsite=np.random.default_rng(5).normal(0, 0.2, 36))
+    grid = (4, 3, 3)
+    E = np.linspace(-6.0, 2.0, 33)
+    w = np.full(33, E[1] - E[0])
+    kw = dict(eta=1e-8, kT=0.05, mu_L=0.05, mu_R=-0.05, u_left=0.0, u_right=0.0, coupling=0.2, mixing=0.6,
+              iterations=60, tol=1e-12)
+    lin = oracle.scf.scf(dev, grid, E, w, **kw)
+    acc = oracle.scf.scf(dev, grid, E, w, history=4, **kw)
+    assert acc["residuals"][-1] < 1e-12 and len(acc["residuals"]) < len(lin["residuals"])
+    assert np.abs(acc["u"] - lin["u"]).max() < 1e-11
