@@ -382,13 +382,19 @@ typedef struct {
   double mixing;             /* beta in (0, 1]: U <- U + beta (U_new - U) */
   int32_t max_iter;          /* >= 1 */
   double tol;                /* stop after the iteration whose residual max|U_new - U| < tol; 0: max_iter */
+  int32_t history;           /* 0: linear mixing; m in [1, 16]: Anderson mixing over the last m steps
+                              * (Anderson 1965, in the form of Walker and Ni 2011): with f_k = U_new - U_k
+                              * and the last m differences dX, dF of U and f, gamma = argmin
+                              * ||f_k - dF gamma||_2 (Householder QR on the host), U_k+1 = U_k + beta f_k
+                              * - (dX + beta dF) gamma; the history is cleared when R is numerically
+                              * singular (a diagonal entry below 1e-12 of the largest) */
 } hsc_scf_opts;
 
 /* The loop: for each iteration, solve every energy with potential u (hsc_solve
  * with opts, diag G^< only), density as hsc_density, source c (n - n0),
  * U_new = hsc_poisson_solve(source), residual max_i |U_new - u|, then
  * u <- u + beta (U_new - u).  u: device double[n], the starting potential on
- * entry and the last mixed one on return; density: device double[n], the density
+ * entry and the last mixed (or Anderson-updated) one on return; density: device double[n], the density
  * of the last solve (at the potential before the last mixing); energies,
  * weights: device double[n_e]; *iterations (host) = iterations run; residuals
  * (host double[max_iter], may be NULL) = residual of each.  The tree must have

@@ -316,6 +316,15 @@ void launch_potential(hipStream_t st, int64_t n, const int64_t* perm, const doub
 void launch_density(hipStream_t st, int ne, int64_t n, const double* w, const void* gl, double* dens);
 // *r = max_i |u_new - u| (bits of a non-negative double), then u += beta (u_new - u)
 void launch_mix(hipStream_t st, int64_t n, double* u, const double* u_new, double beta, unsigned long long* r);
+// Anderson mixing: f = u_new - u with its max |f_i| in *r; the history difference (dX, dF may be null) and the
+// previous (u, f); the update u = u + beta f - sum_j gamma_j (dX_j + beta dF_j) over the slots in `order`
+constexpr int kScfMaxHistory = 16;
+void launch_scf_resid(hipStream_t st, int64_t n, const double* u, const double* u_new, double* f,
+                      unsigned long long* r);
+void launch_scf_hist(hipStream_t st, int64_t n, const double* u, const double* f, double* u_prev, double* f_prev,
+                     double* dX, double* dF);
+void launch_scf_update(hipStream_t st, int64_t n, double* u, const double* f, double beta, int mk, const double* dX,
+                       const double* dF, const int32_t* order, const double* gamma);
 constexpr int kPoissonMaxSide = 1024;
 // 0 when the grid is usable (sides in [1, kPoissonMaxSide], finite lead-plane values), else -1
 // with the reason

@@ -98,6 +98,51 @@ __global__ __launch_bounds__(PB) void k_mix(int64_t n, double* __restrict__ u, c
   if ((threadIdx.x & 63) == 0) atomicMax(r, (unsigned long long)__double_as_longlong(m));
 }
 
+// f = u_new - u and *r = max_i |f_i| (ordered bits), u unchanged
+__global__ __launch_bounds__(PB) void k_scf_resid(int64_t n, const double* __restrict__ u,
+                                                  const double* __restrict__ u_new, double* __restrict__ f,
+                                                  unsigned long long* __restrict__ r) {
+  const int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
+  double d = 0.0;
+  if (i < n) {
+    d = u_new[i] - u[i];
+    f[i] = d;
+  }
+  double m = fabs(d);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(r, (unsigned long long)__double_as_longlong(m));
+}
+
+// Anderson history: dX = u - u_prev, dF = f - f_prev (when given), then u_prev = u, f_prev = f
+__global__ __launch_bounds__(PB) void k_scf_hist(int64_t n, const double* __restrict__ u, const double* __restrict__ f,
+                                                 double* __restrict__ u_prev, double* __restrict__ f_prev,
+                                                 double* __restrict__ dX, double* __restrict__ dF) {
+  const int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
+  if (i >= n) return;
+  if (dX) {
+    dX[i] = u[i] - u_prev[i];
+    dF[i] = f[i] - f_prev[i];
+  }
+  u_prev[i] = u[i];
+  f_prev[i] = f[i];
+}
+
+// u = u + beta f - sum_j gamma_j (dX_j + beta dF_j), history slots in `order`
+__global__ __launch_bounds__(PB) void k_scf_update(int64_t n, double* __restrict__ u, const double* __restrict__ f,
+                                                   double beta, int mk, const double* __restrict__ dX,
+                                                   const double* __restrict__ dF, const int32_t* __restrict__ order,
+                                                   const double* __restrict__ gamma) {
+  const int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x;
+  if (i >= n) return;
+  double x = u[i] + beta * f[i];
+  for (int j = 0; j < mk; ++j) {
+    const int64_t o = (int64_t)order[j] * n + i;
+    x -= gamma[j] * (dX[o] + beta * dF[o]);
+  }
+  u[i] = x;
+}
+
 __global__ void k_zero_u64(unsigned long long* p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0ull;
 }
@@ -125,6 +170,23 @@ void launch_density(hipStream_t st, int ne, int64_t n, const double* w, const vo
 void launch_mix(hipStream_t st, int64_t n, double* u, const double* u_new, double beta, unsigned long long* r) {
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, r);
   if (n > 0) hipLaunchKernelGGL(k_mix, dim3(blocks(n)), dim3(PB), 0, st, n, u, u_new, beta, r);
+}
+
+void launch_scf_resid(hipStream_t st, int64_t n, const double* u, const double* u_new, double* f,
+                      unsigned long long* r) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, r);
+  if (n > 0) hipLaunchKernelGGL(k_scf_resid, dim3(blocks(n)), dim3(PB), 0, st, n, u, u_new, f, r);
+}
+
+void launch_scf_hist(hipStream_t st, int64_t n, const double* u, const double* f, double* u_prev, double* f_prev,
+                     double* dX, double* dF) {
+  if (n > 0) hipLaunchKernelGGL(k_scf_hist, dim3(blocks(n)), dim3(PB), 0, st, n, u, f, u_prev, f_prev, dX, dF);
+}
+
+void launch_scf_update(hipStream_t st, int64_t n, double* u, const double* f, double beta, int mk, const double* dX,
+                       const double* dF, const int32_t* order, const double* gamma) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_scf_update, dim3(blocks(n)), dim3(PB), 0, st, n, u, f, beta, mk, dX, dF, order, gamma);
 }
 
 int poisson_check(const hsc_grid* g, std::string* why) {

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -2433,13 +2434,56 @@ hsc_status hsc_totals(hsc_ctx* ctx, int32_t n_e, int64_t n, const void* diag_gr,
   return HSC_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// gamma = argmin || b - A gamma ||_2 for A (n x m, columns in `a`, column-major, overwritten) by
+// Householder QR; false when R has a diagonal entry below 1e-12 of its largest (numerically singular)
+bool lstsq_householder(int64_t n, int m, std::vector<double>& a, std::vector<double>& b, double* gamma) {
+  std::vector<double> rdiag(m);
+  for (int j = 0; j < m; ++j) {
+    double* cj = a.data() + (size_t)j * n;
+    double nrm = 0.0;
+    for (int64_t i = j; i < n; ++i) nrm += cj[i] * cj[i];
+    nrm = std::sqrt(nrm);
+    if (nrm == 0.0) return false;
+    const double alpha = cj[j] > 0.0 ? -nrm : nrm;
+    cj[j] -= alpha;   // v = column below the diagonal with v_j = a_jj - alpha
+    double vv = 0.0;
+    for (int64_t i = j; i < n; ++i) vv += cj[i] * cj[i];
+    auto reflect = [&](double* y) {
+      double s = 0.0;
+      for (int64_t i = j; i < n; ++i) s += cj[i] * y[i];
+      s = 2.0 * s / vv;
+      for (int64_t i = j; i < n; ++i) y[i] -= s * cj[i];
+    };
+    for (int k = j + 1; k < m; ++k) reflect(a.data() + (size_t)k * n);
+    reflect(b.data());
+    rdiag[j] = alpha;
+  }
+  double dmax = 0.0, dmin = INFINITY;
+  for (double d : rdiag) { dmax = std::max(dmax, std::fabs(d)); dmin = std::min(dmin, std::fabs(d)); }
+  if (!(dmin >= 1e-12 * dmax)) return false;
+  for (int j = m - 1; j >= 0; --j) {   // R gamma = (Q^T b)[0:m]; R above the diagonal sits in a
+    double s = b[j];
+    for (int k = j + 1; k < m; ++k) s -= a[(size_t)k * n + j] * gamma[k];
+    gamma[j] = s / rdiag[j];
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
 hsc_status hsc_scf(hsc_ctx* ctx, const hsc_tree* tree, const hsc_grid* grid, int32_t n_e, const double* energies,
                    const double* weights, const hsc_solve_opts* opts, const hsc_scf_opts* scf, double* u,
                    double* density, int32_t* iterations, double* residuals) {
   std::string why;
   if (!ctx || !tree || !opts || !scf || n_e < 1 || !energies || !weights || !u || !density || !iterations ||
       poisson_check(grid, &why) != 0 || scf->max_iter < 1 || !(scf->mixing > 0.0 && scf->mixing <= 1.0) ||
-      !(scf->coupling >= 0.0) || !(scf->tol >= 0.0)) {
+      !(scf->coupling >= 0.0) || !(scf->tol >= 0.0) || scf->history < 0 || scf->history > kScfMaxHistory) {
     set_error(why.empty() ? std::string("bad arguments to hsc_scf") : "hsc_scf: " + why);
     return HSC_E_ARG;
   }
@@ -2454,10 +2498,13 @@ hsc_status hsc_scf(hsc_ctx* ctx, const hsc_tree* tree, const hsc_grid* grid, int
   PoissonWork pw;
   if (pw.create(*grid) != 0) { set_error("hsc_scf: Poisson workspace allocation failed"); return HSC_E_OOM; }
   char* buf = nullptr;
-  // diag G^< [n_e][n], U_new [n], per-energy status [n_e], residual bits
+  // diag G^< [n_e][n], U_new [n], per-energy status [n_e], residual bits; with Anderson mixing f, the
+  // previous U and f, the m differences of each, and the step's coefficients and slot order
+  const int m = scf->history;
   auto pad = [](size_t v) { return (v + 255) / 256 * 256; };
   const size_t o_un = pad((size_t)n_e * n * 16), o_st = o_un + pad((size_t)n * 8), o_r = o_st + pad((size_t)n_e * 4),
-               total = o_r + 256;
+               o_f = o_r + 256, o_hist = o_f + (m ? pad((size_t)n * 8 * (3 + 2 * (size_t)m)) : 0),
+               total = o_hist + (m ? pad((size_t)m * 12) : 0);
   if (hipMalloc(&buf, total) != hipSuccess) {
     (void)hipGetLastError();
     pw.destroy();
@@ -2468,6 +2515,16 @@ hsc_status hsc_scf(hsc_ctx* ctx, const hsc_tree* tree, const hsc_grid* grid, int
   double* u_new = reinterpret_cast<double*>(buf + o_un);
   int32_t* status = reinterpret_cast<int32_t*>(buf + o_st);
   unsigned long long* rbits = reinterpret_cast<unsigned long long*>(buf + o_r);
+  double* f = m ? reinterpret_cast<double*>(buf + o_f) : nullptr;
+  double* u_prev = m ? f + n : nullptr;
+  double* f_prev = m ? f + 2 * n : nullptr;
+  double* dX = m ? f + 3 * n : nullptr;
+  double* dF = m ? dX + (size_t)m * n : nullptr;
+  double* gamma_d = m ? reinterpret_cast<double*>(buf + o_hist) : nullptr;
+  int32_t* order_d = m ? reinterpret_cast<int32_t*>(gamma_d + m) : nullptr;
+  std::vector<int32_t> order;   // history slots, oldest first
+  int pushes = 0;
+  std::vector<double> a_h, b_h, gamma_h(m > 0 ? m : 1);
   hsc_solve_opts o = *opts;
   o.want = HSC_DIAG_GL;
   o.potential = u;
@@ -2478,9 +2535,42 @@ hsc_status hsc_scf(hsc_ctx* ctx, const hsc_tree* tree, const hsc_grid* grid, int
     if (rc != HSC_OK) break;
     launch_density(ctx->stream, n_e, n, weights, gl, density);
     pw.run(ctx->stream, nullptr, density, scf->n0, scf->coupling, u_new);
-    launch_mix(ctx->stream, n, u, u_new, scf->mixing, rbits);
+    hipError_t e = hipSuccess;
+    if (m == 0) {
+      launch_mix(ctx->stream, n, u, u_new, scf->mixing, rbits);
+    } else {
+      launch_scf_resid(ctx->stream, n, u, u_new, f, rbits);
+      int slot = -1;
+      if (it > 0) {
+        slot = pushes++ % m;
+        order.push_back(slot);
+        if ((int)order.size() > m) order.erase(order.begin());
+      }
+      launch_scf_hist(ctx->stream, n, u, f, u_prev, f_prev, slot >= 0 ? dX + (size_t)slot * n : nullptr,
+                      slot >= 0 ? dF + (size_t)slot * n : nullptr);
+      int mk = (int)order.size();
+      if (mk > 0) {
+        a_h.resize((size_t)mk * n);
+        b_h.resize(n);
+        for (int j = 0; j < mk && e == hipSuccess; ++j)
+          e = hipMemcpyAsync(a_h.data() + (size_t)j * n, dF + (size_t)order[j] * n, 8 * (size_t)n,
+                             hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(b_h.data(), f, 8 * (size_t)n, hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = ctx->stream ? hipStreamSynchronize(ctx->stream) : hipDeviceSynchronize();
+        if (e == hipSuccess && !lstsq_householder(n, mk, a_h, b_h, gamma_h.data())) {
+          order.clear();   // numerically dependent differences: a plain linear step, history restarts
+          mk = 0;
+        }
+        if (e == hipSuccess && mk > 0) {
+          e = hipMemcpyAsync(gamma_d, gamma_h.data(), 8 * (size_t)mk, hipMemcpyHostToDevice, ctx->stream);
+          if (e == hipSuccess)
+            e = hipMemcpyAsync(order_d, order.data(), 4 * (size_t)mk, hipMemcpyHostToDevice, ctx->stream);
+        }
+      }
+      if (e == hipSuccess) launch_scf_update(ctx->stream, n, u, f, scf->mixing, mk, dX, dF, order_d, gamma_d);
+    }
     unsigned long long rb = 0;
-    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(st_h.data(), status, 4 * (size_t)n_e, hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(&rb, rbits, 8, hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = ctx->stream ? hipStreamSynchronize(ctx->stream) : hipDeviceSynchronize();

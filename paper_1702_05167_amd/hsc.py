@@ -61,7 +61,7 @@ class Grid(C.Structure):
 
 class ScfOpts(C.Structure):
     _fields_ = [("coupling", C.c_double), ("n0", C.c_void_p), ("mixing", C.c_double), ("max_iter", C.c_int32),
-                ("tol", C.c_double)]
+                ("tol", C.c_double), ("history", C.c_int32)]
 
 
 _lib = None
@@ -466,9 +466,10 @@ def density(ctx: Context, weights, gl):
 
 def scf(ctx: Context, tree: Tree, grid, energies, weights, u_left=0.0, u_right=0.0, coupling=0.0, n0=None,
         mixing=0.5, max_iter=10, tol=0.0, u0=None, eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, batch=0,
-        precision=3, tune=0, complex3m=0, slices=0):
+        precision=3, tune=0, complex3m=0, slices=0, history=0):
     """hsc_scf: the self-consistent NEGF-Poisson loop; returns (u, density, residuals) with u and
-    density device float64 [n] and residuals a numpy array (one per iteration run)."""
+    density device float64 [n] and residuals a numpy array (one per iteration run).  history > 0
+    mixes by Anderson's method over that many past steps, 0 linearly."""
     import torch
     dev = ctx.torch_device
     n = tree.n
@@ -482,7 +483,8 @@ def scf(ctx: Context, tree: Tree, grid, energies, weights, u_left=0.0, u_right=0
     dens = torch.empty(n, dtype=torch.float64, device=dev)
     g = Grid(int(grid[0]), int(grid[1]), int(grid[2]), float(u_left), float(u_right))
     opts = SolveOpts(eta, kT, mu_L, mu_R, HSC_DIAG_GL, batch, 0.0, 0, precision, 0, tune, complex3m, slices, None)
-    so = ScfOpts(float(coupling), _dptr(n0) if n0 is not None else None, float(mixing), int(max_iter), float(tol))
+    so = ScfOpts(float(coupling), _dptr(n0) if n0 is not None else None, float(mixing), int(max_iter), float(tol),
+                 int(history))
     its = C.c_int32(0)
     res = np.zeros(max(int(max_iter), 1))
     check(lib().hsc_scf(ctx.h, tree.h, C.byref(g), int(e.numel()), _dptr(e), _dptr(w), C.byref(opts), C.byref(so),

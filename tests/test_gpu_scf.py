@@ -198,6 +198,45 @@ def test_scf_converges_to_a_fixed_point(ctx):
     assert np.abs(oracle.scf.poisson_solve((nx, ny, nz), 0.2 * d, 0.0, 0.0) - u).max() < 1e-10
 
 
+@pytest.mark.parametrize("history", [1, 4])
+def test_scf_anderson_iterations_against_oracle(ctx, history):
+    # six iterations with Anderson mixing over the last `history` steps: the device keeps the
+    # differences, the host solves the small least-squares problem, and the update runs on the device
+    dev, grid, E, w = _scf_case()
+    n0 = np.full(dev.n, 0.02)
+    kw = dict(eta=1e-8, kT=0.05, mu_L=0.1, mu_R=-0.1)
+    tree = pkg.Tree.from_device(dev, leaf_side=2)
+    print(f"[scf anderson history {history}]", flush=True)
+    u, dens, res = pkg.scf(ctx, tree, grid, E, w, u_left=0.1, u_right=-0.1, coupling=0.2, n0=n0, mixing=0.4,
+                           max_iter=6, history=history, **kw)
+    ref = oracle.scf.scf(dev, grid, E, w, u_left=0.1, u_right=-0.1, coupling=0.2, n0=n0, mixing=0.4,
+                         iterations=6, history=history, **kw)
+    print("scf anderson residuals", res, ref["residuals"])
+    assert len(res) == 6
+    assert rel(u.cpu().numpy(), ref["u"]) <= 1e-10
+    assert rel(dens.cpu().numpy(), ref["density"]) <= 1e-10
+    assert np.abs(res - ref["residuals"]).max() <= 1e-10 * ref["residuals"].max()
+
+
+def test_scf_anderson_reaches_the_linear_fixed_point_sooner(ctx):
+    # on a 4 x 3 x 3 device, linear mixing needs about three times the iterations of Anderson mixing
+    # over four steps to reach a residual of 1e-12; both stop at the same potential
+    nx, ny, nz = 4, 3, 3
+    n = nx * ny * nz
+    dev = synth.cuboid(nx, ny, nz, onsite=np.random.default_rng(5).normal(0, 0.2, n))
+    E = np.linspace(-6.0, 2.0, 33)
+    w = np.full(33, E[1] - E[0])
+    kw = dict(eta=1e-8, kT=0.05, mu_L=0.05, mu_R=-0.05, coupling=0.2, mixing=0.6, max_iter=60, tol=1e-12)
+    tree = pkg.Tree.from_device(dev, leaf_side=2)
+    u_lin, _, r_lin = pkg.scf(ctx, tree, (nx, ny, nz), E, w, **kw)
+    u_acc, _, r_acc = pkg.scf(ctx, tree, (nx, ny, nz), E, w, history=4, **kw)
+    print("linear", len(r_lin), r_lin[-1], "anderson", len(r_acc), r_acc[-1])
+    assert r_lin[-1] < 1e-12 and r_acc[-1] < 1e-12 and len(r_lin) < 60
+    assert 2 * len(r_acc) <= len(r_lin)
+    assert np.abs(u_lin.cpu().numpy() - u_acc.cpu().numpy()).max() < 1e-11
+    assert u_lin.shape == (n,)
+
+
 def test_scf_rejects_a_grid_that_is_not_the_tree(ctx):
     dev, grid, E, w = _scf_case()
     tree = pkg.Tree.from_device(dev, leaf_side=2)
@@ -206,3 +245,6 @@ def test_scf_rejects_a_grid_that_is_not_the_tree(ctx):
     assert e.value.code == -1
     with pytest.raises(H.HscError):
         pkg.scf(ctx, tree, grid, E, w, coupling=0.1, mixing=1.5, max_iter=1)
+    for history in (-1, 17):
+        with pytest.raises(H.HscError):
+            pkg.scf(ctx, tree, grid, E, w, coupling=0.1, max_iter=1, history=history)
