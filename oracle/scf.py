@@ -105,6 +105,10 @@ class Anderson:
         x_new = x + self.beta * f
         if self.dF:
             dF = np.stack(self.dF, axis=1)
+            if dF.shape[1] > dF.shape[0]:
+                # more differences than unknowns: the columns are dependent, as for a singular R
+                self.dX, self.dF = [], []
+                return x_new
             q, r = np.linalg.qr(dF)
             d = np.abs(np.diag(r))
             if d.min() < 1e-12 * d.max():

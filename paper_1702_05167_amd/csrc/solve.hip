@@ -2440,7 +2440,9 @@ namespace {
 
 // gamma = argmin || b - A gamma ||_2 for A (n x m, columns in `a`, column-major, overwritten) by
 // Householder QR; false when R has a diagonal entry below 1e-12 of its largest (numerically singular)
+// or when m > n (more columns than rows: dependent)
 bool lstsq_householder(int64_t n, int m, std::vector<double>& a, std::vector<double>& b, double* gamma) {
+  if ((int64_t)m > n) return false;
   std::vector<double> rdiag(m);
   for (int j = 0; j < m; ++j) {
     double* cj = a.data() + (size_t)j * n;

@@ -218,6 +218,24 @@ def test_scf_anderson_iterations_against_oracle(ctx, history):
     assert np.abs(res - ref["residuals"]).max() <= 1e-10 * ref["residuals"].max()
 
 
+def test_scf_anderson_with_more_history_than_sites(ctx):
+    # a three-site chain with a history of five: the fifth iteration holds four differences of three
+    # unknowns, which both sides treat as dependent (a linear step, history restarted)
+    dev = synth.cuboid(3, 1, 1, onsite=np.array([0.1, -0.2, 0.05]))
+    E = np.linspace(-3.0, 1.0, 17)
+    w = np.full(17, E[1] - E[0])
+    kw = dict(eta=1e-8, kT=0.05, mu_L=0.1, mu_R=-0.1)
+    tree = pkg.Tree.from_device(dev, leaf_side=2)
+    u, dens, res = pkg.scf(ctx, tree, (3, 1, 1), E, w, u_left=0.1, u_right=-0.1, coupling=0.3, mixing=0.5,
+                           max_iter=8, history=5, **kw)
+    ref = oracle.scf.scf(dev, (3, 1, 1), E, w, u_left=0.1, u_right=-0.1, coupling=0.3, mixing=0.5, iterations=8,
+                         history=5, **kw)
+    print("tiny anderson residuals", res, ref["residuals"])
+    assert len(res) == 8
+    assert rel(u.cpu().numpy(), ref["u"]) <= 1e-10
+    assert np.abs(res - ref["residuals"]).max() <= 1e-10 * ref["residuals"].max()
+
+
 def test_scf_anderson_reaches_the_linear_fixed_point_sooner(ctx):
     # on a 4 x 3 x 3 device, linear mixing needs about three times the iterations of Anderson mixing
     # over four steps to reach a residual of 1e-12; both stop at the same potential

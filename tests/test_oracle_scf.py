@@ -142,6 +142,27 @@ def test_anderson_without_history_is_linear_mixing():
         x = nxt
 
 
+def test_anderson_with_more_history_than_unknowns_restarts_linearly():
+    # two unknowns and a history of four: the second difference already spans the space (the affine
+    # map's fixed point is reached), and a third difference cannot be independent, so that step is
+    # the linear one and the history restarts
+    rng = np.random.default_rng(8)
+    M = 0.5 * rng.normal(size=(2, 2))
+    c = rng.normal(size=2)
+    ref = np.linalg.solve(np.eye(2) - M, c)
+    a = oracle.scf.Anderson(4, 0.5)
+    x = np.array([0.3, -0.2])
+    xs = [x]
+    for _ in range(6):
+        x = a.step(x, M @ x + c)
+        xs.append(x)
+    assert np.abs(xs[3] - ref).max() < 1e-12
+    # the fourth step holds three differences of two unknowns: linear mixing, history cleared
+    lin = xs[3] + 0.5 * (M @ xs[3] + c - xs[3])
+    assert np.array_equal(xs[4], lin)
+    assert np.abs(xs[-1] - ref).max() < 1e-12
+
+
 def test_anderson_solves_an_affine_map_in_dimension_plus_one_steps():
     # for g(x) = M x + c Anderson mixing with enough history is GMRES on (I - M) x = c: it reaches the
     # fixed point (I - M)^-1 c after at most dim + 1 evaluations of g (here 6 unknowns)
