@@ -456,6 +456,8 @@ def poisson_solve(ctx: Context, grid, rho, u_left=0.0, u_right=0.0, out=None):
 def density(ctx: Context, weights, gl):
     """hsc_density: sum_e w_e Im G^<_ii / (2 pi) from diag G^< (device complex128 [n_e, n])."""
     import torch
+    if not (isinstance(gl, torch.Tensor) and gl.dtype == torch.complex128 and gl.is_cuda and gl.dim() == 2):
+        raise ValueError("gl must be a complex128 device tensor of shape [n_e, n]")
     ne, n = int(gl.shape[0]), int(gl.shape[1])
     _check_vec(weights, ne, "weights")
     d = torch.empty(n, dtype=torch.float64, device=gl.device)
@@ -477,6 +479,8 @@ def scf(ctx: Context, tree: Tree, grid, energies, weights, u_left=0.0, u_right=0
     w = torch.as_tensor(weights, dtype=torch.float64, device=dev).contiguous()
     u = (torch.zeros(n, dtype=torch.float64, device=dev) if u0 is None else
          torch.as_tensor(u0, dtype=torch.float64, device=dev).clone().contiguous())
+    _check_vec(w, e.numel(), "weights")
+    _check_vec(u, n, "u0")
     if n0 is not None:
         n0 = torch.as_tensor(n0, dtype=torch.float64, device=dev).contiguous()
         _check_vec(n0, n, "n0")

@@ -266,3 +266,11 @@ def test_scf_rejects_a_grid_that_is_not_the_tree(ctx):
     for history in (-1, 17):
         with pytest.raises(H.HscError):
             pkg.scf(ctx, tree, grid, E, w, coupling=0.1, max_iter=1, history=history)
+    # the binding checks lengths before any call: weights per energy, a start potential per site
+    with pytest.raises(ValueError):
+        pkg.scf(ctx, tree, grid, E, w[:-1], coupling=0.1, max_iter=1)
+    with pytest.raises(ValueError):
+        pkg.scf(ctx, tree, grid, E, w, coupling=0.1, max_iter=1, u0=np.zeros(dev.n + 1))
+    with pytest.raises(ValueError):
+        pkg.density(ctx, torch.ones(2, dtype=torch.float64, device=ctx.torch_device),
+                    torch.zeros((2, dev.n), dtype=torch.complex64, device=ctx.torch_device))
