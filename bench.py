@@ -223,6 +223,9 @@ def main():
                          "elongated Nx x 16 x 16 devices")
     ap.add_argument("--orbital-study", action="store_true",
                     help="time per energy of 10-orbital wires (4 x 4 and 6 x 6 sites across, lengths 32 .. 128)")
+    ap.add_argument("--streams-study", action="store_true",
+                    help="energies/s of the benchmark cube with concurrent batches: batch 16 on one stream, batch 8 "
+                         "on two streams, batch 4 on four (64 energies of the grid each, after one untimed pass)")
     ap.add_argument("--scf-study", action="store_true",
                     help="time the self-consistent NEGF-Poisson loop on the --n-side cube (64 energies, 4 iterations)")
     ap.add_argument("--write-device", metavar="PATH",
@@ -269,6 +272,9 @@ def main():
         return
     if args.scf_study:
         scf_study(pkg, synth, np, torch, args)
+        return
+    if args.streams_study:
+        streams_study(pkg, synth, np, torch, args)
         return
 
     if args.calibrate_copy > 0:
@@ -572,6 +578,35 @@ def dense_study(pkg, synth, np, torch, args):
                       "dtype": "c128 in/out, complex double-double inside", "data": "synthetic",
                       "config": {"energies_per_batch": args.batch, "precision": args.precision, "leaf_side": args.leaf},
                       "rows": rows}), flush=True)
+
+
+def streams_study(pkg, synth, np, torch, args):
+    """Concurrent batches (hsc_solve_opts.streams) on the benchmark cube: 64 energies of the 256-point
+    grid per configuration, each timed after one untimed pass that builds its plans."""
+    N = args.n_side
+    dev = synth.config1_device(n_side=N)
+    ctx = pkg.Context(0)
+    tree = pkg.Tree.from_device(dev, leaf_side=args.leaf)
+    E = torch.tensor(np.linspace(-6.0, 6.0, 256)[::4].copy(), dtype=torch.float64, device="cuda:0")
+    want = pkg.HSC_DIAG_GR | pkg.HSC_DIAG_GL | pkg.HSC_TRANS
+    kw = dict(eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1, want=want, precision=args.precision, slices=args.slices,
+              complex3m=args.complex3m, tune=args.tune)
+    rows = []
+    for batch, streams in ((16, 1), (8, 2), (4, 4)):
+        out = pkg.solve(ctx, tree, E, batch=batch, streams=streams, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = pkg.solve(ctx, tree, E, batch=batch, streams=streams, out=out, **kw)
+        torch.cuda.synchronize()
+        rate = E.numel() / (time.perf_counter() - t0)
+        ok = int(out["status"].abs().max()) == 0
+        note(f"batch {batch} on {streams} stream(s): {rate:.2f} energies/s, status ok {ok}")
+        rows.append({"batch": batch, "streams": streams, "energies_per_s": rate, "status_ok": ok})
+    print(json.dumps({"metric": "energies/s with concurrent batches", "unit": "energies/s", "n_gpus": 1,
+                      "data": "synthetic", "config": {"workload": f"cube{N}^3, 64 energies of the 256-point grid",
+                                                      "precision": args.precision, "leaf_side": args.leaf},
+                      "rows": rows}), flush=True)
+    ctx.close()
 
 
 def scf_study(pkg, synth, np, torch, args):

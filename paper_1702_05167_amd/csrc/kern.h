@@ -319,6 +319,8 @@ void launch_mix(hipStream_t st, int64_t n, double* u, const double* u_new, doubl
 // Anderson mixing: f = u_new - u with its max |f_i| in *r; the history difference (dX, dF may be null) and the
 // previous (u, f); the update u = u + beta f - sum_j gamma_j (dX_j + beta dF_j) over the slots in `order`
 constexpr int kScfMaxHistory = 16;
+// most streams one solve call runs its batches on
+constexpr int kMaxStreams = 8;
 void launch_scf_resid(hipStream_t st, int64_t n, const double* u, const double* u_new, double* f,
                       unsigned long long* r);
 void launch_scf_hist(hipStream_t st, int64_t n, const double* u, const double* f, double* u_prev, double* f_prev,

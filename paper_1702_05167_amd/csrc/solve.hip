@@ -120,6 +120,7 @@ struct Plan {
   int tune = 0;
   int m3 = 0;                    // complex products in the three-multiplication form
   int slices = kOzSlices;        // 8-bit slices per operand of the products on the integer matrix cores
+  int inst = 0;                  // instance of this shape (one per stream of a call with concurrent batches)
   int64_t n = 0;
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -168,6 +169,8 @@ struct hsc_ctx {
   double prof[24][3] = {};                        // kind -> launches, ms, flops (24 >= number of kinds)
   double prof_bytes[24] = {};                     // kind -> algorithmic bytes
   hipStream_t cap_stream = nullptr;               // graph capture (a stream of its own, default priority)
+  hipStream_t sub[hsc::kMaxStreams] = {};              // streams of concurrent batches (default priority)
+  hipEvent_t sub_ev[hsc::kMaxStreams + 1] = {};        // fork (last) and per-stream join events
   std::vector<double> launch_log;                 // (kind, flops, ms, phase) per timed launch since profiling was enabled
   // merged trees of the growth guard: key (tree uid, merged cluster ids), most recent last
   std::vector<std::pair<std::vector<int64_t>, std::shared_ptr<hsc_tree>>> guard_trees;
@@ -1743,12 +1746,17 @@ hsc_status upload_plan(Builder& b, Plan* pl) {
 
 // slices: 8-bit slices per operand of the integer-matrix-core products (precision 3), kOzSlices
 // for the other precisions
+// Plan of this shape and instance (a call with concurrent batches holds instances 0 .. inst - 1 of
+// the shape while it builds instance inst: nothing here frees those).
 int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, int tune, int m3, int slices,
-               Plan** out) {
+               Plan** out, int inst = 0) {
+  auto same_shape = [&](const Plan& p) {
+    return p.uid == t->uid && p.B == B && p.want == want && p.prec == prec && p.tune == tune && p.m3 == m3 &&
+           p.slices == slices;
+  };
+  auto held = [&](const std::unique_ptr<Plan>& p) { return same_shape(*p) && p->inst < inst; };
   for (size_t k = 0; k < ctx->plans.size(); ++k)
-    if (ctx->plans[k]->uid == t->uid && ctx->plans[k]->B == B && ctx->plans[k]->want == want &&
-        ctx->plans[k]->prec == prec && ctx->plans[k]->tune == tune && ctx->plans[k]->m3 == m3 &&
-        ctx->plans[k]->slices == slices) {
+    if (same_shape(*ctx->plans[k]) && ctx->plans[k]->inst == inst) {
       // most recently used goes last
       std::unique_ptr<Plan> p = std::move(ctx->plans[k]);
       ctx->plans.erase(ctx->plans.begin() + k);
@@ -1759,12 +1767,20 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
   // keep memory bounded: drop plans of this tree with other shapes, then the
   // least recently used ones beyond a few
   ctx->plans.erase(std::remove_if(ctx->plans.begin(), ctx->plans.end(),
-                                  [&](const std::unique_ptr<Plan>& p) { return p->uid == t->uid; }),
+                                  [&](const std::unique_ptr<Plan>& p) { return p->uid == t->uid && !same_shape(*p); }),
                    ctx->plans.end());
   HIPCHK(hipSetDevice(ctx->device));
   if (ctx->stream) { HIPCHK(hipStreamSynchronize(ctx->stream)); }
   else { HIPCHK(hipDeviceSynchronize()); }
-  while (ctx->plans.size() > 3) ctx->plans.erase(ctx->plans.begin());
+  for (size_t k = 0; ctx->plans.size() > (size_t)std::max(3, inst + 1) && k < ctx->plans.size();)
+    if (held(ctx->plans[k])) ++k;
+    else ctx->plans.erase(ctx->plans.begin() + k);
+  // drop every plan but the ones this call holds (to make room)
+  auto drop_unheld = [&]() {
+    ctx->plans.erase(std::remove_if(ctx->plans.begin(), ctx->plans.end(),
+                                    [&](const std::unique_ptr<Plan>& p) { return !held(p); }),
+                     ctx->plans.end());
+  };
   for (const Cluster& c : t->cl)
     if (c.n > kMaxCluster) {
       set_error("cluster of " + std::to_string(c.n) + " sites exceeds the dense-block limit of " +
@@ -1773,7 +1789,7 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
     }
   std::unique_ptr<Plan> pl(new Plan());
   pl->uid = t->uid; pl->B = B; pl->want = want; pl->n = t->n; pl->prec = prec; pl->tune = tune; pl->m3 = m3;
-  pl->slices = slices;
+  pl->slices = slices; pl->inst = inst;
   Builder b{t, B, want, (want & (HSC_DIAG_GL | HSC_TRANS | HSC_SPECTRAL_LR | HSC_BOND_GL)) != 0};
   b.ddf = prec >= 1;
   b.ddx = prec >= 2;
@@ -1792,8 +1808,8 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
   if (hipMalloc(&pl->ws, pl->ws_bytes) != hipSuccess) {
     (void)hipGetLastError();
     pl->ws = nullptr;
-    // make room: drop every cached plan and try once more
-    ctx->plans.clear();
+    // make room: drop every cached plan this call does not hold and try once more
+    drop_unheld();
     if (hipMalloc(&pl->ws, pl->ws_bytes) != hipSuccess) {
       (void)hipGetLastError();
       pl->ws = nullptr;
@@ -1829,8 +1845,8 @@ int build_plan(hsc_ctx* ctx, const hsc_tree* t, int B, uint32_t want, int prec, 
     hsc_status rc = upload_plan(b, pl.get());
     if (rc == HSC_E_OOM && b.oz_need > 0 && !pl->oz && !ctx->plans.empty()) {
       // the slice scratch did not fit beside the cached plans (nothing of this plan was uploaded
-      // yet): drop them and try once more
-      ctx->plans.clear();
+      // yet): drop the ones this call does not hold and try once more
+      drop_unheld();
       rc = upload_plan(b, pl.get());
     }
     if (rc != HSC_OK) return rc;
@@ -1931,6 +1947,10 @@ hsc_status hsc_ctx_destroy(hsc_ctx* ctx) {
   if (ctx->forest) hsc_tree_destroy(ctx->forest);
   if (ctx->bstage) (void)hipFree(ctx->bstage);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  for (int k = 0; k < kMaxStreams; ++k)
+    if (ctx->sub[k]) (void)hipStreamDestroy(ctx->sub[k]);
+  for (int k = 0; k <= kMaxStreams; ++k)
+    if (ctx->sub_ev[k]) (void)hipEventDestroy(ctx->sub_ev[k]);
   delete ctx;
   return HSC_OK;
 }
@@ -1974,12 +1994,14 @@ static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
         B = std::max(B, p->B);
   }
   if (B <= 0) {
-    // as many slots as 70 % of the free memory holds (at most 64), then the energies spread
-    // evenly over the fewest batches that count allows (no mostly empty last batch)
+    // as many slots as 70 % of the free memory holds (at most 64; shared by the plans of concurrent
+    // batches), then the energies spread evenly over the fewest batches that count allows (no
+    // mostly empty last batch)
     size_t freeb = 0, totalb = 0;
     HIPCHK(hipMemGetInfo(&freeb, &totalb));
     const size_t per = std::max<size_t>(1, plan_bytes_per_slot(tree, want, opts->precision, slices));
-    const int bmax = (int)std::max<size_t>(1, std::min<size_t>(64, (size_t)(0.70 * (double)freeb) / per));
+    const size_t plans = (size_t)std::min(std::max(opts->streams, 1), kMaxStreams);
+    const int bmax = (int)std::max<size_t>(1, std::min<size_t>(64, (size_t)(0.70 * (double)freeb) / per / plans));
     const int chunks = (n_e + bmax - 1) / bmax;
     B = (n_e + chunks - 1) / chunks;
   }
@@ -1987,84 +2009,115 @@ static hsc_status solve_core(hsc_ctx* ctx, const hsc_tree* tree, int32_t n_e, co
   Plan* pl = nullptr;
   if (opts->precision < 0 || opts->precision > 3) { set_error("precision must be 0, 1, 2 or 3"); return HSC_E_ARG; }
   if (opts->complex3m != 0 && opts->complex3m != 1) { set_error("complex3m must be 0 or 1"); return HSC_E_ARG; }
-  int st = build_plan(ctx, tree, B, want, opts->precision, opts->tune != 0, opts->complex3m, slices, &pl);
-  if (st != HSC_OK) return (hsc_status)st;
-  const int64_t n = tree->n;
-  // the on-site potential of this call (cluster order), or zeros once after a call that had one
-  if (opts->potential) {
-    launch_potential(ctx->stream, n, pl->perm, opts->potential, pl->pot);
-    pl->pot_dirty = true;
-  } else if (pl->pot_dirty) {
-    launch_potential(ctx->stream, n, pl->perm, nullptr, pl->pot);
-    pl->pot_dirty = false;
+  if (opts->streams < 0 || opts->streams > kMaxStreams) {
+    set_error("streams must lie in [0, " + std::to_string(kMaxStreams) + "]");
+    return HSC_E_ARG;
   }
+  // concurrent batches: one plan (and stream) per instance, batches round-robin
+  const int K = (opts->streams > 1 && n_e > B && !guard && !ctx->profile && !(want & (HSC_BOND_GR | HSC_BOND_GL)))
+                    ? std::min(opts->streams, (n_e + B - 1) / B)
+                    : 1;
+  std::vector<Plan*> pls;
+  for (int k = 0; k < K; ++k) {
+    const int st = build_plan(ctx, tree, B, want, opts->precision, opts->tune != 0, opts->complex3m, slices, &pl, k);
+    if (st != HSC_OK) return (hsc_status)st;
+    pls.push_back(pl);
+  }
+  const int64_t n = tree->n;
   const bool use_graph = opts->graph != 0 && !guard && !ctx->profile && !(want & (HSC_BOND_GR | HSC_BOND_GL));
-  double2* sg_gr = nullptr;
-  double2* sg_gl = nullptr;
-  double* sg_sp = nullptr;
-  if (use_graph) {
-    const size_t row = (size_t)B * n;
-    if (!pl->stage && hipMalloc(&pl->stage, row * 48) != hipSuccess) {
-      (void)hipGetLastError();
-      set_error("graph staging allocation failed");
-      return HSC_E_OOM;
+  for (Plan* p : pls) {
+    // the on-site potential of this call (cluster order), or zeros once after a call that had one
+    if (opts->potential) {
+      launch_potential(ctx->stream, n, p->perm, opts->potential, p->pot);
+      p->pot_dirty = true;
+    } else if (p->pot_dirty) {
+      launch_potential(ctx->stream, n, p->perm, nullptr, p->pot);
+      p->pot_dirty = false;
     }
-    sg_gr = (double2*)pl->stage;
-    sg_gl = sg_gr + row;
-    sg_sp = (double*)(sg_gl + row);
-    if (!pl->gexec) {
-      if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
-      HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
-      st = run_steps(ctx, ctx->cap_stream, pl, 0, B, sg_gr, sg_gl, sg_sp, nullptr, (int)tree->cl.size());
-      hipGraph_t g = nullptr;
-      const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &g);
-      if (st != HSC_OK) {
-        if (g) (void)hipGraphDestroy(g);
-        return (hsc_status)st;
+    if (use_graph) {
+      const size_t row = (size_t)B * n;
+      if (!p->stage && hipMalloc(&p->stage, row * 48) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("graph staging allocation failed");
+        return HSC_E_OOM;
       }
-      HIPCHK(ce);
-      pl->graph = g;
-      HIPCHK(hipGraphInstantiate(&pl->gexec, g, nullptr, nullptr, 0));
+      if (!p->gexec) {
+        if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        double2* sg_gr = (double2*)p->stage;
+        HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
+        const int st = run_steps(ctx, ctx->cap_stream, p, 0, B, sg_gr, sg_gr + row, (double*)(sg_gr + 2 * row),
+                                 nullptr, (int)tree->cl.size());
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &g);
+        if (st != HSC_OK) {
+          if (g) (void)hipGraphDestroy(g);
+          return (hsc_status)st;
+        }
+        HIPCHK(ce);
+        p->graph = g;
+        HIPCHK(hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0));
+      }
     }
+  }
+  if (K > 1) {
+    // fork: every stream of the call starts after what the context's stream holds so far
+    for (int k = 0; k < K; ++k)
+      if (!ctx->sub[k]) HIPCHK(hipStreamCreateWithFlags(&ctx->sub[k], hipStreamNonBlocking));
+    for (int k = 0; k <= kMaxStreams; ++k)
+      if (!ctx->sub_ev[k]) HIPCHK(hipEventCreateWithFlags(&ctx->sub_ev[k], hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ctx->sub_ev[kMaxStreams], ctx->stream));
+    for (int k = 0; k < K; ++k) HIPCHK(hipStreamWaitEvent(ctx->sub[k], ctx->sub_ev[kMaxStreams], 0));
   }
   const int nseg = std::max<int>(1, (int)tree->seg_site.size() - 1);
-  for (int e0 = 0; e0 < n_e; e0 += B) {
+  for (int e0 = 0, c = 0; e0 < n_e; e0 += B, ++c) {
+    Plan* p = pls[c % K];
+    hipStream_t s = K > 1 ? ctx->sub[c % K] : ctx->stream;
     const int nv = std::min(B, n_e - e0);
-    launch_energy_setup(ctx->stream, energies + e0, nv, B, opts->eta, opts->kT, opts->mu_L, opts->mu_R, pl->lp,
-                        pl->es, pl->status);
+    launch_energy_setup(s, energies + e0, nv, B, opts->eta, opts->kT, opts->mu_L, opts->mu_R, p->lp, p->es,
+                        p->status);
     const double* spec_rows = spectral_lr ? spectral_lr + (size_t)e0 * 2 * n : nullptr;
     if (use_graph) {
-      HIPCHK(hipGraphLaunch(pl->gexec, ctx->stream));
+      const double2* sg_gr = (const double2*)p->stage;
+      const double2* sg_gl = sg_gr + (size_t)B * n;
+      const double* sg_sp = (const double*)(sg_gl + (size_t)B * n);
+      HIPCHK(hipGraphLaunch(p->gexec, s));
       const size_t rows = (size_t)nv * n;
       if (want & HSC_DIAG_GR)
-        HIPCHK(hipMemcpyAsync((double2*)diag_gr + (size_t)e0 * n, sg_gr, rows * 16, hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync((double2*)diag_gr + (size_t)e0 * n, sg_gr, rows * 16, hipMemcpyDeviceToDevice, s));
       if (want & HSC_DIAG_GL)
-        HIPCHK(hipMemcpyAsync((double2*)diag_gl + (size_t)e0 * n, sg_gl, rows * 16, hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync((double2*)diag_gl + (size_t)e0 * n, sg_gl, rows * 16, hipMemcpyDeviceToDevice, s));
       if (want & HSC_SPECTRAL_LR)
-        HIPCHK(hipMemcpyAsync(spectral_lr + (size_t)e0 * 2 * n, sg_sp, rows * 16, hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(spectral_lr + (size_t)e0 * 2 * n, sg_sp, rows * 16, hipMemcpyDeviceToDevice, s));
       spec_rows = sg_sp;
     } else {
-      st = run_steps(ctx, ctx->stream, pl, e0, nv, diag_gr, diag_gl, spectral_lr, guard, (int)tree->cl.size(),
-                     bond_gr, bond_gl);
+      const int st = run_steps(ctx, s, p, e0, nv, diag_gr, diag_gl, spectral_lr, guard, (int)tree->cl.size(),
+                               bond_gr, bond_gl);
       if (st != HSC_OK) return (hsc_status)st;
     }
     if ((want & HSC_TRANS) && tree->dense) {
-      launch_face_trans(ctx->stream, pl->face_tj, nv, e0, trans);
+      launch_face_trans(s, p->face_tj, nv, e0, trans);
     } else if (want & HSC_TRANS) {
       // one transmission per device of a forest, from its own left-contact sites
       for (int d = 0; d < nseg; ++d) {
         const int64_t l0 = tree->seg_left.empty() ? 0 : tree->seg_left[d];
-        const int64_t l1 = tree->seg_left.empty() ? pl->nleft : tree->seg_left[d + 1];
+        const int64_t l1 = tree->seg_left.empty() ? p->nleft : tree->seg_left[d + 1];
         double* td = trans + (size_t)d * n_e;
         if (want & HSC_SPECTRAL_LR)
-          launch_trans(ctx->stream, spec_rows + n, 2 * n, pl->left + l0, (int)(l1 - l0), B, nv, e0, pl->es, td);
+          launch_trans(s, spec_rows + n, 2 * n, p->left + l0, (int)(l1 - l0), B, nv, e0, p->es, td);
         else
-          launch_trans(ctx->stream, pl->a_r, n, pl->left + l0, (int)(l1 - l0), B, nv, e0, pl->es, td);
+          launch_trans(s, p->a_r, n, p->left + l0, (int)(l1 - l0), B, nv, e0, p->es, td);
       }
     }
     if ((want & HSC_SPECTRAL_LR) && (want & HSC_DIAG_GL))
-      launch_combine_gl(ctx->stream, spectral_lr, nv, e0, n, pl->es, (double2*)diag_gl);
-    if (status) launch_status_out(ctx->stream, pl->status, nv, status + e0);
+      launch_combine_gl(s, spectral_lr, nv, e0, n, p->es, (double2*)diag_gl);
+    if (status) launch_status_out(s, p->status, nv, status + e0);
+  }
+  if (K > 1) {
+    // join: the context's stream continues after every batch of the call
+    for (int k = 0; k < K; ++k) {
+      HIPCHK(hipEventRecord(ctx->sub_ev[k], ctx->sub[k]));
+      HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->sub_ev[k], 0));
+    }
   }
   HIPCHK(hipGetLastError());
   return HSC_OK;

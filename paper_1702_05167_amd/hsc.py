@@ -51,7 +51,7 @@ class SolveOpts(C.Structure):
                 ("want", C.c_uint32), ("batch", C.c_int32), ("guard_tau", C.c_double),
                 ("guard_rounds", C.c_int32), ("precision", C.c_int32), ("graph", C.c_int32),
                 ("tune", C.c_int32), ("complex3m", C.c_int32), ("slices", C.c_int32),
-                ("potential", C.c_void_p)]
+                ("potential", C.c_void_p), ("streams", C.c_int32)]
 
 
 class Grid(C.Structure):
@@ -345,10 +345,13 @@ class Tree:
 
 def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1,
           want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, out=None, sync=True, guard=False,
-          guard_tau=0.0, guard_rounds=6, precision=3, graph=0, tune=0, complex3m=0, slices=0, potential=None):
+          guard_tau=0.0, guard_rounds=6, precision=3, graph=0, tune=0, complex3m=0, slices=0, potential=None,
+          streams=0):
     """Solve all energies; returns a dict of device tensors (gr, gl, trans, spectral, status).
     slices: 8-bit slices per operand of the precision-3 products (0 = the library's 16, or 15).
-    potential: device float64 [n] on-site potential energy added to H (site order), or None."""
+    potential: device float64 [n] on-site potential energy added to H (site order), or None.
+    streams: batches run round-robin on that many streams at once (each with its own plan), 0 or 1
+    one after another."""
     import torch
     dev = ctx.torch_device
     e = torch.as_tensor(energies, dtype=torch.float64, device=dev).contiguous()
@@ -369,7 +372,7 @@ def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R
     if potential is not None:
         _check_vec(potential, n, "potential")
     opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, guard_tau, guard_rounds, precision, graph, tune, complex3m,
-                     slices, _dptr(potential) if potential is not None else None)
+                     slices, _dptr(potential) if potential is not None else None, int(streams))
     if want & (HSC_BOND_GR | HSC_BOND_GL):
         nb = len(tree.bonds())
         for bit, key in ((HSC_BOND_GR, "bond_gr"), (HSC_BOND_GL, "bond_gl")):
@@ -389,7 +392,7 @@ def solve(ctx: Context, tree: Tree, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R
 
 def solve_batch(ctx: Context, trees, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_R=-0.1,
                 want=HSC_DIAG_GR | HSC_DIAG_GL | HSC_TRANS, batch=0, outs=None, sync=True, precision=3, graph=0,
-                tune=0, complex3m=0, slices=0):
+                tune=0, complex3m=0, slices=0, streams=0):
     """Several devices in one call (hsc_solve_batch); energies: one array for all devices or a
     list of per-device arrays.  Returns a list of output dicts (device tensors)."""
     import torch
@@ -425,7 +428,8 @@ def solve_batch(ctx: Context, trees, energies, eta=1e-8, kT=0.025, mu_L=0.1, mu_
     th = (C.c_void_p * nt)(*[t.h.value for t in trees])
     ne_arr = np.array([int(e.numel()) for e in es], np.int32)
     e_arr = (C.c_void_p * nt)(*[e.data_ptr() for e in es])
-    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, 0.0, 0, precision, graph, tune, complex3m, slices)
+    opts = SolveOpts(eta, kT, mu_L, mu_R, want, batch, 0.0, 0, precision, graph, tune, complex3m, slices, None,
+                     int(streams))
     check(lib().hsc_solve_batch(ctx.h, nt, th, _ptr(ne_arr), e_arr, C.byref(opts), arr("gr"), arr("gl"), arr("trans"),
                                 arr("spectral"), arr("status"), None))
     if sync:
