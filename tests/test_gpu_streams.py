@@ -75,3 +75,20 @@ def test_streams_out_of_range(ctx):
     for k in (-1, 9):
         with pytest.raises(H.HscError):
             pkg.solve(ctx, tree, E, batch=2, streams=k, **KW)
+
+
+def test_streams_fall_back_to_one_with_profiling_and_the_guard(ctx):
+    # launch timing and the growth guard run on the context's stream alone; the option is accepted
+    # and the results are those of one stream
+    tree = pkg.Tree.from_device(_device(), leaf_side=4)
+    E = torch.tensor(np.linspace(-4.0, 4.0, 8), dtype=torch.float64, device=ctx.torch_device)
+    one = pkg.solve(ctx, tree, E, batch=2, **KW)
+    ctx.profile(True)
+    try:
+        prof = pkg.solve(ctx, tree, E, batch=2, streams=4, **KW)
+        assert sum(v["launches"] for v in ctx.profile_read().values()) > 0
+    finally:
+        ctx.profile(False)
+    _same(one, prof)
+    guarded = pkg.solve(ctx, tree, E, batch=2, streams=4, guard=True, guard_tau=1e30, **KW)
+    _same(one, guarded)
