@@ -107,27 +107,28 @@ __global__ __launch_bounds__(256) void k_oz_scale(const OzSplitJob* __restrict__
 }
 
 // S digits of y (a double-double with |y.lo| <= ulp(y.hi) / 2 and |y| < 2^6 + 2^-40), digit s of
-// weight 2^(-7 s), in blocks of m <= 4 digits: the block's integer v = rint(y.hi 2^(7 (m - 1)))
-// (|v| <= 2^27 + 1, exact in int32), the remainder y - v 2^(-7 (m - 1)) (exact: y.hi minus v's
-// value is a multiple of ulp(y.hi), so at least twice |y.lo| unless zero), times 2^(7 m), feeds the
-// next block (|remainder| <= 2^6 + 2^-20 in its units); v splits into balanced base-128 digits in
-// integer arithmetic, the lower ones in [-64, 63] and the leading one in [-64, 64] (|v| <= 64.5
-// 2^(7 (m - 1)) after the lower digits are taken off).  Four FP64 steps per block instead of one
-// per digit.  Digit s goes to byte `shift` of word[s].
+// weight 2^(-7 s), in blocks of m <= 4 digits b0 .. b0 + m - 1: the block's integer
+// v = rint(y.hi 2^(7 (b0 + m - 1))) (|v| <= 2^27 + 1, exact in int32), and the remainder
+// y - v 2^(-7 (b0 + m - 1)) (exact: y.hi minus v's value is a multiple of ulp(y.hi), so at least
+// twice |y.lo| unless zero) feeds the next block (|remainder| <= (2^6 + 2^-20) 2^(-7 (b0 + m))).  The
+// remainder keeps the input's scale and the powers of two move into the constants: every step is
+// the one at the block's own scale times an exact power of two, so the digits are the same.  v
+// splits into balanced base-128 digits in integer arithmetic, the lower ones in [-64, 63] and the
+// leading one in [-64, 64] (|v| <= 64.5 2^(7 (m - 1)) after the lower digits are taken off).  Four
+// FP64 steps per block instead of one per digit.  Digit s goes to byte `shift` of word[s].
 template <int S>
 __device__ inline void oz_digits(dd y, uint32_t* word, int shift) {
 #pragma clang fp contract(off)
 #pragma unroll
   for (int b0 = 0; b0 < S; b0 += 4) {
     const int m = S - b0 < 4 ? S - b0 : 4;
-    const double up = ldexp(1.0, 7 * (m - 1)), down = ldexp(1.0, -7 * (m - 1));
+    const double up = ldexp(1.0, 7 * (b0 + m - 1)), down = ldexp(1.0, -7 * (b0 + m - 1));
     const double q = rint(y.hi * up);
     int v = (int)q;
-    const double t = y.hi - q * down;
+    const double t = fma(-q, down, y.hi);   // exact (representable), as the unfused difference is
     const double hi = t + y.lo;
     const double lo = y.lo - (hi - t);
-    const double next = ldexp(1.0, 7 * m);
-    y = dd{hi * next, lo * next};
+    y = dd{hi, lo};
 #pragma unroll
     for (int j = m - 1; j >= 1; --j) {
       const int d = ((v + 64) & 127) - 64;
