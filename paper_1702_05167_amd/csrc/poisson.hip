@@ -23,6 +23,7 @@
 
 #include "hsc_internal.h"
 #include "kern.h"
+#include "poisson_basis.h"
 
 namespace hsc {
 
@@ -213,26 +214,19 @@ int PoissonWork::create(const hsc_grid& g) {
     buf = nullptr;
     return -1;
   }
-  std::vector<double> host;
-  host.reserve(doubles - 2 * (size_t)n);
+  std::vector<double> host(doubles - 2 * (size_t)n);
   double* p = buf + 2 * (size_t)n;
+  double* h = host.data();
   t1 = buf;
   t2 = buf + n;
   for (int a = 0; a < 3; ++a) {
+    // x: Dirichlet (the lead planes); y, z: zero normal derivative
     const int N = side[a];
+    poisson_basis(N, a == 0, h, h + (size_t)N * N);
     Q[a] = p;
-    p += (size_t)N * N;
-    lam[a] = p;
-    p += N;
-    for (int j = 0; j < N; ++j)
-      for (int k = 0; k < N; ++k) {
-        double v;
-        if (a == 0) v = std::sqrt(2.0 / (N + 1)) * std::sin(kPi * (k + 1) * (j + 1) / (N + 1));
-        else v = (k == 0 ? std::sqrt(1.0 / N) : std::sqrt(2.0 / N)) * std::cos(kPi * k * (j + 0.5) / N);
-        host.push_back(v);
-      }
-    for (int k = 0; k < N; ++k)
-      host.push_back(a == 0 ? 2.0 - 2.0 * std::cos(kPi * (k + 1) / (N + 1)) : 2.0 - 2.0 * std::cos(kPi * k / N));
+    lam[a] = p + (size_t)N * N;
+    p += (size_t)N * N + N;
+    h += (size_t)N * N + N;
   }
   if (hipMemcpy(buf + 2 * (size_t)n, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipGetLastError();
