@@ -1940,6 +1940,10 @@ hsc_status hsc_ctx_destroy(hsc_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   else (void)hipDeviceSynchronize();
+  // the streams of concurrent batches are joined into the context's stream by every call that
+  // completes; one that failed between fork and join may have left work on them
+  for (int k = 0; k < kMaxStreams; ++k)
+    if (ctx->sub[k]) (void)hipStreamSynchronize(ctx->sub[k]);
   for (auto& e : ctx->ev_pool) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
@@ -2474,6 +2478,9 @@ hsc_status hsc_sync(hsc_ctx* ctx) {
   HIPCHK(hipSetDevice(ctx->device));
   if (ctx->stream) { HIPCHK(hipStreamSynchronize(ctx->stream)); }
   else { HIPCHK(hipDeviceSynchronize()); }
+  // concurrent batches of a call that failed before its join
+  for (int k = 0; k < kMaxStreams; ++k)
+    if (ctx->sub[k]) HIPCHK(hipStreamSynchronize(ctx->sub[k]));
   HIPCHK(hipGetLastError());
   return fold_events(ctx);   // recorded launch timings into the per-kind totals
 }
