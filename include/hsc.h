@@ -342,7 +342,8 @@ hsc_status hsc_solve_batch(hsc_ctx* ctx, int32_t n_trees, const hsc_tree* const*
                            double* const* spectral_lr, int32_t* const* status,
                            double* const* guard);
 
-/* Wait for the context's stream; returns HSC_E_HIP on an asynchronous HIP error. */
+/* Wait for the context's stream (and the context's streams of concurrent batches, see
+ * hsc_solve_opts.streams); returns HSC_E_HIP on an asynchronous HIP error. */
 hsc_status hsc_sync(hsc_ctx* ctx);
 
 /* Per-energy sums over sites of solve outputs (Section 2: density of states from
