@@ -8,3 +8,4 @@ from .hsc import (  # noqa: F401
     LIB_PATH, poisson_solve, density, scf,
 )
 from .mlp import MLP  # noqa: F401
+from .sweep import sweep  # noqa: F401
