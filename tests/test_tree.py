@@ -5,6 +5,7 @@ These run without a GPU (no compute call is made).
 import os
 import re
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -357,3 +358,12 @@ def test_custom_partition_and_rejections():
     for cs, par in bad:
         with pytest.raises(H.HscError):
             pkg.Tree.build_custom(*args, cs, par)
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    # no fallback: a missing libhsc.so is an error at the first call, in a fresh interpreter
+    code = ("import paper_1702_05167_amd.hsc as H\n"
+            f"H.LIB_PATH = {str(tmp_path / 'libhsc.so')!r}\n"
+            "try:\n    H.lib()\nexcept RuntimeError as e:\n    print('raised', 'is missing' in str(e))\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=120)
+    assert out.stdout.strip() == "raised True", out.stderr
